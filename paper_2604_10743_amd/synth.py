@@ -1,0 +1,423 @@
+"""Seeded synthetic power-grid inputs.
+
+This module only *builds inputs*: node coordinates and layers, wire
+resistors with their extracted geometry and nominal resistance, pads, sink
+currents and thermal rasters.  It holds none of the stress, IR-drop, void or
+Monte Carlo arithmetic of the method; both the HIP path and the CPU oracle
+consume what it returns.  Every generator is deterministic in its seed.
+
+Units are SI throughout (m, A, ohm, K).
+
+The paper's own designs are SAED32 power grids extracted from a commercial
+place-and-route flow (Section V); they are not available, so these grids
+stand in for them with the shape statistics the paper reports (Table III:
+tens to hundreds of trees, up to ~10^4 stress nodes per tree, initial worst
+IR-drop a few percent of the supply; Section V-A: 0.95-1.2 V supply, base
+temperature around 353 K, hotspots tens of kelvin above it).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+RHO_CU = 2.25e-8          # ohm*m, copper resistivity used for extraction
+UM = 1e-6
+
+
+@dataclasses.dataclass
+class Grid:
+    """An extracted P/G netlist plus its optional thermal raster.
+
+    Resistors with ``res_is_via`` set (or joining two different layers) are
+    vias; all others are wire segments on one layer.  ``seg_j`` (optional)
+    prescribes a current density per resistor and switches the run to the
+    trees-only mode (no IR coupling).
+    """
+
+    xy: np.ndarray            # (n_nodes, 2) float64, m
+    layer: np.ndarray         # (n_nodes,) int32
+    res_a: np.ndarray         # (n_res,) int32
+    res_b: np.ndarray         # (n_res,) int32
+    res_len: np.ndarray       # (n_res,) float64, m
+    res_w: np.ndarray         # (n_res,) float64, m
+    res_h: np.ndarray         # (n_res,) float64, m
+    res_is_via: np.ndarray    # (n_res,) uint8
+    res_R0: np.ndarray        # (n_res,) float64, ohm
+    pad_node: np.ndarray      # (n_pads,) int32
+    vdd: float
+    sink_I: np.ndarray        # (n_nodes,) float64, A drawn at each node
+    node_T: Optional[np.ndarray] = None     # (n_nodes,) K
+    tmap: Optional[np.ndarray] = None       # (ny, nx) K raster, row-major
+    tmap_x0: float = 0.0
+    tmap_y0: float = 0.0
+    tmap_dx: float = 1.0
+    tmap_dy: float = 1.0
+    seg_j: Optional[np.ndarray] = None      # (n_res,) A/m^2 along a->b
+    name: str = ""
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.xy.shape[0])
+
+    @property
+    def n_res(self) -> int:
+        return int(self.res_a.shape[0])
+
+
+def default_material() -> dict:
+    """Cu constants of the tiny trees workload plus the values the paper
+    leaves open (heat of transport, residual stress, void-interface
+    thickness, Ta liner): SI units, activation energies in eV."""
+    return dict(B=28e9, Omega=1.18e-29, Z=1.0, rho_cu=RHO_CU, Ea_eV=0.85,
+                D0=7.56e-5, sigma_crit=400e6, Q_eV=0.1, sigma_T=0.0,
+                delta=1e-9, rho_ta=2e-7, h_ta=5e-9)
+
+
+def default_run(**over) -> dict:
+    """Numerics: 20 intervals per segment, 2000 backward-Euler steps over
+    ten years (a year of 365.25 days), IR re-solve every 100 steps, failure
+    at 10 % worst IR-drop."""
+    horizon = 10 * 365.25 * 86400.0
+    r = dict(intervals_per_seg=20, n_steps=2000, dt=horizon / 2000, ir_every=100,
+             fail_frac=0.10, cg_rtol=1e-13, cg_max_iter=20000, prec=0, screen=1,
+             max_voids_per_tree=4, T_ambient=378.0)
+    r.update(over)
+    return r
+
+
+def _wire_R(L, w, h):
+    return RHO_CU * L / (w * h)
+
+
+def _empty_i32():
+    return np.zeros(0, np.int32)
+
+
+# ----------------------------------------------------------------------------
+# Straight standalone trees with prescribed currents (trees-only mode)
+# ----------------------------------------------------------------------------
+def straight_trees(seed: int = 1001, n_trees: int = 200, seg_range=(2, 8),
+                   L_range=(5 * UM, 50 * UM), w_range=(0.1 * UM, 1.0 * UM),
+                   H=0.2 * UM, j_range=(1e9, 5e10)) -> Grid:
+    """Independent straight lines of S ~ U{seg_range} segments; each segment
+    has its own length, width and signed current density."""
+    rng = np.random.default_rng(seed)
+    xs, ys, ra, rb, L, W = [], [], [], [], [], []
+    base = 0
+    for t in range(n_trees):
+        S = int(rng.integers(seg_range[0], seg_range[1] + 1))
+        lens = rng.uniform(L_range[0], L_range[1], S)
+        x = np.concatenate([[0.0], np.cumsum(lens)])
+        xs.append(x)
+        ys.append(np.full(S + 1, t * 20 * UM))
+        ra.append(base + np.arange(S))
+        rb.append(base + np.arange(1, S + 1))
+        L.append(lens)
+        W.append(rng.uniform(w_range[0], w_range[1], S))
+        base += S + 1
+    n = base
+    res_len = np.concatenate(L)
+    res_w = np.concatenate(W)
+    nr = res_len.size
+    mag = rng.uniform(j_range[0], j_range[1], nr)
+    sign = np.where(rng.random(nr) < 0.5, -1.0, 1.0)
+    res_h = np.full(nr, H)
+    return Grid(xy=np.stack([np.concatenate(xs), np.concatenate(ys)], 1),
+                layer=np.ones(n, np.int32),
+                res_a=np.concatenate(ra).astype(np.int32),
+                res_b=np.concatenate(rb).astype(np.int32),
+                res_len=res_len, res_w=res_w, res_h=res_h,
+                res_is_via=np.zeros(nr, np.uint8),
+                res_R0=_wire_R(res_len, res_w, res_h),
+                pad_node=_empty_i32(), vdd=1.0, sink_I=np.zeros(n),
+                seg_j=mag * sign, name=f"straight_trees_{n_trees}_s{seed}")
+
+
+def random_branched_trees(seed: int, n_trees: int, n_vertices=(2, 10),
+                          L_range=(2 * UM, 20 * UM), w_range=(0.2 * UM, 1.0 * UM),
+                          H=0.2 * UM, j_range=(1e8, 5e10), planar_jitter=True) -> Grid:
+    """Random trees from uniform Pruefer sequences (trees-only mode).
+
+    Vertex indices are shuffled so that roots and DFS orders are not the
+    trivial ones; resistor orientation (a->b) is random.  Geometry lengths
+    are drawn independently of the coordinates (an extracted netlist gives
+    lengths; the coordinates only place the nodes on a thermal raster).
+    """
+    rng = np.random.default_rng(seed)
+    xy_all, ra, rb, L, W = [], [], [], [], []
+    base = 0
+    for t in range(n_trees):
+        nv = int(rng.integers(n_vertices[0], n_vertices[1] + 1))
+        if nv == 2:
+            edges = [(0, 1)]
+        else:
+            prufer = rng.integers(0, nv, nv - 2)
+            degree = np.ones(nv, np.int64)
+            for v in prufer:
+                degree[v] += 1
+            edges = []
+            for v in prufer:
+                leaf = int(np.nonzero(degree == 1)[0][0])
+                edges.append((leaf, int(v)))
+                degree[leaf] -= 1
+                degree[v] -= 1
+            u, w = np.nonzero(degree == 1)[0]
+            edges.append((int(u), int(w)))
+        perm = rng.permutation(nv)
+        pos = rng.uniform(0, 100 * UM, (nv, 2)) + np.array([0.0, t * 200 * UM])
+        xy_all.append(pos)
+        order = rng.permutation(len(edges))
+        for k in order:
+            a, b = edges[k]
+            a, b = int(perm[a]), int(perm[b])
+            if rng.random() < 0.5:
+                a, b = b, a
+            ra.append(base + a)
+            rb.append(base + b)
+            L.append(rng.uniform(*L_range))
+            W.append(rng.uniform(*w_range))
+        base += nv
+    nr = len(ra)
+    res_len = np.array(L)
+    res_w = np.array(W)
+    res_h = np.full(nr, H)
+    mag = rng.uniform(j_range[0], j_range[1], nr)
+    sign = np.where(rng.random(nr) < 0.5, -1.0, 1.0)
+    return Grid(xy=np.concatenate(xy_all), layer=np.ones(base, np.int32),
+                res_a=np.array(ra, np.int32), res_b=np.array(rb, np.int32),
+                res_len=res_len, res_w=res_w, res_h=res_h,
+                res_is_via=np.zeros(nr, np.uint8), res_R0=_wire_R(res_len, res_w, res_h),
+                pad_node=_empty_i32(), vdd=1.0, sink_I=np.zeros(base),
+                seg_j=mag * sign, name=f"branched_{n_trees}_s{seed}")
+
+
+# ----------------------------------------------------------------------------
+# Thermal rasters
+# ----------------------------------------------------------------------------
+def gaussian_hotspot_map(seed: int, extent_x: float, extent_y: float, base_K: float,
+                         n_spots: int, amp_range, sig_range, res: float = 1 * UM):
+    """Base temperature plus Gaussian hotspots on a regular raster.
+
+    Returns (tmap[ny, nx], x0, y0, dx, dy)."""
+    rng = np.random.default_rng(seed)
+    nx = int(np.ceil(extent_x / res)) + 1
+    ny = int(np.ceil(extent_y / res)) + 1
+    x = np.arange(nx) * res
+    y = np.arange(ny) * res
+    T = np.full((ny, nx), base_K)
+    for _ in range(n_spots):
+        A = rng.uniform(*amp_range)
+        s = rng.uniform(*sig_range)
+        cx = rng.uniform(0, extent_x)
+        cy = rng.uniform(0, extent_y)
+        gx = np.exp(-0.5 * ((x - cx) / s) ** 2)
+        gy = np.exp(-0.5 * ((y - cy) / s) ** 2)
+        T += A * np.outer(gy, gx)
+    return T, 0.0, 0.0, res, res
+
+
+# ----------------------------------------------------------------------------
+# Two-layer meshes (M1 horizontal rows, M2 vertical columns)
+# ----------------------------------------------------------------------------
+def two_layer_mesh(seed: int = 1001, nr: int = 32, nc: int = 32,
+                   spacing=(5 * UM, 50 * UM), w1=0.5 * UM, w2=1.0 * UM, H=0.2 * UM,
+                   R_via=0.5, vdd=1.0, sink_mu=None, sink_sigma=0.5,
+                   cut_m1=False, cut_seg=(2, 8), T_uniform: Optional[float] = 378.0,
+                   pads: str = "corners") -> Grid:
+    """Small two-layer mesh with a via at every crossing and 4 pads on M2
+    (at the corners, or spread along the top edge with ``pads="edge"``).  Row/column spacings are drawn from U[spacing]; node sinks are
+    lognormal on M1.  With ``cut_m1`` every M1 row is cut into straight
+    trees of U{cut_seg} segments separated by single missing segments.
+
+    The default sink median puts the initial worst IR-drop near 6 % of the
+    supply for seed 1001 (uncut, corner pads): a constant fixed once for this
+    geometry."""
+    rng = np.random.default_rng(seed)
+    dy = rng.uniform(spacing[0], spacing[1], nr - 1)
+    dx = rng.uniform(spacing[0], spacing[1], nc - 1)
+    yr = np.concatenate([[0.0], np.cumsum(dy)])
+    xc = np.concatenate([[0.0], np.cumsum(dx)])
+    n1 = nr * nc
+    idx1 = np.arange(n1).reshape(nr, nc)           # M1 node ids
+    idx2 = n1 + np.arange(n1).reshape(nr, nc)      # M2 node ids
+    X, Y = np.meshgrid(xc, yr)
+    xy = np.concatenate([np.stack([X.ravel(), Y.ravel()], 1)] * 2)
+    layer = np.concatenate([np.ones(n1, np.int32), np.full(n1, 2, np.int32)])
+    ra, rb, L, W, Hh, via = [], [], [], [], [], []
+    # M1 rows
+    for r in range(nr):
+        keep = np.ones(nc - 1, bool)
+        if cut_m1:
+            c = 0
+            while c < nc - 1:
+                S = int(rng.integers(cut_seg[0], cut_seg[1] + 1))
+                c += S
+                if c < nc - 1:
+                    keep[c] = False
+                    c += 1
+        for c in range(nc - 1):
+            if keep[c]:
+                ra.append(idx1[r, c]); rb.append(idx1[r, c + 1])
+                L.append(dx[c]); W.append(w1); Hh.append(H); via.append(0)
+    # M2 columns
+    for c in range(nc):
+        for r in range(nr - 1):
+            ra.append(idx2[r, c]); rb.append(idx2[r + 1, c])
+            L.append(dy[r]); W.append(w2); Hh.append(H); via.append(0)
+    # vias
+    for r in range(nr):
+        for c in range(nc):
+            ra.append(idx1[r, c]); rb.append(idx2[r, c])
+            L.append(0.0); W.append(w1); Hh.append(H); via.append(1)
+    ra = np.array(ra, np.int32); rb = np.array(rb, np.int32)
+    L = np.array(L); W = np.array(W); Hh = np.array(Hh); via = np.array(via, np.uint8)
+    R0 = np.where(via == 1, R_via, _wire_R(np.maximum(L, 1e-12), W, Hh))
+    if pads == "corners":
+        pads = np.array([idx2[0, 0], idx2[0, nc - 1], idx2[nr - 1, 0], idx2[nr - 1, nc - 1]], np.int32)
+    else:       # four pads spread along the top edge (one-sided delivery)
+        cols = [(2 * k + 1) * nc // 8 for k in range(4)]
+        pads = np.array([idx2[nr - 1, c] for c in cols], np.int32)
+    if sink_mu is None:
+        sink_mu = np.log(32.7e-6)
+    sink = np.zeros(2 * n1)
+    sink[:n1] = np.exp(rng.normal(sink_mu, sink_sigma, n1))
+    g = Grid(xy=xy, layer=layer, res_a=ra, res_b=rb, res_len=L, res_w=W, res_h=Hh,
+             res_is_via=via, res_R0=R0, pad_node=pads, vdd=vdd, sink_I=sink,
+             name=f"mesh{nr}x{nc}{'_cut' if cut_m1 else ''}_s{seed}")
+    if T_uniform is not None:
+        g.node_T = np.full(2 * n1, float(T_uniform))
+    return g
+
+
+def pg_grid(seed: int = 2001, n: int = 400, pitch=5 * UM, w1=0.5 * UM, w2=1.0 * UM,
+            H=0.2 * UM, via_every=4, R_via=0.5, pad_lattice=8, vdd=1.2,
+            sink_mu=np.log(50e-6), sink_sigma=0.5, sink_scale=0.0651,
+            seg_range=(100, 399), base_K=330.0, n_spots=6, amp_range=(15.0, 60.0),
+            sig_range=(30 * UM, 80 * UM), raster=1 * UM, thermal=True) -> Grid:
+    """Two-layer n x n P/G grid: M1 rows and M2 columns at a fixed pitch.
+
+    Every line is one tree cut to a random contiguous span of U{seg_range}
+    segments.  A via joins M1 and M2 at every crossing on a row or column
+    whose index is a multiple of ``via_every`` (so every line carries a via
+    at least every ``via_every`` nodes and the two layers form one network);
+    VDD pads sit on M2 at a pad_lattice x pad_lattice lattice (snapped onto
+    the nearest existing M2 node of that column); components that reach no
+    pad are removed; lognormal sinks sit on
+    every M1 node, scaled by ``sink_scale`` (the stated 50 uA median on this
+    geometry gives a worst initial drop above 100 % of the supply; the
+    default scale puts it near 8.5 % of a 1.2 V supply, inside the 5-9 %
+    the paper's failing designs start from).  The thermal raster is the base
+    temperature plus Gaussian hotspots at ``raster`` resolution.
+    """
+    rng = np.random.default_rng(seed)
+    nseg = n - 1
+    span_r = rng.integers(seg_range[0], min(seg_range[1], nseg) + 1, n)
+    off_r = np.array([rng.integers(0, nseg - s + 1) for s in span_r])
+    span_c = rng.integers(seg_range[0], min(seg_range[1], nseg) + 1, n)
+    off_c = np.array([rng.integers(0, nseg - s + 1) for s in span_c])
+    # node ids: allocate only existing nodes
+    id1 = -np.ones((n, n), np.int64)
+    id2 = -np.ones((n, n), np.int64)
+    xy, layer = [], []
+    cnt = 0
+    for r in range(n):
+        for c in range(off_r[r], off_r[r] + span_r[r] + 1):
+            id1[r, c] = cnt; cnt += 1
+            xy.append((c * pitch, r * pitch)); layer.append(1)
+    for c in range(n):
+        for r in range(off_c[c], off_c[c] + span_c[c] + 1):
+            id2[r, c] = cnt; cnt += 1
+            xy.append((c * pitch, r * pitch)); layer.append(2)
+    ra, rb, L, W, via = [], [], [], [], []
+    for r in range(n):
+        for c in range(off_r[r], off_r[r] + span_r[r]):
+            ra.append(id1[r, c]); rb.append(id1[r, c + 1]); L.append(pitch); W.append(w1); via.append(0)
+    for c in range(n):
+        for r in range(off_c[c], off_c[c] + span_c[c]):
+            ra.append(id2[r, c]); rb.append(id2[r + 1, c]); L.append(pitch); W.append(w2); via.append(0)
+    rr, cc = np.nonzero((id1 >= 0) & (id2 >= 0))
+    sel = ((rr % via_every) == 0) | ((cc % via_every) == 0)
+    for r, c in zip(rr[sel], cc[sel]):
+        ra.append(id1[r, c]); rb.append(id2[r, c]); L.append(0.0); W.append(w1); via.append(1)
+    ra = np.array(ra, np.int32); rb = np.array(rb, np.int32)
+    L = np.array(L); W = np.array(W); via = np.array(via, np.uint8)
+    Hh = np.full(L.size, H)
+    R0 = np.where(via == 1, R_via, _wire_R(np.maximum(L, 1e-12), W, Hh))
+    # pads on M2
+    step = n // pad_lattice
+    pads = []
+    for a in range(pad_lattice):
+        for b in range(pad_lattice):
+            r = step // 2 + a * step
+            c = step // 2 + b * step
+            r = int(np.clip(r, off_c[c], off_c[c] + span_c[c]))
+            pads.append(id2[r, c])
+    pads = np.unique(np.array(pads, np.int32))
+    # component labelling (plain union-find over all resistors) to keep the
+    # nodal system non-singular: sinks only where a pad is reachable
+    parent = np.arange(cnt)
+
+    def find(x):
+        while parent[x] != x:
+            parent[x] = parent[parent[x]]
+            x = parent[x]
+        return x
+    for a, b in zip(ra, rb):
+        fa, fb = find(a), find(b)
+        if fa != fb:
+            parent[fa] = fb
+    roots = np.array([find(i) for i in range(cnt)])
+    live_roots = set(roots[pads].tolist())
+    live = np.array([rt in live_roots for rt in roots])
+    # drop pad-less components entirely (nodes and their resistors)
+    remap = -np.ones(cnt, np.int64)
+    remap[live] = np.arange(int(live.sum()))
+    keep_r = live[ra] & live[rb]
+    ra = remap[ra[keep_r]].astype(np.int32); rb = remap[rb[keep_r]].astype(np.int32)
+    L, W, Hh, via, R0 = L[keep_r], W[keep_r], Hh[keep_r], via[keep_r], R0[keep_r]
+    pads = remap[pads].astype(np.int32)
+    xy = np.array(xy, float)[live]
+    layer = np.array(layer, np.int32)[live]
+    cnt = int(live.sum())
+    sink = np.zeros(cnt)
+    m1 = layer == 1
+    sink[m1] = sink_scale * np.exp(rng.normal(sink_mu, sink_sigma, int(m1.sum())))
+    g = Grid(xy=xy, layer=layer, res_a=ra, res_b=rb, res_len=L, res_w=W,
+             res_h=Hh, res_is_via=via, res_R0=R0, pad_node=pads, vdd=vdd, sink_I=sink,
+             name=f"pg{n}x{n}_s{seed}")
+    if thermal:
+        tm, x0, y0, dxr, dyr = gaussian_hotspot_map(seed + 7, (n - 1) * pitch, (n - 1) * pitch,
+                                                   base_K, n_spots, amp_range, sig_range, raster)
+        g.tmap, g.tmap_x0, g.tmap_y0, g.tmap_dx, g.tmap_dy = tm, x0, y0, dxr, dyr
+    else:
+        g.node_T = np.full(cnt, base_K)
+    return g
+
+
+# ----------------------------------------------------------------------------
+# Named workloads
+# ----------------------------------------------------------------------------
+def workload(name: str):
+    """Return (grid, material, run, mc) for a named workload.
+
+    tiny_trees      200 straight trees, prescribed currents, 378 K, FP64
+    tiny_mesh       32x32 two-layer mesh with 4 corner pads (IR solve)
+    pg400           400x400 two-layer grid, ~800 line trees, thermal map
+    mc_mesh         32x32 mesh with cut M1 rows, 1024 Monte Carlo samples
+    """
+    mat = default_material()
+    if name == "tiny_trees":
+        return straight_trees(1001), mat, default_run(prec=0, screen=0), None
+    if name == "tiny_mesh":
+        return two_layer_mesh(1001), mat, default_run(prec=0), None
+    if name == "pg400":
+        return pg_grid(2001), mat, default_run(prec=1, T_ambient=330.0), None
+    if name == "pg400_fp64":
+        return pg_grid(2001), mat, default_run(prec=0, T_ambient=330.0), None
+    if name == "mc_mesh":
+        return (two_layer_mesh(3001, cut_m1=True, vdd=1.2, sink_mu=np.log(32e-6)), mat,
+                default_run(prec=1),
+                dict(n_samples=1024, seed=3001, cov_kappa=0.2, cov_scrit=0.2))
+    raise KeyError(name)
