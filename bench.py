@@ -1,0 +1,156 @@
+"""Benchmark of the coupled EM/TM stress + IR-drop hot path on one MI355X.
+
+A step is one full pass of the hot path over the 400x400 two-layer P/G grid:
+IR solve, backward-Euler stress stepping of every tree (2000 steps over ten
+years, FP32 stress with FP64 void/dR accumulators), nucleation and void
+growth, resistance write-back and an IR re-solve every 100 steps, until the
+10 % IR-drop failure or the horizon.  The batch is built (netlist copied,
+trees partitioned, statics evaluated) before the timed region; each timed
+step resets it to t = 0 and runs it to time-to-failure.
+
+Prints ONE JSON line (rank 0).  Metric: stress-node-steps/s (sum over stepped
+trees of stress nodes x steps, divided by wall time).  Also reported: the
+roofline of the dominant kernel (the stepping kernel, timed with HIP events on
+its own stream inside the library), the FP64 oracle on host cores over a
+bounded sample of the same workload, and a Monte Carlo samples/s figure on the
+32x32 mesh with 1024 samples.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+BYTES_PER_NODE_STEP = {0: 40.0, 1: 20.0}   # sigma r/w, 1/d, l, dt*f (FP64 / FP32)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", type=int, default=1, help="1 = FP32 stepping, 0 = FP64")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mc", action="store_true")
+    ap.add_argument("--mc-samples", type=int, default=1024)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is described in the design notes, not implemented", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2604_10743_amd as P
+    from paper_2604_10743_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    g, mat, run, _ = synth.workload("pg400")
+    run = dict(run, prec=args.prec, screen=0)
+    log(f"bench: building batch for {g.name} ({g.n_nodes} nodes, {g.n_res} resistors)")
+    t0 = time.perf_counter()
+    B = P.Batch(g, mat, run)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    info = B.info()
+    log(f"bench: {info['n_trees']} trees, {info['n_stress']} stress nodes, setup {t_setup:.2f} s")
+
+    for w in range(args.warmup):
+        B.reset()
+        B.run_to_ttf()
+        log(f"bench: warmup {w + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    B.reset()
+    i0 = B.info()
+    t0 = time.perf_counter()
+    results = None
+    for k in range(args.steps):
+        if k:
+            B.reset()
+        results = B.run_to_ttf()
+        log(f"bench: step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # counters are cleared by reset: accumulate per step instead
+    # (node_steps of the last step x steps is exact: every step replays the same run)
+    i1 = B.info()
+    node_steps_total = i1["node_steps"] * args.steps
+    value = node_steps_total / wall
+    bytes_ns = BYTES_PER_NODE_STEP[args.prec]
+    step_ms = i1["step_kernel_ms"]
+    launches = i1["step_launches"]
+    achieved = (bytes_ns * i1["node_steps"] / 1e9) / (step_ms / 1e3) if step_ms > 0 else None
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                "kernel": "k_step", "launches_per_step": launches,
+                "avg_launch_ms": step_ms / max(launches, 1),
+                "bytes_per_node_step": bytes_ns}
+    r0 = results[0]
+    out = {
+        "metric": "stress-node-steps/s", "value": value, "unit": "node-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.prec == 1 else "f64", "data": "synthetic",
+        "config": {"workload": f"pg400: 400x400 two-layer P/G grid, {info['n_trees']} line trees, "
+                               f"{info['n_stress']} stress nodes, 2000 BE steps over 10 y, "
+                               "IR re-solve every 100 steps, thermal map 330 K + 6 hotspots, "
+                               "screen off (every tree stepped)",
+                   "node_steps_per_step": i1["node_steps"], "setup_s": t_setup,
+                   "ir_ms_per_step": i1["ir_ms"], "cg_iters_per_step": i1["cg_iters_total"],
+                   "ttf_s": r0["ttf_s"], "final_drop": r0["final_drop"], "init_drop": r0["init_drop"],
+                   "n_nucleated_trees": r0["n_nucleated_trees"]},
+        "roofline": roofline,
+    }
+    B.close()
+
+    if not args.no_mc:
+        gm, matm, runm, mcm = synth.workload("mc_mesh")
+        mcm = dict(mcm, n_samples=args.mc_samples)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Bm = P.Batch(gm, matm, runm, mcm)
+        res = Bm.run_to_ttf()
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t0
+        ttf = np.array([r["ttf_s"] for r in res if r["failed"]])
+        im = Bm.info()
+        out["mc"] = {"metric": "MC samples/s to TTF", "value": args.mc_samples / tm, "unit": "samples/s",
+                     "workload": f"mc_mesh: 32x32 two-layer mesh, cut M1 rows, {im['n_trees']} trees, "
+                                 f"{args.mc_samples} samples, 20% CoV on kappa and sigma_crit, FP32, screen on",
+                     "wall_s": tm, "n_fail": int(ttf.size), "n_censored": int(len(res) - ttf.size),
+                     "ttf_mean": float(ttf.mean()) if ttf.size else None,
+                     "ttf_cov": float(ttf.std(ddof=1) / ttf.mean()) if ttf.size > 1 else None,
+                     "node_steps": im["node_steps"]}
+        Bm.close()
+        log("bench: mc done")
+
+    if not args.no_cpu:
+        from oracle import oracle as O
+        O.build(force=False)
+        run_c = dict(run)
+        t0 = time.perf_counter()
+        ref = O.run_sample(g, mat, run_c, max_outer=1)
+        tc = time.perf_counter() - t0
+        ns_c = info["n_stress"] * min(run["ir_every"], run["n_steps"])
+        out["cpu_baseline"] = {"value": ns_c / tc, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"pg400, FP64 oracle, first aging interval only "
+                                         f"(IR solve + {run['ir_every']} BE steps of all "
+                                         f"{info['n_stress']} stress nodes + IR re-solve), {tc:.1f} s"}
+        log("bench: cpu baseline done")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,239 @@
+/*
+ * em.h -- C ABI of the MI355X coupled EM/TM stress + IR-drop library.
+ *
+ * The library implements the transient hot path of EMSpice 3 (Lu & Tan,
+ * arXiv 2604.10743): Korhonen stress evolution with electromigration,
+ * stress-migration and thermomigration drives (Sec. III-D, eqs. 10-13),
+ * discretised into the descriptor system C dsigma/dt = A sigma + f (eq. 18)
+ * on every wire tree of an extracted power grid and stepped by backward Euler;
+ * void nucleation against the critical stress, the Robin void row (eq. 20,
+ * Sec. IV-D), void volume by atom conservation (eq. 15), incubation (eq. 16),
+ * early/late failure (Sec. IV-C, eq. 17); periodic IR-drop re-solves of the
+ * nodal system M u = P I (eq. 8) closing the loop to time-to-failure (Fig. 2),
+ * the optional steady-state immortality screen (Sec. II-B) and Monte Carlo
+ * over diffusivity and critical stress (Sec. IV-F).
+ *
+ * Conventions for every entry point:
+ *   - Returns an em_status; never throws, never aborts.  em_last_error() gives a
+ *     human-readable message for the last failing call on a batch.
+ *   - Input arrays are HOST pointers, read during the call and copied; the
+ *     caller may free them afterwards.  Output arrays are HOST pointers owned
+ *     by the caller, sized as documented (counts come from em_get_info).
+ *   - All device memory belongs to the batch and is released by
+ *     em_batch_destroy.  Device work runs on the stream given at creation.
+ *   - A batch is not thread-safe: calls on one batch must not overlap.
+ *   - Asynchronous HIP failures surface as EM_ERR_HIP at the next call that
+ *     synchronises.
+ *   - Units are SI (m, s, K, Pa, A, ohm, V) unless stated.
+ */
+#ifndef EM_MI355X_H
+#define EM_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct em_batch em_batch;   /* opaque, library-owned */
+
+typedef enum {
+    EM_OK = 0,
+    EM_ERR_ARG = 1,       /* invalid argument: NULL, size, NaN, a cycle in a wire tree, ... */
+    EM_ERR_OOM = 2,       /* device or host allocation failed */
+    EM_ERR_HIP = 3,       /* a HIP runtime call or kernel failed */
+    EM_ERR_NOCONV = 4,    /* conjugate gradients missed cg_rtol within cg_max_iter */
+    EM_ERR_STATE = 5,     /* call out of order (e.g. a step on a batch with no currents) */
+    EM_ERR_OVERFLOW = 6   /* event ring overflowed (events beyond its capacity were dropped) */
+} em_status;
+
+typedef enum { EM_FP64 = 0, EM_FP32 = 1 } em_precision;
+
+/* Extracted power-grid netlist (Sec. IV-A: netlist, optional thermal map).
+ * A resistor is a via when res_is_via[r] != 0 or its two nodes lie on
+ * different layers; every other resistor is a wire segment.  Wire segments
+ * on one layer form the wire trees (connected components; a component with a
+ * cycle is rejected with EM_ERR_ARG).  Temperatures: a raster (tmap != NULL,
+ * row-major [tmap_ny][tmap_nx], sample (x,y) -> bilinear with edge clamping),
+ * else per-node node_T (interior FD points interpolate along the segment),
+ * else the uniform em_run_params.T_ambient.  seg_j != NULL switches the batch
+ * to trees-only mode: per-resistor current density prescribed (A/m^2, signed
+ * along res_a -> res_b), no IR solve and no time-to-failure. */
+typedef struct {
+    uint32_t struct_size;           /* sizeof(em_grid_desc) */
+    int32_t n_nodes;
+    const double *xy;               /* [n_nodes][2] node coordinates */
+    const int32_t *layer;           /* [n_nodes] metal layer index (higher = upper) */
+    int32_t n_res;
+    const int32_t *res_a, *res_b;   /* [n_res] end nodes */
+    const double *res_len, *res_w, *res_h;   /* [n_res] length, width, thickness */
+    const uint8_t *res_is_via;      /* [n_res] */
+    const double *res_R0;           /* [n_res] nominal resistance, > 0 */
+    int32_t n_pads;
+    const int32_t *pad_node;        /* [n_pads] ideal VDD sources */
+    double vdd;
+    const double *sink_I;           /* [n_nodes] current drawn at each node, A; may be NULL in trees-only mode */
+    const double *node_T;           /* [n_nodes] K, or NULL */
+    int32_t tmap_nx, tmap_ny;
+    double tmap_x0, tmap_y0, tmap_dx, tmap_dy;
+    const double *tmap;             /* raster, or NULL */
+    const double *seg_j;            /* [n_res] or NULL */
+} em_grid_desc;
+
+/* Material (the paper's YAML material block). Ea and Q in eV. */
+typedef struct {
+    uint32_t struct_size;
+    double B;          /* effective bulk modulus, Pa */
+    double Omega;      /* atomic volume, m^3 */
+    double Z;          /* effective charge number */
+    double rho_cu;     /* copper resistivity, ohm m */
+    double Ea_eV;      /* activation energy of D_a */
+    double D0;         /* diffusion prefactor, m^2/s */
+    double sigma_crit; /* nucleation threshold, Pa */
+    double Q_eV;       /* heat of transport (thermomigration) */
+    double sigma_T;    /* initial residual stress, Pa */
+    double delta;      /* void-interface thickness of the Robin row, m */
+    double rho_ta;     /* liner resistivity, ohm m */
+    double h_ta;       /* liner thickness, m */
+} em_material;
+
+/* Numerics (the paper's YAML numerical block). */
+typedef struct {
+    uint32_t struct_size;
+    int32_t intervals_per_seg;   /* FD intervals per wire segment, >= 1 */
+    double dt;                   /* backward-Euler step, s */
+    int32_t n_steps;             /* horizon in steps for em_run_to_ttf */
+    int32_t ir_every;            /* steps between IR re-solves */
+    double fail_frac;            /* failure when worst IR-drop >= fail_frac * vdd */
+    double cg_rtol;              /* PCG: ||r|| <= cg_rtol ||b|| per sample */
+    int32_t cg_max_iter;
+    int32_t prec;                /* em_precision of the stress stepping */
+    int32_t screen;              /* 1: steady-state immortality screen before stepping */
+    int32_t max_voids_per_tree;  /* 0 disables nucleation */
+    double T_ambient;            /* K, used when no thermal data is given */
+} em_run_params;
+
+/* Monte Carlo (Sec. IV-F): per-segment unit-mean lognormal multipliers on
+ * the diffusivity and the critical stress, coefficient of variation cov_*,
+ * drawn from Philox-4x32-10 with counter (segment, sample, param, 0) and key
+ * (seed low word, seed high word), param 0 = kappa, 1 = sigma_crit. */
+typedef struct {
+    uint32_t struct_size;
+    int32_t n_samples;
+    uint64_t seed;
+    double cov_kappa, cov_scrit;
+} em_mc_params;
+
+typedef struct {
+    double ttf_s;          /* time to failure, s; NaN when censored */
+    double final_drop;     /* worst IR-drop fraction at retirement or at the horizon */
+    double init_drop;      /* worst IR-drop fraction at t = 0 */
+    int32_t failed;        /* 1 if the failure threshold was reached */
+    int32_t outer_idx;     /* IR re-solves done (the one that failed, if failed) */
+    int32_t n_nucleated_trees;
+    int32_t n_failed_segs; /* segments with dR > 0 or open */
+} em_ttf_result;
+
+typedef struct {
+    int32_t n_trees, n_stress, n_samples, n_nodes, n_res;
+    int32_t max_tree_nodes;
+    int32_t prec;
+    int32_t trees_only;
+    int64_t n_events;      /* nucleation events recorded so far (all samples) */
+    int32_t cg_iters_last; /* PCG iterations of the last IR solve */
+    int32_t n_outer_done;
+    int64_t node_steps;    /* stress-node-steps taken: sum over stepped (tree, sample) of nodes x steps */
+    int64_t step_launches; /* launches of the stepping kernel */
+    double step_kernel_ms; /* summed stream time of those launches (HIP events around each) */
+    int64_t cg_iters_total;/* PCG iterations over all IR solves */
+    double ir_ms;          /* summed stream time of the IR solves (HIP events) */
+} em_info;
+
+/* Allocator hook: device memory for the batch (e.g. a framework's caching
+ * allocator).  NULL => hipMalloc/hipFree. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} em_allocator;
+
+/* Build a batch: copies the netlist, partitions it into wire trees (same-layer
+ * components, root = lowest vertex, depth-first in ascending segment order,
+ * each segment refined into intervals_per_seg FD intervals), and on the device
+ * evaluates temperatures, diffusivities, control volumes, Monte Carlo draws
+ * (mc == NULL: one nominal sample) and the tree factors.  Stress starts at
+ * sigma_T.  hip_stream: a hipStream_t, or NULL for the null stream. */
+em_status em_batch_create(const em_grid_desc *grid, const em_material *mat,
+                          const em_run_params *run, const em_mc_params *mc,
+                          const em_allocator *alloc, void *hip_stream, em_batch **out);
+em_status em_batch_destroy(em_batch *b);
+em_status em_get_info(em_batch *b, em_info *info);
+const char *em_last_error(const em_batch *b);
+
+/* IR solve (eq. 8) for every sample with R = R0 + dR (open segments conduct
+ * nothing; nodes with no conducting path to a pad read 0 V), Jacobi-PCG in
+ * FP64 warm-started from the previous solution.  Updates the per-segment
+ * current densities and the stress forcing.  max_drop: [n_samples] host, may
+ * be NULL.  Trees-only batches: EM_ERR_STATE. */
+em_status em_ir_solve(em_batch *b, double *max_drop);
+
+/* Steady-state immortality screen (Sec. II-B) with the current densities of
+ * the last IR solve (or the prescribed ones): a tree is kept for stepping iff
+ * some node's zero-flux steady stress exceeds its critical stress.
+ * tree_mortal: [n_samples][n_trees] host, may be NULL. */
+em_status em_screen(em_batch *b, uint8_t *tree_mortal);
+
+/* Advance every active (sample, tree) by n_steps backward-Euler steps with the
+ * current densities held fixed (quasi-static coupling, Sec. IV-A), checking
+ * nucleation and growing voids after each step.  n_events: new nucleations in
+ * this call, may be NULL. */
+em_status em_stress_step(em_batch *b, int32_t n_steps, int32_t *n_events);
+
+/* Full coupled loop (Fig. 2): IR solve, optional screen, then repeated
+ * {ir_every steps, dR write-back, IR re-solve} until the worst drop reaches
+ * fail_frac (TTF by linear interpolation between re-solves) or the horizon
+ * (censored).  out: [n_samples] host. */
+em_status em_run_to_ttf(em_batch *b, em_ttf_result *out);
+
+/* Return the batch to its state right after creation: stress sigma_T, no
+ * voids, no resistance change, every sample and tree active, IR warm start
+ * at vdd, events and counters cleared.  Netlist, draws and statics are kept. */
+em_status em_reset(em_batch *b);
+
+/* ---- read-back (host outputs) ---- */
+/* Tree partition: tree_off [n_trees+1]; per stress node parent (-1 at a root),
+ * seg (segment of the edge to the parent, -1 at a root), dir (+1 if parent->node
+ * runs res_a->res_b), vert (grid node or -1 for interior FD nodes), kpos (FD
+ * index from res_a); seg_tree [n_res] (-1 for vias).  Any pointer may be NULL. */
+em_status em_get_topology(em_batch *b, int32_t *tree_off, int32_t *parent, int32_t *seg,
+                          int32_t *dir, int32_t *vert, int32_t *kpos, int32_t *seg_tree);
+em_status em_get_stress(em_batch *b, int32_t sample, double *sigma /* [n_stress] */);
+em_status em_set_stress(em_batch *b, int32_t sample, const double *sigma /* [n_stress] */);
+em_status em_get_voltages(em_batch *b, int32_t sample, double *u /* [n_nodes] */);
+em_status em_get_seg_j(em_batch *b, int32_t sample, double *j /* [n_res] */);
+/* dR [n_res] (ohm), open [n_res] (0/1) */
+em_status em_get_seg_state(em_batch *b, int32_t sample, double *dR, uint8_t *open);
+/* Per-node temperature, control volume and critical stress for one sample. */
+em_status em_get_node_state(em_batch *b, int32_t sample, double *T, double *V, double *sc);
+/* Nucleation events, each 5 int32: sample, tree, step, node, host segment;
+ * in no particular order.  *n = number copied (<= cap). */
+em_status em_get_events(em_batch *b, int32_t *buf, int32_t cap, int32_t *n);
+/* Voids of one sample: iv [cap][6] = tree, node, host seg, phase (0 incubation,
+ * 1 growth), nucleation step, early-failure flag; dv [cap][2] = volume (m^3),
+ * length (m).  Ordered by tree, then nucleation order. */
+em_status em_get_voids(em_batch *b, int32_t sample, int32_t *iv, double *dv, int32_t cap, int32_t *n);
+/* Screen output of one sample: tree_mortal [n_trees], seg_mortal [n_res],
+ * sigma_ss [n_stress]; any may be NULL. */
+em_status em_get_screen(em_batch *b, int32_t sample, uint8_t *tree_mortal, uint8_t *seg_mortal,
+                        double *sigma_ss);
+/* Test hook: place a void at stress node `node` of `tree` in `sample` as a
+ * nucleation there would (host segment and failure mode chosen the same way). */
+em_status em_inject_void(em_batch *b, int32_t sample, int32_t tree, int32_t node);
+/* Per-(sample, segment) Monte Carlo multipliers, xi [n_res]; param 0 kappa, 1 sigma_crit. */
+em_status em_get_xi(em_batch *b, int32_t sample, int32_t param, double *xi);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EM_MI355X_H */

@@ -1,0 +1,317 @@
+"""ctypes binding of libem.so (the C ABI declared in include/em.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch supplies device memory (its caching allocator, through
+the em_allocator hook) and the stream.  Loading fails loudly if the library
+has not been built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libem.so")
+
+EM_OK, EM_ERR_ARG, EM_ERR_OOM, EM_ERR_HIP, EM_ERR_NOCONV, EM_ERR_STATE, EM_ERR_OVERFLOW = range(7)
+STATUS_NAMES = {0: "EM_OK", 1: "EM_ERR_ARG", 2: "EM_ERR_OOM", 3: "EM_ERR_HIP", 4: "EM_ERR_NOCONV",
+                5: "EM_ERR_STATE", 6: "EM_ERR_OVERFLOW"}
+
+# Every entry point declared in include/em.h.
+API = ["em_batch_create", "em_batch_destroy", "em_get_info", "em_last_error", "em_ir_solve",
+       "em_screen", "em_stress_step", "em_run_to_ttf", "em_get_topology", "em_get_stress",
+       "em_set_stress", "em_get_voltages", "em_get_seg_j", "em_get_seg_state", "em_get_node_state",
+       "em_get_events", "em_get_voids", "em_get_screen", "em_inject_void", "em_get_xi",
+       "em_reset"]
+
+
+class EmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("n_nodes", C.c_int32), ("xy", C.c_void_p),
+                ("layer", C.c_void_p), ("n_res", C.c_int32), ("res_a", C.c_void_p),
+                ("res_b", C.c_void_p), ("res_len", C.c_void_p), ("res_w", C.c_void_p),
+                ("res_h", C.c_void_p), ("res_is_via", C.c_void_p), ("res_R0", C.c_void_p),
+                ("n_pads", C.c_int32), ("pad_node", C.c_void_p), ("vdd", C.c_double),
+                ("sink_I", C.c_void_p), ("node_T", C.c_void_p), ("tmap_nx", C.c_int32),
+                ("tmap_ny", C.c_int32), ("tmap_x0", C.c_double), ("tmap_y0", C.c_double),
+                ("tmap_dx", C.c_double), ("tmap_dy", C.c_double), ("tmap", C.c_void_p),
+                ("seg_j", C.c_void_p)]
+
+
+class Material(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32)] + [(k, C.c_double) for k in (
+        "B", "Omega", "Z", "rho_cu", "Ea_eV", "D0", "sigma_crit", "Q_eV", "sigma_T", "delta",
+        "rho_ta", "h_ta")]
+
+
+class RunParams(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("intervals_per_seg", C.c_int32), ("dt", C.c_double),
+                ("n_steps", C.c_int32), ("ir_every", C.c_int32), ("fail_frac", C.c_double),
+                ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32), ("prec", C.c_int32),
+                ("screen", C.c_int32), ("max_voids_per_tree", C.c_int32), ("T_ambient", C.c_double)]
+
+
+class MCParams(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("n_samples", C.c_int32), ("seed", C.c_uint64),
+                ("cov_kappa", C.c_double), ("cov_scrit", C.c_double)]
+
+
+class TTFResult(C.Structure):
+    _fields_ = [("ttf_s", C.c_double), ("final_drop", C.c_double), ("init_drop", C.c_double),
+                ("failed", C.c_int32), ("outer_idx", C.c_int32), ("n_nucleated_trees", C.c_int32),
+                ("n_failed_segs", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_trees", C.c_int32), ("n_stress", C.c_int32), ("n_samples", C.c_int32),
+                ("n_nodes", C.c_int32), ("n_res", C.c_int32), ("max_tree_nodes", C.c_int32),
+                ("prec", C.c_int32), ("trees_only", C.c_int32), ("n_events", C.c_int64),
+                ("cg_iters_last", C.c_int32), ("n_outer_done", C.c_int32),
+                ("node_steps", C.c_int64), ("step_launches", C.c_int64),
+                ("step_kernel_ms", C.c_double), ("cg_iters_total", C.c_int64), ("ir_ms", C.c_double)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libem.so; raises if it was not built (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                              "(or python -m paper_2604_10743_amd.build) first")
+        L = C.CDLL(LIB_PATH)
+        L.em_last_error.restype = C.c_char_p
+        L.em_last_error.argtypes = [C.c_void_p]
+        for name in API:
+            if name != "em_last_error":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def _pint(a):
+    return None if a is None else a.ctypes.data
+
+
+class Batch:
+    """One batch of (tree, sample) instances on the current GPU."""
+
+    def __init__(self, grid, mat: dict, run: dict, mc: dict | None = None, stream=None,
+                 torch_alloc: bool = True):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the EM library runs only on the device")
+        self._torch = torch
+        L = lib()
+        self._keep = []
+
+        def keep(a, dt):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=dt)
+            self._keep.append(a)
+            return a
+        g = GridDesc()
+        g.struct_size = C.sizeof(GridDesc)
+        g.n_nodes = grid.n_nodes
+        g.xy = _pint(keep(grid.xy, np.float64))
+        g.layer = _pint(keep(grid.layer, np.int32))
+        g.n_res = grid.n_res
+        g.res_a = _pint(keep(grid.res_a, np.int32)); g.res_b = _pint(keep(grid.res_b, np.int32))
+        g.res_len = _pint(keep(grid.res_len, np.float64)); g.res_w = _pint(keep(grid.res_w, np.float64))
+        g.res_h = _pint(keep(grid.res_h, np.float64))
+        g.res_is_via = _pint(keep(grid.res_is_via, np.uint8))
+        g.res_R0 = _pint(keep(grid.res_R0, np.float64))
+        g.n_pads = int(grid.pad_node.size)
+        g.pad_node = _pint(keep(grid.pad_node, np.int32)) if grid.pad_node.size else None
+        g.vdd = float(grid.vdd)
+        g.sink_I = _pint(keep(grid.sink_I, np.float64))
+        g.node_T = _pint(keep(grid.node_T, np.float64))
+        if grid.tmap is not None:
+            tm = keep(grid.tmap, np.float64)
+            g.tmap = _pint(tm); g.tmap_ny, g.tmap_nx = tm.shape
+            g.tmap_x0, g.tmap_y0 = grid.tmap_x0, grid.tmap_y0
+            g.tmap_dx, g.tmap_dy = grid.tmap_dx, grid.tmap_dy
+        g.seg_j = _pint(keep(grid.seg_j, np.float64))
+        m = Material(struct_size=C.sizeof(Material), **{k: float(mat[k]) for k in (
+            "B", "Omega", "Z", "rho_cu", "Ea_eV", "D0", "sigma_crit", "Q_eV", "sigma_T", "delta",
+            "rho_ta", "h_ta")})
+        r = RunParams(struct_size=C.sizeof(RunParams),
+                      intervals_per_seg=int(run["intervals_per_seg"]), dt=float(run["dt"]),
+                      n_steps=int(run["n_steps"]), ir_every=int(run["ir_every"]),
+                      fail_frac=float(run["fail_frac"]), cg_rtol=float(run["cg_rtol"]),
+                      cg_max_iter=int(run["cg_max_iter"]), prec=int(run["prec"]),
+                      screen=int(run["screen"]), max_voids_per_tree=int(run["max_voids_per_tree"]),
+                      T_ambient=float(run["T_ambient"]))
+        mcp = None
+        if mc is not None:
+            mcp = MCParams(struct_size=C.sizeof(MCParams), n_samples=int(mc["n_samples"]),
+                           seed=int(mc["seed"]), cov_kappa=float(mc["cov_kappa"]),
+                           cov_scrit=float(mc["cov_scrit"]))
+        self._alloc = None
+        if torch_alloc:
+            dev = torch.cuda.current_device()
+            st = torch.cuda.current_stream()
+
+            def _a(nbytes, ctx):
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev, st)
+
+            def _f(ptr, ctx):
+                torch.cuda.caching_allocator_delete(int(ptr))
+            self._alloc_fns = (ALLOC_FN(_a), FREE_FN(_f))
+            self._alloc = Allocator(self._alloc_fns[0], self._alloc_fns[1], None)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        self._h = C.c_void_p()
+        rc = L.em_batch_create(C.byref(g), C.byref(m), C.byref(r),
+                               C.byref(mcp) if mcp is not None else None,
+                               C.byref(self._alloc) if self._alloc is not None else None,
+                               C.c_void_p(stream), C.byref(self._h))
+        if rc != EM_OK:
+            msg = L.em_last_error(self._h).decode() if self._h else ""
+            L.em_batch_destroy(self._h)
+            self._h = None
+            raise EmError(rc, msg)
+        self.grid = grid
+        self.S = int(mc["n_samples"]) if mc else 1
+        inf = self.info()
+        self.n_trees, self.n_stress = inf["n_trees"], inf["n_stress"]
+        self.n_res, self.n_nodes = grid.n_res, grid.n_nodes
+
+    # -- lifecycle --------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().em_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        if rc != EM_OK:
+            raise EmError(rc, lib().em_last_error(self._h).decode())
+
+    # -- entry points -----------------------------------------------------
+    def info(self) -> dict:
+        i = Info()
+        self._chk(lib().em_get_info(self._h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in Info._fields_}
+
+    def ir_solve(self) -> np.ndarray:
+        d = np.zeros(self.S)
+        self._chk(lib().em_ir_solve(self._h, _ptr(d)))
+        return d
+
+    def screen(self) -> np.ndarray:
+        out = np.zeros((self.S, self.n_trees), np.uint8)
+        self._chk(lib().em_screen(self._h, _ptr(out)))
+        return out
+
+    def stress_step(self, n: int) -> int:
+        ne = C.c_int32()
+        self._chk(lib().em_stress_step(self._h, C.c_int32(n), C.byref(ne)))
+        return ne.value
+
+    def reset(self):
+        self._chk(lib().em_reset(self._h))
+
+    def run_to_ttf(self) -> list:
+        res = (TTFResult * self.S)()
+        self._chk(lib().em_run_to_ttf(self._h, res))
+        return [{k: getattr(r, k) for k, _ in TTFResult._fields_} for r in res]
+
+    # -- read-back ------------------------------------------------------------
+    def topology(self) -> dict:
+        t = dict(tree_off=np.zeros(self.n_trees + 1, np.int32),
+                 **{k: np.zeros(self.n_stress, np.int32) for k in ("parent", "seg", "dir", "vert", "kpos")},
+                 seg_tree=np.zeros(self.n_res, np.int32))
+        self._chk(lib().em_get_topology(self._h, *[_ptr(t[k]) for k in (
+            "tree_off", "parent", "seg", "dir", "vert", "kpos", "seg_tree")]))
+        return t
+
+    def stress(self, sample: int = 0) -> np.ndarray:
+        s = np.zeros(self.n_stress)
+        self._chk(lib().em_get_stress(self._h, C.c_int32(sample), _ptr(s)))
+        return s
+
+    def set_stress(self, sigma, sample: int = 0):
+        s = np.ascontiguousarray(sigma, np.float64)
+        self._chk(lib().em_set_stress(self._h, C.c_int32(sample), _ptr(s)))
+
+    def voltages(self, sample: int = 0) -> np.ndarray:
+        u = np.zeros(self.n_nodes)
+        self._chk(lib().em_get_voltages(self._h, C.c_int32(sample), _ptr(u)))
+        return u
+
+    def seg_j(self, sample: int = 0) -> np.ndarray:
+        j = np.zeros(self.n_res)
+        self._chk(lib().em_get_seg_j(self._h, C.c_int32(sample), _ptr(j)))
+        return j
+
+    def seg_state(self, sample: int = 0):
+        dR = np.zeros(self.n_res)
+        op = np.zeros(self.n_res, np.uint8)
+        self._chk(lib().em_get_seg_state(self._h, C.c_int32(sample), _ptr(dR), _ptr(op)))
+        return dR, op
+
+    def node_state(self, sample: int = 0):
+        T = np.zeros(self.n_stress); V = np.zeros(self.n_stress); sc = np.zeros(self.n_stress)
+        self._chk(lib().em_get_node_state(self._h, C.c_int32(sample), _ptr(T), _ptr(V), _ptr(sc)))
+        return T, V, sc
+
+    def events(self) -> np.ndarray:
+        n_ev = self.info()["n_events"]
+        cap = max(int(n_ev), 1)
+        buf = np.zeros((cap, 5), np.int32)
+        n = C.c_int32()
+        self._chk(lib().em_get_events(self._h, _ptr(buf), C.c_int32(cap), C.byref(n)))
+        return buf[:n.value]
+
+    def voids(self, sample: int = 0):
+        n = C.c_int32()
+        self._chk(lib().em_get_voids(self._h, C.c_int32(sample), None, None, C.c_int32(0), C.byref(n)))
+        cap = max(n.value, 1)
+        iv = np.zeros((cap, 6), np.int32)
+        dv = np.zeros((cap, 2))
+        self._chk(lib().em_get_voids(self._h, C.c_int32(sample), _ptr(iv), _ptr(dv), C.c_int32(cap), C.byref(n)))
+        return iv[:n.value], dv[:n.value]
+
+    def screen_state(self, sample: int = 0):
+        tm = np.zeros(self.n_trees, np.uint8)
+        sm = np.zeros(self.n_res, np.uint8)
+        ss = np.zeros(self.n_stress)
+        self._chk(lib().em_get_screen(self._h, C.c_int32(sample), _ptr(tm), _ptr(sm), _ptr(ss)))
+        return tm, sm, ss
+
+    def inject_void(self, sample: int, tree: int, node: int):
+        self._chk(lib().em_inject_void(self._h, C.c_int32(sample), C.c_int32(tree), C.c_int32(node)))
+
+    def xi(self, sample: int = 0, param: int = 0) -> np.ndarray:
+        x = np.zeros(self.n_res)
+        self._chk(lib().em_get_xi(self._h, C.c_int32(sample), C.c_int32(param), _ptr(x)))
+        return x

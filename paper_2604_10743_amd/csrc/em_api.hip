@@ -1,0 +1,921 @@
+// Host runtime and C ABI of the EM/TM library: input validation, wire-tree
+// partition of the netlist (Sec. IV-A), device layout, and the coupled outer
+// loop of Fig. 2 (IR solve -> screen -> {stress steps, dR write-back,
+// IR re-solve} -> time to failure).  All arithmetic of the method runs in the
+// kernels of k_tree.hip and k_ir.hip; the host only does integer topology,
+// memory management, launches and the convergence/retirement control flow.
+#include "em_internal.h"
+#include "../../include/em.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace em;
+
+struct em_batch {
+    em_material mat;
+    em_run_params run;
+    int S = 1;
+    uint64_t seed = 0;
+    double cov_k = 0, cov_s = 0;
+    bool trees_only = false;
+    bool fp32 = false;
+    hipStream_t stream = nullptr;
+    em_allocator alloc{};
+    bool has_alloc = false;
+    std::string err;
+    std::vector<void *> allocs;
+    // host copies of the partition (read-back)
+    int n_nodes = 0, n_res = 0, n_trees = 0, ns = 0, N = 0, max_tree_nodes = 0;
+    std::vector<int> tree_off, parent, seg, dir, vert, kpos, seg_tree;
+    Dev d{};
+    bool have_j = false;
+    bool live_dirty = true;
+    int cg_iters_last = 0;
+    int n_outer_done = 0;
+    int step_counter = 0;         // steps taken through em_stress_step
+    // stream-time accounting with HIP events around each stepping launch and
+    // each IR solve; folded in at the next synchronisation
+    hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr, ev_d = nullptr;
+    bool step_pending = false, ir_pending = false;
+    double step_ms = 0.0, ir_ms = 0.0;
+    long long step_launches = 0, cg_iters_total = 0;
+    uint8_t *h_flags = nullptr;   // pinned scratch for small read-backs
+    size_t h_flags_cap = 0;
+};
+
+namespace {
+
+em_status fail(em_batch *b, em_status st, const std::string &msg)
+{
+    if (b) b->err = msg;
+    return st;
+}
+
+#define HIPCHK(b, call)                                                                   \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail((b), EM_ERR_HIP, std::string(#call " failed: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCHCHK(b)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = hipGetLastError();                                                \
+        if (e_ != hipSuccess)                                                             \
+            return fail((b), EM_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+void *dalloc(em_batch *b, size_t bytes)
+{
+    if (bytes == 0) bytes = 8;
+    bytes = (bytes + 255) & ~(size_t)255;
+    void *p = nullptr;
+    if (b->has_alloc) {
+        p = b->alloc.alloc(bytes, b->alloc.ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (!p) return nullptr;
+    b->allocs.push_back(p);
+    if (hipMemsetAsync(p, 0, bytes, b->stream) != hipSuccess) return nullptr;
+    return p;
+}
+
+template <typename T>
+T *upload(em_batch *b, const std::vector<T> &v)
+{
+    T *p = (T *)dalloc(b, v.size() * sizeof(T));
+    if (!p) return nullptr;
+    if (!v.empty() &&
+        hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, b->stream) != hipSuccess)
+        return nullptr;
+    return p;
+}
+
+template <typename T>
+T *upload_raw(em_batch *b, const T *src, size_t n)
+{
+    T *p = (T *)dalloc(b, n * sizeof(T));
+    if (!p) return nullptr;
+    if (n && hipMemcpyAsync(p, src, n * sizeof(T), hipMemcpyHostToDevice, b->stream) != hipSuccess)
+        return nullptr;
+    return p;
+}
+
+uint8_t *pinned(em_batch *b, size_t n)
+{
+    if (n > b->h_flags_cap) {
+        if (b->h_flags) (void)hipHostFree(b->h_flags);
+        b->h_flags = nullptr;
+        b->h_flags_cap = 0;
+        if (hipHostMalloc((void **)&b->h_flags, n) != hipSuccess) return nullptr;
+        b->h_flags_cap = n;
+    }
+    return b->h_flags;
+}
+
+bool finite_all(const double *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// --------------------------------------------------------------------------
+// Wire-tree partition.  Wire segments on one layer form trees; the root is
+// the lowest-index vertex, the walk is depth-first taking incident segments in
+// ascending index order, and each segment is refined into N intervals whose
+// FD nodes are numbered in visiting (pre-)order, so every parent precedes its
+// children.  Iterative, with an explicit stack of (vertex, node, arrival
+// segment, next incidence) frames.
+// --------------------------------------------------------------------------
+struct Partition {
+    std::vector<int> tree_off, parent, seg, dir, vert, kpos, seg_tree;
+    std::vector<int> inc_off, inc;   // vertex -> wire segments, ascending
+};
+
+em_status partition(em_batch *b, const em_grid_desc *g, int N, Partition &P)
+{
+    const int n = g->n_nodes, m = g->n_res;
+    std::vector<uint8_t> wire(m);
+    for (int r = 0; r < m; ++r)
+        wire[r] = !g->res_is_via[r] && g->layer[g->res_a[r]] == g->layer[g->res_b[r]];
+    P.inc_off.assign(n + 1, 0);
+    for (int r = 0; r < m; ++r) {
+        if (!wire[r]) continue;
+        if (g->res_a[r] == g->res_b[r]) return fail(b, EM_ERR_ARG, "wire segment with both ends on one node");
+        P.inc_off[g->res_a[r] + 1]++;
+        P.inc_off[g->res_b[r] + 1]++;
+    }
+    for (int v = 0; v < n; ++v) P.inc_off[v + 1] += P.inc_off[v];
+    P.inc.assign(P.inc_off[n], 0);
+    {
+        std::vector<int> pos(P.inc_off.begin(), P.inc_off.end() - 1);
+        for (int r = 0; r < m; ++r) {
+            if (!wire[r]) continue;
+            P.inc[pos[g->res_a[r]]++] = r;
+            P.inc[pos[g->res_b[r]]++] = r;
+        }
+    }
+    P.seg_tree.assign(m, -1);
+    std::vector<int> vnode(n, -1);
+    struct Frame { int u, su, from, k; };
+    std::vector<Frame> stack;
+    P.tree_off.assign(1, 0);
+    auto emit = [&](int par, int sg, int dr, int vt, int kp) {
+        P.parent.push_back(par); P.seg.push_back(sg); P.dir.push_back(dr);
+        P.vert.push_back(vt); P.kpos.push_back(kp);
+        return (int)P.parent.size() - 1;
+    };
+    for (int v = 0; v < n; ++v) {
+        if (vnode[v] >= 0 || P.inc_off[v + 1] == P.inc_off[v]) continue;
+        int t = (int)P.tree_off.size() - 1;
+        int s0 = emit(-1, -1, 0, v, 0);
+        vnode[v] = s0;
+        stack.clear();
+        stack.push_back({v, s0, -1, P.inc_off[v]});
+        while (!stack.empty()) {
+            Frame &f = stack.back();
+            if (f.k == P.inc_off[f.u + 1]) { stack.pop_back(); continue; }
+            int e = P.inc[f.k++];
+            if (e == f.from) continue;
+            int a = g->res_a[e], bb = g->res_b[e];
+            int u = f.u, su = f.su;
+            int wv = (a == u) ? bb : a;
+            if (vnode[wv] >= 0)
+                return fail(b, EM_ERR_ARG, "wire component containing node " + std::to_string(u) +
+                                               " has a cycle (not a tree)");
+            P.seg_tree[e] = t;
+            bool fwd = (a == u);
+            int dr = fwd ? 1 : -1;
+            int prev = su;
+            for (int q = 1; q < N; ++q) prev = emit(prev, e, dr, -1, fwd ? q : N - q);
+            int sw = emit(prev, e, dr, wv, fwd ? N : 0);
+            vnode[wv] = sw;
+            stack.push_back({wv, sw, e, P.inc_off[wv]});   // invalidates f
+        }
+        P.tree_off.push_back((int)P.parent.size());
+        if ((long long)P.parent.size() > (1LL << 31) - 64) return fail(b, EM_ERR_ARG, "too many stress nodes");
+    }
+    return EM_OK;
+}
+
+em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, const em_run_params *r,
+                   const em_mc_params *mc)
+{
+    if (!g || !m || !r) return fail(b, EM_ERR_ARG, "grid, material and run must be non-NULL");
+    if (g->struct_size != sizeof(em_grid_desc) || m->struct_size != sizeof(em_material) ||
+        r->struct_size != sizeof(em_run_params) || (mc && mc->struct_size != sizeof(em_mc_params)))
+        return fail(b, EM_ERR_ARG, "struct_size mismatch (ABI version)");
+    if (g->n_nodes <= 0 || g->n_res <= 0 || !g->xy || !g->layer || !g->res_a || !g->res_b ||
+        !g->res_len || !g->res_w || !g->res_h || !g->res_is_via || !g->res_R0)
+        return fail(b, EM_ERR_ARG, "netlist arrays missing or empty");
+    for (int i = 0; i < g->n_res; ++i) {
+        int a = g->res_a[i], c = g->res_b[i];
+        if (a < 0 || a >= g->n_nodes || c < 0 || c >= g->n_nodes) return fail(b, EM_ERR_ARG, "resistor node out of range");
+        bool wire = !g->res_is_via[i] && g->layer[a] == g->layer[c];
+        if (!(g->res_R0[i] > 0) || !std::isfinite(g->res_R0[i])) return fail(b, EM_ERR_ARG, "R0 must be positive and finite");
+        if (wire && (!(g->res_len[i] > 0) || !(g->res_w[i] > 0) || !(g->res_h[i] > 0) ||
+                     !std::isfinite(g->res_len[i]) || !std::isfinite(g->res_w[i]) || !std::isfinite(g->res_h[i])))
+            return fail(b, EM_ERR_ARG, "wire geometry must be positive and finite");
+    }
+    if (!finite_all(g->xy, 2 * (size_t)g->n_nodes)) return fail(b, EM_ERR_ARG, "non-finite coordinates");
+    if (g->node_T && !finite_all(g->node_T, g->n_nodes)) return fail(b, EM_ERR_ARG, "non-finite node_T");
+    if (g->tmap) {
+        if (g->tmap_nx < 1 || g->tmap_ny < 1 || !(g->tmap_dx > 0) || !(g->tmap_dy > 0))
+            return fail(b, EM_ERR_ARG, "bad thermal raster");
+        if (!finite_all(g->tmap, (size_t)g->tmap_nx * g->tmap_ny)) return fail(b, EM_ERR_ARG, "non-finite tmap");
+    }
+    if (g->seg_j) {
+        if (!finite_all(g->seg_j, g->n_res)) return fail(b, EM_ERR_ARG, "non-finite seg_j");
+    } else {
+        if (g->n_pads <= 0 || !g->pad_node || !g->sink_I) return fail(b, EM_ERR_ARG, "coupled mode needs pads and sinks");
+        for (int k = 0; k < g->n_pads; ++k)
+            if (g->pad_node[k] < 0 || g->pad_node[k] >= g->n_nodes) return fail(b, EM_ERR_ARG, "pad out of range");
+        if (!finite_all(g->sink_I, g->n_nodes)) return fail(b, EM_ERR_ARG, "non-finite sinks");
+        if (!(g->vdd > 0)) return fail(b, EM_ERR_ARG, "vdd must be positive");
+    }
+    const double mv[] = {m->B, m->Omega, m->Z, m->rho_cu, m->Ea_eV, m->D0, m->sigma_crit, m->Q_eV,
+                         m->sigma_T, m->delta, m->rho_ta, m->h_ta};
+    if (!finite_all(mv, 12) || !(m->B > 0) || !(m->Omega > 0) || !(m->delta > 0) || !(m->D0 > 0) || !(m->h_ta > 0))
+        return fail(b, EM_ERR_ARG, "bad material constants");
+    if (r->intervals_per_seg < 1 || !(r->dt > 0) || !std::isfinite(r->dt) || r->n_steps < 0 || r->ir_every < 1 ||
+        r->cg_max_iter < 1 || !(r->cg_rtol > 0) || (r->prec != EM_FP64 && r->prec != EM_FP32) ||
+        r->max_voids_per_tree < 0 || r->max_voids_per_tree > MAXV || !(r->T_ambient > 0))
+        return fail(b, EM_ERR_ARG, "bad run parameters (max_voids_per_tree <= 4)");
+    if (mc && (mc->n_samples < 1 || mc->n_samples > 65535 || mc->cov_kappa < 0 || mc->cov_scrit < 0 || !std::isfinite(mc->cov_kappa) ||
+               !std::isfinite(mc->cov_scrit)))
+        return fail(b, EM_ERR_ARG, "bad Monte Carlo parameters");
+    return EM_OK;
+}
+
+em_status ir_solve_impl(em_batch *b)
+{
+    Dev &d = b->d;
+    hipStream_t st = b->stream;
+    launch_ir_conductance(d, st);
+    LAUNCHCHK(b);
+    if (b->live_dirty) {
+        launch_ir_live_init(d, st);
+        uint32_t *hc = (uint32_t *)pinned(b, std::max<size_t>(d.S, 8));
+        if (!hc) return fail(b, EM_ERR_OOM, "pinned host buffer");
+        for (int round = 0;; ++round) {
+            HIPCHK(b, hipMemsetAsync(d.live_changed, 0, 4, st));
+            for (int k = 0; k < 16; ++k) launch_ir_live_step(d, st);
+            LAUNCHCHK(b);
+            HIPCHK(b, hipMemcpyAsync(hc, d.live_changed, 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(b, hipStreamSynchronize(st));
+            if (*hc == 0) break;
+            if (round > d.n_nodes) return fail(b, EM_ERR_HIP, "reachability did not settle");
+        }
+        b->live_dirty = false;
+    }
+    const double rtol = b->run.cg_rtol;
+    launch_ir_setup(d, st);
+    launch_ir_finalize0(d, rtol, st);
+    LAUNCHCHK(b);
+    uint8_t *hconv = pinned(b, std::max<size_t>(d.S, 8));
+    if (!hconv) return fail(b, EM_ERR_OOM, "pinned host buffer");
+    int it = 0;
+    const int check_every = 8;
+    for (;;) {
+        if (it % check_every == 0) {
+            HIPCHK(b, hipMemcpyAsync(hconv, d.conv, d.S, hipMemcpyDeviceToHost, st));
+            HIPCHK(b, hipStreamSynchronize(st));
+            bool all = true;
+            for (int s = 0; s < d.S; ++s) all &= hconv[s] != 0;
+            if (all) break;
+            if (it >= b->run.cg_max_iter) {
+                b->cg_iters_last = it;
+                return fail(b, EM_ERR_NOCONV, "PCG did not reach cg_rtol within cg_max_iter iterations");
+            }
+        }
+        launch_ir_spmv(d, st);
+        launch_ir_update(d, it, st);
+        launch_ir_pupdate(d, it, rtol, st);
+        ++it;
+    }
+    LAUNCHCHK(b);
+    b->cg_iters_last = it;
+    launch_ir_finish(d, st);
+    launch_update_f(d, b->fp32, st);
+    LAUNCHCHK(b);
+    b->have_j = true;
+    return EM_OK;
+}
+
+em_status sync_open_dirty(em_batch *b)
+{
+    uint32_t *h = (uint32_t *)pinned(b, std::max<size_t>(b->d.S, 8));
+    if (!h) return fail(b, EM_ERR_OOM, "pinned host buffer");
+    HIPCHK(b, hipMemcpyAsync(h, b->d.open_dirty, 4, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    if (*h) {
+        b->live_dirty = true;
+        HIPCHK(b, hipMemsetAsync(b->d.open_dirty, 0, 4, b->stream));
+    }
+    return EM_OK;
+}
+
+void fold_timers(em_batch *b)
+{
+    float ms = 0.f;
+    if (b->step_pending && hipEventElapsedTime(&ms, b->ev_a, b->ev_b) == hipSuccess) b->step_ms += ms;
+    b->step_pending = false;
+    if (b->ir_pending && hipEventElapsedTime(&ms, b->ev_c, b->ev_d) == hipSuccess) b->ir_ms += ms;
+    b->ir_pending = false;
+}
+
+em_status timed_step(em_batch *b, int n_steps, int step0)
+{
+    fold_timers(b);
+    HIPCHK(b, hipEventRecord(b->ev_a, b->stream));
+    launch_step(b->d, b->fp32, n_steps, step0, b->stream);
+    LAUNCHCHK(b);
+    HIPCHK(b, hipEventRecord(b->ev_b, b->stream));
+    b->step_pending = true;
+    b->step_launches++;
+    launch_void_dR(b->d, b->stream);
+    LAUNCHCHK(b);
+    return EM_OK;
+}
+
+em_status timed_ir(em_batch *b)
+{
+    HIPCHK(b, hipEventRecord(b->ev_c, b->stream));
+    em_status st = ir_solve_impl(b);
+    if (st != EM_OK) return st;
+    HIPCHK(b, hipEventRecord(b->ev_d, b->stream));
+    b->ir_pending = true;
+    b->cg_iters_total += b->cg_iters_last;
+    return EM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *em_last_error(const em_batch *b)
+{
+    return b ? b->err.c_str() : "null batch";
+}
+
+em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_run_params *r,
+                          const em_mc_params *mc, const em_allocator *alloc, void *hip_stream,
+                          em_batch **out)
+{
+    if (!out) return EM_ERR_ARG;
+    *out = nullptr;
+    em_batch *b = new (std::nothrow) em_batch();
+    if (!b) return EM_ERR_OOM;
+    *out = b;                       // returned even on failure so em_last_error works
+    em_status st = validate(b, g, m, r, mc);
+    if (st != EM_OK) return st;
+    b->mat = *m;
+    b->run = *r;
+    b->S = mc ? mc->n_samples : 1;
+    b->seed = mc ? mc->seed : 0;
+    b->cov_k = mc ? mc->cov_kappa : 0.0;
+    b->cov_s = mc ? mc->cov_scrit : 0.0;
+    b->trees_only = g->seg_j != nullptr;
+    b->fp32 = r->prec == EM_FP32;
+    b->stream = (hipStream_t)hip_stream;
+    if (alloc && alloc->alloc && alloc->free) { b->alloc = *alloc; b->has_alloc = true; }
+
+    const int N = r->intervals_per_seg;
+    Partition P;
+    st = partition(b, g, N, P);
+    if (st != EM_OK) return st;
+    b->n_nodes = g->n_nodes; b->n_res = g->n_res; b->N = N;
+    b->n_trees = (int)P.tree_off.size() - 1;
+    b->ns = (int)P.parent.size();
+    if (b->n_trees == 0) return fail(b, EM_ERR_ARG, "netlist has no wire segment");
+    b->tree_off = P.tree_off; b->parent = P.parent; b->seg = P.seg; b->dir = P.dir;
+    b->vert = P.vert; b->kpos = P.kpos; b->seg_tree = P.seg_tree;
+    const int ns = b->ns, nt = b->n_trees, S = b->S, nr = g->n_res, nn = g->n_nodes;
+    for (int t = 0; t < nt; ++t) b->max_tree_nodes = std::max(b->max_tree_nodes, P.tree_off[t + 1] - P.tree_off[t]);
+    if ((long long)nt * S > (1LL << 31) - 1024 || (long long)ns * S > (1LL << 40))
+        return fail(b, EM_ERR_ARG, "batch too large");
+
+    // children of each stress node, ascending
+    std::vector<int> child_off(ns + 1, 0), child;
+    for (int i = 0; i < ns; ++i) if (P.parent[i] >= 0) child_off[P.parent[i] + 1]++;
+    for (int i = 0; i < ns; ++i) child_off[i + 1] += child_off[i];
+    child.assign(child_off[ns], 0);
+    {
+        std::vector<int> pos(child_off.begin(), child_off.end() - 1);
+        for (int i = 0; i < ns; ++i) if (P.parent[i] >= 0) child[pos[P.parent[i]]++] = i;
+    }
+    // segments of each tree
+    std::vector<int> tseg_off(nt + 1, 0), tseg;
+    for (int e = 0; e < nr; ++e) if (P.seg_tree[e] >= 0) tseg_off[P.seg_tree[e] + 1]++;
+    for (int t = 0; t < nt; ++t) tseg_off[t + 1] += tseg_off[t];
+    tseg.assign(tseg_off[nt], 0);
+    {
+        std::vector<int> pos(tseg_off.begin(), tseg_off.end() - 1);
+        for (int e = 0; e < nr; ++e) if (P.seg_tree[e] >= 0) tseg[pos[P.seg_tree[e]]++] = e;
+    }
+    // via map: a vertex with an inter-layer resistor to a strictly higher layer
+    std::vector<uint8_t> via_up(nn, 0), is_wire(nr, 0), is_pad(nn, 0);
+    for (int e = 0; e < nr; ++e) {
+        int a = g->res_a[e], c = g->res_b[e];
+        is_wire[e] = !g->res_is_via[e] && g->layer[a] == g->layer[c];
+        if (is_wire[e]) continue;
+        if (g->layer[c] > g->layer[a]) via_up[a] = 1;
+        if (g->layer[a] > g->layer[c]) via_up[c] = 1;
+    }
+    if (!b->trees_only)
+        for (int k = 0; k < g->n_pads; ++k) is_pad[g->pad_node[k]] = 1;
+    // node incidence over all resistors (IR)
+    std::vector<int> ninc_off(nn + 1, 0), ninc_res, ninc_nbr;
+    for (int e = 0; e < nr; ++e) { ninc_off[g->res_a[e] + 1]++; ninc_off[g->res_b[e] + 1]++; }
+    for (int v = 0; v < nn; ++v) ninc_off[v + 1] += ninc_off[v];
+    ninc_res.assign(ninc_off[nn], 0); ninc_nbr.assign(ninc_off[nn], 0);
+    {
+        std::vector<int> pos(ninc_off.begin(), ninc_off.end() - 1);
+        for (int e = 0; e < nr; ++e) {
+            int a = g->res_a[e], c = g->res_b[e];
+            ninc_res[pos[a]] = e; ninc_nbr[pos[a]++] = c;
+            ninc_res[pos[c]] = e; ninc_nbr[pos[c]++] = a;
+        }
+    }
+    // lane slots: larger trees first so a wavefront of trees has similar sizes
+    std::vector<int> tree_perm(nt);
+    for (int t = 0; t < nt; ++t) tree_perm[t] = t;
+    std::stable_sort(tree_perm.begin(), tree_perm.end(), [&](int x, int y) {
+        return (P.tree_off[x + 1] - P.tree_off[x]) > (P.tree_off[y + 1] - P.tree_off[y]);
+    });
+
+    Dev &d = b->d;
+    d.n_nodes = nn; d.n_res = nr; d.n_trees = nt; d.ns = ns; d.N = N; d.S = S;
+    d.n_pads = b->trees_only ? 0 : g->n_pads;
+    d.max_voids = r->max_voids_per_tree;
+    d.dt = r->dt; d.vdd = g->vdd;
+    d.B = m->B; d.Omega = m->Omega; d.Z = m->Z; d.rho = m->rho_cu; d.Ea_eV = m->Ea_eV; d.D0 = m->D0;
+    d.scrit = m->sigma_crit; d.Q_eV = m->Q_eV; d.sigT = m->sigma_T; d.delta = m->delta;
+    d.rho_ta = m->rho_ta; d.h_ta = m->h_ta;
+    d.T_amb = r->T_ambient;
+
+#define UP(dst, vec) do { auto *p_ = upload(b, vec); if (!p_) return fail(b, EM_ERR_OOM, "device upload"); dst = p_; } while (0)
+#define UPR(dst, src, n) do { auto *p_ = upload_raw(b, src, n); if (!p_) return fail(b, EM_ERR_OOM, "device upload"); dst = p_; } while (0)
+#define AL(dst, T, n) do { dst = (T *)dalloc(b, sizeof(T) * (size_t)(n)); if (!dst) return fail(b, EM_ERR_OOM, "device allocation"); } while (0)
+
+    UPR(d.xy, g->xy, 2 * (size_t)nn);
+    UPR(d.layer, g->layer, nn);
+    UPR(d.ra, g->res_a, nr); UPR(d.rb, g->res_b, nr);
+    UPR(d.len, g->res_len, nr); UPR(d.w, g->res_w, nr); UPR(d.h, g->res_h, nr); UPR(d.R0, g->res_R0, nr);
+    UP(d.is_wire, is_wire); UP(d.is_pad, is_pad);
+    if (g->sink_I) UPR(d.sink, g->sink_I, nn);
+    else { double *z; AL(z, double, nn); d.sink = z; }
+    UP(d.ninc_off, ninc_off); UP(d.ninc_res, ninc_res); UP(d.ninc_nbr, ninc_nbr);
+    d.node_T = nullptr; d.tmap = nullptr;
+    if (g->tmap) {
+        UPR(d.tmap, g->tmap, (size_t)g->tmap_nx * g->tmap_ny);
+        d.tnx = g->tmap_nx; d.tny = g->tmap_ny;
+        d.tx0 = g->tmap_x0; d.ty0 = g->tmap_y0; d.tdx = g->tmap_dx; d.tdy = g->tmap_dy;
+    } else if (g->node_T) {
+        UPR(d.node_T, g->node_T, nn);
+    }
+    d.seg_j_in = nullptr;
+    if (g->seg_j) UPR(d.seg_j_in, g->seg_j, nr);
+    UP(d.tree_off, P.tree_off); UP(d.parent, P.parent); UP(d.seg, P.seg); UP(d.dir, P.dir);
+    UP(d.vert, P.vert); UP(d.kpos, P.kpos);
+    UP(d.child_off, child_off); UP(d.child, child);
+    UP(d.vinc_off, P.inc_off); UP(d.vinc, P.inc);
+    UP(d.tseg_off, tseg_off); UP(d.tseg, tseg);
+    UP(d.via_up, via_up); UP(d.tree_perm, tree_perm);
+
+    const size_t rs = b->fp32 ? 4 : 8;
+    const size_t NS = (size_t)ns * S, RS = (size_t)nr * S, IS = (size_t)nt * S, VS = (size_t)nn * S;
+    AL(d.T, double, ns); AL(d.V, double, ns); AL(d.g0, double, ns); AL(d.rob0, double, ns);
+    AL(d.gdx0, double, ns); AL(d.mdrv, double, ns);
+    d.Vr = dalloc(b, rs * ns);
+    d.sigma = dalloc(b, rs * NS); d.dtf = dalloc(b, rs * NS); d.dinv = dalloc(b, rs * NS);
+    d.lfac = dalloc(b, rs * NS); d.sc = dalloc(b, rs * NS);
+    if (!d.Vr || !d.sigma || !d.dtf || !d.dinv || !d.lfac || !d.sc) return fail(b, EM_ERR_OOM, "device allocation");
+    AL(d.psi, double, NS);
+    AL(d.xi_k, double, RS); AL(d.xi_s, double, RS);
+    AL(d.jseg, double, RS); AL(d.dR, double, RS); AL(d.open, uint8_t, RS); AL(d.seg_mortal, uint8_t, RS);
+    AL(d.inst_active, uint8_t, IS); AL(d.tree_mortal, uint8_t, IS); AL(d.nv, int, IS);
+    AL(d.vnode, int, IS * MAXV); AL(d.vseg, int, IS * MAXV); AL(d.vphase, int, IS * MAXV);
+    AL(d.vstep, int, IS * MAXV); AL(d.vearly, int, IS * MAXV);
+    AL(d.vvol, double, IS * MAXV); AL(d.vlen, double, IS * MAXV); AL(d.vrob, double, IS * MAXV);
+    AL(d.n_suppressed, int, IS);
+    AL(d.sample_active, uint8_t, S); AL(d.open_dirty, uint32_t, 1);
+    d.ev_cap = 1 << 20;
+    AL(d.events, int, (size_t)d.ev_cap * EV_WORDS); AL(d.ev_count, unsigned int, 1);
+    AL(d.node_steps, unsigned long long, 1);
+    HIPCHK(b, hipEventCreate(&b->ev_a)); HIPCHK(b, hipEventCreate(&b->ev_b));
+    HIPCHK(b, hipEventCreate(&b->ev_c)); HIPCHK(b, hipEventCreate(&b->ev_d));
+    AL(d.G, double, RS);
+    AL(d.diag, double, VS); AL(d.rhs, double, VS); AL(d.u, double, VS); AL(d.r, double, VS);
+    AL(d.z, double, VS); AL(d.p, double, VS); AL(d.q, double, VS);
+    AL(d.live, uint8_t, VS); AL(d.live_changed, uint32_t, 1);
+    d.ir_nblk = (nn + 255) / 256;
+    AL(d.part, double, (size_t)S * d.ir_nblk * 4);
+    AL(d.rz, double, 2 * (size_t)S); AL(d.bb, double, S); AL(d.conv, uint8_t, S); AL(d.drop, double, S);
+    AL(d.ttf, double, S); AL(d.final_drop, double, S); AL(d.init_drop, double, S);
+    AL(d.t_prev, double, S); AL(d.d_prev, double, S); AL(d.failed, int, S); AL(d.outer_idx, int, S);
+
+    hipStream_t stq = b->stream;
+    HIPCHK(b, hipMemsetAsync(d.inst_active, 1, IS, stq));
+    HIPCHK(b, hipMemsetAsync(d.sample_active, 1, S, stq));
+    launch_fill_f64(d.u, VS, g->vdd, stq);
+    launch_node_T(d, stq);
+    launch_edge_static(d, stq);
+    launch_node_V(d, b->fp32, stq);
+    launch_draws(d, b->seed, b->cov_k, b->cov_s, stq);
+    launch_node_sc(d, b->fp32, stq);
+    launch_set_sigma_T(d, b->fp32, stq);
+    LAUNCHCHK(b);
+    if (b->trees_only) {
+        for (int s = 0; s < S; ++s)
+            HIPCHK(b, hipMemcpyAsync(d.jseg + (size_t)s * nr, d.seg_j_in, nr * 8, hipMemcpyDeviceToDevice, stq));
+        launch_update_f(d, b->fp32, stq);
+        b->have_j = true;
+    }
+    launch_factor(d, b->fp32, stq);
+    LAUNCHCHK(b);
+    HIPCHK(b, hipStreamSynchronize(stq));
+    return EM_OK;
+#undef UP
+#undef UPR
+#undef AL
+}
+
+em_status em_batch_destroy(em_batch *b)
+{
+    if (!b) return EM_OK;
+    if (b->stream || !b->allocs.empty()) (void)hipStreamSynchronize(b->stream);
+    for (void *p : b->allocs) {
+        if (b->has_alloc) b->alloc.free(p, b->alloc.ctx);
+        else (void)hipFree(p);
+    }
+    if (b->h_flags) (void)hipHostFree(b->h_flags);
+    for (hipEvent_t e : {b->ev_a, b->ev_b, b->ev_c, b->ev_d})
+        if (e) (void)hipEventDestroy(e);
+    delete b;
+    return EM_OK;
+}
+
+em_status em_get_info(em_batch *b, em_info *info)
+{
+    if (!b || !info) return EM_ERR_ARG;
+    info->n_trees = b->n_trees; info->n_stress = b->ns; info->n_samples = b->S;
+    info->n_nodes = b->n_nodes; info->n_res = b->n_res; info->max_tree_nodes = b->max_tree_nodes;
+    info->prec = b->fp32 ? EM_FP32 : EM_FP64; info->trees_only = b->trees_only ? 1 : 0;
+    unsigned int cnt = 0;
+    if (b->d.ev_count) {
+        HIPCHK(b, hipMemcpyAsync(&cnt, b->d.ev_count, 4, hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(b, hipStreamSynchronize(b->stream));
+    }
+    info->n_events = cnt;
+    info->cg_iters_last = b->cg_iters_last;
+    info->n_outer_done = b->n_outer_done;
+    unsigned long long nsd = 0;
+    HIPCHK(b, hipMemcpyAsync(&nsd, b->d.node_steps, 8, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    fold_timers(b);
+    info->node_steps = (int64_t)nsd;
+    info->step_launches = b->step_launches;
+    info->step_kernel_ms = b->step_ms;
+    info->cg_iters_total = b->cg_iters_total;
+    info->ir_ms = b->ir_ms;
+    return EM_OK;
+}
+
+em_status em_ir_solve(em_batch *b, double *max_drop)
+{
+    if (!b) return EM_ERR_ARG;
+    if (b->trees_only) return fail(b, EM_ERR_STATE, "trees-only batch has no IR network");
+    em_status st = sync_open_dirty(b);
+    if (st != EM_OK) return st;
+    st = timed_ir(b);
+    if (st != EM_OK) return st;
+    if (max_drop) {
+        HIPCHK(b, hipMemcpyAsync(max_drop, b->d.drop, 8 * (size_t)b->S, hipMemcpyDeviceToHost, b->stream));
+    }
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    return EM_OK;
+}
+
+em_status em_screen(em_batch *b, uint8_t *tree_mortal)
+{
+    if (!b) return EM_ERR_ARG;
+    if (!b->have_j) return fail(b, EM_ERR_STATE, "no current densities yet (call em_ir_solve first)");
+    launch_screen(b->d, true, b->stream);
+    LAUNCHCHK(b);
+    if (tree_mortal) {
+        // device layout is [tree][sample]; output is [sample][tree]
+        std::vector<uint8_t> tmp((size_t)b->n_trees * b->S);
+        HIPCHK(b, hipMemcpyAsync(tmp.data(), b->d.tree_mortal, tmp.size(), hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(b, hipStreamSynchronize(b->stream));
+        for (int t = 0; t < b->n_trees; ++t)
+            for (int s = 0; s < b->S; ++s) tree_mortal[(size_t)s * b->n_trees + t] = tmp[(size_t)t * b->S + s];
+    }
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    return EM_OK;
+}
+
+em_status em_stress_step(em_batch *b, int32_t n_steps, int32_t *n_events)
+{
+    if (!b || n_steps < 0) return fail(b, EM_ERR_ARG, "bad step count");
+    if (!b->have_j) return fail(b, EM_ERR_STATE, "no current densities yet (call em_ir_solve first)");
+    unsigned int before = 0, after = 0;
+    HIPCHK(b, hipMemcpyAsync(&before, b->d.ev_count, 4, hipMemcpyDeviceToHost, b->stream));
+    if (n_steps > 0) {
+        em_status st = timed_step(b, n_steps, b->step_counter);
+        if (st != EM_OK) return st;
+        b->step_counter += n_steps;
+    }
+    HIPCHK(b, hipMemcpyAsync(&after, b->d.ev_count, 4, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    if (n_events) *n_events = (int32_t)(after - before);
+    if (after > (unsigned)b->d.ev_cap) return fail(b, EM_ERR_OVERFLOW, "event ring overflow");
+    return EM_OK;
+}
+
+em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
+{
+    if (!b || !out) return fail(b, EM_ERR_ARG, "null output");
+    if (b->trees_only) return fail(b, EM_ERR_STATE, "trees-only batch has no IR coupling");
+    Dev &d = b->d;
+    hipStream_t st = b->stream;
+    const int S = b->S;
+    em_status rc = sync_open_dirty(b);
+    if (rc != EM_OK) return rc;
+    rc = timed_ir(b);
+    if (rc != EM_OK) return rc;
+    const double fail_frac = b->run.fail_frac;
+    launch_ttf_init(d, fail_frac, st);
+    if (b->run.screen) launch_screen(d, true, st);
+    LAUNCHCHK(b);
+    uint8_t *h = pinned(b, std::max<size_t>(S, 8));
+    if (!h) return fail(b, EM_ERR_OOM, "pinned host buffer");
+    const int n_steps = b->run.n_steps, K = b->run.ir_every;
+    int done = 0, k = 0;
+    while (done < n_steps) {
+        HIPCHK(b, hipMemcpyAsync(h, d.sample_active, S, hipMemcpyDeviceToHost, st));
+        HIPCHK(b, hipStreamSynchronize(st));
+        int n_active = 0;
+        for (int s = 0; s < S; ++s) n_active += h[s] != 0;
+        if (n_active == 0) break;
+        int nst = std::min(K, n_steps - done);
+        rc = timed_step(b, nst, done);
+        if (rc != EM_OK) return rc;
+        done += nst;
+        ++k;
+        rc = sync_open_dirty(b);
+        if (rc != EM_OK) return rc;
+        fold_timers(b);
+        rc = timed_ir(b);
+        if (rc != EM_OK) return rc;
+        launch_ttf_update(d, fail_frac, k, done * b->run.dt, st);
+        LAUNCHCHK(b);
+    }
+    b->n_outer_done = k;
+    // per-sample results
+    std::vector<double> ttf(S), fd(S), idr(S);
+    std::vector<int> failed(S), oidx(S), nv((size_t)b->n_trees * S);
+    std::vector<double> dR((size_t)S * b->n_res);
+    std::vector<uint8_t> op((size_t)S * b->n_res);
+    HIPCHK(b, hipMemcpyAsync(ttf.data(), d.ttf, 8 * S, hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipMemcpyAsync(fd.data(), d.final_drop, 8 * S, hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipMemcpyAsync(idr.data(), d.init_drop, 8 * S, hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipMemcpyAsync(failed.data(), d.failed, 4 * S, hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipMemcpyAsync(oidx.data(), d.outer_idx, 4 * S, hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipMemcpyAsync(nv.data(), d.nv, 4 * nv.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipMemcpyAsync(dR.data(), d.dR, 8 * dR.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipMemcpyAsync(op.data(), d.open, op.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipStreamSynchronize(st));
+    fold_timers(b);
+    for (int s = 0; s < S; ++s) {
+        em_ttf_result &o = out[s];
+        o.ttf_s = ttf[s]; o.final_drop = fd[s]; o.init_drop = idr[s];
+        o.failed = failed[s]; o.outer_idx = oidx[s];
+        int nn = 0;
+        for (int t = 0; t < b->n_trees; ++t) nn += nv[(size_t)t * S + s] > 0;
+        o.n_nucleated_trees = nn;
+        int nf = 0;
+        for (int e = 0; e < b->n_res; ++e)
+            nf += (dR[(size_t)s * b->n_res + e] > 0.0) || op[(size_t)s * b->n_res + e];
+        o.n_failed_segs = nf;
+    }
+    return EM_OK;
+}
+
+em_status em_reset(em_batch *b)
+{
+    if (!b) return EM_ERR_ARG;
+    Dev &d = b->d;
+    hipStream_t st = b->stream;
+    const size_t IS = (size_t)d.n_trees * d.S, RS = (size_t)d.n_res * d.S, VS = (size_t)d.n_nodes * d.S;
+    HIPCHK(b, hipStreamSynchronize(st));
+    fold_timers(b);
+    HIPCHK(b, hipMemsetAsync(d.nv, 0, 4 * IS, st));
+    HIPCHK(b, hipMemsetAsync(d.n_suppressed, 0, 4 * IS, st));
+    HIPCHK(b, hipMemsetAsync(d.inst_active, 1, IS, st));
+    HIPCHK(b, hipMemsetAsync(d.sample_active, 1, d.S, st));
+    HIPCHK(b, hipMemsetAsync(d.dR, 0, 8 * RS, st));
+    HIPCHK(b, hipMemsetAsync(d.open, 0, RS, st));
+    HIPCHK(b, hipMemsetAsync(d.ev_count, 0, 4, st));
+    HIPCHK(b, hipMemsetAsync(d.node_steps, 0, 8, st));
+    HIPCHK(b, hipMemsetAsync(d.open_dirty, 0, 4, st));
+    launch_fill_f64(d.u, VS, d.vdd, st);
+    launch_set_sigma_T(d, b->fp32, st);
+    launch_factor(d, b->fp32, st);
+    LAUNCHCHK(b);
+    HIPCHK(b, hipStreamSynchronize(st));
+    b->live_dirty = true;
+    b->have_j = b->trees_only;
+    b->step_counter = 0;
+    b->n_outer_done = 0;
+    b->cg_iters_last = 0;
+    b->cg_iters_total = 0;
+    b->step_launches = 0;
+    b->step_ms = b->ir_ms = 0.0;
+    return EM_OK;
+}
+
+em_status em_get_topology(em_batch *b, int32_t *tree_off, int32_t *parent, int32_t *seg, int32_t *dir,
+                          int32_t *vert, int32_t *kpos, int32_t *seg_tree)
+{
+    if (!b) return EM_ERR_ARG;
+    auto cp = [](int32_t *dst, const std::vector<int> &v) { if (dst) std::memcpy(dst, v.data(), 4 * v.size()); };
+    cp(tree_off, b->tree_off); cp(parent, b->parent); cp(seg, b->seg); cp(dir, b->dir);
+    cp(vert, b->vert); cp(kpos, b->kpos); cp(seg_tree, b->seg_tree);
+    return EM_OK;
+}
+
+static em_status column_io(em_batch *b, int sample, double *host, bool to_state, int which)
+{
+    if (!b || !host || sample < 0 || sample >= b->S) return fail(b, EM_ERR_ARG, "bad sample or buffer");
+    double *buf = nullptr;
+    HIPCHK(b, hipMalloc(&buf, 8 * (size_t)b->ns));
+    hipError_t e = hipSuccess;
+    if (to_state) e = hipMemcpyAsync(buf, host, 8 * (size_t)b->ns, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) {
+        if (which < 0) launch_copy_sigma(b->d, b->fp32, sample, buf, to_state, b->stream);
+        else launch_copy_node_col(b->d, b->fp32, which, sample, buf, b->stream);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && !to_state)
+        e = hipMemcpyAsync(host, buf, 8 * (size_t)b->ns, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return fail(b, EM_ERR_HIP, std::string("column copy: ") + hipGetErrorString(e));
+    return EM_OK;
+}
+
+em_status em_get_stress(em_batch *b, int32_t sample, double *sigma) { return column_io(b, sample, sigma, false, -1); }
+em_status em_set_stress(em_batch *b, int32_t sample, const double *sigma)
+{
+    return column_io(b, sample, const_cast<double *>(sigma), true, -1);
+}
+
+em_status em_get_node_state(em_batch *b, int32_t sample, double *T, double *V, double *sc)
+{
+    if (!b || sample < 0 || sample >= b->S) return fail(b, EM_ERR_ARG, "bad sample");
+    if (T) HIPCHK(b, hipMemcpyAsync(T, b->d.T, 8 * (size_t)b->ns, hipMemcpyDeviceToHost, b->stream));
+    if (V) HIPCHK(b, hipMemcpyAsync(V, b->d.V, 8 * (size_t)b->ns, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    if (sc) return column_io(b, sample, sc, false, 0);
+    return EM_OK;
+}
+
+em_status em_get_voltages(em_batch *b, int32_t sample, double *u)
+{
+    if (!b || !u || sample < 0 || sample >= b->S) return fail(b, EM_ERR_ARG, "bad sample or buffer");
+    HIPCHK(b, hipMemcpyAsync(u, b->d.u + (size_t)sample * b->n_nodes, 8 * (size_t)b->n_nodes,
+                             hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    return EM_OK;
+}
+
+em_status em_get_seg_j(em_batch *b, int32_t sample, double *j)
+{
+    if (!b || !j || sample < 0 || sample >= b->S) return fail(b, EM_ERR_ARG, "bad sample or buffer");
+    HIPCHK(b, hipMemcpyAsync(j, b->d.jseg + (size_t)sample * b->n_res, 8 * (size_t)b->n_res,
+                             hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    return EM_OK;
+}
+
+em_status em_get_seg_state(em_batch *b, int32_t sample, double *dR, uint8_t *open)
+{
+    if (!b || sample < 0 || sample >= b->S) return fail(b, EM_ERR_ARG, "bad sample");
+    if (dR) HIPCHK(b, hipMemcpyAsync(dR, b->d.dR + (size_t)sample * b->n_res, 8 * (size_t)b->n_res,
+                                     hipMemcpyDeviceToHost, b->stream));
+    if (open) HIPCHK(b, hipMemcpyAsync(open, b->d.open + (size_t)sample * b->n_res, (size_t)b->n_res,
+                                       hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    return EM_OK;
+}
+
+em_status em_get_events(em_batch *b, int32_t *buf, int32_t cap, int32_t *n)
+{
+    if (!b || cap < 0 || (cap > 0 && !buf)) return fail(b, EM_ERR_ARG, "bad event buffer");
+    unsigned int cnt = 0;
+    HIPCHK(b, hipMemcpyAsync(&cnt, b->d.ev_count, 4, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    int avail = (int)std::min<unsigned int>(cnt, (unsigned)b->d.ev_cap);
+    int k = std::min(avail, cap);
+    if (k > 0) {
+        HIPCHK(b, hipMemcpyAsync(buf, b->d.events, 4 * (size_t)k * EV_WORDS, hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(b, hipStreamSynchronize(b->stream));
+    }
+    if (n) *n = k;
+    if (cnt > (unsigned)b->d.ev_cap) return fail(b, EM_ERR_OVERFLOW, "event ring overflow");
+    return EM_OK;
+}
+
+em_status em_get_voids(em_batch *b, int32_t sample, int32_t *iv, double *dv, int32_t cap, int32_t *n)
+{
+    if (!b || sample < 0 || sample >= b->S || cap < 0) return fail(b, EM_ERR_ARG, "bad arguments");
+    const int S = b->S, nt = b->n_trees;
+    std::vector<int> nv((size_t)nt * S), vn((size_t)nt * S * MAXV), vs(vn.size()), vp(vn.size()),
+        vst(vn.size()), ve(vn.size());
+    std::vector<double> vv(vn.size()), vl(vn.size());
+    hipStream_t st = b->stream;
+    HIPCHK(b, hipMemcpyAsync(nv.data(), b->d.nv, 4 * nv.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipMemcpyAsync(vn.data(), b->d.vnode, 4 * vn.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipMemcpyAsync(vs.data(), b->d.vseg, 4 * vn.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipMemcpyAsync(vp.data(), b->d.vphase, 4 * vn.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipMemcpyAsync(vst.data(), b->d.vstep, 4 * vn.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipMemcpyAsync(ve.data(), b->d.vearly, 4 * vn.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipMemcpyAsync(vv.data(), b->d.vvol, 8 * vn.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipMemcpyAsync(vl.data(), b->d.vlen, 8 * vn.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipStreamSynchronize(st));
+    int c = 0;
+    for (int t = 0; t < nt; ++t) {
+        int inst = t * S + sample;
+        for (int k = 0; k < nv[inst]; ++k) {
+            int q = inst * MAXV + k;
+            if (c < cap) {
+                if (iv) {
+                    int32_t *I = iv + 6 * (size_t)c;
+                    I[0] = t; I[1] = vn[q]; I[2] = vs[q]; I[3] = vp[q]; I[4] = vst[q]; I[5] = ve[q];
+                }
+                if (dv) { dv[2 * (size_t)c] = vv[q]; dv[2 * (size_t)c + 1] = vl[q]; }
+            }
+            ++c;
+        }
+    }
+    if (n) *n = c;
+    return EM_OK;
+}
+
+em_status em_get_screen(em_batch *b, int32_t sample, uint8_t *tree_mortal, uint8_t *seg_mortal, double *sigma_ss)
+{
+    if (!b || sample < 0 || sample >= b->S) return fail(b, EM_ERR_ARG, "bad sample");
+    const int S = b->S;
+    hipStream_t st = b->stream;
+    if (tree_mortal) {
+        std::vector<uint8_t> tmp((size_t)b->n_trees * S);
+        HIPCHK(b, hipMemcpyAsync(tmp.data(), b->d.tree_mortal, tmp.size(), hipMemcpyDeviceToHost, st));
+        HIPCHK(b, hipStreamSynchronize(st));
+        for (int t = 0; t < b->n_trees; ++t) tree_mortal[t] = tmp[(size_t)t * S + sample];
+    }
+    if (seg_mortal)
+        HIPCHK(b, hipMemcpyAsync(seg_mortal, b->d.seg_mortal + (size_t)sample * b->n_res, b->n_res,
+                                 hipMemcpyDeviceToHost, st));
+    if (sigma_ss) {
+        std::vector<double> tmp((size_t)b->ns * S);
+        HIPCHK(b, hipMemcpyAsync(tmp.data(), b->d.psi, 8 * tmp.size(), hipMemcpyDeviceToHost, st));
+        HIPCHK(b, hipStreamSynchronize(st));
+        for (int i = 0; i < b->ns; ++i) sigma_ss[i] = tmp[(size_t)i * S + sample];
+    }
+    HIPCHK(b, hipStreamSynchronize(st));
+    return EM_OK;
+}
+
+em_status em_inject_void(em_batch *b, int32_t sample, int32_t tree, int32_t node)
+{
+    if (!b || sample < 0 || sample >= b->S || tree < 0 || tree >= b->n_trees ||
+        node < b->tree_off[tree] || node >= b->tree_off[tree + 1])
+        return fail(b, EM_ERR_ARG, "bad void location");
+    launch_inject_void(b->d, b->fp32, sample, tree, node, b->stream);
+    LAUNCHCHK(b);
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    return EM_OK;
+}
+
+em_status em_get_xi(em_batch *b, int32_t sample, int32_t param, double *xi)
+{
+    if (!b || !xi || sample < 0 || sample >= b->S || (param != 0 && param != 1))
+        return fail(b, EM_ERR_ARG, "bad arguments");
+    const int S = b->S;
+    std::vector<double> tmp((size_t)b->n_res * S);
+    HIPCHK(b, hipMemcpyAsync(tmp.data(), param == 0 ? b->d.xi_k : b->d.xi_s, 8 * tmp.size(),
+                             hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    for (int e = 0; e < b->n_res; ++e) xi[e] = tmp[(size_t)e * S + sample];
+    return EM_OK;
+}
+
+}  // extern "C"

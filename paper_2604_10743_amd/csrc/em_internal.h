@@ -1,0 +1,124 @@
+// Internal device-side data layout and kernel launchers of the EM/TM library.
+//
+// Layouts (S = number of Monte Carlo samples):
+//   stress-node arrays   [node][S]  (sample fastest: the lanes of a wavefront
+//                                    are samples of one tree, or trees when
+//                                    S == 1)
+//   IR node vectors      [S][node]  (node fastest: per-sample reductions over
+//                                    contiguous ranges)
+//   per-segment MC draws [res][S]
+//   per-segment state    [S][res]   (dR, open, current density)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace em {
+
+constexpr int MAXV = 4;                 // void slots per (tree, sample)
+constexpr double E_CHG = 1.602176634e-19;
+constexpr double K_B = 1.380649e-23;
+constexpr int EV_WORDS = 5;             // sample, tree, step, node, host segment
+
+struct Dev {
+    // ---- sizes ----
+    int n_nodes, n_res, n_trees, ns, N, S, n_pads;
+    int max_voids;
+    double dt, vdd;
+    // material
+    double B, Omega, Z, rho, Ea_eV, D0, scrit, Q_eV, sigT, delta, rho_ta, h_ta;
+    // ---- netlist (shared) ----
+    const double *xy;
+    const int *layer;
+    const int *ra, *rb;
+    const double *len, *w, *h, *R0;
+    const uint8_t *is_wire;             // 1 for a wire segment
+    const double *sink;
+    const uint8_t *is_pad;              // [n_nodes]
+    const int *ninc_off, *ninc_res, *ninc_nbr;   // node incidence (all resistors)
+    // temperature inputs
+    const double *node_T;               // may be null
+    const double *tmap;                 // may be null
+    int tnx, tny;
+    double tx0, ty0, tdx, tdy, T_amb;
+    const double *seg_j_in;             // trees-only prescribed j (null otherwise)
+    // ---- tree topology (shared) ----
+    const int *tree_off, *parent, *seg, *dir, *vert, *kpos;
+    const int *child_off, *child;       // children of each stress node, ascending
+    const int *vinc_off, *vinc;         // wire segments incident to each vertex, ascending
+    const int *tseg_off, *tseg;         // segments of each tree
+    const uint8_t *via_up;              // vertex has a via to a strictly higher layer
+    const int *tree_perm;               // lane slot -> tree id (larger trees first)
+    // ---- per stress node statics (FP64) ----
+    double *T, *V, *g0, *rob0, *gdx0, *mdrv;
+    // ---- per (node, sample) stepping state; element type float or double ----
+    void *sigma, *dtf, *dinv, *lfac, *sc, *Vr;
+    double *psi;                        // screen scratch / steady stress [node][S]
+    // ---- Monte Carlo draws [res][S] ----
+    double *xi_k, *xi_s;
+    // ---- per (sample, segment) ----
+    double *jseg;                       // [S][res]
+    double *dR;                         // [S][res]
+    uint8_t *open;                      // [S][res]
+    uint8_t *seg_mortal;                // [S][res]
+    // ---- per instance (tree, sample), inst = tree * S + sample ----
+    uint8_t *inst_active;               // stepped at all (screen)
+    uint8_t *tree_mortal;               // screen verdict
+    int *nv;                            // voids in use
+    int *vnode, *vseg, *vphase, *vstep, *vearly;   // [inst][MAXV]
+    double *vvol, *vlen, *vrob;         // [inst][MAXV]
+    int *n_suppressed;                  // [inst]
+    // ---- per sample ----
+    uint8_t *sample_active;             // not yet retired
+    uint32_t *open_dirty;               // [1] set when a segment opened
+    unsigned long long *node_steps;     // [1] stepped (node, sample) x steps
+    // ---- events ----
+    int *events;                        // [ev_cap][EV_WORDS]
+    unsigned int *ev_count;
+    int ev_cap;
+    // ---- IR ([S][n_nodes] unless noted) ----
+    double *G;                          // [S][res] conductance
+    double *diag, *rhs, *u, *r, *z, *p, *q;
+    uint8_t *live;                      // [S][n_nodes]
+    uint32_t *live_changed;
+    double *part;                       // [S][nblk][4] block partial sums
+    double *rz;                         // [2][S]
+    double *bb;                         // [S]
+    uint8_t *conv;                      // [S]
+    double *drop;                       // [S]
+    int ir_nblk;
+    // ---- TTF ----
+    double *ttf, *final_drop, *init_drop, *t_prev, *d_prev;
+    int *failed, *outer_idx;
+};
+
+// ---- launchers (defined in the kernel translation units) ----
+void launch_node_T(const Dev &d, hipStream_t st);
+void launch_edge_static(const Dev &d, hipStream_t st);
+void launch_node_V(const Dev &d, bool fp32, hipStream_t st);
+void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, hipStream_t st);
+void launch_node_sc(const Dev &d, bool fp32, hipStream_t st);
+void launch_update_f(const Dev &d, bool fp32, hipStream_t st);
+void launch_factor(const Dev &d, bool fp32, hipStream_t st);
+void launch_screen(const Dev &d, bool apply, hipStream_t st);
+void launch_step(const Dev &d, bool fp32, int n_steps, int step0, hipStream_t st);
+void launch_void_dR(const Dev &d, hipStream_t st);
+void launch_set_sigma_T(const Dev &d, bool fp32, hipStream_t st);
+void launch_inject_void(const Dev &d, bool fp32, int sample, int tree, int node, hipStream_t st);
+void launch_copy_sigma(const Dev &d, bool fp32, int sample, double *out_dev, bool to_state, hipStream_t st);
+void launch_copy_node_col(const Dev &d, bool fp32, int which, int sample, double *out_dev, hipStream_t st);
+
+// IR
+void launch_ir_conductance(const Dev &d, hipStream_t st);
+void launch_ir_live_init(const Dev &d, hipStream_t st);
+void launch_ir_live_step(const Dev &d, hipStream_t st);
+void launch_ir_setup(const Dev &d, hipStream_t st);       // diag, rhs, r = b - A x, z, p, partials
+void launch_ir_finalize0(const Dev &d, double rtol, hipStream_t st);
+void launch_ir_spmv(const Dev &d, hipStream_t st);        // q = A p, partial p.q
+void launch_ir_update(const Dev &d, int it, hipStream_t st);   // x,r,z; partial r.z, r.r
+void launch_ir_pupdate(const Dev &d, int it, double rtol, hipStream_t st);  // p = z + beta p, conv
+void launch_ir_finish(const Dev &d, hipStream_t st);      // u, j, drop
+void launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
+void launch_ttf_init(const Dev &d, double fail, hipStream_t st);
+void launch_ttf_update(const Dev &d, double fail, int k, double t, hipStream_t st);
+
+}  // namespace em

@@ -1,0 +1,360 @@
+// IR-drop solve (Sec. II-C, eq. 8): nodal analysis M u = P I of the resistor
+// network with ideal VDD pads, batched over Monte Carlo samples.  Jacobi-
+// preconditioned conjugate gradients in FP64 on the free nodes (live, not a
+// pad); an open segment conducts nothing and a node with no conducting path
+// to a pad reads 0 V.  Vectors are [S][node]; a block covers 256 nodes of one
+// sample and per-sample dot products are reduced deterministically through
+// per-block partials.  The time-to-failure bookkeeping of the outer loop
+// (Fig. 2, Table I caption) lives here too.
+#include "em_internal.h"
+#include <cmath>
+
+namespace em {
+
+#define IR_BS 256
+#define EM_KERNEL __global__ __launch_bounds__(IR_BS)
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Sum of up to 4 per-thread values over the block; thread 0 writes them to
+// part[(s*nblk + bx)*4 + slot].
+__device__ inline void block_partials(const Dev &d, int s, int bx, double v0, double v1, double v2,
+                                      double v3, int mask)
+{
+    __shared__ double red[4][IR_BS / 64];
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double v[4] = {v0, v1, v2, v3};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        if (!(mask & (1 << c))) continue;
+        double x = wave_sum(v[c]);
+        if (lane == 0) red[c][wid] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double *P = d.part + ((size_t)s * d.ir_nblk + bx) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (!(mask & (1 << c))) continue;
+            double acc = 0.0;
+            for (int w = 0; w < IR_BS / 64; ++w) acc += red[c][w];
+            P[c] = acc;
+        }
+    }
+}
+
+// Deterministic sum of partial `slot` over all blocks of sample s, broadcast
+// to every thread of the block.
+__device__ inline double sum_partials(const Dev &d, int s, int slot)
+{
+    __shared__ double bc;
+    if (threadIdx.x < 64) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < d.ir_nblk; b += 64)
+            acc += d.part[((size_t)s * d.ir_nblk + b) * 4 + slot];
+        acc = wave_sum(acc);
+        if (threadIdx.x == 0) bc = acc;
+    }
+    __syncthreads();
+    double r = bc;
+    __syncthreads();
+    return r;
+}
+
+__device__ inline bool is_free(const Dev &d, int s, int i)
+{
+    return d.live[(size_t)s * d.n_nodes + i] && !d.is_pad[i];
+}
+
+EM_KERNEL void k_ir_conductance(Dev d)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)d.S * d.n_res) return;
+    int r = (int)(g % d.n_res);
+    d.G[g] = d.open[g] ? 0.0 : 1.0 / (d.R0[r] + d.dR[g]);
+}
+
+EM_KERNEL void k_ir_live_init(Dev d)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)d.S * d.n_nodes) return;
+    int i = (int)(g % d.n_nodes);
+    d.live[g] = d.is_pad[i];
+}
+
+// One relaxation of reachability from the pads over conducting resistors.
+// Flags only ever go 0 -> 1, so concurrent updates are benign.
+EM_KERNEL void k_ir_live_step(Dev d)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)d.S * d.n_nodes) return;
+    int s = (int)(g / d.n_nodes), i = (int)(g % d.n_nodes);
+    if (d.live[g]) return;
+    const double *G = d.G + (size_t)s * d.n_res;
+    const uint8_t *L = d.live + (size_t)s * d.n_nodes;
+    for (int k = d.ninc_off[i]; k < d.ninc_off[i + 1]; ++k) {
+        if (G[d.ninc_res[k]] > 0.0 && L[d.ninc_nbr[k]]) {
+            d.live[g] = 1;
+            *d.live_changed = 1u;
+            return;
+        }
+    }
+}
+
+// Diagonal, right-hand side (sinks and pad injections), residual of the warm
+// start, z = r/diag, p = z; partials r.z, r.r, b.b.
+EM_KERNEL void k_ir_setup(Dev d)
+{
+    int s = blockIdx.y, bx = blockIdx.x;
+    int i = bx * IR_BS + threadIdx.x;
+    double rz = 0, rr = 0, bbv = 0;
+    if (i < d.n_nodes) {
+        size_t x = (size_t)s * d.n_nodes + i;
+        const double *G = d.G + (size_t)s * d.n_res;
+        const double *u = d.u + (size_t)s * d.n_nodes;
+        double dg = 0.0;
+        for (int k = d.ninc_off[i]; k < d.ninc_off[i + 1]; ++k) dg += G[d.ninc_res[k]];
+        d.diag[x] = dg;
+        if (is_free(d, s, i)) {
+            double b = -d.sink[i], Ax = dg * u[i];
+            for (int k = d.ninc_off[i]; k < d.ninc_off[i + 1]; ++k) {
+                int nb = d.ninc_nbr[k];
+                double gk = G[d.ninc_res[k]];
+                if (d.is_pad[nb]) b += gk * d.vdd;
+                else if (is_free(d, s, nb)) Ax -= gk * u[nb];
+            }
+            double r = b - Ax, z = r / dg;
+            d.rhs[x] = b; d.r[x] = r; d.z[x] = z; d.p[x] = z;
+            rz = r * z; rr = r * r; bbv = b * b;
+        } else {
+            d.rhs[x] = 0; d.r[x] = 0; d.z[x] = 0; d.p[x] = 0;
+        }
+    }
+    block_partials(d, s, bx, 0.0, rz, rr, bbv, 0xE);
+}
+
+EM_KERNEL void k_ir_finalize0(Dev d, double rtol)
+{
+    int s = blockIdx.x;
+    double rz = sum_partials(d, s, 1);
+    double rr = sum_partials(d, s, 2);
+    double bb = sum_partials(d, s, 3);
+    if (threadIdx.x == 0) {
+        d.rz[s] = rz;
+        d.bb[s] = bb;
+        d.conv[s] = (!d.sample_active[s] || rr <= rtol * rtol * bb) ? 1 : 0;
+    }
+}
+
+EM_KERNEL void k_ir_spmv(Dev d)
+{
+    int s = blockIdx.y, bx = blockIdx.x;
+    int i = bx * IR_BS + threadIdx.x;
+    double pq = 0;
+    if (i < d.n_nodes && !d.conv[s]) {
+        size_t x = (size_t)s * d.n_nodes + i;
+        double q = 0.0;
+        if (is_free(d, s, i)) {
+            const double *G = d.G + (size_t)s * d.n_res;
+            const double *p = d.p + (size_t)s * d.n_nodes;
+            q = d.diag[x] * p[i];
+            for (int k = d.ninc_off[i]; k < d.ninc_off[i + 1]; ++k) {
+                int nb = d.ninc_nbr[k];
+                if (is_free(d, s, nb)) q -= G[d.ninc_res[k]] * p[nb];
+            }
+            pq = p[i] * q;
+        }
+        d.q[x] = q;
+    }
+    block_partials(d, s, bx, pq, 0.0, 0.0, 0.0, 0x1);
+}
+
+EM_KERNEL void k_ir_update(Dev d, int it)
+{
+    int s = blockIdx.y, bx = blockIdx.x;
+    int i = bx * IR_BS + threadIdx.x;
+    bool active = !d.conv[s];
+    double pq = active ? sum_partials(d, s, 0) : 0.0;
+    double alpha = (active && pq > 0.0) ? d.rz[(it & 1) * d.S + s] / pq : 0.0;
+    double rz = 0, rr = 0;
+    if (i < d.n_nodes && active && is_free(d, s, i)) {
+        size_t x = (size_t)s * d.n_nodes + i;
+        d.u[x] += alpha * d.p[x];
+        double r = d.r[x] - alpha * d.q[x];
+        double z = r / d.diag[x];
+        d.r[x] = r; d.z[x] = z;
+        rz = r * z; rr = r * r;
+    }
+    if (active) block_partials(d, s, bx, 0.0, rz, rr, 0.0, 0x6);
+}
+
+EM_KERNEL void k_ir_pupdate(Dev d, int it, double rtol)
+{
+    int s = blockIdx.y, bx = blockIdx.x;
+    int i = bx * IR_BS + threadIdx.x;
+    if (d.conv[s]) return;
+    double rz_new = sum_partials(d, s, 1);
+    double rr = sum_partials(d, s, 2);
+    double rz_old = d.rz[(it & 1) * d.S + s];
+    double beta = rz_old != 0.0 ? rz_new / rz_old : 0.0;
+    if (i < d.n_nodes && is_free(d, s, i)) {
+        size_t x = (size_t)s * d.n_nodes + i;
+        d.p[x] = d.z[x] + beta * d.p[x];
+    }
+    if (bx == 0 && threadIdx.x == 0) {
+        d.rz[((it + 1) & 1) * d.S + s] = rz_new;
+        if (rr <= rtol * rtol * d.bb[s]) d.conv[s] = 1;
+    }
+}
+
+// Fixed nodes, worst drop partials.
+EM_KERNEL void k_ir_finish_nodes(Dev d)
+{
+    int s = blockIdx.y, bx = blockIdx.x;
+    int i = bx * IR_BS + threadIdx.x;
+    double dm = -INFINITY;
+    if (i < d.n_nodes) {
+        size_t x = (size_t)s * d.n_nodes + i;
+        if (d.is_pad[i]) d.u[x] = d.vdd;
+        else if (!d.live[x]) d.u[x] = 0.0;
+        dm = (d.vdd - d.u[x]) / d.vdd;
+    }
+    __shared__ double red[IR_BS / 64];
+    double m = wave_max(dm);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double acc = red[0];
+        for (int w = 1; w < IR_BS / 64; ++w) acc = fmax(acc, red[w]);
+        d.part[((size_t)s * d.ir_nblk + bx) * 4 + 0] = acc;
+    }
+}
+
+EM_KERNEL void k_ir_finalize_drop(Dev d)
+{
+    int s = blockIdx.x;
+    double m = -INFINITY;
+    for (int b = threadIdx.x; b < d.ir_nblk; b += 64)
+        m = fmax(m, d.part[((size_t)s * d.ir_nblk + b) * 4 + 0]);
+    m = wave_max(m);
+    if (threadIdx.x == 0) d.drop[s] = m;
+}
+
+// Branch currents and signed current densities along res_a -> res_b.
+EM_KERNEL void k_ir_currents(Dev d)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)d.S * d.n_res) return;
+    int s = (int)(g / d.n_res), r = (int)(g % d.n_res);
+    if (!d.sample_active[s]) return;
+    const double *u = d.u + (size_t)s * d.n_nodes;
+    double I = (u[d.ra[r]] - u[d.rb[r]]) * d.G[g];
+    d.jseg[g] = I / (d.w[r] * d.h[r]);
+}
+
+// ---------------------------- TTF ----------------------------------------
+EM_KERNEL void k_ttf_init(Dev d, double fail)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= d.S) return;
+    double dr = d.drop[s];
+    d.init_drop[s] = dr; d.final_drop[s] = dr;
+    d.t_prev[s] = 0.0; d.d_prev[s] = dr;
+    d.outer_idx[s] = 0;
+    if (dr >= fail) { d.failed[s] = 1; d.ttf[s] = 0.0; d.sample_active[s] = 0; }
+    else { d.failed[s] = 0; d.ttf[s] = NAN; }
+}
+
+// After re-solve k at time t: failure when the worst drop reaches the
+// threshold; TTF interpolates linearly between the bracketing re-solves.
+EM_KERNEL void k_ttf_update(Dev d, double fail, int k, double t)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= d.S || !d.sample_active[s]) return;
+    double dr = d.drop[s];
+    d.final_drop[s] = dr;
+    d.outer_idx[s] = k;
+    if (dr >= fail) {
+        double tp = d.t_prev[s], dp = d.d_prev[s];
+        d.ttf[s] = tp + (fail - dp) / (dr - dp) * (t - tp);
+        d.failed[s] = 1;
+        d.sample_active[s] = 0;
+    } else {
+        d.t_prev[s] = t;
+        d.d_prev[s] = dr;
+    }
+}
+
+EM_KERNEL void k_fill_f64(double *p, long long n, double v)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n) p[g] = v;
+}
+
+// ---------------------------- launchers ---------------------------------
+static inline int nb(long long n) { return (int)((n + IR_BS - 1) / IR_BS); }
+
+void launch_ir_conductance(const Dev &d, hipStream_t st)
+{
+    k_ir_conductance<<<nb((long long)d.S * d.n_res), IR_BS, 0, st>>>(d);
+}
+void launch_ir_live_init(const Dev &d, hipStream_t st)
+{
+    k_ir_live_init<<<nb((long long)d.S * d.n_nodes), IR_BS, 0, st>>>(d);
+}
+void launch_ir_live_step(const Dev &d, hipStream_t st)
+{
+    k_ir_live_step<<<nb((long long)d.S * d.n_nodes), IR_BS, 0, st>>>(d);
+}
+void launch_ir_setup(const Dev &d, hipStream_t st)
+{
+    k_ir_setup<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d);
+}
+void launch_ir_finalize0(const Dev &d, double rtol, hipStream_t st)
+{
+    k_ir_finalize0<<<d.S, 64, 0, st>>>(d, rtol);
+}
+void launch_ir_spmv(const Dev &d, hipStream_t st)
+{
+    k_ir_spmv<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d);
+}
+void launch_ir_update(const Dev &d, int it, hipStream_t st)
+{
+    k_ir_update<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d, it);
+}
+void launch_ir_pupdate(const Dev &d, int it, double rtol, hipStream_t st)
+{
+    k_ir_pupdate<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d, it, rtol);
+}
+void launch_ir_finish(const Dev &d, hipStream_t st)
+{
+    k_ir_finish_nodes<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d);
+    k_ir_finalize_drop<<<d.S, 64, 0, st>>>(d);
+    k_ir_currents<<<nb((long long)d.S * d.n_res), IR_BS, 0, st>>>(d);
+}
+void launch_fill_f64(double *p, size_t n, double v, hipStream_t st)
+{
+    k_fill_f64<<<nb((long long)n), IR_BS, 0, st>>>(p, (long long)n, v);
+}
+void launch_ttf_init(const Dev &d, double fail, hipStream_t st)
+{
+    k_ttf_init<<<nb(d.S), IR_BS, 0, st>>>(d, fail);
+}
+void launch_ttf_update(const Dev &d, double fail, int k, double t, hipStream_t st)
+{
+    k_ttf_update<<<nb(d.S), IR_BS, 0, st>>>(d, fail, k, t);
+}
+
+}  // namespace em

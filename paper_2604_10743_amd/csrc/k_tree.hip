@@ -1,0 +1,611 @@
+// Per-tree kernels: temperatures, diffusivities, control volumes, Monte Carlo
+// draws, forcing, tree factorisation, steady-state screen, and the
+// backward-Euler stepping loop with nucleation, Robin void rows and void growth.
+//
+// Lanes map to instances (tree, sample).  With S >= 64 the 64 lanes of a
+// wavefront are 64 samples of one tree: identical control flow and coalesced
+// [node][sample] accesses.  With S == 1 lanes are trees, ordered largest
+// first so that a wavefront holds trees of similar size.
+#include "em_internal.h"
+#include <cmath>
+
+namespace em {
+
+#define EM_KERNEL __global__ __launch_bounds__(256)
+
+static inline int nblocks(long long n, int bs = 256) { return (int)((n + bs - 1) / bs); }
+
+// ------------------------------------------------------------------------
+// Temperature at every stress node (Sec. II-A: per-tree profile from the
+// thermal map).  Raster: bilinear with clamping at the raster edge; vertex
+// temperatures: linear along the segment; otherwise the ambient value.
+// ------------------------------------------------------------------------
+__device__ inline void node_position(const Dev &d, int i, double &x, double &y)
+{
+    int v = d.vert[i];
+    if (v >= 0) { x = d.xy[2 * v]; y = d.xy[2 * v + 1]; return; }
+    int e = d.seg[i];
+    double f = (double)d.kpos[i] / d.N;
+    int a = d.ra[e], b = d.rb[e];
+    x = d.xy[2 * a] + f * (d.xy[2 * b] - d.xy[2 * a]);
+    y = d.xy[2 * a + 1] + f * (d.xy[2 * b + 1] - d.xy[2 * a + 1]);
+}
+
+__device__ inline double raster_T(const Dev &d, double x, double y)
+{
+    double fx = (x - d.tx0) / d.tdx, fy = (y - d.ty0) / d.tdy;
+    fx = fmin(fmax(fx, 0.0), (double)(d.tnx - 1));
+    fy = fmin(fmax(fy, 0.0), (double)(d.tny - 1));
+    int ix = (int)floor(fx), iy = (int)floor(fy);
+    ix = max(0, min(ix, d.tnx - 2));
+    iy = max(0, min(iy, d.tny - 2));
+    double tx = fx - ix, ty = fy - iy;
+    int ix1 = d.tnx > 1 ? ix + 1 : ix, iy1 = d.tny > 1 ? iy + 1 : iy;
+    const double *M = d.tmap;
+    double lo = (1 - tx) * M[iy * d.tnx + ix] + tx * M[iy * d.tnx + ix1];
+    double hi = (1 - tx) * M[iy1 * d.tnx + ix] + tx * M[iy1 * d.tnx + ix1];
+    return (1 - ty) * lo + ty * hi;
+}
+
+EM_KERNEL void k_node_T(Dev d)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.ns) return;
+    double T;
+    if (d.tmap) {
+        double x, y;
+        node_position(d, i, x, y);
+        T = raster_T(d, x, y);
+    } else if (d.node_T) {
+        int v = d.vert[i];
+        if (v >= 0) T = d.node_T[v];
+        else {
+            int e = d.seg[i];
+            double f = (double)d.kpos[i] / d.N;
+            T = d.node_T[d.ra[e]] + f * (d.node_T[d.rb[e]] - d.node_T[d.ra[e]]);
+        }
+    } else {
+        T = d.T_amb;
+    }
+    d.T[i] = T;
+}
+
+// ------------------------------------------------------------------------
+// Per-edge statics for the edge (parent(i), i): diffusivity at the edge
+// midpoint temperature, kappa = D0 exp(-Ea/kT) B Omega/(kT) (eqs. 10-11),
+// conductance g0 = a kappa/dx, Robin weight a kappa/delta (eq. 20), and the
+// thermomigration drive M = (Q/(Omega T)) dT/dx along res_a -> res_b (eq. 13).
+// Monte Carlo multipliers scale kappa later, per sample.
+// ------------------------------------------------------------------------
+EM_KERNEL void k_edge_static(Dev d)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.ns) return;
+    int p = d.parent[i];
+    if (p < 0) { d.g0[i] = 0; d.rob0[i] = 0; d.gdx0[i] = 0; d.mdrv[i] = 0; return; }
+    int e = d.seg[i];
+    double dx = d.len[e] / d.N;
+    double a = d.w[e] * d.h[e];
+    double Te = 0.5 * (d.T[i] + d.T[p]);
+    double kT = K_B * Te;
+    double kap = d.D0 * exp(-d.Ea_eV * E_CHG / kT) * d.B * d.Omega / kT;
+    d.g0[i] = a * kap / dx;
+    d.rob0[i] = a * kap / d.delta;
+    d.gdx0[i] = a * kap;
+    d.mdrv[i] = d.dir[i] * (d.Q_eV * E_CHG / (d.Omega * Te)) * (d.T[i] - d.T[p]) / dx;
+}
+
+// Control volume of a node: half of every incident interval's volume.
+EM_KERNEL void k_node_V(Dev d, int fp32)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.ns) return;
+    double V = 0;
+    if (d.parent[i] >= 0) {
+        int e = d.seg[i];
+        V += 0.5 * d.w[e] * d.h[e] * (d.len[e] / d.N);
+    }
+    for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k) {
+        int e = d.seg[d.child[k]];
+        V += 0.5 * d.w[e] * d.h[e] * (d.len[e] / d.N);
+    }
+    d.V[i] = V;
+    if (fp32) ((float *)d.Vr)[i] = (float)V; else ((double *)d.Vr)[i] = V;
+}
+
+// ------------------------------------------------------------------------
+// Monte Carlo multipliers (Sec. IV-F): Philox-4x32-10 (Salmon et al., SC'11)
+// counter (segment, sample, param, 0), key (seed lo, seed hi); Box-Muller on
+// u1 = (x0 + 1) 2^-32, u2 = x1 2^-32; unit-mean lognormal with CoV `cov`.
+// ------------------------------------------------------------------------
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+        uint32_t hi0 = __umulhi(m0, c[0]), lo0 = m0 * c[0];
+        uint32_t hi1 = __umulhi(m1, c[2]), lo1 = m1 * c[2];
+        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+}
+
+__device__ inline double lognormal_xi(uint64_t seed, int sample, int segment, int param, double cov)
+{
+    if (cov == 0.0) return 1.0;
+    uint32_t c[4] = {(uint32_t)segment, (uint32_t)sample, (uint32_t)param, 0u};
+    philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+    double u1 = ((double)c[0] + 1.0) * (1.0 / 4294967296.0);
+    double u2 = (double)c[1] * (1.0 / 4294967296.0);
+    double z = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+    double s2 = log(1.0 + cov * cov);
+    return exp(-0.5 * s2 + sqrt(s2) * z);
+}
+
+EM_KERNEL void k_draws(Dev d, uint64_t seed, double cov_k, double cov_s, int use_mc)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)d.n_res * d.S) return;
+    int s = (int)(g % d.S), e = (int)(g / d.S);
+    d.xi_k[g] = use_mc ? lognormal_xi(seed, s, e, 0, cov_k) : 1.0;
+    d.xi_s[g] = use_mc ? lognormal_xi(seed, s, e, 1, cov_s) : 1.0;
+}
+
+// Critical stress of a node: sigma_crit x the smallest multiplier over the
+// segments meeting at it.
+__device__ inline double node_scrit(const Dev &d, int i, int s)
+{
+    double m = INFINITY;
+    if (d.parent[i] >= 0) m = d.xi_s[(size_t)d.seg[i] * d.S + s];
+    for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k)
+        m = fmin(m, d.xi_s[(size_t)d.seg[d.child[k]] * d.S + s]);
+    return d.scrit * m;
+}
+
+template <typename R>
+EM_KERNEL void k_node_sc(Dev d)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)d.ns * d.S) return;
+    int s = (int)(g % d.S), i = (int)(g / d.S);
+    ((R *)d.sc)[g] = (R)node_scrit(d, i, s);
+}
+
+// ------------------------------------------------------------------------
+// Forcing f of the descriptor system (eq. 18): the edge (p, i) carries
+// phi = dir * g dx (S + M) from p into i, with S = eZ rho j/Omega along
+// res_a -> res_b; f_i = phi_i - sum over children c of phi_c.  Stored as dt*f.
+// ------------------------------------------------------------------------
+__device__ inline double edge_phi(const Dev &d, int i, int s)
+{
+    int e = d.seg[i];
+    double j = d.jseg[(size_t)s * d.n_res + e];
+    double Sd = E_CHG * d.Z * d.rho * j / d.Omega;
+    return d.dir[i] * d.xi_k[(size_t)e * d.S + s] * d.gdx0[i] * (Sd + d.mdrv[i]);
+}
+
+template <typename R>
+EM_KERNEL void k_update_f(Dev d)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)d.ns * d.S) return;
+    int s = (int)(g % d.S), i = (int)(g / d.S);
+    double f = 0.0;
+    if (d.parent[i] >= 0) f += edge_phi(d, i, s);
+    for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k) f -= edge_phi(d, d.child[k], s);
+    ((R *)d.dtf)[g] = (R)(d.dt * f);
+}
+
+// ------------------------------------------------------------------------
+// Tree factorisation of M = C - dt A (SPD on the tree): leaf-to-root
+// elimination in reverse pre-order with no fill,
+//   d_i = V_i + dt g_i + sum_c dt g_c (1 - l_c) [+ dt * Robin weight at a void],
+//   l_i = dt g_i / d_i,
+// stored as dinv = 1/d and l.
+// ------------------------------------------------------------------------
+__device__ inline bool in_list(int i, const int *vn, int nv)
+{
+    bool r = false;
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) r |= (k < nv) && (vn[k] == i);
+    return r;
+}
+
+__device__ inline double robin_weight(const Dev &d, int v, int s)
+{
+    double r = 0.0;
+    if (d.parent[v] >= 0) r += d.xi_k[(size_t)d.seg[v] * d.S + s] * d.rob0[v];
+    for (int k = d.child_off[v]; k < d.child_off[v + 1]; ++k) {
+        int c = d.child[k];
+        r += d.xi_k[(size_t)d.seg[c] * d.S + s] * d.rob0[c];
+    }
+    return r;
+}
+
+template <typename R>
+__device__ void factor_instance(const Dev &d, int t, int s, const int *vn, const double *vrob, int nv)
+{
+    const int S = d.S;
+    R *dinv = (R *)d.dinv, *lf = (R *)d.lfac;
+    int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
+    const double dt = d.dt;
+    for (int i = i1 - 1; i >= i0; --i) {
+        double gi = 0.0;
+        if (d.parent[i] >= 0) gi = dt * d.xi_k[(size_t)d.seg[i] * S + s] * d.g0[i];
+        double dd = d.V[i] + gi;
+        for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k) {
+            int c = d.child[k];
+            double gc = dt * d.xi_k[(size_t)d.seg[c] * S + s] * d.g0[c];
+            dd += gc * (1.0 - (double)lf[(size_t)c * S + s]);
+        }
+        for (int k = 0; k < nv; ++k)
+            if (vn[k] == i) dd += dt * vrob[k];
+        dinv[(size_t)i * S + s] = (R)(1.0 / dd);
+        lf[(size_t)i * S + s] = (R)(gi / dd);
+    }
+}
+
+__device__ inline int inst_of_slot(const Dev &d, int slot, int &t, int &s)
+{
+    s = slot % d.S;
+    t = d.tree_perm[slot / d.S];
+    return t * d.S + s;
+}
+
+template <typename R>
+EM_KERNEL void k_factor(Dev d)
+{
+    int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= d.n_trees * d.S) return;
+    int t, s;
+    int inst = inst_of_slot(d, slot, t, s);
+    int vn[MAXV];
+    double vr[MAXV];
+    int nv = d.nv[inst];
+    for (int k = 0; k < MAXV; ++k) {
+        vn[k] = k < nv ? d.vnode[inst * MAXV + k] : -1;
+        vr[k] = k < nv ? d.vrob[inst * MAXV + k] : 0.0;
+    }
+    factor_instance<R>(d, t, s, vn, vr, nv);
+}
+
+// ------------------------------------------------------------------------
+// Steady-state immortality screen (Sec. II-B).  Zero flux on every edge:
+// psi_i = psi_p + dir dx (S + M); the constant follows from conservation
+// (sum V sigma = sum V sigma_T), so sigma_ss = sigma_T + psi - <psi>_V.
+// A node is mortal iff its finite sigma_ss exceeds its critical stress;
+// segments through a mortal node and its tree are flagged.
+// ------------------------------------------------------------------------
+EM_KERNEL void k_screen(Dev d, int apply)
+{
+    int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= d.n_trees * d.S) return;
+    int t, s;
+    int inst = inst_of_slot(d, slot, t, s);
+    const int S = d.S;
+    int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
+    double *psi = d.psi;
+    psi[(size_t)i0 * S + s] = 0.0;
+    double num = 0.0, den = d.V[i0];
+    for (int i = i0 + 1; i < i1; ++i) {
+        int p = d.parent[i], e = d.seg[i];
+        double dx = d.len[e] / d.N;
+        double j = d.jseg[(size_t)s * d.n_res + e];
+        double Sd = E_CHG * d.Z * d.rho * j / d.Omega;
+        double v = psi[(size_t)p * S + s] + d.dir[i] * dx * (Sd + d.mdrv[i]);
+        psi[(size_t)i * S + s] = v;
+        num += d.V[i] * v;
+        den += d.V[i];
+    }
+    double mean = num / den;
+    int mortal = 0;
+    uint8_t *sm = d.seg_mortal + (size_t)s * d.n_res;
+    for (int k = d.tseg_off[t]; k < d.tseg_off[t + 1]; ++k) sm[d.tseg[k]] = 0;
+    for (int i = i0; i < i1; ++i) {
+        double v = d.sigT + psi[(size_t)i * S + s] - mean;
+        psi[(size_t)i * S + s] = v;
+        if (isfinite(v) && v > node_scrit(d, i, s)) {
+            mortal = 1;
+            if (d.parent[i] >= 0) sm[d.seg[i]] = 1;
+            for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k) sm[d.seg[d.child[k]]] = 1;
+        }
+    }
+    d.tree_mortal[inst] = (uint8_t)mortal;
+    if (apply) d.inst_active[inst] = (uint8_t)mortal;
+}
+
+// ------------------------------------------------------------------------
+// Late-failure resistance (eq. 17) with V_v - V_crit = (l - W) W H.
+// ------------------------------------------------------------------------
+__device__ inline double late_dR(const Dev &d, double l, double W, double H)
+{
+    double ex = l - W;
+    if (ex <= 0) return 0.0;
+    return ex * (d.rho_ta / (d.h_ta * (2 * H + W)) - d.rho / (W * H));
+}
+
+// Host segment of a void at node v: its own segment for an interior node; at
+// a vertex, the incident segment with the largest wind away from it (signed
+// j with the vertex at res_b, -j at res_a), ties to the lowest index.
+__device__ inline int host_segment(const Dev &d, int v, int s)
+{
+    int x = d.vert[v];
+    if (x < 0) return d.seg[v];
+    int best = -1;
+    double bd = 0.0;
+    for (int k = d.vinc_off[x]; k < d.vinc_off[x + 1]; ++k) {
+        int e = d.vinc[k];
+        double j = d.jseg[(size_t)s * d.n_res + e];
+        double drv = (d.rb[e] == x) ? j : -j;
+        if (best < 0 || drv > bd) { best = e; bd = drv; }
+    }
+    return best;
+}
+
+template <typename R>
+__device__ void add_void(const Dev &d, int inst, int t, int s, int v, int step, int *vn, double *vvol,
+                         double *vlen, double *vrob, int *vseg, int *vphase, int *vearly, int &nv)
+{
+    int k = nv;
+    vn[k] = v;
+    vvol[k] = 0.0;
+    vlen[k] = 0.0;
+    vrob[k] = robin_weight(d, v, s);
+    vseg[k] = host_segment(d, v, s);
+    vphase[k] = 0;
+    vearly[k] = d.vert[v] >= 0 ? d.via_up[d.vert[v]] : 0;
+    d.vstep[inst * MAXV + k] = step;
+    nv = k + 1;
+    unsigned int q = atomicAdd(d.ev_count, 1u);
+    if ((int)q < d.ev_cap) {
+        int *E = d.events + (size_t)q * EV_WORDS;
+        E[0] = s; E[1] = t; E[2] = step; E[3] = v; E[4] = vseg[k];
+    }
+    factor_instance<R>(d, t, s, vn, vrob, nv);
+}
+
+// ------------------------------------------------------------------------
+// Backward-Euler stepping: (C - dt A) sigma^{n+1} = C sigma^n + dt f, one
+// (tree, sample) per lane, n_steps steps per launch with the current
+// densities fixed.  Per step: leaf-to-root rhs elimination (the rhs b
+// overwrites sigma in place), root-to-leaf back substitution, void growth
+// from atom conservation (eq. 15), then the nucleation check (peak stress at
+// or above the node's critical stress; ties within 1e-12 relative go to the
+// lowest node) which stamps the Robin row (eq. 20) and refactors the tree.
+// ------------------------------------------------------------------------
+template <typename R>
+EM_KERNEL void k_step(Dev d, int n_steps, int step0)
+{
+    int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= d.n_trees * d.S) return;
+    int t, s;
+    int inst = inst_of_slot(d, slot, t, s);
+    if (!d.sample_active[s] || !d.inst_active[inst]) return;
+    const int S = d.S;
+    R *sig = (R *)d.sigma;
+    const R *dtf = (const R *)d.dtf, *dinv = (const R *)d.dinv, *lf = (const R *)d.lfac;
+    const R *sc = (const R *)d.sc, *Vr = (const R *)d.Vr;
+    const int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
+    atomicAdd(d.node_steps, (unsigned long long)(i1 - i0) * (unsigned long long)n_steps);
+
+    int nv = d.nv[inst];
+    int vn[MAXV], vseg[MAXV], vphase[MAXV], vearly[MAXV];
+    double vvol[MAXV], vlen[MAXV], vrob[MAXV];
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) {
+        int q = inst * MAXV + k;
+        bool u = k < nv;
+        vn[k] = u ? d.vnode[q] : -1;
+        vseg[k] = u ? d.vseg[q] : -1;
+        vphase[k] = u ? d.vphase[q] : 0;
+        vearly[k] = u ? d.vearly[q] : 0;
+        vvol[k] = u ? d.vvol[q] : 0.0;
+        vlen[k] = u ? d.vlen[q] : 0.0;
+        vrob[k] = u ? d.vrob[q] : 0.0;
+    }
+    int suppressed = 0;
+
+    for (int st = 0; st < n_steps; ++st) {
+        // rhs, eliminated leaf-to-root: b_i = V_i sigma_i + dt f_i + sum_c l_c b_c
+        for (int i = i1 - 1; i >= i0; --i) {
+            size_t x = (size_t)i * S + s;
+            R b = Vr[i] * sig[x];
+            if (!in_list(i, vn, nv)) b += dtf[x];
+            for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k) {
+                size_t y = (size_t)d.child[k] * S + s;
+                b += lf[y] * sig[y];
+            }
+            sig[x] = b;
+        }
+        // back substitution root-to-leaf; track the nucleation candidate peak
+        R mx = (R)0;
+        bool any = false;
+        for (int i = i0; i < i1; ++i) {
+            size_t x = (size_t)i * S + s;
+            R v = sig[x] * dinv[x];
+            if (i > i0) v += lf[x] * sig[(size_t)d.parent[i] * S + s];
+            sig[x] = v;
+            if (v >= sc[x] && !in_list(i, vn, nv)) {
+                mx = any ? (v > mx ? v : mx) : v;
+                any = true;
+            }
+        }
+        // void growth: dV = (dt/B) (Robin weight * sigma_v + f_v)
+        for (int k = 0; k < nv; ++k) {
+            size_t x = (size_t)vn[k] * S + s;
+            vvol[k] += (d.dt * vrob[k] * (double)sig[x] + (double)dtf[x]) / d.B;
+            int e = vseg[k];
+            double W = d.w[e], H = d.h[e];
+            double l = fmin(vvol[k] / (W * H), d.len[e]);
+            vlen[k] = l;
+            if (vphase[k] == 0 && l >= W) {
+                vphase[k] = 1;
+                if (vearly[k]) {
+                    d.open[(size_t)s * d.n_res + e] = 1;
+                    *d.open_dirty = 1u;
+                }
+            }
+        }
+        // nucleation
+        if (any) {
+            if (nv < d.max_voids) {
+                R thr = mx - (R)1e-12 * (mx < 0 ? -mx : mx);
+                int v = -1;
+                for (int i = i0; i < i1 && v < 0; ++i) {
+                    size_t x = (size_t)i * S + s;
+                    R val = sig[x];
+                    if (val >= sc[x] && val >= thr && !in_list(i, vn, nv)) v = i;
+                }
+                add_void<R>(d, inst, t, s, v, step0 + st, vn, vvol, vlen, vrob, vseg, vphase, vearly, nv);
+            } else {
+                ++suppressed;
+            }
+        }
+    }
+    d.nv[inst] = nv;
+    for (int k = 0; k < nv; ++k) {
+        int q = inst * MAXV + k;
+        d.vnode[q] = vn[k]; d.vseg[q] = vseg[k]; d.vphase[q] = vphase[k]; d.vearly[q] = vearly[k];
+        d.vvol[q] = vvol[k]; d.vlen[q] = vlen[k]; d.vrob[q] = vrob[k];
+    }
+    d.n_suppressed[inst] += suppressed;
+}
+
+// Resistance write-back of one (tree, sample): dR of each segment of the tree
+// is the sum of its late-failure voids' eq. 17 increments.
+EM_KERNEL void k_void_dR(Dev d)
+{
+    int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= d.n_trees * d.S) return;
+    int t, s;
+    int inst = inst_of_slot(d, slot, t, s);
+    double *dR = d.dR + (size_t)s * d.n_res;
+    for (int k = d.tseg_off[t]; k < d.tseg_off[t + 1]; ++k) dR[d.tseg[k]] = 0.0;
+    int nv = d.nv[inst];
+    for (int k = 0; k < nv; ++k) {
+        int q = inst * MAXV + k;
+        if (d.vearly[q]) continue;
+        int e = d.vseg[q];
+        dR[e] += late_dR(d, d.vlen[q], d.w[e], d.h[e]);
+    }
+}
+
+template <typename R>
+EM_KERNEL void k_set_sigma_T(Dev d)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)d.ns * d.S) return;
+    ((R *)d.sigma)[g] = (R)d.sigT;
+}
+
+template <typename R>
+EM_KERNEL void k_inject_void(Dev d, int s, int t, int v)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int inst = t * d.S + s;
+    int nv = d.nv[inst];
+    if (nv >= d.max_voids) return;
+    int vn[MAXV], vseg[MAXV], vphase[MAXV], vearly[MAXV];
+    double vvol[MAXV], vlen[MAXV], vrob[MAXV];
+    for (int k = 0; k < MAXV; ++k) {
+        int q = inst * MAXV + k;
+        bool u = k < nv;
+        vn[k] = u ? d.vnode[q] : -1; vseg[k] = u ? d.vseg[q] : -1;
+        vphase[k] = u ? d.vphase[q] : 0; vearly[k] = u ? d.vearly[q] : 0;
+        vvol[k] = u ? d.vvol[q] : 0.0; vlen[k] = u ? d.vlen[q] : 0.0; vrob[k] = u ? d.vrob[q] : 0.0;
+    }
+    add_void<R>(d, inst, t, s, v, 0, vn, vvol, vlen, vrob, vseg, vphase, vearly, nv);
+    d.nv[inst] = nv;
+    for (int k = 0; k < nv; ++k) {
+        int q = inst * MAXV + k;
+        d.vnode[q] = vn[k]; d.vseg[q] = vseg[k]; d.vphase[q] = vphase[k]; d.vearly[q] = vearly[k];
+        d.vvol[q] = vvol[k]; d.vlen[q] = vlen[k]; d.vrob[q] = vrob[k];
+    }
+}
+
+// Copy one sample's column of a [node][S] array to/from a dense FP64 vector.
+template <typename R>
+EM_KERNEL void k_copy_col(Dev d, void *arr, int s, double *out, int to_state)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.ns) return;
+    R *a = (R *)arr;
+    if (to_state) a[(size_t)i * d.S + s] = (R)out[i];
+    else out[i] = (double)a[(size_t)i * d.S + s];
+}
+
+// ---------------------------- launchers ---------------------------------
+void launch_node_T(const Dev &d, hipStream_t st)
+{
+    k_node_T<<<nblocks(d.ns), 256, 0, st>>>(d);
+}
+void launch_edge_static(const Dev &d, hipStream_t st)
+{
+    k_edge_static<<<nblocks(d.ns), 256, 0, st>>>(d);
+}
+void launch_node_V(const Dev &d, bool fp32, hipStream_t st)
+{
+    k_node_V<<<nblocks(d.ns), 256, 0, st>>>(d, fp32 ? 1 : 0);
+}
+void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, hipStream_t st)
+{
+    int use = (cov_k != 0.0 || cov_s != 0.0) ? 1 : 0;
+    k_draws<<<nblocks((long long)d.n_res * d.S), 256, 0, st>>>(d, seed, cov_k, cov_s, use);
+}
+void launch_node_sc(const Dev &d, bool fp32, hipStream_t st)
+{
+    long long n = (long long)d.ns * d.S;
+    if (fp32) k_node_sc<float><<<nblocks(n), 256, 0, st>>>(d);
+    else k_node_sc<double><<<nblocks(n), 256, 0, st>>>(d);
+}
+void launch_update_f(const Dev &d, bool fp32, hipStream_t st)
+{
+    long long n = (long long)d.ns * d.S;
+    if (fp32) k_update_f<float><<<nblocks(n), 256, 0, st>>>(d);
+    else k_update_f<double><<<nblocks(n), 256, 0, st>>>(d);
+}
+void launch_factor(const Dev &d, bool fp32, hipStream_t st)
+{
+    int n = d.n_trees * d.S;
+    if (fp32) k_factor<float><<<nblocks(n), 256, 0, st>>>(d);
+    else k_factor<double><<<nblocks(n), 256, 0, st>>>(d);
+}
+void launch_screen(const Dev &d, bool apply, hipStream_t st)
+{
+    k_screen<<<nblocks(d.n_trees * d.S), 256, 0, st>>>(d, apply ? 1 : 0);
+}
+void launch_step(const Dev &d, bool fp32, int n_steps, int step0, hipStream_t st)
+{
+    int n = d.n_trees * d.S;
+    if (fp32) k_step<float><<<nblocks(n), 256, 0, st>>>(d, n_steps, step0);
+    else k_step<double><<<nblocks(n), 256, 0, st>>>(d, n_steps, step0);
+}
+void launch_void_dR(const Dev &d, hipStream_t st)
+{
+    k_void_dR<<<nblocks(d.n_trees * d.S), 256, 0, st>>>(d);
+}
+void launch_set_sigma_T(const Dev &d, bool fp32, hipStream_t st)
+{
+    long long n = (long long)d.ns * d.S;
+    if (fp32) k_set_sigma_T<float><<<nblocks(n), 256, 0, st>>>(d);
+    else k_set_sigma_T<double><<<nblocks(n), 256, 0, st>>>(d);
+}
+void launch_inject_void(const Dev &d, bool fp32, int sample, int tree, int node, hipStream_t st)
+{
+    if (fp32) k_inject_void<float><<<1, 64, 0, st>>>(d, sample, tree, node);
+    else k_inject_void<double><<<1, 64, 0, st>>>(d, sample, tree, node);
+}
+void launch_copy_sigma(const Dev &d, bool fp32, int sample, double *buf, bool to_state, hipStream_t st)
+{
+    if (fp32) k_copy_col<float><<<nblocks(d.ns), 256, 0, st>>>(d, d.sigma, sample, buf, to_state);
+    else k_copy_col<double><<<nblocks(d.ns), 256, 0, st>>>(d, d.sigma, sample, buf, to_state);
+}
+void launch_copy_node_col(const Dev &d, bool fp32, int which, int sample, double *buf, hipStream_t st)
+{
+    void *arr = which == 0 ? d.sc : d.dtf;
+    if (fp32) k_copy_col<float><<<nblocks(d.ns), 256, 0, st>>>(d, arr, sample, buf, 0);
+    else k_copy_col<double><<<nblocks(d.ns), 256, 0, st>>>(d, arr, sample, buf, 0);
+}
+
+}  // namespace em
