@@ -506,12 +506,24 @@ int ora_steps(ora_state *S, int n_steps, int step0)
         if (!S->active[t]) continue;
         int i0 = S->tree_off[t], i1 = S->tree_off[t + 1];
         for (int st = 0; st < n_steps; ++st) {
-            /* rhs and diagonal of (C - dt A) sigma = C sigma^n + dt f; a void
-             * row carries the Robin term and no drive (eq. 20) */
+            /* Backward Euler for the increment: (C - dt A) (sigma^{n+1} - sigma^n)
+             * = dt (A sigma^n + f), the same equation as (C - dt A) sigma^{n+1} =
+             * C sigma^n + dt f.  The right-hand side is assembled edge by edge from
+             * the net flux of each edge (diffusion plus drive), so its rounding
+             * shrinks with the flux and the stress content does not drift once a
+             * tree is at steady state.  A void row keeps only the diffusion of its
+             * edges and adds the Robin sink (eq. 20). */
             for (int i = i0; i < i1; ++i) {
                 int isv = void_slot(S, t, i) >= 0;
-                S->b[i] = S->V[i] * S->sigma[i] + (isv ? 0.0 : dt * S->f[i]);
+                S->b[i] = isv ? -dt * S->robsum[i] * S->sigma[i] : 0.0;
                 S->d[i] = S->V[i] + dt * S->gsum[i] + (isv ? dt * S->robsum[i] : 0.0);
+            }
+            for (int i = i0 + 1; i < i1; ++i) {
+                int p = S->parent[i];
+                double diff = S->g[i] * (S->sigma[p] - S->sigma[i]);  /* into i */
+                double full = diff + S->phi[i];
+                S->b[i] += dt * (void_slot(S, t, i) >= 0 ? diff : full);
+                S->b[p] -= dt * (void_slot(S, t, p) >= 0 ? diff : full);
             }
             /* eliminate leaves into parents (reverse pre-order) */
             for (int i = i1 - 1; i > i0; --i) {
@@ -521,10 +533,11 @@ int ora_steps(ora_state *S, int n_steps, int step0)
                 S->d[p] -= m * c;
                 S->b[p] += m * S->b[i];
             }
-            /* back substitution root-to-leaves (pre-order) */
-            S->sigma[i0] = S->b[i0] / S->d[i0];
+            /* back substitution root-to-leaves (pre-order); b becomes the increment */
+            S->b[i0] = S->b[i0] / S->d[i0];
             for (int i = i0 + 1; i < i1; ++i)
-                S->sigma[i] = (S->b[i] + dt * S->g[i] * S->sigma[S->parent[i]]) / S->d[i];
+                S->b[i] = (S->b[i] + dt * S->g[i] * S->b[S->parent[i]]) / S->d[i];
+            for (int i = i0; i < i1; ++i) S->sigma[i] += S->b[i];
 
             /* void growth from atom conservation (eq. 15): the Robin row removes
              * dt*(robsum*sigma_v + f_v) of stress content per step */
