@@ -493,7 +493,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     const size_t rs = b->fp32 ? 4 : 8;
     const size_t NS = (size_t)ns * S, RS = (size_t)nr * S, IS = (size_t)nt * S, VS = (size_t)nn * S;
     AL(d.T, double, ns); AL(d.V, double, ns); AL(d.g0, double, ns); AL(d.rob0, double, ns);
-    AL(d.gdx0, double, ns); AL(d.mdrv, double, ns);
+    AL(d.gdx0, double, ns); AL(d.mdrv, double, ns); AL(d.tree_V, double, nt);
     d.Vr = dalloc(b, rs * ns);
     d.sigma = dalloc(b, rs * NS); d.dtf = dalloc(b, rs * NS); d.dinv = dalloc(b, rs * NS);
     d.lfac = dalloc(b, rs * NS); d.sc = dalloc(b, rs * NS);

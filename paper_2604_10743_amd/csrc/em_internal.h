@@ -50,6 +50,7 @@ struct Dev {
     const int *tree_perm;               // lane slot -> tree id (larger trees first)
     // ---- per stress node statics (FP64) ----
     double *T, *V, *g0, *rob0, *gdx0, *mdrv;
+    double *tree_V;                     // [n_trees] total control volume
     // ---- per (node, sample) stepping state; element type float or double ----
     void *sigma, *dtf, *dinv, *lfac, *sc, *Vr;
     double *psi;                        // screen scratch / steady stress [node][S]
@@ -94,7 +95,7 @@ struct Dev {
 // ---- launchers (defined in the kernel translation units) ----
 void launch_node_T(const Dev &d, hipStream_t st);
 void launch_edge_static(const Dev &d, hipStream_t st);
-void launch_node_V(const Dev &d, bool fp32, hipStream_t st);
+void launch_node_V(const Dev &d, bool fp32, hipStream_t st);   // also per-tree volume
 void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, hipStream_t st);
 void launch_node_sc(const Dev &d, bool fp32, hipStream_t st);
 void launch_update_f(const Dev &d, bool fp32, hipStream_t st);

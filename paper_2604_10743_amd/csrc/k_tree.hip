@@ -113,6 +113,16 @@ EM_KERNEL void k_node_V(Dev d, int fp32)
     if (fp32) ((float *)d.Vr)[i] = (float)V; else ((double *)d.Vr)[i] = V;
 }
 
+// Total control volume of each tree (fixed summation order).
+EM_KERNEL void k_tree_V(Dev d)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= d.n_trees) return;
+    double s = 0.0;
+    for (int i = d.tree_off[t]; i < d.tree_off[t + 1]; ++i) s += d.V[i];
+    d.tree_V[t] = s;
+}
+
 // ------------------------------------------------------------------------
 // Monte Carlo multipliers (Sec. IV-F): Philox-4x32-10 (Salmon et al., SC'11)
 // counter (segment, sample, param, 0), key (seed lo, seed hi); Box-Muller on
@@ -373,6 +383,14 @@ __device__ void add_void(const Dev &d, int inst, int t, int s, int v, int step, 
 // from atom conservation (eq. 15), then the nucleation check (peak stress at
 // or above the node's critical stress; ties within 1e-12 relative go to the
 // lowest node) which stamps the Robin row (eq. 20) and refactors the tree.
+//
+// Conservation projection: the scheme keeps sum_i V_i sigma_i + B * (void
+// volumes) equal to its initial value exactly; in floating point the rounding
+// of dt f (whose node sums cancel) would make that content drift linearly in
+// the step count.  The content is accumulated in FP64 during the back
+// substitution and the uniform correction restoring it is folded into the
+// next step's right-hand side (and into the stored stress at the end of the
+// launch).  It changes the solution only at the rounding level.
 // ------------------------------------------------------------------------
 template <typename R>
 EM_KERNEL void k_step(Dev d, int n_steps, int step0)
@@ -405,12 +423,16 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
         vrob[k] = u ? d.vrob[q] : 0.0;
     }
     int suppressed = 0;
+    const double Vsum = d.tree_V[t];
+    const double Q0 = d.sigT * Vsum;
+    double corr = 0.0;
 
     for (int st = 0; st < n_steps; ++st) {
+        const R rc = (R)corr;
         // rhs, eliminated leaf-to-root: b_i = V_i sigma_i + dt f_i + sum_c l_c b_c
         for (int i = i1 - 1; i >= i0; --i) {
             size_t x = (size_t)i * S + s;
-            R b = Vr[i] * sig[x];
+            R b = Vr[i] * (sig[x] + rc);
             if (!in_list(i, vn, nv)) b += dtf[x];
             for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k) {
                 size_t y = (size_t)d.child[k] * S + s;
@@ -421,11 +443,13 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
         // back substitution root-to-leaf; track the nucleation candidate peak
         R mx = (R)0;
         bool any = false;
+        double Q = 0.0;
         for (int i = i0; i < i1; ++i) {
             size_t x = (size_t)i * S + s;
             R v = sig[x] * dinv[x];
             if (i > i0) v += lf[x] * sig[(size_t)d.parent[i] * S + s];
             sig[x] = v;
+            Q += d.V[i] * (double)v;
             if (v >= sc[x] && !in_list(i, vn, nv)) {
                 mx = any ? (v > mx ? v : mx) : v;
                 any = true;
@@ -447,6 +471,11 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
                 }
             }
         }
+        {
+            double vtot = 0.0;
+            for (int k = 0; k < nv; ++k) vtot += vvol[k];
+            corr = (Q0 - d.B * vtot - Q) / Vsum;
+        }
         // nucleation
         if (any) {
             if (nv < d.max_voids) {
@@ -462,6 +491,10 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
                 ++suppressed;
             }
         }
+    }
+    if (corr != 0.0) {
+        const R rc = (R)corr;
+        for (int i = i0; i < i1; ++i) sig[(size_t)i * S + s] += rc;
     }
     d.nv[inst] = nv;
     for (int k = 0; k < nv; ++k) {
@@ -547,6 +580,7 @@ void launch_edge_static(const Dev &d, hipStream_t st)
 void launch_node_V(const Dev &d, bool fp32, hipStream_t st)
 {
     k_node_V<<<nblocks(d.ns), 256, 0, st>>>(d, fp32 ? 1 : 0);
+    k_tree_V<<<nblocks(d.n_trees), 256, 0, st>>>(d);
 }
 void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, hipStream_t st)
 {
