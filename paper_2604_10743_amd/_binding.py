@@ -173,12 +173,14 @@ class Batch:
         if torch_alloc:
             dev = torch.cuda.current_device()
             st = torch.cuda.current_stream()
+            _alloc_fn = torch.cuda.caching_allocator_alloc
+            _delete_fn = torch.cuda.caching_allocator_delete
 
             def _a(nbytes, ctx):
-                return torch.cuda.caching_allocator_alloc(int(nbytes), dev, st)
+                return _alloc_fn(int(nbytes), dev, st)
 
             def _f(ptr, ctx):
-                torch.cuda.caching_allocator_delete(int(ptr))
+                _delete_fn(int(ptr))
             self._alloc_fns = (ALLOC_FN(_a), FREE_FN(_f))
             self._alloc = Allocator(self._alloc_fns[0], self._alloc_fns[1], None)
         if stream is None:

@@ -385,7 +385,7 @@ __device__ void add_void(const Dev &d, int inst, int t, int s, int v, int step, 
 // lowest node) which stamps the Robin row (eq. 20) and refactors the tree.
 //
 // Conservation projection: the scheme keeps sum_i V_i sigma_i + B * (void
-// volumes) equal to its initial value exactly; in floating point the rounding
+// volumes) equal to its value at the start of the launch exactly; in floating point the rounding
 // of dt f (whose node sums cancel) would make that content drift linearly in
 // the step count.  The content is accumulated in FP64 during the back
 // substitution and the uniform correction restoring it is folded into the
@@ -424,7 +424,10 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
     }
     int suppressed = 0;
     const double Vsum = d.tree_V[t];
-    const double Q0 = d.sigT * Vsum;
+    // conserved content at launch start: sum V sigma + B * void volume
+    double Q0 = 0.0;
+    for (int i = i0; i < i1; ++i) Q0 += d.V[i] * (double)sig[(size_t)i * S + s];
+    for (int k = 0; k < nv; ++k) Q0 += d.B * vvol[k];
     double corr = 0.0;
 
     for (int st = 0; st < n_steps; ++st) {
