@@ -432,26 +432,41 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
 
     for (int st = 0; st < n_steps; ++st) {
         const R rc = (R)corr;
-        // rhs, eliminated leaf-to-root: b_i = V_i sigma_i + dt f_i + sum_c l_c b_c
+        // rhs, eliminated leaf-to-root: b_i = V_i sigma_i + dt f_i + sum_c l_c b_c.
+        // The previous node's value stays in a register: along a chain the
+        // child of i is i+1, so no store->load round trip is needed.
+        R b_next = (R)0, l_next = (R)0;
         for (int i = i1 - 1; i >= i0; --i) {
             size_t x = (size_t)i * S + s;
             R b = Vr[i] * (sig[x] + rc);
             if (!in_list(i, vn, nv)) b += dtf[x];
             for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k) {
-                size_t y = (size_t)d.child[k] * S + s;
-                b += lf[y] * sig[y];
+                int c = d.child[k];
+                if (c == i + 1) {
+                    b += l_next * b_next;
+                } else {
+                    size_t y = (size_t)c * S + s;
+                    b += lf[y] * sig[y];
+                }
             }
             sig[x] = b;
+            b_next = b;
+            l_next = lf[x];
         }
         // back substitution root-to-leaf; track the nucleation candidate peak
         R mx = (R)0;
         bool any = false;
         double Q = 0.0;
+        R v_prev = (R)0;
         for (int i = i0; i < i1; ++i) {
             size_t x = (size_t)i * S + s;
             R v = sig[x] * dinv[x];
-            if (i > i0) v += lf[x] * sig[(size_t)d.parent[i] * S + s];
+            if (i > i0) {
+                int p = d.parent[i];
+                v += lf[x] * (p == i - 1 ? v_prev : sig[(size_t)p * S + s]);
+            }
             sig[x] = v;
+            v_prev = v;
             Q += d.V[i] * (double)v;
             if (v >= sc[x] && !in_list(i, vn, nv)) {
                 mx = any ? (v > mx ? v : mx) : v;
