@@ -11,7 +11,8 @@ step resets it to t = 0 and runs it to time-to-failure.
 Prints ONE JSON line (rank 0).  Metric: stress-node-steps/s (sum over stepped
 trees of stress nodes x steps, divided by wall time).  Also reported: the
 roofline of the dominant kernel (the stepping kernel, timed with HIP events on
-its own stream inside the library), the FP64 oracle on host cores over a
+its own stream inside the library), the plain FP64 GPU form (one tree per
+lane, FP64) over one aging interval, the FP64 oracle on host cores over a
 bounded sample of the same workload, and a Monte Carlo samples/s figure on the
 32x32 mesh with 1024 samples.
 """
@@ -42,6 +43,7 @@ def main():
     ap.add_argument("--prec", type=int, default=1, help="1 = FP32 stepping, 0 = FP64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mc", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--mc-samples", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -94,7 +96,8 @@ def main():
     achieved = (bytes_ns * i1["node_steps"] / 1e9) / (step_ms / 1e3) if step_ms > 0 else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
-                "kernel": "k_step", "launches_per_step": launches,
+                "kernel": "k_chain<float,8,1024>" if args.prec == 1 else "k_step<double>",
+                "launches_per_step": launches,
                 "avg_launch_ms": step_ms / max(launches, 1),
                 "bytes_per_node_step": bytes_ns}
     r0 = results[0]
@@ -136,18 +139,44 @@ def main():
         Bm.close()
         log("bench: mc done")
 
+    if not args.no_plain:
+        # the plain FP64 GPU FDTD form (generic tree kernel, FP64) on one aging
+        # interval of the same workload, for the speedup of the batched form
+        Bp = P.Batch(g, mat, dict(run, prec=0, stepper=1))
+        Bp.ir_solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Bp.stress_step(run["ir_every"])
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        ip = Bp.info()
+        out["plain_fp64_gpu"] = {"value": ip["node_steps"] / tp, "unit": "node-steps/s",
+                                 "sample": f"pg400, {run['ir_every']} BE steps of every tree, FP64, "
+                                           "one (tree) per lane tree-elimination kernel",
+                                 "speedup_of_value": value / (ip["node_steps"] / tp)}
+        Bp.close()
+        log("bench: plain fp64 done")
+
     if not args.no_cpu:
+        import numpy as np
         from oracle import oracle as O
         O.build(force=False)
-        run_c = dict(run)
+        topo = O.topology(g, run["intervals_per_seg"])
+        n_tr = max(1, topo.n_trees // 4)
         t0 = time.perf_counter()
-        ref = O.run_sample(g, mat, run_c, max_outer=1)
+        u, I, j, d0 = O.ir_solve(g, g.res_R0)
+        sim = O.SampleSim(g, mat, run, topo)
+        sim.set_j(j)
+        act = np.zeros(topo.n_trees, np.uint8)
+        act[:n_tr] = 1
+        sim.set_active(act)
+        sim.steps(run["ir_every"], 0)
         tc = time.perf_counter() - t0
-        ns_c = info["n_stress"] * min(run["ir_every"], run["n_steps"])
+        ns_c = int(topo.tree_off[n_tr]) * run["ir_every"]
         out["cpu_baseline"] = {"value": ns_c / tc, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
-                               "sample": f"pg400, FP64 oracle, first aging interval only "
-                                         f"(IR solve + {run['ir_every']} BE steps of all "
-                                         f"{info['n_stress']} stress nodes + IR re-solve), {tc:.1f} s"}
+                               "sample": f"pg400, FP64 oracle, IR solve + {run['ir_every']} BE steps of the "
+                                         f"first {n_tr} of {topo.n_trees} trees ({ns_c} node-steps), "
+                                         f"{tc:.1f} s incl. setup"}
         log("bench: cpu baseline done")
     print(json.dumps(out), flush=True)
 

@@ -112,6 +112,9 @@ typedef struct {
     int32_t screen;              /* 1: steady-state immortality screen before stepping */
     int32_t max_voids_per_tree;  /* 0 disables nucleation */
     double T_ambient;            /* K, used when no thermal data is given */
+    int32_t stepper;             /* 0: resident chain kernel for chain trees (straight wires)
+                                    that fit a workgroup, generic tree kernel otherwise;
+                                    1: generic tree kernel for every tree */
 } em_run_params;
 
 /* Monte Carlo (Sec. IV-F): per-segment unit-mean lognormal multipliers on

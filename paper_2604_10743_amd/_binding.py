@@ -55,7 +55,8 @@ class RunParams(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("intervals_per_seg", C.c_int32), ("dt", C.c_double),
                 ("n_steps", C.c_int32), ("ir_every", C.c_int32), ("fail_frac", C.c_double),
                 ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32), ("prec", C.c_int32),
-                ("screen", C.c_int32), ("max_voids_per_tree", C.c_int32), ("T_ambient", C.c_double)]
+                ("screen", C.c_int32), ("max_voids_per_tree", C.c_int32), ("T_ambient", C.c_double),
+                ("stepper", C.c_int32)]
 
 
 class MCParams(C.Structure):
@@ -163,7 +164,7 @@ class Batch:
                       fail_frac=float(run["fail_frac"]), cg_rtol=float(run["cg_rtol"]),
                       cg_max_iter=int(run["cg_max_iter"]), prec=int(run["prec"]),
                       screen=int(run["screen"]), max_voids_per_tree=int(run["max_voids_per_tree"]),
-                      T_ambient=float(run["T_ambient"]))
+                      T_ambient=float(run["T_ambient"]), stepper=int(run.get("stepper", 0)))
         mcp = None
         if mc is not None:
             mcp = MCParams(struct_size=C.sizeof(MCParams), n_samples=int(mc["n_samples"]),

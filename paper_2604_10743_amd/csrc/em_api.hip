@@ -33,11 +33,13 @@ struct em_batch {
     int n_nodes = 0, n_res = 0, n_trees = 0, ns = 0, N = 0, max_tree_nodes = 0;
     std::vector<int> tree_off, parent, seg, dir, vert, kpos, seg_tree;
     Dev d{};
+    Dev *d_dev = nullptr;         // device copy of d (read by kernels through a pointer)
     bool have_j = false;
     bool live_dirty = true;
     int cg_iters_last = 0;
     int n_outer_done = 0;
     int step_counter = 0;         // steps taken through em_stress_step
+    int n_generic_trees = 0;      // trees stepped by the generic tree kernel
     // stream-time accounting with HIP events around each stepping launch and
     // each IR solve; folded in at the next synchronisation
     hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr, ev_d = nullptr;
@@ -246,7 +248,8 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
         return fail(b, EM_ERR_ARG, "bad material constants");
     if (r->intervals_per_seg < 1 || !(r->dt > 0) || !std::isfinite(r->dt) || r->n_steps < 0 || r->ir_every < 1 ||
         r->cg_max_iter < 1 || !(r->cg_rtol > 0) || (r->prec != EM_FP64 && r->prec != EM_FP32) ||
-        r->max_voids_per_tree < 0 || r->max_voids_per_tree > MAXV || !(r->T_ambient > 0))
+        r->max_voids_per_tree < 0 || r->max_voids_per_tree > MAXV || !(r->T_ambient > 0) ||
+        r->stepper < 0 || r->stepper > 1)
         return fail(b, EM_ERR_ARG, "bad run parameters (max_voids_per_tree <= 4)");
     if (mc && (mc->n_samples < 1 || mc->n_samples > 65535 || mc->cov_kappa < 0 || mc->cov_scrit < 0 || !std::isfinite(mc->cov_kappa) ||
                !std::isfinite(mc->cov_scrit)))
@@ -335,7 +338,8 @@ em_status timed_step(em_batch *b, int n_steps, int step0)
 {
     fold_timers(b);
     HIPCHK(b, hipEventRecord(b->ev_a, b->stream));
-    launch_step(b->d, b->fp32, n_steps, step0, b->stream);
+    if (b->d.n_chain_wg > 0) launch_chain(b->d, b->d_dev, b->fp32, n_steps, step0, b->stream);
+    if (b->n_generic_trees > 0) launch_step(b->d, b->fp32, n_steps, step0, b->stream);
     LAUNCHCHK(b);
     HIPCHK(b, hipEventRecord(b->ev_b, b->stream));
     b->step_pending = true;
@@ -450,6 +454,38 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     std::stable_sort(tree_perm.begin(), tree_perm.end(), [&](int x, int y) {
         return (P.tree_off[x + 1] - P.tree_off[x]) > (P.tree_off[y + 1] - P.tree_off[y]);
     });
+    // Chains (every FD node's parent is its predecessor: a straight wire
+    // rooted at an end) that fit one workgroup go to the resident chain
+    // kernel; instances are packed into workgroups without straddling.
+    const int cM = b->fp32 ? CHAIN_M32 : CHAIN_M64;
+    const int cWG = b->fp32 ? CHAIN_WG32 : CHAIN_WG64;
+    std::vector<uint8_t> tree_chain(nt, 0);
+    std::vector<int> lane_inst, lane_blk;
+    if (r->stepper == 0) {
+        for (int t = 0; t < nt; ++t) {
+            int i0 = P.tree_off[t], i1 = P.tree_off[t + 1];
+            if ((i1 - i0 + cM - 1) / cM > cWG) continue;
+            bool chain = true;
+            for (int i = i0 + 1; i < i1 && chain; ++i) chain = P.parent[i] == i - 1;
+            tree_chain[t] = chain;
+        }
+        int fill = 0;
+        for (int q = 0; q < nt; ++q) {
+            int t = tree_perm[q];
+            if (!tree_chain[t]) continue;
+            int L = (P.tree_off[t + 1] - P.tree_off[t] + cM - 1) / cM;
+            for (int s = 0; s < S; ++s) {
+                if (fill + L > cWG) {
+                    for (; fill < cWG; ++fill) { lane_inst.push_back(-1); lane_blk.push_back(0); }
+                    fill = 0;
+                }
+                for (int k = 0; k < L; ++k) { lane_inst.push_back(t * S + s); lane_blk.push_back(k); }
+                fill += L;
+            }
+        }
+        if (fill > 0)
+            for (; fill < cWG; ++fill) { lane_inst.push_back(-1); lane_blk.push_back(0); }
+    }
 
     Dev &d = b->d;
     d.n_nodes = nn; d.n_res = nr; d.n_trees = nt; d.ns = ns; d.N = N; d.S = S;
@@ -488,7 +524,11 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     UP(d.child_off, child_off); UP(d.child, child);
     UP(d.vinc_off, P.inc_off); UP(d.vinc, P.inc);
     UP(d.tseg_off, tseg_off); UP(d.tseg, tseg);
-    UP(d.via_up, via_up); UP(d.tree_perm, tree_perm);
+    UP(d.via_up, via_up); UP(d.tree_perm, tree_perm); UP(d.tree_chain, tree_chain);
+    d.n_chain_wg = (int)(lane_inst.size() / cWG);
+    b->n_generic_trees = 0;
+    for (int t = 0; t < nt; ++t) b->n_generic_trees += tree_chain[t] ? 0 : 1;
+    UP(d.lane_inst, lane_inst); UP(d.lane_blk, lane_blk);
 
     const size_t rs = b->fp32 ? 4 : 8;
     const size_t NS = (size_t)ns * S, RS = (size_t)nr * S, IS = (size_t)nt * S, VS = (size_t)nn * S;
@@ -499,6 +539,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     d.lfac = dalloc(b, rs * NS); d.sc = dalloc(b, rs * NS);
     if (!d.Vr || !d.sigma || !d.dtf || !d.dinv || !d.lfac || !d.sc) return fail(b, EM_ERR_OOM, "device allocation");
     AL(d.psi, double, NS);
+    if (b->n_generic_trees > 0) { AL(d.wsp, double, NS); } else { d.wsp = nullptr; }
     AL(d.xi_k, double, RS); AL(d.xi_s, double, RS);
     AL(d.jseg, double, RS); AL(d.dR, double, RS); AL(d.open, uint8_t, RS); AL(d.seg_mortal, uint8_t, RS);
     AL(d.inst_active, uint8_t, IS); AL(d.tree_mortal, uint8_t, IS); AL(d.nv, int, IS);
@@ -523,6 +564,9 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     AL(d.t_prev, double, S); AL(d.d_prev, double, S); AL(d.failed, int, S); AL(d.outer_idx, int, S);
 
     hipStream_t stq = b->stream;
+    b->d_dev = (Dev *)dalloc(b, sizeof(Dev));
+    if (!b->d_dev) return fail(b, EM_ERR_OOM, "device allocation");
+    HIPCHK(b, hipMemcpyAsync(b->d_dev, &d, sizeof(Dev), hipMemcpyHostToDevice, stq));
     HIPCHK(b, hipMemsetAsync(d.inst_active, 1, IS, stq));
     HIPCHK(b, hipMemsetAsync(d.sample_active, 1, S, stq));
     launch_fill_f64(d.u, VS, g->vdd, stq);

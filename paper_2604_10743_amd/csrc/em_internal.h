@@ -18,6 +18,11 @@ constexpr int MAXV = 4;                 // void slots per (tree, sample)
 constexpr double E_CHG = 1.602176634e-19;
 constexpr double K_B = 1.380649e-23;
 constexpr int EV_WORDS = 5;             // sample, tree, step, node, host segment
+// resident chain kernel: nodes per lane and lanes per workgroup
+#define CHAIN_M32 8
+#define CHAIN_WG32 1024
+#define CHAIN_M64 8
+#define CHAIN_WG64 512
 
 struct Dev {
     // ---- sizes ----
@@ -48,12 +53,16 @@ struct Dev {
     const int *tseg_off, *tseg;         // segments of each tree
     const uint8_t *via_up;              // vertex has a via to a strictly higher layer
     const int *tree_perm;               // lane slot -> tree id (larger trees first)
+    const uint8_t *tree_chain;          // tree stepped by the resident chain kernel
+    const int *lane_inst, *lane_blk;    // chain kernel lanes: instance, block index
+    int n_chain_wg;
     // ---- per stress node statics (FP64) ----
     double *T, *V, *g0, *rob0, *gdx0, *mdrv;
     double *tree_V;                     // [n_trees] total control volume
     // ---- per (node, sample) stepping state; element type float or double ----
     void *sigma, *dtf, *dinv, *lfac, *sc, *Vr;
     double *psi;                        // screen scratch / steady stress [node][S]
+    double *wsp;                        // stepping workspace [node][S] (generic tree kernel)
     // ---- Monte Carlo draws [res][S] ----
     double *xi_k, *xi_s;
     // ---- per (sample, segment) ----
@@ -103,6 +112,7 @@ void launch_factor(const Dev &d, bool fp32, hipStream_t st);
 void launch_screen(const Dev &d, bool apply, hipStream_t st);
 void launch_step(const Dev &d, bool fp32, int n_steps, int step0, hipStream_t st);
 void launch_void_dR(const Dev &d, hipStream_t st);
+void launch_chain(const Dev &d, const Dev *d_dev, bool fp32, int n_steps, int step0, hipStream_t st);
 void launch_set_sigma_T(const Dev &d, bool fp32, hipStream_t st);
 void launch_inject_void(const Dev &d, bool fp32, int sample, int tree, int node, hipStream_t st);
 void launch_copy_sigma(const Dev &d, bool fp32, int sample, double *out_dev, bool to_state, hipStream_t st);

@@ -1,0 +1,524 @@
+// Resident chain kernel: backward-Euler stepping of wire trees that are
+// chains (every FD node has at most one child in pre-order, i.e. a straight
+// wire split into segments -- the common case of power stripes), held on chip
+// for a whole aging interval.
+//
+// Layout.  A workgroup of WG lanes holds whole instances (tree, sample); each
+// lane owns a block of at most M consecutive FD nodes of one instance.  The
+// first node of every block is a separator; the others are the block's
+// interior.  Per step:
+//   1. rhs b = V (sigma + corr) + dt f                        (registers)
+//   2. interior Thomas solve with zero separator values      (registers)
+//      -> y, plus the precomputed responses alpha, beta to the left and
+//      right separators (interior = y + alpha x_k + beta x_{k+1})
+//   3. reduced tridiagonal system on the separators, solved by parallel
+//      cyclic reduction through LDS; instance boundaries have zero coupling,
+//      so one reduction serves every instance packed in the workgroup
+//   4. back-out of the interior; void growth; nucleation test
+// The elimination is exact (a reordering of the tree elimination); only the
+// rounding order differs.  The factors (interior Thomas multipliers, alpha,
+// beta, cyclic-reduction multipliers) are built in the kernel at launch start
+// and rebuilt when a void row is stamped, so HBM is touched once per launch.
+// The stress content sum V sigma + B * void volume is projected back to its
+// launch-start value every `proj_every` steps (rounding-level correction, see
+// the tree kernel).
+#include "em_internal.h"
+#include <cmath>
+
+namespace em {
+
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int N>
+struct Log2 { static constexpr int v = 1 + Log2<N / 2>::v; };
+template <>
+struct Log2<1> { static constexpr int v = 0; };
+
+__device__ inline int chain_host_segment(const Dev &d, int v, int s)
+{
+    int x = d.vert[v];
+    if (x < 0) return d.seg[v];
+    int best = -1;
+    double bd = 0.0;
+    for (int k = d.vinc_off[x]; k < d.vinc_off[x + 1]; ++k) {
+        int e = d.vinc[k];
+        double j = d.jseg[(size_t)s * d.n_res + e];
+        double drv = (d.rb[e] == x) ? j : -j;
+        if (best < 0 || drv > bd) { best = e; bd = drv; }
+    }
+    return best;
+}
+
+__device__ inline double chain_robin_weight(const Dev &d, int v, int s)
+{
+    double r = 0.0;
+    if (d.parent[v] >= 0) r += d.xi_k[(size_t)d.seg[v] * d.S + s] * d.rob0[v];
+    for (int k = d.child_off[v]; k < d.child_off[v + 1]; ++k) {
+        int c = d.child[k];
+        r += d.xi_k[(size_t)d.seg[c] * d.S + s] * d.rob0[c];
+    }
+    return r;
+}
+
+struct ChainHot {
+    void *sigma;
+    const void *Vr, *dtf, *sc;
+    const int *lane_inst, *lane_blk, *tree_off;
+    const uint8_t *sample_active, *inst_active;
+    const Dev *dev;          // device-resident copy of every other field
+    int S, n_steps, step0, proj_every;
+    double dt;
+};
+
+// dt * kappa-scaled conductance of the edge (parent(i), i) for sample s
+__device__ inline double edge_dtg(const Dev *d, int i, int s, double dt)
+{
+    return dt * d->xi_k[(size_t)d->seg[i] * d->S + s] * d->g0[i];
+}
+
+template <typename R, int M, int WG>
+__global__ __launch_bounds__(WG) void k_chain(ChainHot h)
+{
+    constexpr int LEV = Log2<WG>::v;
+    __shared__ R s_al[LEV][WG];
+    __shared__ R s_ga[LEV][WG];
+    __shared__ R s_x[2][WG];
+    __shared__ R s_e[3][WG];
+    __shared__ double s_q[WG];
+
+    const Dev *d = h.dev;
+    const int lane = threadIdx.x;
+    const size_t gl = (size_t)blockIdx.x * WG + lane;
+    const int S = h.S;
+    const int inst = h.lane_inst[gl];
+    const int kb = inst >= 0 ? h.lane_blk[gl] : 0;
+    int t = 0, s = 0, start = 0, cnt = 0, lo = lane, hi = lane, nT = 0;
+    bool act = false;
+    if (inst >= 0) {
+        t = inst / S;
+        s = inst - t * S;
+        int base = h.tree_off[t];
+        nT = h.tree_off[t + 1] - base;
+        start = base + kb * M;
+        cnt = min(M, nT - kb * M);
+        lo = lane - kb;
+        hi = lo + (nT + M - 1) / M - 1;
+        act = h.sample_active[s] && h.inst_active[inst];
+    }
+    const bool first = act && kb == 0;
+    const bool last = act && (kb * M + cnt == nT);
+    if (!act) cnt = 0;
+    if (act && lane == lo)
+        atomicAdd(d->node_steps, (unsigned long long)nT * (unsigned long long)h.n_steps);
+
+    R *sig = (R *)h.sigma;
+    const R *dtf_g = (const R *)h.dtf;
+    const R *sc_g = (const R *)h.sc;
+    const R *Vr_g = (const R *)h.Vr;
+    const double dt = h.dt;
+
+    // ---- per-lane node data (registers for the whole launch) ----
+    R sg[M], fv[M], w[M], dinv[M], al[M], be[M];
+    R gE[M + 1];                    // gE[j] = dt*g of edge (j-1, j); gE[0] previous block, gE[cnt] next block
+    R scmin = (R)INFINITY;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        sg[j] = 0; fv[j] = 0; w[j] = 0; dinv[j] = 0; al[j] = 0; be[j] = 0;
+        if (j < cnt) {
+            size_t x = (size_t)(start + j) * S + s;
+            sg[j] = sig[x];
+            fv[j] = dtf_g[x];
+            R scj = sc_g[x];
+            scmin = scj < scmin ? scj : scmin;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j <= M; ++j) {
+        gE[j] = 0;
+        if (act && j <= cnt) {
+            bool exists = (j == 0) ? !first : (j == cnt ? !last : true);
+            if (exists) gE[j] = (R)edge_dtg(d, start + j, s, dt);
+        }
+    }
+    int nv = act ? d->nv[inst] : 0;
+    unsigned vmask = 0;             // block nodes carrying a void
+    auto refresh_vmask = [&]() {
+        vmask = 0;
+        for (int k = 0; k < nv; ++k) {
+            int jv = d->vnode[inst * MAXV + k] - start;
+            if (jv >= 0 && jv < cnt) vmask |= 1u << jv;
+        }
+    };
+    if (act) refresh_vmask();
+    auto e_first = [&]() -> R {     // coupling from the separator to what follows it
+        R e = gE[1];
+        if (cnt == 1) e = gE[1];   // gE[cnt] is the next block's edge
+        return e;
+    };
+
+    // ---- factorisation (interior Thomas, alpha/beta, reduced row, PCR) ----
+    R dfin = 1;
+    auto factor = [&]() {
+        R Dg[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) Dg[j] = (j < cnt ? Vr_g[start + j] : (R)0) + gE[j] + gE[j + 1];
+        for (int k = 0; k < nv; ++k) {          // Robin rows of the block's voids
+            int jv = d->vnode[inst * MAXV + k] - start;
+            R rw = (R)(dt * d->vrob[inst * MAXV + k]);
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+                if (j == jv) Dg[j] += rw;
+        }
+        // interior nodes 1..cnt-1: forward multipliers and pivots
+#pragma unroll
+        for (int j = 1; j < M; ++j) {
+            if (j < cnt) {
+                R dp = Dg[j];
+                if (j >= 2) { w[j] = gE[j] * dinv[j - 1]; dp = Dg[j] - w[j] * gE[j]; }
+                else w[j] = 0;
+                dinv[j] = (R)1 / dp;
+            }
+        }
+        // alpha = T^-1 (gE[1] e_first), beta = T^-1 (gE[cnt] e_last)
+        {
+            R a = 0;
+#pragma unroll
+            for (int j = 1; j < M; ++j)
+                if (j < cnt) { a = (j == 1) ? gE[1] : w[j] * a; al[j] = a; }
+            R an = 0, bn = 0;
+#pragma unroll
+            for (int j = M - 1; j >= 1; --j) {
+                if (j < cnt) {
+                    const R uj = (j + 1 < cnt) ? gE[j + 1] * dinv[j] : (R)0;
+                    const R bj = (j == cnt - 1) ? gE[cnt] : (R)0;
+                    an = al[j] * dinv[j] + uj * an;
+                    bn = bj * dinv[j] + uj * bn;
+                    al[j] = an;
+                    be[j] = bn;
+                }
+            }
+        }
+        // the block's first interior node (F) and last node (L) in terms of
+        // (own separator, next separator)
+        R aF, bF, aL, bL;
+        if (cnt >= 2) {
+            aF = al[1]; bF = be[1];
+            aL = 0; bL = 0;
+#pragma unroll
+            for (int j = 1; j < M; ++j) if (j == cnt - 1) { aL = al[j]; bL = be[j]; }
+        } else {
+            aF = 0; bF = 1;
+            aL = 1; bL = 0;
+        }
+        s_x[0][lane] = aL;
+        s_x[1][lane] = bL;
+        lds_barrier();
+        const R aLp = (act && !first) ? s_x[0][lane - 1] : (R)0;
+        const R bLp = (act && !first) ? s_x[1][lane - 1] : (R)0;
+        lds_barrier();
+        R A = 0, Dd = 1, C = 0;
+        if (act) {
+            const R e1 = e_first();
+            A = -gE[0] * aLp;
+            Dd = Dg[0] - gE[0] * bLp - e1 * aF;
+            C = -e1 * bF;
+        }
+        // cyclic reduction of the separator matrix; keep the rhs multipliers
+#pragma unroll
+        for (int l = 0; l < LEV; ++l) {
+            const int dd = 1 << l;
+            s_e[0][lane] = A; s_e[1][lane] = Dd; s_e[2][lane] = C;
+            lds_barrier();
+            R al_l = 0, ga_l = 0, Am = 0, Cm = 0, Ap = 0, Cp = 0;
+            if (A != (R)0) {
+                al_l = -A / s_e[1][lane - dd];
+                Am = s_e[0][lane - dd]; Cm = s_e[2][lane - dd];
+            }
+            if (C != (R)0) {
+                ga_l = -C / s_e[1][lane + dd];
+                Ap = s_e[0][lane + dd]; Cp = s_e[2][lane + dd];
+            }
+            lds_barrier();
+            Dd = Dd + al_l * Cm + ga_l * Ap;
+            A = al_l * Am;
+            C = ga_l * Cp;
+            s_al[l][lane] = al_l;
+            s_ga[l][lane] = ga_l;
+        }
+        dfin = (R)1 / Dd;
+        lds_barrier();
+    };
+    factor();
+
+    // ---- segmented (per-instance) sums over the lanes of the workgroup ----
+    auto seg_sum = [&](double v) -> double {
+        s_q[lane] = v;
+        lds_barrier();
+#pragma unroll
+        for (int l = 0; l < LEV; ++l) {
+            const int dd = 1 << l;
+            if (act && ((lane - lo) & ((dd << 1) - 1)) == 0 && lane + dd <= hi) s_q[lane] += s_q[lane + dd];
+            lds_barrier();
+        }
+        double r = act ? s_q[lo] : 0.0;
+        lds_barrier();
+        return r;
+    };
+    // stress content of this lane: its nodes plus the voids on them (a void's
+    // volume is only ever written by the lane that owns its node)
+    auto content = [&]() -> double {
+        double q = 0.0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) if (j < cnt) q += (double)Vr_g[start + j] * (double)sg[j];
+        if (vmask) {
+            for (int k = 0; k < nv; ++k) {
+                int jv = d->vnode[inst * MAXV + k] - start;
+                if (jv >= 0 && jv < cnt) q += d->B * d->vvol[inst * MAXV + k];
+            }
+        }
+        return q;
+    };
+    double vs = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) if (j < cnt) vs += (double)Vr_g[start + j];
+    const double Vtot = seg_sum(vs);
+    const double Q0 = seg_sum(content());
+    // stress at the next block's separator (kept in step with that lane)
+    s_x[0][lane] = sg[0];
+    lds_barrier();
+    R sn = (act && !last) ? s_x[0][lane + 1] : (R)0;
+    lds_barrier();
+
+    for (int st = 0; st < h.n_steps; ++st) {
+        // 1. residual dt (A sigma + f) in FP64 (flux differences are exact),
+        //    rounded once for the solve: the step solves for the increment
+        R y[M];
+        double r0_part = 0.0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            y[j] = 0;
+            if (j < cnt) {
+                const double sj = (double)sg[j];
+                double r = ((vmask >> j) & 1u) ? 0.0 : (double)fv[j];
+                const double sr = (j + 1 < cnt) ? (double)sg[j + 1] : (double)sn;
+                r += (double)gE[j + 1] * (sr - sj);
+                if (j > 0) r += (double)gE[j] * ((double)sg[j - 1] - sj);
+                if (j == 0) r0_part = r; else y[j] = (R)r;
+            }
+        }
+        if (vmask) {                           // Robin sinks at void nodes
+            for (int k = 0; k < nv; ++k) {
+                const int jv = d->vnode[inst * MAXV + k] - start;
+                if (jv < 0 || jv >= cnt) continue;
+                const double rb = dt * d->vrob[inst * MAXV + k];
+#pragma unroll
+                for (int j = 0; j < M; ++j)
+                    if (j == jv) {
+                        if (j == 0) r0_part -= rb * (double)sg[0];
+                        else y[j] = (R)((double)y[j] - rb * (double)sg[j]);
+                    }
+            }
+        }
+        // 2. interior solve with zero separator values (y overwrites the rhs)
+        R yp = 0;
+#pragma unroll
+        for (int j = 1; j < M; ++j)
+            if (j < cnt) { yp = (j == 1) ? y[1] : y[j] + w[j] * yp; y[j] = yp; }
+        R yn = 0;
+#pragma unroll
+        for (int j = M - 1; j >= 1; --j)
+            if (j < cnt) {
+                const R uj = (j + 1 < cnt) ? gE[j + 1] * dinv[j] : (R)0;
+                yn = y[j] * dinv[j] + uj * yn;
+                y[j] = yn;
+            }
+        R yF = 0, yL = 0, sL = sg[0];
+        if (cnt >= 2) {
+            yF = y[1];
+#pragma unroll
+            for (int j = 1; j < M; ++j) if (j == cnt - 1) { yL = y[j]; sL = sg[j]; }
+        }
+        // 3. exchange with the previous block: its last interior value and its
+        //    last node's stress (for the separator's residual), then PCR
+        s_e[0][lane] = yL;
+        s_e[1][lane] = sL;
+        lds_barrier();
+        R Rk = 0;
+        if (act) {
+            double r0 = r0_part;
+            R yLp = 0;
+            if (!first) {
+                yLp = s_e[0][lane - 1];
+                r0 += (double)gE[0] * ((double)s_e[1][lane - 1] - (double)sg[0]);
+            }
+            Rk = (R)r0 + gE[0] * yLp + e_first() * yF;
+        }
+        int buf = 1;
+#pragma unroll
+        for (int l = 0; l < LEV; ++l) {
+            const int dd = 1 << l;
+            s_x[buf][lane] = Rk;
+            lds_barrier();
+            const R al_l = s_al[l][lane], ga_l = s_ga[l][lane];
+            R nr = Rk;
+            if (al_l != (R)0) nr += al_l * s_x[buf][lane - dd];
+            if (ga_l != (R)0) nr += ga_l * s_x[buf][lane + dd];
+            Rk = nr;
+            buf ^= 1;
+        }
+        const R xk = Rk * dfin;
+        s_x[buf][lane] = xk;
+        lds_barrier();
+        const R xn = (act && !last) ? s_x[buf][lane + 1] : (R)0;
+        // 4. increments and new stress
+        sg[0] += xk;
+#pragma unroll
+        for (int j = 1; j < M; ++j)
+            if (j < cnt) sg[j] += y[j] + al[j] * xk + be[j] * xn;
+        sn += xn;
+
+        // void growth on the lanes owning void nodes (eq. 15 accounting)
+        if (vmask) {
+            for (int k = 0; k < nv; ++k) {
+                const int q = inst * MAXV + k;
+                const int jv = d->vnode[q] - start;
+                if (jv < 0 || jv >= cnt) continue;
+                R sv = 0, fvv = 0;
+#pragma unroll
+                for (int j = 0; j < M; ++j) if (j == jv) { sv = sg[j]; fvv = fv[j]; }
+                const double vol = d->vvol[q] + (dt * d->vrob[q] * (double)sv + (double)fvv) / d->B;
+                d->vvol[q] = vol;
+                const int e = d->vseg[q];
+                const double W = d->w[e], H = d->h[e];
+                const double l = fmin(vol / (W * H), d->len[e]);
+                d->vlen[q] = l;
+                if (d->vphase[q] == 0 && l >= W) {
+                    d->vphase[q] = 1;
+                    if (d->vearly[q]) {
+                        d->open[(size_t)s * d->n_res + e] = 1;
+                        *d->open_dirty = 1u;
+                    }
+                }
+            }
+        }
+
+        // nucleation: any non-void node at or above its critical stress?
+        bool cand = false;
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+                if (j < cnt && sg[j] >= scmin && !((vmask >> j) & 1u)) cand = true;
+            if (cand) {
+                cand = false;
+#pragma unroll
+                for (int j = 0; j < M; ++j)
+                    if (j < cnt && !((vmask >> j) & 1u) && sg[j] >= sc_g[(size_t)(start + j) * S + s])
+                        cand = true;
+            }
+        }
+        if (__syncthreads_or(cand ? 1 : 0)) {
+            // peak candidate per instance, then the lowest node within the tie window
+            R lm = (R)(-INFINITY);
+            if (cand) {
+#pragma unroll
+                for (int j = 0; j < M; ++j)
+                    if (j < cnt && !((vmask >> j) & 1u) && sg[j] >= sc_g[(size_t)(start + j) * S + s])
+                        lm = sg[j] > lm ? sg[j] : lm;
+            }
+            s_q[lane] = (double)lm;
+            lds_barrier();
+#pragma unroll
+            for (int l = 0; l < LEV; ++l) {
+                const int dd = 1 << l;
+                if (act && ((lane - lo) & ((dd << 1) - 1)) == 0 && lane + dd <= hi)
+                    s_q[lane] = fmax(s_q[lane], s_q[lane + dd]);
+                lds_barrier();
+            }
+            const double mxd = act ? s_q[lo] : -INFINITY;
+            lds_barrier();
+            const bool any = act && mxd != -INFINITY;
+            const bool has = any && nv < d->max_voids;
+            const R mx = (R)mxd;
+            const R thr = mx - (R)1e-12 * (mx < 0 ? -mx : mx);
+            int loc = 0x7fffffff;
+            if (has && cand) {
+#pragma unroll
+                for (int j = M - 1; j >= 0; --j)
+                    if (j < cnt && !((vmask >> j) & 1u) && sg[j] >= thr &&
+                        sg[j] >= sc_g[(size_t)(start + j) * S + s])
+                        loc = start + j;
+            }
+            s_q[lane] = (double)loc;
+            lds_barrier();
+#pragma unroll
+            for (int l = 0; l < LEV; ++l) {
+                const int dd = 1 << l;
+                if (act && ((lane - lo) & ((dd << 1) - 1)) == 0 && lane + dd <= hi)
+                    s_q[lane] = fmin(s_q[lane], s_q[lane + dd]);
+                lds_barrier();
+            }
+            const int v = act ? (int)s_q[lo] : 0x7fffffff;
+            lds_barrier();
+            if (any && !has && lane == lo) d->n_suppressed[inst] += 1;
+            if (has && v != 0x7fffffff) {
+                if (lane == lo) {
+                    const int k = nv;
+                    const int q = inst * MAXV + k;
+                    d->vnode[q] = v;
+                    d->vvol[q] = 0.0;
+                    d->vlen[q] = 0.0;
+                    d->vrob[q] = chain_robin_weight(*d, v, s);
+                    const int hs = chain_host_segment(*d, v, s);
+                    d->vseg[q] = hs;
+                    d->vphase[q] = 0;
+                    d->vearly[q] = d->vert[v] >= 0 ? d->via_up[d->vert[v]] : 0;
+                    d->vstep[q] = h.step0 + st;
+                    d->nv[inst] = k + 1;
+                    const unsigned int qe = atomicAdd(d->ev_count, 1u);
+                    if ((int)qe < d->ev_cap) {
+                        int *E = d->events + (size_t)qe * EV_WORDS;
+                        E[0] = s; E[1] = t; E[2] = h.step0 + st; E[3] = v; E[4] = hs;
+                    }
+                }
+                nv += 1;
+            }
+            __syncthreads();   // void records written by lane `lo` visible to the owner lane
+            if (act) refresh_vmask();
+            factor();
+        }
+
+        // conservation projection (rounding-level)
+        if (h.proj_every > 0 && ((st + 1) % h.proj_every == 0 || st + 1 == h.n_steps)) {
+            const double Q = seg_sum(content());
+            const R corr = act ? (R)((Q0 - Q) / Vtot) : (R)0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) sg[j] += corr;
+            sn += corr;
+        }
+    }
+    // ---- write back ----
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+        if (j < cnt) sig[(size_t)(start + j) * S + s] = sg[j];
+}
+
+void launch_chain(const Dev &d, const Dev *d_dev, bool fp32, int n_steps, int step0, hipStream_t st)
+{
+    if (d.n_chain_wg <= 0) return;
+    ChainHot h;
+    h.sigma = d.sigma; h.Vr = d.Vr; h.dtf = d.dtf; h.sc = d.sc;
+    h.lane_inst = d.lane_inst; h.lane_blk = d.lane_blk; h.tree_off = d.tree_off;
+    h.sample_active = d.sample_active; h.inst_active = d.inst_active;
+    h.dev = d_dev;
+    h.S = d.S; h.n_steps = n_steps; h.step0 = step0; h.proj_every = 8;
+    h.dt = d.dt;
+    if (fp32) k_chain<float, CHAIN_M32, CHAIN_WG32><<<d.n_chain_wg, CHAIN_WG32, 0, st>>>(h);
+    else k_chain<double, CHAIN_M64, CHAIN_WG64><<<d.n_chain_wg, CHAIN_WG64, 0, st>>>(h);
+}
+
+}  // namespace em

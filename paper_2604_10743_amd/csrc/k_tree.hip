@@ -376,21 +376,25 @@ __device__ void add_void(const Dev &d, int inst, int t, int s, int v, int step, 
 }
 
 // ------------------------------------------------------------------------
-// Backward-Euler stepping: (C - dt A) sigma^{n+1} = C sigma^n + dt f, one
-// (tree, sample) per lane, n_steps steps per launch with the current
-// densities fixed.  Per step: leaf-to-root rhs elimination (the rhs b
-// overwrites sigma in place), root-to-leaf back substitution, void growth
-// from atom conservation (eq. 15), then the nucleation check (peak stress at
-// or above the node's critical stress; ties within 1e-12 relative go to the
-// lowest node) which stamps the Robin row (eq. 20) and refactors the tree.
+// Backward-Euler stepping, one (tree, sample) per lane, n_steps steps per
+// launch with the current densities fixed.  Each step solves the BE equation
+// (C - dt A) sigma^{n+1} = C sigma^n + dt f in increment form,
+// (C - dt A) delta = dt (A sigma^n + f): the residual is assembled in FP64
+// from exact flux differences, eliminated leaf-to-root into an FP64
+// workspace, back-substituted root-to-leaf, and added to the stored stress.
+// The rounding of the solve then scales with the residual, which vanishes at
+// steady state (for FP32 storage this acts as iterative refinement inside the
+// time stepping).  After each step: void growth from atom conservation
+// (eq. 15), then the nucleation check (peak stress at or above the node's
+// critical stress; ties within 1e-12 relative go to the lowest node), which
+// stamps the Robin row (eq. 20) and refactors the tree.
 //
 // Conservation projection: the scheme keeps sum_i V_i sigma_i + B * (void
-// volumes) equal to its value at the start of the launch exactly; in floating point the rounding
-// of dt f (whose node sums cancel) would make that content drift linearly in
-// the step count.  The content is accumulated in FP64 during the back
-// substitution and the uniform correction restoring it is folded into the
-// next step's right-hand side (and into the stored stress at the end of the
-// launch).  It changes the solution only at the rounding level.
+// volumes) equal to its value at the start of the launch exactly; the content
+// is accumulated in FP64 during the back substitution and the uniform
+// correction restoring it is folded into the next step (and into the stored
+// stress at the end of the launch).  It changes the solution only at the
+// rounding level.
 // ------------------------------------------------------------------------
 template <typename R>
 EM_KERNEL void k_step(Dev d, int n_steps, int step0)
@@ -399,11 +403,11 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
     if (slot >= d.n_trees * d.S) return;
     int t, s;
     int inst = inst_of_slot(d, slot, t, s);
-    if (!d.sample_active[s] || !d.inst_active[inst]) return;
+    if (!d.sample_active[s] || !d.inst_active[inst] || d.tree_chain[t]) return;
     const int S = d.S;
     R *sig = (R *)d.sigma;
     const R *dtf = (const R *)d.dtf, *dinv = (const R *)d.dinv, *lf = (const R *)d.lfac;
-    const R *sc = (const R *)d.sc, *Vr = (const R *)d.Vr;
+    const R *sc = (const R *)d.sc;
     const int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
     atomicAdd(d.node_steps, (unsigned long long)(i1 - i0) * (unsigned long long)n_steps);
 
@@ -430,43 +434,51 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
     for (int k = 0; k < nv; ++k) Q0 += d.B * vvol[k];
     double corr = 0.0;
 
+    double *W = d.wsp;              // FP64 workspace [node][S]
     for (int st = 0; st < n_steps; ++st) {
-        const R rc = (R)corr;
-        // rhs, eliminated leaf-to-root: b_i = V_i sigma_i + dt f_i + sum_c l_c b_c.
-        // The previous node's value stays in a register: along a chain the
-        // child of i is i+1, so no store->load round trip is needed.
-        R b_next = (R)0, l_next = (R)0;
+        // Increment form: (C - dt A) delta = dt (A sigma + f), residual in FP64
+        // from exact flux differences.  Pass 1 (leaf-to-root) assembles the
+        // residual and eliminates it into the parents: b_i = r_i + sum_c l_c b_c.
+        double b_next = 0.0, s_next = 0.0;
         for (int i = i1 - 1; i >= i0; --i) {
-            size_t x = (size_t)i * S + s;
-            R b = Vr[i] * (sig[x] + rc);
-            if (!in_list(i, vn, nv)) b += dtf[x];
+            const size_t x = (size_t)i * S + s;
+            const double si = (double)sig[x] + corr;
+            const bool isv = in_list(i, vn, nv);
+            double r = isv ? 0.0 : (double)dtf[x];
+            const int p = d.parent[i];
+            if (p >= 0) r += d.dt * d.xi_k[(size_t)d.seg[i] * S + s] * d.g0[i] * (((double)sig[(size_t)p * S + s] + corr) - si);
             for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k) {
-                int c = d.child[k];
-                if (c == i + 1) {
-                    b += l_next * b_next;
-                } else {
-                    size_t y = (size_t)c * S + s;
-                    b += lf[y] * sig[y];
-                }
+                const int c = d.child[k];
+                const size_t y = (size_t)c * S + s;
+                const double gc = d.dt * d.xi_k[(size_t)d.seg[c] * S + s] * d.g0[c];
+                const double sc_ = (c == i + 1) ? s_next : (double)sig[y] + corr;
+                const double bc = (c == i + 1) ? b_next : W[y];
+                r += gc * (sc_ - si) + (double)lf[y] * bc;
             }
-            sig[x] = b;
-            b_next = b;
-            l_next = lf[x];
+            if (isv) {
+                for (int k = 0; k < nv; ++k) if (vn[k] == i) r -= d.dt * vrob[k] * si;
+            }
+            W[x] = r;
+            b_next = r;
+            s_next = si;
         }
-        // back substitution root-to-leaf; track the nucleation candidate peak
+        // Pass 2 (root-to-leaf): delta_i = b_i / d_i + l_i delta_parent;
+        // sigma += delta; track the nucleation candidate peak.
         R mx = (R)0;
         bool any = false;
         double Q = 0.0;
-        R v_prev = (R)0;
+        double dprev = 0.0;
         for (int i = i0; i < i1; ++i) {
-            size_t x = (size_t)i * S + s;
-            R v = sig[x] * dinv[x];
+            const size_t x = (size_t)i * S + s;
+            double dl = W[x] * (double)dinv[x];
             if (i > i0) {
-                int p = d.parent[i];
-                v += lf[x] * (p == i - 1 ? v_prev : sig[(size_t)p * S + s]);
+                const int p = d.parent[i];
+                dl += (double)lf[x] * (p == i - 1 ? dprev : W[(size_t)p * S + s]);
             }
+            W[x] = dl;
+            dprev = dl;
+            const R v = (R)((double)sig[x] + corr + dl);
             sig[x] = v;
-            v_prev = v;
             Q += d.V[i] * (double)v;
             if (v >= sc[x] && !in_list(i, vn, nv)) {
                 mx = any ? (v > mx ? v : mx) : v;
@@ -478,10 +490,10 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
             size_t x = (size_t)vn[k] * S + s;
             vvol[k] += (d.dt * vrob[k] * (double)sig[x] + (double)dtf[x]) / d.B;
             int e = vseg[k];
-            double W = d.w[e], H = d.h[e];
-            double l = fmin(vvol[k] / (W * H), d.len[e]);
+            double Wd = d.w[e], H = d.h[e];
+            double l = fmin(vvol[k] / (Wd * H), d.len[e]);
             vlen[k] = l;
-            if (vphase[k] == 0 && l >= W) {
+            if (vphase[k] == 0 && l >= Wd) {
                 vphase[k] = 1;
                 if (vearly[k]) {
                     d.open[(size_t)s * d.n_res + e] = 1;
