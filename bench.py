@@ -35,6 +35,22 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel_src: str, profile_md: str):
+    """HBM bytes per launch from the committed PMC summary, or None when the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    try:
+        txt = open(os.path.join(ROOT, profile_md)).read()
+        block = txt.split("```json", 1)[1].split("```", 1)[0]
+        pm = json.loads(block)
+        sha = hashlib.sha256(open(os.path.join(ROOT, kernel_src), "rb").read()).hexdigest()[:16]
+        if pm.get("source_sha256_16") != sha:
+            return None
+        return pm["traffic_bytes_per_launch"]
+    except (OSError, IndexError, ValueError, KeyError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -45,7 +61,19 @@ def main():
     ap.add_argument("--no-mc", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--mc-samples", type=int, default=1024)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only copy this many bytes device-to-device (a plain copy kernel of known "
+                         "size, to scale the FETCH_SIZE/WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 4}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is described in the design notes, not implemented", file=sys.stderr)
@@ -94,8 +122,11 @@ def main():
     step_ms = i1["step_kernel_ms"]
     launches = i1["step_launches"]
     achieved = (bytes_ns * i1["node_steps"] / 1e9) / (step_ms / 1e3) if step_ms > 0 else None
+    traffic = (measured_traffic("paper_2604_10743_amd/csrc/k_chain.hip", "profiles/k_chain_pg400.md")
+               if args.prec == 1 else None)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-scaled)",
                 "kernel": "k_chain<float,8,1024>" if args.prec == 1 else "k_step<double>",
                 "launches_per_step": launches,
                 "avg_launch_ms": step_ms / max(launches, 1),

@@ -40,6 +40,11 @@ struct em_batch {
     int n_outer_done = 0;
     int step_counter = 0;         // steps taken through em_stress_step
     int n_generic_trees = 0;      // trees stepped by the generic tree kernel
+    int n_inc = 0;                // node-incidence entries (SpMV nonzeros off the diagonal)
+    // CG iterations captured once in a HIP graph and replayed in blocks
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t cg_graph = nullptr;
+    hipGraphExec_t cg_exec = nullptr;
     // stream-time accounting with HIP events around each stepping launch and
     // each IR solve; folded in at the next synchronisation
     hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr, ev_d = nullptr;
@@ -279,29 +284,39 @@ em_status ir_solve_impl(em_batch *b)
         b->live_dirty = false;
     }
     const double rtol = b->run.cg_rtol;
+    launch_ir_gather_inc(d, b->n_inc, st);
     launch_ir_setup(d, st);
     launch_ir_finalize0(d, rtol, st);
     LAUNCHCHK(b);
     uint8_t *hconv = pinned(b, std::max<size_t>(d.S, 8));
     if (!hconv) return fail(b, EM_ERR_OOM, "pinned host buffer");
-    int it = 0;
-    const int check_every = 8;
-    for (;;) {
-        if (it % check_every == 0) {
-            HIPCHK(b, hipMemcpyAsync(hconv, d.conv, d.S, hipMemcpyDeviceToHost, st));
-            HIPCHK(b, hipStreamSynchronize(st));
-            bool all = true;
-            for (int s = 0; s < d.S; ++s) all &= hconv[s] != 0;
-            if (all) break;
-            if (it >= b->run.cg_max_iter) {
-                b->cg_iters_last = it;
-                return fail(b, EM_ERR_NOCONV, "PCG did not reach cg_rtol within cg_max_iter iterations");
-            }
+    // CG_BLOCK iterations (an even count, so the r.z parity pattern repeats)
+    // are captured once on a private stream and replayed as one graph launch.
+    constexpr int CG_BLOCK = 8;
+    if (!b->cg_exec) {
+        if (!b->cap_stream) HIPCHK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+        HIPCHK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < CG_BLOCK; ++k) {
+            launch_ir_spmv(d, b->cap_stream);
+            launch_ir_update(d, k, b->cap_stream);
+            launch_ir_pupdate(d, k, rtol, b->cap_stream);
         }
-        launch_ir_spmv(d, st);
-        launch_ir_update(d, it, st);
-        launch_ir_pupdate(d, it, rtol, st);
-        ++it;
+        HIPCHK(b, hipStreamEndCapture(b->cap_stream, &b->cg_graph));
+        HIPCHK(b, hipGraphInstantiate(&b->cg_exec, b->cg_graph, nullptr, nullptr, 0));
+    }
+    int it = 0;
+    for (;;) {
+        HIPCHK(b, hipMemcpyAsync(hconv, d.conv, d.S, hipMemcpyDeviceToHost, st));
+        HIPCHK(b, hipStreamSynchronize(st));
+        bool all = true;
+        for (int s = 0; s < d.S; ++s) all &= hconv[s] != 0;
+        if (all) break;
+        if (it >= b->run.cg_max_iter) {
+            b->cg_iters_last = it;
+            return fail(b, EM_ERR_NOCONV, "PCG did not reach cg_rtol within cg_max_iter iterations");
+        }
+        HIPCHK(b, hipGraphLaunch(b->cg_exec, st));
+        it += CG_BLOCK;
     }
     LAUNCHCHK(b);
     b->cg_iters_last = it;
@@ -554,10 +569,12 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     HIPCHK(b, hipEventCreate(&b->ev_a)); HIPCHK(b, hipEventCreate(&b->ev_b));
     HIPCHK(b, hipEventCreate(&b->ev_c)); HIPCHK(b, hipEventCreate(&b->ev_d));
     AL(d.G, double, RS);
+    AL(d.G_inc, double, (size_t)S * ninc_off[nn]);
+    b->n_inc = ninc_off[nn];
     AL(d.diag, double, VS); AL(d.rhs, double, VS); AL(d.u, double, VS); AL(d.r, double, VS);
     AL(d.z, double, VS); AL(d.p, double, VS); AL(d.q, double, VS);
     AL(d.live, uint8_t, VS); AL(d.live_changed, uint32_t, 1);
-    d.ir_nblk = (nn + 255) / 256;
+    d.ir_nblk = (nn + ir_nodes_per_block() - 1) / ir_nodes_per_block();
     AL(d.part, double, (size_t)S * d.ir_nblk * 4);
     AL(d.rz, double, 2 * (size_t)S); AL(d.bb, double, S); AL(d.conv, uint8_t, S); AL(d.drop, double, S);
     AL(d.ttf, double, S); AL(d.final_drop, double, S); AL(d.init_drop, double, S);
@@ -603,6 +620,9 @@ em_status em_batch_destroy(em_batch *b)
     if (b->h_flags) (void)hipHostFree(b->h_flags);
     for (hipEvent_t e : {b->ev_a, b->ev_b, b->ev_c, b->ev_d})
         if (e) (void)hipEventDestroy(e);
+    if (b->cg_exec) (void)hipGraphExecDestroy(b->cg_exec);
+    if (b->cg_graph) (void)hipGraphDestroy(b->cg_graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
     return EM_OK;
 }

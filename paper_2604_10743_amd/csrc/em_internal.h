@@ -87,11 +87,12 @@ struct Dev {
     int ev_cap;
     // ---- IR ([S][n_nodes] unless noted) ----
     double *G;                          // [S][res] conductance
+    double *G_inc;                      // [S][node incidence] conductance per SpMV entry
     double *diag, *rhs, *u, *r, *z, *p, *q;
     uint8_t *live;                      // [S][n_nodes]
     uint32_t *live_changed;
     double *part;                       // [S][nblk][4] block partial sums
-    double *rz;                         // [2][S]
+    double *rz;                         // [2][S] r.z, double-buffered by iteration parity
     double *bb;                         // [S]
     uint8_t *conv;                      // [S]
     double *drop;                       // [S]
@@ -120,6 +121,7 @@ void launch_copy_node_col(const Dev &d, bool fp32, int which, int sample, double
 
 // IR
 void launch_ir_conductance(const Dev &d, hipStream_t st);
+void launch_ir_gather_inc(const Dev &d, int ninc, hipStream_t st);
 void launch_ir_live_init(const Dev &d, hipStream_t st);
 void launch_ir_live_step(const Dev &d, hipStream_t st);
 void launch_ir_setup(const Dev &d, hipStream_t st);       // diag, rhs, r = b - A x, z, p, partials
@@ -127,6 +129,7 @@ void launch_ir_finalize0(const Dev &d, double rtol, hipStream_t st);
 void launch_ir_spmv(const Dev &d, hipStream_t st);        // q = A p, partial p.q
 void launch_ir_update(const Dev &d, int it, hipStream_t st);   // x,r,z; partial r.z, r.r
 void launch_ir_pupdate(const Dev &d, int it, double rtol, hipStream_t st);  // p = z + beta p, conv
+int ir_nodes_per_block();
 void launch_ir_finish(const Dev &d, hipStream_t st);      // u, j, drop
 void launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
 void launch_ttf_init(const Dev &d, double fail, hipStream_t st);

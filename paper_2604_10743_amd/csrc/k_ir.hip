@@ -12,6 +12,8 @@
 namespace em {
 
 #define IR_BS 256
+#define IR_NPT 4                      // nodes per thread in the CG kernels
+#define IR_NPB (IR_BS * IR_NPT)       // nodes per block
 #define EM_KERNEL __global__ __launch_bounds__(IR_BS)
 
 __device__ inline double wave_sum(double v)
@@ -86,6 +88,16 @@ EM_KERNEL void k_ir_conductance(Dev d)
     d.G[g] = d.open[g] ? 0.0 : 1.0 / (d.R0[r] + d.dR[g]);
 }
 
+// Conductance of every node-incidence entry, contiguous per node (SpMV rows).
+EM_KERNEL void k_ir_gather_inc(Dev d)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ninc = d.ninc_off[d.n_nodes];
+    if (g >= (long long)d.S * ninc) return;
+    int s = (int)(g / ninc), k = (int)(g % ninc);
+    d.G_inc[g] = d.G[(size_t)s * d.n_res + d.ninc_res[k]];
+}
+
 EM_KERNEL void k_ir_live_init(Dev d)
 {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -118,9 +130,10 @@ EM_KERNEL void k_ir_live_step(Dev d)
 EM_KERNEL void k_ir_setup(Dev d)
 {
     int s = blockIdx.y, bx = blockIdx.x;
-    int i = bx * IR_BS + threadIdx.x;
     double rz = 0, rr = 0, bbv = 0;
-    if (i < d.n_nodes) {
+    for (int c = 0; c < IR_NPT; ++c) {
+        int i = bx * IR_NPB + c * IR_BS + threadIdx.x;
+        if (i >= d.n_nodes) break;
         size_t x = (size_t)s * d.n_nodes + i;
         const double *G = d.G + (size_t)s * d.n_res;
         const double *u = d.u + (size_t)s * d.n_nodes;
@@ -137,7 +150,7 @@ EM_KERNEL void k_ir_setup(Dev d)
             }
             double r = b - Ax, z = r / dg;
             d.rhs[x] = b; d.r[x] = r; d.z[x] = z; d.p[x] = z;
-            rz = r * z; rr = r * r; bbv = b * b;
+            rz += r * z; rr += r * r; bbv += b * b;
         } else {
             d.rhs[x] = 0; d.r[x] = 0; d.z[x] = 0; d.p[x] = 0;
         }
@@ -158,58 +171,67 @@ EM_KERNEL void k_ir_finalize0(Dev d, double rtol)
     }
 }
 
+// q = A p on the free nodes; partial p.q.
 EM_KERNEL void k_ir_spmv(Dev d)
 {
     int s = blockIdx.y, bx = blockIdx.x;
-    int i = bx * IR_BS + threadIdx.x;
+    if (d.conv[s]) return;
     double pq = 0;
-    if (i < d.n_nodes && !d.conv[s]) {
+    for (int c = 0; c < IR_NPT; ++c) {
+        int i = bx * IR_NPB + c * IR_BS + threadIdx.x;
+        if (i >= d.n_nodes) break;
         size_t x = (size_t)s * d.n_nodes + i;
         double q = 0.0;
         if (is_free(d, s, i)) {
-            const double *G = d.G + (size_t)s * d.n_res;
+            // p vanishes on pads and dead nodes, so every neighbour can be summed
+            const double *Gi = d.G_inc + (size_t)s * d.ninc_off[d.n_nodes];
             const double *p = d.p + (size_t)s * d.n_nodes;
-            q = d.diag[x] * p[i];
-            for (int k = d.ninc_off[i]; k < d.ninc_off[i + 1]; ++k) {
-                int nb = d.ninc_nbr[k];
-                if (is_free(d, s, nb)) q -= G[d.ninc_res[k]] * p[nb];
-            }
-            pq = p[i] * q;
+            const double pi = p[i];
+            q = d.diag[x] * pi;
+            for (int k = d.ninc_off[i]; k < d.ninc_off[i + 1]; ++k) q -= Gi[k] * p[d.ninc_nbr[k]];
+            pq += pi * q;
         }
         d.q[x] = q;
     }
     block_partials(d, s, bx, pq, 0.0, 0.0, 0.0, 0x1);
 }
 
+// alpha = (r.z)/(p.q) from the partials (every block sums them in the same
+// order); x += alpha p, r -= alpha q, z = r/diag; partials r.z and r.r.
 EM_KERNEL void k_ir_update(Dev d, int it)
 {
     int s = blockIdx.y, bx = blockIdx.x;
-    int i = bx * IR_BS + threadIdx.x;
-    bool active = !d.conv[s];
-    double pq = active ? sum_partials(d, s, 0) : 0.0;
-    double alpha = (active && pq > 0.0) ? d.rz[(it & 1) * d.S + s] / pq : 0.0;
+    if (d.conv[s]) return;
+    const double pq = sum_partials(d, s, 0);
+    const double alpha = pq > 0.0 ? d.rz[(it & 1) * d.S + s] / pq : 0.0;
     double rz = 0, rr = 0;
-    if (i < d.n_nodes && active && is_free(d, s, i)) {
+    for (int c = 0; c < IR_NPT; ++c) {
+        int i = bx * IR_NPB + c * IR_BS + threadIdx.x;
+        if (i >= d.n_nodes) break;
+        if (!is_free(d, s, i)) continue;
         size_t x = (size_t)s * d.n_nodes + i;
         d.u[x] += alpha * d.p[x];
         double r = d.r[x] - alpha * d.q[x];
         double z = r / d.diag[x];
         d.r[x] = r; d.z[x] = z;
-        rz = r * z; rr = r * r;
+        rz += r * z; rr += r * r;
     }
-    if (active) block_partials(d, s, bx, 0.0, rz, rr, 0.0, 0x6);
+    block_partials(d, s, bx, 0.0, rz, rr, 0.0, 0x6);
 }
 
+// beta = (new r.z)/(old r.z); p = z + beta p; convergence flag.
 EM_KERNEL void k_ir_pupdate(Dev d, int it, double rtol)
 {
     int s = blockIdx.y, bx = blockIdx.x;
-    int i = bx * IR_BS + threadIdx.x;
     if (d.conv[s]) return;
-    double rz_new = sum_partials(d, s, 1);
-    double rr = sum_partials(d, s, 2);
-    double rz_old = d.rz[(it & 1) * d.S + s];
-    double beta = rz_old != 0.0 ? rz_new / rz_old : 0.0;
-    if (i < d.n_nodes && is_free(d, s, i)) {
+    const double rz_new = sum_partials(d, s, 1);
+    const double rr = sum_partials(d, s, 2);
+    const double rz_old = d.rz[(it & 1) * d.S + s];
+    const double beta = rz_old != 0.0 ? rz_new / rz_old : 0.0;
+    for (int c = 0; c < IR_NPT; ++c) {
+        int i = bx * IR_NPB + c * IR_BS + threadIdx.x;
+        if (i >= d.n_nodes) break;
+        if (!is_free(d, s, i)) continue;
         size_t x = (size_t)s * d.n_nodes + i;
         d.p[x] = d.z[x] + beta * d.p[x];
     }
@@ -223,13 +245,14 @@ EM_KERNEL void k_ir_pupdate(Dev d, int it, double rtol)
 EM_KERNEL void k_ir_finish_nodes(Dev d)
 {
     int s = blockIdx.y, bx = blockIdx.x;
-    int i = bx * IR_BS + threadIdx.x;
     double dm = -INFINITY;
-    if (i < d.n_nodes) {
+    for (int c = 0; c < IR_NPT; ++c) {
+        int i = bx * IR_NPB + c * IR_BS + threadIdx.x;
+        if (i >= d.n_nodes) break;
         size_t x = (size_t)s * d.n_nodes + i;
         if (d.is_pad[i]) d.u[x] = d.vdd;
         else if (!d.live[x]) d.u[x] = 0.0;
-        dm = (d.vdd - d.u[x]) / d.vdd;
+        dm = fmax(dm, (d.vdd - d.u[x]) / d.vdd);
     }
     __shared__ double red[IR_BS / 64];
     double m = wave_max(dm);
@@ -310,6 +333,10 @@ void launch_ir_conductance(const Dev &d, hipStream_t st)
 {
     k_ir_conductance<<<nb((long long)d.S * d.n_res), IR_BS, 0, st>>>(d);
 }
+void launch_ir_gather_inc(const Dev &d, int ninc, hipStream_t st)
+{
+    k_ir_gather_inc<<<nb((long long)d.S * ninc), IR_BS, 0, st>>>(d);
+}
 void launch_ir_live_init(const Dev &d, hipStream_t st)
 {
     k_ir_live_init<<<nb((long long)d.S * d.n_nodes), IR_BS, 0, st>>>(d);
@@ -338,6 +365,7 @@ void launch_ir_pupdate(const Dev &d, int it, double rtol, hipStream_t st)
 {
     k_ir_pupdate<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d, it, rtol);
 }
+int ir_nodes_per_block() { return IR_NPB; }
 void launch_ir_finish(const Dev &d, hipStream_t st)
 {
     k_ir_finish_nodes<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d);

@@ -270,6 +270,7 @@ EM_KERNEL void k_factor(Dev d)
     if (slot >= d.n_trees * d.S) return;
     int t, s;
     int inst = inst_of_slot(d, slot, t, s);
+    if (d.tree_chain[t]) return;         // the chain kernel factors in place
     int vn[MAXV];
     double vr[MAXV];
     int nv = d.nv[inst];
@@ -544,8 +545,9 @@ EM_KERNEL void k_void_dR(Dev d)
     int t, s;
     int inst = inst_of_slot(d, slot, t, s);
     double *dR = d.dR + (size_t)s * d.n_res;
-    for (int k = d.tseg_off[t]; k < d.tseg_off[t + 1]; ++k) dR[d.tseg[k]] = 0.0;
+    // voids never disappear, so only their host segments can carry a change
     int nv = d.nv[inst];
+    for (int k = 0; k < nv; ++k) dR[d.vseg[inst * MAXV + k]] = 0.0;
     for (int k = 0; k < nv; ++k) {
         int q = inst * MAXV + k;
         if (d.vearly[q]) continue;

@@ -81,7 +81,7 @@ def default_run(**over) -> dict:
     at 10 % worst IR-drop."""
     horizon = 10 * 365.25 * 86400.0
     r = dict(intervals_per_seg=20, n_steps=2000, dt=horizon / 2000, ir_every=100,
-             fail_frac=0.10, cg_rtol=1e-13, cg_max_iter=20000, prec=0, screen=1,
+             fail_frac=0.10, cg_rtol=1e-11, cg_max_iter=20000, prec=0, screen=1,
              max_voids_per_tree=4, T_ambient=378.0)
     r.update(over)
     return r

@@ -158,6 +158,7 @@ def test_single_step_with_injected_voids_fp64(em, oracle_mod):
 
 def test_ir_solve_matches_direct_solve(em, oracle_mod):
     g, mat, rn, _ = synth.workload("tiny_mesh")
+    rn = dict(rn, cg_rtol=1e-14, cg_max_iter=100000)
     _flush("ir tiny_mesh")
     B = em.Batch(g, mat, rn)
     drop = B.ir_solve()
