@@ -1,0 +1,219 @@
+"""FP64 CPU oracle of the learned screen: per-tree features, the MLP forward
+and backward passes, Adam, and the lazy-activation schedule.
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite and the benchmark's
+CPU-baseline leg, never by the product package; it shares no code with the
+HIP path.
+
+The learned screen has no counterpart in EMSpice 3; it is this library's own
+addition in front of the transient stage.  What it computes is defined here in
+plain numpy:
+
+* Features (12 per (tree, sample)) from quantities the paper defines: segment
+  lengths and current densities (Sec. II-C), the Arrhenius diffusivity
+  kappa = D0 exp(-Ea/kT) B Omega/(kT) (Sec. III-D), the zero-flux steady
+  stress of the immortality screen (Sec. II-B) against the critical stress,
+  and the diffusion time L^2/(pi^2 kappa) of the slowest Korhonen mode.
+* A multilayer perceptron 12 -> 256 -> 256 -> 256 -> 1 with GELU activations
+  in the exact erf form (Hendrycks & Gimpel, 2016), predicting
+  log10(t_nuc / 1e8 s).  Precision contract of the device path, mirrored
+  here: the operands of the three hidden-layer products (forward and
+  backward) are rounded to float32 and then to bfloat16 (round to nearest,
+  ties to even) before an exact-product, wide-accumulation contraction; the
+  output layer, bias, GELU and loss are unrounded.  ``rnd=None`` switches the
+  rounding off, which makes the backward pass the exact gradient of the
+  float64 network (pinned by central finite differences).
+* Mean-squared-error loss and Adam with bias-corrected moments (Kingma & Ba,
+  ICLR 2015, Algorithm 1).
+* Lazy activation: a steady-state-mortal tree whose predicted nucleation time
+  exceeds margin x (end of the first aging interval) is deferred; before the
+  aging interval ending at t_{k+1} it is activated once t_hat <= margin x
+  t_{k+1} and caught up by replaying the stored per-interval current
+  densities from t = 0.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+NF, HID = 12, 256
+T_REF = 1e8            # s; the network predicts log10(t_nuc / T_REF)
+E_CHG = 1.602176634e-19
+K_B = 1.380649e-23
+
+# flat parameter layout (row-major [out][in] weights)
+SHAPES = [("W1", (HID, NF)), ("b1", (HID,)), ("W2", (HID, HID)), ("b2", (HID,)),
+          ("W3", (HID, HID)), ("b3", (HID,)), ("w4", (HID,)), ("b4", (1,))]
+NPARAM = sum(int(np.prod(s)) for _, s in SHAPES)
+
+
+def unpack(p):
+    out, o = {}, 0
+    for name, shp in SHAPES:
+        n = int(np.prod(shp))
+        out[name] = np.asarray(p[o:o + n], np.float64).reshape(shp)
+        o += n
+    return out
+
+
+def pack(d):
+    return np.concatenate([np.asarray(d[name], np.float64).ravel() for name, _ in SHAPES])
+
+
+# ---------------------------------------------------------------------------
+# bfloat16 rounding: float64 -> float32 (IEEE round to nearest) -> the upper
+# 16 bits of the float32 pattern, rounding to nearest with ties to even.
+# ---------------------------------------------------------------------------
+def bf16(x):
+    x32 = np.ascontiguousarray(np.asarray(x, np.float64).astype(np.float32))
+    u = x32.view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    u = (u + np.uint64(0x7FFF) + lsb) & np.uint64(0xFFFF0000)
+    return u.astype(np.uint32).view(np.float32).astype(np.float64).reshape(np.shape(x))
+
+
+def _erf(z):
+    return np.vectorize(math.erf, otypes=[np.float64])(z)
+
+
+def gelu(z):
+    z = np.asarray(z, np.float64)
+    return 0.5 * z * (1.0 + _erf(z / math.sqrt(2.0)))
+
+
+def gelu_grad(z):
+    """d/dz of z Phi(z) = Phi(z) + z phi(z)."""
+    z = np.asarray(z, np.float64)
+    return 0.5 * (1.0 + _erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+
+
+def _ident(x):
+    return np.asarray(x, np.float64)
+
+
+def forward(p, X, rnd=bf16):
+    """Network output y [n] and the cache of pre-/post-activations."""
+    r = rnd if rnd is not None else _ident
+    P = unpack(p)
+    X = np.asarray(X, np.float64)
+    Z1 = r(X) @ r(P["W1"]).T + P["b1"]
+    H1 = gelu(Z1)
+    Z2 = r(H1) @ r(P["W2"]).T + P["b2"]
+    H2 = gelu(Z2)
+    Z3 = r(H2) @ r(P["W3"]).T + P["b3"]
+    H3 = gelu(Z3)
+    y = H3 @ P["w4"] + P["b4"][0]
+    return y, dict(X=X, Z1=Z1, H1=H1, Z2=Z2, H2=H2, Z3=Z3, H3=H3)
+
+
+def loss_and_grad(p, X, t, rnd=bf16):
+    """Mean squared error (1/n) sum (y - t)^2 and its gradient (flat layout)
+    by the chain rule through the three GELU layers."""
+    r = rnd if rnd is not None else _ident
+    P = unpack(p)
+    y, c = forward(p, X, rnd)
+    t = np.asarray(t, np.float64)
+    n = y.size
+    loss = float(np.mean((y - t) ** 2))
+    dy = 2.0 * (y - t) / n
+    g = {}
+    g["w4"] = c["H3"].T @ dy
+    g["b4"] = np.array([dy.sum()])
+    dZ3 = np.outer(dy, P["w4"]) * gelu_grad(c["Z3"])
+    g["W3"] = r(dZ3).T @ r(c["H2"])
+    g["b3"] = dZ3.sum(axis=0)
+    dZ2 = (r(dZ3) @ r(P["W3"])) * gelu_grad(c["Z2"])
+    g["W2"] = r(dZ2).T @ r(c["H1"])
+    g["b2"] = dZ2.sum(axis=0)
+    dZ1 = (r(dZ2) @ r(P["W2"])) * gelu_grad(c["Z1"])
+    g["W1"] = r(dZ1).T @ r(c["X"])
+    g["b1"] = dZ1.sum(axis=0)
+    return loss, pack(g)
+
+
+def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (bias-corrected first and second moments); t >= 1 is
+    the step number.  Returns the new (p, m, v)."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ---------------------------------------------------------------------------
+# Features
+# ---------------------------------------------------------------------------
+def kappa0(T, mat):
+    """Arrhenius diffusivity kappa = D0 exp(-Ea/kT) B Omega / (kT) (Sec. III-D)."""
+    T = np.asarray(T, np.float64)
+    kT = K_B * T
+    return mat["D0"] * np.exp(-mat["Ea_eV"] * E_CHG / kT) * mat["B"] * mat["Omega"] / kT
+
+
+FEATURE_NAMES = ["log10 Ltot/um", "log10 Lpath/um", "nseg/8", "njunc/4", "log10 jmax/1e9",
+                 "log10 jmean/1e9", "log10 kmean/1e-15", "log10 kmin/1e-15", "r = max sss/sc",
+                 "log10 max(r-1,1e-6)", "log10 tau/s - 8", "(Tmean-300)/100"]
+
+
+def features(topo, grid, mat, jseg, xi_k, T, sig_ss, sc):
+    """[n_trees][12] features of one sample.
+
+    topo: the tree partition; jseg [n_res] current density; xi_k [n_res]
+    diffusivity multipliers; T, sig_ss, sc [n_stress]: node temperature, the
+    screen's zero-flux steady stress, and the node critical stress.
+    """
+    N = topo.N
+    out = np.zeros((topo.n_trees, NF))
+    nchild = np.zeros(topo.n_stress, np.int64)
+    for i in range(topo.n_stress):
+        if topo.parent[i] >= 0:
+            nchild[topo.parent[i]] += 1
+    for t in range(topo.n_trees):
+        i0, i1 = int(topo.tree_off[t]), int(topo.tree_off[t + 1])
+        segs = sorted({int(topo.seg[i]) for i in range(i0, i1) if topo.parent[i] >= 0})
+        lens = np.array([grid.res_len[e] for e in segs])
+        js = np.array([abs(jseg[e]) for e in segs])
+        Ltot = lens.sum()
+        dist = {i0: 0.0}
+        kap = []
+        njunc = 0
+        for i in range(i0, i1):
+            p = int(topo.parent[i])
+            deg = nchild[i] + (1 if p >= 0 else 0)
+            njunc += deg >= 3
+            if p >= 0:
+                e = int(topo.seg[i])
+                dist[i] = dist[p] + grid.res_len[e] / N
+                kap.append(xi_k[e] * kappa0(0.5 * (T[i] + T[p]), mat))
+        Lpath = max(dist.values())
+        kap = np.array(kap)
+        kmean, kmin = kap.mean(), kap.min()
+        ss = np.asarray(sig_ss[i0:i1])
+        scn = np.asarray(sc[i0:i1])
+        fin = np.isfinite(ss)
+        rr = float(np.max(ss[fin] / scn[fin])) if fin.any() else -10.0
+        rr = min(max(rr, -10.0), 10.0)
+        tau = Lpath ** 2 / (math.pi ** 2 * kmean)
+        out[t] = [math.log10(Ltot / 1e-6), math.log10(Lpath / 1e-6), len(segs) / 8.0, njunc / 4.0,
+                  math.log10(max(js.max(), 1e3) / 1e9), math.log10(max((lens * js).sum() / Ltot, 1e3) / 1e9),
+                  math.log10(kmean / 1e-15), math.log10(kmin / 1e-15), rr,
+                  math.log10(max(rr - 1.0, 1e-6)), math.log10(tau) - 8.0,
+                  (float(np.mean(T[i0:i1])) - 300.0) / 100.0]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Lazy activation
+# ---------------------------------------------------------------------------
+def t_hat(y):
+    return T_REF * np.power(10.0, np.asarray(y, np.float64))
+
+
+def activation_interval(that, margin, K, dt):
+    """Index k of the aging interval (ending at t_{k+1} = (k+1) K dt) before
+    which a tree predicted to nucleate at ``that`` must be active: the
+    smallest k >= 0 with that <= margin t_{k+1}."""
+    T1 = margin * K * dt
+    return np.maximum(0, np.ceil(np.asarray(that) / T1) - 1).astype(np.int64)

@@ -1,0 +1,169 @@
+"""Pins of the learned-screen oracle (CPU only).
+
+Each pin checks the oracle against something other than itself: bfloat16
+rounding against hand-worked bit patterns and torch's own conversion, GELU
+against the normal-distribution table and its odd-part identity, the backward
+pass against central finite differences, Adam against its closed-form first
+two steps, and the features against closed forms on a straight line and a
+hand-measured branched tree.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from cases import UM, line_grid, material, run, tree_from_edges
+from oracle import surrogate_oracle as SO
+
+
+# ---------------------------------------------------------------- bfloat16
+def test_bf16_hand_values():
+    x = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -8 + 2.0 ** -20,
+                  -2.5, 3.0e-3, 0.0])
+    # spacing of bfloat16 at 1 is 2^-7: ties go to the even mantissa
+    want = np.array([1.0, 1.0, 1.0 + 2.0 ** -6, 1.0 + 2.0 ** -7, -2.5, None, 0.0], dtype=object)
+    got = SO.bf16(x)
+    for k in (0, 1, 2, 3, 4, 6):
+        assert got[k] == want[k], (k, got[k], want[k])
+    # 3e-3 = 1.536 x 2^-9 -> mantissa 1.5390625 (nearest of 1.53125, 1.5390625)
+    assert got[5] == 1.5390625 * 2.0 ** -9
+
+
+def test_bf16_matches_torch_conversion():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(5)
+    x = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-6, 6, 20000),
+                        (1.0 + np.arange(256) * 2.0 ** -15)])
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(SO.bf16(x), ref)
+
+
+# ------------------------------------------------------------------- GELU
+def test_gelu_table_values_and_identity():
+    # GELU(1) = Phi(1); Phi(1) = 0.841344746068543 (standard normal table)
+    assert abs(SO.gelu(1.0) - 0.841344746068543) < 1e-15
+    assert SO.gelu(0.0) == 0.0
+    z = np.linspace(-6, 6, 97)
+    # z Phi(z) - (-z) Phi(-z) = z (Phi(z) + Phi(-z)) = z
+    assert np.allclose(SO.gelu(z) - SO.gelu(-z), z, atol=1e-14, rtol=0)
+    h = 1e-5
+    fd = (SO.gelu(z + h) - SO.gelu(z - h)) / (2 * h)
+    assert np.allclose(SO.gelu_grad(z), fd, atol=1e-9, rtol=0)
+
+
+# --------------------------------------------------------- MLP gradients
+def _params(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    P = {}
+    for name, shp in SO.SHAPES:
+        fan_in = shp[1] if len(shp) == 2 else SO.HID
+        P[name] = rng.standard_normal(shp) * scale / math.sqrt(fan_in)
+    return SO.pack(P)
+
+
+def test_backward_matches_finite_differences():
+    rng = np.random.default_rng(11)
+    p = _params(3)
+    X = rng.standard_normal((6, SO.NF))
+    t = rng.standard_normal(6)
+    loss, g = SO.loss_and_grad(p, X, t, rnd=None)
+    # a few coordinates in every parameter block
+    offs, o = [], 0
+    for name, shp in SO.SHAPES:
+        n = int(np.prod(shp))
+        offs += list(o + rng.choice(n, size=min(n, 6), replace=False))
+        o += n
+    h = 1e-6
+    for k in offs:
+        pp, pm = p.copy(), p.copy()
+        pp[k] += h
+        pm[k] -= h
+        lp = SO.loss_and_grad(pp, X, t, rnd=None)[0]
+        lm = SO.loss_and_grad(pm, X, t, rnd=None)[0]
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(fd)), (k, fd, g[k])
+
+
+def test_rounded_forward_is_forward_of_rounded_operands():
+    # with every hidden-layer operand already a bfloat16 value, rounding must
+    # change nothing in the first layer's pre-activation
+    rng = np.random.default_rng(2)
+    p = SO.bf16(_params(4))
+    X = SO.bf16(rng.standard_normal((5, SO.NF)))
+    y_r, c_r = SO.forward(p, X)
+    y_n, c_n = SO.forward(p, X, rnd=None)
+    assert np.array_equal(c_r["Z1"], c_n["Z1"])
+    assert np.max(np.abs(y_r - y_n)) < 0.05 * (1 + np.max(np.abs(y_n)))
+
+
+# ------------------------------------------------------------------- Adam
+def test_adam_first_two_steps_closed_form():
+    rng = np.random.default_rng(9)
+    p0 = rng.standard_normal(50)
+    g1, g2 = rng.standard_normal(50), rng.standard_normal(50)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    m = v = np.zeros(50)
+    p1, m, v = SO.adam_step(p0, g1, m, v, 1, lr, b1, b2, eps)
+    # step 1: bias correction gives mhat = g, vhat = g^2
+    assert np.allclose(p1, p0 - lr * g1 / (np.abs(g1) + eps), rtol=0, atol=1e-15)
+    p2, m, v = SO.adam_step(p1, g2, m, v, 2, lr, b1, b2, eps)
+    mh = (b1 * (1 - b1) * g1 + (1 - b1) * g2) / (1 - b1 ** 2)
+    vh = (b2 * (1 - b2) * g1 ** 2 + (1 - b2) * g2 ** 2) / (1 - b2 ** 2)
+    assert np.allclose(p2, p1 - lr * mh / (np.sqrt(vh) + eps), rtol=0, atol=1e-15)
+
+
+# --------------------------------------------------------------- features
+def _oracle_features(O, grid, mat, rn):
+    topo = O.topology(grid, rn["intervals_per_seg"])
+    sim = O.SampleSim(grid, mat, rn, topo)
+    sim.set_j(grid.seg_j)
+    _, _, ss = sim.screen()
+    na = sim.node_arrays()
+    xi = np.ones(grid.n_res)
+    return SO.features(topo, grid, mat, grid.seg_j, xi, na["T"], ss, na["sc"]), topo
+
+
+def test_features_straight_line_closed_forms(oracle_mod):
+    L, S, j, T = 10 * UM, 3, 4e10, 378.0
+    g = line_grid(S=S, L=L, j=j, T=T)
+    mat = material(sigma_crit=100e6)
+    F, _ = _oracle_features(oracle_mod, g, mat, run())
+    f = F[0]
+    Lt = S * L
+    k = 2.22409e-14                         # Arrhenius value at 378 K (golden file)
+    Sd = SO.E_CHG * mat["Z"] * mat["rho_cu"] * j / mat["Omega"]
+    smax = mat["sigma_T"] + Sd * Lt / 2     # linear steady profile, volume mean at the midpoint
+    r = smax / mat["sigma_crit"]
+    assert abs(f[0] - math.log10(Lt / UM)) < 1e-12
+    assert abs(f[1] - math.log10(Lt / UM)) < 1e-12
+    assert f[2] == S / 8 and f[3] == 0.0
+    assert abs(f[4] - math.log10(j / 1e9)) < 1e-12 and abs(f[5] - math.log10(j / 1e9)) < 1e-12
+    assert abs(f[6] - math.log10(k / 1e-15)) < 3e-6 and abs(f[7] - f[6]) < 1e-12
+    assert abs(f[8] - r) < 1e-9 * r
+    assert abs(f[9] - math.log10(r - 1)) < 1e-9
+    assert abs(f[10] - (math.log10(Lt ** 2 / (math.pi ** 2 * k)) - 8)) < 3e-6
+    assert abs(f[11] - (T - 300) / 100) < 1e-12
+
+
+def test_features_branched_tree_hand_measures(oracle_mod):
+    # vertex 0 - 1 - 2 with a branch 1 - 3 and 3 - 4: segment lengths 10, 20, 5, 7 um
+    edges = [(0, 1), (1, 2), (1, 3), (3, 4)]
+    Ls = np.array([10, 20, 5, 7]) * UM
+    js = np.array([1e10, -3e10, 2e9, 0.0])
+    g = tree_from_edges(5, edges, Ls, 0.5 * UM, 0.2 * UM, js)
+    F, topo = _oracle_features(oracle_mod, g, material(), run())
+    assert topo.n_trees == 1
+    f = F[0]
+    assert abs(f[0] - math.log10(42.0)) < 1e-12
+    assert abs(f[1] - math.log10(30.0)) < 1e-12          # root 0 -> vertex 2
+    assert f[2] == 4 / 8 and f[3] == 1 / 4                # vertex 1 has degree 3
+    assert abs(f[4] - math.log10(3e10 / 1e9)) < 1e-12
+    jm = (10 * 1e10 + 20 * 3e10 + 5 * 2e9 + 0) / 42
+    assert abs(f[5] - math.log10(jm / 1e9)) < 1e-12
+
+
+# ------------------------------------------------------- lazy activation
+def test_activation_interval_hand_values():
+    K, dt, m = 100, 1.0, 2.0                 # margin x t_{k+1} = 200 (k + 1)
+    th = np.array([1.0, 200.0, 200.0001, 400.0, 1e4])
+    assert list(SO.activation_interval(th, m, K, dt)) == [0, 0, 1, 1, 49]
