@@ -13,7 +13,9 @@ plain numpy:
   lengths and current densities (Sec. II-C), the Arrhenius diffusivity
   kappa = D0 exp(-Ea/kT) B Omega/(kT) (Sec. III-D), the zero-flux steady
   stress of the immortality screen (Sec. II-B) against the critical stress,
-  and the diffusion time L^2/(pi^2 kappa) of the slowest Korhonen mode.
+  and the diffusion time L^2/(pi^2 kappa) of the slowest Korhonen mode over
+  the span between the stress peak and the neutral point of the steady
+  profile.
 * A multilayer perceptron 12 -> 256 -> 256 -> 256 -> 1 with GELU activations
   in the exact erf form (Hendrycks & Gimpel, 2016), predicting
   log10(t_nuc / 1e8 s).  Precision contract of the device path, mirrored
@@ -153,8 +155,8 @@ def kappa0(T, mat):
 
 
 FEATURE_NAMES = ["log10 Ltot/um", "log10 Lpath/um", "nseg/8", "njunc/4", "log10 jmax/1e9",
-                 "log10 jmean/1e9", "log10 kmean/1e-15", "log10 kmin/1e-15", "r = max sss/sc",
-                 "log10 max(r-1,1e-6)", "log10 tau/s - 8", "(Tmean-300)/100"]
+                 "log10 jmean/1e9", "log10 kmean/1e-15", "log10 kpk/1e-15", "r = max sss/sc",
+                 "log10 max(r-1,1e-6)", "log10 tau_pk/s - 8", "(Tpk-300)/100"]
 
 
 def features(topo, grid, mat, jseg, xi_k, T, sig_ss, sc):
@@ -163,6 +165,14 @@ def features(topo, grid, mat, jseg, xi_k, T, sig_ss, sc):
     topo: the tree partition; jseg [n_res] current density; xi_k [n_res]
     diffusivity multipliers; T, sig_ss, sc [n_stress]: node temperature, the
     screen's zero-flux steady stress, and the node critical stress.
+
+    The peak node p is the first node (lowest index) of largest finite
+    sig_ss / sc.  Its length scale Lpk is the distance along the root path
+    coordinate, |d(i) - d(p)| with d the distance from the root, to the
+    nearest node whose steady stress does not exceed sigma_T (floored at
+    0.1 um); on a straight line this is the distance to the neutral point of
+    the steady profile.  kappa_pk is the mean diffusivity of the edges at p,
+    tau_pk = Lpk^2 / (pi^2 kappa_pk).
     """
     N = topo.N
     out = np.zeros((topo.n_trees, NF))
@@ -170,6 +180,15 @@ def features(topo, grid, mat, jseg, xi_k, T, sig_ss, sc):
     for i in range(topo.n_stress):
         if topo.parent[i] >= 0:
             nchild[topo.parent[i]] += 1
+    children = [[] for _ in range(topo.n_stress)]
+    for i in range(topo.n_stress):
+        if topo.parent[i] >= 0:
+            children[topo.parent[i]].append(i)
+
+    def edge_kappa(i):          # edge (parent(i), i)
+        p = int(topo.parent[i])
+        return xi_k[int(topo.seg[i])] * kappa0(0.5 * (T[i] + T[p]), mat)
+
     for t in range(topo.n_trees):
         i0, i1 = int(topo.tree_off[t]), int(topo.tree_off[t + 1])
         segs = sorted({int(topo.seg[i]) for i in range(i0, i1) if topo.parent[i] >= 0})
@@ -184,23 +203,35 @@ def features(topo, grid, mat, jseg, xi_k, T, sig_ss, sc):
             deg = nchild[i] + (1 if p >= 0 else 0)
             njunc += deg >= 3
             if p >= 0:
-                e = int(topo.seg[i])
-                dist[i] = dist[p] + grid.res_len[e] / N
-                kap.append(xi_k[e] * kappa0(0.5 * (T[i] + T[p]), mat))
+                dist[i] = dist[p] + grid.res_len[int(topo.seg[i])] / N
+                kap.append(edge_kappa(i))
         Lpath = max(dist.values())
-        kap = np.array(kap)
-        kmean, kmin = kap.mean(), kap.min()
-        ss = np.asarray(sig_ss[i0:i1])
-        scn = np.asarray(sc[i0:i1])
-        fin = np.isfinite(ss)
-        rr = float(np.max(ss[fin] / scn[fin])) if fin.any() else -10.0
+        kmean = float(np.mean(kap))
+        # peak of the steady stress over the critical stress
+        pk, rr = -1, -np.inf
+        for i in range(i0, i1):
+            if np.isfinite(sig_ss[i]):
+                q = sig_ss[i] / sc[i]
+                if q > rr:
+                    pk, rr = i, q
+        if pk < 0:
+            pk, rr = i0, -10.0
         rr = min(max(rr, -10.0), 10.0)
-        tau = Lpath ** 2 / (math.pi ** 2 * kmean)
+        lpk = np.inf
+        for i in range(i0, i1):
+            if sig_ss[i] <= mat["sigma_T"]:
+                lpk = min(lpk, abs(dist[i] - dist[pk]))
+        lpk = max(lpk if np.isfinite(lpk) else Lpath, 1e-7)
+        ke = [edge_kappa(c) for c in children[pk]]
+        if topo.parent[pk] >= 0:
+            ke.append(edge_kappa(pk))
+        kpk = float(np.mean(ke))
+        tau = lpk ** 2 / (math.pi ** 2 * kpk)
         out[t] = [math.log10(Ltot / 1e-6), math.log10(Lpath / 1e-6), len(segs) / 8.0, njunc / 4.0,
                   math.log10(max(js.max(), 1e3) / 1e9), math.log10(max((lens * js).sum() / Ltot, 1e3) / 1e9),
-                  math.log10(kmean / 1e-15), math.log10(kmin / 1e-15), rr,
+                  math.log10(kmean / 1e-15), math.log10(kpk / 1e-15), rr,
                   math.log10(max(rr - 1.0, 1e-6)), math.log10(tau) - 8.0,
-                  (float(np.mean(T[i0:i1])) - 300.0) / 100.0]
+                  (float(T[pk]) - 300.0) / 100.0]
     return out
 
 

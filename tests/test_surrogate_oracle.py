@@ -124,25 +124,48 @@ def _oracle_features(O, grid, mat, rn):
 
 
 def test_features_straight_line_closed_forms(oracle_mod):
-    L, S, j, T = 10 * UM, 3, 4e10, 378.0
-    g = line_grid(S=S, L=L, j=j, T=T)
-    mat = material(sigma_crit=100e6)
-    F, _ = _oracle_features(oracle_mod, g, mat, run())
+    # segments of 10 and 13 um carrying the same j: the steady profile is
+    # linear, sigma_T at x = 11.5 um (volume mean = midpoint value), peak at
+    # the low-voltage end x = 23 um; the nearest node at or below sigma_T is
+    # the 20-interval node at x = 10 + 2 x 0.65 = 11.3 um, so Lpk = 11.7 um
+    j, T = 4e10, 378.0
+    g = tree_from_edges(3, [(0, 1), (1, 2)], np.array([10, 13]) * UM, 0.5 * UM, 0.2 * UM, j, T=T)
+    mat = material(sigma_crit=60e6)
+    rn = run()
+    F, topo = _oracle_features(oracle_mod, g, mat, rn)
     f = F[0]
-    Lt = S * L
+    Lt = 23 * UM
     k = 2.22409e-14                         # Arrhenius value at 378 K (golden file)
     Sd = SO.E_CHG * mat["Z"] * mat["rho_cu"] * j / mat["Omega"]
-    smax = mat["sigma_T"] + Sd * Lt / 2     # linear steady profile, volume mean at the midpoint
+    smax = mat["sigma_T"] + Sd * Lt / 2
     r = smax / mat["sigma_crit"]
-    assert abs(f[0] - math.log10(Lt / UM)) < 1e-12
-    assert abs(f[1] - math.log10(Lt / UM)) < 1e-12
-    assert f[2] == S / 8 and f[3] == 0.0
+    assert abs(f[0] - math.log10(23.0)) < 1e-12
+    assert abs(f[1] - math.log10(23.0)) < 1e-12
+    assert f[2] == 2 / 8 and f[3] == 0.0
     assert abs(f[4] - math.log10(j / 1e9)) < 1e-12 and abs(f[5] - math.log10(j / 1e9)) < 1e-12
     assert abs(f[6] - math.log10(k / 1e-15)) < 3e-6 and abs(f[7] - f[6]) < 1e-12
     assert abs(f[8] - r) < 1e-9 * r
     assert abs(f[9] - math.log10(r - 1)) < 1e-9
-    assert abs(f[10] - (math.log10(Lt ** 2 / (math.pi ** 2 * k)) - 8)) < 3e-6
+    assert abs(f[10] - (math.log10((11.7 * UM) ** 2 / (math.pi ** 2 * k)) - 8)) < 3e-6
     assert abs(f[11] - (T - 300) / 100) < 1e-12
+
+
+def test_features_uniform_line_peak_end():
+    # pure-numpy check of the peak/neutral-point rule on a prescribed profile
+    class Topo:
+        pass
+    t = Topo()
+    t.N, t.n_trees, t.n_stress = 4, 1, 5
+    t.tree_off = np.array([0, 5]); t.parent = np.array([-1, 0, 1, 2, 3]); t.seg = np.array([-1, 0, 0, 0, 0])
+    g = Topo()
+    g.res_len = np.array([8 * UM])
+    mat = material()
+    ss = np.array([5.0, 3.0, 0.0, -3.0, -5.0]) * 1e7     # sigma_T = 0: neutral node 2
+    F = SO.features(t, g, mat, np.array([1e10]), np.ones(1), np.full(5, 350.0), ss, np.full(5, 4e7))
+    k = SO.kappa0(350.0, mat)
+    assert abs(F[0, 8] - 1.25) < 1e-12
+    assert abs(F[0, 10] - (math.log10((4 * UM) ** 2 / (math.pi ** 2 * k)) - 8)) < 1e-12
+    assert abs(F[0, 11] - 0.5) < 1e-12
 
 
 def test_features_branched_tree_hand_measures(oracle_mod):
