@@ -51,6 +51,80 @@ def measured_traffic(kernel_src: str, profile_md: str):
         return None
 
 
+def surrogate_leg(args):
+    """Learned screen: labels from the library's own transient runs on random
+    sparse-via grids, training with the BF16 MFMA kernels, then the screened
+    and the unscreened Monte Carlo run of the screen_mc workload."""
+    import numpy as np
+    import torch
+    import paper_2604_10743_amd as P
+    from paper_2604_10743_amd import surrogate, synth
+
+    g, mat, run, mc = synth.workload("screen_mc")
+    mc = dict(mc, n_samples=args.sur_samples)
+    horizon = 4 * run["n_steps"]                  # labels up to 40 years
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, y, infos = surrogate.training_set(11, args.sur_grids, mat, run, args.sur_label_samples, horizon,
+                                         log=log)
+    torch.cuda.synchronize()
+    t_label = time.perf_counter() - t0
+    Xv, yv, _ = surrogate.training_set(12, 2, mat, run, args.sur_label_samples, horizon)
+    model = P.MLP(synth.init_mlp_params(1, out_bias=float(y.mean().item())))
+    n = int(X.shape[0])
+    batch = min(4096, max(256, n // 16))
+    steps = args.sur_steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    surrogate.train(model, X, y, steps, batch=batch, lr=1e-3, lr_final=1e-4)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    flop_step = 3 * 2 * batch * (16 * 256 + 2 * 256 * 256)      # hidden-layer GEMMs, fwd + 2x bwd
+    train_loss = model.grad(X, y)[0]
+    val_loss = model.grad(Xv, yv)[0]
+    ratio = 10.0 ** (model.forward(Xv).cpu().numpy() - yv.cpu().numpy())
+    log(f"bench: surrogate trained on {n} pairs: loss {train_loss:.4f}, held-out {val_loss:.4f}")
+
+    def mc_run(with_model):
+        B = P.Batch(g, mat, run, mc)
+        if with_model:
+            B.surrogate_screen(model, 2.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = B.run_to_ttf()
+        torch.cuda.synchronize()
+        w = time.perf_counter() - t0
+        inf = B.info()
+        B.close()
+        return res, inf, w
+
+    r0, i0, w0 = mc_run(False)
+    r1, i1, w1 = mc_run(True)
+    same = all((a["failed"] == b["failed"]) and (a["outer_idx"] == b["outer_idx"]) and
+               (np.isnan(a["ttf_s"]) and np.isnan(b["ttf_s"]) or a["ttf_s"] == b["ttf_s"]) and
+               a["final_drop"] == b["final_drop"] and a["n_failed_segs"] == b["n_failed_segs"]
+               for a, b in zip(r0, r1))
+    ttf = np.array([r["ttf_s"] for r in r1 if r["failed"]])
+    S = mc["n_samples"]
+    return {"metric": "MC samples/s to TTF, learned screen on", "value": S / w1, "unit": "samples/s",
+            "workload": f"screen_mc: 200x200 sparse-via grid (via every 64 nodes), 330 K + 6 hotspots, "
+                        f"{S} samples, 20% CoV on kappa and sigma_crit, FP32, margin 2",
+            "unscreened_samples_per_s": S / w0, "speedup": w0 / w1,
+            "node_steps": i1["node_steps"], "node_steps_unscreened": i0["node_steps"],
+            "n_deferred": i1["n_deferred"], "n_activated": i1["n_activated"],
+            "n_late": i1["n_late"], "n_violations": i1["n_violations"], "results_identical": bool(same),
+            "ir_ms": i1["ir_ms"], "ir_ms_unscreened": i0["ir_ms"], "step_kernel_ms": i1["step_kernel_ms"],
+            "step_kernel_ms_unscreened": i0["step_kernel_ms"],
+            "n_fail": int(ttf.size), "ttf_mean_y": float(ttf.mean() / 3.15576e7) if ttf.size else None,
+            "surrogate_ms": i1["surrogate_ms"],
+            "training": {"pairs": n, "label_grids": args.sur_grids, "label_samples": args.sur_label_samples,
+                         "label_s": t_label, "batch": batch, "steps": steps, "train_s": t_train,
+                         "mfma_tflops": flop_step * steps / t_train / 1e12,
+                         "mfma_frac_of_bf16_peak": flop_step * steps / t_train / 2.5e15,
+                         "loss": train_loss, "heldout_loss": val_loss,
+                         "heldout_ratio_pct_0.1_1_50_99": np.percentile(ratio, [0.1, 1, 50, 99]).tolist()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +135,11 @@ def main():
     ap.add_argument("--no-mc", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--mc-samples", type=int, default=1024)
+    ap.add_argument("--no-sur", action="store_true", help="skip the learned-screen leg")
+    ap.add_argument("--sur-grids", type=int, default=24, help="label grids for the learned screen")
+    ap.add_argument("--sur-label-samples", type=int, default=128)
+    ap.add_argument("--sur-steps", type=int, default=3000, help="Adam steps of the screen model")
+    ap.add_argument("--sur-samples", type=int, default=256, help="MC samples of the screened run")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only copy this many bytes device-to-device (a plain copy kernel of known "
                          "size, to scale the FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -169,6 +248,10 @@ def main():
                      "node_steps": im["node_steps"]}
         Bm.close()
         log("bench: mc done")
+
+    if not args.no_sur:
+        out["surrogate"] = surrogate_leg(args)
+        log("bench: surrogate done")
 
     if not args.no_plain:
         # the plain FP64 GPU FDTD form (generic tree kernel, FP64) on one aging

@@ -37,6 +37,7 @@ extern "C" {
 #endif
 
 typedef struct em_batch em_batch;   /* opaque, library-owned */
+typedef struct em_mlp em_mlp;       /* opaque learned-screen model, library-owned */
 
 typedef enum {
     EM_OK = 0,
@@ -151,6 +152,14 @@ typedef struct {
     double step_kernel_ms; /* summed stream time of those launches (HIP events around each) */
     int64_t cg_iters_total;/* PCG iterations over all IR solves */
     double ir_ms;          /* summed stream time of the IR solves (HIP events) */
+    int64_t n_deferred;    /* learned screen: instances deferred at t = 0 */
+    int64_t n_activated;   /* learned screen: deferred instances activated (and caught up) later */
+    int64_t n_late;        /* learned screen: activated instances that had nucleated before
+                              the interval they were activated for */
+    int64_t n_violations;  /* learned screen: late activations whose void had also reached the
+                              growth phase (a resistance change that earlier IR solves missed);
+                              with none, results equal those of the unscreened run */
+    double surrogate_ms;   /* wall time of the learned-screen evaluations (features + model) */
 } em_info;
 
 /* Allocator hook: device memory for the batch (e.g. a framework's caching
@@ -235,6 +244,76 @@ em_status em_get_screen(em_batch *b, int32_t sample, uint8_t *tree_mortal, uint8
 em_status em_inject_void(em_batch *b, int32_t sample, int32_t tree, int32_t node);
 /* Per-(sample, segment) Monte Carlo multipliers, xi [n_res]; param 0 kappa, 1 sigma_crit. */
 em_status em_get_xi(em_batch *b, int32_t sample, int32_t param, double *xi);
+
+/* ---- learned screen ----
+ * A small model, not part of EMSpice 3, that sits in front of the transient
+ * stage: from 12 features of a (tree, sample) it predicts the nucleation time
+ * of the steady-state-mortal trees, so trees predicted to nucleate long after
+ * the current aging interval need not be stepped yet.  Feature vector
+ * (float32, in this order): log10 total wire length/1um; log10 longest
+ * root-to-node distance/1um; segments/8; junctions (degree >= 3)/4;
+ * log10 max|j|/1e9 A/m^2; log10 length-weighted mean |j|/1e9 (both |j|
+ * floored at 1e3); log10 mean diffusivity/1e-15 m^2/s (the Arrhenius kappa
+ * of Sec. III-D at edge-midpoint temperature, times the Monte Carlo
+ * multiplier); log10 mean diffusivity of the edges at the peak node p/1e-15;
+ * r = peak over nodes of the zero-flux steady stress of the screen
+ * (Sec. II-B) / node critical stress, clamped to [-10, 10] (p = first node of
+ * the largest ratio); log10 max(r - 1, 1e-6); log10(Lpk^2 / (pi^2 kappa_pk)
+ * / 1 s) - 8 with Lpk the difference of root distances from p to the nearest
+ * node whose steady stress is at or below sigma_T (floored at 0.1 um);
+ * (temperature at p - 300 K)/100.
+ * Model: 12 -> 256 -> 256 -> 256 -> 1 perceptron with exact (erf) GELU,
+ * output y = log10(t_nuc / 1e8 s).  Hidden-layer products run on bfloat16
+ * matrix cores with float32 accumulation (operands rounded to nearest even);
+ * bias, GELU, output layer, loss and Adam are float32, with a float32 master
+ * copy of every parameter.  Parameter vector (float32, em_mlp_num_params()):
+ * W1 [256][12], b1 [256], W2 [256][256], b2, W3 [256][256], b3, w4 [256], b4
+ * ([out][in] row-major).  X, t, y arguments of the em_mlp_* calls are DEVICE
+ * pointers (X [n][12] row-major); calls on one model must not overlap. */
+em_status em_mlp_create(void *hip_stream, em_mlp **out);   /* parameters start at zero */
+em_status em_mlp_destroy(em_mlp *m);
+const char *em_mlp_last_error(const em_mlp *m);
+int32_t em_mlp_num_params(void);
+/* Host float32 copies of the parameters; set also clears the Adam moments. */
+em_status em_mlp_set_params(em_mlp *m, const float *params, int32_t n);
+em_status em_mlp_get_params(em_mlp *m, float *params, int32_t n);
+/* y [n] (device) = model(X). */
+em_status em_mlp_forward(em_mlp *m, const float *X, int32_t n, float *y);
+/* Mean squared error (1/n) sum (y - t)^2 of the model on (X, t) and its
+ * gradient; grad [em_mlp_num_params()] host, loss host; either may be NULL. */
+em_status em_mlp_grad(em_mlp *m, const float *X, const float *t, int32_t n, float *grad, float *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+ * mean squared error of the minibatch (X, t).  loss: host, may be NULL (then
+ * the call does not synchronise). */
+em_status em_mlp_train_step(em_mlp *m, const float *X, const float *t, int32_t n, float lr, float *loss);
+
+/* Features of every (tree, sample) for the current densities, written to X
+ * (DEVICE, [n_trees * n_samples][12], row tree * n_samples + sample).
+ * Refreshes the screen verdict (em_get_screen) without changing which trees
+ * are stepped.  EM_ERR_STATE before any currents exist. */
+em_status em_features(em_batch *b, float *X);
+/* Attach a learned screen with safety margin m >= 1 (mlp NULL detaches it;
+ * the model must outlive its use by the batch).  em_run_to_ttf then, at
+ * t = 0, defers every steady-state-mortal tree whose predicted nucleation
+ * time exceeds m x (end of the first aging interval); before the aging
+ * interval ending at t_{k+1} it activates every deferred tree with prediction
+ * <= m x t_{k+1} and catches it up from t = 0 by replaying the stored current
+ * densities of the earlier intervals.  Before each activation check the
+ * deferred trees are re-evaluated with the current densities (a prediction
+ * can only move earlier).  The replay reproduces the unscreened run exactly
+ * unless an activated tree's void had already reached the growth phase
+ * before its activation (counted in em_info.n_violations; nucleation alone
+ * before activation is counted in n_late).  Called on a batch that has currents
+ * and has not been stepped since creation or reset, it also evaluates the
+ * model at once, so that em_stress_step skips the deferred trees;
+ * *n_deferred (may be NULL) is then their number, else 0. */
+em_status em_surrogate_screen(em_batch *b, em_mlp *mlp, double margin, int64_t *n_deferred);
+/* Model output y (log10 of the predicted nucleation time / 1e8 s) and the
+ * deferred flags of one sample: [n_trees] host each, either may be NULL. */
+em_status em_get_surrogate(em_batch *b, int32_t sample, float *y_hat, uint8_t *deferred);
+/* Step of the first nucleation of every (sample, tree), -1 if none:
+ * [n_samples][n_trees] host.  The nucleation time is (step + 1) x dt. */
+em_status em_first_nucleation(em_batch *b, int32_t *step);
 
 #ifdef __cplusplus
 }

@@ -3,6 +3,6 @@
 The work runs in libem.so (HIP kernels for gfx950, C ABI in include/em.h);
 ``Batch`` is its ctypes binding and ``synth`` builds seeded synthetic grids.
 """
-from ._binding import API, Batch, EmError, lib  # noqa: F401
+from ._binding import API, MLP, Batch, EmError, lib  # noqa: F401
 
-__all__ = ["Batch", "EmError", "lib", "API"]
+__all__ = ["Batch", "MLP", "EmError", "lib", "API"]

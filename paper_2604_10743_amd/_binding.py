@@ -7,8 +7,10 @@ has not been built; there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -24,7 +26,10 @@ API = ["em_batch_create", "em_batch_destroy", "em_get_info", "em_last_error", "e
        "em_screen", "em_stress_step", "em_run_to_ttf", "em_get_topology", "em_get_stress",
        "em_set_stress", "em_get_voltages", "em_get_seg_j", "em_get_seg_state", "em_get_node_state",
        "em_get_events", "em_get_voids", "em_get_screen", "em_inject_void", "em_get_xi",
-       "em_reset"]
+       "em_reset", "em_mlp_create", "em_mlp_destroy", "em_mlp_last_error", "em_mlp_num_params",
+       "em_mlp_set_params", "em_mlp_get_params", "em_mlp_forward", "em_mlp_grad",
+       "em_mlp_train_step", "em_features", "em_surrogate_screen", "em_get_surrogate",
+       "em_first_nucleation"]
 
 
 class EmError(RuntimeError):
@@ -76,7 +81,10 @@ class Info(C.Structure):
                 ("prec", C.c_int32), ("trees_only", C.c_int32), ("n_events", C.c_int64),
                 ("cg_iters_last", C.c_int32), ("n_outer_done", C.c_int32),
                 ("node_steps", C.c_int64), ("step_launches", C.c_int64),
-                ("step_kernel_ms", C.c_double), ("cg_iters_total", C.c_int64), ("ir_ms", C.c_double)]
+                ("step_kernel_ms", C.c_double), ("cg_iters_total", C.c_int64), ("ir_ms", C.c_double),
+                ("n_deferred", C.c_int64), ("n_activated", C.c_int64), ("n_late", C.c_int64),
+                ("n_violations", C.c_int64),
+                ("surrogate_ms", C.c_double)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -88,6 +96,18 @@ class Allocator(C.Structure):
 
 
 _lib = None
+_live = weakref.WeakSet()        # batches and models still open
+
+
+@atexit.register
+def _close_all():
+    """Release library objects before the interpreter tears down the modules
+    their allocator callbacks use."""
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 def lib():
@@ -98,11 +118,14 @@ def lib():
             raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
                               "(or python -m paper_2604_10743_amd.build) first")
         L = C.CDLL(LIB_PATH)
-        L.em_last_error.restype = C.c_char_p
-        L.em_last_error.argtypes = [C.c_void_p]
         for name in API:
-            if name != "em_last_error":
-                getattr(L, name).restype = C.c_int
+            getattr(L, name).restype = C.c_int
+        for name in ("em_last_error", "em_mlp_last_error"):
+            getattr(L, name).restype = C.c_char_p
+            getattr(L, name).argtypes = [C.c_void_p]
+        L.em_mlp_train_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
+                                        C.c_void_p]
+        L.em_surrogate_screen.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
         _lib = L
     return _lib
 
@@ -197,6 +220,7 @@ class Batch:
             L.em_batch_destroy(self._h)
             self._h = None
             raise EmError(rc, msg)
+        _live.add(self)
         self.grid = grid
         self.S = int(mc["n_samples"]) if mc else 1
         inf = self.info()
@@ -318,3 +342,103 @@ class Batch:
         x = np.zeros(self.n_res)
         self._chk(lib().em_get_xi(self._h, C.c_int32(sample), C.c_int32(param), _ptr(x)))
         return x
+
+    # -- learned screen ------------------------------------------------------
+    def features(self):
+        """[n_trees * n_samples][12] float32 device tensor (row tree * S + sample)."""
+        X = self._torch.empty((self.n_trees * self.S, 12), dtype=self._torch.float32, device="cuda")
+        self._chk(lib().em_features(self._h, C.c_void_p(X.data_ptr())))
+        return X
+
+    def surrogate_screen(self, mlp, margin: float = 2.0) -> int:
+        nd = C.c_int64()
+        self._chk(lib().em_surrogate_screen(self._h, mlp._h if mlp is not None else None,
+                                            C.c_double(margin), C.byref(nd)))
+        self._mlp_ref = mlp
+        return nd.value
+
+    def surrogate(self, sample: int = 0):
+        y = np.zeros(self.n_trees, np.float32)
+        df = np.zeros(self.n_trees, np.uint8)
+        self._chk(lib().em_get_surrogate(self._h, C.c_int32(sample), _ptr(y), _ptr(df)))
+        return y, df
+
+    def first_nucleation(self) -> np.ndarray:
+        out = np.zeros((self.S, self.n_trees), np.int32)
+        self._chk(lib().em_first_nucleation(self._h, _ptr(out)))
+        return out
+
+
+class MLP:
+    """The learned-screen model (parameters, Adam state, activations on the GPU)."""
+
+    def __init__(self, params=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the EM library runs only on the device")
+        self._torch = torch
+        L = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self._h = C.c_void_p()
+        rc = L.em_mlp_create(C.c_void_p(stream), C.byref(self._h))
+        if rc != EM_OK:
+            L.em_mlp_destroy(self._h)
+            self._h = None
+            raise EmError(rc, "em_mlp_create failed")
+        _live.add(self)
+        self.n_params = L.em_mlp_num_params()
+        if params is not None:
+            self.set_params(params)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().em_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        if rc != EM_OK:
+            raise EmError(rc, lib().em_mlp_last_error(self._h).decode())
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, np.float32)
+        self._chk(lib().em_mlp_set_params(self._h, _ptr(a), C.c_int32(a.size)))
+
+    def params(self) -> np.ndarray:
+        a = np.zeros(self.n_params, np.float32)
+        self._chk(lib().em_mlp_get_params(self._h, _ptr(a), C.c_int32(a.size)))
+        return a
+
+    def _dev(self, x):
+        t = self._torch.as_tensor(x, dtype=self._torch.float32, device="cuda").contiguous()
+        return t
+
+    def forward(self, X):
+        X = self._dev(X)
+        n = X.shape[0]
+        y = self._torch.empty(n, dtype=self._torch.float32, device="cuda")
+        self._chk(lib().em_mlp_forward(self._h, C.c_void_p(X.data_ptr()), C.c_int32(n),
+                                       C.c_void_p(y.data_ptr())))
+        return y
+
+    def grad(self, X, t):
+        X, t = self._dev(X), self._dev(t)
+        g = np.zeros(self.n_params, np.float32)
+        loss = C.c_float()
+        self._chk(lib().em_mlp_grad(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(t.data_ptr()),
+                                    C.c_int32(X.shape[0]), _ptr(g), C.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, X, t, lr: float, want_loss: bool = False):
+        """One Adam step on device tensors X [n][12], t [n]."""
+        loss = C.c_float()
+        self._chk(lib().em_mlp_train_step(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(t.data_ptr()),
+                                          C.c_int32(X.shape[0]), C.c_float(lr),
+                                          C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None

@@ -8,6 +8,7 @@
 #include "../../include/em.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -53,6 +54,15 @@ struct em_batch {
     long long step_launches = 0, cg_iters_total = 0;
     uint8_t *h_flags = nullptr;   // pinned scratch for small read-backs
     size_t h_flags_cap = 0;
+    // learned screen (model borrowed from the caller)
+    em_mlp *sur = nullptr;
+    double sur_margin = 2.0;
+    bool sur_ready = false;       // its device buffers exist
+    float *sur_y = nullptr;       // [inst] model output of the last evaluation
+    double *jhist = nullptr;      // [n_hist][S][n_res] current densities of each aging interval
+    int n_hist = 0;
+    double sur_ms = 0.0;
+    int n_def_list = 0;           // length of d.def_list from the t = 0 evaluation
 };
 
 namespace {
@@ -349,12 +359,14 @@ void fold_timers(em_batch *b)
     b->ir_pending = false;
 }
 
-em_status timed_step(em_batch *b, int n_steps, int step0)
+// Step the instances that `dd.inst_active` marks (the batch's own set, or the
+// catch-up set of the learned screen with dd a modified copy of the batch's Dev).
+em_status timed_step_dev(em_batch *b, const Dev &dd, int n_steps, int step0)
 {
     fold_timers(b);
     HIPCHK(b, hipEventRecord(b->ev_a, b->stream));
-    if (b->d.n_chain_wg > 0) launch_chain(b->d, b->d_dev, b->fp32, n_steps, step0, b->stream);
-    if (b->n_generic_trees > 0) launch_step(b->d, b->fp32, n_steps, step0, b->stream);
+    if (dd.n_chain_wg > 0) launch_chain(dd, b->d_dev, b->fp32, n_steps, step0, b->stream);
+    if (b->n_generic_trees > 0) launch_step(dd, b->fp32, n_steps, step0, b->stream);
     LAUNCHCHK(b);
     HIPCHK(b, hipEventRecord(b->ev_b, b->stream));
     b->step_pending = true;
@@ -364,6 +376,8 @@ em_status timed_step(em_batch *b, int n_steps, int step0)
     return EM_OK;
 }
 
+em_status timed_step(em_batch *b, int n_steps, int step0) { return timed_step_dev(b, b->d, n_steps, step0); }
+
 em_status timed_ir(em_batch *b)
 {
     HIPCHK(b, hipEventRecord(b->ev_c, b->stream));
@@ -372,6 +386,85 @@ em_status timed_ir(em_batch *b)
     HIPCHK(b, hipEventRecord(b->ev_d, b->stream));
     b->ir_pending = true;
     b->cg_iters_total += b->cg_iters_last;
+    return EM_OK;
+}
+
+// Device buffers of the learned screen and the per-tree static features.
+em_status sur_buffers(em_batch *b)
+{
+    if (b->sur_ready) return EM_OK;
+    Dev &d = b->d;
+    const size_t IS = (size_t)d.n_trees * d.S;
+    d.tstat = (double *)dalloc(b, 4 * 8 * (size_t)d.n_trees);
+    d.rdist = (double *)dalloc(b, 8 * (size_t)d.ns);
+    d.feat = (float *)dalloc(b, 4 * IS * NFEAT);
+    d.yhat = (float *)dalloc(b, 4 * IS);
+    d.deferred = (uint8_t *)dalloc(b, IS);
+    d.catchup = (uint8_t *)dalloc(b, IS);
+    d.def_list = (int *)dalloc(b, 4 * IS);
+    d.sur_cnt = (unsigned int *)dalloc(b, 32);
+    b->sur_y = (float *)dalloc(b, 4 * IS);
+    if (!d.tstat || !d.rdist || !d.feat || !d.yhat || !d.deferred || !d.catchup || !d.def_list ||
+        !d.sur_cnt || !b->sur_y)
+        return fail(b, EM_ERR_OOM, "learned-screen buffers");
+    launch_tree_static(d, b->stream);
+    LAUNCHCHK(b);
+    HIPCHK(b, hipMemcpyAsync(b->d_dev, &d, sizeof(Dev), hipMemcpyHostToDevice, b->stream));
+    b->sur_ready = true;
+    return EM_OK;
+}
+
+// Features of every (tree, sample) with the current densities: the screen's
+// steady stress is refreshed first (without changing the active set).
+em_status features_impl(em_batch *b, float *X)
+{
+    launch_screen(b->d, false, b->stream);
+    launch_features(b->d, X, b->stream);
+    LAUNCHCHK(b);
+    return EM_OK;
+}
+
+// Evaluate the attached model and defer the mortal active instances predicted
+// to nucleate after thr; returns how many were deferred (synchronises).
+em_status sur_evaluate(em_batch *b, double thr, int64_t *n_def)
+{
+    Dev &d = b->d;
+    auto t0 = std::chrono::steady_clock::now();
+    em_status rc = features_impl(b, d.feat);
+    if (rc != EM_OK) return rc;
+    int irc = mlp_forward_async(b->sur, d.feat, d.n_trees * d.S, b->sur_y, b->stream);
+    if (irc != EM_OK) return fail(b, (em_status)irc, "learned-screen model evaluation failed");
+    HIPCHK(b, hipMemsetAsync(d.sur_cnt, 0, 32, b->stream));
+    launch_defer(d, b->sur_y, thr, b->stream);
+    LAUNCHCHK(b);
+    unsigned int *h = (unsigned int *)pinned(b, 32);
+    if (!h) return fail(b, EM_ERR_OOM, "pinned host buffer");
+    HIPCHK(b, hipMemcpyAsync(h, d.sur_cnt, 32, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    if (n_def) *n_def = h[0];
+    b->n_def_list = (int)h[4];
+    b->sur_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return EM_OK;
+}
+
+// Replay the stored aging intervals 0..k-1 for the instances just activated
+// (catch-up from t = 0), then return them to the active set.
+em_status sur_catch_up(em_batch *b, int k)
+{
+    Dev &d = b->d;
+    const int K = b->run.ir_every;
+    Dev dr = d;
+    dr.inst_active = d.catchup;
+    for (int i = 0; i < k; ++i) {
+        dr.jseg = b->jhist + (size_t)i * d.S * d.n_res;
+        launch_update_f(dr, b->fp32, b->stream);
+        LAUNCHCHK(b);
+        em_status rc = timed_step_dev(b, dr, K, i * K);
+        if (rc != EM_OK) return rc;
+    }
+    launch_update_f(d, b->fp32, b->stream);
+    launch_catchup_done(d, k * K, b->stream);
+    LAUNCHCHK(b);
     return EM_OK;
 }
 
@@ -650,6 +743,16 @@ em_status em_get_info(em_batch *b, em_info *info)
     info->step_kernel_ms = b->step_ms;
     info->cg_iters_total = b->cg_iters_total;
     info->ir_ms = b->ir_ms;
+    unsigned int sc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (b->sur_ready) {
+        HIPCHK(b, hipMemcpyAsync(sc, b->d.sur_cnt, 32, hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(b, hipStreamSynchronize(b->stream));
+    }
+    info->n_deferred = sc[0];
+    info->n_activated = sc[1];
+    info->n_late = sc[2];
+    info->n_violations = sc[3];
+    info->surrogate_ms = b->sur_ms;
     return EM_OK;
 }
 
@@ -719,16 +822,61 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
     launch_ttf_init(d, fail_frac, st);
     if (b->run.screen) launch_screen(d, true, st);
     LAUNCHCHK(b);
-    uint8_t *h = pinned(b, std::max<size_t>(S, 8));
-    if (!h) return fail(b, EM_ERR_OOM, "pinned host buffer");
     const int n_steps = b->run.n_steps, K = b->run.ir_every;
+    const bool sur = b->sur != nullptr;
+    if (sur) {
+        // learned screen at t = 0; the current densities of every aging
+        // interval are kept for the catch-up replay of later activations
+        rc = sur_buffers(b);
+        if (rc != EM_OK) return rc;
+        const int n_hist = (n_steps + K - 1) / K;
+        if (!b->jhist || b->n_hist < n_hist) {
+            b->jhist = (double *)dalloc(b, 8 * (size_t)n_hist * S * b->n_res);
+            if (!b->jhist) return fail(b, EM_ERR_OOM, "current-density history");
+            b->n_hist = n_hist;
+        }
+        HIPCHK(b, hipMemsetAsync(d.deferred, 0, (size_t)b->n_trees * S, st));
+        rc = sur_evaluate(b, b->sur_margin * std::min(K, n_steps) * b->run.dt, nullptr);
+        if (rc != EM_OK) return rc;
+    }
+    const size_t cnt_off = (std::max<size_t>(S, 8) + 15) & ~(size_t)15;
+    uint8_t *h = pinned(b, cnt_off + 32);
+    if (!h) return fail(b, EM_ERR_OOM, "pinned host buffer");
+    unsigned int *hcnt = (unsigned int *)(h + cnt_off);
+    unsigned int n_activated = 0;
     int done = 0, k = 0;
     while (done < n_steps) {
+        if (sur) {
+            HIPCHK(b, hipMemcpyAsync(b->jhist + (size_t)k * S * b->n_res, d.jseg, 8 * (size_t)S * b->n_res,
+                                     hipMemcpyDeviceToDevice, st));
+            if (k > 0) {
+                // predictions of the deferred trees with the current densities
+                // (only ever brought forward), then activation of those due
+                const int nl = b->n_def_list;
+                if (nl > 0) {
+                    launch_reeval_features(d, nl, d.feat, st);
+                    LAUNCHCHK(b);
+                    int irc = mlp_forward_async(b->sur, d.feat, nl, b->sur_y, st);
+                    if (irc != EM_OK) return fail(b, (em_status)irc, "learned-screen model evaluation failed");
+                    launch_yhat_min(d, nl, b->sur_y, st);
+                }
+                launch_activate(d, b->sur_margin * std::min(done + K, n_steps) * b->run.dt, st);
+                LAUNCHCHK(b);
+            }
+            HIPCHK(b, hipMemcpyAsync(hcnt, d.sur_cnt, 32, hipMemcpyDeviceToHost, st));
+        }
         HIPCHK(b, hipMemcpyAsync(h, d.sample_active, S, hipMemcpyDeviceToHost, st));
         HIPCHK(b, hipStreamSynchronize(st));
         int n_active = 0;
         for (int s = 0; s < S; ++s) n_active += h[s] != 0;
         if (n_active == 0) break;
+        if (sur && hcnt[1] != n_activated) {
+            n_activated = hcnt[1];
+            rc = sur_catch_up(b, k);
+            if (rc != EM_OK) return rc;
+            rc = sync_open_dirty(b);
+            if (rc != EM_OK) return rc;
+        }
         int nst = std::min(K, n_steps - done);
         rc = timed_step(b, nst, done);
         if (rc != EM_OK) return rc;
@@ -790,11 +938,18 @@ em_status em_reset(em_batch *b)
     HIPCHK(b, hipMemsetAsync(d.ev_count, 0, 4, st));
     HIPCHK(b, hipMemsetAsync(d.node_steps, 0, 8, st));
     HIPCHK(b, hipMemsetAsync(d.open_dirty, 0, 4, st));
+    if (b->sur_ready) {
+        HIPCHK(b, hipMemsetAsync(d.deferred, 0, IS, st));
+        HIPCHK(b, hipMemsetAsync(d.catchup, 0, IS, st));
+        HIPCHK(b, hipMemsetAsync(d.sur_cnt, 0, 32, st));
+    }
+    b->n_def_list = 0;
     launch_fill_f64(d.u, VS, d.vdd, st);
     launch_set_sigma_T(d, b->fp32, st);
     launch_factor(d, b->fp32, st);
     LAUNCHCHK(b);
     HIPCHK(b, hipStreamSynchronize(st));
+    b->sur_ms = 0.0;
     b->live_dirty = true;
     b->have_j = b->trees_only;
     b->step_counter = 0;
@@ -979,6 +1134,69 @@ em_status em_get_xi(em_batch *b, int32_t sample, int32_t param, double *xi)
                              hipMemcpyDeviceToHost, b->stream));
     HIPCHK(b, hipStreamSynchronize(b->stream));
     for (int e = 0; e < b->n_res; ++e) xi[e] = tmp[(size_t)e * S + sample];
+    return EM_OK;
+}
+
+em_status em_features(em_batch *b, float *X)
+{
+    if (!b || !X) return fail(b, EM_ERR_ARG, "null feature buffer");
+    if (!b->have_j) return fail(b, EM_ERR_STATE, "no current densities yet (call em_ir_solve first)");
+    em_status rc = sur_buffers(b);
+    if (rc != EM_OK) return rc;
+    rc = features_impl(b, X);
+    if (rc != EM_OK) return rc;
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    return EM_OK;
+}
+
+em_status em_surrogate_screen(em_batch *b, em_mlp *mlp, double margin, int64_t *n_deferred)
+{
+    if (!b) return EM_ERR_ARG;
+    if (n_deferred) *n_deferred = 0;
+    if (mlp && !(margin >= 1.0 && std::isfinite(margin))) return fail(b, EM_ERR_ARG, "margin must be finite and >= 1");
+    b->sur = mlp;
+    b->sur_margin = margin;
+    if (!mlp) return EM_OK;
+    em_status rc = sur_buffers(b);
+    if (rc != EM_OK) return rc;
+    if (b->have_j && b->step_counter == 0 && b->n_outer_done == 0) {
+        const int K = std::min(b->run.ir_every, b->run.n_steps);
+        rc = sur_evaluate(b, margin * K * b->run.dt, n_deferred);
+        if (rc != EM_OK) return rc;
+    }
+    return EM_OK;
+}
+
+em_status em_get_surrogate(em_batch *b, int32_t sample, float *y_hat, uint8_t *deferred)
+{
+    if (!b || sample < 0 || sample >= b->S) return fail(b, EM_ERR_ARG, "bad sample");
+    if (!b->sur_ready) return fail(b, EM_ERR_STATE, "no learned screen has been evaluated on this batch");
+    const size_t IS = (size_t)b->n_trees * b->S;
+    std::vector<float> y(IS);
+    std::vector<uint8_t> df(IS);
+    HIPCHK(b, hipMemcpyAsync(y.data(), b->d.yhat, 4 * IS, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipMemcpyAsync(df.data(), b->d.deferred, IS, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    for (int t = 0; t < b->n_trees; ++t) {
+        if (y_hat) y_hat[t] = y[(size_t)t * b->S + sample];
+        if (deferred) deferred[t] = df[(size_t)t * b->S + sample];
+    }
+    return EM_OK;
+}
+
+em_status em_first_nucleation(em_batch *b, int32_t *step)
+{
+    if (!b || !step) return fail(b, EM_ERR_ARG, "null output");
+    const size_t IS = (size_t)b->n_trees * b->S;
+    std::vector<int> nv(IS), vs(IS * MAXV);
+    HIPCHK(b, hipMemcpyAsync(nv.data(), b->d.nv, 4 * IS, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipMemcpyAsync(vs.data(), b->d.vstep, 4 * IS * MAXV, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    for (int t = 0; t < b->n_trees; ++t)
+        for (int s = 0; s < b->S; ++s) {
+            size_t inst = (size_t)t * b->S + s;
+            step[(size_t)s * b->n_trees + t] = nv[inst] > 0 ? vs[inst * MAXV] : -1;
+        }
     return EM_OK;
 }
 

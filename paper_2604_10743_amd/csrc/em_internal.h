@@ -100,7 +100,18 @@ struct Dev {
     // ---- TTF ----
     double *ttf, *final_drop, *init_drop, *t_prev, *d_prev;
     int *failed, *outer_idx;
+    // ---- learned screen (allocated when a model is attached) ----
+    double *tstat;                      // [n_trees][4] Ltot, Lpath, nseg, njunc
+    double *rdist;                      // [ns] distance from the tree root along the tree
+    float *feat;                        // [inst][NFEAT]
+    float *yhat;                        // [inst] predicted log10(t_nuc / T_REF)
+    uint8_t *deferred, *catchup;        // [inst]
+    int *def_list;                      // [inst] instances deferred at t = 0 (in no particular order)
+    unsigned int *sur_cnt;              // [8] deferred, activated, late, violations, list length
 };
+
+constexpr int NFEAT = 12;               // learned-screen features per (tree, sample)
+constexpr double T_REF = 1e8;           // s; the model predicts log10(t_nuc / T_REF)
 
 // ---- launchers (defined in the kernel translation units) ----
 void launch_node_T(const Dev &d, hipStream_t st);
@@ -135,4 +146,20 @@ void launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
 void launch_ttf_init(const Dev &d, double fail, hipStream_t st);
 void launch_ttf_update(const Dev &d, double fail, int k, double t, hipStream_t st);
 
+// learned screen
+void launch_tree_static(const Dev &d, hipStream_t st);                 // tstat, rdist
+void launch_features(const Dev &d, float *X, hipStream_t st);          // needs the screen's psi
+void launch_reeval_features(const Dev &d, int n, float *X, hipStream_t st);   // def_list[0..n)
+void launch_yhat_min(const Dev &d, int n, const float *y, hipStream_t st);
+void launch_defer(const Dev &d, const float *y, double thr, hipStream_t st);
+void launch_activate(const Dev &d, double thr, hipStream_t st);
+void launch_catchup_done(const Dev &d, int step_lim, hipStream_t st);
+
 }  // namespace em
+
+// MLP forward on a caller's stream (X, y device; rows n); defined with the
+// model in em_mlp.hip.
+struct em_mlp;
+namespace em {
+int mlp_forward_async(em_mlp *m, const float *X, int n, float *y, hipStream_t st);
+}

@@ -110,6 +110,7 @@ __global__ __launch_bounds__(WG) void k_chain(ChainHot h)
         hi = lo + (nT + M - 1) / M - 1;
         act = h.sample_active[s] && h.inst_active[inst];
     }
+    if (!__syncthreads_or(act ? 1 : 0)) return;   // nothing to step in this workgroup
     const bool first = act && kb == 0;
     const bool last = act && (kb * M + cnt == nT);
     if (!act) cnt = 0;

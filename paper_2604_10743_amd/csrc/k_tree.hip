@@ -288,12 +288,8 @@ EM_KERNEL void k_factor(Dev d)
 // A node is mortal iff its finite sigma_ss exceeds its critical stress;
 // segments through a mortal node and its tree are flagged.
 // ------------------------------------------------------------------------
-EM_KERNEL void k_screen(Dev d, int apply)
+__device__ void steady_stress(const Dev &d, int t, int s)
 {
-    int slot = blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= d.n_trees * d.S) return;
-    int t, s;
-    int inst = inst_of_slot(d, slot, t, s);
     const int S = d.S;
     int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
     double *psi = d.psi;
@@ -310,12 +306,23 @@ EM_KERNEL void k_screen(Dev d, int apply)
         den += d.V[i];
     }
     double mean = num / den;
+    for (int i = i0; i < i1; ++i) psi[(size_t)i * S + s] = d.sigT + psi[(size_t)i * S + s] - mean;
+}
+
+EM_KERNEL void k_screen(Dev d, int apply)
+{
+    int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= d.n_trees * d.S) return;
+    int t, s;
+    int inst = inst_of_slot(d, slot, t, s);
+    const int S = d.S;
+    steady_stress(d, t, s);
+    int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
     int mortal = 0;
     uint8_t *sm = d.seg_mortal + (size_t)s * d.n_res;
     for (int k = d.tseg_off[t]; k < d.tseg_off[t + 1]; ++k) sm[d.tseg[k]] = 0;
     for (int i = i0; i < i1; ++i) {
-        double v = d.sigT + psi[(size_t)i * S + s] - mean;
-        psi[(size_t)i * S + s] = v;
+        double v = d.psi[(size_t)i * S + s];
         if (isfinite(v) && v > node_scrit(d, i, s)) {
             mortal = 1;
             if (d.parent[i] >= 0) sm[d.seg[i]] = 1;
@@ -600,6 +607,195 @@ EM_KERNEL void k_copy_col(Dev d, void *arr, int s, double *out, int to_state)
     else out[i] = (double)a[(size_t)i * d.S + s];
 }
 
+// ------------------------------------------------------------------------
+// Learned screen.  Per tree (sample-independent): total wire length, the
+// longest root-to-node distance along the tree, segment count and junction
+// count (nodes of degree >= 3).  Per (tree, sample): current densities, the
+// Arrhenius diffusivity of Sec. III-D at edge-midpoint temperature times the
+// Monte Carlo multiplier, the peak p of the screen's zero-flux steady stress
+// over the node critical stress (Sec. II-B, first node of the largest ratio),
+// and the slowest-mode diffusion time Lpk^2/(pi^2 kappa_pk) over the
+// distance Lpk (difference of root distances, floored at 0.1 um) from p to
+// the nearest node whose steady stress is at or below sigma_T, kappa_pk the
+// mean diffusivity of the edges at p; and the temperature at p.
+// ------------------------------------------------------------------------
+EM_KERNEL void k_tree_static(Dev d)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= d.n_trees) return;
+    int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
+    double lpath = 0.0, nj = 0.0;
+    d.rdist[i0] = 0.0;
+    for (int i = i0; i < i1; ++i) {
+        int p = d.parent[i];
+        int deg = (p >= 0 ? 1 : 0) + (d.child_off[i + 1] - d.child_off[i]);
+        nj += deg >= 3 ? 1.0 : 0.0;
+        if (p >= 0) {
+            double r = d.rdist[p] + d.len[d.seg[i]] / d.N;
+            d.rdist[i] = r;
+            lpath = fmax(lpath, r);
+        }
+    }
+    double lt = 0.0;
+    for (int k = d.tseg_off[t]; k < d.tseg_off[t + 1]; ++k) lt += d.len[d.tseg[k]];
+    double *o = d.tstat + (size_t)t * 4;
+    o[0] = lt;
+    o[1] = lpath;
+    o[2] = (double)(d.tseg_off[t + 1] - d.tseg_off[t]);
+    o[3] = nj;
+}
+
+__device__ inline double kappa_arrhenius(const Dev &d, double T)
+{
+    double kT = K_B * T;
+    return d.D0 * exp(-d.Ea_eV * E_CHG / kT) * d.B * d.Omega / kT;
+}
+
+__device__ void features_of(const Dev &d, int t, int s, float *x)
+{
+    const int S = d.S;
+    const double *ts = d.tstat + (size_t)t * 4;
+    double jmax = 0.0, jl = 0.0;
+    for (int k = d.tseg_off[t]; k < d.tseg_off[t + 1]; ++k) {
+        int e = d.tseg[k];
+        double j = fabs(d.jseg[(size_t)s * d.n_res + e]);
+        jmax = fmax(jmax, j);
+        jl += d.len[e] * j;
+    }
+    // edge (parent(i), i): Arrhenius diffusivity at the midpoint temperature
+    auto edge_kappa = [&](int i) {
+        return d.xi_k[(size_t)d.seg[i] * S + s] * kappa_arrhenius(d, 0.5 * (d.T[i] + d.T[d.parent[i]]));
+    };
+    int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
+    double ksum = 0.0, r = -INFINITY;
+    int ne = 0, pk = -1;
+    for (int i = i0; i < i1; ++i) {
+        if (d.parent[i] >= 0) {
+            ksum += edge_kappa(i);
+            ++ne;
+        }
+        double ss = d.psi[(size_t)i * S + s];
+        if (isfinite(ss)) {
+            double q = ss / node_scrit(d, i, s);
+            if (q > r) { r = q; pk = i; }
+        }
+    }
+    if (pk < 0) { pk = i0; r = -10.0; }
+    r = fmin(fmax(r, -10.0), 10.0);
+    // distance from the peak to the nearest node at or below sigma_T
+    double lpk = INFINITY;
+    const double dp = d.rdist[pk];
+    for (int i = i0; i < i1; ++i)
+        if (d.psi[(size_t)i * S + s] <= d.sigT) lpk = fmin(lpk, fabs(d.rdist[i] - dp));
+    if (!isfinite(lpk)) lpk = ts[1];
+    lpk = fmax(lpk, 1e-7);
+    double kp = 0.0;
+    int np_ = 0;
+    for (int k = d.child_off[pk]; k < d.child_off[pk + 1]; ++k) { kp += edge_kappa(d.child[k]); ++np_; }
+    if (d.parent[pk] >= 0) { kp += edge_kappa(pk); ++np_; }
+    kp /= np_;
+    double kmean = ksum / ne;
+    double tau = lpk * lpk / (M_PI * M_PI * kp);
+    x[0] = (float)log10(ts[0] / 1e-6);
+    x[1] = (float)log10(ts[1] / 1e-6);
+    x[2] = (float)(ts[2] / 8.0);
+    x[3] = (float)(ts[3] / 4.0);
+    x[4] = (float)log10(fmax(jmax, 1e3) / 1e9);
+    x[5] = (float)log10(fmax(jl / ts[0], 1e3) / 1e9);
+    x[6] = (float)log10(kmean / 1e-15);
+    x[7] = (float)log10(kp / 1e-15);
+    x[8] = (float)r;
+    x[9] = (float)log10(fmax(r - 1.0, 1e-6));
+    x[10] = (float)(log10(tau) - 8.0);
+    x[11] = (float)((d.T[pk] - 300.0) / 100.0);
+}
+
+EM_KERNEL void k_features(Dev d, float *X)
+{
+    int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= d.n_trees * d.S) return;
+    int t, s;
+    int inst = inst_of_slot(d, slot, t, s);
+    features_of(d, t, s, X + (size_t)inst * NFEAT);
+}
+
+// Features of the still-deferred instances of def_list[0..n) with the current
+// densities (their steady stress is refreshed first), row k for def_list[k].
+EM_KERNEL void k_reeval_features(Dev d, int n, float *X)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int inst = d.def_list[k];
+    if (!d.deferred[inst]) return;
+    int t = inst / d.S, s = inst - (inst / d.S) * d.S;
+    steady_stress(d, t, s);
+    features_of(d, t, s, X + (size_t)k * NFEAT);
+}
+
+// A re-evaluated prediction can only bring a deferred instance's activation forward.
+EM_KERNEL void k_yhat_min(Dev d, int n, const float *y)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int inst = d.def_list[k];
+    if (d.deferred[inst]) d.yhat[inst] = fminf(d.yhat[inst], y[k]);
+}
+
+__device__ inline double t_hat(float y) { return T_REF * pow(10.0, (double)y); }
+
+// Defer the steady-state-mortal active instances predicted to nucleate after thr.
+EM_KERNEL void k_defer(Dev d, const float *y, double thr)
+{
+    int inst = blockIdx.x * blockDim.x + threadIdx.x;
+    if (inst >= d.n_trees * d.S) return;
+    d.yhat[inst] = y[inst];
+    d.catchup[inst] = 0;
+    uint8_t df = 0;
+    const uint8_t act = d.inst_active[inst] | d.deferred[inst];   // a repeated evaluation starts over
+    d.inst_active[inst] = act;
+    if (act && d.tree_mortal[inst] && t_hat(y[inst]) > thr) {
+        d.inst_active[inst] = 0;
+        df = 1;
+        atomicAdd(&d.sur_cnt[0], 1u);
+        d.def_list[atomicAdd(&d.sur_cnt[4], 1u)] = inst;
+    }
+    d.deferred[inst] = df;
+}
+
+// Mark deferred instances of running samples whose prediction falls due by thr.
+EM_KERNEL void k_activate(Dev d, double thr)
+{
+    int inst = blockIdx.x * blockDim.x + threadIdx.x;
+    if (inst >= d.n_trees * d.S) return;
+    if (!d.deferred[inst] || !d.sample_active[inst % d.S]) return;
+    if (t_hat(d.yhat[inst]) <= thr) {
+        d.deferred[inst] = 0;
+        d.catchup[inst] = 1;
+        atomicAdd(&d.sur_cnt[1], 1u);
+    }
+}
+
+// Caught-up instances join the active set.  One that nucleated before the
+// interval it was activated for is a late activation; if one of its voids had
+// also reached the growth phase (a resistance change the earlier IR solves
+// did not see), it is a violation: only then can the screened run differ from
+// the unscreened one.
+EM_KERNEL void k_catchup_done(Dev d, int step_lim)
+{
+    int inst = blockIdx.x * blockDim.x + threadIdx.x;
+    if (inst >= d.n_trees * d.S) return;
+    if (!d.catchup[inst]) return;
+    const int nv = d.nv[inst];
+    if (nv > 0 && d.vstep[(size_t)inst * MAXV] < step_lim) {
+        atomicAdd(&d.sur_cnt[2], 1u);
+        bool grown = false;
+        for (int k = 0; k < nv; ++k) grown |= d.vphase[(size_t)inst * MAXV + k] != 0;
+        if (grown) atomicAdd(&d.sur_cnt[3], 1u);
+    }
+    d.catchup[inst] = 0;
+    d.inst_active[inst] = 1;
+}
+
 // ---------------------------- launchers ---------------------------------
 void launch_node_T(const Dev &d, hipStream_t st)
 {
@@ -672,6 +868,35 @@ void launch_copy_node_col(const Dev &d, bool fp32, int which, int sample, double
     void *arr = which == 0 ? d.sc : d.dtf;
     if (fp32) k_copy_col<float><<<nblocks(d.ns), 256, 0, st>>>(d, arr, sample, buf, 0);
     else k_copy_col<double><<<nblocks(d.ns), 256, 0, st>>>(d, arr, sample, buf, 0);
+}
+
+void launch_tree_static(const Dev &d, hipStream_t st)
+{
+    k_tree_static<<<nblocks(d.n_trees), 256, 0, st>>>(d);
+}
+void launch_features(const Dev &d, float *X, hipStream_t st)
+{
+    k_features<<<nblocks(d.n_trees * d.S), 256, 0, st>>>(d, X);
+}
+void launch_reeval_features(const Dev &d, int n, float *X, hipStream_t st)
+{
+    k_reeval_features<<<nblocks(n), 256, 0, st>>>(d, n, X);
+}
+void launch_yhat_min(const Dev &d, int n, const float *y, hipStream_t st)
+{
+    k_yhat_min<<<nblocks(n), 256, 0, st>>>(d, n, y);
+}
+void launch_defer(const Dev &d, const float *y, double thr, hipStream_t st)
+{
+    k_defer<<<nblocks(d.n_trees * d.S), 256, 0, st>>>(d, y, thr);
+}
+void launch_activate(const Dev &d, double thr, hipStream_t st)
+{
+    k_activate<<<nblocks(d.n_trees * d.S), 256, 0, st>>>(d, thr);
+}
+void launch_catchup_done(const Dev &d, int step_lim, hipStream_t st)
+{
+    k_catchup_done<<<nblocks(d.n_trees * d.S), 256, 0, st>>>(d, step_lim);
 }
 
 }  // namespace em

@@ -206,7 +206,7 @@ def gaussian_hotspot_map(seed: int, extent_x: float, extent_y: float, base_K: fl
     ny = int(np.ceil(extent_y / res)) + 1
     x = np.arange(nx) * res
     y = np.arange(ny) * res
-    T = np.full((ny, nx), base_K)
+    T = np.full((ny, nx), float(base_K))
     for _ in range(n_spots):
         A = rng.uniform(*amp_range)
         s = rng.uniform(*sig_range)
@@ -406,6 +406,9 @@ def workload(name: str):
     tiny_mesh       32x32 two-layer mesh with 4 corner pads (IR solve)
     pg400           400x400 two-layer grid, ~800 line trees, thermal map
     mc_mesh         32x32 mesh with cut M1 rows, 1024 Monte Carlo samples
+    screen_mc       200x200 sparse-via grid (via every 64 nodes), 330 K + hotspots,
+                    64 Monte Carlo samples: mortal trees with nucleation times
+                    spread over years and failures within the horizon
     """
     mat = default_material()
     if name == "tiny_trees":
@@ -420,4 +423,66 @@ def workload(name: str):
         return (two_layer_mesh(3001, cut_m1=True, vdd=1.2, sink_mu=np.log(32e-6)), mat,
                 default_run(prec=1),
                 dict(n_samples=1024, seed=3001, cov_kappa=0.2, cov_scrit=0.2))
+    if name == "screen_mc":
+        return (sparse_via_grid(2101), mat, default_run(prec=1, T_ambient=330.0),
+                dict(n_samples=64, seed=5, cov_kappa=0.2, cov_scrit=0.2))
     raise KeyError(name)
+
+
+# ----------------------------------------------------------------------------
+# Learned-screen inputs: initial parameters and training grids
+# ----------------------------------------------------------------------------
+MLP_SHAPES = [(256, 12), (256,), (256, 256), (256,), (256, 256), (256,), (256,), (1,)]
+
+
+def init_mlp_params(seed: int, out_bias: float = 0.0) -> np.ndarray:
+    """Seeded initial parameters of the 12-256-256-256-1 screen model in its
+    flat layout (W1, b1, W2, b2, W3, b3, w4, b4): weights N(0, 2/fan_in)
+    (He scaling for rectifier-like units), biases zero, output bias
+    ``out_bias``."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for k, shp in enumerate(MLP_SHAPES):
+        if len(shp) == 2:
+            parts.append(rng.standard_normal(shp) * np.sqrt(2.0 / shp[1]))
+        elif k == 6:
+            parts.append(rng.standard_normal(shp) * np.sqrt(1.0 / 256))
+        elif k == 7:
+            parts.append(np.array([out_bias]))
+        else:
+            parts.append(np.zeros(shp))
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+def sparse_via_grid(seed: int, n: int = 200, via_every: int = 64, sink_scale: float = 0.012,
+                    base_K: float = 330.0) -> Grid:
+    """The P/G grid family of :func:`pg_grid` with sparse vias (one every
+    ``via_every`` nodes along a line), so that M1 lines carry one-directional
+    current over long spans: the regime where many trees are steady-state
+    mortal and their nucleation times spread over years at 330 K."""
+    return pg_grid(seed, n=n, via_every=via_every, sink_scale=sink_scale, base_K=base_K)
+
+
+def screen_training_grids(seed: int, n_grids: int, n: int = 200, j_scale=(0.8, 1.5)):
+    """Random sparse-via grids for learned-screen labels: via spacing 48 or
+    64 nodes, sink scale drawn per grid so that the initial worst drop stays
+    roughly within 5-9 % of the supply, new thermal map per grid.  Returns
+    (grid, factor) pairs; the labels hold each grid's t = 0 currents fixed,
+    multiplied by ``factor`` ~ U[j_scale] to widen the range of stress
+    margins seen in training."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_grids):
+        ve = int(rng.choice([48, 64]))
+        lo, hi = (0.014, 0.022) if ve == 48 else (0.008, 0.013)
+        g = sparse_via_grid(int(rng.integers(1, 2 ** 31)), n=n, via_every=ve,
+                            sink_scale=float(rng.uniform(lo, hi)))
+        out.append((g, float(rng.uniform(*j_scale))))
+    return out
+
+
+def with_prescribed_j(g: Grid, seg_j: np.ndarray) -> Grid:
+    """A copy of ``g`` in trees-only mode with the given per-resistor current
+    densities held fixed."""
+    return dataclasses.replace(g, seg_j=np.asarray(seg_j, np.float64).copy(),
+                               name=g.name + "_fixed_j")
