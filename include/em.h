@@ -116,6 +116,9 @@ typedef struct {
     int32_t stepper;             /* 0: resident chain kernel for chain trees (straight wires)
                                     that fit a workgroup, generic tree kernel otherwise;
                                     1: generic tree kernel for every tree */
+    int32_t ir_precond;          /* PCG preconditioner of the IR solve: 0 Jacobi (diagonal),
+                                    1 aggregation-multigrid V-cycle (same solution to cg_rtol,
+                                    far fewer iterations) */
 } em_run_params;
 
 /* Monte Carlo (Sec. IV-F): per-segment unit-mean lognormal multipliers on
@@ -184,8 +187,9 @@ em_status em_get_info(em_batch *b, em_info *info);
 const char *em_last_error(const em_batch *b);
 
 /* IR solve (eq. 8) for every sample with R = R0 + dR (open segments conduct
- * nothing; nodes with no conducting path to a pad read 0 V), Jacobi-PCG in
- * FP64 warm-started from the previous solution.  Updates the per-segment
+ * nothing; nodes with no conducting path to a pad read 0 V), preconditioned
+ * CG in FP64 (em_run_params.ir_precond) warm-started from the previous
+ * solution.  Updates the per-segment
  * current densities and the stress forcing.  max_drop: [n_samples] host, may
  * be NULL.  Trees-only batches: EM_ERR_STATE. */
 em_status em_ir_solve(em_batch *b, double *max_drop);

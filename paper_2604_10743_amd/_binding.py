@@ -61,7 +61,7 @@ class RunParams(C.Structure):
                 ("n_steps", C.c_int32), ("ir_every", C.c_int32), ("fail_frac", C.c_double),
                 ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32), ("prec", C.c_int32),
                 ("screen", C.c_int32), ("max_voids_per_tree", C.c_int32), ("T_ambient", C.c_double),
-                ("stepper", C.c_int32)]
+                ("stepper", C.c_int32), ("ir_precond", C.c_int32)]
 
 
 class MCParams(C.Structure):
@@ -187,7 +187,8 @@ class Batch:
                       fail_frac=float(run["fail_frac"]), cg_rtol=float(run["cg_rtol"]),
                       cg_max_iter=int(run["cg_max_iter"]), prec=int(run["prec"]),
                       screen=int(run["screen"]), max_voids_per_tree=int(run["max_voids_per_tree"]),
-                      T_ambient=float(run["T_ambient"]), stepper=int(run.get("stepper", 0)))
+                      T_ambient=float(run["T_ambient"]), stepper=int(run.get("stepper", 0)),
+                      ir_precond=int(run.get("ir_precond", 1)))
         mcp = None
         if mc is not None:
             mcp = MCParams(struct_size=C.sizeof(MCParams), n_samples=int(mc["n_samples"]),

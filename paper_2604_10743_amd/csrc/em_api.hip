@@ -63,6 +63,9 @@ struct em_batch {
     int n_hist = 0;
     double sur_ms = 0.0;
     int n_def_list = 0;           // length of d.def_list from the t = 0 evaluation
+    // multigrid preconditioner of the IR solve (device arrays owned through allocs)
+    Amg amg;
+    bool use_amg = false;
 };
 
 namespace {
@@ -264,7 +267,7 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
     if (r->intervals_per_seg < 1 || !(r->dt > 0) || !std::isfinite(r->dt) || r->n_steps < 0 || r->ir_every < 1 ||
         r->cg_max_iter < 1 || !(r->cg_rtol > 0) || (r->prec != EM_FP64 && r->prec != EM_FP32) ||
         r->max_voids_per_tree < 0 || r->max_voids_per_tree > MAXV || !(r->T_ambient > 0) ||
-        r->stepper < 0 || r->stepper > 1)
+        r->stepper < 0 || r->stepper > 1 || r->ir_precond < 0 || r->ir_precond > 1)
         return fail(b, EM_ERR_ARG, "bad run parameters (max_voids_per_tree <= 4)");
     if (mc && (mc->n_samples < 1 || mc->n_samples > 65535 || mc->cov_kappa < 0 || mc->cov_scrit < 0 || !std::isfinite(mc->cov_kappa) ||
                !std::isfinite(mc->cov_scrit)))
@@ -294,22 +297,39 @@ em_status ir_solve_impl(em_batch *b)
         b->live_dirty = false;
     }
     const double rtol = b->run.cg_rtol;
+    const bool amg = b->use_amg;
     launch_ir_gather_inc(d, b->n_inc, st);
     launch_ir_setup(d, st);
     launch_ir_finalize0(d, rtol, st);
     LAUNCHCHK(b);
     uint8_t *hconv = pinned(b, std::max<size_t>(d.S, 8));
     if (!hconv) return fail(b, EM_ERR_OOM, "pinned host buffer");
+    if (amg) {
+        // samples whose warm start already meets the tolerance need no
+        // preconditioner; for the others: this solve's coarse operators, then
+        // z = M^-1 r, p = z and r.z
+        HIPCHK(b, hipMemcpyAsync(hconv, d.conv, d.S, hipMemcpyDeviceToHost, st));
+        HIPCHK(b, hipStreamSynchronize(st));
+        bool all = true;
+        for (int s = 0; s < d.S; ++s) all &= hconv[s] != 0;
+        if (!all) {
+            launch_amg_setup(d, b->amg, st);
+            launch_amg_vcycle(d, b->amg, true, st);
+            launch_ir_finalize_rz(d, st);
+            LAUNCHCHK(b);
+        }
+    }
     // CG_BLOCK iterations (an even count, so the r.z parity pattern repeats)
     // are captured once on a private stream and replayed as one graph launch.
-    constexpr int CG_BLOCK = 8;
+    const int CG_BLOCK = amg ? 4 : 8;
     if (!b->cg_exec) {
         if (!b->cap_stream) HIPCHK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
         HIPCHK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
         for (int k = 0; k < CG_BLOCK; ++k) {
             launch_ir_spmv(d, b->cap_stream);
-            launch_ir_update(d, k, b->cap_stream);
-            launch_ir_pupdate(d, k, rtol, b->cap_stream);
+            launch_ir_update(d, k, amg ? b->amg.omega : 0.0, b->cap_stream);
+            if (amg) launch_amg_vcycle(d, b->amg, false, b->cap_stream);
+            launch_ir_pupdate(d, k, rtol, d.z, b->cap_stream);
         }
         HIPCHK(b, hipStreamEndCapture(b->cap_stream, &b->cg_graph));
         HIPCHK(b, hipGraphInstantiate(&b->cg_exec, b->cg_graph, nullptr, nullptr, 0));
@@ -672,6 +692,34 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     AL(d.rz, double, 2 * (size_t)S); AL(d.bb, double, S); AL(d.conv, uint8_t, S); AL(d.drop, double, S);
     AL(d.ttf, double, S); AL(d.final_drop, double, S); AL(d.init_drop, double, S);
     AL(d.t_prev, double, S); AL(d.d_prev, double, S); AL(d.failed, int, S); AL(d.outer_idx, int, S);
+    if (!b->trees_only && r->ir_precond == 1) {
+        AmgHost H = amg_build(nn, is_pad.data(), nr, g->res_a, g->res_b, g->res_R0);
+        Amg &a = b->amg;
+        a.nlev = (int)H.lev.size() - 1;
+        if (a.nlev >= 1) {
+            a.l0.ne0 = (int)H.e0_res.size();
+            UP(a.l0.e0_res, H.e0_res); UP(a.l0.e0_a, H.e0_a); UP(a.l0.e0_b, H.e0_b);
+            AL(a.l0.w0, double, VS);
+            for (int l = 1; l <= a.nlev; ++l) {
+                const AmgHostLevel &h = H.lev[l];
+                AmgLevel &L = a.lev[l];
+                L.n = h.n; L.ne = h.ne; L.nf = h.nf; L.nef = h.nef;
+                UP(L.agg, h.agg); UP(L.mem_off, h.mem_off); UP(L.mem, h.mem);
+                UP(L.int_off, h.int_off); UP(L.int_e, h.int_e);
+                UP(L.src_off, h.src_off); UP(L.src_e, h.src_e);
+                UP(L.adj_off, h.adj_off); UP(L.adj_nbr, h.adj_nbr); UP(L.adj_e, h.adj_e);
+                AL(L.D, double, (size_t)S * h.n); AL(L.W, double, (size_t)S * std::max(h.ne, 1));
+                AL(L.b, double, (size_t)S * h.n); AL(L.x, double, (size_t)S * h.n);
+                AL(L.y, double, (size_t)S * h.n); AL(L.w, double, (size_t)S * h.n);
+            }
+            const int nc = a.lev[a.nlev].n;
+            a.dense = nc <= AMG_NC_MAX ? 1 : 0;
+            if (a.dense) AL(a.Ainv, double, (size_t)S * nc * nc);
+            b->use_amg = true;
+            a.omega = 0.9;          // Jacobi weight and coarse-correction scale chosen by
+            a.alpha = 1.4;          // measurement (PCG iterations on the P/G grids)
+        }
+    }
 
     hipStream_t stq = b->stream;
     b->d_dev = (Dev *)dalloc(b, sizeof(Dev));

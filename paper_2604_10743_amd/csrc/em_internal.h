@@ -11,6 +11,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <vector>
 
 namespace em {
 
@@ -110,6 +111,52 @@ struct Dev {
     unsigned int *sur_cnt;              // [8] deferred, activated, late, violations, list length
 };
 
+// Aggregation multigrid preconditioner of the IR solve.  Level 0 is the nodal
+// system on the free nodes; level l >= 1 has one node per aggregate of level
+// l - 1 nodes (heavy-edge pair matching applied twice, so aggregates of up to
+// four) and the Galerkin operator of piecewise-constant prolongation.
+constexpr int AMG_MAXLEV = 16;
+constexpr int AMG_NC_MAX = 88;          // coarsest level inverted densely when this small
+
+struct AmgLevel {
+    int n, ne, nf, nef;                 // nodes, edges of this level; nodes, edges of the finer one
+    const int *agg;                     // [nf] finer node -> node of this level (-1: outside)
+    const int *mem_off, *mem;           // members of each node
+    const int *int_off, *int_e;         // finer edges inside each node
+    const int *src_off, *src_e;         // finer edges merged into each edge
+    const int *adj_off, *adj_nbr, *adj_e;   // this level's graph (both directions)
+    double *D, *W;                      // [S][n] diagonal, [S][ne] edge conductance
+    double *b, *x, *y, *w;              // [S][n] V-cycle vectors
+};
+
+struct Amg0 {                           // level-0 edges: resistors with both ends off the pads
+    int ne0;
+    const int *e0_res, *e0_a, *e0_b;
+    double *w0;                         // [S][n_nodes] level-0 scratch
+};
+
+struct Amg {
+    int nlev = 0;                       // coarse levels 1..nlev
+    AmgLevel lev[AMG_MAXLEV + 1];
+    Amg0 l0;
+    double *Ainv = nullptr;             // [S][n][n] inverse of the coarsest operator (dense case)
+    int dense = 0;
+    double omega = 2.0 / 3.0, alpha = 1.0;
+};
+
+// Host-side construction of the aggregation hierarchy on the nominal
+// conductances (1/R0); every array is returned for upload.
+struct AmgHostLevel {
+    int n = 0, ne = 0, nf = 0, nef = 0;
+    std::vector<int> agg, mem_off, mem, int_off, int_e, src_off, src_e, adj_off, adj_nbr, adj_e;
+};
+struct AmgHost {
+    std::vector<int> e0_res, e0_a, e0_b;
+    std::vector<AmgHostLevel> lev;      // lev[0] unused
+};
+AmgHost amg_build(int n_nodes, const uint8_t *is_pad, int n_res, const int *ra, const int *rb,
+                  const double *R0);
+
 constexpr int NFEAT = 12;               // learned-screen features per (tree, sample)
 constexpr double T_REF = 1e8;           // s; the model predicts log10(t_nuc / T_REF)
 
@@ -138,10 +185,22 @@ void launch_ir_live_step(const Dev &d, hipStream_t st);
 void launch_ir_setup(const Dev &d, hipStream_t st);       // diag, rhs, r = b - A x, z, p, partials
 void launch_ir_finalize0(const Dev &d, double rtol, hipStream_t st);
 void launch_ir_spmv(const Dev &d, hipStream_t st);        // q = A p, partial p.q
-void launch_ir_update(const Dev &d, int it, hipStream_t st);   // x,r,z; partial r.z, r.r
-void launch_ir_pupdate(const Dev &d, int it, double rtol, hipStream_t st);  // p = z + beta p, conv
+// x, r; z = r/diag and partials r.z, r.r (amg_omega == 0), or the multigrid
+// pre-smoothing z = omega r/diag and partial r.r only
+void launch_ir_update(const Dev &d, int it, double amg_omega, hipStream_t st);
+// p = z + beta p (z read from zs: d.z, or the multigrid output), conv
+void launch_ir_pupdate(const Dev &d, int it, double rtol, const double *zs, hipStream_t st);
 int ir_nodes_per_block();
 void launch_ir_finish(const Dev &d, hipStream_t st);      // u, j, drop
+// multigrid: per-solve Galerkin operators and coarsest inverse; one V-cycle
+// z = M^-1 r (init: also pre-smoothing and p = z), partial r.z
+void launch_ir_finalize_rz(const Dev &d, hipStream_t st);
+void launch_amg_pre0(const Dev &d, double omega, hipStream_t st);
+void launch_amg_res0(const Dev &d, double *w0, hipStream_t st);
+void launch_amg_post0(const Dev &d, double *w0, const AmgLevel &L1, const double *r1, double alpha,
+                      double omega, bool init, hipStream_t st);
+void launch_amg_setup(const Dev &d, const Amg &a, hipStream_t st);
+void launch_amg_vcycle(const Dev &d, const Amg &a, bool init, hipStream_t st);
 void launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
 void launch_ttf_init(const Dev &d, double fail, hipStream_t st);
 void launch_ttf_update(const Dev &d, double fail, int k, double t, hipStream_t st);

@@ -198,12 +198,13 @@ EM_KERNEL void k_ir_spmv(Dev d)
 
 // alpha = (r.z)/(p.q) from the partials (every block sums them in the same
 // order); x += alpha p, r -= alpha q, z = r/diag; partials r.z and r.r.
-EM_KERNEL void k_ir_update(Dev d, int it)
+EM_KERNEL void k_ir_update(Dev d, int it, double amg_omega)
 {
     int s = blockIdx.y, bx = blockIdx.x;
     if (d.conv[s]) return;
     const double pq = sum_partials(d, s, 0);
     const double alpha = pq > 0.0 ? d.rz[(it & 1) * d.S + s] / pq : 0.0;
+    const bool amg = amg_omega > 0.0;
     double rz = 0, rr = 0;
     for (int c = 0; c < IR_NPT; ++c) {
         int i = bx * IR_NPB + c * IR_BS + threadIdx.x;
@@ -212,15 +213,98 @@ EM_KERNEL void k_ir_update(Dev d, int it)
         size_t x = (size_t)s * d.n_nodes + i;
         d.u[x] += alpha * d.p[x];
         double r = d.r[x] - alpha * d.q[x];
-        double z = r / d.diag[x];
+        double z = (amg ? amg_omega * r : r) / d.diag[x];
         d.r[x] = r; d.z[x] = z;
         rz += r * z; rr += r * r;
     }
-    block_partials(d, s, bx, 0.0, rz, rr, 0.0, 0x6);
+    block_partials(d, s, bx, 0.0, rz, rr, 0.0, amg ? 0x4 : 0x6);
+}
+
+// ---- multigrid V-cycle, level 0 (the free nodes of the nodal system) ----
+// r.z of the preconditioned start of the not yet converged samples
+EM_KERNEL void k_ir_finalize_rz(Dev d)
+{
+    int s = blockIdx.x;
+    if (d.conv[s]) return;
+    double rz = sum_partials(d, s, 1);
+    if (threadIdx.x == 0) d.rz[s] = rz;
+}
+
+// z = omega r / diag (pre-smoothing from zero)
+EM_KERNEL void k_amg_pre0(Dev d, double omega)
+{
+    int s = blockIdx.y, bx = blockIdx.x;
+    if (d.conv[s]) return;
+    for (int c = 0; c < IR_NPT; ++c) {
+        int i = bx * IR_NPB + c * IR_BS + threadIdx.x;
+        if (i >= d.n_nodes) break;
+        size_t x = (size_t)s * d.n_nodes + i;
+        d.z[x] = is_free(d, s, i) ? omega * d.r[x] / d.diag[x] : 0.0;
+    }
+}
+
+// A v at free node i (v vanishes off the free nodes)
+__device__ inline double A0v(const Dev &d, int s, int i, const double *v)
+{
+    const double *Gi = d.G_inc + (size_t)s * d.ninc_off[d.n_nodes];
+    double a = d.diag[(size_t)s * d.n_nodes + i] * v[i];
+    for (int k = d.ninc_off[i]; k < d.ninc_off[i + 1]; ++k) a -= Gi[k] * v[d.ninc_nbr[k]];
+    return a;
+}
+
+// w0 = r - A z (z the pre-smoothed vector)
+EM_KERNEL void k_amg_res0(Dev d, double *w0)
+{
+    int s = blockIdx.y, bx = blockIdx.x;
+    if (d.conv[s]) return;
+    const double *z = d.z + (size_t)s * d.n_nodes;
+    for (int c = 0; c < IR_NPT; ++c) {
+        int i = bx * IR_NPB + c * IR_BS + threadIdx.x;
+        if (i >= d.n_nodes) break;
+        size_t x = (size_t)s * d.n_nodes + i;
+        w0[x] = is_free(d, s, i) ? d.r[x] - A0v(d, s, i, z) : 0.0;
+    }
+}
+
+// w0 = z + alpha r1[agg] on the free nodes, 0 elsewhere (r1: level 1's result)
+EM_KERNEL void k_amg_prolong0(Dev d, double *w0, AmgLevel L1, const double *r1, double alpha)
+{
+    int s = blockIdx.y, bx = blockIdx.x;
+    if (d.conv[s]) return;
+    for (int c = 0; c < IR_NPT; ++c) {
+        int i = bx * IR_NPB + c * IR_BS + threadIdx.x;
+        if (i >= d.n_nodes) break;
+        size_t x = (size_t)s * d.n_nodes + i;
+        int J = L1.agg[i];
+        w0[x] = (is_free(d, s, i) && J >= 0) ? d.z[x] + alpha * r1[(size_t)s * L1.n + J] : 0.0;
+    }
+}
+
+// z = w0 + omega (r - A w0) / diag on the free nodes, 0 elsewhere; partial
+// r.z; at the start of a solve also p = z
+EM_KERNEL void k_amg_smooth0(Dev d, const double *w0, double omega, int init)
+{
+    int s = blockIdx.y, bx = blockIdx.x;
+    if (d.conv[s]) return;
+    const double *w = w0 + (size_t)s * d.n_nodes;
+    double rz = 0.0;
+    for (int c = 0; c < IR_NPT; ++c) {
+        int i = bx * IR_NPB + c * IR_BS + threadIdx.x;
+        if (i >= d.n_nodes) break;
+        size_t x = (size_t)s * d.n_nodes + i;
+        double z = 0.0;
+        if (is_free(d, s, i)) {
+            z = w[i] + omega * (d.r[x] - A0v(d, s, i, w)) / d.diag[x];
+            rz += d.r[x] * z;
+        }
+        d.z[x] = z;
+        if (init) d.p[x] = z;
+    }
+    block_partials(d, s, bx, 0.0, rz, 0.0, 0.0, 0x2);
 }
 
 // beta = (new r.z)/(old r.z); p = z + beta p; convergence flag.
-EM_KERNEL void k_ir_pupdate(Dev d, int it, double rtol)
+EM_KERNEL void k_ir_pupdate(Dev d, int it, double rtol, const double *zs)
 {
     int s = blockIdx.y, bx = blockIdx.x;
     if (d.conv[s]) return;
@@ -233,7 +317,7 @@ EM_KERNEL void k_ir_pupdate(Dev d, int it, double rtol)
         if (i >= d.n_nodes) break;
         if (!is_free(d, s, i)) continue;
         size_t x = (size_t)s * d.n_nodes + i;
-        d.p[x] = d.z[x] + beta * d.p[x];
+        d.p[x] = zs[x] + beta * d.p[x];
     }
     if (bx == 0 && threadIdx.x == 0) {
         d.rz[((it + 1) & 1) * d.S + s] = rz_new;
@@ -357,13 +441,31 @@ void launch_ir_spmv(const Dev &d, hipStream_t st)
 {
     k_ir_spmv<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d);
 }
-void launch_ir_update(const Dev &d, int it, hipStream_t st)
+void launch_ir_update(const Dev &d, int it, double amg_omega, hipStream_t st)
 {
-    k_ir_update<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d, it);
+    k_ir_update<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d, it, amg_omega);
 }
-void launch_ir_pupdate(const Dev &d, int it, double rtol, hipStream_t st)
+void launch_ir_finalize_rz(const Dev &d, hipStream_t st)
 {
-    k_ir_pupdate<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d, it, rtol);
+    k_ir_finalize_rz<<<d.S, 64, 0, st>>>(d);
+}
+void launch_amg_pre0(const Dev &d, double omega, hipStream_t st)
+{
+    k_amg_pre0<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d, omega);
+}
+void launch_amg_res0(const Dev &d, double *w0, hipStream_t st)
+{
+    k_amg_res0<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d, w0);
+}
+void launch_amg_post0(const Dev &d, double *w0, const AmgLevel &L1, const double *r1, double alpha,
+                      double omega, bool init, hipStream_t st)
+{
+    k_amg_prolong0<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d, w0, L1, r1, alpha);
+    k_amg_smooth0<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d, w0, omega, init ? 1 : 0);
+}
+void launch_ir_pupdate(const Dev &d, int it, double rtol, const double *zs, hipStream_t st)
+{
+    k_ir_pupdate<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d, it, rtol, zs);
 }
 int ir_nodes_per_block() { return IR_NPB; }
 void launch_ir_finish(const Dev &d, hipStream_t st)
