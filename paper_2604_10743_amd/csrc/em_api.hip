@@ -37,6 +37,8 @@ struct em_batch {
     Dev *d_dev = nullptr;         // device copy of d (read by kernels through a pointer)
     bool have_j = false;
     bool live_dirty = true;
+    bool any_open = false;        // some segment of some sample has opened since creation/reset
+    uint8_t *live0 = nullptr;     // [n_nodes] reachability from the pads with every resistor conducting
     int cg_iters_last = 0;
     int n_outer_done = 0;
     int step_counter = 0;         // steps taken through em_stress_step
@@ -281,6 +283,11 @@ em_status ir_solve_impl(em_batch *b)
     hipStream_t st = b->stream;
     launch_ir_conductance(d, st);
     LAUNCHCHK(b);
+    if (b->live_dirty && !b->any_open && b->live0) {
+        launch_ir_live_copy(d, b->live0, st);     // nothing open: the static reachability holds
+        LAUNCHCHK(b);
+        b->live_dirty = false;
+    }
     if (b->live_dirty) {
         launch_ir_live_init(d, st);
         uint32_t *hc = (uint32_t *)pinned(b, std::max<size_t>(d.S, 8));
@@ -365,6 +372,7 @@ em_status sync_open_dirty(em_batch *b)
     HIPCHK(b, hipStreamSynchronize(b->stream));
     if (*h) {
         b->live_dirty = true;
+        b->any_open = true;
         HIPCHK(b, hipMemsetAsync(b->d.open_dirty, 0, 4, b->stream));
     }
     return EM_OK;
@@ -576,6 +584,19 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
             ninc_res[pos[c]] = e; ninc_nbr[pos[c]++] = a;
         }
     }
+    // static reachability from the pads (breadth-first over every resistor)
+    std::vector<uint8_t> live0(nn, 0);
+    {
+        std::vector<int> queue;
+        for (int v = 0; v < nn; ++v) if (is_pad[v]) { live0[v] = 1; queue.push_back(v); }
+        for (size_t q = 0; q < queue.size(); ++q) {
+            int v = queue[q];
+            for (int k = ninc_off[v]; k < ninc_off[v + 1]; ++k) {
+                int u = ninc_nbr[k];
+                if (!live0[u]) { live0[u] = 1; queue.push_back(u); }
+            }
+        }
+    }
     // lane slots: larger trees first so a wavefront of trees has similar sizes
     std::vector<int> tree_perm(nt);
     for (int t = 0; t < nt; ++t) tree_perm[t] = t;
@@ -634,6 +655,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     UPR(d.ra, g->res_a, nr); UPR(d.rb, g->res_b, nr);
     UPR(d.len, g->res_len, nr); UPR(d.w, g->res_w, nr); UPR(d.h, g->res_h, nr); UPR(d.R0, g->res_R0, nr);
     UP(d.is_wire, is_wire); UP(d.is_pad, is_pad);
+    UP(b->live0, live0);
     if (g->sink_I) UPR(d.sink, g->sink_I, nn);
     else { double *z; AL(z, double, nn); d.sink = z; }
     UP(d.ninc_off, ninc_off); UP(d.ninc_res, ninc_res); UP(d.ninc_nbr, ninc_nbr);
@@ -999,6 +1021,7 @@ em_status em_reset(em_batch *b)
     HIPCHK(b, hipStreamSynchronize(st));
     b->sur_ms = 0.0;
     b->live_dirty = true;
+    b->any_open = false;
     b->have_j = b->trees_only;
     b->step_counter = 0;
     b->n_outer_done = 0;

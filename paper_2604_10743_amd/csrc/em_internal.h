@@ -180,6 +180,7 @@ void launch_copy_node_col(const Dev &d, bool fp32, int which, int sample, double
 // IR
 void launch_ir_conductance(const Dev &d, hipStream_t st);
 void launch_ir_gather_inc(const Dev &d, int ninc, hipStream_t st);
+void launch_ir_live_copy(const Dev &d, const uint8_t *live0, hipStream_t st);
 void launch_ir_live_init(const Dev &d, hipStream_t st);
 void launch_ir_live_step(const Dev &d, hipStream_t st);
 void launch_ir_setup(const Dev &d, hipStream_t st);       // diag, rhs, r = b - A x, z, p, partials

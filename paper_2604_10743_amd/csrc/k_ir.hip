@@ -98,6 +98,13 @@ EM_KERNEL void k_ir_gather_inc(Dev d)
     d.G_inc[g] = d.G[(size_t)s * d.n_res + d.ninc_res[k]];
 }
 
+EM_KERNEL void k_ir_live_copy(Dev d, const uint8_t *live0)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)d.S * d.n_nodes) return;
+    d.live[g] = live0[g % d.n_nodes];
+}
+
 EM_KERNEL void k_ir_live_init(Dev d)
 {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -420,6 +427,11 @@ void launch_ir_conductance(const Dev &d, hipStream_t st)
 void launch_ir_gather_inc(const Dev &d, int ninc, hipStream_t st)
 {
     k_ir_gather_inc<<<nb((long long)d.S * ninc), IR_BS, 0, st>>>(d);
+}
+void launch_ir_live_copy(const Dev &d, const uint8_t *live0, hipStream_t st)
+{
+    long long n = (long long)d.S * d.n_nodes;
+    k_ir_live_copy<<<(int)((n + IR_BS - 1) / IR_BS), IR_BS, 0, st>>>(d, live0);
 }
 void launch_ir_live_init(const Dev &d, hipStream_t st)
 {

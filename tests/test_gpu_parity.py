@@ -156,10 +156,11 @@ def test_single_step_with_injected_voids_fp64(em, oracle_mod):
     assert np.allclose(dv, dv_o, rtol=1e-9, atol=1e-30)
 
 
-def test_ir_solve_matches_direct_solve(em, oracle_mod):
+@pytest.mark.parametrize("precond", [0, 1])
+def test_ir_solve_matches_direct_solve(em, oracle_mod, precond):
     g, mat, rn, _ = synth.workload("tiny_mesh")
-    rn = dict(rn, cg_rtol=1e-14, cg_max_iter=100000)
-    _flush("ir tiny_mesh")
+    rn = dict(rn, cg_rtol=1e-14, cg_max_iter=100000, ir_precond=precond)
+    _flush(f"ir tiny_mesh precond {precond}")
     B = em.Batch(g, mat, rn)
     drop = B.ir_solve()
     u_o, I_o, j_o, d_o = oracle_mod.ir_solve(g, g.res_R0)
@@ -168,6 +169,25 @@ def test_ir_solve_matches_direct_solve(em, oracle_mod):
     assert abs(drop[0] - d_o) <= 1e-9 * d_o
     j = B.seg_j()
     assert np.max(np.abs(j - j_o)) <= 1e-6 * np.max(np.abs(j_o))
+
+
+def test_ir_multigrid_large_grid_matches_direct_solve(em, oracle_mod):
+    # 200x200 sparse-via grid (~57k nodes, several multigrid levels), three
+    # Monte Carlo samples sharing one nominal network
+    g = synth.sparse_via_grid(2101)
+    mat = material()
+    rn = run(prec=1, T_ambient=330.0, cg_rtol=1e-13, cg_max_iter=20000)
+    mc = dict(n_samples=3, seed=1, cov_kappa=0.2, cov_scrit=0.2)
+    _flush("ir sparse-via multigrid")
+    B = em.Batch(g, mat, rn, mc)
+    drop = B.ir_solve()
+    it = B.info()["cg_iters_last"]
+    u_o, I_o, j_o, d_o = oracle_mod.ir_solve(g, g.res_R0)
+    for s in range(3):
+        u = B.voltages(s)
+        assert np.max(np.abs(u - u_o)) <= 1e-9 * g.vdd, s
+        assert abs(drop[s] - d_o) <= 1e-8 * d_o
+    assert it < 400, it
 
 
 def test_screen_bit_exact(em, oracle_mod):
