@@ -38,6 +38,7 @@ struct em_batch {
     bool have_j = false;
     bool live_dirty = true;
     bool any_open = false;        // some segment of some sample has opened since creation/reset
+    bool ir_valid = false;        // u, j, drop hold the solution for the current conductances
     uint8_t *live0 = nullptr;     // [n_nodes] reachability from the pads with every resistor conducting
     int cg_iters_last = 0;
     int n_outer_done = 0;
@@ -281,8 +282,20 @@ em_status ir_solve_impl(em_batch *b)
 {
     Dev &d = b->d;
     hipStream_t st = b->stream;
+    HIPCHK(b, hipMemsetAsync(d.g_changed, 0, 4, st));
     launch_ir_conductance(d, st);
     LAUNCHCHK(b);
+    if (b->ir_valid && !b->live_dirty) {
+        // no conductance changed since the last solve: its solution stands
+        uint32_t *hg = (uint32_t *)pinned(b, std::max<size_t>(d.S, 8));
+        if (!hg) return fail(b, EM_ERR_OOM, "pinned host buffer");
+        HIPCHK(b, hipMemcpyAsync(hg, d.g_changed, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(b, hipStreamSynchronize(st));
+        if (*hg == 0) {
+            b->cg_iters_last = 0;
+            return EM_OK;
+        }
+    }
     if (b->live_dirty && !b->any_open && b->live0) {
         launch_ir_live_copy(d, b->live0, st);     // nothing open: the static reachability holds
         LAUNCHCHK(b);
@@ -361,6 +374,7 @@ em_status ir_solve_impl(em_batch *b)
     launch_update_f(d, b->fp32, st);
     LAUNCHCHK(b);
     b->have_j = true;
+    b->ir_valid = true;
     return EM_OK;
 }
 
@@ -708,7 +722,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     b->n_inc = ninc_off[nn];
     AL(d.diag, double, VS); AL(d.rhs, double, VS); AL(d.u, double, VS); AL(d.r, double, VS);
     AL(d.z, double, VS); AL(d.p, double, VS); AL(d.q, double, VS);
-    AL(d.live, uint8_t, VS); AL(d.live_changed, uint32_t, 1);
+    AL(d.live, uint8_t, VS); AL(d.live_changed, uint32_t, 1); AL(d.g_changed, uint32_t, 1);
     d.ir_nblk = (nn + ir_nodes_per_block() - 1) / ir_nodes_per_block();
     AL(d.part, double, (size_t)S * d.ir_nblk * 4);
     AL(d.rz, double, 2 * (size_t)S); AL(d.bb, double, S); AL(d.conv, uint8_t, S); AL(d.drop, double, S);
@@ -1022,6 +1036,7 @@ em_status em_reset(em_batch *b)
     b->sur_ms = 0.0;
     b->live_dirty = true;
     b->any_open = false;
+    b->ir_valid = false;
     b->have_j = b->trees_only;
     b->step_counter = 0;
     b->n_outer_done = 0;

@@ -92,6 +92,7 @@ struct Dev {
     double *diag, *rhs, *u, *r, *z, *p, *q;
     uint8_t *live;                      // [S][n_nodes]
     uint32_t *live_changed;
+    uint32_t *g_changed;                // [1] some conductance differs from the last solve's
     double *part;                       // [S][nblk][4] block partial sums
     double *rz;                         // [2][S] r.z, double-buffered by iteration parity
     double *bb;                         // [S]

@@ -167,13 +167,17 @@ AmgHost amg_build(int n_nodes, const uint8_t *is_pad, int n_res, const int *ra, 
     int n_sys = 0;
     for (int i = 0; i < n_nodes; ++i) n_sys += !g.excl[i];
     if (n_sys < 2) return H;
+    const int npass = 2;          // matching passes per level (3 or 4 measured slower)
     while ((int)H.lev.size() <= AMG_MAXLEV) {
-        std::vector<int> m1, m2;
-        int n1 = match_pass(g, m1);
-        Graph g1 = collapse(g, m1, n1, nullptr);
-        int n2 = match_pass(g1, m2);
-        std::vector<int> agg(g.n, -1);
-        for (int i = 0; i < g.n; ++i) agg[i] = m1[i] < 0 ? -1 : m2[m1[i]];
+        std::vector<int> agg(g.n), mk;
+        for (int i = 0; i < g.n; ++i) agg[i] = g.excl[i] ? -1 : i;
+        Graph gk = g;
+        int n2 = 0;
+        for (int pass = 0; pass < npass; ++pass) {
+            n2 = match_pass(gk, mk);
+            for (int i = 0; i < g.n; ++i) agg[i] = agg[i] < 0 ? -1 : mk[agg[i]];
+            if (pass + 1 < npass) gk = collapse(gk, mk, n2, nullptr);
+        }
         AmgHostLevel L;
         Graph c = collapse(g, agg, n2, &L);
         int n_prev = 0;

@@ -85,7 +85,11 @@ EM_KERNEL void k_ir_conductance(Dev d)
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long long)d.S * d.n_res) return;
     int r = (int)(g % d.n_res);
-    d.G[g] = d.open[g] ? 0.0 : 1.0 / (d.R0[r] + d.dR[g]);
+    const double Gn = d.open[g] ? 0.0 : 1.0 / (d.R0[r] + d.dR[g]);
+    if (Gn != d.G[g]) {
+        d.G[g] = Gn;
+        *d.g_changed = 1u;
+    }
 }
 
 // Conductance of every node-incidence entry, contiguous per node (SpMV rows).
