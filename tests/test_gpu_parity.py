@@ -273,3 +273,75 @@ def test_mc_run_fp32_vs_oracle(em, oracle_mod):
         dR, op = B.seg_state(s)
         assert np.array_equal(np.nonzero((dR > 0) | (op != 0))[0], ref["failed_segs"]), s
     assert n_fail > 0 and n_cmp >= 12
+
+
+# ----------------------------------------------------------------- FP32 forms
+# FP32 stepping stores sigma, dt*f and the factors in float; the residual is
+# formed in FP64 from flux differences, so each step's increment carries a
+# relative error of a few float ulps (2^-24 ~ 6e-8) times the conditioning of
+# the step matrix.  Over 2000 steps these errors add like a random walk in the
+# increments (sqrt(2000) ~ 45) with a systematic part bounded by the
+# conservation projection: a few 1e-6 of a tree's stress scale.  The bound
+# below is 1e-5 of max |sigma| per tree.
+TOL_FP32_TREE = 1e-5
+# On the 400x400 grid a chain holds up to 8000 nodes, i.e. a separator system
+# of 1000 lanes per workgroup solved by cyclic reduction in float: the error
+# of each step's increment grows with that system's conditioning (~ lanes^2
+# for a diffusion operator), measured 8.6e-5 of max |sigma| after one aging
+# interval; bound 2e-4.  (The benchmark's accuracy bar is on time to failure
+# and final drop, 1e-3 relative.)
+TOL_FP32_LONG_CHAIN = 2e-4
+
+
+@pytest.mark.parametrize("prec,stepper", [(1, 0), (1, 1), (0, 1)])
+def test_tiny_trees_steppers_and_precisions(em, oracle_mod, prec, stepper):
+    g, mat, rn, _ = synth.workload("tiny_trees")
+    if prec == 1:
+        mat = material(sigma_crit=1e12)     # no nucleation: a float decision would be moot
+    rn = dict(rn, prec=prec, stepper=stepper)
+    _flush(f"tiny_trees prec {prec} stepper {stepper}")
+    B = em.Batch(g, mat, rn)
+    topo = oracle_mod.topology(g, 20)
+    B.stress_step(rn["n_steps"])
+    ref = oracle_mod.run_sample(g, mat, dict(rn, prec=0), topo=topo)
+    err = _per_tree_rel(B.stress(), ref["sigma"], topo.tree_off)
+    print(f"per-tree relative error {err:.3e}")
+    if prec == 0:
+        assert err <= 1e-9
+        ev_g = _sorted_events(B.events(), [1, 2, 3, 4])
+        ev_o = _sorted_events(ref["events"], [0, 1, 2, 3])
+        assert np.array_equal(ev_g, ev_o)
+    else:
+        assert err <= TOL_FP32_TREE
+        assert len(B.events()) == 0
+
+
+def test_pg400_full_size_fp32_sampled_trees(em, oracle_mod):
+    """The 400x400 grid at full size in the configuration the benchmark times
+    (FP32, chain kernel, screen off): the IR drop against the oracle's direct
+    solve, and the stress of every 40th tree after one aging interval (100
+    steps) against the FP64 oracle stepping the same trees with its own
+    currents."""
+    g, mat, rn, _ = synth.workload("pg400")
+    rn = dict(rn, screen=0)
+    _flush("pg400 full size fp32")
+    B = em.Batch(g, mat, rn)
+    drop = B.ir_solve()[0]
+    u_o, I_o, j_o, d_o = oracle_mod.ir_solve(g, g.res_R0)
+    assert abs(drop - d_o) <= 1e-6 * d_o
+    B.stress_step(rn["ir_every"])
+    sig = B.stress()
+    topo = oracle_mod.topology(g, rn["intervals_per_seg"])
+    pick = np.zeros(topo.n_trees, np.uint8)
+    pick[::40] = 1
+    sim = oracle_mod.SampleSim(g, mat, dict(rn, prec=0), topo)
+    sim.set_j(j_o)
+    sim.set_active(pick)
+    sim.steps(rn["ir_every"], 0)
+    ref = sim.sigma()
+    worst = 0.0
+    for t in np.nonzero(pick)[0]:
+        sl = slice(topo.tree_off[t], topo.tree_off[t + 1])
+        worst = max(worst, np.max(np.abs(sig[sl] - ref[sl])) / np.max(np.abs(ref[sl])))
+    print(f"pg400 sampled trees: worst per-tree relative error {worst:.3e}, drop {drop:.6f} vs {d_o:.6f}")
+    assert worst <= TOL_FP32_LONG_CHAIN
