@@ -100,6 +100,20 @@ def surrogate_leg(args):
 
     r0, i0, w0 = mc_run(False)
     r1, i1, w1 = mc_run(True)
+    # inference throughput of the screen model on this workload's feature rows
+    Bf = P.Batch(g, mat, run, mc)
+    Bf.ir_solve()
+    Xf = Bf.features()
+    Bf.close()
+    model.forward(Xf)
+    torch.cuda.synchronize()
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        model.forward(Xf)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t0) / reps
+    flop_inf = 2 * int(Xf.shape[0]) * (16 * 256 + 2 * 256 * 256)
     same = all((a["failed"] == b["failed"]) and (a["outer_idx"] == b["outer_idx"]) and
                (np.isnan(a["ttf_s"]) and np.isnan(b["ttf_s"]) or a["ttf_s"] == b["ttf_s"]) and
                a["final_drop"] == b["final_drop"] and a["n_failed_segs"] == b["n_failed_segs"]
@@ -117,6 +131,8 @@ def surrogate_leg(args):
             "step_kernel_ms_unscreened": i0["step_kernel_ms"],
             "n_fail": int(ttf.size), "ttf_mean_y": float(ttf.mean() / 3.15576e7) if ttf.size else None,
             "surrogate_ms": i1["surrogate_ms"],
+            "inference": {"rows": int(Xf.shape[0]), "ms": t_inf * 1e3, "mfma_tflops": flop_inf / t_inf / 1e12,
+                          "mfma_frac_of_bf16_peak": flop_inf / t_inf / 2.5e15},
             "training": {"pairs": n, "label_grids": args.sur_grids, "label_samples": args.sur_label_samples,
                          "label_s": t_label, "batch": batch, "steps": steps, "train_s": t_train,
                          "mfma_tflops": flop_step * steps / t_train / 1e12,

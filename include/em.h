@@ -313,7 +313,9 @@ em_status em_features(em_batch *b, float *X);
  * *n_deferred (may be NULL) is then their number, else 0. */
 em_status em_surrogate_screen(em_batch *b, em_mlp *mlp, double margin, int64_t *n_deferred);
 /* Model output y (log10 of the predicted nucleation time / 1e8 s) and the
- * deferred flags of one sample: [n_trees] host each, either may be NULL. */
+ * deferred flags of one sample: [n_trees] host each, either may be NULL.
+ * Only trees that were deferral candidates (steady-state mortal and active)
+ * are evaluated; y of the others is unspecified. */
 em_status em_get_surrogate(em_batch *b, int32_t sample, float *y_hat, uint8_t *deferred);
 /* Step of the first nucleation of every (sample, tree), -1 if none:
  * [n_samples][n_trees] host.  The nucleation time is (step + 1) x dt. */

@@ -39,6 +39,7 @@ struct em_batch {
     bool live_dirty = true;
     bool any_open = false;        // some segment of some sample has opened since creation/reset
     bool ir_valid = false;        // u, j, drop hold the solution for the current conductances
+    bool ir_unchanged = false;    // the last IR solve was skipped: currents as before
     uint8_t *live0 = nullptr;     // [n_nodes] reachability from the pads with every resistor conducting
     int cg_iters_last = 0;
     int n_outer_done = 0;
@@ -293,9 +294,11 @@ em_status ir_solve_impl(em_batch *b)
         HIPCHK(b, hipStreamSynchronize(st));
         if (*hg == 0) {
             b->cg_iters_last = 0;
+            b->ir_unchanged = true;
             return EM_OK;
         }
     }
+    b->ir_unchanged = false;
     if (b->live_dirty && !b->any_open && b->live0) {
         launch_ir_live_copy(d, b->live0, st);     // nothing open: the static reachability holds
         LAUNCHCHK(b);
@@ -431,10 +434,17 @@ em_status timed_ir(em_batch *b)
     return EM_OK;
 }
 
-// Device buffers of the learned screen and the per-tree static features.
+// Device buffers of the learned screen (the per-interval current-density
+// history for the catch-up replay included) and the per-tree static features.
 em_status sur_buffers(em_batch *b)
 {
     if (b->sur_ready) return EM_OK;
+    if (!b->trees_only) {
+        const int n_hist = (b->run.n_steps + b->run.ir_every - 1) / b->run.ir_every;
+        b->jhist = (double *)dalloc(b, 8 * (size_t)std::max(n_hist, 1) * b->S * b->n_res);
+        if (!b->jhist) return fail(b, EM_ERR_OOM, "current-density history");
+        b->n_hist = n_hist;
+    }
     Dev &d = b->d;
     const size_t IS = (size_t)d.n_trees * d.S;
     d.tstat = (double *)dalloc(b, 4 * 8 * (size_t)d.n_trees);
@@ -444,10 +454,11 @@ em_status sur_buffers(em_batch *b)
     d.deferred = (uint8_t *)dalloc(b, IS);
     d.catchup = (uint8_t *)dalloc(b, IS);
     d.def_list = (int *)dalloc(b, 4 * IS);
+    d.act_list = (int *)dalloc(b, 4 * IS);
     d.sur_cnt = (unsigned int *)dalloc(b, 32);
     b->sur_y = (float *)dalloc(b, 4 * IS);
     if (!d.tstat || !d.rdist || !d.feat || !d.yhat || !d.deferred || !d.catchup || !d.def_list ||
-        !d.sur_cnt || !b->sur_y)
+        !d.act_list || !d.sur_cnt || !b->sur_y)
         return fail(b, EM_ERR_OOM, "learned-screen buffers");
     launch_tree_static(d, b->stream);
     LAUNCHCHK(b);
@@ -458,21 +469,21 @@ em_status sur_buffers(em_batch *b)
 
 // Features of every (tree, sample) with the current densities: the screen's
 // steady stress is refreshed first (without changing the active set).
-em_status features_impl(em_batch *b, float *X)
+em_status features_impl(em_batch *b, float *X, bool screen_current = false, bool candidates_only = false)
 {
-    launch_screen(b->d, false, b->stream);
-    launch_features(b->d, X, b->stream);
+    if (!screen_current) launch_screen(b->d, false, b->stream);
+    launch_features(b->d, X, candidates_only, b->stream);
     LAUNCHCHK(b);
     return EM_OK;
 }
 
 // Evaluate the attached model and defer the mortal active instances predicted
 // to nucleate after thr; returns how many were deferred (synchronises).
-em_status sur_evaluate(em_batch *b, double thr, int64_t *n_def)
+em_status sur_evaluate(em_batch *b, double thr, int64_t *n_def, bool screen_current)
 {
     Dev &d = b->d;
     auto t0 = std::chrono::steady_clock::now();
-    em_status rc = features_impl(b, d.feat);
+    em_status rc = features_impl(b, d.feat, screen_current, true);
     if (rc != EM_OK) return rc;
     int irc = mlp_forward_async(b->sur, d.feat, d.n_trees * d.S, b->sur_y, b->stream);
     if (irc != EM_OK) return fail(b, (em_status)irc, "learned-screen model evaluation failed");
@@ -485,13 +496,25 @@ em_status sur_evaluate(em_batch *b, double thr, int64_t *n_def)
     HIPCHK(b, hipStreamSynchronize(b->stream));
     if (n_def) *n_def = h[0];
     b->n_def_list = (int)h[4];
+    if (b->n_def_list > 0) {
+        // the deferred list in instance order, so that the re-evaluations read
+        // the [node][sample] arrays of one tree's samples together
+        const size_t IS = (size_t)d.n_trees * d.S;
+        std::vector<uint8_t> df(IS);
+        HIPCHK(b, hipMemcpy(df.data(), d.deferred, IS, hipMemcpyDeviceToHost));
+        std::vector<int> lst;
+        lst.reserve(b->n_def_list);
+        for (size_t i = 0; i < IS; ++i) if (df[i]) lst.push_back((int)i);
+        b->n_def_list = (int)lst.size();
+        HIPCHK(b, hipMemcpy(d.def_list, lst.data(), 4 * lst.size(), hipMemcpyHostToDevice));
+    }
     b->sur_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return EM_OK;
 }
 
 // Replay the stored aging intervals 0..k-1 for the instances just activated
 // (catch-up from t = 0), then return them to the active set.
-em_status sur_catch_up(em_batch *b, int k)
+em_status sur_catch_up(em_batch *b, int k, int n_new)
 {
     Dev &d = b->d;
     const int K = b->run.ir_every;
@@ -499,12 +522,12 @@ em_status sur_catch_up(em_batch *b, int k)
     dr.inst_active = d.catchup;
     for (int i = 0; i < k; ++i) {
         dr.jseg = b->jhist + (size_t)i * d.S * d.n_res;
-        launch_update_f(dr, b->fp32, b->stream);
+        launch_update_f_list(dr, b->fp32, d.act_list, n_new, b->stream);
         LAUNCHCHK(b);
         em_status rc = timed_step_dev(b, dr, K, i * K);
         if (rc != EM_OK) return rc;
     }
-    launch_update_f(d, b->fp32, b->stream);
+    launch_update_f_list(d, b->fp32, d.act_list, n_new, b->stream);
     launch_catchup_done(d, k * K, b->stream);
     LAUNCHCHK(b);
     return EM_OK;
@@ -913,14 +936,8 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
         // interval are kept for the catch-up replay of later activations
         rc = sur_buffers(b);
         if (rc != EM_OK) return rc;
-        const int n_hist = (n_steps + K - 1) / K;
-        if (!b->jhist || b->n_hist < n_hist) {
-            b->jhist = (double *)dalloc(b, 8 * (size_t)n_hist * S * b->n_res);
-            if (!b->jhist) return fail(b, EM_ERR_OOM, "current-density history");
-            b->n_hist = n_hist;
-        }
         HIPCHK(b, hipMemsetAsync(d.deferred, 0, (size_t)b->n_trees * S, st));
-        rc = sur_evaluate(b, b->sur_margin * std::min(K, n_steps) * b->run.dt, nullptr);
+        rc = sur_evaluate(b, b->sur_margin * std::min(K, n_steps) * b->run.dt, nullptr, b->run.screen != 0);
         if (rc != EM_OK) return rc;
     }
     const size_t cnt_off = (std::max<size_t>(S, 8) + 15) & ~(size_t)15;
@@ -937,13 +954,14 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
                 // predictions of the deferred trees with the current densities
                 // (only ever brought forward), then activation of those due
                 const int nl = b->n_def_list;
-                if (nl > 0) {
+                if (nl > 0 && !b->ir_unchanged) {
                     launch_reeval_features(d, nl, d.feat, st);
                     LAUNCHCHK(b);
                     int irc = mlp_forward_async(b->sur, d.feat, nl, b->sur_y, st);
                     if (irc != EM_OK) return fail(b, (em_status)irc, "learned-screen model evaluation failed");
                     launch_yhat_min(d, nl, b->sur_y, st);
                 }
+                HIPCHK(b, hipMemsetAsync(d.sur_cnt + 5, 0, 4, st));
                 launch_activate(d, b->sur_margin * std::min(done + K, n_steps) * b->run.dt, st);
                 LAUNCHCHK(b);
             }
@@ -956,7 +974,7 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
         if (n_active == 0) break;
         if (sur && hcnt[1] != n_activated) {
             n_activated = hcnt[1];
-            rc = sur_catch_up(b, k);
+            rc = sur_catch_up(b, k, (int)hcnt[5]);
             if (rc != EM_OK) return rc;
             rc = sync_open_dirty(b);
             if (rc != EM_OK) return rc;
@@ -1229,7 +1247,7 @@ em_status em_features(em_batch *b, float *X)
     if (!b->have_j) return fail(b, EM_ERR_STATE, "no current densities yet (call em_ir_solve first)");
     em_status rc = sur_buffers(b);
     if (rc != EM_OK) return rc;
-    rc = features_impl(b, X);
+    rc = features_impl(b, X, false, false);
     if (rc != EM_OK) return rc;
     HIPCHK(b, hipStreamSynchronize(b->stream));
     return EM_OK;
@@ -1245,9 +1263,11 @@ em_status em_surrogate_screen(em_batch *b, em_mlp *mlp, double margin, int64_t *
     if (!mlp) return EM_OK;
     em_status rc = sur_buffers(b);
     if (rc != EM_OK) return rc;
+    if (mlp_reserve(mlp, b->n_trees * b->S) != EM_OK)     // model activations for every instance
+        return fail(b, EM_ERR_OOM, "learned-screen model buffers");
     if (b->have_j && b->step_counter == 0 && b->n_outer_done == 0) {
         const int K = std::min(b->run.ir_every, b->run.n_steps);
-        rc = sur_evaluate(b, margin * K * b->run.dt, n_deferred);
+        rc = sur_evaluate(b, margin * K * b->run.dt, n_deferred, false);
         if (rc != EM_OK) return rc;
     }
     return EM_OK;

@@ -109,7 +109,9 @@ struct Dev {
     float *yhat;                        // [inst] predicted log10(t_nuc / T_REF)
     uint8_t *deferred, *catchup;        // [inst]
     int *def_list;                      // [inst] instances deferred at t = 0 (in no particular order)
-    unsigned int *sur_cnt;              // [8] deferred, activated, late, violations, list length
+    int *act_list;                      // [inst] instances activated by the last activation check
+    unsigned int *sur_cnt;              // [8] deferred, activated, late, violations, def_list length,
+                                        //     act_list length
 };
 
 // Aggregation multigrid preconditioner of the IR solve.  Level 0 is the nodal
@@ -209,11 +211,12 @@ void launch_ttf_update(const Dev &d, double fail, int k, double t, hipStream_t s
 
 // learned screen
 void launch_tree_static(const Dev &d, hipStream_t st);                 // tstat, rdist
-void launch_features(const Dev &d, float *X, hipStream_t st);          // needs the screen's psi
+void launch_features(const Dev &d, float *X, bool candidates_only, hipStream_t st);   // needs psi
 void launch_reeval_features(const Dev &d, int n, float *X, hipStream_t st);   // def_list[0..n)
 void launch_yhat_min(const Dev &d, int n, const float *y, hipStream_t st);
 void launch_defer(const Dev &d, const float *y, double thr, hipStream_t st);
 void launch_activate(const Dev &d, double thr, hipStream_t st);
+void launch_update_f_list(const Dev &d, bool fp32, const int *list, int n, hipStream_t st);
 void launch_catchup_done(const Dev &d, int step_lim, hipStream_t st);
 
 }  // namespace em
@@ -223,4 +226,5 @@ void launch_catchup_done(const Dev &d, int step_lim, hipStream_t st);
 struct em_mlp;
 namespace em {
 int mlp_forward_async(em_mlp *m, const float *X, int n, float *y, hipStream_t st);
+int mlp_reserve(em_mlp *m, int n);        // activation buffers for n rows (allocates)
 }

@@ -312,6 +312,12 @@ em_status backward(em_mlp *m, const float *t, int n, float *loss)
 }  // namespace
 
 namespace em {
+int mlp_reserve(em_mlp *m, int n)
+{
+    if (!m || n <= 0) return EM_ERR_ARG;
+    return ensure_rows(m, n);
+}
+
 int mlp_forward_async(em_mlp *m, const float *X, int n, float *y, hipStream_t st)
 {
     if (!m || !X || !y || n <= 0) return EM_ERR_ARG;

@@ -195,16 +195,31 @@ __device__ inline double edge_phi(const Dev &d, int i, int s)
     return d.dir[i] * d.xi_k[(size_t)e * d.S + s] * d.gdx0[i] * (Sd + d.mdrv[i]);
 }
 
+__device__ inline double node_dtf(const Dev &d, int i, int s)
+{
+    double f = 0.0;
+    if (d.parent[i] >= 0) f += edge_phi(d, i, s);
+    for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k) f -= edge_phi(d, d.child[k], s);
+    return d.dt * f;
+}
+
 template <typename R>
 EM_KERNEL void k_update_f(Dev d)
 {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long long)d.ns * d.S) return;
     int s = (int)(g % d.S), i = (int)(g / d.S);
-    double f = 0.0;
-    if (d.parent[i] >= 0) f += edge_phi(d, i, s);
-    for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k) f -= edge_phi(d, d.child[k], s);
-    ((R *)d.dtf)[g] = (R)(d.dt * f);
+    ((R *)d.dtf)[g] = (R)node_dtf(d, i, s);
+}
+
+// dt*f of the nodes of the listed instances only (one block per instance)
+template <typename R>
+EM_KERNEL void k_update_f_list(Dev d, const int *list)
+{
+    const int inst = list[blockIdx.x];
+    const int t = inst / d.S, s = inst - t * d.S;
+    for (int i = d.tree_off[t] + threadIdx.x; i < d.tree_off[t + 1]; i += blockDim.x)
+        ((R *)d.dtf)[(size_t)i * d.S + s] = (R)node_dtf(d, i, s);
 }
 
 // ------------------------------------------------------------------------
@@ -288,49 +303,98 @@ EM_KERNEL void k_factor(Dev d)
 // A node is mortal iff its finite sigma_ss exceeds its critical stress;
 // segments through a mortal node and its tree are flagged.
 // ------------------------------------------------------------------------
-__device__ void steady_stress(const Dev &d, int t, int s)
+// The per-(tree, sample) passes below run one instance per 64-lane
+// wavefront, lanes over the tree's nodes in chunks of 64.
+__device__ inline double wsum(double v)
 {
-    const int S = d.S;
-    int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
-    double *psi = d.psi;
-    psi[(size_t)i0 * S + s] = 0.0;
-    double num = 0.0, den = d.V[i0];
-    for (int i = i0 + 1; i < i1; ++i) {
-        int p = d.parent[i], e = d.seg[i];
-        double dx = d.len[e] / d.N;
-        double j = d.jseg[(size_t)s * d.n_res + e];
-        double Sd = E_CHG * d.Z * d.rho * j / d.Omega;
-        double v = psi[(size_t)p * S + s] + d.dir[i] * dx * (Sd + d.mdrv[i]);
-        psi[(size_t)i * S + s] = v;
-        num += d.V[i] * v;
-        den += d.V[i];
-    }
-    double mean = num / den;
-    for (int i = i0; i < i1; ++i) psi[(size_t)i * S + s] = d.sigT + psi[(size_t)i * S + s] - mean;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline double wmax(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline double wmin(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
 }
 
+// psi_i = psi_parent + dir dx (S + M) from the root (pre-order: a parent
+// precedes its children).  Within a chunk the parent links are followed by
+// pointer jumping; a parent in an earlier chunk is the previous chunk's last
+// node (carried) or is read back.  Then sigma_ss = sigma_T + psi - <psi>_V.
+__device__ void steady_stress_wave(const Dev &d, int t, int s, int lane)
+{
+    const int S = d.S;
+    const int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
+    double *psi = d.psi;
+    double num = 0.0, den = 0.0, last = 0.0;
+    for (int c = i0; c < i1; c += 64) {
+        const int i = c + lane;
+        const bool ok = i < i1;
+        double v = 0.0;
+        int a = -1;
+        if (ok && i > i0) {
+            const int e = d.seg[i];
+            const double dx = d.len[e] / d.N;
+            const double Sd = E_CHG * d.Z * d.rho * d.jseg[(size_t)s * d.n_res + e] / d.Omega;
+            v = d.dir[i] * dx * (Sd + d.mdrv[i]);
+            a = d.parent[i];
+        }
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            const bool in = a >= c;
+            const int src = in ? a - c : lane;
+            const double vo = __shfl(v, src, 64);
+            const int ao = __shfl(a, src, 64);
+            if (in) { v += vo; a = ao; }
+        }
+        if (a >= 0) v += (a == c - 1) ? last : psi[(size_t)a * S + s];
+        if (ok) {
+            psi[(size_t)i * S + s] = v;
+            num += d.V[i] * v;
+            den += d.V[i];
+        }
+        last = __shfl(v, 63, 64);
+        __threadfence_block();
+    }
+    const double mean = wsum(num) / wsum(den);
+    for (int i = i0 + lane; i < i1; i += 64) psi[(size_t)i * S + s] = d.sigT + psi[(size_t)i * S + s] - mean;
+}
+
+// Steady-state immortality screen of one instance per wavefront.
 EM_KERNEL void k_screen(Dev d, int apply)
 {
-    int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int slot = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (slot >= d.n_trees * d.S) return;
     int t, s;
-    int inst = inst_of_slot(d, slot, t, s);
+    const int inst = inst_of_slot(d, slot, t, s);
     const int S = d.S;
-    steady_stress(d, t, s);
-    int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
-    int mortal = 0;
+    steady_stress_wave(d, t, s, lane);
+    const int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
     uint8_t *sm = d.seg_mortal + (size_t)s * d.n_res;
-    for (int k = d.tseg_off[t]; k < d.tseg_off[t + 1]; ++k) sm[d.tseg[k]] = 0;
-    for (int i = i0; i < i1; ++i) {
+    for (int k = d.tseg_off[t] + lane; k < d.tseg_off[t + 1]; k += 64) sm[d.tseg[k]] = 0;
+    __threadfence_block();
+    bool mortal = false;
+    for (int i = i0 + lane; i < i1; i += 64) {
         double v = d.psi[(size_t)i * S + s];
         if (isfinite(v) && v > node_scrit(d, i, s)) {
-            mortal = 1;
+            mortal = true;
             if (d.parent[i] >= 0) sm[d.seg[i]] = 1;
             for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k) sm[d.seg[d.child[k]]] = 1;
         }
     }
-    d.tree_mortal[inst] = (uint8_t)mortal;
-    if (apply) d.inst_active[inst] = (uint8_t)mortal;
+    const bool any = __any(mortal);
+    if (lane == 0) {
+        d.tree_mortal[inst] = any ? 1 : 0;
+        if (apply) d.inst_active[inst] = any ? 1 : 0;
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -624,15 +688,16 @@ EM_KERNEL void k_tree_static(Dev d)
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= d.n_trees) return;
     int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
-    double lpath = 0.0, nj = 0.0;
+    double lpath = 0.0, nj = 0.0, prev = 0.0;
     d.rdist[i0] = 0.0;
     for (int i = i0; i < i1; ++i) {
         int p = d.parent[i];
         int deg = (p >= 0 ? 1 : 0) + (d.child_off[i + 1] - d.child_off[i]);
         nj += deg >= 3 ? 1.0 : 0.0;
         if (p >= 0) {
-            double r = d.rdist[p] + d.len[d.seg[i]] / d.N;
+            double r = ((p == i - 1) ? prev : d.rdist[p]) + d.len[d.seg[i]] / d.N;
             d.rdist[i] = r;
+            prev = r;
             lpath = fmax(lpath, r);
         }
     }
@@ -651,42 +716,57 @@ __device__ inline double kappa_arrhenius(const Dev &d, double T)
     return d.D0 * exp(-d.Ea_eV * E_CHG / kT) * d.B * d.Omega / kT;
 }
 
-__device__ void features_of(const Dev &d, int t, int s, float *x)
+// Features of one instance by a wavefront (the screen's steady stress must
+// be current); lane 0 writes the 12 values.
+__device__ void features_wave(const Dev &d, int t, int s, int lane, float *x)
 {
     const int S = d.S;
     const double *ts = d.tstat + (size_t)t * 4;
     double jmax = 0.0, jl = 0.0;
-    for (int k = d.tseg_off[t]; k < d.tseg_off[t + 1]; ++k) {
+    for (int k = d.tseg_off[t] + lane; k < d.tseg_off[t + 1]; k += 64) {
         int e = d.tseg[k];
         double j = fabs(d.jseg[(size_t)s * d.n_res + e]);
         jmax = fmax(jmax, j);
         jl += d.len[e] * j;
     }
+    jmax = wmax(jmax);
+    jl = wsum(jl);
     // edge (parent(i), i): Arrhenius diffusivity at the midpoint temperature
     auto edge_kappa = [&](int i) {
         return d.xi_k[(size_t)d.seg[i] * S + s] * kappa_arrhenius(d, 0.5 * (d.T[i] + d.T[d.parent[i]]));
     };
-    int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
-    double ksum = 0.0, r = -INFINITY;
-    int ne = 0, pk = -1;
-    for (int i = i0; i < i1; ++i) {
+    const int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
+    double ksum = 0.0, ne = 0.0, r = -INFINITY;
+    int pk = 0x7fffffff;
+    for (int i = i0 + lane; i < i1; i += 64) {
         if (d.parent[i] >= 0) {
             ksum += edge_kappa(i);
-            ++ne;
+            ne += 1.0;
         }
         double ss = d.psi[(size_t)i * S + s];
         if (isfinite(ss)) {
             double q = ss / node_scrit(d, i, s);
-            if (q > r) { r = q; pk = i; }
+            if (q > r) { r = q; pk = i; }          // lanes visit ascending nodes: first max
         }
     }
-    if (pk < 0) { pk = i0; r = -10.0; }
+    ksum = wsum(ksum);
+    ne = wsum(ne);
+    // peak: largest ratio, lowest node on ties
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ro = __shfl_xor(r, o, 64);
+        const int po = __shfl_xor(pk, o, 64);
+        if (ro > r || (ro == r && po < pk)) { r = ro; pk = po; }
+    }
+    if (pk == 0x7fffffff) { pk = i0; r = -10.0; }
     r = fmin(fmax(r, -10.0), 10.0);
     // distance from the peak to the nearest node at or below sigma_T
     double lpk = INFINITY;
     const double dp = d.rdist[pk];
-    for (int i = i0; i < i1; ++i)
+    for (int i = i0 + lane; i < i1; i += 64)
         if (d.psi[(size_t)i * S + s] <= d.sigT) lpk = fmin(lpk, fabs(d.rdist[i] - dp));
+    lpk = wmin(lpk);
+    if (lane != 0) return;
     if (!isfinite(lpk)) lpk = ts[1];
     lpk = fmax(lpk, 1e-7);
     double kp = 0.0;
@@ -710,26 +790,31 @@ __device__ void features_of(const Dev &d, int t, int s, float *x)
     x[11] = (float)((d.T[pk] - 300.0) / 100.0);
 }
 
-EM_KERNEL void k_features(Dev d, float *X)
+// every instance, or only those a deferral could apply to (mortal, and
+// active or already deferred); one instance per wavefront
+EM_KERNEL void k_features(Dev d, float *X, int candidates_only)
 {
-    int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int slot = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (slot >= d.n_trees * d.S) return;
     int t, s;
     int inst = inst_of_slot(d, slot, t, s);
-    features_of(d, t, s, X + (size_t)inst * NFEAT);
+    if (candidates_only && !(d.tree_mortal[inst] && (d.inst_active[inst] || d.deferred[inst]))) return;
+    features_wave(d, t, s, lane, X + (size_t)inst * NFEAT);
 }
 
 // Features of the still-deferred instances of def_list[0..n) with the current
 // densities (their steady stress is refreshed first), row k for def_list[k].
 EM_KERNEL void k_reeval_features(Dev d, int n, float *X)
 {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (k >= n) return;
     int inst = d.def_list[k];
     if (!d.deferred[inst]) return;
     int t = inst / d.S, s = inst - (inst / d.S) * d.S;
-    steady_stress(d, t, s);
-    features_of(d, t, s, X + (size_t)k * NFEAT);
+    steady_stress_wave(d, t, s, lane);
+    features_wave(d, t, s, lane, X + (size_t)k * NFEAT);
 }
 
 // A re-evaluated prediction can only bring a deferred instance's activation forward.
@@ -762,7 +847,8 @@ EM_KERNEL void k_defer(Dev d, const float *y, double thr)
     d.deferred[inst] = df;
 }
 
-// Mark deferred instances of running samples whose prediction falls due by thr.
+// Mark deferred instances of running samples whose prediction falls due by
+// thr and list them (sur_cnt[5] counts this activation's list).
 EM_KERNEL void k_activate(Dev d, double thr)
 {
     int inst = blockIdx.x * blockDim.x + threadIdx.x;
@@ -772,6 +858,7 @@ EM_KERNEL void k_activate(Dev d, double thr)
         d.deferred[inst] = 0;
         d.catchup[inst] = 1;
         atomicAdd(&d.sur_cnt[1], 1u);
+        d.act_list[atomicAdd(&d.sur_cnt[5], 1u)] = inst;
     }
 }
 
@@ -835,7 +922,7 @@ void launch_factor(const Dev &d, bool fp32, hipStream_t st)
 }
 void launch_screen(const Dev &d, bool apply, hipStream_t st)
 {
-    k_screen<<<nblocks(d.n_trees * d.S), 256, 0, st>>>(d, apply ? 1 : 0);
+    k_screen<<<nblocks((long long)d.n_trees * d.S, 4), 256, 0, st>>>(d, apply ? 1 : 0);
 }
 void launch_step(const Dev &d, bool fp32, int n_steps, int step0, hipStream_t st)
 {
@@ -874,13 +961,13 @@ void launch_tree_static(const Dev &d, hipStream_t st)
 {
     k_tree_static<<<nblocks(d.n_trees), 256, 0, st>>>(d);
 }
-void launch_features(const Dev &d, float *X, hipStream_t st)
+void launch_features(const Dev &d, float *X, bool candidates_only, hipStream_t st)
 {
-    k_features<<<nblocks(d.n_trees * d.S), 256, 0, st>>>(d, X);
+    k_features<<<nblocks((long long)d.n_trees * d.S, 4), 256, 0, st>>>(d, X, candidates_only ? 1 : 0);
 }
 void launch_reeval_features(const Dev &d, int n, float *X, hipStream_t st)
 {
-    k_reeval_features<<<nblocks(n), 256, 0, st>>>(d, n, X);
+    k_reeval_features<<<nblocks(n, 4), 256, 0, st>>>(d, n, X);
 }
 void launch_yhat_min(const Dev &d, int n, const float *y, hipStream_t st)
 {
@@ -889,6 +976,12 @@ void launch_yhat_min(const Dev &d, int n, const float *y, hipStream_t st)
 void launch_defer(const Dev &d, const float *y, double thr, hipStream_t st)
 {
     k_defer<<<nblocks(d.n_trees * d.S), 256, 0, st>>>(d, y, thr);
+}
+void launch_update_f_list(const Dev &d, bool fp32, const int *list, int n, hipStream_t st)
+{
+    if (n <= 0) return;
+    if (fp32) k_update_f_list<float><<<n, 256, 0, st>>>(d, list);
+    else k_update_f_list<double><<<n, 256, 0, st>>>(d, list);
 }
 void launch_activate(const Dev &d, double thr, hipStream_t st)
 {
