@@ -105,3 +105,16 @@ def train(mlp: MLP, X, y, steps: int, batch: int = 4096, lr: float = 1e-3, seed:
                                   want_loss=(k == steps - 1))
             k += 1
     return loss
+
+
+def calibrate(mlp: MLP, Xv, yv, quantile: float = 0.995) -> float:
+    """Shift the output bias so that the predicted nucleation time is at most
+    the label on a ``quantile`` fraction of held-out pairs: the screen then
+    errs towards activating trees early.  Returns the shift (decades)."""
+    pred = mlp.forward(Xv).cpu().numpy().astype(np.float64)
+    err = pred - yv.cpu().numpy().astype(np.float64)
+    shift = float(np.quantile(err, quantile))
+    p = mlp.params()
+    p[-1] -= shift
+    mlp.set_params(p)
+    return shift
