@@ -9,6 +9,7 @@
 #include "em_internal.h"
 #include "../../include/em.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -49,62 +50,130 @@ struct GemmArgs {
     int M, N, K, ldc;
 };
 
-// C[MxN] = A[MxK] B[KxN]: 64x64 tile per 256-thread block, four waves of one
-// 32x32x16 BF16 MFMA sub-tile each.  Operand layout of the 32x32x16 MFMA:
-// lane l supplies A[l%32][8*(l/32) .. +7] and B[8*(l/32) .. +7][l%32]; the 16
-// accumulator registers of lane l hold C[8*(r/4) + 4*(l/32) + r%4][l%32].
-template <int EPI>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
+// C[MxN] = A[MxK] B[KxN] on BF16 matrix cores.  A 256-thread block computes
+// a 128x128 tile, each of its four waves a 64x64 quarter as 2x2 sub-tiles of
+// the 32x32x16 BF16 MFMA, over K in steps of 32 staged through LDS (k
+// contiguous, so every lane reads its 8 operand values with one 16-byte
+// load).  Operand layout of the 32x32x16 MFMA: lane l supplies
+// A[l%32][8*(l/32) .. +7] and B[8*(l/32) .. +7][l%32]; the 16 accumulator
+// registers of lane l hold C[8*(r/4) + 4*(l/32) + r%4][l%32].  Blocks along
+// grid z split K (partial tiles to a workspace, summed in a fixed order by
+// k_splitk_sum) when the output is small and K long.
+constexpr int TB = 128, BK = 32, LDK = BK + 8;
+
+// Stage rows [r0, r0+128) x k [k0, k0+32) of a strided FP32 operand, element
+// (r, k) at P[r*sr + k*sk], into T[row][k] as BF16 (zero outside R x K).
+__device__ inline void stage_tile(__bf16 (*T)[LDK], const float *P, long long sr, long long sk, int r0, int R,
+                                  int k0, int K, int tid)
 {
-    __shared__ __bf16 As[64][16 + 8];
-    __shared__ __bf16 Bs[16][64 + 8];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-    const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
-    f32x16 acc;
+    if (sk == 1) {
+        const int r = tid >> 1, kk = (tid & 1) * 16;
+        const int gr = r0 + r, gk = k0 + kk;
+        const float *src = P + (long long)gr * sr + gk;
+        if (gr < R && gk + 16 <= K && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-    for (int k0 = 0; k0 < g.K; k0 += 16) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int idx = tid * 4 + e;
-            const int ar = idx >> 4, ac = idx & 15;
-            const int gm = m0 + ar, gk = k0 + ac;
-            float av = (gm < g.M && gk < g.K) ? g.A[(long long)gm * g.sam + (long long)gk * g.sak] : 0.0f;
-            As[ar][ac] = to_bf16(av);
-            const int br = idx >> 6, bc = idx & 63;
-            const int gk2 = k0 + br, gn = n0 + bc;
-            float bv = (gk2 < g.K && gn < g.N) ? g.B[(long long)gk2 * g.sbk + (long long)gn * g.sbn] : 0.0f;
-            Bs[br][bc] = to_bf16(bv);
-        }
-        __syncthreads();
-        bf16x8 a, b;
-        const int kb = 8 * (lane >> 5);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            a[e] = As[wm + (lane & 31)][kb + e];
-            b[e] = Bs[kb + e][wn + (lane & 31)];
-        }
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-        __syncthreads();
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int row = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int col = n0 + wn + (lane & 31);
-        if (row >= g.M || col >= g.N) continue;
-        const long long o = (long long)row * g.ldc + col;
-        float v = acc[r];
-        if (EPI == EPI_BIAS_GELU) {
-            v += g.bias[col];
-            g.C[o] = v;
-            g.H[o] = gelu(v);
-        } else if (EPI == EPI_GELU_BWD) {
-            g.C[o] = v * gelu_d(g.Z[o]);
+            for (int q = 0; q < 4; ++q) {
+                const float4 v = reinterpret_cast<const float4 *>(src)[q];
+                T[r][kk + 4 * q + 0] = to_bf16(v.x); T[r][kk + 4 * q + 1] = to_bf16(v.y);
+                T[r][kk + 4 * q + 2] = to_bf16(v.z); T[r][kk + 4 * q + 3] = to_bf16(v.w);
+            }
         } else {
-            g.C[o] = v;
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                T[r][kk + e] = to_bf16((gr < R && gk + e < K) ? P[(long long)gr * sr + gk + e] : 0.0f);
+        }
+    } else {
+        const int kk = tid >> 3, rr = (tid & 7) * 16;
+        const int gk = k0 + kk, gr = r0 + rr;
+        const float *src = P + (long long)gr * sr + (long long)gk * sk;
+        if (sr == 1 && gk < K && gr + 16 <= R && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 v = reinterpret_cast<const float4 *>(src)[q];
+                T[rr + 4 * q + 0][kk] = to_bf16(v.x); T[rr + 4 * q + 1][kk] = to_bf16(v.y);
+                T[rr + 4 * q + 2][kk] = to_bf16(v.z); T[rr + 4 * q + 3][kk] = to_bf16(v.w);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                T[rr + e][kk] = to_bf16((gk < K && gr + e < R) ? P[(long long)(gr + e) * sr + (long long)gk * sk]
+                                                               : 0.0f);
         }
     }
+}
+
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, float *ws, int kchunk)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 As[TB][LDK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[TB][LDK];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m0 = blockIdx.y * TB, n0 = blockIdx.x * TB;
+    const int wm = (wv >> 1) * 64, wn = (wv & 1) * 64;
+    const int kbeg = blockIdx.z * kchunk, kend = min(g.K, kbeg + kchunk);
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        stage_tile(As, g.A, g.sam, g.sak, m0, g.M, k0, kend, tid);
+        stage_tile(Bs, g.B, g.sbn, g.sbk, n0, g.N, k0, kend, tid);
+        __syncthreads();
+#pragma unroll
+        for (int kc = 0; kc < BK; kc += 16) {
+            const int kb = kc + 8 * (lane >> 5);
+            bf16x8 a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                a[i] = *reinterpret_cast<const bf16x8 *>(&As[wm + 32 * i + (lane & 31)][kb]);
+                b[i] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + 32 * i + (lane & 31)][kb]);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int col = n0 + wn + 32 * j + (lane & 31);
+                if (row >= g.M || col >= g.N) continue;
+                float v = acc[i][j][r];
+                if (ws) {                                   // split-K partial
+                    ws[((size_t)blockIdx.z * g.M + row) * g.N + col] = v;
+                    continue;
+                }
+                const long long o = (long long)row * g.ldc + col;
+                if (EPI == EPI_BIAS_GELU) {
+                    v += g.bias[col];
+                    g.C[o] = v;
+                    g.H[o] = gelu(v);
+                } else if (EPI == EPI_GELU_BWD) {
+                    g.C[o] = v * gelu_d(g.Z[o]);
+                } else {
+                    g.C[o] = v;
+                }
+            }
+}
+
+// C = sum over the splits of the workspace partials (fixed order)
+__global__ __launch_bounds__(256) void k_splitk_sum(const float *ws, int splits, float *C, int M, int N, int ldc)
+{
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (long long)M * N) return;
+    float acc = 0.0f;
+    for (int z = 0; z < splits; ++z) acc += ws[(size_t)z * M * N + i];
+    C[(i / N) * ldc + (i % N)] = acc;
 }
 
 // y = H3 w4 + b4, one wave per row (fixed summation order)
@@ -195,6 +264,7 @@ struct em_mlp {
     float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;   // [NPARAM]
     float *W1p = nullptr;      // [HID][KF] padded first layer (rebuilt from p before use)
     float *gW1p = nullptr;
+    float *ws = nullptr;       // split-K partials of the weight gradients [32][HID][HID]
     int cap = 0;               // rows allocated
     float *Xp = nullptr, *Z1 = nullptr, *H1 = nullptr, *Z2 = nullptr, *H2 = nullptr, *Z3 = nullptr, *H3 = nullptr;
     float *y = nullptr, *dy = nullptr, *dZ3 = nullptr, *dZ2 = nullptr, *dZ1 = nullptr, *part = nullptr;
@@ -249,17 +319,28 @@ em_status ensure_rows(em_mlp *m, int n)
     return EM_OK;
 }
 
-void gemm(int epi, const float *A, long long sam, long long sak, const float *B, long long sbk, long long sbn,
-          float *C, int ldc, int M, int N, int K, const float *bias, float *H, const float *Z, hipStream_t st)
+constexpr int SPLITK_MAX = 32;
+
+void gemm(em_mlp *m, int epi, const float *A, long long sam, long long sak, const float *B, long long sbk,
+          long long sbn, float *C, int ldc, int M, int N, int K, const float *bias, float *H, const float *Z,
+          hipStream_t st)
 {
     GemmArgs g;
     g.A = A; g.B = B; g.C = C; g.H = H; g.bias = bias; g.Z = Z;
     g.sam = sam; g.sak = sak; g.sbk = sbk; g.sbn = sbn;
     g.M = M; g.N = N; g.K = K; g.ldc = ldc;
-    dim3 grid(cdiv(N, 64), cdiv(M, 64));
-    if (epi == EPI_BIAS_GELU) k_gemm_bf16<EPI_BIAS_GELU><<<grid, 256, 0, st>>>(g);
-    else if (epi == EPI_GELU_BWD) k_gemm_bf16<EPI_GELU_BWD><<<grid, 256, 0, st>>>(g);
-    else k_gemm_bf16<EPI_STORE><<<grid, 256, 0, st>>>(g);
+    const int tiles = cdiv(N, TB) * cdiv(M, TB);
+    int splits = 1;
+    if (epi == EPI_STORE && tiles < 64 && K >= 2048 && (long long)M * N <= (long long)HID * HID)
+        splits = std::min(SPLITK_MAX, K / 1024);
+    const int kchunk = splits > 1 ? ((K + splits - 1) / splits + BK - 1) / BK * BK : K;
+    splits = (K + kchunk - 1) / kchunk;
+    dim3 grid(cdiv(N, TB), cdiv(M, TB), splits);
+    float *ws = splits > 1 ? m->ws : nullptr;
+    if (epi == EPI_BIAS_GELU) k_gemm_bf16<EPI_BIAS_GELU><<<grid, 256, 0, st>>>(g, nullptr, kchunk);
+    else if (epi == EPI_GELU_BWD) k_gemm_bf16<EPI_GELU_BWD><<<grid, 256, 0, st>>>(g, nullptr, kchunk);
+    else k_gemm_bf16<EPI_STORE><<<grid, 256, 0, st>>>(g, ws, kchunk);
+    if (ws) k_splitk_sum<<<cdiv((long long)M * N, 256), 256, 0, st>>>(ws, splits, C, M, N, ldc);
 }
 
 // forward pass into the activation buffers (X: device [n][12])
@@ -268,9 +349,9 @@ void forward(em_mlp *m, const float *X, int n, hipStream_t st)
     k_pad_x<<<cdiv((long long)n * KF, 256), 256, 0, st>>>(X, m->Xp, n);
     k_w1_pad<<<cdiv(HID * KF, 256), 256, 0, st>>>(m->p, m->W1p);
     // Z1 = X W1^T + b1 : B(k, n) = W1p[n][k]
-    gemm(EPI_BIAS_GELU, m->Xp, KF, 1, m->W1p, 1, KF, m->Z1, HID, n, HID, KF, m->p + OB1, m->H1, nullptr, st);
-    gemm(EPI_BIAS_GELU, m->H1, HID, 1, m->p + OW2, 1, HID, m->Z2, HID, n, HID, HID, m->p + OB2, m->H2, nullptr, st);
-    gemm(EPI_BIAS_GELU, m->H2, HID, 1, m->p + OW3, 1, HID, m->Z3, HID, n, HID, HID, m->p + OB3, m->H3, nullptr, st);
+    gemm(m, EPI_BIAS_GELU, m->Xp, KF, 1, m->W1p, 1, KF, m->Z1, HID, n, HID, KF, m->p + OB1, m->H1, nullptr, st);
+    gemm(m, EPI_BIAS_GELU, m->H1, HID, 1, m->p + OW2, 1, HID, m->Z2, HID, n, HID, HID, m->p + OB2, m->H2, nullptr, st);
+    gemm(m, EPI_BIAS_GELU, m->H2, HID, 1, m->p + OW3, 1, HID, m->Z3, HID, n, HID, HID, m->p + OB3, m->H3, nullptr, st);
     k_out<<<cdiv(n, 4), 256, 0, st>>>(m->H3, m->p + OW4, m->p + OB4, m->y, n);
 }
 
@@ -286,15 +367,15 @@ em_status backward(em_mlp *m, const float *t, int n, float *loss)
     k_colsum<<<1, 256, 0, st>>>(m->dy, nullptr, m->g + OB4, n, 1, 1);
     k_out_bwd<<<cdiv((long long)n * HID, 256), 256, 0, st>>>(m->dy, m->p + OW4, m->Z3, m->dZ3, n);
     // layer 3: dW3[o][i] = sum_r dZ3[r][o] H2[r][i]  (A(m=o,k=r) = dZ3[r][o])
-    gemm(EPI_STORE, m->dZ3, 1, HID, m->H2, HID, 1, m->g + OW3, HID, HID, HID, n, nullptr, nullptr, nullptr, st);
+    gemm(m, EPI_STORE, m->dZ3, 1, HID, m->H2, HID, 1, m->g + OW3, HID, HID, HID, n, nullptr, nullptr, nullptr, st);
     k_colsum<<<HID, 256, 0, st>>>(m->dZ3, nullptr, m->g + OB3, n, HID, HID);
     // dZ2 = (dZ3 W3) * gelu'(Z2) : B(k=o, n=i) = W3[o][i]
-    gemm(EPI_GELU_BWD, m->dZ3, HID, 1, m->p + OW3, HID, 1, m->dZ2, HID, n, HID, HID, nullptr, nullptr, m->Z2, st);
-    gemm(EPI_STORE, m->dZ2, 1, HID, m->H1, HID, 1, m->g + OW2, HID, HID, HID, n, nullptr, nullptr, nullptr, st);
+    gemm(m, EPI_GELU_BWD, m->dZ3, HID, 1, m->p + OW3, HID, 1, m->dZ2, HID, n, HID, HID, nullptr, nullptr, m->Z2, st);
+    gemm(m, EPI_STORE, m->dZ2, 1, HID, m->H1, HID, 1, m->g + OW2, HID, HID, HID, n, nullptr, nullptr, nullptr, st);
     k_colsum<<<HID, 256, 0, st>>>(m->dZ2, nullptr, m->g + OB2, n, HID, HID);
-    gemm(EPI_GELU_BWD, m->dZ2, HID, 1, m->p + OW2, HID, 1, m->dZ1, HID, n, HID, HID, nullptr, nullptr, m->Z1, st);
+    gemm(m, EPI_GELU_BWD, m->dZ2, HID, 1, m->p + OW2, HID, 1, m->dZ1, HID, n, HID, HID, nullptr, nullptr, m->Z1, st);
     // dW1[o][c] = sum_r dZ1[r][o] X[r][c]
-    gemm(EPI_STORE, m->dZ1, 1, HID, m->Xp, KF, 1, m->gW1p, KF, HID, KF, n, nullptr, nullptr, nullptr, st);
+    gemm(m, EPI_STORE, m->dZ1, 1, HID, m->Xp, KF, 1, m->gW1p, KF, HID, KF, n, nullptr, nullptr, nullptr, st);
     k_w1_unpad<<<cdiv(HID * NF, 256), 256, 0, st>>>(m->gW1p, m->g);
     k_colsum<<<HID, 256, 0, st>>>(m->dZ1, nullptr, m->g + OB1, n, HID, HID);
     MCHK(m, hipGetLastError());
@@ -345,6 +426,7 @@ em_status em_mlp_create(void *hip_stream, em_mlp **out)
         MCHK(m, hipMemsetAsync(*b, 0, sizeof(float) * NPARAM, m->stream));
     }
     MCHK(m, hipMalloc((void **)&m->W1p, sizeof(float) * HID * KF));
+    MCHK(m, hipMalloc((void **)&m->ws, sizeof(float) * 32 * HID * HID));
     MCHK(m, hipMalloc((void **)&m->gW1p, sizeof(float) * HID * KF));
     MCHK(m, hipStreamSynchronize(m->stream));
     return EM_OK;
@@ -354,7 +436,7 @@ em_status em_mlp_destroy(em_mlp *m)
 {
     if (!m) return EM_OK;
     (void)hipStreamSynchronize(m->stream);
-    float *bufs[] = {m->p, m->g, m->m, m->v, m->W1p, m->gW1p, m->Xp, m->Z1, m->H1, m->Z2, m->H2, m->Z3, m->H3,
+    float *bufs[] = {m->p, m->g, m->m, m->v, m->W1p, m->gW1p, m->ws, m->Xp, m->Z1, m->H1, m->Z2, m->H2, m->Z3, m->H3,
                      m->y, m->dy, m->dZ3, m->dZ2, m->dZ1, m->part};
     for (float *b : bufs)
         if (b) (void)hipFree(b);
