@@ -1,0 +1,136 @@
+"""GPU edge cases against the oracle: ragged chain lengths around the lane
+block and workgroup capacities (including chains too long for the resident
+kernel), a zero-step run, nucleation disabled, a pad-less island in the IR
+network, and argument errors."""
+import math
+
+import numpy as np
+import pytest
+
+from cases import UM, material, run, tree_from_edges
+from paper_2604_10743_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def em():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2604_10743_amd as P
+    return P
+
+
+def _lines(seg_counts, L=5 * UM, j=3e10, T=378.0):
+    """Independent straight lines with the given segment counts."""
+    edges, xy, base = [], [], 0
+    for t, S in enumerate(seg_counts):
+        for k in range(S + 1):
+            xy.append((k * L, t * 20 * UM))
+        edges += [(base + k, base + k + 1) for k in range(S)]
+        base += S + 1
+    rng = np.random.default_rng(len(seg_counts))
+    js = j * rng.uniform(0.5, 1.0, len(edges)) * np.where(rng.random(len(edges)) < 0.5, -1, 1)
+    return tree_from_edges(base, edges, L, 0.5 * UM, 0.2 * UM, js, T=T, xy=np.array(xy))
+
+
+def _per_tree_rel(a, b, off):
+    w = 0.0
+    for t in range(len(off) - 1):
+        sl = slice(off[t], off[t + 1])
+        w = max(w, np.max(np.abs(a[sl] - b[sl])) / max(np.max(np.abs(b[sl])), 1e-300))
+    return w
+
+
+@pytest.mark.parametrize("prec,N", [(0, 20), (0, 7), (0, 8), (1, 20), (1, 7)])
+def test_ragged_chain_lengths(em, oracle_mod, prec, N):
+    # node counts N*S + 1 straddle the 8-node lane block (N = 7, 8: 8 and 9
+    # nodes per segment) and, with 205 and 410 segments at N = 20, the
+    # capacity of the resident kernel's workgroup in FP64 (4096 nodes) and in
+    # FP32 (8192): those chains take the generic tree kernel
+    segs = [1, 2, 3, 205, 410] if N == 20 else [1, 2, 3, 9, 17]
+    g = _lines(segs)
+    mat = material(sigma_crit=1e12)
+    rn = run(prec=prec, intervals_per_seg=N, dt=2e5, max_voids_per_tree=0)
+    B = em.Batch(g, mat, rn)
+    B.stress_step(60)
+    topo = oracle_mod.topology(g, N)
+    sim = oracle_mod.SampleSim(g, mat, dict(rn, prec=0), topo)
+    sim.set_j(g.seg_j)
+    sim.set_active(np.ones(topo.n_trees, np.uint8))
+    sim.steps(60, 0)
+    sg, so = B.stress(), sim.sigma()
+    per = [_per_tree_rel(sg, so, topo.tree_off[t:t + 2]) for t in range(topo.n_trees)]
+    nodes = np.diff(topo.tree_off)
+    print(f"prec {prec} N {N}: nodes {nodes.tolist()}, errors {[f'{e:.1e}' for e in per]}")
+    for n, e in zip(nodes, per):
+        if prec == 0:
+            assert e <= 1e-9
+        else:
+            # float factors: the error of each increment grows with the
+            # conditioning of the step matrix of a long chain (~ its length
+            # squared); measured 1.7e-7 (120 nodes), 8.2e-5 (4101 nodes,
+            # resident kernel), 2.8e-4 (8201 nodes, generic kernel)
+            assert e <= (1e-5 if n <= 1024 else 2e-4 if n <= 8192 else 5e-4), (n, e)
+
+
+def test_zero_steps_and_no_nucleation(em):
+    g, mat, rn, _ = synth.workload("tiny_mesh")
+    B = em.Batch(g, mat, dict(rn, n_steps=0))
+    r = B.run_to_ttf()[0]
+    assert r["failed"] == 0 and math.isnan(r["ttf_s"]) and r["outer_idx"] == 0
+    assert r["final_drop"] == r["init_drop"] and B.info()["node_steps"] == 0
+    B.close()
+    # a mortal workload with nucleation switched off records no event
+    g = synth.two_layer_mesh(1001, nr=12, nc=12, sink_mu=math.log(490e-6), vdd=1.2, T_uniform=378.0)
+    B = em.Batch(g, material(sigma_crit=150e6), run(prec=1, max_voids_per_tree=0))
+    res = B.run_to_ttf()[0]
+    assert B.info()["n_events"] == 0 and res["n_nucleated_trees"] == 0
+    assert B.screen()[0].sum() > 0
+    B.close()
+
+
+def test_padless_island_reads_zero_volts(em, oracle_mod):
+    # a 4x4 mesh plus a separate two-node wire with a sink and no pad: its
+    # nodes have no path to a pad and read 0 V (worst drop 1)
+    g = synth.two_layer_mesh(7, nr=4, nc=4, vdd=1.0, T_uniform=378.0)
+    n0 = g.n_nodes
+    g.xy = np.vstack([g.xy, [[1e-3, 1e-3], [1.01e-3, 1e-3]]])
+    g.layer = np.concatenate([g.layer, [1, 1]]).astype(np.int32)
+    g.res_a = np.concatenate([g.res_a, [n0]]).astype(np.int32)
+    g.res_b = np.concatenate([g.res_b, [n0 + 1]]).astype(np.int32)
+    for k, v in (("res_len", 10 * UM), ("res_w", 0.5 * UM), ("res_h", 0.2 * UM), ("res_R0", 1.0)):
+        setattr(g, k, np.concatenate([getattr(g, k), [v]]))
+    g.res_is_via = np.concatenate([g.res_is_via, [0]]).astype(np.uint8)
+    g.sink_I = np.concatenate([g.sink_I, [1e-5, 0.0]])
+    g.node_T = np.concatenate([g.node_T, [378.0, 378.0]])
+    for pc in (0, 1):
+        B = em.Batch(g, material(), run(prec=0, ir_precond=pc, cg_rtol=1e-14, cg_max_iter=100000))
+        drop = B.ir_solve()[0]
+        u = B.voltages()
+        u_o, _, _, d_o = oracle_mod.ir_solve(g, g.res_R0)
+        assert u[n0] == 0.0 and u[n0 + 1] == 0.0
+        assert drop == 1.0 and d_o == 1.0
+        assert np.max(np.abs(u - u_o)) <= 1e-10
+        B.close()
+
+
+def test_argument_errors(em):
+    g, mat, rn, _ = synth.workload("tiny_trees")
+    bad = []
+    bad.append((g, dict(mat, B=float("nan")), rn))
+    bad.append((g, mat, dict(rn, dt=-1.0)))
+    bad.append((g, mat, dict(rn, max_voids_per_tree=5)))
+    bad.append((g, mat, dict(rn, ir_precond=2)))
+    bad.append((g, mat, dict(rn, intervals_per_seg=0)))
+    for gg, mm, rr in bad:
+        with pytest.raises(em.EmError) as ei:
+            em.Batch(gg, mm, rr)
+        assert ei.value.status == 1
+    B = em.Batch(g, mat, rn)
+    with pytest.raises(em.EmError):
+        B.stress(5)                    # no such sample
+    with pytest.raises(em.EmError) as ei:
+        B.run_to_ttf()                 # trees-only batch has no IR coupling
+    assert ei.value.status == 5
+    B.close()
