@@ -248,6 +248,24 @@ em_status em_get_screen(em_batch *b, int32_t sample, uint8_t *tree_mortal, uint8
 em_status em_inject_void(em_batch *b, int32_t sample, int32_t tree, int32_t node);
 /* Per-(sample, segment) Monte Carlo multipliers, xi [n_res]; param 0 kappa, 1 sigma_crit. */
 em_status em_get_xi(em_batch *b, int32_t sample, int32_t param, double *xi);
+/* Failed segments of one sample (dR > 0 or open; the set counted by
+ * em_ttf_result.n_failed_segs), ascending: *n = their number, the first
+ * min(*n, cap) written to idx (idx may be NULL when cap == 0). */
+em_status em_get_failed_segments(em_batch *b, int32_t sample, int32_t *idx, int32_t cap, int32_t *n);
+
+/* ---- checkpoint ----
+ * em_snapshot copies the batch's dynamic state (stress, currents, IR
+ * solution, void records, resistance changes, screen and retirement flags,
+ * time-to-failure bookkeeping, step counters, event ring) into host_buf;
+ * with host_buf NULL (or cap too small: EM_ERR_ARG) it only reports the size
+ * in *used.  em_restore loads such a snapshot into a batch created from the
+ * same inputs (EM_ERR_ARG otherwise) and rebuilds the derived state (forcing,
+ * factors, reachability).  em_stress_step and em_ir_solve then continue
+ * exactly where the snapshot was taken; em_run_to_ttf always starts from
+ * t = 0.  The learned-screen attachment and the screen's steady-stress
+ * scratch are not part of a snapshot. */
+em_status em_snapshot(em_batch *b, void *host_buf, size_t cap, size_t *used);
+em_status em_restore(em_batch *b, const void *host_buf, size_t n);
 
 /* ---- learned screen ----
  * A small model, not part of EMSpice 3, that sits in front of the transient

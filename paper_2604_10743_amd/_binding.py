@@ -29,7 +29,7 @@ API = ["em_batch_create", "em_batch_destroy", "em_get_info", "em_last_error", "e
        "em_reset", "em_mlp_create", "em_mlp_destroy", "em_mlp_last_error", "em_mlp_num_params",
        "em_mlp_set_params", "em_mlp_get_params", "em_mlp_forward", "em_mlp_grad",
        "em_mlp_train_step", "em_features", "em_surrogate_screen", "em_get_surrogate",
-       "em_first_nucleation"]
+       "em_first_nucleation", "em_get_failed_segments", "em_snapshot", "em_restore"]
 
 
 class EmError(RuntimeError):
@@ -126,6 +126,8 @@ def lib():
         L.em_mlp_train_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
                                         C.c_void_p]
         L.em_surrogate_screen.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
+        L.em_snapshot.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.em_restore.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
         _lib = L
     return _lib
 
@@ -343,6 +345,25 @@ class Batch:
         x = np.zeros(self.n_res)
         self._chk(lib().em_get_xi(self._h, C.c_int32(sample), C.c_int32(param), _ptr(x)))
         return x
+
+    def failed_segments(self, sample: int = 0) -> np.ndarray:
+        n = C.c_int32()
+        self._chk(lib().em_get_failed_segments(self._h, C.c_int32(sample), None, C.c_int32(0), C.byref(n)))
+        idx = np.zeros(max(n.value, 1), np.int32)
+        self._chk(lib().em_get_failed_segments(self._h, C.c_int32(sample), _ptr(idx), C.c_int32(idx.size),
+                                               C.byref(n)))
+        return idx[:n.value]
+
+    def snapshot(self) -> bytes:
+        used = C.c_size_t()
+        self._chk(lib().em_snapshot(self._h, None, 0, C.byref(used)))
+        buf = (C.c_uint8 * used.value)()
+        self._chk(lib().em_snapshot(self._h, buf, used.value, C.byref(used)))
+        return bytes(buf)
+
+    def restore(self, snap: bytes):
+        buf = (C.c_uint8 * len(snap)).from_buffer_copy(snap)
+        self._chk(lib().em_restore(self._h, buf, len(snap)))
 
     # -- learned screen ------------------------------------------------------
     def features(self):

@@ -1228,6 +1228,147 @@ em_status em_inject_void(em_batch *b, int32_t sample, int32_t tree, int32_t node
     return EM_OK;
 }
 
+em_status em_get_failed_segments(em_batch *b, int32_t sample, int32_t *idx, int32_t cap, int32_t *n)
+{
+    if (!b || !n || sample < 0 || sample >= b->S || cap < 0 || (cap > 0 && !idx))
+        return fail(b, EM_ERR_ARG, "bad arguments");
+    std::vector<double> dR(b->n_res);
+    std::vector<uint8_t> op(b->n_res);
+    HIPCHK(b, hipMemcpyAsync(dR.data(), b->d.dR + (size_t)sample * b->n_res, 8 * (size_t)b->n_res,
+                             hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipMemcpyAsync(op.data(), b->d.open + (size_t)sample * b->n_res, (size_t)b->n_res,
+                             hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    int c = 0;
+    for (int e = 0; e < b->n_res; ++e)
+        if (dR[e] > 0.0 || op[e]) {
+            if (c < cap) idx[c] = e;
+            ++c;
+        }
+    *n = c;
+    return EM_OK;
+}
+
+// ---- snapshot / restore -------------------------------------------------
+namespace {
+constexpr uint32_t SNAP_MAGIC = 0x31534d45u;    // "EMS1"
+
+struct SnapIO {
+    uint8_t *p;          // host buffer (null: size only)
+    const uint8_t *q;    // restore source
+    size_t cap, pos;
+    bool ok = true;
+};
+
+// device <-> snapshot region of n bytes
+em_status snap_dev(em_batch *b, SnapIO &io, void *dev, size_t n, bool restore)
+{
+    if (restore) {
+        if (io.pos + n > io.cap) { io.ok = false; return EM_OK; }
+        HIPCHK(b, hipMemcpy(dev, io.q + io.pos, n, hipMemcpyHostToDevice));
+    } else if (io.p) {
+        if (io.pos + n > io.cap) { io.ok = false; return EM_OK; }
+        HIPCHK(b, hipMemcpy(io.p + io.pos, dev, n, hipMemcpyDeviceToHost));
+    }
+    io.pos += n;
+    return EM_OK;
+}
+
+void snap_host(SnapIO &io, void *h, size_t n, bool restore)
+{
+    if (restore) {
+        if (io.pos + n > io.cap) { io.ok = false; return; }
+        std::memcpy(h, io.q + io.pos, n);
+    } else if (io.p) {
+        if (io.pos + n > io.cap) { io.ok = false; return; }
+        std::memcpy(io.p + io.pos, h, n);
+    }
+    io.pos += n;
+}
+
+// The dynamic state in a fixed order (the netlist, draws and statics are
+// rebuilt by em_batch_create from the same inputs).
+em_status snap_walk(em_batch *b, SnapIO &io, bool restore)
+{
+    Dev &d = b->d;
+    const size_t S = b->S, IS = (size_t)b->n_trees * S, NS = (size_t)b->ns * S, RS = (size_t)b->n_res * S,
+                 VS = (size_t)b->n_nodes * S, rsz = b->fp32 ? 4 : 8, IV = IS * MAXV;
+    struct Item { void *p; size_t n; } items[] = {
+        {d.sigma, rsz * NS}, {d.jseg, 8 * RS}, {d.u, 8 * VS}, {d.drop, 8 * S}, {d.dR, 8 * RS},
+        {d.open, RS}, {d.inst_active, IS}, {d.tree_mortal, IS}, {d.seg_mortal, RS}, {d.sample_active, S},
+        {d.nv, 4 * IS}, {d.vnode, 4 * IV}, {d.vseg, 4 * IV}, {d.vphase, 4 * IV}, {d.vstep, 4 * IV},
+        {d.vearly, 4 * IV}, {d.vvol, 8 * IV}, {d.vlen, 8 * IV}, {d.vrob, 8 * IV}, {d.n_suppressed, 4 * IS},
+        {d.ttf, 8 * S}, {d.final_drop, 8 * S}, {d.init_drop, 8 * S}, {d.t_prev, 8 * S}, {d.d_prev, 8 * S},
+        {d.failed, 4 * S}, {d.outer_idx, 4 * S}, {d.node_steps, 8}, {d.ev_count, 4}};
+    for (const Item &it : items) {
+        em_status rc = snap_dev(b, io, it.p, it.n, restore);
+        if (rc != EM_OK) return rc;
+    }
+    return EM_OK;
+}
+}  // namespace
+
+em_status em_snapshot(em_batch *b, void *host_buf, size_t cap, size_t *used)
+{
+    if (!b || !used) return fail(b, EM_ERR_ARG, "null argument");
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    uint32_t hdr[12] = {SNAP_MAGIC, 1u, (uint32_t)b->n_trees, (uint32_t)b->ns, (uint32_t)b->S,
+                        (uint32_t)b->n_nodes, (uint32_t)b->n_res, b->fp32 ? 1u : 0u, (uint32_t)MAXV,
+                        (uint32_t)b->step_counter, (uint32_t)b->n_outer_done, b->have_j ? 1u : 0u};
+    unsigned int nev = 0;
+    HIPCHK(b, hipMemcpy(&nev, b->d.ev_count, 4, hipMemcpyDeviceToHost));
+    const size_t ev_bytes = 4 * (size_t)EV_WORDS * std::min<unsigned int>(nev, (unsigned int)b->d.ev_cap);
+    SnapIO io{(uint8_t *)host_buf, nullptr, host_buf ? cap : 0, 0};
+    snap_host(io, hdr, sizeof hdr, false);
+    em_status rc = snap_walk(b, io, false);
+    if (rc != EM_OK) return rc;
+    rc = snap_dev(b, io, b->d.events, ev_bytes, false);
+    if (rc != EM_OK) return rc;
+    *used = io.pos;
+    if (host_buf && !io.ok) return fail(b, EM_ERR_ARG, "snapshot buffer too small (see *used)");
+    return EM_OK;
+}
+
+em_status em_restore(em_batch *b, const void *host_buf, size_t n)
+{
+    if (!b || !host_buf) return fail(b, EM_ERR_ARG, "null argument");
+    uint32_t hdr[12];
+    if (n < sizeof hdr) return fail(b, EM_ERR_ARG, "snapshot too short");
+    std::memcpy(hdr, host_buf, sizeof hdr);
+    if (hdr[0] != SNAP_MAGIC || hdr[1] != 1u || hdr[2] != (uint32_t)b->n_trees || hdr[3] != (uint32_t)b->ns ||
+        hdr[4] != (uint32_t)b->S || hdr[5] != (uint32_t)b->n_nodes || hdr[6] != (uint32_t)b->n_res ||
+        hdr[7] != (b->fp32 ? 1u : 0u) || hdr[8] != (uint32_t)MAXV)
+        return fail(b, EM_ERR_ARG, "snapshot does not belong to a batch of this shape");
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    SnapIO io{nullptr, (const uint8_t *)host_buf, n, sizeof hdr};
+    em_status rc = snap_walk(b, io, true);
+    if (rc != EM_OK) return rc;
+    if (!io.ok) return fail(b, EM_ERR_ARG, "snapshot truncated");
+    unsigned int nev = 0;
+    HIPCHK(b, hipMemcpy(&nev, b->d.ev_count, 4, hipMemcpyDeviceToHost));
+    const size_t ev_bytes = 4 * (size_t)EV_WORDS * std::min<unsigned int>(nev, (unsigned int)b->d.ev_cap);
+    rc = snap_dev(b, io, b->d.events, ev_bytes, true);
+    if (rc != EM_OK) return rc;
+    if (!io.ok) return fail(b, EM_ERR_ARG, "snapshot truncated");
+    b->step_counter = (int)hdr[9];
+    b->n_outer_done = (int)hdr[10];
+    b->have_j = hdr[11] != 0;
+    // derived state: forcing from the restored currents, factors from the
+    // restored void rows, reachability and the IR solution status
+    std::vector<uint8_t> op((size_t)b->n_res * b->S);
+    HIPCHK(b, hipMemcpy(op.data(), b->d.open, op.size(), hipMemcpyDeviceToHost));
+    b->any_open = false;
+    for (uint8_t o : op) b->any_open |= o != 0;
+    b->live_dirty = true;
+    b->ir_valid = false;
+    HIPCHK(b, hipMemsetAsync(b->d.open_dirty, 0, 4, b->stream));
+    if (b->have_j) launch_update_f(b->d, b->fp32, b->stream);
+    launch_factor(b->d, b->fp32, b->stream);
+    LAUNCHCHK(b);
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    return EM_OK;
+}
+
 em_status em_get_xi(em_batch *b, int32_t sample, int32_t param, double *xi)
 {
     if (!b || !xi || sample < 0 || sample >= b->S || (param != 0 && param != 1))

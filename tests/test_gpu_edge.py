@@ -134,3 +134,57 @@ def test_argument_errors(em):
         B.run_to_ttf()                 # trees-only batch has no IR coupling
     assert ei.value.status == 5
     B.close()
+
+
+def _stressed():
+    g = synth.two_layer_mesh(1001, nr=12, nc=12, sink_mu=math.log(490e-6), vdd=1.2, T_uniform=378.0)
+    return g, material(sigma_crit=150e6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_snapshot_restore_continues_exactly(em, prec):
+    g, mat = _stressed()
+    rn = run(prec=prec)
+    mc = dict(n_samples=3, seed=11, cov_kappa=0.2, cov_scrit=0.2)
+    A = em.Batch(g, mat, rn, mc)
+    A.ir_solve()
+    A.stress_step(30)
+    snap = A.snapshot()
+
+    def cont(X):
+        X.stress_step(40)
+        X.ir_solve()
+        X.stress_step(20)
+        ev = X.events()
+        ev = ev[np.lexsort(ev.T[::-1])]
+        return ([X.stress(s) for s in range(3)], [X.voids(s) for s in range(3)],
+                [X.seg_state(s) for s in range(3)], ev, X.info()["node_steps"])
+
+    ra = cont(A)
+    B = em.Batch(g, mat, rn, mc)
+    B.restore(snap)
+    rb = cont(B)
+    assert len(ra[3]) > 0                      # voids appeared in the continued run
+    for s in range(3):
+        assert np.array_equal(ra[0][s], rb[0][s])
+        assert np.array_equal(ra[1][s][0], rb[1][s][0]) and np.array_equal(ra[1][s][1], rb[1][s][1])
+        assert np.array_equal(ra[2][s][0], rb[2][s][0]) and np.array_equal(ra[2][s][1], rb[2][s][1])
+    assert np.array_equal(ra[3], rb[3]) and ra[4] == rb[4]
+    # a snapshot belongs to a batch of the same shape
+    C = em.Batch(*synth.workload("tiny_mesh")[:3])
+    with pytest.raises(em.EmError):
+        C.restore(snap)
+    for X in (A, B, C):
+        X.close()
+
+
+def test_failed_segments_match_segment_state(em):
+    g, mat = _stressed()
+    B = em.Batch(g, mat, run(prec=0))
+    r = B.run_to_ttf()[0]
+    idx = B.failed_segments(0)
+    dR, op = B.seg_state(0)
+    want = np.nonzero((dR > 0) | (op != 0))[0]
+    assert r["n_failed_segs"] > 0
+    assert np.array_equal(idx, want) and len(idx) == r["n_failed_segs"]
+    B.close()
