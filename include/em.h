@@ -116,9 +116,20 @@ typedef struct {
     int32_t stepper;             /* 0: resident chain kernel for chain trees (straight wires)
                                     that fit a workgroup, generic tree kernel otherwise;
                                     1: generic tree kernel for every tree */
-    int32_t ir_precond;          /* PCG preconditioner of the IR solve: 0 Jacobi (diagonal),
-                                    1 aggregation-multigrid V-cycle (same solution to cg_rtol,
-                                    far fewer iterations) */
+    int32_t ir_precond;          /* IR solve: 0 Jacobi-preconditioned CG on the nodal system;
+                                    1 CG with an aggregation-multigrid V-cycle on the nodal
+                                    system; 2 the same on the chain-condensed system (exact
+                                    Schur complement onto pads and nodes with other than one or
+                                    two resistors; interior node voltages by back-substitution
+                                    along each chain).  Same solution to cg_rtol; 2 iterates a
+                                    far smaller, better conditioned system on P/G grids. */
+    int32_t ir_launch;           /* launch shape of the multigrid PCG: 0 automatic (2 when the
+                                    iterated system has at most 4096 nodes, or at most 65536
+                                    nodes and 32 or more samples; else 1); 1 one kernel per
+                                    V-cycle step over all samples, iterations replayed as a
+                                    graph; 2 one workgroup per sample running its whole PCG in
+                                    one launch.  Same preconditioner and stopping rule; the
+                                    reduction order of the dot products differs. */
 } em_run_params;
 
 /* Monte Carlo (Sec. IV-F): per-segment unit-mean lognormal multipliers on
@@ -230,6 +241,11 @@ em_status em_get_voltages(em_batch *b, int32_t sample, double *u /* [n_nodes] */
 em_status em_get_seg_j(em_batch *b, int32_t sample, double *j /* [n_res] */);
 /* dR [n_res] (ohm), open [n_res] (0/1) */
 em_status em_get_seg_state(em_batch *b, int32_t sample, double *dR, uint8_t *open);
+/* Replace one sample's resistance state (the R = R0 + dR of eq. 17 and the
+ * open resistors of early failures) that the next IR solve uses: a what-if
+ * degradation state.  dR [n_res] finite and >= 0, open [n_res] 0 or 1; host
+ * arrays, copied.  Void growth during later steps adds to this dR. */
+em_status em_set_seg_state(em_batch *b, int32_t sample, const double *dR, const uint8_t *open);
 /* Per-node temperature, control volume and critical stress for one sample. */
 em_status em_get_node_state(em_batch *b, int32_t sample, double *T, double *V, double *sc);
 /* Nucleation events, each 5 int32: sample, tree, step, node, host segment;

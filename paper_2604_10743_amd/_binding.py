@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "EM_OK", 1: "EM_ERR_ARG", 2: "EM_ERR_OOM", 3: "EM_ERR_HIP", 4
 # Every entry point declared in include/em.h.
 API = ["em_batch_create", "em_batch_destroy", "em_get_info", "em_last_error", "em_ir_solve",
        "em_screen", "em_stress_step", "em_run_to_ttf", "em_get_topology", "em_get_stress",
-       "em_set_stress", "em_get_voltages", "em_get_seg_j", "em_get_seg_state", "em_get_node_state",
+       "em_set_stress", "em_get_voltages", "em_get_seg_j", "em_get_seg_state", "em_set_seg_state", "em_get_node_state",
        "em_get_events", "em_get_voids", "em_get_screen", "em_inject_void", "em_get_xi",
        "em_reset", "em_mlp_create", "em_mlp_destroy", "em_mlp_last_error", "em_mlp_num_params",
        "em_mlp_set_params", "em_mlp_get_params", "em_mlp_forward", "em_mlp_grad",
@@ -61,7 +61,7 @@ class RunParams(C.Structure):
                 ("n_steps", C.c_int32), ("ir_every", C.c_int32), ("fail_frac", C.c_double),
                 ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32), ("prec", C.c_int32),
                 ("screen", C.c_int32), ("max_voids_per_tree", C.c_int32), ("T_ambient", C.c_double),
-                ("stepper", C.c_int32), ("ir_precond", C.c_int32)]
+                ("stepper", C.c_int32), ("ir_precond", C.c_int32), ("ir_launch", C.c_int32)]
 
 
 class MCParams(C.Structure):
@@ -190,7 +190,8 @@ class Batch:
                       cg_max_iter=int(run["cg_max_iter"]), prec=int(run["prec"]),
                       screen=int(run["screen"]), max_voids_per_tree=int(run["max_voids_per_tree"]),
                       T_ambient=float(run["T_ambient"]), stepper=int(run.get("stepper", 0)),
-                      ir_precond=int(run.get("ir_precond", 1)))
+                      ir_precond=int(run.get("ir_precond", 2)),
+                      ir_launch=int(run.get("ir_launch", 0)))
         mcp = None
         if mc is not None:
             mcp = MCParams(struct_size=C.sizeof(MCParams), n_samples=int(mc["n_samples"]),
@@ -308,6 +309,12 @@ class Batch:
         op = np.zeros(self.n_res, np.uint8)
         self._chk(lib().em_get_seg_state(self._h, C.c_int32(sample), _ptr(dR), _ptr(op)))
         return dR, op
+
+    def set_seg_state(self, sample: int, dR, open_):
+        dR = np.ascontiguousarray(dR, np.float64)
+        op = np.ascontiguousarray(open_, np.uint8)
+        assert dR.shape == (self.n_res,) and op.shape == (self.n_res,)
+        self._chk(lib().em_set_seg_state(self._h, C.c_int32(sample), _ptr(dR), _ptr(op)))
 
     def node_state(self, sample: int = 0):
         T = np.zeros(self.n_stress); V = np.zeros(self.n_stress); sc = np.zeros(self.n_stress)

@@ -40,12 +40,13 @@ struct em_batch {
     bool any_open = false;        // some segment of some sample has opened since creation/reset
     bool ir_valid = false;        // u, j, drop hold the solution for the current conductances
     bool ir_unchanged = false;    // the last IR solve was skipped: currents as before
-    uint8_t *live0 = nullptr;     // [n_nodes] reachability from the pads with every resistor conducting
+    uint8_t *live0 = nullptr;     // reachability from the pads with every resistor conducting, per
+                                  // node of the iterated system
     int cg_iters_last = 0;
     int n_outer_done = 0;
     int step_counter = 0;         // steps taken through em_stress_step
     int n_generic_trees = 0;      // trees stepped by the generic tree kernel
-    int n_inc = 0;                // node-incidence entries (SpMV nonzeros off the diagonal)
+    int n_inc = 0;                // node-incidence entries of the iterated system
     // CG iterations captured once in a HIP graph and replayed in blocks
     hipStream_t cap_stream = nullptr;
     hipGraph_t cg_graph = nullptr;
@@ -69,7 +70,15 @@ struct em_batch {
     int n_def_list = 0;           // length of d.def_list from the t = 0 evaluation
     // multigrid preconditioner of the IR solve (device arrays owned through allocs)
     Amg amg;
+    Amg *amg_dev = nullptr;             // device copy of amg (one-workgroup PCG)
     bool use_amg = false;
+    bool ir_wg = false;                 // multigrid PCG with one workgroup per sample
+    // chain condensation: the PCG iterates the terminal system rd; interior
+    // voltages follow from the chains
+    bool condensed = false;
+    Dev rd{};
+    Cond cond{};
+    int n_term = 0, n_redge = 0, n_cchain = 0;
 };
 
 namespace {
@@ -271,7 +280,8 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
     if (r->intervals_per_seg < 1 || !(r->dt > 0) || !std::isfinite(r->dt) || r->n_steps < 0 || r->ir_every < 1 ||
         r->cg_max_iter < 1 || !(r->cg_rtol > 0) || (r->prec != EM_FP64 && r->prec != EM_FP32) ||
         r->max_voids_per_tree < 0 || r->max_voids_per_tree > MAXV || !(r->T_ambient > 0) ||
-        r->stepper < 0 || r->stepper > 1 || r->ir_precond < 0 || r->ir_precond > 1)
+        r->stepper < 0 || r->stepper > 1 || r->ir_precond < 0 || r->ir_precond > 2 ||
+        r->ir_launch < 0 || r->ir_launch > 2)
         return fail(b, EM_ERR_ARG, "bad run parameters (max_voids_per_tree <= 4)");
     if (mc && (mc->n_samples < 1 || mc->n_samples > 65535 || mc->cov_kappa < 0 || mc->cov_scrit < 0 || !std::isfinite(mc->cov_kappa) ||
                !std::isfinite(mc->cov_scrit)))
@@ -299,46 +309,90 @@ em_status ir_solve_impl(em_batch *b)
         }
     }
     b->ir_unchanged = false;
+    // the system the PCG iterates (with chain condensation: its terminals,
+    // whose conductances, sinks and warm start the chain reduction forms)
+    Dev &X = b->condensed ? b->rd : d;
+    if (b->condensed) {
+        launch_chain_reduce(d, X, b->cond, st);
+        LAUNCHCHK(b);
+    }
     if (b->live_dirty && !b->any_open && b->live0) {
-        launch_ir_live_copy(d, b->live0, st);     // nothing open: the static reachability holds
+        launch_ir_live_copy(X, b->live0, st);     // nothing open: the static reachability holds
         LAUNCHCHK(b);
         b->live_dirty = false;
     }
     if (b->live_dirty) {
-        launch_ir_live_init(d, st);
+        // connected components of the conducting network; labels only
+        // decrease, so the rounds end (in practice after a few)
+        launch_ir_cc_init(X, st);
         uint32_t *hc = (uint32_t *)pinned(b, std::max<size_t>(d.S, 8));
         if (!hc) return fail(b, EM_ERR_OOM, "pinned host buffer");
         for (int round = 0;; ++round) {
-            HIPCHK(b, hipMemsetAsync(d.live_changed, 0, 4, st));
-            for (int k = 0; k < 16; ++k) launch_ir_live_step(d, st);
+            HIPCHK(b, hipMemsetAsync(X.live_changed, 0, 4, st));
+            launch_ir_cc_round(X, st);
+            launch_ir_cc_round(X, st);
             LAUNCHCHK(b);
-            HIPCHK(b, hipMemcpyAsync(hc, d.live_changed, 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(b, hipMemcpyAsync(hc, X.live_changed, 4, hipMemcpyDeviceToHost, st));
             HIPCHK(b, hipStreamSynchronize(st));
             if (*hc == 0) break;
-            if (round > d.n_nodes) return fail(b, EM_ERR_HIP, "reachability did not settle");
+            if (round > X.n_nodes) return fail(b, EM_ERR_HIP, "reachability did not settle");
         }
+        launch_ir_cc_finish(X, st);
+        LAUNCHCHK(b);
         b->live_dirty = false;
     }
     const double rtol = b->run.cg_rtol;
     const bool amg = b->use_amg;
-    launch_ir_gather_inc(d, b->n_inc, st);
-    launch_ir_setup(d, st);
-    launch_ir_finalize0(d, rtol, st);
+    launch_ir_gather_inc(X, b->n_inc, st);
+    launch_ir_setup(X, st);
+    launch_ir_finalize0(X, rtol, st);
     LAUNCHCHK(b);
     uint8_t *hconv = pinned(b, std::max<size_t>(d.S, 8));
     if (!hconv) return fail(b, EM_ERR_OOM, "pinned host buffer");
+    if (b->ir_wg) {
+        // one workgroup per sample runs the whole PCG; converged samples exit
+        HIPCHK(b, hipMemcpyAsync(hconv, X.conv, X.S, hipMemcpyDeviceToHost, st));
+        HIPCHK(b, hipStreamSynchronize(st));
+        bool all = true;
+        for (int s = 0; s < X.S; ++s) all &= hconv[s] != 0;
+        int itmax = 0;
+        if (!all) {
+            launch_amg_setup(X, b->amg, st);
+            launch_ir_pcg_wg(X, b->amg_dev, rtol, b->run.cg_max_iter, st);
+            LAUNCHCHK(b);
+            std::vector<int> its(X.S);
+            HIPCHK(b, hipMemcpyAsync(hconv, X.conv, X.S, hipMemcpyDeviceToHost, st));
+            HIPCHK(b, hipMemcpyAsync(its.data(), X.ir_iters, 4 * (size_t)X.S, hipMemcpyDeviceToHost, st));
+            HIPCHK(b, hipStreamSynchronize(st));
+            all = true;
+            for (int s = 0; s < X.S; ++s) {
+                itmax = std::max(itmax, its[s]);
+                all &= hconv[s] != 0;
+            }
+            b->cg_iters_last = itmax;
+            if (!all) return fail(b, EM_ERR_NOCONV, "PCG did not reach cg_rtol within cg_max_iter iterations");
+        }
+        b->cg_iters_last = itmax;
+        if (b->condensed) launch_chain_expand(d, X, b->cond, st);
+        launch_ir_finish(d, st);
+        launch_update_f(d, b->fp32, st);
+        LAUNCHCHK(b);
+        b->have_j = true;
+        b->ir_valid = true;
+        return EM_OK;
+    }
     if (amg) {
         // samples whose warm start already meets the tolerance need no
         // preconditioner; for the others: this solve's coarse operators, then
         // z = M^-1 r, p = z and r.z
-        HIPCHK(b, hipMemcpyAsync(hconv, d.conv, d.S, hipMemcpyDeviceToHost, st));
+        HIPCHK(b, hipMemcpyAsync(hconv, X.conv, X.S, hipMemcpyDeviceToHost, st));
         HIPCHK(b, hipStreamSynchronize(st));
         bool all = true;
-        for (int s = 0; s < d.S; ++s) all &= hconv[s] != 0;
+        for (int s = 0; s < X.S; ++s) all &= hconv[s] != 0;
         if (!all) {
-            launch_amg_setup(d, b->amg, st);
-            launch_amg_vcycle(d, b->amg, true, st);
-            launch_ir_finalize_rz(d, st);
+            launch_amg_setup(X, b->amg, st);
+            launch_amg_vcycle(X, b->amg, true, st);
+            launch_ir_finalize_rz(X, st);
             LAUNCHCHK(b);
         }
     }
@@ -349,20 +403,20 @@ em_status ir_solve_impl(em_batch *b)
         if (!b->cap_stream) HIPCHK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
         HIPCHK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
         for (int k = 0; k < CG_BLOCK; ++k) {
-            launch_ir_spmv(d, b->cap_stream);
-            launch_ir_update(d, k, amg ? b->amg.omega : 0.0, b->cap_stream);
-            if (amg) launch_amg_vcycle(d, b->amg, false, b->cap_stream);
-            launch_ir_pupdate(d, k, rtol, d.z, b->cap_stream);
+            launch_ir_spmv(X, b->cap_stream);
+            launch_ir_update(X, k, amg ? b->amg.omega : 0.0, b->cap_stream);
+            if (amg) launch_amg_vcycle(X, b->amg, false, b->cap_stream);
+            launch_ir_pupdate(X, k, rtol, X.z, b->cap_stream);
         }
         HIPCHK(b, hipStreamEndCapture(b->cap_stream, &b->cg_graph));
         HIPCHK(b, hipGraphInstantiate(&b->cg_exec, b->cg_graph, nullptr, nullptr, 0));
     }
     int it = 0;
     for (;;) {
-        HIPCHK(b, hipMemcpyAsync(hconv, d.conv, d.S, hipMemcpyDeviceToHost, st));
+        HIPCHK(b, hipMemcpyAsync(hconv, X.conv, X.S, hipMemcpyDeviceToHost, st));
         HIPCHK(b, hipStreamSynchronize(st));
         bool all = true;
-        for (int s = 0; s < d.S; ++s) all &= hconv[s] != 0;
+        for (int s = 0; s < X.S; ++s) all &= hconv[s] != 0;
         if (all) break;
         if (it >= b->run.cg_max_iter) {
             b->cg_iters_last = it;
@@ -373,6 +427,7 @@ em_status ir_solve_impl(em_batch *b)
     }
     LAUNCHCHK(b);
     b->cg_iters_last = it;
+    if (b->condensed) launch_chain_expand(d, X, b->cond, st);
     launch_ir_finish(d, st);
     launch_update_f(d, b->fp32, st);
     LAUNCHCHK(b);
@@ -692,7 +747,6 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     UPR(d.ra, g->res_a, nr); UPR(d.rb, g->res_b, nr);
     UPR(d.len, g->res_len, nr); UPR(d.w, g->res_w, nr); UPR(d.h, g->res_h, nr); UPR(d.R0, g->res_R0, nr);
     UP(d.is_wire, is_wire); UP(d.is_pad, is_pad);
-    UP(b->live0, live0);
     if (g->sink_I) UPR(d.sink, g->sink_I, nn);
     else { double *z; AL(z, double, nn); d.sink = z; }
     UP(d.ninc_off, ninc_off); UP(d.ninc_res, ninc_res); UP(d.ninc_nbr, ninc_nbr);
@@ -740,25 +794,81 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     AL(d.node_steps, unsigned long long, 1);
     HIPCHK(b, hipEventCreate(&b->ev_a)); HIPCHK(b, hipEventCreate(&b->ev_b));
     HIPCHK(b, hipEventCreate(&b->ev_c)); HIPCHK(b, hipEventCreate(&b->ev_d));
-    AL(d.G, double, RS);
-    AL(d.G_inc, double, (size_t)S * ninc_off[nn]);
-    b->n_inc = ninc_off[nn];
-    AL(d.diag, double, VS); AL(d.rhs, double, VS); AL(d.u, double, VS); AL(d.r, double, VS);
-    AL(d.z, double, VS); AL(d.p, double, VS); AL(d.q, double, VS);
-    AL(d.live, uint8_t, VS); AL(d.live_changed, uint32_t, 1); AL(d.g_changed, uint32_t, 1);
+    AL(d.G, double, RS); AL(d.u, double, VS);
+    AL(d.live, uint8_t, VS); AL(d.g_changed, uint32_t, 1);
     d.ir_nblk = (nn + ir_nodes_per_block() - 1) / ir_nodes_per_block();
     AL(d.part, double, (size_t)S * d.ir_nblk * 4);
-    AL(d.rz, double, 2 * (size_t)S); AL(d.bb, double, S); AL(d.conv, uint8_t, S); AL(d.drop, double, S);
+    AL(d.drop, double, S);
     AL(d.ttf, double, S); AL(d.final_drop, double, S); AL(d.init_drop, double, S);
     AL(d.t_prev, double, S); AL(d.d_prev, double, S); AL(d.failed, int, S); AL(d.outer_idx, int, S);
-    if (!b->trees_only && r->ir_precond == 1) {
-        AmgHost H = amg_build(nn, is_pad.data(), nr, g->res_a, g->res_b, g->res_R0);
+
+    // The system the PCG iterates: the nodal network, or (multigrid on the
+    // condensed network) its terminals with one reduced edge per two-ended
+    // chain.
+    b->condensed = !b->trees_only && r->ir_precond == 2;
+    Dev &X = b->condensed ? b->rd : d;
+    int xn = nn, xr = nr;
+    std::vector<int> xoff, xres, xnbr, xra, xrb;
+    std::vector<uint8_t> xpad, xlive0;
+    std::vector<double> xR0;
+    if (b->condensed) {
+        CondHost C = cond_build(nn, nr, g->res_a, g->res_b, g->res_R0, is_pad.data());
+        xn = C.n_term;
+        xr = (int)C.red_a.size();
+        xra = C.red_a; xrb = C.red_b; xR0 = C.red_R0; xpad = C.red_pad;
+        xlive0.assign(xn, 0);
+        for (int t = 0; t < xn; ++t) xlive0[t] = live0[C.term_node[t]];
+        xoff.assign(xn + 1, 0);
+        for (int e = 0; e < xr; ++e) { xoff[xra[e] + 1]++; xoff[xrb[e] + 1]++; }
+        for (int v = 0; v < xn; ++v) xoff[v + 1] += xoff[v];
+        xres.assign(xoff[xn], 0); xnbr.assign(xoff[xn], 0);
+        {
+            std::vector<int> pos(xoff.begin(), xoff.end() - 1);
+            for (int e = 0; e < xr; ++e) {
+                xres[pos[xra[e]]] = e; xnbr[pos[xra[e]]++] = xrb[e];
+                xres[pos[xrb[e]]] = e; xnbr[pos[xrb[e]]++] = xra[e];
+            }
+        }
+        Cond &c = b->cond;
+        c.n_term = xn; c.n_chain = C.n_chain;
+        UP(c.term_node, C.term_node); UP(c.eoff, C.eoff); UP(c.e, C.e); UP(c.voff, C.voff); UP(c.v, C.v);
+        UP(c.cA, C.cA); UP(c.cB, C.cB); UP(c.cred, C.cred); UP(c.tce_off, C.tce_off); UP(c.tce, C.tce);
+        AL(c.cinj, double, (size_t)S * C.n_chain * 2);
+        X.n_nodes = xn; X.n_res = xr; X.S = S; X.vdd = g->vdd;
+        X.sample_active = d.sample_active;
+        UP(X.ra, xra); UP(X.rb, xrb); UP(X.is_pad, xpad);
+        UP(X.ninc_off, xoff); UP(X.ninc_res, xres); UP(X.ninc_nbr, xnbr);
+        X.sink = nullptr;
+        AL(X.sink_s, double, (size_t)S * xn);
+        AL(X.G, double, (size_t)S * xr); AL(X.u, double, (size_t)S * xn); AL(X.live, uint8_t, (size_t)S * xn);
+        b->n_term = xn; b->n_redge = xr; b->n_cchain = C.n_chain;
+    } else {
+        xoff = ninc_off; xpad = is_pad; xlive0 = live0;
+        xra.assign(g->res_a, g->res_a + nr); xrb.assign(g->res_b, g->res_b + nr);
+        xR0.assign(g->res_R0, g->res_R0 + nr);
+    }
+    UP(b->live0, xlive0);
+    const size_t XS = (size_t)S * xn;
+    AL(X.G_inc, double, (size_t)S * xoff[xn]);
+    b->n_inc = xoff[xn];
+    AL(X.diag, double, XS); AL(X.rhs, double, XS); AL(X.r, double, XS);
+    AL(X.z, double, XS); AL(X.p, double, XS); AL(X.q, double, XS);
+    AL(X.live_changed, uint32_t, 1);
+    AL(X.cc_label, int, (size_t)S * (xn + 1));
+    if (b->condensed) {
+        X.ir_nblk = (xn + ir_nodes_per_block() - 1) / ir_nodes_per_block();
+        AL(X.part, double, (size_t)S * X.ir_nblk * 4);
+    }
+    AL(X.rz, double, 2 * (size_t)S); AL(X.bb, double, S); AL(X.conv, uint8_t, S);
+    AL(X.ir_iters, int, S);
+    if (!b->trees_only && r->ir_precond >= 1) {
+        AmgHost H = amg_build(xn, xpad.data(), xr, xra.data(), xrb.data(), xR0.data());
         Amg &a = b->amg;
         a.nlev = (int)H.lev.size() - 1;
         if (a.nlev >= 1) {
             a.l0.ne0 = (int)H.e0_res.size();
             UP(a.l0.e0_res, H.e0_res); UP(a.l0.e0_a, H.e0_a); UP(a.l0.e0_b, H.e0_b);
-            AL(a.l0.w0, double, VS);
+            AL(a.l0.w0, double, XS);
             for (int l = 1; l <= a.nlev; ++l) {
                 const AmgHostLevel &h = H.lev[l];
                 AmgLevel &L = a.lev[l];
@@ -777,6 +887,14 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
             b->use_amg = true;
             a.omega = 0.9;          // Jacobi weight and coarse-correction scale chosen by
             a.alpha = 1.4;          // measurement (PCG iterations on the P/G grids)
+            // one workgroup per sample pays off when the samples fill the chip
+            // or the system is small; a single large system keeps every CU busy
+            // only in the one-kernel-per-step form
+            b->ir_wg = r->ir_launch == 2 ||
+                       (r->ir_launch == 0 && (xn <= 4096 || (S >= 32 && xn <= ir_wg_max_nodes())));
+            b->amg_dev = (Amg *)dalloc(b, sizeof(Amg));
+            if (!b->amg_dev) return fail(b, EM_ERR_OOM, "device allocation");
+            HIPCHK(b, hipMemcpyAsync(b->amg_dev, &a, sizeof(Amg), hipMemcpyHostToDevice, b->stream));
         }
     }
 
@@ -1137,6 +1255,24 @@ em_status em_get_seg_state(em_batch *b, int32_t sample, double *dR, uint8_t *ope
     if (open) HIPCHK(b, hipMemcpyAsync(open, b->d.open + (size_t)sample * b->n_res, (size_t)b->n_res,
                                        hipMemcpyDeviceToHost, b->stream));
     HIPCHK(b, hipStreamSynchronize(b->stream));
+    return EM_OK;
+}
+
+em_status em_set_seg_state(em_batch *b, int32_t sample, const double *dR, const uint8_t *open)
+{
+    if (!b || sample < 0 || sample >= b->S || !dR || !open) return fail(b, EM_ERR_ARG, "bad sample or null state");
+    if (b->trees_only) return fail(b, EM_ERR_STATE, "trees-only batch has no IR network");
+    bool any = false;
+    for (int e = 0; e < b->n_res; ++e) {
+        if (!std::isfinite(dR[e]) || dR[e] < 0.0 || open[e] > 1) return fail(b, EM_ERR_ARG, "dR must be finite and >= 0, open 0 or 1");
+        any |= open[e] != 0;
+    }
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    HIPCHK(b, hipMemcpy(b->d.dR + (size_t)sample * b->n_res, dR, 8 * (size_t)b->n_res, hipMemcpyHostToDevice));
+    HIPCHK(b, hipMemcpy(b->d.open + (size_t)sample * b->n_res, open, (size_t)b->n_res, hipMemcpyHostToDevice));
+    b->live_dirty = true;
+    b->any_open = b->any_open || any;
+    b->ir_valid = false;
     return EM_OK;
 }
 

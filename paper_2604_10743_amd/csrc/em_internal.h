@@ -39,6 +39,7 @@ struct Dev {
     const double *len, *w, *h, *R0;
     const uint8_t *is_wire;             // 1 for a wire segment
     const double *sink;
+    double *sink_s;                     // [S][n_nodes] per-sample sinks (condensed system), or null
     const uint8_t *is_pad;              // [n_nodes]
     const int *ninc_off, *ninc_res, *ninc_nbr;   // node incidence (all resistors)
     // temperature inputs
@@ -93,10 +94,12 @@ struct Dev {
     uint8_t *live;                      // [S][n_nodes]
     uint32_t *live_changed;
     uint32_t *g_changed;                // [1] some conductance differs from the last solve's
+    int *cc_label;                      // [S][n_nodes + 1] component labels (reachability)
     double *part;                       // [S][nblk][4] block partial sums
     double *rz;                         // [2][S] r.z, double-buffered by iteration parity
     double *bb;                         // [S]
     uint8_t *conv;                      // [S]
+    int *ir_iters;                      // [S] PCG iterations of the last solve (one-workgroup form)
     double *drop;                       // [S]
     int ir_nblk;
     // ---- TTF ----
@@ -147,6 +150,32 @@ struct Amg {
     double omega = 2.0 / 3.0, alpha = 1.0;
 };
 
+// Chain condensation of the IR network: terminals (pads and nodes whose
+// resistor count is neither 1 nor 2) and the chains of interior nodes
+// between them; the condensed system has one reduced edge per two-ended
+// chain joining two distinct terminals.
+struct CondHost {
+    int n_term = 0, n_chain = 0;
+    std::vector<int> term_node, tid;    // terminal -> node, node -> terminal (-1: interior)
+    std::vector<int> eoff, e;           // resistors of each chain, from end A
+    std::vector<int> voff, v;           // interior nodes of each chain, from end A
+    std::vector<int> cA, cB;            // terminal at each end (cB -1: dangling chain)
+    std::vector<int> cred;              // reduced edge of each chain (-1: none)
+    std::vector<int> red_a, red_b;      // reduced edges (terminal indices)
+    std::vector<double> red_R0;         // nominal series resistance of each reduced edge
+    std::vector<uint8_t> red_pad;       // terminal is a pad
+    std::vector<int> tce_off, tce;      // chain ends at each terminal: 2 * chain + (end B)
+};
+CondHost cond_build(int nn, int nr, const int *ra, const int *rb, const double *R0, const uint8_t *is_pad);
+
+struct Cond {
+    int n_term, n_chain;
+    const int *term_node;
+    const int *eoff, *e, *voff, *v, *cA, *cB, *cred;
+    const int *tce_off, *tce;
+    double *cinj;                       // [S][n_chain][2] current drawn from end A, end B
+};
+
 // Host-side construction of the aggregation hierarchy on the nominal
 // conductances (1/R0); every array is returned for upload.
 struct AmgHostLevel {
@@ -184,8 +213,9 @@ void launch_copy_node_col(const Dev &d, bool fp32, int which, int sample, double
 void launch_ir_conductance(const Dev &d, hipStream_t st);
 void launch_ir_gather_inc(const Dev &d, int ninc, hipStream_t st);
 void launch_ir_live_copy(const Dev &d, const uint8_t *live0, hipStream_t st);
-void launch_ir_live_init(const Dev &d, hipStream_t st);
-void launch_ir_live_step(const Dev &d, hipStream_t st);
+void launch_ir_cc_init(const Dev &d, hipStream_t st);
+void launch_ir_cc_round(const Dev &d, hipStream_t st);    // hooking + pointer jumping, sets live_changed
+void launch_ir_cc_finish(const Dev &d, hipStream_t st);   // live = label is the pads'
 void launch_ir_setup(const Dev &d, hipStream_t st);       // diag, rhs, r = b - A x, z, p, partials
 void launch_ir_finalize0(const Dev &d, double rtol, hipStream_t st);
 void launch_ir_spmv(const Dev &d, hipStream_t st);        // q = A p, partial p.q
@@ -205,6 +235,12 @@ void launch_amg_post0(const Dev &d, double *w0, const AmgLevel &L1, const double
                       double omega, bool init, hipStream_t st);
 void launch_amg_setup(const Dev &d, const Amg &a, hipStream_t st);
 void launch_amg_vcycle(const Dev &d, const Amg &a, bool init, hipStream_t st);
+int ir_wg_max_nodes();
+// condensed IR solve: chain reduction + reduced sinks and warm start; terminal
+// scatter + interior back-substitution into the nodal u and live
+void launch_chain_reduce(const Dev &d, const Dev &r, const Cond &c, hipStream_t st);
+void launch_chain_expand(const Dev &d, const Dev &r, const Cond &c, hipStream_t st);
+void launch_ir_pcg_wg(const Dev &d, const Amg *amg_dev, double rtol, int max_iter, hipStream_t st);
 void launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
 void launch_ttf_init(const Dev &d, double fail, hipStream_t st);
 void launch_ttf_update(const Dev &d, double fail, int k, double t, hipStream_t st);

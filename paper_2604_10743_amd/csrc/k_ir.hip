@@ -109,31 +109,54 @@ EM_KERNEL void k_ir_live_copy(Dev d, const uint8_t *live0)
     d.live[g] = live0[g % d.n_nodes];
 }
 
-EM_KERNEL void k_ir_live_init(Dev d)
+// Reachability from the pads as connected components of the conducting
+// network (min-label hooking with pointer jumping): node i has index i + 1,
+// index 0 stands for all pads; a node is live iff its final label is 0.
+EM_KERNEL void k_ir_cc_init(Dev d)
 {
+    const long long n1 = d.n_nodes + 1;
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (long long)d.S * d.n_nodes) return;
-    int i = (int)(g % d.n_nodes);
-    d.live[g] = d.is_pad[i];
+    if (g >= (long long)d.S * n1) return;
+    const int x = (int)(g % n1);
+    d.cc_label[g] = (x == 0 || d.is_pad[x - 1]) ? 0 : x;
 }
 
-// One relaxation of reachability from the pads over conducting resistors.
-// Flags only ever go 0 -> 1, so concurrent updates are benign.
-EM_KERNEL void k_ir_live_step(Dev d)
+EM_KERNEL void k_ir_cc_hook(Dev d)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)d.S * d.n_res) return;
+    const int s = (int)(g / d.n_res), e = (int)(g % d.n_res);
+    if (!(d.G[g] > 0.0)) return;
+    int *L = d.cc_label + (size_t)s * (d.n_nodes + 1);
+    const int a = d.ra[e] + 1, b = d.rb[e] + 1;
+    const int la = L[a], lb = L[b];
+    if (la == lb) return;
+    // any edge whose ends disagree keeps the rounds going: a round that
+    // sees none has reached equal labels on every conducting component
+    *d.live_changed = 1u;
+    const int lo = min(la, lb), hi = max(la, lb);
+    atomicMin(&L[hi], lo);
+    atomicMin(&L[a], lo);
+    atomicMin(&L[b], lo);
+}
+
+EM_KERNEL void k_ir_cc_jump(Dev d)
+{
+    const long long n1 = d.n_nodes + 1;
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)d.S * n1) return;
+    int *L = d.cc_label + (g / n1) * n1;
+    int x = L[g % n1];
+    for (int k = 0; k < 32 && L[x] < x; ++k) x = L[x];
+    L[g % n1] = x;
+}
+
+EM_KERNEL void k_ir_cc_finish(Dev d)
 {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long long)d.S * d.n_nodes) return;
-    int s = (int)(g / d.n_nodes), i = (int)(g % d.n_nodes);
-    if (d.live[g]) return;
-    const double *G = d.G + (size_t)s * d.n_res;
-    const uint8_t *L = d.live + (size_t)s * d.n_nodes;
-    for (int k = d.ninc_off[i]; k < d.ninc_off[i + 1]; ++k) {
-        if (G[d.ninc_res[k]] > 0.0 && L[d.ninc_nbr[k]]) {
-            d.live[g] = 1;
-            *d.live_changed = 1u;
-            return;
-        }
-    }
+    const int s = (int)(g / d.n_nodes), i = (int)(g % d.n_nodes);
+    d.live[g] = d.cc_label[(size_t)s * (d.n_nodes + 1) + i + 1] == 0 ? 1 : 0;
 }
 
 // Diagonal, right-hand side (sinks and pad injections), residual of the warm
@@ -152,7 +175,7 @@ EM_KERNEL void k_ir_setup(Dev d)
         for (int k = d.ninc_off[i]; k < d.ninc_off[i + 1]; ++k) dg += G[d.ninc_res[k]];
         d.diag[x] = dg;
         if (is_free(d, s, i)) {
-            double b = -d.sink[i], Ax = dg * u[i];
+            double b = -(d.sink_s ? d.sink_s[x] : d.sink[i]), Ax = dg * u[i];
             for (int k = d.ninc_off[i]; k < d.ninc_off[i + 1]; ++k) {
                 int nb = d.ninc_nbr[k];
                 double gk = G[d.ninc_res[k]];
@@ -437,13 +460,18 @@ void launch_ir_live_copy(const Dev &d, const uint8_t *live0, hipStream_t st)
     long long n = (long long)d.S * d.n_nodes;
     k_ir_live_copy<<<(int)((n + IR_BS - 1) / IR_BS), IR_BS, 0, st>>>(d, live0);
 }
-void launch_ir_live_init(const Dev &d, hipStream_t st)
+void launch_ir_cc_init(const Dev &d, hipStream_t st)
 {
-    k_ir_live_init<<<nb((long long)d.S * d.n_nodes), IR_BS, 0, st>>>(d);
+    k_ir_cc_init<<<nb((long long)d.S * (d.n_nodes + 1)), IR_BS, 0, st>>>(d);
 }
-void launch_ir_live_step(const Dev &d, hipStream_t st)
+void launch_ir_cc_round(const Dev &d, hipStream_t st)
 {
-    k_ir_live_step<<<nb((long long)d.S * d.n_nodes), IR_BS, 0, st>>>(d);
+    k_ir_cc_hook<<<nb((long long)d.S * d.n_res), IR_BS, 0, st>>>(d);
+    k_ir_cc_jump<<<nb((long long)d.S * (d.n_nodes + 1)), IR_BS, 0, st>>>(d);
+}
+void launch_ir_cc_finish(const Dev &d, hipStream_t st)
+{
+    k_ir_cc_finish<<<nb((long long)d.S * d.n_nodes), IR_BS, 0, st>>>(d);
 }
 void launch_ir_setup(const Dev &d, hipStream_t st)
 {

@@ -104,7 +104,7 @@ def test_padless_island_reads_zero_volts(em, oracle_mod):
     g.res_is_via = np.concatenate([g.res_is_via, [0]]).astype(np.uint8)
     g.sink_I = np.concatenate([g.sink_I, [1e-5, 0.0]])
     g.node_T = np.concatenate([g.node_T, [378.0, 378.0]])
-    for pc in (0, 1):
+    for pc in (0, 1, 2):
         B = em.Batch(g, material(), run(prec=0, ir_precond=pc, cg_rtol=1e-14, cg_max_iter=100000))
         drop = B.ir_solve()[0]
         u = B.voltages()
@@ -121,7 +121,8 @@ def test_argument_errors(em):
     bad.append((g, dict(mat, B=float("nan")), rn))
     bad.append((g, mat, dict(rn, dt=-1.0)))
     bad.append((g, mat, dict(rn, max_voids_per_tree=5)))
-    bad.append((g, mat, dict(rn, ir_precond=2)))
+    bad.append((g, mat, dict(rn, ir_precond=3)))
+    bad.append((g, mat, dict(rn, ir_launch=3)))
     bad.append((g, mat, dict(rn, intervals_per_seg=0)))
     for gg, mm, rr in bad:
         with pytest.raises(em.EmError) as ei:
