@@ -121,8 +121,10 @@ typedef struct {
                                     system; 2 the same on the chain-condensed system (exact
                                     Schur complement onto pads and nodes with other than one or
                                     two resistors; interior node voltages by back-substitution
-                                    along each chain).  Same solution to cg_rtol; 2 iterates a
-                                    far smaller, better conditioned system on P/G grids. */
+                                    along each chain), applied when it removes at least a
+                                    quarter of the nodes, else as 1.  Same solution to cg_rtol;
+                                    2 iterates a far smaller, better conditioned system on P/G
+                                    grids with sparse vias. */
     int32_t ir_launch;           /* launch shape of the multigrid PCG: 0 automatic (2 when the
                                     iterated system has at most 4096 nodes, or at most 65536
                                     nodes and 32 or more samples; else 1); 1 one kernel per
@@ -174,6 +176,9 @@ typedef struct {
                               growth phase (a resistance change that earlier IR solves missed);
                               with none, results equal those of the unscreened run */
     double surrogate_ms;   /* wall time of the learned-screen evaluations (features + model) */
+    int32_t ir_sys_nodes;  /* nodes of the system the IR PCG iterates (n_nodes, or the terminals
+                              of the chain condensation) */
+    int32_t ir_sys_edges;  /* its resistors (or reduced edges) */
 } em_info;
 
 /* Allocator hook: device memory for the batch (e.g. a framework's caching

@@ -84,7 +84,7 @@ class Info(C.Structure):
                 ("step_kernel_ms", C.c_double), ("cg_iters_total", C.c_int64), ("ir_ms", C.c_double),
                 ("n_deferred", C.c_int64), ("n_activated", C.c_int64), ("n_late", C.c_int64),
                 ("n_violations", C.c_int64),
-                ("surrogate_ms", C.c_double)]
+                ("surrogate_ms", C.c_double), ("ir_sys_nodes", C.c_int32), ("ir_sys_edges", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)

@@ -701,7 +701,11 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     const int cM = b->fp32 ? CHAIN_M32 : CHAIN_M64;
     const int cWG = b->fp32 ? CHAIN_WG32 : CHAIN_WG64;
     std::vector<uint8_t> tree_chain(nt, 0);
-    std::vector<int> lane_inst, lane_blk;
+    // placement of each chain instance: first lane (global) and lane count;
+    // the per-lane table itself is expanded on the device
+    std::vector<int> place_inst, place_L;
+    std::vector<long long> place_off;
+    long long n_lanes = 0;
     if (r->stepper == 0) {
         for (int t = 0; t < nt; ++t) {
             int i0 = P.tree_off[t], i1 = P.tree_off[t + 1];
@@ -717,15 +721,17 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
             int L = (P.tree_off[t + 1] - P.tree_off[t] + cM - 1) / cM;
             for (int s = 0; s < S; ++s) {
                 if (fill + L > cWG) {
-                    for (; fill < cWG; ++fill) { lane_inst.push_back(-1); lane_blk.push_back(0); }
+                    n_lanes += cWG - fill;
                     fill = 0;
                 }
-                for (int k = 0; k < L; ++k) { lane_inst.push_back(t * S + s); lane_blk.push_back(k); }
+                place_inst.push_back(t * S + s);
+                place_off.push_back(n_lanes);
+                place_L.push_back(L);
+                n_lanes += L;
                 fill += L;
             }
         }
-        if (fill > 0)
-            for (; fill < cWG; ++fill) { lane_inst.push_back(-1); lane_blk.push_back(0); }
+        if (fill > 0) n_lanes += cWG - fill;
     }
 
     Dev &d = b->d;
@@ -766,10 +772,20 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     UP(d.vinc_off, P.inc_off); UP(d.vinc, P.inc);
     UP(d.tseg_off, tseg_off); UP(d.tseg, tseg);
     UP(d.via_up, via_up); UP(d.tree_perm, tree_perm); UP(d.tree_chain, tree_chain);
-    d.n_chain_wg = (int)(lane_inst.size() / cWG);
+    if (n_lanes / cWG > (1LL << 30)) return fail(b, EM_ERR_ARG, "batch too large");
+    d.n_chain_wg = (int)(n_lanes / cWG);
     b->n_generic_trees = 0;
     for (int t = 0; t < nt; ++t) b->n_generic_trees += tree_chain[t] ? 0 : 1;
-    UP(d.lane_inst, lane_inst); UP(d.lane_blk, lane_blk);
+    {
+        int *li, *lb;
+        AL(li, int, n_lanes); AL(lb, int, n_lanes);
+        const int *pi, *pL;
+        const long long *po;
+        UP(pi, place_inst); UP(po, place_off); UP(pL, place_L);
+        launch_place_lanes(li, lb, n_lanes, pi, po, pL, (int)place_inst.size(), b->stream);
+        LAUNCHCHK(b);
+        d.lane_inst = li; d.lane_blk = lb;
+    }
 
     const size_t rs = b->fp32 ? 4 : 8;
     const size_t NS = (size_t)ns * S, RS = (size_t)nr * S, IS = (size_t)nt * S, VS = (size_t)nn * S;
@@ -805,14 +821,19 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     // The system the PCG iterates: the nodal network, or (multigrid on the
     // condensed network) its terminals with one reduced edge per two-ended
     // chain.
-    b->condensed = !b->trees_only && r->ir_precond == 2;
+    CondHost C;
+    if (!b->trees_only && r->ir_precond == 2) {
+        // condensed only where it removes at least a quarter of the nodes:
+        // below that the extra chain passes cost more than they save
+        C = cond_build(nn, nr, g->res_a, g->res_b, g->res_R0, is_pad.data());
+        b->condensed = (long long)C.n_term * 4 <= (long long)nn * 3;
+    }
     Dev &X = b->condensed ? b->rd : d;
     int xn = nn, xr = nr;
     std::vector<int> xoff, xres, xnbr, xra, xrb;
     std::vector<uint8_t> xpad, xlive0;
     std::vector<double> xR0;
     if (b->condensed) {
-        CondHost C = cond_build(nn, nr, g->res_a, g->res_b, g->res_R0, is_pad.data());
         xn = C.n_term;
         xr = (int)C.red_a.size();
         xra = C.red_a; xrb = C.red_b; xR0 = C.red_R0; xpad = C.red_pad;
@@ -968,6 +989,8 @@ em_status em_get_info(em_batch *b, em_info *info)
     info->step_kernel_ms = b->step_ms;
     info->cg_iters_total = b->cg_iters_total;
     info->ir_ms = b->ir_ms;
+    info->ir_sys_nodes = b->condensed ? b->n_term : b->n_nodes;
+    info->ir_sys_edges = b->condensed ? b->n_redge : b->n_res;
     unsigned int sc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (b->sur_ready) {
         HIPCHK(b, hipMemcpyAsync(sc, b->d.sur_cnt, 32, hipMemcpyDeviceToHost, b->stream));

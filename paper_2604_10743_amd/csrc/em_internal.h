@@ -236,6 +236,10 @@ void launch_amg_post0(const Dev &d, double *w0, const AmgLevel &L1, const double
 void launch_amg_setup(const Dev &d, const Amg &a, hipStream_t st);
 void launch_amg_vcycle(const Dev &d, const Amg &a, bool init, hipStream_t st);
 int ir_wg_max_nodes();
+// chain-kernel lane table: lane_inst = -1 everywhere, then instance i fills
+// lanes off[i] .. off[i] + L[i] - 1 with (inst[i], block 0 .. L[i] - 1)
+void launch_place_lanes(int *lane_inst, int *lane_blk, long long n_lanes, const int *inst,
+                        const long long *off, const int *L, int n_place, hipStream_t st);
 // condensed IR solve: chain reduction + reduced sinks and warm start; terminal
 // scatter + interior back-substitution into the nodal u and live
 void launch_chain_reduce(const Dev &d, const Dev &r, const Cond &c, hipStream_t st);

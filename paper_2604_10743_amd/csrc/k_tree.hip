@@ -992,4 +992,29 @@ void launch_catchup_done(const Dev &d, int step_lim, hipStream_t st)
     k_catchup_done<<<nblocks(d.n_trees * d.S), 256, 0, st>>>(d, step_lim);
 }
 
+// ---- chain-kernel lane table (built once per batch) ----
+__global__ void k_fill_i32(int *p, long long n, int v)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n) p[g] = v;
+}
+
+// one block per placed instance; its threads stride over the instance's lanes
+__global__ void k_place_lanes(int *lane_inst, int *lane_blk, const int *inst, const long long *off,
+                              const int *L)
+{
+    const int i = blockIdx.x;
+    for (int k = threadIdx.x; k < L[i]; k += blockDim.x) {
+        lane_inst[off[i] + k] = inst[i];
+        lane_blk[off[i] + k] = k;
+    }
+}
+
+void launch_place_lanes(int *lane_inst, int *lane_blk, long long n_lanes, const int *inst,
+                        const long long *off, const int *L, int n_place, hipStream_t st)
+{
+    if (n_lanes > 0) k_fill_i32<<<(int)((n_lanes + 255) / 256), 256, 0, st>>>(lane_inst, n_lanes, -1);
+    if (n_place > 0) k_place_lanes<<<n_place, 64, 0, st>>>(lane_inst, lane_blk, inst, off, L);
+}
+
 }  // namespace em

@@ -91,6 +91,11 @@ def test_condensed_network_with_opens_matches_direct_solve(em, oracle_mod, preco
     for s, (dR, op) in enumerate(states):
         B.set_seg_state(s, dR, op)
     drop = B.ir_solve()
+    info = B.info()
+    if precond == 2:
+        assert info["ir_sys_nodes"] * 4 < g.n_nodes      # condensed
+    else:
+        assert info["ir_sys_nodes"] == g.n_nodes
     for s, (dR, op) in enumerate(states):
         u_o, I_o, j_o, d_o = oracle_mod.ir_solve(g, g.res_R0 + dR, op)
         u = B.voltages(s)
