@@ -73,6 +73,19 @@ struct em_batch {
     Amg *amg_dev = nullptr;             // device copy of amg (one-workgroup PCG)
     bool use_amg = false;
     bool ir_wg = false;                 // multigrid PCG with one workgroup per sample
+    // compaction of the active instances (screen, learned screen): the list
+    // the forcing update walks and the lanes the chain kernel launches
+    bool act_dirty = true;              // inst_active may have changed since the last compaction
+    bool act_built = false;
+    int n_act = 0;
+    int *act_inst = nullptr;            // [IS] active instances, ascending
+    std::vector<uint8_t> act_prev;      // active flags at the last compaction
+    int *pl_inst = nullptr, *pl_L = nullptr;   // [IS] chain-lane placement (device staging)
+    long long *pl_off = nullptr;
+    std::vector<int> chain_L;           // lanes per instance of a chain tree (0: generic tree)
+    std::vector<int> tree_perm_h;
+    int chain_wg = 0;
+    long long lanes_cap = 0;            // lanes allocated for the chain kernel's table
     // chain condensation: the PCG iterates the terminal system rd; interior
     // voltages follow from the chains
     bool condensed = false;
@@ -289,6 +302,8 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
     return EM_OK;
 }
 
+em_status update_forcing(em_batch *b);
+
 em_status ir_solve_impl(em_batch *b)
 {
     Dev &d = b->d;
@@ -375,8 +390,9 @@ em_status ir_solve_impl(em_batch *b)
         b->cg_iters_last = itmax;
         if (b->condensed) launch_chain_expand(d, X, b->cond, st);
         launch_ir_finish(d, st);
-        launch_update_f(d, b->fp32, st);
         LAUNCHCHK(b);
+        em_status rf = update_forcing(b);
+        if (rf != EM_OK) return rf;
         b->have_j = true;
         b->ir_valid = true;
         return EM_OK;
@@ -429,8 +445,9 @@ em_status ir_solve_impl(em_batch *b)
     b->cg_iters_last = it;
     if (b->condensed) launch_chain_expand(d, X, b->cond, st);
     launch_ir_finish(d, st);
-    launch_update_f(d, b->fp32, st);
     LAUNCHCHK(b);
+    em_status rf = update_forcing(b);
+    if (rf != EM_OK) return rf;
     b->have_j = true;
     b->ir_valid = true;
     return EM_OK;
@@ -459,6 +476,107 @@ void fold_timers(em_batch *b)
     b->ir_pending = false;
 }
 
+// Active-instance compaction (after the screen, the learned screen's
+// deferrals and activations, a reset or a restore): the ascending list of
+// active instances for the forcing update, and the chain kernel's lane table
+// rebuilt over the active chain instances only (the kernel still checks the
+// flags, so a superset would also be correct).  Instances that became active
+// get their forcing from the present current densities.
+em_status ensure_active(em_batch *b)
+{
+    if (!b->act_dirty) return EM_OK;
+    Dev &d = b->d;
+    hipStream_t st = b->stream;
+    const int S = d.S;
+    const size_t IS = (size_t)d.n_trees * S;
+    std::vector<uint8_t> ia(IS), sa(S), cu;
+    HIPCHK(b, hipMemcpyAsync(ia.data(), d.inst_active, IS, hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipMemcpyAsync(sa.data(), d.sample_active, S, hipMemcpyDeviceToHost, st));
+    if (b->sur_ready) {
+        // instances activated by the learned screen are stepped in its
+        // catch-up replay before they rejoin the active set
+        cu.resize(IS);
+        HIPCHK(b, hipMemcpyAsync(cu.data(), d.catchup, IS, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(b, hipStreamSynchronize(st));
+    if (!cu.empty())
+        for (size_t i = 0; i < IS; ++i) ia[i] |= cu[i];
+    std::vector<int> lst, fresh;
+    if (b->act_prev.size() != IS) b->act_prev.assign(IS, 0);
+    for (size_t i = 0; i < IS; ++i) {
+        const uint8_t a = ia[i] && sa[i % S];
+        if (a) {
+            lst.push_back((int)i);
+            if (b->act_built && !b->act_prev[i]) fresh.push_back((int)i);
+        }
+        b->act_prev[i] = a;
+    }
+    b->n_act = (int)lst.size();
+    if (!lst.empty())
+        HIPCHK(b, hipMemcpyAsync(b->act_inst, lst.data(), 4 * lst.size(), hipMemcpyHostToDevice, st));
+    // lanes: the placement rule of the full table (an instance never
+    // straddles two workgroups), over the active chain instances
+    const int cWG = b->chain_wg;
+    std::vector<int> pi, pL;
+    std::vector<long long> po;
+    long long n_lanes = 0;
+    auto place = [&](bool all) {
+        pi.clear(); pL.clear(); po.clear();
+        n_lanes = 0;
+        int fill = 0;
+        for (int t : b->tree_perm_h) {
+            const int L = b->chain_L[t];
+            if (L == 0) continue;
+            for (int s = 0; s < S; ++s) {
+                const size_t inst = (size_t)t * S + s;
+                if (!all && !(ia[inst] && sa[s])) continue;
+                if (fill + L > cWG) { n_lanes += cWG - fill; fill = 0; }
+                pi.push_back((int)inst); po.push_back(n_lanes); pL.push_back(L);
+                n_lanes += L;
+                fill += L;
+            }
+        }
+        if (fill > 0) n_lanes += cWG - fill;
+    };
+    place(false);
+    if (n_lanes > b->lanes_cap) place(true);      // the creation-time table always fits
+    if (!pi.empty()) {
+        HIPCHK(b, hipMemcpyAsync(b->pl_inst, pi.data(), 4 * pi.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(b, hipMemcpyAsync(b->pl_off, po.data(), 8 * po.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(b, hipMemcpyAsync(b->pl_L, pL.data(), 4 * pL.size(), hipMemcpyHostToDevice, st));
+    }
+    launch_place_lanes(const_cast<int *>(d.lane_inst), const_cast<int *>(d.lane_blk), n_lanes, b->pl_inst,
+                       b->pl_off, b->pl_L, (int)pi.size(), st);
+    d.n_chain_wg = cWG > 0 ? (int)(n_lanes / cWG) : 0;
+    LAUNCHCHK(b);
+    HIPCHK(b, hipMemcpyAsync(b->d_dev, &d, sizeof(Dev), hipMemcpyHostToDevice, st));
+    HIPCHK(b, hipStreamSynchronize(st));          // host staging vectors go out of scope
+    if (!fresh.empty() && b->have_j) {
+        HIPCHK(b, hipMemcpyAsync(b->pl_inst, fresh.data(), 4 * fresh.size(), hipMemcpyHostToDevice, st));
+        launch_update_f_list(d, b->fp32, b->pl_inst, (int)fresh.size(), st);
+        LAUNCHCHK(b);
+        HIPCHK(b, hipStreamSynchronize(st));
+    }
+    b->act_dirty = false;
+    b->act_built = true;
+    return EM_OK;
+}
+
+// dt*f from the present current densities: every node, or (when few are
+// active) the nodes of the active instances only.
+em_status update_forcing(em_batch *b)
+{
+    em_status rc = ensure_active(b);
+    if (rc != EM_OK) return rc;
+    Dev &d = b->d;
+    if ((long long)b->n_act * 4 < (long long)d.n_trees * d.S)
+        launch_update_f_list(d, b->fp32, b->act_inst, b->n_act, b->stream);
+    else
+        launch_update_f(d, b->fp32, b->stream);
+    LAUNCHCHK(b);
+    return EM_OK;
+}
+
 // Step the instances that `dd.inst_active` marks (the batch's own set, or the
 // catch-up set of the learned screen with dd a modified copy of the batch's Dev).
 em_status timed_step_dev(em_batch *b, const Dev &dd, int n_steps, int step0)
@@ -476,7 +594,12 @@ em_status timed_step_dev(em_batch *b, const Dev &dd, int n_steps, int step0)
     return EM_OK;
 }
 
-em_status timed_step(em_batch *b, int n_steps, int step0) { return timed_step_dev(b, b->d, n_steps, step0); }
+em_status timed_step(em_batch *b, int n_steps, int step0)
+{
+    em_status rc = ensure_active(b);
+    if (rc != EM_OK) return rc;
+    return timed_step_dev(b, b->d, n_steps, step0);
+}
 
 em_status timed_ir(em_batch *b)
 {
@@ -545,6 +668,7 @@ em_status sur_evaluate(em_batch *b, double thr, int64_t *n_def, bool screen_curr
     HIPCHK(b, hipMemsetAsync(d.sur_cnt, 0, 32, b->stream));
     launch_defer(d, b->sur_y, thr, b->stream);
     LAUNCHCHK(b);
+    b->act_dirty = true;
     unsigned int *h = (unsigned int *)pinned(b, 32);
     if (!h) return fail(b, EM_ERR_OOM, "pinned host buffer");
     HIPCHK(b, hipMemcpyAsync(h, d.sur_cnt, 32, hipMemcpyDeviceToHost, b->stream));
@@ -573,6 +697,9 @@ em_status sur_catch_up(em_batch *b, int k, int n_new)
 {
     Dev &d = b->d;
     const int K = b->run.ir_every;
+    b->act_dirty = true;                  // the activated (catch-up) instances join the lane table
+    em_status rc0 = ensure_active(b);
+    if (rc0 != EM_OK) return rc0;
     Dev dr = d;
     dr.inst_active = d.catchup;
     for (int i = 0; i < k; ++i) {
@@ -776,6 +903,17 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     d.n_chain_wg = (int)(n_lanes / cWG);
     b->n_generic_trees = 0;
     for (int t = 0; t < nt; ++t) b->n_generic_trees += tree_chain[t] ? 0 : 1;
+    b->chain_wg = cWG;
+    b->lanes_cap = n_lanes;
+    b->tree_perm_h = tree_perm;
+    b->chain_L.assign(nt, 0);
+    for (int t = 0; t < nt; ++t)
+        if (tree_chain[t]) b->chain_L[t] = (P.tree_off[t + 1] - P.tree_off[t] + cM - 1) / cM;
+    {
+        const size_t ISb = (size_t)nt * S;
+        AL(b->act_inst, int, ISb); AL(b->pl_inst, int, ISb); AL(b->pl_L, int, ISb);
+        AL(b->pl_off, long long, ISb);
+    }
     {
         int *li, *lb;
         AL(li, int, n_lanes); AL(lb, int, n_lanes);
@@ -798,7 +936,9 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     AL(d.psi, double, NS);
     if (b->n_generic_trees > 0) { AL(d.wsp, double, NS); } else { d.wsp = nullptr; }
     AL(d.xi_k, double, RS); AL(d.xi_s, double, RS);
-    AL(d.jseg, double, RS); AL(d.dR, double, RS); AL(d.open, uint8_t, RS); AL(d.seg_mortal, uint8_t, RS);
+    AL(d.jseg, double, RS);
+    if (S > 1) AL(d.jT, double, RS);
+    AL(d.dR, double, RS); AL(d.open, uint8_t, RS); AL(d.seg_mortal, uint8_t, RS);
     AL(d.inst_active, uint8_t, IS); AL(d.tree_mortal, uint8_t, IS); AL(d.nv, int, IS);
     AL(d.vnode, int, IS * MAXV); AL(d.vseg, int, IS * MAXV); AL(d.vphase, int, IS * MAXV);
     AL(d.vstep, int, IS * MAXV); AL(d.vearly, int, IS * MAXV);
@@ -1025,6 +1165,7 @@ em_status em_screen(em_batch *b, uint8_t *tree_mortal)
     if (!b->have_j) return fail(b, EM_ERR_STATE, "no current densities yet (call em_ir_solve first)");
     launch_screen(b->d, true, b->stream);
     LAUNCHCHK(b);
+    b->act_dirty = true;
     if (tree_mortal) {
         // device layout is [tree][sample]; output is [sample][tree]
         std::vector<uint8_t> tmp((size_t)b->n_trees * b->S);
@@ -1070,6 +1211,7 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
     launch_ttf_init(d, fail_frac, st);
     if (b->run.screen) launch_screen(d, true, st);
     LAUNCHCHK(b);
+    b->act_dirty = true;
     const int n_steps = b->run.n_steps, K = b->run.ir_every;
     const bool sur = b->sur != nullptr;
     if (sur) {
@@ -1176,6 +1318,7 @@ em_status em_reset(em_batch *b)
     HIPCHK(b, hipMemsetAsync(d.n_suppressed, 0, 4 * IS, st));
     HIPCHK(b, hipMemsetAsync(d.inst_active, 1, IS, st));
     HIPCHK(b, hipMemsetAsync(d.sample_active, 1, d.S, st));
+    b->act_dirty = true;
     HIPCHK(b, hipMemsetAsync(d.dR, 0, 8 * RS, st));
     HIPCHK(b, hipMemsetAsync(d.open, 0, RS, st));
     HIPCHK(b, hipMemsetAsync(d.ev_count, 0, 4, st));
@@ -1520,6 +1663,7 @@ em_status em_restore(em_batch *b, const void *host_buf, size_t n)
     for (uint8_t o : op) b->any_open |= o != 0;
     b->live_dirty = true;
     b->ir_valid = false;
+    b->act_dirty = true;
     HIPCHK(b, hipMemsetAsync(b->d.open_dirty, 0, 4, b->stream));
     if (b->have_j) launch_update_f(b->d, b->fp32, b->stream);
     launch_factor(b->d, b->fp32, b->stream);

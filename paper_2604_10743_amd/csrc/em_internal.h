@@ -69,6 +69,7 @@ struct Dev {
     double *xi_k, *xi_s;
     // ---- per (sample, segment) ----
     double *jseg;                       // [S][res]
+    double *jT;                         // [res][S] transposed copy of jseg for the forcing update (S > 1)
     double *dR;                         // [S][res]
     uint8_t *open;                      // [S][res]
     uint8_t *seg_mortal;                // [S][res]

@@ -190,7 +190,7 @@ EM_KERNEL void k_node_sc(Dev d)
 __device__ inline double edge_phi(const Dev &d, int i, int s)
 {
     int e = d.seg[i];
-    double j = d.jseg[(size_t)s * d.n_res + e];
+    double j = d.S == 1 ? d.jseg[e] : d.jT[(size_t)e * d.S + s];
     double Sd = E_CHG * d.Z * d.rho * j / d.Omega;
     return d.dir[i] * d.xi_k[(size_t)e * d.S + s] * d.gdx0[i] * (Sd + d.mdrv[i]);
 }
@@ -201,6 +201,30 @@ __device__ inline double node_dtf(const Dev &d, int i, int s)
     if (d.parent[i] >= 0) f += edge_phi(d, i, s);
     for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k) f -= edge_phi(d, d.child[k], s);
     return d.dt * f;
+}
+
+// jT = jseg transposed ([S][res] -> [res][S]) through 32 x 32 LDS tiles, so
+// that the forcing update reads the current density of a segment for
+// consecutive samples from consecutive addresses
+__global__ __launch_bounds__(256) void k_transpose_j(Dev d, const double *jseg)
+{
+    __shared__ double tile[32][33];
+    const int r0 = blockIdx.x * 32, s0 = blockIdx.y * 32, tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int k = ty; k < 32; k += 8) {
+        const int s = s0 + k, r = r0 + tx;
+        if (s < d.S && r < d.n_res) tile[k][tx] = jseg[(size_t)s * d.n_res + r];
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int r = r0 + k, s = s0 + tx;
+        if (r < d.n_res && s < d.S) d.jT[(size_t)r * d.S + s] = tile[tx][k];
+    }
+}
+
+static void transpose_j(const Dev &d, hipStream_t st)
+{
+    if (d.S == 1) return;
+    k_transpose_j<<<dim3((d.n_res + 31) / 32, (d.S + 31) / 32), 256, 0, st>>>(d, d.jseg);
 }
 
 template <typename R>
@@ -911,6 +935,7 @@ void launch_node_sc(const Dev &d, bool fp32, hipStream_t st)
 void launch_update_f(const Dev &d, bool fp32, hipStream_t st)
 {
     long long n = (long long)d.ns * d.S;
+    transpose_j(d, st);
     if (fp32) k_update_f<float><<<nblocks(n), 256, 0, st>>>(d);
     else k_update_f<double><<<nblocks(n), 256, 0, st>>>(d);
 }
@@ -980,6 +1005,7 @@ void launch_defer(const Dev &d, const float *y, double thr, hipStream_t st)
 void launch_update_f_list(const Dev &d, bool fp32, const int *list, int n, hipStream_t st)
 {
     if (n <= 0) return;
+    transpose_j(d, st);
     if (fp32) k_update_f_list<float><<<n, 256, 0, st>>>(d, list);
     else k_update_f_list<double><<<n, 256, 0, st>>>(d, list);
 }
