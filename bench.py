@@ -13,8 +13,9 @@ trees of stress nodes x steps, divided by wall time).  Also reported: the
 roofline of the dominant kernel (the stepping kernel, timed with HIP events on
 its own stream inside the library), the plain FP64 GPU form (one tree per
 lane, FP64) over one aging interval, the FP64 oracle on host cores over a
-bounded sample of the same workload, and a Monte Carlo samples/s figure on the
-32x32 mesh with 1024 samples.
+bounded sample of the same workload, and Monte Carlo samples/s to TTF with 1024
+samples on the 96x96 sparse-via grid (failures within the horizon; checked
+against the FP64 oracle on 64 samples) and on the 32x32 mesh.
 """
 from __future__ import annotations
 
@@ -144,6 +145,94 @@ def surrogate_leg(args):
                          "calibration_shift_decades": shift}}
 
 
+MC_DESC = {
+    "mc_grid": "96x96 two-layer sparse-via P/G grid (via every 32 nodes, 16 pads, 12309 nodes, "
+               "169 line trees), 330 K + 6 hotspots, worst initial drop 7 %",
+    "mc_mesh": "32x32 two-layer mesh with 4 corner pads, M1 rows cut into 213 trees, 378 K",
+}
+
+
+def mc_leg(args, name, oracle, plain):
+    """Monte Carlo samples/s to TTF: batch creation and the run of every
+    sample to its 10 % IR-drop failure or the 10-year horizon, FP32 stepping,
+    steady-state screen on.  One untimed run first (code paths warm), then the
+    timed one.  With ``oracle``: every 16th sample (64) recomputed by the FP64
+    CPU oracle, compared and timed (the CPU baseline of this metric).  With
+    ``plain``: the plain FP64 GPU form (generic tree kernel, no screen,
+    Jacobi-CG on the nodal system) on a subset of the samples."""
+    import numpy as np
+    import torch
+    import paper_2604_10743_amd as P
+    from paper_2604_10743_amd import synth
+
+    g, mat, run, mc = synth.workload(name)
+    mc = dict(mc, n_samples=args.mc_samples)
+    S = mc["n_samples"]
+
+    def one(run_, mc_):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B = P.Batch(g, mat, run_, mc_)
+        res = B.run_to_ttf()
+        torch.cuda.synchronize()
+        return B, res, time.perf_counter() - t0
+
+    B, _, _ = one(run, mc)
+    B.close()
+    B, res, wall = one(run, mc)
+    info = B.info()
+    segs = {s: B.failed_segments(s) for s in range(0, S, 16)}
+    B.close()
+    ttf = np.array([r["ttf_s"] for r in res if r["failed"]])
+    yr = 365.25 * 86400.0
+    o = {"metric": "MC samples/s to TTF", "value": S / wall, "unit": "samples/s",
+         "workload": f"{name}: {MC_DESC[name]}; {S} samples, 20% lognormal CoV on kappa and sigma_crit, "
+                     "2000 BE steps over 10 y, IR re-solve every 100 steps, FP32 stepping, screen on",
+         "wall_s": wall, "n_fail": int(ttf.size), "n_censored": int(S - ttf.size),
+         "ttf_mean_y": float(ttf.mean() / yr) if ttf.size else None,
+         "ttf_cov": float(ttf.std(ddof=1) / ttf.mean()) if ttf.size > 1 else None,
+         "final_drop_mean": float(np.mean([r["final_drop"] for r in res])),
+         "node_steps": info["node_steps"], "ir_ms": info["ir_ms"], "step_kernel_ms": info["step_kernel_ms"],
+         "ir_system_nodes": info["ir_sys_nodes"], "cg_iters_total": info["cg_iters_total"]}
+    if oracle:
+        from oracle import oracle as O
+        O.build(force=False)
+        topo = O.topology(g, run["intervals_per_seg"])
+        t0 = time.perf_counter()
+        refs = {s: O.run_sample(g, mat, run, mc, s, topo=topo) for s in range(0, S, 16)}
+        t_or = time.perf_counter() - t0
+        n_cmp = n_guard = flag_mis = seg_mis = 0
+        e_ttf = e_fd = 0.0
+        for s, ref in refs.items():
+            r = res[s]
+            if np.min(np.abs(np.asarray(ref["drops"]) - run["fail_frac"])) < 2e-3 * run["fail_frac"]:
+                n_guard += 1
+                continue
+            n_cmp += 1
+            flag_mis += int(r["failed"] != ref["failed"])
+            e_fd = max(e_fd, abs(r["final_drop"] - ref["final_drop"]) / ref["final_drop"])
+            if r["failed"] and ref["failed"]:
+                e_ttf = max(e_ttf, abs(r["ttf_s"] - ref["ttf"]) / ref["ttf"])
+            seg_mis += int(not np.array_equal(segs[s], ref["failed_segs"]))
+        o["vs_fp64_oracle"] = {"samples": len(refs), "compared": n_cmp, "guard_band_skipped": n_guard,
+                               "failure_flag_mismatches": flag_mis, "failed_segment_set_mismatches": seg_mis,
+                               "max_rel_err_ttf": e_ttf, "max_rel_err_final_drop": e_fd,
+                               "oracle_failed": int(sum(refs[s]["failed"] for s in refs))}
+        o["cpu_baseline"] = {"value": len(refs) / t_or, "unit": "samples/s", "cores": 1, "kind": "oracle",
+                             "sample": f"every 16th of the {S} samples ({len(refs)}), FP64 oracle, "
+                                      f"{t_or:.1f} s incl. its IR direct solves"}
+    if plain:
+        Sp = min(64, S)
+        runp = dict(run, prec=0, stepper=1, screen=0, ir_precond=0)
+        Bp, resp, wp = one(runp, dict(mc, n_samples=Sp))
+        Bp.close()
+        o["plain_fp64_gpu"] = {"value": Sp / wp, "unit": "samples/s",
+                               "sample": f"first {Sp} samples, FP64, generic tree kernel, every tree stepped, "
+                                         "Jacobi-preconditioned CG on the nodal system",
+                               "speedup_of_value": (S / wall) / (Sp / wp)}
+    return o
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,25 +337,10 @@ def main():
     B.close()
 
     if not args.no_mc:
-        gm, matm, runm, mcm = synth.workload("mc_mesh")
-        mcm = dict(mcm, n_samples=args.mc_samples)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        Bm = P.Batch(gm, matm, runm, mcm)
-        res = Bm.run_to_ttf()
-        torch.cuda.synchronize()
-        tm = time.perf_counter() - t0
-        ttf = np.array([r["ttf_s"] for r in res if r["failed"]])
-        im = Bm.info()
-        out["mc"] = {"metric": "MC samples/s to TTF", "value": args.mc_samples / tm, "unit": "samples/s",
-                     "workload": f"mc_mesh: 32x32 two-layer mesh, cut M1 rows, {im['n_trees']} trees, "
-                                 f"{args.mc_samples} samples, 20% CoV on kappa and sigma_crit, FP32, screen on",
-                     "wall_s": tm, "n_fail": int(ttf.size), "n_censored": int(len(res) - ttf.size),
-                     "ttf_mean": float(ttf.mean()) if ttf.size else None,
-                     "ttf_cov": float(ttf.std(ddof=1) / ttf.mean()) if ttf.size > 1 else None,
-                     "node_steps": im["node_steps"]}
-        Bm.close()
-        log("bench: mc done")
+        out["mc"] = mc_leg(args, "mc_grid", oracle=not args.no_cpu, plain=not args.no_plain)
+        log("bench: mc (mc_grid) done")
+        out["mc_mesh"] = mc_leg(args, "mc_mesh", oracle=False, plain=False)
+        log("bench: mc (mc_mesh) done")
 
     if not args.no_sur:
         out["surrogate"] = surrogate_leg(args)
