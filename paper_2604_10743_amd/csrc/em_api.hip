@@ -86,6 +86,7 @@ struct em_batch {
     std::vector<int> tree_perm_h;
     int chain_wg = 0;
     long long lanes_cap = 0;            // lanes allocated for the chain kernel's table
+    int *res_cnt = nullptr;             // [S][2] per-sample result counts (device)
     // chain condensation: the PCG iterates the terminal system rd; interior
     // voltages follow from the chains
     bool condensed = false;
@@ -309,6 +310,10 @@ em_status ir_solve_impl(em_batch *b)
     Dev &d = b->d;
     hipStream_t st = b->stream;
     HIPCHK(b, hipMemsetAsync(d.g_changed, 0, 4, st));
+    // per-sample change flags: samples whose conductances are those of the
+    // last solve keep its solution (every sample counts as changed when the
+    // state was replaced since: creation, reset, restore, set_seg_state)
+    HIPCHK(b, hipMemsetAsync(d.g_chg_s, b->ir_valid ? 0 : 1, d.S, st));
     launch_ir_conductance(d, st);
     LAUNCHCHK(b);
     if (b->ir_valid && !b->live_dirty) {
@@ -912,6 +917,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     {
         const size_t ISb = (size_t)nt * S;
         AL(b->act_inst, int, ISb); AL(b->pl_inst, int, ISb); AL(b->pl_L, int, ISb);
+        AL(b->res_cnt, int, 2 * (size_t)S);
         AL(b->pl_off, long long, ISb);
     }
     {
@@ -951,7 +957,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     HIPCHK(b, hipEventCreate(&b->ev_a)); HIPCHK(b, hipEventCreate(&b->ev_b));
     HIPCHK(b, hipEventCreate(&b->ev_c)); HIPCHK(b, hipEventCreate(&b->ev_d));
     AL(d.G, double, RS); AL(d.u, double, VS);
-    AL(d.live, uint8_t, VS); AL(d.g_changed, uint32_t, 1);
+    AL(d.live, uint8_t, VS); AL(d.g_changed, uint32_t, 1); AL(d.g_chg_s, uint8_t, S);
     d.ir_nblk = (nn + ir_nodes_per_block() - 1) / ir_nodes_per_block();
     AL(d.part, double, (size_t)S * d.ir_nblk * 4);
     AL(d.drop, double, S);
@@ -1278,30 +1284,23 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
     b->n_outer_done = k;
     // per-sample results
     std::vector<double> ttf(S), fd(S), idr(S);
-    std::vector<int> failed(S), oidx(S), nv((size_t)b->n_trees * S);
-    std::vector<double> dR((size_t)S * b->n_res);
-    std::vector<uint8_t> op((size_t)S * b->n_res);
+    std::vector<int> failed(S), oidx(S), cnt(2 * (size_t)S);
+    launch_result_counts(d, b->res_cnt, st);
+    LAUNCHCHK(b);
     HIPCHK(b, hipMemcpyAsync(ttf.data(), d.ttf, 8 * S, hipMemcpyDeviceToHost, st));
     HIPCHK(b, hipMemcpyAsync(fd.data(), d.final_drop, 8 * S, hipMemcpyDeviceToHost, st));
     HIPCHK(b, hipMemcpyAsync(idr.data(), d.init_drop, 8 * S, hipMemcpyDeviceToHost, st));
     HIPCHK(b, hipMemcpyAsync(failed.data(), d.failed, 4 * S, hipMemcpyDeviceToHost, st));
     HIPCHK(b, hipMemcpyAsync(oidx.data(), d.outer_idx, 4 * S, hipMemcpyDeviceToHost, st));
-    HIPCHK(b, hipMemcpyAsync(nv.data(), d.nv, 4 * nv.size(), hipMemcpyDeviceToHost, st));
-    HIPCHK(b, hipMemcpyAsync(dR.data(), d.dR, 8 * dR.size(), hipMemcpyDeviceToHost, st));
-    HIPCHK(b, hipMemcpyAsync(op.data(), d.open, op.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(b, hipMemcpyAsync(cnt.data(), b->res_cnt, 8 * (size_t)S, hipMemcpyDeviceToHost, st));
     HIPCHK(b, hipStreamSynchronize(st));
     fold_timers(b);
     for (int s = 0; s < S; ++s) {
         em_ttf_result &o = out[s];
         o.ttf_s = ttf[s]; o.final_drop = fd[s]; o.init_drop = idr[s];
         o.failed = failed[s]; o.outer_idx = oidx[s];
-        int nn = 0;
-        for (int t = 0; t < b->n_trees; ++t) nn += nv[(size_t)t * S + s] > 0;
-        o.n_nucleated_trees = nn;
-        int nf = 0;
-        for (int e = 0; e < b->n_res; ++e)
-            nf += (dR[(size_t)s * b->n_res + e] > 0.0) || op[(size_t)s * b->n_res + e];
-        o.n_failed_segs = nf;
+        o.n_nucleated_trees = cnt[2 * (size_t)s];
+        o.n_failed_segs = cnt[2 * (size_t)s + 1];
     }
     return EM_OK;
 }

@@ -95,6 +95,7 @@ struct Dev {
     uint8_t *live;                      // [S][n_nodes]
     uint32_t *live_changed;
     uint32_t *g_changed;                // [1] some conductance differs from the last solve's
+    uint8_t *g_chg_s;                   // [S] this sample's conductances differ (or: first solve)
     int *cc_label;                      // [S][n_nodes + 1] component labels (reachability)
     double *part;                       // [S][nblk][4] block partial sums
     double *rz;                         // [2][S] r.z, double-buffered by iteration parity
@@ -249,6 +250,8 @@ void launch_ir_pcg_wg(const Dev &d, const Amg *amg_dev, double rtol, int max_ite
 void launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
 void launch_ttf_init(const Dev &d, double fail, hipStream_t st);
 void launch_ttf_update(const Dev &d, double fail, int k, double t, hipStream_t st);
+// cnt[2s] = trees of sample s holding a void, cnt[2s+1] = segments with dR > 0 or open
+void launch_result_counts(const Dev &d, int *cnt, hipStream_t st);
 
 // learned screen
 void launch_tree_static(const Dev &d, hipStream_t st);                 // tstat, rdist

@@ -213,7 +213,7 @@ __device__ inline double g0(const Dev &d, const Amg0 &z, int s, int e)
 __global__ __launch_bounds__(AMG_BS) void k_amg_asm_nodes(Dev d, Amg0 z, AmgLevel L, AmgLevel F, int lvl)
 {
     int I = blockIdx.x * AMG_BS + threadIdx.x, s = blockIdx.y;
-    if (I >= L.n) return;
+    if (I >= L.n || d.conv[s]) return;
     double acc = 0.0;
     for (int k = L.mem_off[I]; k < L.mem_off[I + 1]; ++k) {
         int m = L.mem[k];
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(AMG_BS) void k_amg_asm_nodes(Dev d, Amg0 z, AmgLeve
 __global__ __launch_bounds__(AMG_BS) void k_amg_asm_edges(Dev d, Amg0 z, AmgLevel L, AmgLevel F, int lvl)
 {
     int E = blockIdx.x * AMG_BS + threadIdx.x, s = blockIdx.y;
-    if (E >= L.ne) return;
+    if (E >= L.ne || d.conv[s]) return;
     double acc = 0.0;
     for (int k = L.src_off[E]; k < L.src_off[E + 1]; ++k) {
         int e = L.src_e[k];
@@ -241,11 +241,12 @@ __global__ __launch_bounds__(AMG_BS) void k_amg_asm_edges(Dev d, Amg0 z, AmgLeve
 
 // Dense inverse of the coarsest operator of one sample (Gauss-Jordan in LDS,
 // no pivoting: the operator is symmetric positive definite), symmetrised.
-__global__ __launch_bounds__(AMG_BS) void k_amg_coarse_inv(AmgLevel C, double *Ainv)
+__global__ __launch_bounds__(AMG_BS) void k_amg_coarse_inv(AmgLevel C, double *Ainv, const uint8_t *conv)
 {
     __shared__ double A[AMG_NC_MAX][AMG_NC_MAX];
     __shared__ double prow[AMG_NC_MAX], pcol[AMG_NC_MAX];
     const int s = blockIdx.x, n = C.n, t = threadIdx.x;
+    if (conv[s]) return;                    // converged samples take no V-cycle
     for (int k = t; k < n * n; k += AMG_BS) A[k / n][k % n] = 0.0;
     __syncthreads();
     for (int i = t; i < n; i += AMG_BS) {
@@ -358,7 +359,7 @@ void launch_amg_setup(const Dev &d, const Amg &a, hipStream_t st)
         k_amg_asm_nodes<<<grid_of(L.n, d.S), AMG_BS, 0, st>>>(d, a.l0, L, F, l);
         if (L.ne > 0) k_amg_asm_edges<<<grid_of(L.ne, d.S), AMG_BS, 0, st>>>(d, a.l0, L, F, l);
     }
-    if (a.dense) k_amg_coarse_inv<<<d.S, AMG_BS, 0, st>>>(a.lev[a.nlev], a.Ainv);
+    if (a.dense) k_amg_coarse_inv<<<d.S, AMG_BS, 0, st>>>(a.lev[a.nlev], a.Ainv, d.conv);
 }
 
 void launch_amg_vcycle(const Dev &d, const Amg &a, bool init, hipStream_t st)

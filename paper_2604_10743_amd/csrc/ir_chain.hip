@@ -148,7 +148,7 @@ __global__ __launch_bounds__(CH_BS) void k_chain_reduce(Dev d, Dev r, Cond c)
     long long g = (long long)blockIdx.x * CH_BS + threadIdx.x;
     if (g >= (long long)d.S * c.n_chain) return;
     const int s = (int)(g / c.n_chain), ch = (int)(g % c.n_chain);
-    if (!d.sample_active[s]) return;
+    if (!d.sample_active[s] || !d.g_chg_s[s]) return;    // unchanged: as at the last solve
     const double *G = d.G + (size_t)s * d.n_res;
     const int e0 = c.eoff[ch], v0 = c.voff[ch], m = c.voff[ch + 1] - v0;
     const bool two = c.cB[ch] >= 0;
@@ -185,6 +185,7 @@ __global__ __launch_bounds__(CH_BS) void k_red_assemble(Dev d, Dev r, Cond c)
     long long g = (long long)blockIdx.x * CH_BS + threadIdx.x;
     if (g >= (long long)d.S * c.n_term) return;
     const int s = (int)(g / c.n_term), t = (int)(g % c.n_term);
+    if (!d.g_chg_s[s]) return;
     const int node = c.term_node[t];
     double acc = d.sink[node];
     const double *ci = c.cinj + (size_t)s * c.n_chain * 2;
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(CH_BS) void k_red_scatter(Dev d, Dev r, Cond c)
     long long g = (long long)blockIdx.x * CH_BS + threadIdx.x;
     if (g >= (long long)d.S * c.n_term) return;
     const int s = (int)(g / c.n_term), t = (int)(g % c.n_term);
-    if (!d.sample_active[s]) return;
+    if (!d.sample_active[s] || !d.g_chg_s[s]) return;    // unchanged: as at the last solve
     const size_t x = (size_t)s * d.n_nodes + c.term_node[t];
     const bool pad = r.is_pad[t], live = pad || r.live[g];
     d.u[x] = pad ? d.vdd : (live ? r.u[g] : 0.0);
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(CH_BS) void k_chain_backsub(Dev d, Cond c)
     long long g = (long long)blockIdx.x * CH_BS + threadIdx.x;
     if (g >= (long long)d.S * c.n_chain) return;
     const int s = (int)(g / c.n_chain), ch = (int)(g % c.n_chain);
-    if (!d.sample_active[s]) return;
+    if (!d.sample_active[s] || !d.g_chg_s[s]) return;    // unchanged: as at the last solve
     const double *G = d.G + (size_t)s * d.n_res;
     double *u = d.u + (size_t)s * d.n_nodes;
     uint8_t *live = d.live + (size_t)s * d.n_nodes;

@@ -89,6 +89,7 @@ EM_KERNEL void k_ir_conductance(Dev d)
     if (Gn != d.G[g]) {
         d.G[g] = Gn;
         *d.g_changed = 1u;
+        d.g_chg_s[g / d.n_res] = 1;
     }
 }
 
@@ -363,6 +364,7 @@ EM_KERNEL void k_ir_pupdate(Dev d, int it, double rtol, const double *zs)
 EM_KERNEL void k_ir_finish_nodes(Dev d)
 {
     int s = blockIdx.y, bx = blockIdx.x;
+    if (!d.g_chg_s[s]) return;              // voltages as at the last solve
     double dm = -INFINITY;
     for (int c = 0; c < IR_NPT; ++c) {
         int i = bx * IR_NPB + c * IR_BS + threadIdx.x;
@@ -386,6 +388,7 @@ EM_KERNEL void k_ir_finish_nodes(Dev d)
 EM_KERNEL void k_ir_finalize_drop(Dev d)
 {
     int s = blockIdx.x;
+    if (!d.g_chg_s[s]) return;
     double m = -INFINITY;
     for (int b = threadIdx.x; b < d.ir_nblk; b += 64)
         m = fmax(m, d.part[((size_t)s * d.ir_nblk + b) * 4 + 0]);
@@ -399,7 +402,7 @@ EM_KERNEL void k_ir_currents(Dev d)
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long long)d.S * d.n_res) return;
     int s = (int)(g / d.n_res), r = (int)(g % d.n_res);
-    if (!d.sample_active[s]) return;
+    if (!d.sample_active[s] || !d.g_chg_s[s]) return;
     const double *u = d.u + (size_t)s * d.n_nodes;
     double I = (u[d.ra[r]] - u[d.rb[r]]) * d.G[g];
     d.jseg[g] = I / (d.w[r] * d.h[r]);
@@ -525,6 +528,32 @@ void launch_fill_f64(double *p, size_t n, double v, hipStream_t st)
 void launch_ttf_init(const Dev &d, double fail, hipStream_t st)
 {
     k_ttf_init<<<nb(d.S), IR_BS, 0, st>>>(d, fail);
+}
+// Per-sample result counts (one block per sample): segments with a
+// resistance change or open, and trees holding a void.
+EM_KERNEL void k_result_counts(Dev d, int *cnt)
+{
+    const int s = blockIdx.x;
+    int nf = 0, nt = 0;
+    for (int e = threadIdx.x; e < d.n_res; e += IR_BS) {
+        const size_t x = (size_t)s * d.n_res + e;
+        nf += (d.dR[x] > 0.0 || d.open[x]) ? 1 : 0;
+    }
+    for (int t = threadIdx.x; t < d.n_trees; t += IR_BS) nt += d.nv[(size_t)t * d.S + s] > 0 ? 1 : 0;
+    __shared__ int red[2][IR_BS / 64];
+    for (int o = 32; o > 0; o >>= 1) { nf += __shfl_xor(nf, o, 64); nt += __shfl_xor(nt, o, 64); }
+    if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = nf; red[1][threadIdx.x >> 6] = nt; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int a = 0, b = 0;
+        for (int w = 0; w < IR_BS / 64; ++w) { a += red[0][w]; b += red[1][w]; }
+        cnt[2 * s] = b;
+        cnt[2 * s + 1] = a;
+    }
+}
+void launch_result_counts(const Dev &d, int *cnt, hipStream_t st)
+{
+    k_result_counts<<<d.S, IR_BS, 0, st>>>(d, cnt);
 }
 void launch_ttf_update(const Dev &d, double fail, int k, double t, hipStream_t st)
 {
