@@ -132,6 +132,11 @@ typedef struct {
                                     graph; 2 one workgroup per sample running its whole PCG in
                                     one launch.  Same preconditioner and stopping rule; the
                                     reduction order of the dot products differs. */
+    int32_t chain_wg;            /* lanes per workgroup of the resident chain kernel: 0 automatic
+                                    (the smallest of 256, 512, 1024 that holds the longest chain
+                                    tree), or one of those (at most 512 in FP64) that holds it.
+                                    Results do not depend on it (instances never share a
+                                    reduction: the couplings across their boundaries are zero). */
 } em_run_params;
 
 /* Monte Carlo (Sec. IV-F): per-segment unit-mean lognormal multipliers on
@@ -251,6 +256,21 @@ em_status em_get_seg_state(em_batch *b, int32_t sample, double *dR, uint8_t *ope
  * degradation state.  dR [n_res] finite and >= 0, open [n_res] 0 or 1; host
  * arrays, copied.  Void growth during later steps adds to this dR. */
 em_status em_set_seg_state(em_batch *b, int32_t sample, const double *dR, const uint8_t *open);
+/* Autotuner: on a batch at t = 0 (just created or reset), time every
+ * launch shape this batch can use -- each feasible chain-kernel workgroup
+ * size over n_steps steps of the screened instances, and (multigrid IR) the
+ * multi-kernel and the one-workgroup-per-sample PCG on a cold solve -- keep
+ * the fastest of each and reset the batch.  Results do not depend on the
+ * choice beyond the rounding of the IR dot products.  out may be NULL. */
+typedef struct {
+    int32_t chain_wg;            /* chosen lanes per workgroup */
+    int32_t ir_launch;           /* chosen IR launch shape (1 or 2; 0: not tuned) */
+    int32_t n_wg;                /* candidates tried */
+    int32_t wg[4];
+    double wg_ms[4];             /* stream time of the n_steps steps per candidate */
+    double ir_ms[2];             /* cold IR solve: multi-kernel, one workgroup per sample (-1: not tried) */
+} em_tune_info;
+em_status em_autotune(em_batch *b, int32_t n_steps, em_tune_info *out);
 /* Per-node temperature, control volume and critical stress for one sample. */
 em_status em_get_node_state(em_batch *b, int32_t sample, double *T, double *V, double *sc);
 /* Nucleation events, each 5 int32: sample, tree, step, node, host segment;

@@ -29,7 +29,7 @@ API = ["em_batch_create", "em_batch_destroy", "em_get_info", "em_last_error", "e
        "em_reset", "em_mlp_create", "em_mlp_destroy", "em_mlp_last_error", "em_mlp_num_params",
        "em_mlp_set_params", "em_mlp_get_params", "em_mlp_forward", "em_mlp_grad",
        "em_mlp_train_step", "em_features", "em_surrogate_screen", "em_get_surrogate",
-       "em_first_nucleation", "em_get_failed_segments", "em_snapshot", "em_restore"]
+       "em_first_nucleation", "em_get_failed_segments", "em_snapshot", "em_restore", "em_autotune"]
 
 
 class EmError(RuntimeError):
@@ -61,7 +61,8 @@ class RunParams(C.Structure):
                 ("n_steps", C.c_int32), ("ir_every", C.c_int32), ("fail_frac", C.c_double),
                 ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32), ("prec", C.c_int32),
                 ("screen", C.c_int32), ("max_voids_per_tree", C.c_int32), ("T_ambient", C.c_double),
-                ("stepper", C.c_int32), ("ir_precond", C.c_int32), ("ir_launch", C.c_int32)]
+                ("stepper", C.c_int32), ("ir_precond", C.c_int32), ("ir_launch", C.c_int32),
+                ("chain_wg", C.c_int32)]
 
 
 class MCParams(C.Structure):
@@ -85,6 +86,11 @@ class Info(C.Structure):
                 ("n_deferred", C.c_int64), ("n_activated", C.c_int64), ("n_late", C.c_int64),
                 ("n_violations", C.c_int64),
                 ("surrogate_ms", C.c_double), ("ir_sys_nodes", C.c_int32), ("ir_sys_edges", C.c_int32)]
+
+
+class TuneInfo(C.Structure):
+    _fields_ = [("chain_wg", C.c_int32), ("ir_launch", C.c_int32), ("n_wg", C.c_int32),
+                ("wg", C.c_int32 * 4), ("wg_ms", C.c_double * 4), ("ir_ms", C.c_double * 2)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -191,7 +197,7 @@ class Batch:
                       screen=int(run["screen"]), max_voids_per_tree=int(run["max_voids_per_tree"]),
                       T_ambient=float(run["T_ambient"]), stepper=int(run.get("stepper", 0)),
                       ir_precond=int(run.get("ir_precond", 2)),
-                      ir_launch=int(run.get("ir_launch", 0)))
+                      ir_launch=int(run.get("ir_launch", 0)), chain_wg=int(run.get("chain_wg", 0)))
         mcp = None
         if mc is not None:
             mcp = MCParams(struct_size=C.sizeof(MCParams), n_samples=int(mc["n_samples"]),
@@ -309,6 +315,14 @@ class Batch:
         op = np.zeros(self.n_res, np.uint8)
         self._chk(lib().em_get_seg_state(self._h, C.c_int32(sample), _ptr(dR), _ptr(op)))
         return dR, op
+
+    def autotune(self, n_steps: int = 100) -> dict:
+        t = TuneInfo()
+        self._chk(lib().em_autotune(self._h, C.c_int32(n_steps), C.byref(t)))
+        n = t.n_wg
+        return {"chain_wg": t.chain_wg, "ir_launch": t.ir_launch,
+                "wg_ms": {int(t.wg[k]): float(t.wg_ms[k]) for k in range(n)},
+                "ir_ms": {1: float(t.ir_ms[0]), 2: float(t.ir_ms[1])}}
 
     def set_seg_state(self, sample: int, dR, open_):
         dR = np.ascontiguousarray(dR, np.float64)

@@ -85,6 +85,7 @@ struct em_batch {
     std::vector<int> chain_L;           // lanes per instance of a chain tree (0: generic tree)
     std::vector<int> tree_perm_h;
     int chain_wg = 0;
+    std::vector<int> wg_cand;           // chain workgroup sizes that hold the longest chain tree
     long long lanes_cap = 0;            // lanes allocated for the chain kernel's table
     int *res_cnt = nullptr;             // [S][2] per-sample result counts (device)
     // chain condensation: the PCG iterates the terminal system rd; interior
@@ -481,6 +482,34 @@ void fold_timers(em_batch *b)
     b->ir_pending = false;
 }
 
+// Lane layout of the chain kernel: instances of chain trees in tree_perm
+// order (samples consecutive), L lanes each, never straddling a workgroup of
+// cWG lanes; only the active ones when flags are given.  Returns the lane
+// count (whole workgroups) and, when asked, each placed instance's id, first
+// lane and lane count.
+long long place_chain_lanes(const std::vector<int> &perm, const std::vector<int> &chain_L, int S, int cWG,
+                            const uint8_t *ia, const uint8_t *sa, std::vector<int> *pi,
+                            std::vector<long long> *po, std::vector<int> *pL)
+{
+    if (pi) { pi->clear(); po->clear(); pL->clear(); }
+    long long n = 0;
+    int fill = 0;
+    for (int t : perm) {
+        const int L = chain_L[t];
+        if (L == 0) continue;
+        for (int s = 0; s < S; ++s) {
+            const size_t inst = (size_t)t * S + s;
+            if (ia && !(ia[inst] && sa[s])) continue;
+            if (fill + L > cWG) { n += cWG - fill; fill = 0; }
+            if (pi) { pi->push_back((int)inst); po->push_back(n); pL->push_back(L); }
+            n += L;
+            fill += L;
+        }
+    }
+    if (fill > 0) n += cWG - fill;
+    return n;
+}
+
 // Active-instance compaction (after the screen, the learned screen's
 // deferrals and activations, a reset or a restore): the ascending list of
 // active instances for the forcing update, and the chain kernel's lane table
@@ -524,27 +553,10 @@ em_status ensure_active(em_batch *b)
     const int cWG = b->chain_wg;
     std::vector<int> pi, pL;
     std::vector<long long> po;
-    long long n_lanes = 0;
-    auto place = [&](bool all) {
-        pi.clear(); pL.clear(); po.clear();
-        n_lanes = 0;
-        int fill = 0;
-        for (int t : b->tree_perm_h) {
-            const int L = b->chain_L[t];
-            if (L == 0) continue;
-            for (int s = 0; s < S; ++s) {
-                const size_t inst = (size_t)t * S + s;
-                if (!all && !(ia[inst] && sa[s])) continue;
-                if (fill + L > cWG) { n_lanes += cWG - fill; fill = 0; }
-                pi.push_back((int)inst); po.push_back(n_lanes); pL.push_back(L);
-                n_lanes += L;
-                fill += L;
-            }
-        }
-        if (fill > 0) n_lanes += cWG - fill;
-    };
-    place(false);
-    if (n_lanes > b->lanes_cap) place(true);      // the creation-time table always fits
+    d.chain_wg = cWG;
+    long long n_lanes = place_chain_lanes(b->tree_perm_h, b->chain_L, S, cWG, ia.data(), sa.data(), &pi, &po, &pL);
+    if (n_lanes > b->lanes_cap)      // the full layout of any candidate size always fits
+        n_lanes = place_chain_lanes(b->tree_perm_h, b->chain_L, S, cWG, nullptr, nullptr, &pi, &po, &pL);
     if (!pi.empty()) {
         HIPCHK(b, hipMemcpyAsync(b->pl_inst, pi.data(), 4 * pi.size(), hipMemcpyHostToDevice, st));
         HIPCHK(b, hipMemcpyAsync(b->pl_off, po.data(), 8 * po.size(), hipMemcpyHostToDevice, st));
@@ -831,40 +843,44 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     // rooted at an end) that fit one workgroup go to the resident chain
     // kernel; instances are packed into workgroups without straddling.
     const int cM = b->fp32 ? CHAIN_M32 : CHAIN_M64;
-    const int cWG = b->fp32 ? CHAIN_WG32 : CHAIN_WG64;
+    const int cWGmax = b->fp32 ? CHAIN_WG32 : CHAIN_WG64;
     std::vector<uint8_t> tree_chain(nt, 0);
-    // placement of each chain instance: first lane (global) and lane count;
-    // the per-lane table itself is expanded on the device
-    std::vector<int> place_inst, place_L;
-    std::vector<long long> place_off;
-    long long n_lanes = 0;
+    std::vector<int> chain_L(nt, 0);
+    int need = 1;
     if (r->stepper == 0) {
         for (int t = 0; t < nt; ++t) {
             int i0 = P.tree_off[t], i1 = P.tree_off[t + 1];
-            if ((i1 - i0 + cM - 1) / cM > cWG) continue;
+            const int L = (i1 - i0 + cM - 1) / cM;
+            if (L > cWGmax) continue;
             bool chain = true;
             for (int i = i0 + 1; i < i1 && chain; ++i) chain = P.parent[i] == i - 1;
             tree_chain[t] = chain;
+            if (chain) { chain_L[t] = L; need = std::max(need, L); }
         }
-        int fill = 0;
-        for (int q = 0; q < nt; ++q) {
-            int t = tree_perm[q];
-            if (!tree_chain[t]) continue;
-            int L = (P.tree_off[t + 1] - P.tree_off[t] + cM - 1) / cM;
-            for (int s = 0; s < S; ++s) {
-                if (fill + L > cWG) {
-                    n_lanes += cWG - fill;
-                    fill = 0;
-                }
-                place_inst.push_back(t * S + s);
-                place_off.push_back(n_lanes);
-                place_L.push_back(L);
-                n_lanes += L;
-                fill += L;
-            }
-        }
-        if (fill > 0) n_lanes += cWG - fill;
     }
+    // workgroup sizes that hold the longest chain tree; the smallest unless
+    // the caller (or the autotuner) names one
+    std::vector<int> wg_cand;
+    for (int w = 256; w <= cWGmax; w *= 2)
+        if (w >= need) wg_cand.push_back(w);
+    int cWG = wg_cand.front();
+    if (r->chain_wg != 0) {
+        if (std::find(wg_cand.begin(), wg_cand.end(), r->chain_wg) == wg_cand.end())
+            return fail(b, EM_ERR_ARG, "chain_wg must be a power of two from 256 to the precision's maximum "
+                                       "(1024 FP32, 512 FP64) holding the longest chain tree");
+        cWG = r->chain_wg;
+    }
+    // placement of each chain instance: first lane (global) and lane count;
+    // the per-lane table itself is expanded on the device.  The table is
+    // allocated for the largest of the candidate sizes' layouts.
+    std::vector<int> place_inst, place_L;
+    std::vector<long long> place_off;
+    long long lanes_cap = 0;
+    for (int w : wg_cand)
+        lanes_cap = std::max(lanes_cap, place_chain_lanes(tree_perm, chain_L, S, w, nullptr, nullptr,
+                                                          nullptr, nullptr, nullptr));
+    const long long n_lanes = place_chain_lanes(tree_perm, chain_L, S, cWG, nullptr, nullptr,
+                                                &place_inst, &place_off, &place_L);
 
     Dev &d = b->d;
     d.n_nodes = nn; d.n_res = nr; d.n_trees = nt; d.ns = ns; d.N = N; d.S = S;
@@ -904,16 +920,16 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     UP(d.vinc_off, P.inc_off); UP(d.vinc, P.inc);
     UP(d.tseg_off, tseg_off); UP(d.tseg, tseg);
     UP(d.via_up, via_up); UP(d.tree_perm, tree_perm); UP(d.tree_chain, tree_chain);
-    if (n_lanes / cWG > (1LL << 30)) return fail(b, EM_ERR_ARG, "batch too large");
+    if (lanes_cap / 256 > (1LL << 30)) return fail(b, EM_ERR_ARG, "batch too large");
     d.n_chain_wg = (int)(n_lanes / cWG);
     b->n_generic_trees = 0;
     for (int t = 0; t < nt; ++t) b->n_generic_trees += tree_chain[t] ? 0 : 1;
     b->chain_wg = cWG;
-    b->lanes_cap = n_lanes;
+    b->wg_cand = wg_cand;
+    b->lanes_cap = lanes_cap;
     b->tree_perm_h = tree_perm;
-    b->chain_L.assign(nt, 0);
-    for (int t = 0; t < nt; ++t)
-        if (tree_chain[t]) b->chain_L[t] = (P.tree_off[t + 1] - P.tree_off[t] + cM - 1) / cM;
+    b->chain_L = chain_L;
+    d.chain_wg = cWG;
     {
         const size_t ISb = (size_t)nt * S;
         AL(b->act_inst, int, ISb); AL(b->pl_inst, int, ISb); AL(b->pl_L, int, ISb);
@@ -922,7 +938,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     }
     {
         int *li, *lb;
-        AL(li, int, n_lanes); AL(lb, int, n_lanes);
+        AL(li, int, lanes_cap); AL(lb, int, lanes_cap);
         const int *pi, *pL;
         const long long *po;
         UP(pi, place_inst); UP(po, place_off); UP(pL, place_L);
@@ -1345,6 +1361,85 @@ em_status em_reset(em_batch *b)
     b->cg_iters_total = 0;
     b->step_launches = 0;
     b->step_ms = b->ir_ms = 0.0;
+    return EM_OK;
+}
+
+em_status em_autotune(em_batch *b, int32_t n_steps, em_tune_info *out)
+{
+    if (!b || n_steps < 1) return fail(b, EM_ERR_ARG, "bad step count");
+    if (b->step_counter != 0 || b->n_outer_done != 0)
+        return fail(b, EM_ERR_STATE, "autotune needs the batch at t = 0 (just created or reset)");
+    hipStream_t st = b->stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(b, hipEventCreate(&e0));
+    HIPCHK(b, hipEventCreate(&e1));
+    auto stream_ms = [&](float &ms) -> em_status {
+        HIPCHK(b, hipEventSynchronize(e1));
+        HIPCHK(b, hipEventElapsedTime(&ms, e0, e1));
+        return EM_OK;
+    };
+    em_tune_info info{};
+    info.ir_ms[0] = info.ir_ms[1] = -1.0;
+    em_status rc = EM_OK;
+    // IR launch shape: a cold solve (warm start at VDD) in each form
+    if (!b->trees_only && b->use_amg) {
+        double best = 1e300;
+        bool best_wg = b->ir_wg;
+        for (int k = 0; k < 2 && rc == EM_OK; ++k) {
+            b->ir_wg = k == 1;
+            for (int rep = 0; rep < 2 && rc == EM_OK; ++rep) {     // the first pass warms the code paths
+                if ((rc = em_reset(b)) != EM_OK) break;
+                HIPCHK(b, hipEventRecord(e0, st));
+                if ((rc = ir_solve_impl(b)) != EM_OK) break;
+                HIPCHK(b, hipEventRecord(e1, st));
+                float ms = 0.f;
+                if ((rc = stream_ms(ms)) != EM_OK) break;
+                if (rep == 1) {
+                    info.ir_ms[k] = ms;
+                    if (ms < best) { best = ms; best_wg = b->ir_wg; }
+                }
+            }
+        }
+        b->ir_wg = best_wg;
+        info.ir_launch = best_wg ? 2 : 1;
+    }
+    // chain-kernel workgroup size: n_steps steps of the screened instances
+    if (rc == EM_OK && b->d.n_chain_wg >= 0) {
+        double best = 1e300;
+        int best_w = b->chain_wg;
+        for (size_t k = 0; k < b->wg_cand.size() && k < 4 && rc == EM_OK; ++k) {
+            b->chain_wg = b->wg_cand[k];
+            for (int rep = 0; rep < 2 && rc == EM_OK; ++rep) {
+                if ((rc = em_reset(b)) != EM_OK) break;
+                if (!b->trees_only && (rc = ir_solve_impl(b)) != EM_OK) break;
+                if (b->run.screen) {
+                    launch_screen(b->d, true, st);
+                    LAUNCHCHK(b);
+                }
+                b->act_dirty = true;
+                if ((rc = ensure_active(b)) != EM_OK) break;
+                HIPCHK(b, hipEventRecord(e0, st));
+                if ((rc = timed_step(b, rep == 0 ? 1 : n_steps, 0)) != EM_OK) break;
+                HIPCHK(b, hipEventRecord(e1, st));
+                float ms = 0.f;
+                if ((rc = stream_ms(ms)) != EM_OK) break;
+                if (rep == 1) {
+                    info.wg[info.n_wg] = b->chain_wg;
+                    info.wg_ms[info.n_wg++] = ms;
+                    if (ms < best) { best = ms; best_w = b->chain_wg; }
+                }
+            }
+        }
+        b->chain_wg = best_w;
+        info.chain_wg = best_w;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != EM_OK) return rc;
+    b->act_dirty = true;
+    rc = em_reset(b);
+    if (rc != EM_OK) return rc;
+    if (out) *out = info;
     return EM_OK;
 }
 

@@ -19,7 +19,7 @@ constexpr int MAXV = 4;                 // void slots per (tree, sample)
 constexpr double E_CHG = 1.602176634e-19;
 constexpr double K_B = 1.380649e-23;
 constexpr int EV_WORDS = 5;             // sample, tree, step, node, host segment
-// resident chain kernel: nodes per lane and lanes per workgroup
+// resident chain kernel: nodes per lane and the largest lanes per workgroup
 #define CHAIN_M32 8
 #define CHAIN_WG32 1024
 #define CHAIN_M64 8
@@ -57,7 +57,8 @@ struct Dev {
     const int *tree_perm;               // lane slot -> tree id (larger trees first)
     const uint8_t *tree_chain;          // tree stepped by the resident chain kernel
     const int *lane_inst, *lane_blk;    // chain kernel lanes: instance, block index
-    int n_chain_wg;
+    int n_chain_wg;                     // workgroups of the chain kernel's launch
+    int chain_wg;                       // its lanes per workgroup (256, 512 or the precision's maximum)
     // ---- per stress node statics (FP64) ----
     double *T, *V, *g0, *rob0, *gdx0, *mdrv;
     double *tree_V;                     // [n_trees] total control volume

@@ -518,8 +518,16 @@ void launch_chain(const Dev &d, const Dev *d_dev, bool fp32, int n_steps, int st
     h.dev = d_dev;
     h.S = d.S; h.n_steps = n_steps; h.step0 = step0; h.proj_every = 8;
     h.dt = d.dt;
-    if (fp32) k_chain<float, CHAIN_M32, CHAIN_WG32><<<d.n_chain_wg, CHAIN_WG32, 0, st>>>(h);
-    else k_chain<double, CHAIN_M64, CHAIN_WG64><<<d.n_chain_wg, CHAIN_WG64, 0, st>>>(h);
+    // the batch's workgroup size (lanes): the smallest that holds its longest
+    // chain, or the one the autotuner measured fastest
+    if (fp32) {
+        if (d.chain_wg == 256) k_chain<float, CHAIN_M32, 256><<<d.n_chain_wg, 256, 0, st>>>(h);
+        else if (d.chain_wg == 512) k_chain<float, CHAIN_M32, 512><<<d.n_chain_wg, 512, 0, st>>>(h);
+        else k_chain<float, CHAIN_M32, CHAIN_WG32><<<d.n_chain_wg, CHAIN_WG32, 0, st>>>(h);
+    } else {
+        if (d.chain_wg == 256) k_chain<double, CHAIN_M64, 256><<<d.n_chain_wg, 256, 0, st>>>(h);
+        else k_chain<double, CHAIN_M64, CHAIN_WG64><<<d.n_chain_wg, CHAIN_WG64, 0, st>>>(h);
+    }
 }
 
 }  // namespace em

@@ -189,3 +189,52 @@ def test_failed_segments_match_segment_state(em):
     assert r["n_failed_segs"] > 0
     assert np.array_equal(idx, want) and len(idx) == r["n_failed_segs"]
     B.close()
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_chain_workgroup_sizes_give_identical_results(em, prec):
+    # instances never share a reduction, so the lanes per workgroup (how many
+    # instances a workgroup holds, how many reduction levels it runs) change
+    # no result bit
+    g, mat, rn, _ = synth.workload("tiny_trees")
+    mc = dict(n_samples=8, seed=5, cov_kappa=0.2, cov_scrit=0.2)
+    sizes = (256, 512, 1024) if prec == 1 else (256, 512)
+    out = []
+    for w in sizes:
+        B = em.Batch(g, mat, dict(rn, prec=prec, chain_wg=w), mc)
+        B.stress_step(1000)
+        ev = B.events()
+        ev = ev[np.lexsort(ev.T[::-1])] if len(ev) else ev
+        out.append(([B.stress(s) for s in range(8)], ev))
+        B.close()
+    assert len(out[0][1]) > 0
+    for st, ev in out[1:]:
+        assert all(np.array_equal(a, b) for a, b in zip(st, out[0][0]))
+        assert np.array_equal(ev, out[0][1])
+    with pytest.raises(em.EmError):
+        em.Batch(g, mat, dict(rn, prec=0, chain_wg=1024), mc)     # above the FP64 maximum
+
+
+def test_autotune_keeps_results_and_resets(em):
+    g, mat, rn, mc = synth.workload("mc_grid")
+    rn = dict(rn, prec=0)
+    mc = dict(mc, n_samples=48)
+    A = em.Batch(g, mat, rn, mc)
+    ref = A.run_to_ttf()
+    A.close()
+    B = em.Batch(g, mat, rn, mc)
+    t = B.autotune(20)
+    print("autotune", t, flush=True)
+    assert set(t["wg_ms"]) == {256, 512} and t["chain_wg"] in t["wg_ms"]      # FP64: up to 512 lanes
+    assert t["ir_launch"] in (1, 2) and min(t["ir_ms"].values()) > 0
+    res = B.run_to_ttf()
+    assert sum(r["failed"] for r in ref) > 0
+    for a, b in zip(ref, res):
+        assert a["failed"] == b["failed"] and a["n_failed_segs"] == b["n_failed_segs"]
+        assert abs(a["final_drop"] - b["final_drop"]) <= 1e-9 * a["final_drop"]
+        if a["failed"]:
+            assert abs(a["ttf_s"] - b["ttf_s"]) <= 1e-8 * a["ttf_s"]
+    B.stress_step(1)
+    with pytest.raises(em.EmError):
+        B.autotune(5)                      # not at t = 0
+    B.close()
