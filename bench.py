@@ -241,6 +241,8 @@ def main():
     ap.add_argument("--prec", type=int, default=1, help="1 = FP32 stepping, 0 = FP64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mc", action="store_true")
+    ap.add_argument("--only-mc", action="store_true",
+                    help="run only the Monte Carlo legs (no oracle, no plain form) and print them")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--mc-samples", type=int, default=1024)
     ap.add_argument("--no-sur", action="store_true", help="skip the learned-screen leg")
@@ -273,6 +275,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+
+    if args.only_mc:
+        out = {"mc": mc_leg(args, "mc_grid", oracle=False, plain=False),
+               "mc_mesh": mc_leg(args, "mc_mesh", oracle=False, plain=False)}
+        print(json.dumps(out), flush=True)
+        return
 
     g, mat, run, _ = synth.workload("pg400")
     run = dict(run, prec=args.prec, screen=0)

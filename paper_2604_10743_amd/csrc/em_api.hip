@@ -1301,6 +1301,7 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
     // per-sample results
     std::vector<double> ttf(S), fd(S), idr(S);
     std::vector<int> failed(S), oidx(S), cnt(2 * (size_t)S);
+    HIPCHK(b, hipMemsetAsync(b->res_cnt, 0, 8 * (size_t)S, st));
     launch_result_counts(d, b->res_cnt, st);
     LAUNCHCHK(b);
     HIPCHK(b, hipMemcpyAsync(ttf.data(), d.ttf, 8 * S, hipMemcpyDeviceToHost, st));

@@ -7,6 +7,7 @@
 // per-block partials.  The time-to-failure bookkeeping of the outer loop
 // (Fig. 2, Table I caption) lives here too.
 #include "em_internal.h"
+#include <algorithm>
 #include <cmath>
 
 namespace em {
@@ -533,13 +534,14 @@ void launch_ttf_init(const Dev &d, double fail, hipStream_t st)
 // resistance change or open, and trees holding a void.
 EM_KERNEL void k_result_counts(Dev d, int *cnt)
 {
-    const int s = blockIdx.x;
+    const int s = blockIdx.y;
     int nf = 0, nt = 0;
-    for (int e = threadIdx.x; e < d.n_res; e += IR_BS) {
+    for (int e = blockIdx.x * IR_BS + threadIdx.x; e < d.n_res; e += gridDim.x * IR_BS) {
         const size_t x = (size_t)s * d.n_res + e;
         nf += (d.dR[x] > 0.0 || d.open[x]) ? 1 : 0;
     }
-    for (int t = threadIdx.x; t < d.n_trees; t += IR_BS) nt += d.nv[(size_t)t * d.S + s] > 0 ? 1 : 0;
+    for (int t = blockIdx.x * IR_BS + threadIdx.x; t < d.n_trees; t += gridDim.x * IR_BS)
+        nt += d.nv[(size_t)t * d.S + s] > 0 ? 1 : 0;
     __shared__ int red[2][IR_BS / 64];
     for (int o = 32; o > 0; o >>= 1) { nf += __shfl_xor(nf, o, 64); nt += __shfl_xor(nt, o, 64); }
     if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = nf; red[1][threadIdx.x >> 6] = nt; }
@@ -547,13 +549,15 @@ EM_KERNEL void k_result_counts(Dev d, int *cnt)
     if (threadIdx.x == 0) {
         int a = 0, b = 0;
         for (int w = 0; w < IR_BS / 64; ++w) { a += red[0][w]; b += red[1][w]; }
-        cnt[2 * s] = b;
-        cnt[2 * s + 1] = a;
+        if (b) atomicAdd(&cnt[2 * s], b);
+        if (a) atomicAdd(&cnt[2 * s + 1], a);
     }
 }
 void launch_result_counts(const Dev &d, int *cnt, hipStream_t st)
 {
-    k_result_counts<<<d.S, IR_BS, 0, st>>>(d, cnt);
+    // cnt zeroed by the caller; blocks per sample sized to the segment count
+    const int bx = std::min(64, std::max(1, d.n_res / (8 * IR_BS)));
+    k_result_counts<<<dim3(bx, d.S), IR_BS, 0, st>>>(d, cnt);
 }
 void launch_ttf_update(const Dev &d, double fail, int k, double t, hipStream_t st)
 {
