@@ -130,8 +130,10 @@ typedef struct {
                                     nodes and 32 or more samples; else 1); 1 one kernel per
                                     V-cycle step over all samples, iterations replayed as a
                                     graph; 2 one workgroup per sample running its whole PCG in
-                                    one launch.  Same preconditioner and stopping rule; the
-                                    reduction order of the dot products differs. */
+                                    one launch, from LDS when the sample's system and hierarchy
+                                    fit (else as 3); 3 the same with the vectors in HBM.  Same
+                                    preconditioner and stopping rule; the reduction order of
+                                    the dot products differs. */
     int32_t chain_wg;            /* lanes per workgroup of the resident chain kernel: 0 automatic
                                     (the smallest of 256, 512, 1024 that holds the longest chain
                                     tree), or one of those (at most 512 in FP64) that holds it.
@@ -264,11 +266,12 @@ em_status em_set_seg_state(em_batch *b, int32_t sample, const double *dR, const 
  * choice beyond the rounding of the IR dot products.  out may be NULL. */
 typedef struct {
     int32_t chain_wg;            /* chosen lanes per workgroup */
-    int32_t ir_launch;           /* chosen IR launch shape (1 or 2; 0: not tuned) */
+    int32_t ir_launch;           /* chosen IR launch shape (1, 2 or 3; 0: not tuned) */
     int32_t n_wg;                /* candidates tried */
     int32_t wg[4];
     double wg_ms[4];             /* stream time of the n_steps steps per candidate */
-    double ir_ms[2];             /* cold IR solve: multi-kernel, one workgroup per sample (-1: not tried) */
+    double ir_ms[3];             /* cold IR solve: multi-kernel, one workgroup per sample from HBM,
+                                    from LDS (-1: not tried) */
 } em_tune_info;
 em_status em_autotune(em_batch *b, int32_t n_steps, em_tune_info *out);
 /* Per-node temperature, control volume and critical stress for one sample. */

@@ -90,7 +90,7 @@ class Info(C.Structure):
 
 class TuneInfo(C.Structure):
     _fields_ = [("chain_wg", C.c_int32), ("ir_launch", C.c_int32), ("n_wg", C.c_int32),
-                ("wg", C.c_int32 * 4), ("wg_ms", C.c_double * 4), ("ir_ms", C.c_double * 2)]
+                ("wg", C.c_int32 * 4), ("wg_ms", C.c_double * 4), ("ir_ms", C.c_double * 3)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -322,7 +322,7 @@ class Batch:
         n = t.n_wg
         return {"chain_wg": t.chain_wg, "ir_launch": t.ir_launch,
                 "wg_ms": {int(t.wg[k]): float(t.wg_ms[k]) for k in range(n)},
-                "ir_ms": {1: float(t.ir_ms[0]), 2: float(t.ir_ms[1])}}
+                "ir_ms": {1: float(t.ir_ms[0]), 3: float(t.ir_ms[1]), 2: float(t.ir_ms[2])}}
 
     def set_seg_state(self, sample: int, dR, open_):
         dR = np.ascontiguousarray(dR, np.float64)

@@ -73,6 +73,7 @@ struct em_batch {
     Amg *amg_dev = nullptr;             // device copy of amg (one-workgroup PCG)
     bool use_amg = false;
     bool ir_wg = false;                 // multigrid PCG with one workgroup per sample
+    bool ir_lds = false;                // ... running from LDS
     // compaction of the active instances (screen, learned screen): the list
     // the forcing update walks and the lanes the chain kernel launches
     bool act_dirty = true;              // inst_active may have changed since the last compaction
@@ -296,7 +297,7 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
         r->cg_max_iter < 1 || !(r->cg_rtol > 0) || (r->prec != EM_FP64 && r->prec != EM_FP32) ||
         r->max_voids_per_tree < 0 || r->max_voids_per_tree > MAXV || !(r->T_ambient > 0) ||
         r->stepper < 0 || r->stepper > 1 || r->ir_precond < 0 || r->ir_precond > 2 ||
-        r->ir_launch < 0 || r->ir_launch > 2)
+        r->ir_launch < 0 || r->ir_launch > 3)
         return fail(b, EM_ERR_ARG, "bad run parameters (max_voids_per_tree <= 4)");
     if (mc && (mc->n_samples < 1 || mc->n_samples > 65535 || mc->cov_kappa < 0 || mc->cov_scrit < 0 || !std::isfinite(mc->cov_kappa) ||
                !std::isfinite(mc->cov_scrit)))
@@ -379,7 +380,8 @@ em_status ir_solve_impl(em_batch *b)
         int itmax = 0;
         if (!all) {
             launch_amg_setup(X, b->amg, st);
-            launch_ir_pcg_wg(X, b->amg_dev, rtol, b->run.cg_max_iter, st);
+            if (b->ir_lds) launch_ir_pcg_lds(X, b->n_inc, b->amg, b->amg_dev, rtol, b->run.cg_max_iter, st);
+            else launch_ir_pcg_wg(X, b->amg_dev, rtol, b->run.cg_max_iter, st);
             LAUNCHCHK(b);
             std::vector<int> its(X.S);
             HIPCHK(b, hipMemcpyAsync(hconv, X.conv, X.S, hipMemcpyDeviceToHost, st));
@@ -1055,7 +1057,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
             for (int l = 1; l <= a.nlev; ++l) {
                 const AmgHostLevel &h = H.lev[l];
                 AmgLevel &L = a.lev[l];
-                L.n = h.n; L.ne = h.ne; L.nf = h.nf; L.nef = h.nef;
+                L.n = h.n; L.ne = h.ne; L.nf = h.nf; L.nef = h.nef; L.nmem = (int)h.mem.size();
                 UP(L.agg, h.agg); UP(L.mem_off, h.mem_off); UP(L.mem, h.mem);
                 UP(L.int_off, h.int_off); UP(L.int_e, h.int_e);
                 UP(L.src_off, h.src_off); UP(L.src_e, h.src_e);
@@ -1073,8 +1075,10 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
             // one workgroup per sample pays off when the samples fill the chip
             // or the system is small; a single large system keeps every CU busy
             // only in the one-kernel-per-step form
-            b->ir_wg = r->ir_launch == 2 ||
+            b->ir_wg = r->ir_launch >= 2 ||
                        (r->ir_launch == 0 && (xn <= 4096 || (S >= 32 && xn <= ir_wg_max_nodes())));
+            // from LDS when the sample's system and hierarchy fit a workgroup
+            b->ir_lds = b->ir_wg && r->ir_launch != 3 && ir_lds_bytes(X, xoff[xn], a) > 0;
             b->amg_dev = (Amg *)dalloc(b, sizeof(Amg));
             if (!b->amg_dev) return fail(b, EM_ERR_OOM, "device allocation");
             HIPCHK(b, hipMemcpyAsync(b->amg_dev, &a, sizeof(Amg), hipMemcpyHostToDevice, b->stream));
@@ -1380,14 +1384,17 @@ em_status em_autotune(em_batch *b, int32_t n_steps, em_tune_info *out)
         return EM_OK;
     };
     em_tune_info info{};
-    info.ir_ms[0] = info.ir_ms[1] = -1.0;
+    info.ir_ms[0] = info.ir_ms[1] = info.ir_ms[2] = -1.0;
     em_status rc = EM_OK;
     // IR launch shape: a cold solve (warm start at VDD) in each form
     if (!b->trees_only && b->use_amg) {
         double best = 1e300;
-        bool best_wg = b->ir_wg;
-        for (int k = 0; k < 2 && rc == EM_OK; ++k) {
-            b->ir_wg = k == 1;
+        bool best_wg = b->ir_wg, best_lds = b->ir_lds;
+        const bool lds_ok = ir_lds_bytes(b->condensed ? b->rd : b->d, b->n_inc, b->amg) > 0;
+        for (int k = 0; k < 3 && rc == EM_OK; ++k) {
+            if (k == 2 && !lds_ok) break;
+            b->ir_wg = k >= 1;
+            b->ir_lds = k == 2;
             for (int rep = 0; rep < 2 && rc == EM_OK; ++rep) {     // the first pass warms the code paths
                 if ((rc = em_reset(b)) != EM_OK) break;
                 HIPCHK(b, hipEventRecord(e0, st));
@@ -1397,12 +1404,13 @@ em_status em_autotune(em_batch *b, int32_t n_steps, em_tune_info *out)
                 if ((rc = stream_ms(ms)) != EM_OK) break;
                 if (rep == 1) {
                     info.ir_ms[k] = ms;
-                    if (ms < best) { best = ms; best_wg = b->ir_wg; }
+                    if (ms < best) { best = ms; best_wg = b->ir_wg; best_lds = b->ir_lds; }
                 }
             }
         }
         b->ir_wg = best_wg;
-        info.ir_launch = best_wg ? 2 : 1;
+        b->ir_lds = best_lds;
+        info.ir_launch = best_lds ? 2 : best_wg ? 3 : 1;
     }
     // chain-kernel workgroup size: n_steps steps of the screened instances
     if (rc == EM_OK && b->d.n_chain_wg >= 0) {

@@ -129,6 +129,7 @@ constexpr int AMG_NC_MAX = 88;          // coarsest level inverted densely when 
 
 struct AmgLevel {
     int n, ne, nf, nef;                 // nodes, edges of this level; nodes, edges of the finer one
+    int nmem;                           // member entries (mem_off[n])
     const int *agg;                     // [nf] finer node -> node of this level (-1: outside)
     const int *mem_off, *mem;           // members of each node
     const int *int_off, *int_e;         // finer edges inside each node
@@ -239,6 +240,11 @@ void launch_amg_post0(const Dev &d, double *w0, const AmgLevel &L1, const double
 void launch_amg_setup(const Dev &d, const Amg &a, hipStream_t st);
 void launch_amg_vcycle(const Dev &d, const Amg &a, bool init, hipStream_t st);
 int ir_wg_max_nodes();
+// LDS-resident form: bytes of dynamic LDS one sample's system and hierarchy
+// take (0 when it does not fit a workgroup), and its launch
+int ir_lds_bytes(const Dev &d, int nnz, const Amg &a);
+void launch_ir_pcg_lds(const Dev &d, int nnz, const Amg &a, const Amg *amg_dev, double rtol, int max_iter,
+                       hipStream_t st);
 // chain-kernel lane table: lane_inst = -1 everywhere, then instance i fills
 // lanes off[i] .. off[i] + L[i] - 1 with (inst[i], block 0 .. L[i] - 1)
 void launch_place_lanes(int *lane_inst, int *lane_blk, long long n_lanes, const int *inst,

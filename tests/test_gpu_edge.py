@@ -226,7 +226,7 @@ def test_autotune_keeps_results_and_resets(em):
     t = B.autotune(20)
     print("autotune", t, flush=True)
     assert set(t["wg_ms"]) == {256, 512} and t["chain_wg"] in t["wg_ms"]      # FP64: up to 512 lanes
-    assert t["ir_launch"] in (1, 2) and min(t["ir_ms"].values()) > 0
+    assert t["ir_launch"] in (1, 2, 3) and t["ir_ms"][1] > 0 and t["ir_ms"][3] > 0 and t["ir_ms"][2] > 0
     res = B.run_to_ttf()
     assert sum(r["failed"] for r in ref) > 0
     for a, b in zip(ref, res):

@@ -79,7 +79,7 @@ def _states(g, S, seed):
     return out
 
 
-@pytest.mark.parametrize("precond,launch", [(0, 0), (1, 1), (1, 2), (2, 1), (2, 2)])
+@pytest.mark.parametrize("precond,launch", [(0, 0), (1, 1), (1, 2), (1, 3), (2, 1), (2, 2), (2, 3)])
 def test_condensed_network_with_opens_matches_direct_solve(em, oracle_mod, precond, launch):
     g = _zoo()
     S = 5

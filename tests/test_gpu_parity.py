@@ -156,7 +156,7 @@ def test_single_step_with_injected_voids_fp64(em, oracle_mod):
     assert np.allclose(dv, dv_o, rtol=1e-9, atol=1e-30)
 
 
-@pytest.mark.parametrize("precond,launch", [(0, 0), (1, 1), (1, 2), (2, 1), (2, 2)])
+@pytest.mark.parametrize("precond,launch", [(0, 0), (1, 1), (1, 2), (1, 3), (2, 1), (2, 2), (2, 3)])
 def test_ir_solve_matches_direct_solve(em, oracle_mod, precond, launch):
     g, mat, rn, _ = synth.workload("tiny_mesh")
     rn = dict(rn, cg_rtol=1e-14, cg_max_iter=100000, ir_precond=precond, ir_launch=launch)
@@ -171,7 +171,7 @@ def test_ir_solve_matches_direct_solve(em, oracle_mod, precond, launch):
     assert np.max(np.abs(j - j_o)) <= 1e-6 * np.max(np.abs(j_o))
 
 
-@pytest.mark.parametrize("precond,launch", [(1, 1), (1, 2), (2, 1), (2, 2)])
+@pytest.mark.parametrize("precond,launch", [(1, 1), (1, 2), (2, 1), (2, 2), (2, 3)])
 def test_ir_multigrid_large_grid_matches_direct_solve(em, oracle_mod, precond, launch):
     # 200x200 sparse-via grid (~57k nodes, several multigrid levels), three
     # Monte Carlo samples sharing one nominal network; both launch shapes
@@ -240,27 +240,29 @@ def test_run_to_ttf_fp64(em, oracle_mod):
 
 def test_ir_launch_shapes_agree_through_failures(em):
     # the multigrid PCG as one kernel per step over all samples and as one
-    # workgroup per sample: same TTF, drops and failed segments in a Monte
-    # Carlo run whose voids change the conductances of some samples
+    # workgroup per sample (from LDS and from HBM): same TTF, drops and failed
+    # segments in a Monte Carlo run whose voids change the conductances of
+    # some samples
     g, mat = _stressed_mesh(460e-6)
     mc = dict(n_samples=24, seed=77, cov_kappa=0.2, cov_scrit=0.2)
     out = []
-    for launch in (1, 2):
+    for launch in (1, 2, 3):
         _flush(f"mc launch shape {launch}")
         B = em.Batch(g, mat, run(prec=0, n_steps=400, ir_every=40, dt=4e4, ir_precond=1, ir_launch=launch), mc)
         res = B.run_to_ttf()
         segs = [B.failed_segments(s) for s in range(24)]
         out.append((res, segs))
         B.close()
-    (ra, sa), (rb, sb) = out
+    (ra, sa) = out[0]
     assert sum(r["failed"] for r in ra) > 0
-    for s in range(24):
-        a, b = ra[s], rb[s]
-        assert a["failed"] == b["failed"] and a["outer_idx"] == b["outer_idx"], s
-        assert abs(a["final_drop"] - b["final_drop"]) <= 1e-9 * a["final_drop"], s
-        if a["failed"]:
-            assert abs(a["ttf_s"] - b["ttf_s"]) <= 1e-8 * a["ttf_s"], s
-        assert np.array_equal(sa[s], sb[s]), s
+    for rb, sb in out[1:]:
+        for s in range(24):
+            a, b = ra[s], rb[s]
+            assert a["failed"] == b["failed"] and a["outer_idx"] == b["outer_idx"], s
+            assert abs(a["final_drop"] - b["final_drop"]) <= 1e-9 * a["final_drop"], s
+            if a["failed"]:
+                assert abs(a["ttf_s"] - b["ttf_s"]) <= 1e-8 * a["ttf_s"], s
+            assert np.array_equal(sa[s], sb[s]), s
 
 
 def test_mc_draws_match(em, oracle_mod):
