@@ -76,6 +76,8 @@ struct em_batch {
     bool ir_lds = false;                // ... running from LDS
     // compaction of the active instances (screen, learned screen): the list
     // the forcing update walks and the lanes the chain kernel launches
+    bool nominal = true;                // every sample still has the nominal resistances (no step taken
+                                        // since creation or reset, no state set or restored)
     bool act_dirty = true;              // inst_active may have changed since the last compaction
     bool act_built = false;
     int n_act = 0;
@@ -484,6 +486,23 @@ void fold_timers(em_batch *b)
     b->ir_pending = false;
 }
 
+// The steady-state screen; with the nominal resistances every sample has
+// the same current densities and the steady stress is computed once per tree.
+em_status run_screen(em_batch *b, bool apply)
+{
+    Dev &d = b->d;
+    if (b->nominal || b->trees_only) {
+        HIPCHK(b, hipMemsetAsync(d.tree_mortal, 0, (size_t)d.n_trees * d.S, b->stream));
+        HIPCHK(b, hipMemsetAsync(d.seg_mortal, 0, (size_t)d.n_res * d.S, b->stream));
+        launch_screen_shared(d, apply, b->stream);
+    } else {
+        launch_screen(d, apply, b->stream);
+    }
+    LAUNCHCHK(b);
+    if (apply) b->act_dirty = true;
+    return EM_OK;
+}
+
 // Lane layout of the chain kernel: instances of chain trees in tree_perm
 // order (samples consecutive), L lanes each, never straddling a workgroup of
 // cWG lanes; only the active ones when flags are given.  Returns the lane
@@ -601,6 +620,7 @@ em_status update_forcing(em_batch *b)
 em_status timed_step_dev(em_batch *b, const Dev &dd, int n_steps, int step0)
 {
     fold_timers(b);
+    b->nominal = false;                   // voids may grow from here on
     HIPCHK(b, hipEventRecord(b->ev_a, b->stream));
     if (dd.n_chain_wg > 0) launch_chain(dd, b->d_dev, b->fp32, n_steps, step0, b->stream);
     if (b->n_generic_trees > 0) launch_step(dd, b->fp32, n_steps, step0, b->stream);
@@ -668,7 +688,10 @@ em_status sur_buffers(em_batch *b)
 // steady stress is refreshed first (without changing the active set).
 em_status features_impl(em_batch *b, float *X, bool screen_current = false, bool candidates_only = false)
 {
-    if (!screen_current) launch_screen(b->d, false, b->stream);
+    if (!screen_current) {
+        em_status rc = run_screen(b, false);
+        if (rc != EM_OK) return rc;
+    }
     launch_features(b->d, X, candidates_only, b->stream);
     LAUNCHCHK(b);
     return EM_OK;
@@ -917,6 +940,12 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     d.seg_j_in = nullptr;
     if (g->seg_j) UPR(d.seg_j_in, g->seg_j, nr);
     UP(d.tree_off, P.tree_off); UP(d.parent, P.parent); UP(d.seg, P.seg); UP(d.dir, P.dir);
+    {
+        std::vector<int> ntree(ns);
+        for (int t = 0; t < nt; ++t)
+            for (int i = P.tree_off[t]; i < P.tree_off[t + 1]; ++i) ntree[i] = t;
+        UP(d.ntree, ntree);
+    }
     UP(d.vert, P.vert); UP(d.kpos, P.kpos);
     UP(d.child_off, child_off); UP(d.child, child);
     UP(d.vinc_off, P.inc_off); UP(d.vinc, P.inc);
@@ -1189,9 +1218,8 @@ em_status em_screen(em_batch *b, uint8_t *tree_mortal)
 {
     if (!b) return EM_ERR_ARG;
     if (!b->have_j) return fail(b, EM_ERR_STATE, "no current densities yet (call em_ir_solve first)");
-    launch_screen(b->d, true, b->stream);
-    LAUNCHCHK(b);
-    b->act_dirty = true;
+    em_status rs = run_screen(b, true);
+    if (rs != EM_OK) return rs;
     if (tree_mortal) {
         // device layout is [tree][sample]; output is [sample][tree]
         std::vector<uint8_t> tmp((size_t)b->n_trees * b->S);
@@ -1235,9 +1263,10 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
     if (rc != EM_OK) return rc;
     const double fail_frac = b->run.fail_frac;
     launch_ttf_init(d, fail_frac, st);
-    if (b->run.screen) launch_screen(d, true, st);
-    LAUNCHCHK(b);
-    b->act_dirty = true;
+    if (b->run.screen) {
+        rc = run_screen(b, true);
+        if (rc != EM_OK) return rc;
+    }
     const int n_steps = b->run.n_steps, K = b->run.ir_every;
     const bool sur = b->sur != nullptr;
     if (sur) {
@@ -1339,6 +1368,7 @@ em_status em_reset(em_batch *b)
     HIPCHK(b, hipMemsetAsync(d.inst_active, 1, IS, st));
     HIPCHK(b, hipMemsetAsync(d.sample_active, 1, d.S, st));
     b->act_dirty = true;
+    b->nominal = true;
     HIPCHK(b, hipMemsetAsync(d.dR, 0, 8 * RS, st));
     HIPCHK(b, hipMemsetAsync(d.open, 0, RS, st));
     HIPCHK(b, hipMemsetAsync(d.ev_count, 0, 4, st));
@@ -1421,10 +1451,7 @@ em_status em_autotune(em_batch *b, int32_t n_steps, em_tune_info *out)
             for (int rep = 0; rep < 2 && rc == EM_OK; ++rep) {
                 if ((rc = em_reset(b)) != EM_OK) break;
                 if (!b->trees_only && (rc = ir_solve_impl(b)) != EM_OK) break;
-                if (b->run.screen) {
-                    launch_screen(b->d, true, st);
-                    LAUNCHCHK(b);
-                }
+                if (b->run.screen && (rc = run_screen(b, true)) != EM_OK) break;
                 b->act_dirty = true;
                 if ((rc = ensure_active(b)) != EM_OK) break;
                 HIPCHK(b, hipEventRecord(e0, st));
@@ -1542,6 +1569,7 @@ em_status em_set_seg_state(em_batch *b, int32_t sample, const double *dR, const 
     b->live_dirty = true;
     b->any_open = b->any_open || any;
     b->ir_valid = false;
+    b->nominal = false;
     return EM_OK;
 }
 
@@ -1767,6 +1795,7 @@ em_status em_restore(em_batch *b, const void *host_buf, size_t n)
     b->live_dirty = true;
     b->ir_valid = false;
     b->act_dirty = true;
+    b->nominal = false;
     HIPCHK(b, hipMemsetAsync(b->d.open_dirty, 0, 4, b->stream));
     if (b->have_j) launch_update_f(b->d, b->fp32, b->stream);
     launch_factor(b->d, b->fp32, b->stream);

@@ -50,6 +50,7 @@ struct Dev {
     const double *seg_j_in;             // trees-only prescribed j (null otherwise)
     // ---- tree topology (shared) ----
     const int *tree_off, *parent, *seg, *dir, *vert, *kpos;
+    const int *ntree;                   // [ns] tree of each stress node
     const int *child_off, *child;       // children of each stress node, ascending
     const int *vinc_off, *vinc;         // wire segments incident to each vertex, ascending
     const int *tseg_off, *tseg;         // segments of each tree
@@ -205,6 +206,9 @@ void launch_node_sc(const Dev &d, bool fp32, hipStream_t st);
 void launch_update_f(const Dev &d, bool fp32, hipStream_t st);
 void launch_factor(const Dev &d, bool fp32, hipStream_t st);
 void launch_screen(const Dev &d, bool apply, hipStream_t st);
+// the screen when every sample has the same current densities (sample 0's);
+// tree_mortal and seg_mortal zeroed by the caller
+void launch_screen_shared(const Dev &d, bool apply, hipStream_t st);
 void launch_step(const Dev &d, bool fp32, int n_steps, int step0, hipStream_t st);
 void launch_void_dR(const Dev &d, hipStream_t st);
 void launch_chain(const Dev &d, const Dev *d_dev, bool fp32, int n_steps, int step0, hipStream_t st);

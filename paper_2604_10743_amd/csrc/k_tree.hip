@@ -421,6 +421,40 @@ EM_KERNEL void k_screen(Dev d, int apply)
     }
 }
 
+// The same screen when every sample carries the same current densities
+// (nominal resistances: the t = 0 screen of a Monte Carlo run): the steady
+// stress does not depend on the diffusivity, so it is computed once per tree
+// (sample 0, a wavefront per tree) and then compared with each sample's
+// critical stress, one thread per (node, sample).
+EM_KERNEL void k_screen_ss0(Dev d)
+{
+    const int lane = threadIdx.x & 63;
+    const int slot = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (slot >= d.n_trees) return;
+    steady_stress_wave(d, d.tree_perm[slot], 0, lane);
+}
+
+EM_KERNEL void k_screen_bcast(Dev d)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)d.ns * d.S) return;
+    const int S = d.S, i = (int)(g / S), s = (int)(g % S);
+    const double v = d.psi[(size_t)i * S];
+    if (s) d.psi[g] = v;
+    if (isfinite(v) && v > node_scrit(d, i, s)) {
+        d.tree_mortal[(size_t)d.ntree[i] * S + s] = 1;
+        uint8_t *sm = d.seg_mortal + (size_t)s * d.n_res;
+        if (d.parent[i] >= 0) sm[d.seg[i]] = 1;
+        for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k) sm[d.seg[d.child[k]]] = 1;
+    }
+}
+
+EM_KERNEL void k_screen_activate(Dev d)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < (long long)d.n_trees * d.S) d.inst_active[g] = d.tree_mortal[g];
+}
+
 // ------------------------------------------------------------------------
 // Late-failure resistance (eq. 17) with V_v - V_crit = (l - W) W H.
 // ------------------------------------------------------------------------
@@ -948,6 +982,12 @@ void launch_factor(const Dev &d, bool fp32, hipStream_t st)
 void launch_screen(const Dev &d, bool apply, hipStream_t st)
 {
     k_screen<<<nblocks((long long)d.n_trees * d.S, 4), 256, 0, st>>>(d, apply ? 1 : 0);
+}
+void launch_screen_shared(const Dev &d, bool apply, hipStream_t st)
+{
+    k_screen_ss0<<<nblocks((long long)d.n_trees, 4), 256, 0, st>>>(d);
+    k_screen_bcast<<<nblocks((long long)d.ns * d.S), 256, 0, st>>>(d);
+    if (apply) k_screen_activate<<<nblocks((long long)d.n_trees * d.S), 256, 0, st>>>(d);
 }
 void launch_step(const Dev &d, bool fp32, int n_steps, int step0, hipStream_t st)
 {

@@ -122,7 +122,7 @@ def test_argument_errors(em):
     bad.append((g, mat, dict(rn, dt=-1.0)))
     bad.append((g, mat, dict(rn, max_voids_per_tree=5)))
     bad.append((g, mat, dict(rn, ir_precond=3)))
-    bad.append((g, mat, dict(rn, ir_launch=3)))
+    bad.append((g, mat, dict(rn, ir_launch=4)))
     bad.append((g, mat, dict(rn, intervals_per_seg=0)))
     for gg, mm, rr in bad:
         with pytest.raises(em.EmError) as ei:

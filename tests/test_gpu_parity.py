@@ -210,6 +210,41 @@ def test_screen_bit_exact(em, oracle_mod):
     assert np.max(np.abs(ss - ss_o)) <= 1e-7 * np.max(np.abs(ss_o))
 
 
+def test_screen_monte_carlo_shared_and_per_instance(em, oracle_mod):
+    # with the nominal resistances every sample has the same currents and the
+    # steady stress is computed once per tree; after the same state is set
+    # explicitly the screen runs per (tree, sample): both give the oracle's
+    # per-sample verdicts (sample-dependent through sigma_crit)
+    g = synth.two_layer_mesh(1001, nr=12, nc=12, sink_mu=np.log(400e-6), vdd=1.2)
+    mat = material(sigma_crit=300e6)       # mortal tree counts 7..11 over the six samples
+    rn = run(prec=0)
+    mc = dict(n_samples=6, seed=7, cov_kappa=0.2, cov_scrit=0.3)
+    _flush("screen mc")
+    B = em.Batch(g, mat, rn, mc)
+    B.ir_solve()
+    tm_a = B.screen()
+    st_a = [B.screen_state(s) for s in range(6)]
+    for s in range(6):
+        B.set_seg_state(s, np.zeros(g.n_res), np.zeros(g.n_res, np.uint8))
+    B.ir_solve()
+    tm_b = B.screen()
+    st_b = [B.screen_state(s) for s in range(6)]
+    assert np.array_equal(tm_a, tm_b)
+    topo = oracle_mod.topology(g, 20)
+    _, _, j_o, _ = oracle_mod.ir_solve(g, g.res_R0)
+    n_mortal = []
+    for s in range(6):
+        for k in range(3):
+            assert np.array_equal(st_a[s][k], st_b[s][k]), (s, k)
+        xk, xs = oracle_mod.sample_xi(g, mc, s)
+        sim = oracle_mod.SampleSim(g, mat, rn, topo, xk, xs)
+        sim.set_j(j_o)
+        tm_o, sm_o, _ = sim.screen()
+        assert np.array_equal(tm_a[s], tm_o) and np.array_equal(st_a[s][1], sm_o), s
+        n_mortal.append(int(tm_o.sum()))
+    assert len(set(n_mortal)) > 1          # the verdicts differ between samples
+
+
 def _stressed_mesh(sink=490e-6):
     """12x12 mesh loaded so that voids push the worst drop over 10 %."""
     g = synth.two_layer_mesh(1001, nr=12, nc=12, sink_mu=np.log(sink), vdd=1.2, T_uniform=378.0)
