@@ -194,6 +194,13 @@ def mc_leg(args, name, oracle, plain):
          "final_drop_mean": float(np.mean([r["final_drop"] for r in res])),
          "node_steps": info["node_steps"], "ir_ms": info["ir_ms"], "step_kernel_ms": info["step_kernel_ms"],
          "ir_system_nodes": info["ir_sys_nodes"], "cg_iters_total": info["cg_iters_total"]}
+    # roofline of the whole Monte Carlo job: algorithmic HBM bytes per sample =
+    # 20 B per FP32 node-step actually stepped + 124 B per iterated-system node
+    # and PCG iteration of that sample (both streamed once), at 8 TB/s
+    bps = (BYTES_PER_NODE_STEP[1] * info["node_steps"] + 124.0 * info["ir_sys_nodes"] * info["cg_sample_iters"]) / S
+    o["roofline"] = {"bound": "hbm", "algorithmic_bytes_per_sample": bps,
+                     "roofline_samples_per_s": HBM_PEAK_GBS * 1e9 / bps, "frac": (S / wall) / (HBM_PEAK_GBS * 1e9 / bps),
+                     "note": "latency-bound: a few hundred-node system per sample and few active trees"}
     if oracle:
         from oracle import oracle as O
         O.build(force=False)

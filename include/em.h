@@ -186,6 +186,8 @@ typedef struct {
     int32_t ir_sys_nodes;  /* nodes of the system the IR PCG iterates (n_nodes, or the terminals
                               of the chain condensation) */
     int32_t ir_sys_edges;  /* its resistors (or reduced edges) */
+    int64_t cg_sample_iters; /* PCG iterations summed over samples (one-kernel form: counted in
+                              blocks of the graph's iterations per unconverged sample) */
 } em_info;
 
 /* Allocator hook: device memory for the batch (e.g. a framework's caching

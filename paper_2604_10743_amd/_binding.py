@@ -85,7 +85,8 @@ class Info(C.Structure):
                 ("step_kernel_ms", C.c_double), ("cg_iters_total", C.c_int64), ("ir_ms", C.c_double),
                 ("n_deferred", C.c_int64), ("n_activated", C.c_int64), ("n_late", C.c_int64),
                 ("n_violations", C.c_int64),
-                ("surrogate_ms", C.c_double), ("ir_sys_nodes", C.c_int32), ("ir_sys_edges", C.c_int32)]
+                ("surrogate_ms", C.c_double), ("ir_sys_nodes", C.c_int32), ("ir_sys_edges", C.c_int32),
+                ("cg_sample_iters", C.c_int64)]
 
 
 class TuneInfo(C.Structure):

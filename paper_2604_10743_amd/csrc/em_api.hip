@@ -57,6 +57,7 @@ struct em_batch {
     bool step_pending = false, ir_pending = false;
     double step_ms = 0.0, ir_ms = 0.0;
     long long step_launches = 0, cg_iters_total = 0;
+    long long cg_sample_iters = 0;      // PCG iterations summed over samples (each sample's own count)
     uint8_t *h_flags = nullptr;   // pinned scratch for small read-backs
     size_t h_flags_cap = 0;
     // learned screen (model borrowed from the caller)
@@ -370,6 +371,10 @@ em_status ir_solve_impl(em_batch *b)
     launch_ir_gather_inc(X, b->n_inc, st);
     launch_ir_setup(X, st);
     launch_ir_finalize0(X, rtol, st);
+    // every sample carries the nominal network and the same warm start: one
+    // solve serves all of them
+    const bool uniform = b->nominal && !b->ir_valid && d.S > 1;
+    if (uniform) launch_ir_only_sample0(X, st);
     LAUNCHCHK(b);
     uint8_t *hconv = pinned(b, std::max<size_t>(d.S, 8));
     if (!hconv) return fail(b, EM_ERR_OOM, "pinned host buffer");
@@ -392,6 +397,7 @@ em_status ir_solve_impl(em_batch *b)
             all = true;
             for (int s = 0; s < X.S; ++s) {
                 itmax = std::max(itmax, its[s]);
+                b->cg_sample_iters += its[s];
                 all &= hconv[s] != 0;
             }
             b->cg_iters_last = itmax;
@@ -399,6 +405,10 @@ em_status ir_solve_impl(em_batch *b)
         }
         b->cg_iters_last = itmax;
         if (b->condensed) launch_chain_expand(d, X, b->cond, st);
+        if (uniform) {
+            launch_ir_bcast0(d, st);
+            if (b->condensed) launch_ir_bcast0(X, st);     // the next warm start too
+        }
         launch_ir_finish(d, st);
         LAUNCHCHK(b);
         em_status rf = update_forcing(b);
@@ -442,7 +452,12 @@ em_status ir_solve_impl(em_batch *b)
         HIPCHK(b, hipMemcpyAsync(hconv, X.conv, X.S, hipMemcpyDeviceToHost, st));
         HIPCHK(b, hipStreamSynchronize(st));
         bool all = true;
-        for (int s = 0; s < X.S; ++s) all &= hconv[s] != 0;
+        int n_open = 0;
+        for (int s = 0; s < X.S; ++s) {
+            all &= hconv[s] != 0;
+            n_open += hconv[s] == 0;
+        }
+        b->cg_sample_iters += (long long)n_open * (it > 0 ? CG_BLOCK : 0);
         if (all) break;
         if (it >= b->run.cg_max_iter) {
             b->cg_iters_last = it;
@@ -454,6 +469,10 @@ em_status ir_solve_impl(em_batch *b)
     LAUNCHCHK(b);
     b->cg_iters_last = it;
     if (b->condensed) launch_chain_expand(d, X, b->cond, st);
+    if (uniform) {
+        launch_ir_bcast0(d, st);
+        if (b->condensed) launch_ir_bcast0(X, st);         // the next warm start too
+    }
     launch_ir_finish(d, st);
     LAUNCHCHK(b);
     em_status rf = update_forcing(b);
@@ -1184,6 +1203,7 @@ em_status em_get_info(em_batch *b, em_info *info)
     info->step_kernel_ms = b->step_ms;
     info->cg_iters_total = b->cg_iters_total;
     info->ir_ms = b->ir_ms;
+    info->cg_sample_iters = b->cg_sample_iters;
     info->ir_sys_nodes = b->condensed ? b->n_term : b->n_nodes;
     info->ir_sys_edges = b->condensed ? b->n_redge : b->n_res;
     unsigned int sc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -1394,6 +1414,7 @@ em_status em_reset(em_batch *b)
     b->n_outer_done = 0;
     b->cg_iters_last = 0;
     b->cg_iters_total = 0;
+    b->cg_sample_iters = 0;
     b->step_launches = 0;
     b->step_ms = b->ir_ms = 0.0;
     return EM_OK;

@@ -530,6 +530,31 @@ void launch_ttf_init(const Dev &d, double fail, hipStream_t st)
 {
     k_ttf_init<<<nb(d.S), IR_BS, 0, st>>>(d, fail);
 }
+// All samples share the nominal network: only sample 0 iterates ...
+EM_KERNEL void k_ir_only_sample0(Dev d)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= 1 && s < d.S) d.conv[s] = 1;
+}
+// ... and its voltages and reachability are every sample's.
+EM_KERNEL void k_ir_bcast0(Dev d)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)d.S * d.n_nodes) return;
+    const int i = (int)(g % d.n_nodes);
+    if (g < d.n_nodes) return;
+    d.u[g] = d.u[i];
+    d.live[g] = d.live[i];
+}
+void launch_ir_only_sample0(const Dev &d, hipStream_t st)
+{
+    k_ir_only_sample0<<<nb(d.S), IR_BS, 0, st>>>(d);
+}
+void launch_ir_bcast0(const Dev &d, hipStream_t st)
+{
+    k_ir_bcast0<<<nb((long long)d.S * d.n_nodes), IR_BS, 0, st>>>(d);
+}
+
 // Per-sample result counts (one block per sample): segments with a
 // resistance change or open, and trees holding a void.
 EM_KERNEL void k_result_counts(Dev d, int *cnt)
