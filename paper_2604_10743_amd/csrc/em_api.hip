@@ -80,6 +80,7 @@ struct em_batch {
     bool nominal = true;                // every sample still has the nominal resistances (no step taken
                                         // since creation or reset, no state set or restored)
     bool act_dirty = true;              // inst_active may have changed since the last compaction
+    bool forcing_stale = false;         // dt*f lags the last IR solve's currents
     bool act_built = false;
     int n_act = 0;
     int *act_inst = nullptr;            // [IS] active instances, ascending
@@ -310,15 +311,42 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
 
 em_status update_forcing(em_batch *b);
 
+// After a solve of sample 0 for identical samples: its voltages, reachability,
+// drop and currents, and (condensed) the reduced system it solved, become
+// every sample's, so that later solves can skip unchanged samples.
+em_status bcast_ir_state(em_batch *b, Dev &X)
+{
+    Dev &d = b->d;
+    hipStream_t st = b->stream;
+    const int S = d.S;
+    launch_bcast0_f64(d.u, d.n_nodes, S, st);
+    launch_bcast0_u8(d.live, d.n_nodes, S, st);
+    launch_bcast0_f64(d.drop, 1, S, st);
+    launch_bcast0_f64(d.jseg, d.n_res, S, st);
+    if (b->condensed) {
+        launch_bcast0_f64(X.G, X.n_res, S, st);
+        launch_bcast0_f64(X.u, X.n_nodes, S, st);
+        launch_bcast0_u8(X.live, X.n_nodes, S, st);
+        launch_bcast0_f64(X.sink_s, X.n_nodes, S, st);
+        launch_bcast0_f64(b->cond.cinj, 2LL * b->cond.n_chain, S, st);
+    }
+    LAUNCHCHK(b);
+    return EM_OK;
+}
+
 em_status ir_solve_impl(em_batch *b)
 {
     Dev &d = b->d;
     hipStream_t st = b->stream;
     HIPCHK(b, hipMemsetAsync(d.g_changed, 0, 4, st));
-    // per-sample change flags: samples whose conductances are those of the
+    // Per-sample change flags: samples whose conductances are those of the
     // last solve keep its solution (every sample counts as changed when the
-    // state was replaced since: creation, reset, restore, set_seg_state)
-    HIPCHK(b, hipMemsetAsync(d.g_chg_s, b->ir_valid ? 0 : 1, d.S, st));
+    // state was replaced since: creation, reset, restore, set_seg_state).
+    // When every sample carries the nominal network and the same warm start,
+    // one solve (sample 0) serves all of them and its state is copied.
+    const bool uniform = b->nominal && !b->ir_valid && d.S > 1;
+    HIPCHK(b, hipMemsetAsync(d.g_chg_s, (b->ir_valid || uniform) ? 0 : 1, d.S, st));
+    if (uniform) HIPCHK(b, hipMemsetAsync(d.g_chg_s, 1, 1, st));
     launch_ir_conductance(d, st);
     LAUNCHCHK(b);
     if (b->ir_valid && !b->live_dirty) {
@@ -371,9 +399,6 @@ em_status ir_solve_impl(em_batch *b)
     launch_ir_gather_inc(X, b->n_inc, st);
     launch_ir_setup(X, st);
     launch_ir_finalize0(X, rtol, st);
-    // every sample carries the nominal network and the same warm start: one
-    // solve serves all of them
-    const bool uniform = b->nominal && !b->ir_valid && d.S > 1;
     if (uniform) launch_ir_only_sample0(X, st);
     LAUNCHCHK(b);
     uint8_t *hconv = pinned(b, std::max<size_t>(d.S, 8));
@@ -405,14 +430,13 @@ em_status ir_solve_impl(em_batch *b)
         }
         b->cg_iters_last = itmax;
         if (b->condensed) launch_chain_expand(d, X, b->cond, st);
-        if (uniform) {
-            launch_ir_bcast0(d, st);
-            if (b->condensed) launch_ir_bcast0(X, st);     // the next warm start too
-        }
         launch_ir_finish(d, st);
+        if (uniform) {
+            em_status rb = bcast_ir_state(b, X);
+            if (rb != EM_OK) return rb;
+        }
         LAUNCHCHK(b);
-        em_status rf = update_forcing(b);
-        if (rf != EM_OK) return rf;
+        b->forcing_stale = true;          // dt*f follows before the next step
         b->have_j = true;
         b->ir_valid = true;
         return EM_OK;
@@ -469,14 +493,13 @@ em_status ir_solve_impl(em_batch *b)
     LAUNCHCHK(b);
     b->cg_iters_last = it;
     if (b->condensed) launch_chain_expand(d, X, b->cond, st);
-    if (uniform) {
-        launch_ir_bcast0(d, st);
-        if (b->condensed) launch_ir_bcast0(X, st);         // the next warm start too
-    }
     launch_ir_finish(d, st);
+    if (uniform) {
+        em_status rb = bcast_ir_state(b, X);
+        if (rb != EM_OK) return rb;
+    }
     LAUNCHCHK(b);
-    em_status rf = update_forcing(b);
-    if (rf != EM_OK) return rf;
+    b->forcing_stale = true;              // dt*f follows before the next step (active set known)
     b->have_j = true;
     b->ir_valid = true;
     return EM_OK;
@@ -656,6 +679,11 @@ em_status timed_step(em_batch *b, int n_steps, int step0)
 {
     em_status rc = ensure_active(b);
     if (rc != EM_OK) return rc;
+    if (b->forcing_stale) {
+        rc = update_forcing(b);
+        if (rc != EM_OK) return rc;
+        b->forcing_stale = false;
+    }
     return timed_step_dev(b, b->d, n_steps, step0);
 }
 

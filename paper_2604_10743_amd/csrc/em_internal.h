@@ -262,9 +262,10 @@ void launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
 void launch_ttf_init(const Dev &d, double fail, hipStream_t st);
 void launch_ttf_update(const Dev &d, double fail, int k, double t, hipStream_t st);
 // identical samples: iterate sample 0 only (conv of the others set), then
-// copy its voltages and reachability to every sample
+// copy its [S][n] state to every sample
 void launch_ir_only_sample0(const Dev &d, hipStream_t st);
-void launch_ir_bcast0(const Dev &d, hipStream_t st);
+void launch_bcast0_f64(double *a, long long n, int S, hipStream_t st);
+void launch_bcast0_u8(uint8_t *a, long long n, int S, hipStream_t st);
 // cnt[2s] = trees of sample s holding a void, cnt[2s+1] = segments with dR > 0 or open
 void launch_result_counts(const Dev &d, int *cnt, hipStream_t st);
 

@@ -536,23 +536,25 @@ EM_KERNEL void k_ir_only_sample0(Dev d)
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= 1 && s < d.S) d.conv[s] = 1;
 }
-// ... and its voltages and reachability are every sample's.
-EM_KERNEL void k_ir_bcast0(Dev d)
+// ... and its per-sample IR state ([S][n] arrays) is every sample's.
+template <typename T>
+EM_KERNEL void k_bcast0(T *a, long long n, int S)
 {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (long long)d.S * d.n_nodes) return;
-    const int i = (int)(g % d.n_nodes);
-    if (g < d.n_nodes) return;
-    d.u[g] = d.u[i];
-    d.live[g] = d.live[i];
+    if (g < n || g >= n * S) return;
+    a[g] = a[g % n];
 }
 void launch_ir_only_sample0(const Dev &d, hipStream_t st)
 {
     k_ir_only_sample0<<<nb(d.S), IR_BS, 0, st>>>(d);
 }
-void launch_ir_bcast0(const Dev &d, hipStream_t st)
+void launch_bcast0_f64(double *a, long long n, int S, hipStream_t st)
 {
-    k_ir_bcast0<<<nb((long long)d.S * d.n_nodes), IR_BS, 0, st>>>(d);
+    if (n > 0 && S > 1) k_bcast0<double><<<nb(n * S), IR_BS, 0, st>>>(a, n, S);
+}
+void launch_bcast0_u8(uint8_t *a, long long n, int S, hipStream_t st)
+{
+    if (n > 0 && S > 1) k_bcast0<uint8_t><<<nb(n * S), IR_BS, 0, st>>>(a, n, S);
 }
 
 // Per-sample result counts (one block per sample): segments with a
