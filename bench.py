@@ -240,6 +240,47 @@ def mc_leg(args, name, oracle, plain):
     return o
 
 
+def thermal_leg(args):
+    """Equal-average thermal maps (the paper's thermal-profile observation):
+    the mc_grid network under a uniform map, four hotspots over the wires of
+    highest current density, the same hotspots over the wires of lowest
+    current density, and the latter 5 K hotter on average; Monte Carlo to TTF
+    for each (256 samples)."""
+    import numpy as np
+    import torch
+    import paper_2604_10743_amd as P
+    from paper_2604_10743_amd import synth
+
+    g, mat, run, mc = synth.workload("mc_grid")
+    mc = dict(mc, n_samples=256)
+    B = P.Batch(g, mat, run)
+    B.ir_solve()
+    j = B.seg_j(0)
+    B.close()
+    hot = synth.hotspot_centers(g, j, 4, 150e-6, highest=True)
+    cold = synth.hotspot_centers(g, j, 4, 150e-6, highest=False)
+    out = {"workload": "mc_grid network, 256 samples per map, hotspots 4 x +60 K (sigma 60 um, 150 um apart), "
+                       "die-average 335 K (hotter variant 340 K)", "maps": {}}
+    yr = 365.25 * 86400.0
+    t_all = 0.0
+    for name, h in synth.thermal_variants(g, hot, cold, 335.0, 60.0, 60e-6, hotter_K=5.0).items():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Bm = P.Batch(h, mat, run, mc)
+        res = Bm.run_to_ttf()
+        torch.cuda.synchronize()
+        t_all += time.perf_counter() - t0
+        ttf = np.array([r["ttf_s"] for r in res if r["failed"]])
+        out["maps"][name] = {"mean_T_K": float(h.tmap.mean()), "max_T_K": float(h.tmap.max()),
+                             "n_fail": int(ttf.size), "n_censored": int(len(res) - ttf.size),
+                             "ttf_mean_y": float(ttf.mean() / yr) if ttf.size else None,
+                             "nucleated_trees_per_sample": float(np.mean([r["n_nucleated_trees"] for r in res])),
+                             "final_drop_mean": float(np.mean([r["final_drop"] for r in res]))}
+        Bm.close()
+    out["samples_per_s"] = 4 * 256 / t_all
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -356,6 +397,10 @@ def main():
         log("bench: mc (mc_grid) done")
         out["mc_mesh"] = mc_leg(args, "mc_mesh", oracle=False, plain=False)
         log("bench: mc (mc_mesh) done")
+
+    if not args.no_mc:
+        out["thermal_sweep"] = thermal_leg(args)
+        log("bench: thermal sweep done")
 
     if not args.no_sur:
         out["surrogate"] = surrogate_leg(args)

@@ -1031,6 +1031,11 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     AL(d.gdx0, double, ns); AL(d.mdrv, double, ns); AL(d.tree_V, double, nt);
     d.Vr = dalloc(b, rs * ns);
     d.sigma = dalloc(b, rs * NS); d.dtf = dalloc(b, rs * NS); d.dinv = dalloc(b, rs * NS);
+    d.sig_lo = nullptr;
+    if (b->fp32) {
+        d.sig_lo = (float *)dalloc(b, 4 * NS);
+        if (!d.sig_lo) return fail(b, EM_ERR_OOM, "device allocation");
+    }
     d.lfac = dalloc(b, rs * NS); d.sc = dalloc(b, rs * NS);
     if (!d.Vr || !d.sigma || !d.dtf || !d.dinv || !d.lfac || !d.sc) return fail(b, EM_ERR_OOM, "device allocation");
     AL(d.psi, double, NS);
@@ -1745,6 +1750,7 @@ struct SnapIO {
 // device <-> snapshot region of n bytes
 em_status snap_dev(em_batch *b, SnapIO &io, void *dev, size_t n, bool restore)
 {
+    if (n == 0) return EM_OK;
     if (restore) {
         if (io.pos + n > io.cap) { io.ok = false; return EM_OK; }
         HIPCHK(b, hipMemcpy(dev, io.q + io.pos, n, hipMemcpyHostToDevice));
@@ -1776,7 +1782,7 @@ em_status snap_walk(em_batch *b, SnapIO &io, bool restore)
     const size_t S = b->S, IS = (size_t)b->n_trees * S, NS = (size_t)b->ns * S, RS = (size_t)b->n_res * S,
                  VS = (size_t)b->n_nodes * S, rsz = b->fp32 ? 4 : 8, IV = IS * MAXV;
     struct Item { void *p; size_t n; } items[] = {
-        {d.sigma, rsz * NS}, {d.jseg, 8 * RS}, {d.u, 8 * VS}, {d.drop, 8 * S}, {d.dR, 8 * RS},
+        {d.sigma, rsz * NS}, {d.sig_lo, d.sig_lo ? 4 * NS : 0}, {d.jseg, 8 * RS}, {d.u, 8 * VS}, {d.drop, 8 * S}, {d.dR, 8 * RS},
         {d.open, RS}, {d.inst_active, IS}, {d.tree_mortal, IS}, {d.seg_mortal, RS}, {d.sample_active, S},
         {d.nv, 4 * IS}, {d.vnode, 4 * IV}, {d.vseg, 4 * IV}, {d.vphase, 4 * IV}, {d.vstep, 4 * IV},
         {d.vearly, 4 * IV}, {d.vvol, 8 * IV}, {d.vlen, 8 * IV}, {d.vrob, 8 * IV}, {d.n_suppressed, 4 * IS},

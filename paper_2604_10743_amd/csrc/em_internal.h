@@ -65,6 +65,7 @@ struct Dev {
     double *tree_V;                     // [n_trees] total control volume
     // ---- per (node, sample) stepping state; element type float or double ----
     void *sigma, *dtf, *dinv, *lfac, *sc, *Vr;
+    float *sig_lo;                      // FP32 form: low part of the stress state (null in FP64)
     double *psi;                        // screen scratch / steady stress [node][S]
     double *wsp;                        // stepping workspace [node][S] (generic tree kernel)
     // ---- Monte Carlo draws [res][S] ----

@@ -67,6 +67,7 @@ __device__ inline double chain_robin_weight(const Dev &d, int v, int s)
 
 struct ChainHot {
     void *sigma;
+    float *sig_lo;           // FP32 form: low part of the stress state
     const void *Vr, *dtf, *sc;
     const int *lane_inst, *lane_blk, *tree_off;
     const uint8_t *sample_active, *inst_active;
@@ -118,6 +119,7 @@ __global__ __launch_bounds__(WG) void k_chain(ChainHot h)
         atomicAdd(d->node_steps, (unsigned long long)nT * (unsigned long long)h.n_steps);
 
     R *sig = (R *)h.sigma;
+    float *sig_lo = h.sig_lo;
     const R *dtf_g = (const R *)h.dtf;
     const R *sc_g = (const R *)h.sc;
     const R *Vr_g = (const R *)h.Vr;
@@ -125,6 +127,14 @@ __global__ __launch_bounds__(WG) void k_chain(ChainHot h)
 
     // ---- per-lane node data (registers for the whole launch) ----
     R sg[M], fv[M], w[M], dinv[M], al[M], be[M];
+    // FP32 form: the state carries a float low part sl (sg + sl), which keeps
+    // the increments that fall below half an ulp of sg (near saturation the
+    // per-step increments shrink to a few Pa and float alone would stall the
+    // approach to sigma_crit).  With 1024 lanes (chains of more than 4096
+    // nodes) the register file has no room for it: there the low part is
+    // folded in at load and the state rounds to float every step.
+    constexpr bool LO = sizeof(R) == 4 && WG < 1024;
+    float sl[LO ? M : 1];
     R gE[M + 1];                    // gE[j] = dt*g of edge (j-1, j); gE[0] previous block, gE[cnt] next block
     R scmin = (R)INFINITY;
 #pragma unroll
@@ -133,6 +143,11 @@ __global__ __launch_bounds__(WG) void k_chain(ChainHot h)
         if (j < cnt) {
             size_t x = (size_t)(start + j) * S + s;
             sg[j] = sig[x];
+            if constexpr (LO) {
+                sl[j] = sig_lo ? sig_lo[x] : 0.f;
+            } else if constexpr (sizeof(R) == 4) {
+                if (sig_lo) sg[j] = (R)((double)sg[j] + (double)sig_lo[x]);
+            }
             fv[j] = dtf_g[x];
             R scj = sc_g[x];
             scmin = scj < scmin ? scj : scmin;
@@ -270,12 +285,16 @@ __global__ __launch_bounds__(WG) void k_chain(ChainHot h)
         lds_barrier();
         return r;
     };
+    auto sv = [&](int j) -> double {
+        if constexpr (LO) return (double)sg[j] + (double)sl[j];
+        else return (double)sg[j];
+    };
     // stress content of this lane: its nodes plus the voids on them (a void's
     // volume is only ever written by the lane that owns its node)
     auto content = [&]() -> double {
         double q = 0.0;
 #pragma unroll
-        for (int j = 0; j < M; ++j) if (j < cnt) q += (double)Vr_g[start + j] * (double)sg[j];
+        for (int j = 0; j < M; ++j) if (j < cnt) q += (double)Vr_g[start + j] * sv(j);
         if (vmask) {
             for (int k = 0; k < nv; ++k) {
                 int jv = d->vnode[inst * MAXV + k] - start;
@@ -291,8 +310,11 @@ __global__ __launch_bounds__(WG) void k_chain(ChainHot h)
     const double Q0 = seg_sum(content());
     // stress at the next block's separator (kept in step with that lane)
     s_x[0][lane] = sg[0];
+    if constexpr (LO) s_x[1][lane] = sl[0];
     lds_barrier();
     R sn = (act && !last) ? s_x[0][lane + 1] : (R)0;
+    float snl = 0.f;                   // its low part (FP32 form)
+    if constexpr (LO) snl = (act && !last) ? s_x[1][lane + 1] : 0.f;
     lds_barrier();
 
     for (int st = 0; st < h.n_steps; ++st) {
@@ -304,11 +326,11 @@ __global__ __launch_bounds__(WG) void k_chain(ChainHot h)
         for (int j = 0; j < M; ++j) {
             y[j] = 0;
             if (j < cnt) {
-                const double sj = (double)sg[j];
+                const double sj = sv(j);
                 double r = ((vmask >> j) & 1u) ? 0.0 : (double)fv[j];
-                const double sr = (j + 1 < cnt) ? (double)sg[j + 1] : (double)sn;
+                const double sr = (j + 1 < cnt) ? sv(j + 1) : (LO ? (double)sn + (double)snl : (double)sn);
                 r += (double)gE[j + 1] * (sr - sj);
-                if (j > 0) r += (double)gE[j] * ((double)sg[j - 1] - sj);
+                if (j > 0) r += (double)gE[j] * (sv(j - 1) - sj);
                 if (j == 0) r0_part = r; else y[j] = (R)r;
             }
         }
@@ -320,8 +342,8 @@ __global__ __launch_bounds__(WG) void k_chain(ChainHot h)
 #pragma unroll
                 for (int j = 0; j < M; ++j)
                     if (j == jv) {
-                        if (j == 0) r0_part -= rb * (double)sg[0];
-                        else y[j] = (R)((double)y[j] - rb * (double)sg[j]);
+                        if (j == 0) r0_part -= rb * sv(0);
+                        else y[j] = (R)((double)y[j] - rb * sv(j));
                     }
             }
         }
@@ -339,15 +361,22 @@ __global__ __launch_bounds__(WG) void k_chain(ChainHot h)
                 y[j] = yn;
             }
         R yF = 0, yL = 0, sL = sg[0];
+        float sLl = 0.f;
+        if constexpr (LO) sLl = sl[0];
         if (cnt >= 2) {
             yF = y[1];
 #pragma unroll
-            for (int j = 1; j < M; ++j) if (j == cnt - 1) { yL = y[j]; sL = sg[j]; }
+            for (int j = 1; j < M; ++j)
+                if (j == cnt - 1) {
+                    yL = y[j]; sL = sg[j];
+                    if constexpr (LO) sLl = sl[j];
+                }
         }
         // 3. exchange with the previous block: its last interior value and its
         //    last node's stress (for the separator's residual), then PCR
         s_e[0][lane] = yL;
         s_e[1][lane] = sL;
+        if constexpr (LO) s_e[2][lane] = sLl;
         lds_barrier();
         R Rk = 0;
         if (act) {
@@ -355,7 +384,9 @@ __global__ __launch_bounds__(WG) void k_chain(ChainHot h)
             R yLp = 0;
             if (!first) {
                 yLp = s_e[0][lane - 1];
-                r0 += (double)gE[0] * ((double)s_e[1][lane - 1] - (double)sg[0]);
+                double sp = (double)s_e[1][lane - 1];
+                if constexpr (LO) sp += (double)s_e[2][lane - 1];
+                r0 += (double)gE[0] * (sp - sv(0));
             }
             Rk = (R)r0 + gE[0] * yLp + e_first() * yF;
         }
@@ -377,11 +408,26 @@ __global__ __launch_bounds__(WG) void k_chain(ChainHot h)
         lds_barrier();
         const R xn = (act && !last) ? s_x[buf][lane + 1] : (R)0;
         // 4. increments and new stress
-        sg[0] += xk;
+        if constexpr (LO) {
+            auto put = [&](int j, double v) {      // state <- v as sg + sl
+                const R hv = (R)v;
+                sg[j] = hv;
+                sl[j] = (float)(v - (double)hv);
+            };
+            put(0, sv(0) + (double)xk);
 #pragma unroll
-        for (int j = 1; j < M; ++j)
-            if (j < cnt) sg[j] += y[j] + al[j] * xk + be[j] * xn;
-        sn += xn;
+            for (int j = 1; j < M; ++j)
+                if (j < cnt) put(j, sv(j) + (double)(y[j] + al[j] * xk + be[j] * xn));
+            const double v = (double)sn + (double)snl + (double)xn;
+            sn = (R)v;
+            snl = (float)(v - (double)sn);
+        } else {
+            sg[0] += xk;
+#pragma unroll
+            for (int j = 1; j < M; ++j)
+                if (j < cnt) sg[j] += y[j] + al[j] * xk + be[j] * xn;
+            sn += xn;
+        }
 
         // void growth on the lanes owning void nodes (eq. 15 accounting)
         if (vmask) {
@@ -389,10 +435,17 @@ __global__ __launch_bounds__(WG) void k_chain(ChainHot h)
                 const int q = inst * MAXV + k;
                 const int jv = d->vnode[q] - start;
                 if (jv < 0 || jv >= cnt) continue;
-                R sv = 0, fvv = 0;
+                R sh = 0, fvv = 0;
+                float slo = 0.f;
 #pragma unroll
-                for (int j = 0; j < M; ++j) if (j == jv) { sv = sg[j]; fvv = fv[j]; }
-                const double vol = d->vvol[q] + (dt * d->vrob[q] * (double)sv + (double)fvv) / d->B;
+                for (int j = 0; j < M; ++j)
+                    if (j == jv) {
+                        sh = sg[j]; fvv = fv[j];
+                        if constexpr (LO) slo = sl[j];
+                    }
+                double svv = (double)sh;
+                if constexpr (LO) svv += (double)slo;
+                const double vol = d->vvol[q] + (dt * d->vrob[q] * svv + (double)fvv) / d->B;
                 d->vvol[q] = vol;
                 const int e = d->vseg[q];
                 const double W = d->w[e], H = d->h[e];
@@ -411,27 +464,51 @@ __global__ __launch_bounds__(WG) void k_chain(ChainHot h)
         // nucleation: any non-void node at or above its critical stress?
         bool cand = false;
         if (act) {
-#pragma unroll
-            for (int j = 0; j < M; ++j)
-                if (j < cnt && sg[j] >= scmin && !((vmask >> j) & 1u)) cand = true;
-            if (cand) {
-                cand = false;
+            if constexpr (LO) {
 #pragma unroll
                 for (int j = 0; j < M; ++j)
-                    if (j < cnt && !((vmask >> j) & 1u) && sg[j] >= sc_g[(size_t)(start + j) * S + s])
-                        cand = true;
+                    if (j < cnt && sv(j) >= (double)scmin && !((vmask >> j) & 1u)) cand = true;
+                if (cand) {
+                    cand = false;
+#pragma unroll
+                    for (int j = 0; j < M; ++j)
+                        if (j < cnt && !((vmask >> j) & 1u) && sv(j) >= (double)sc_g[(size_t)(start + j) * S + s])
+                            cand = true;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < M; ++j)
+                    if (j < cnt && sg[j] >= scmin && !((vmask >> j) & 1u)) cand = true;
+                if (cand) {
+                    cand = false;
+#pragma unroll
+                    for (int j = 0; j < M; ++j)
+                        if (j < cnt && !((vmask >> j) & 1u) && sg[j] >= sc_g[(size_t)(start + j) * S + s])
+                            cand = true;
+                }
             }
         }
         if (__syncthreads_or(cand ? 1 : 0)) {
             // peak candidate per instance, then the lowest node within the tie window
-            R lm = (R)(-INFINITY);
-            if (cand) {
+            if constexpr (LO) {
+                double lm = -INFINITY;
+                if (cand) {
 #pragma unroll
-                for (int j = 0; j < M; ++j)
-                    if (j < cnt && !((vmask >> j) & 1u) && sg[j] >= sc_g[(size_t)(start + j) * S + s])
-                        lm = sg[j] > lm ? sg[j] : lm;
+                    for (int j = 0; j < M; ++j)
+                        if (j < cnt && !((vmask >> j) & 1u) && sv(j) >= (double)sc_g[(size_t)(start + j) * S + s])
+                            lm = sv(j) > lm ? sv(j) : lm;
+                }
+                s_q[lane] = lm;
+            } else {
+                R lm = (R)(-INFINITY);
+                if (cand) {
+#pragma unroll
+                    for (int j = 0; j < M; ++j)
+                        if (j < cnt && !((vmask >> j) & 1u) && sg[j] >= sc_g[(size_t)(start + j) * S + s])
+                            lm = sg[j] > lm ? sg[j] : lm;
+                }
+                s_q[lane] = (double)lm;
             }
-            s_q[lane] = (double)lm;
             lds_barrier();
 #pragma unroll
             for (int l = 0; l < LEV; ++l) {
@@ -444,15 +521,26 @@ __global__ __launch_bounds__(WG) void k_chain(ChainHot h)
             lds_barrier();
             const bool any = act && mxd != -INFINITY;
             const bool has = any && nv < d->max_voids;
-            const R mx = (R)mxd;
-            const R thr = mx - (R)1e-12 * (mx < 0 ? -mx : mx);
             int loc = 0x7fffffff;
-            if (has && cand) {
+            if constexpr (LO) {
+                const double thr = mxd - 1e-12 * (mxd < 0 ? -mxd : mxd);
+                if (has && cand) {
 #pragma unroll
-                for (int j = M - 1; j >= 0; --j)
-                    if (j < cnt && !((vmask >> j) & 1u) && sg[j] >= thr &&
-                        sg[j] >= sc_g[(size_t)(start + j) * S + s])
-                        loc = start + j;
+                    for (int j = M - 1; j >= 0; --j)
+                        if (j < cnt && !((vmask >> j) & 1u) && sv(j) >= thr &&
+                            sv(j) >= (double)sc_g[(size_t)(start + j) * S + s])
+                            loc = start + j;
+                }
+            } else {
+                const R mx = (R)mxd;
+                const R thr = mx - (R)1e-12 * (mx < 0 ? -mx : mx);
+                if (has && cand) {
+#pragma unroll
+                    for (int j = M - 1; j >= 0; --j)
+                        if (j < cnt && !((vmask >> j) & 1u) && sg[j] >= thr &&
+                            sg[j] >= sc_g[(size_t)(start + j) * S + s])
+                            loc = start + j;
+                }
             }
             s_q[lane] = (double)loc;
             lds_barrier();
@@ -496,23 +584,44 @@ __global__ __launch_bounds__(WG) void k_chain(ChainHot h)
         // conservation projection (rounding-level)
         if (h.proj_every > 0 && ((st + 1) % h.proj_every == 0 || st + 1 == h.n_steps)) {
             const double Q = seg_sum(content());
-            const R corr = act ? (R)((Q0 - Q) / Vtot) : (R)0;
+            if constexpr (LO) {
+                const double corr = act ? (Q0 - Q) / Vtot : 0.0;
 #pragma unroll
-            for (int j = 0; j < M; ++j) sg[j] += corr;
-            sn += corr;
+                for (int j = 0; j < M; ++j) {
+                    const double v = sv(j) + corr;
+                    sg[j] = (R)v;
+                    sl[j] = (float)(v - (double)sg[j]);
+                }
+                const double v = (double)sn + (double)snl + corr;
+                sn = (R)v;
+                snl = (float)(v - (double)sn);
+            } else {
+                const R corr = act ? (R)((Q0 - Q) / Vtot) : (R)0;
+#pragma unroll
+                for (int j = 0; j < M; ++j) sg[j] += corr;
+                sn += corr;
+            }
         }
     }
     // ---- write back ----
 #pragma unroll
     for (int j = 0; j < M; ++j)
-        if (j < cnt) sig[(size_t)(start + j) * S + s] = sg[j];
+        if (j < cnt) {
+            const size_t x = (size_t)(start + j) * S + s;
+            sig[x] = sg[j];
+            if constexpr (LO) {
+                if (sig_lo) sig_lo[x] = sl[j];
+            } else if constexpr (sizeof(R) == 4) {
+                if (sig_lo) sig_lo[x] = 0.f;
+            }
+        }
 }
 
 void launch_chain(const Dev &d, const Dev *d_dev, bool fp32, int n_steps, int step0, hipStream_t st)
 {
     if (d.n_chain_wg <= 0) return;
     ChainHot h;
-    h.sigma = d.sigma; h.Vr = d.Vr; h.dtf = d.dtf; h.sc = d.sc;
+    h.sigma = d.sigma; h.sig_lo = d.sig_lo; h.Vr = d.Vr; h.dtf = d.dtf; h.sc = d.sc;
     h.lane_inst = d.lane_inst; h.lane_blk = d.lane_blk; h.tree_off = d.tree_off;
     h.sample_active = d.sample_active; h.inst_active = d.inst_active;
     h.dev = d_dev;

@@ -302,6 +302,23 @@ __device__ inline int inst_of_slot(const Dev &d, int slot, int &t, int &s)
     return t * d.S + s;
 }
 
+// Stress state: R per (node, sample), plus (FP32 form) a float low part, so
+// that the state carries the increments that fall below half an ulp of the
+// stored value (near saturation the per-step increments shrink to a few Pa,
+// which float alone would drop: the approach to sigma_crit would stall).
+template <typename R>
+__device__ inline double ld_sig(const Dev &d, const R *hi, size_t x)
+{
+    return (double)hi[x] + (d.sig_lo ? (double)d.sig_lo[x] : 0.0);
+}
+template <typename R>
+__device__ inline void st_sig(const Dev &d, R *hi, size_t x, double v)
+{
+    const R h = (R)v;
+    hi[x] = h;
+    if (d.sig_lo) d.sig_lo[x] = (float)(v - (double)h);
+}
+
 template <typename R>
 EM_KERNEL void k_factor(Dev d)
 {
@@ -560,7 +577,7 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
     const double Vsum = d.tree_V[t];
     // conserved content at launch start: sum V sigma + B * void volume
     double Q0 = 0.0;
-    for (int i = i0; i < i1; ++i) Q0 += d.V[i] * (double)sig[(size_t)i * S + s];
+    for (int i = i0; i < i1; ++i) Q0 += d.V[i] * ld_sig(d, sig, (size_t)i * S + s);
     for (int k = 0; k < nv; ++k) Q0 += d.B * vvol[k];
     double corr = 0.0;
 
@@ -572,16 +589,16 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
         double b_next = 0.0, s_next = 0.0;
         for (int i = i1 - 1; i >= i0; --i) {
             const size_t x = (size_t)i * S + s;
-            const double si = (double)sig[x] + corr;
+            const double si = ld_sig(d, sig, x) + corr;
             const bool isv = in_list(i, vn, nv);
             double r = isv ? 0.0 : (double)dtf[x];
             const int p = d.parent[i];
-            if (p >= 0) r += d.dt * d.xi_k[(size_t)d.seg[i] * S + s] * d.g0[i] * (((double)sig[(size_t)p * S + s] + corr) - si);
+            if (p >= 0) r += d.dt * d.xi_k[(size_t)d.seg[i] * S + s] * d.g0[i] * ((ld_sig(d, sig, (size_t)p * S + s) + corr) - si);
             for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k) {
                 const int c = d.child[k];
                 const size_t y = (size_t)c * S + s;
                 const double gc = d.dt * d.xi_k[(size_t)d.seg[c] * S + s] * d.g0[c];
-                const double sc_ = (c == i + 1) ? s_next : (double)sig[y] + corr;
+                const double sc_ = (c == i + 1) ? s_next : ld_sig(d, sig, y) + corr;
                 const double bc = (c == i + 1) ? b_next : W[y];
                 r += gc * (sc_ - si) + (double)lf[y] * bc;
             }
@@ -594,7 +611,7 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
         }
         // Pass 2 (root-to-leaf): delta_i = b_i / d_i + l_i delta_parent;
         // sigma += delta; track the nucleation candidate peak.
-        R mx = (R)0;
+        double mx = 0.0;
         bool any = false;
         double Q = 0.0;
         double dprev = 0.0;
@@ -607,10 +624,10 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
             }
             W[x] = dl;
             dprev = dl;
-            const R v = (R)((double)sig[x] + corr + dl);
-            sig[x] = v;
-            Q += d.V[i] * (double)v;
-            if (v >= sc[x] && !in_list(i, vn, nv)) {
+            const double v = ld_sig(d, sig, x) + corr + dl;
+            st_sig(d, sig, x, v);
+            Q += d.V[i] * v;
+            if (v >= (double)sc[x] && !in_list(i, vn, nv)) {
                 mx = any ? (v > mx ? v : mx) : v;
                 any = true;
             }
@@ -618,7 +635,7 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
         // void growth: dV = (dt/B) (Robin weight * sigma_v + f_v)
         for (int k = 0; k < nv; ++k) {
             size_t x = (size_t)vn[k] * S + s;
-            vvol[k] += (d.dt * vrob[k] * (double)sig[x] + (double)dtf[x]) / d.B;
+            vvol[k] += (d.dt * vrob[k] * ld_sig(d, sig, x) + (double)dtf[x]) / d.B;
             int e = vseg[k];
             double Wd = d.w[e], H = d.h[e];
             double l = fmin(vvol[k] / (Wd * H), d.len[e]);
@@ -639,12 +656,12 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
         // nucleation
         if (any) {
             if (nv < d.max_voids) {
-                R thr = mx - (R)1e-12 * (mx < 0 ? -mx : mx);
+                const double thr = mx - 1e-12 * (mx < 0 ? -mx : mx);
                 int v = -1;
                 for (int i = i0; i < i1 && v < 0; ++i) {
                     size_t x = (size_t)i * S + s;
-                    R val = sig[x];
-                    if (val >= sc[x] && val >= thr && !in_list(i, vn, nv)) v = i;
+                    const double val = ld_sig(d, sig, x);
+                    if (val >= (double)sc[x] && val >= thr && !in_list(i, vn, nv)) v = i;
                 }
                 add_void<R>(d, inst, t, s, v, step0 + st, vn, vvol, vlen, vrob, vseg, vphase, vearly, nv);
             } else {
@@ -652,10 +669,11 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
             }
         }
     }
-    if (corr != 0.0) {
-        const R rc = (R)corr;
-        for (int i = i0; i < i1; ++i) sig[(size_t)i * S + s] += rc;
-    }
+    if (corr != 0.0)
+        for (int i = i0; i < i1; ++i) {
+            const size_t x = (size_t)i * S + s;
+            st_sig(d, sig, x, ld_sig(d, sig, x) + corr);
+        }
     d.nv[inst] = nv;
     for (int k = 0; k < nv; ++k) {
         int q = inst * MAXV + k;
@@ -691,6 +709,7 @@ EM_KERNEL void k_set_sigma_T(Dev d)
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long long)d.ns * d.S) return;
     ((R *)d.sigma)[g] = (R)d.sigT;
+    if (d.sig_lo) d.sig_lo[g] = (float)(d.sigT - (double)(R)d.sigT);
 }
 
 template <typename R>
@@ -725,8 +744,14 @@ EM_KERNEL void k_copy_col(Dev d, void *arr, int s, double *out, int to_state)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= d.ns) return;
     R *a = (R *)arr;
-    if (to_state) a[(size_t)i * d.S + s] = (R)out[i];
-    else out[i] = (double)a[(size_t)i * d.S + s];
+    const size_t x = (size_t)i * d.S + s;
+    if (arr == d.sigma) {               // the stress state (with its low part)
+        if (to_state) st_sig(d, a, x, out[i]);
+        else out[i] = ld_sig(d, (const R *)a, x);
+    } else {
+        if (to_state) a[x] = (R)out[i];
+        else out[i] = (double)a[x];
+    }
 }
 
 // ------------------------------------------------------------------------

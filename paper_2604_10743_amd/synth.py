@@ -17,6 +17,7 @@ temperature around 353 K, hotspots tens of kelvin above it).
 """
 from __future__ import annotations
 
+import copy
 import dataclasses
 from typing import Optional
 
@@ -486,6 +487,66 @@ def screen_training_grids(seed: int, n_grids: int, n: int = 200, j_scale=(0.8, 1
         g = sparse_via_grid(int(rng.integers(1, 2 ** 31)), n=n, via_every=ve,
                             sink_scale=float(rng.uniform(lo, hi)))
         out.append((g, float(rng.uniform(*j_scale))))
+    return out
+
+
+def hotspot_map_at(extent_x: float, extent_y: float, base_K: float, centers, amp_K: float,
+                   sigma: float, res: float = 1 * UM):
+    """Base temperature plus equal Gaussian hotspots (amplitude amp_K, width
+    sigma) at the given (x, y) centres, on a regular raster.  Returns
+    (tmap[ny, nx], x0, y0, dx, dy)."""
+    nx = int(np.ceil(extent_x / res)) + 1
+    ny = int(np.ceil(extent_y / res)) + 1
+    x = np.arange(nx) * res
+    y = np.arange(ny) * res
+    T = np.full((ny, nx), float(base_K))
+    for cx, cy in centers:
+        T += amp_K * np.outer(np.exp(-0.5 * ((y - cy) / sigma) ** 2), np.exp(-0.5 * ((x - cx) / sigma) ** 2))
+    return T, 0.0, 0.0, res, res
+
+
+def hotspot_centers(g: Grid, seg_j: np.ndarray, k: int, min_sep: float, highest: bool = True):
+    """Midpoints of the k wire segments of highest (or lowest) |j| that lie
+    at least min_sep apart (greedy in |j| order)."""
+    wire = g.res_is_via == 0
+    key = np.where(wire, np.abs(seg_j), -np.inf if highest else np.inf)
+    order = np.argsort(-key if highest else key, kind="stable")
+    mid = 0.5 * (g.xy[g.res_a] + g.xy[g.res_b])
+    out = []
+    for e in order:
+        if not wire[e]:
+            break
+        c = mid[e]
+        if all(np.hypot(*(c - h)) >= min_sep for h in out):
+            out.append(c)
+            if len(out) == k:
+                break
+    return out
+
+
+def thermal_variants(g: Grid, hot_centers, cold_centers, mean_K: float, amp_K: float, sigma: float,
+                     hotter_K: float = 0.0):
+    """Copies of grid g under thermal maps of one die-average temperature
+    (the raster mean): 'uniform'; 'hot_on_high_j', hotspots at hot_centers
+    (e.g. over the wires of highest current density); 'hot_on_low_j', the
+    same hotspots at cold_centers; and 'hot_on_low_j_hotter', the latter
+    raised by hotter_K on average.  The paper's thermal observations compare
+    lifetimes under maps of equal and of different average temperature."""
+    ext_x = float(g.xy[:, 0].max())
+    ext_y = float(g.xy[:, 1].max())
+    out = {}
+    for name, centers, shift in (("uniform", [], 0.0), ("hot_on_high_j", hot_centers, 0.0),
+                                 ("hot_on_low_j", cold_centers, 0.0),
+                                 ("hot_on_low_j_hotter", cold_centers, hotter_K)):
+        if name == "hot_on_low_j_hotter" and hotter_K == 0.0:
+            continue
+        T, x0, y0, dx, dy = hotspot_map_at(ext_x, ext_y, 0.0, centers, amp_K, sigma)
+        T = T - T.mean() + mean_K + shift
+        h = copy.deepcopy(g)
+        h.node_T = None
+        h.tmap, h.tmap_x0, h.tmap_y0, h.tmap_dx, h.tmap_dy = T, x0, y0, dx, dy
+        h.name = f"{g.name}_{name}"
+        out[name] = h
     return out
 
 
