@@ -97,6 +97,11 @@ typedef struct {
     double delta;      /* void-interface thickness of the Robin row, m */
     double rho_ta;     /* liner resistivity, ohm m */
     double h_ta;       /* liner thickness, m */
+    /* Thermal block of the Joule-heating pre-pass (Sec. II-A, eqs. 2-4; read
+     * only when em_run_params.joule != 0): wire and dielectric thermal
+     * conductivities (W/(m K)) and the dielectric thickness t_ILD (m).  The
+     * wire thickness t_cu of eq. 2 is each segment's res_h. */
+    double k_cu, k_ild, t_ild;
 } em_material;
 
 /* Numerics (the paper's YAML numerical block). */
@@ -139,6 +144,19 @@ typedef struct {
                                     tree), or one of those (at most 512 in FP64) that holds it.
                                     Results do not depend on it (instances never share a
                                     reduction: the couplings across their boundaries are zero). */
+    int32_t joule;               /* 1: one-time Joule-heating thermal pre-pass at batch creation
+                                    (Sec. II-A): the currents of a nominal IR solve (or the
+                                    prescribed seg_j) heat every wire segment; each segment's
+                                    steady profile solves k T'' + j^2 rho = k (T - T0)/Gamma^2,
+                                    Gamma^2 = t_cu t_ILD k_cu / k_ILD, between its end
+                                    temperatures.  A tree vertex with a via takes the map
+                                    temperature; the other vertices follow from heat-flux
+                                    balance over their segments (exact per-tree elimination).
+                                    T0 of a segment is the map temperature at its midpoint
+                                    (the uniform T_ambient without thermal data).  The stress
+                                    nodes then take the profile's values; the field is fixed for
+                                    the batch (resets keep it).  0: node temperatures sampled
+                                    from the map directly. */
 } em_run_params;
 
 /* Monte Carlo (Sec. IV-F): per-segment unit-mean lognormal multipliers on

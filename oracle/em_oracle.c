@@ -10,7 +10,8 @@
  * Every routine follows the paper's definitions in the paper's order, with
  * scalar loops and no blocking or fusion:
  *   - topology           : wire trees of the extracted netlist (Sec. IV-A)
- *   - node temperatures  : per-tree thermal profile from the map (Sec. II-A)
+ *   - node temperatures  : sampled from the thermal map (Sec. II-A), or given
+ *                          by the Joule-heating pre-pass (oracle/thermal.py)
  *   - diffusivity        : kappa = D_a(T) B Omega / (k_B T), D_a = D0 exp(-Ea/k_B T)
  *                          (Korhonen PDE, eqs. 10-13)
  *   - descriptor system  : C dsigma/dt = A sigma + f (eq. 18), vertex-centred
@@ -65,6 +66,9 @@ typedef struct {
     int max_voids;
     /* per-segment Monte Carlo multipliers; NULL means 1 */
     const double *xi_k, *xi_s;
+    /* stress-node temperatures [ns] from the Joule-heating pre-pass (Sec. II-A,
+     * oracle/thermal.py); NULL: sampled from the map as below */
+    const double *T_stress;
 } ora_problem;
 
 static int res_is_wire(const ora_problem *P, int r)
@@ -263,6 +267,10 @@ static double bilinear(const ora_problem *P, double x, double y)
 static void node_temperatures(ora_state *S)
 {
     const ora_problem *P = &S->P;
+    if (P->T_stress) {
+        for (int i = 0; i < S->ns; ++i) S->T[i] = P->T_stress[i];
+        return;
+    }
     for (int i = 0; i < S->ns; ++i) {
         int e = S->seg[i];
         double x, y;

@@ -31,6 +31,8 @@ import scipy.sparse as sp
 import scipy.sparse.csgraph as csg
 import scipy.sparse.linalg as spla
 
+from . import thermal
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 
@@ -80,7 +82,7 @@ class _Problem(C.Structure):
         ("Ea_eV", C.c_double), ("D0", C.c_double), ("scrit", C.c_double), ("Q_eV", C.c_double),
         ("sigT", C.c_double), ("delta", C.c_double), ("rho_ta", C.c_double), ("h_ta", C.c_double),
         ("N", C.c_int), ("dt", C.c_double), ("max_voids", C.c_int),
-        ("xi_k", C.c_void_p), ("xi_s", C.c_void_p),
+        ("xi_k", C.c_void_p), ("xi_s", C.c_void_p), ("T_stress", C.c_void_p),
     ]
 
 
@@ -108,7 +110,7 @@ class _Keep:
         return a
 
 
-def make_problem(grid, mat, run, xi_k=None, xi_s=None):
+def make_problem(grid, mat, run, xi_k=None, xi_s=None, T_stress=None):
     keep = _Keep()
     P = _Problem()
     P.n_nodes = grid.n_nodes
@@ -130,6 +132,7 @@ def make_problem(grid, mat, run, xi_k=None, xi_s=None):
     P.N = int(run["intervals_per_seg"]); P.dt = float(run["dt"])
     P.max_voids = int(run["max_voids_per_tree"])
     P.xi_k = _pi(keep(xi_k, np.float64)); P.xi_s = _pi(keep(xi_s, np.float64))
+    P.T_stress = _pi(keep(T_stress, np.float64))
     return P, keep
 
 
@@ -182,10 +185,11 @@ def lognormal_xi(seed: int, sample: int, n_seg: int, param: int, cov: float) -> 
 class SampleSim:
     """One sample's stress/void state (wraps the C oracle)."""
 
-    def __init__(self, grid, mat, run, topo: Topology, xi_k=None, xi_s=None, cap_events=1 << 16):
+    def __init__(self, grid, mat, run, topo: Topology, xi_k=None, xi_s=None, cap_events=1 << 16,
+                 T_stress=None):
         L = lib()
         self.grid, self.mat, self.run, self.topo = grid, mat, run, topo
-        self.P, self.keep = make_problem(grid, mat, run, xi_k, xi_s)
+        self.P, self.keep = make_problem(grid, mat, run, xi_k, xi_s, T_stress)
         t = topo
         self._t = [np.ascontiguousarray(a, np.int32) for a in
                    (t.tree_off, t.parent, t.seg, t.dir, t.vert, t.kpos, t.seg_tree)]
@@ -330,10 +334,18 @@ def run_sample(grid, mat, run, mc=None, sample=0, topo=None, keep_sim=False, max
     N = int(run["intervals_per_seg"])
     topo = topo or topology(grid, N)
     xi_k, xi_s = sample_xi(grid, mc, sample)
-    sim = SampleSim(grid, mat, run, topo, xi_k, xi_s)
+    trees_only = grid.seg_j is not None
+    if not trees_only:
+        R0 = grid.res_R0.astype(np.float64)
+        u, I, j, d0 = ir_solve(grid, R0)
+    T_stress = None
+    if run.get("joule", 0):
+        # one-time thermal pre-pass with the currents of the nominal network
+        T_stress = thermal.node_temperatures(grid, mat, float(run.get("T_ambient", 300.0)), topo,
+                                             grid.seg_j if trees_only else j)
+    sim = SampleSim(grid, mat, run, topo, xi_k, xi_s, T_stress=T_stress)
     n_steps, K = int(run["n_steps"]), int(run["ir_every"])
     res = dict(sample=sample)
-    trees_only = grid.seg_j is not None
     if trees_only:
         sim.set_j(grid.seg_j)
         if run.get("screen", 0):
@@ -344,8 +356,6 @@ def run_sample(grid, mat, run, mc=None, sample=0, topo=None, keep_sim=False, max
         res.update(ttf=float("nan"), failed=0, outer_idx=0, init_drop=float("nan"),
                    final_drop=float("nan"))
     else:
-        R0 = grid.res_R0.astype(np.float64)
-        u, I, j, d0 = ir_solve(grid, R0)
         sim.set_j(j)
         res["init_drop"] = d0
         res["u0"] = u

@@ -32,6 +32,11 @@ API = ["em_batch_create", "em_batch_destroy", "em_get_info", "em_last_error", "e
        "em_first_nucleation", "em_get_failed_segments", "em_snapshot", "em_restore", "em_autotune"]
 
 
+# Thermal block used when a material dict leaves it out (only read with joule=1):
+# k_cu, k_ILD in W/(m K), t_ILD in m.
+THERMAL_DEFAULTS = {"k_cu": 400.0, "k_ild": 1.4, "t_ild": 0.2e-6}
+
+
 class EmError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -53,7 +58,7 @@ class GridDesc(C.Structure):
 class Material(C.Structure):
     _fields_ = [("struct_size", C.c_uint32)] + [(k, C.c_double) for k in (
         "B", "Omega", "Z", "rho_cu", "Ea_eV", "D0", "sigma_crit", "Q_eV", "sigma_T", "delta",
-        "rho_ta", "h_ta")]
+        "rho_ta", "h_ta", "k_cu", "k_ild", "t_ild")]
 
 
 class RunParams(C.Structure):
@@ -62,7 +67,7 @@ class RunParams(C.Structure):
                 ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32), ("prec", C.c_int32),
                 ("screen", C.c_int32), ("max_voids_per_tree", C.c_int32), ("T_ambient", C.c_double),
                 ("stepper", C.c_int32), ("ir_precond", C.c_int32), ("ir_launch", C.c_int32),
-                ("chain_wg", C.c_int32)]
+                ("chain_wg", C.c_int32), ("joule", C.c_int32)]
 
 
 class MCParams(C.Structure):
@@ -189,7 +194,7 @@ class Batch:
         g.seg_j = _pint(keep(grid.seg_j, np.float64))
         m = Material(struct_size=C.sizeof(Material), **{k: float(mat[k]) for k in (
             "B", "Omega", "Z", "rho_cu", "Ea_eV", "D0", "sigma_crit", "Q_eV", "sigma_T", "delta",
-            "rho_ta", "h_ta")})
+            "rho_ta", "h_ta")}, **{k: float(mat.get(k, v)) for k, v in THERMAL_DEFAULTS.items()})
         r = RunParams(struct_size=C.sizeof(RunParams),
                       intervals_per_seg=int(run["intervals_per_seg"]), dt=float(run["dt"]),
                       n_steps=int(run["n_steps"]), ir_every=int(run["ir_every"]),
@@ -198,7 +203,8 @@ class Batch:
                       screen=int(run["screen"]), max_voids_per_tree=int(run["max_voids_per_tree"]),
                       T_ambient=float(run["T_ambient"]), stepper=int(run.get("stepper", 0)),
                       ir_precond=int(run.get("ir_precond", 2)),
-                      ir_launch=int(run.get("ir_launch", 0)), chain_wg=int(run.get("chain_wg", 0)))
+                      ir_launch=int(run.get("ir_launch", 0)), chain_wg=int(run.get("chain_wg", 0)),
+                      joule=int(run.get("joule", 0)))
         mcp = None
         if mc is not None:
             mcp = MCParams(struct_size=C.sizeof(MCParams), n_samples=int(mc["n_samples"]),

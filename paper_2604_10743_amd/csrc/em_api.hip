@@ -301,8 +301,13 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
         r->cg_max_iter < 1 || !(r->cg_rtol > 0) || (r->prec != EM_FP64 && r->prec != EM_FP32) ||
         r->max_voids_per_tree < 0 || r->max_voids_per_tree > MAXV || !(r->T_ambient > 0) ||
         r->stepper < 0 || r->stepper > 1 || r->ir_precond < 0 || r->ir_precond > 2 ||
-        r->ir_launch < 0 || r->ir_launch > 3)
+        r->ir_launch < 0 || r->ir_launch > 3 || r->joule < 0 || r->joule > 1)
         return fail(b, EM_ERR_ARG, "bad run parameters (max_voids_per_tree <= 4)");
+    if (r->joule) {
+        const double tv[] = {m->k_cu, m->k_ild, m->t_ild};
+        if (!finite_all(tv, 3) || !(m->k_cu > 0) || !(m->k_ild > 0) || !(m->t_ild > 0))
+            return fail(b, EM_ERR_ARG, "Joule pre-pass needs positive finite k_cu, k_ild and t_ild");
+    }
     if (mc && (mc->n_samples < 1 || mc->n_samples > 65535 || mc->cov_kappa < 0 || mc->cov_scrit < 0 || !std::isfinite(mc->cov_kappa) ||
                !std::isfinite(mc->cov_scrit)))
         return fail(b, EM_ERR_ARG, "bad Monte Carlo parameters");
@@ -813,6 +818,33 @@ const char *em_last_error(const em_batch *b)
     return b ? b->err.c_str() : "null batch";
 }
 
+// One-time thermal pre-pass (Sec. II-A): currents of the nominal network (one
+// IR solve, or the prescribed densities) -> per-tree vertex temperatures and
+// per-segment steady profiles -> node temperatures; the coefficients that
+// depend on temperature (diffusivity, thermomigration drive, the factor, and
+// in trees-only mode the forcing) are rebuilt from them, and the dynamic
+// state returns to t = 0.
+static em_status joule_prepass(em_batch *b)
+{
+    Dev &d = b->d;
+    hipStream_t st = b->stream;
+    if (!b->trees_only) {
+        em_status s = em_ir_solve(b, nullptr);
+        if (s != EM_OK) return s;
+    }
+    double *scr = (double *)dalloc(b, 16 * (size_t)d.ns);
+    if (!scr) return fail(b, EM_ERR_OOM, "device allocation");
+    launch_joule_T(d, d.jseg, scr, scr + d.ns, st);     // sample 0's currents
+    launch_edge_static(d, st);
+    if (b->trees_only) launch_update_f(d, b->fp32, st);
+    LAUNCHCHK(b);
+    if (!b->trees_only) return em_reset(b);              // refactors, voltages back to vdd
+    launch_factor(d, b->fp32, st);
+    LAUNCHCHK(b);
+    HIPCHK(b, hipStreamSynchronize(st));
+    return EM_OK;
+}
+
 em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_run_params *r,
                           const em_mc_params *mc, const em_allocator *alloc, void *hip_stream,
                           em_batch **out)
@@ -963,6 +995,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     d.scrit = m->sigma_crit; d.Q_eV = m->Q_eV; d.sigT = m->sigma_T; d.delta = m->delta;
     d.rho_ta = m->rho_ta; d.h_ta = m->h_ta;
     d.T_amb = r->T_ambient;
+    d.k_cu = m->k_cu; d.k_ild = m->k_ild; d.t_ild = m->t_ild;
 
 #define UP(dst, vec) do { auto *p_ = upload(b, vec); if (!p_) return fail(b, EM_ERR_OOM, "device upload"); dst = p_; } while (0)
 #define UPR(dst, src, n) do { auto *p_ = upload_raw(b, src, n); if (!p_) return fail(b, EM_ERR_OOM, "device upload"); dst = p_; } while (0)
@@ -1069,9 +1102,12 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     CondHost C;
     if (!b->trees_only && r->ir_precond == 2) {
         // condensed only where it removes at least a quarter of the nodes:
-        // below that the extra chain passes cost more than they save
+        // below that the extra chain passes cost more than they save.  A
+        // reduction to isolated terminals (every chain dangling, as on a
+        // single pad feeding open-ended wires) leaves no system to iterate:
+        // the nodal one is solved instead.
         C = cond_build(nn, nr, g->res_a, g->res_b, g->res_R0, is_pad.data());
-        b->condensed = (long long)C.n_term * 4 <= (long long)nn * 3;
+        b->condensed = (long long)C.n_term * 4 <= (long long)nn * 3 && !C.red_a.empty();
     }
     Dev &X = b->condensed ? b->rd : d;
     int xn = nn, xr = nr;
@@ -1189,6 +1225,10 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     launch_factor(d, b->fp32, stq);
     LAUNCHCHK(b);
     HIPCHK(b, hipStreamSynchronize(stq));
+    if (r->joule) {
+        em_status js = joule_prepass(b);
+        if (js != EM_OK) return js;
+    }
     return EM_OK;
 #undef UP
 #undef UPR

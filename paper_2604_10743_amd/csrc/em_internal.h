@@ -32,6 +32,7 @@ struct Dev {
     double dt, vdd;
     // material
     double B, Omega, Z, rho, Ea_eV, D0, scrit, Q_eV, sigT, delta, rho_ta, h_ta;
+    double k_cu, k_ild, t_ild;          // thermal block of the Joule pre-pass
     // ---- netlist (shared) ----
     const double *xy;
     const int *layer;
@@ -200,6 +201,9 @@ constexpr double T_REF = 1e8;           // s; the model predicts log10(t_nuc / T
 
 // ---- launchers (defined in the kernel translation units) ----
 void launch_node_T(const Dev &d, hipStream_t st);
+// Joule pre-pass: vertex temperatures per tree (scratch D, r: [ns] each), then
+// the steady profile at every interior node; j = [n_res] current densities.
+void launch_joule_T(const Dev &d, const double *j, double *D, double *r, hipStream_t st);
 void launch_edge_static(const Dev &d, hipStream_t st);
 void launch_node_V(const Dev &d, bool fp32, hipStream_t st);   // also per-tree volume
 void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, hipStream_t st);

@@ -71,6 +71,134 @@ EM_KERNEL void k_node_T(Dev d)
 }
 
 // ------------------------------------------------------------------------
+// Joule-heating thermal pre-pass (Sec. II-A, eqs. 1-4).  Along a wire segment
+// of length L the steady temperature solves k T'' + j^2 rho = k (T - T0)/G^2
+// (heat conduction, Joule source, loss through the dielectric to the local
+// ambient T0), G^2 = t_cu t_ILD k_cu / k_ILD (eq. 2).  With c = T0 + Tm,
+// Tm = j^2 rho G^2 / k_cu, and the end temperatures T1 (res_a end, x = -L/2)
+// and T2 (res_b end, x = +L/2):
+//   T(x) = c + (Tbar - c) cosh(x/G)/cosh(L/2G) + (T2 - T1)/2 sinh(x/G)/sinh(L/2G).
+// The temperature gradient entering the segment at an end is
+//   [-(T_here - c) coth(L/G) + (T_there - c) csch(L/G)] / G,
+// so heat-flux balance at a vertex without a via (no heat exchanged there
+// other than through its segments; a free wire end is adiabatic) reads
+//   T_v sum_e w_e coth_e - sum_e w_e csch_e T_u = sum_e w_e c_e tanh(L_e/2G_e),
+// w_e = (cross-section)/G_e: a diagonally dominant system on the tree's vertex
+// graph, eliminated exactly leaf to root.  Vertices with a via are held at
+// the map temperature.
+// ------------------------------------------------------------------------
+
+// map temperature at a grid node / at the midpoint of segment e
+__device__ inline double map_T_vertex(const Dev &d, int v)
+{
+    if (d.tmap) return raster_T(d, d.xy[2 * v], d.xy[2 * v + 1]);
+    if (d.node_T) return d.node_T[v];
+    return d.T_amb;
+}
+__device__ inline double map_T_mid(const Dev &d, int e)
+{
+    const int a = d.ra[e], b = d.rb[e];
+    if (d.tmap)
+        return raster_T(d, 0.5 * (d.xy[2 * a] + d.xy[2 * b]), 0.5 * (d.xy[2 * a + 1] + d.xy[2 * b + 1]));
+    if (d.node_T) return 0.5 * (d.node_T[a] + d.node_T[b]);
+    return d.T_amb;
+}
+
+struct SegHeat { double G, c, w, cth, csh, th; };   // G, c, w; coth, csch of L/G; tanh(L/2G)
+
+__device__ inline SegHeat seg_heat(const Dev &d, int e, const double *j)
+{
+    SegHeat q;
+    q.G = sqrt(d.h[e] * d.t_ild * d.k_cu / d.k_ild);
+    q.c = map_T_mid(d, e) + j[e] * j[e] * d.rho * q.G * q.G / d.k_cu;
+    q.w = d.w[e] * d.h[e] / q.G;
+    const double y = d.len[e] / q.G;
+    const double em2 = expm1(-2.0 * y);                 // e^{-2y} - 1 < 0
+    q.cth = (2.0 + em2) / -em2;                          // (1 + e^{-2y}) / (1 - e^{-2y})
+    q.csh = 2.0 * exp(-y) / -em2;                        // 2 e^{-y} / (1 - e^{-2y})
+    q.th = -expm1(-y) / (2.0 + expm1(-y));               // (1 - e^{-y}) / (1 + e^{-y})
+    return q;
+}
+
+__device__ inline bool vertex_has_via(const Dev &d, int v)
+{
+    for (int k = d.ninc_off[v]; k < d.ninc_off[v + 1]; ++k)
+        if (!d.is_wire[d.ninc_res[k]]) return true;
+    return false;
+}
+
+// One thread per tree: vertex temperatures into d.T (vertex nodes only).
+// A vertex node i other than the root reached its tree walk through segment
+// seg[i], whose N - 1 interior nodes precede it, so its neighbour vertex on
+// that segment is parent[i - N + 1].
+EM_KERNEL void k_joule_vertices(Dev d, const double *j, double *D, double *r)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= d.n_trees) return;
+    const int o0 = d.tree_off[t], o1 = d.tree_off[t + 1], N = d.N;
+    for (int i = o0; i < o1; ++i)
+        if (d.vert[i] >= 0) { D[i] = 0.0; r[i] = 0.0; }
+    for (int i = o0 + 1; i < o1; ++i) {
+        if (d.vert[i] < 0) continue;
+        const int p = d.parent[i - N + 1];
+        const SegHeat q = seg_heat(d, d.seg[i], j);
+        D[i] += q.w * q.cth; D[p] += q.w * q.cth;
+        r[i] += q.w * q.c * q.th; r[p] += q.w * q.c * q.th;
+    }
+    // leaf to root (reverse walk order: children before parents)
+    for (int i = o1 - 1; i > o0; --i) {
+        const int v = d.vert[i];
+        if (v < 0) continue;
+        const int p = d.parent[i - N + 1];
+        const SegHeat q = seg_heat(d, d.seg[i], j);
+        const double beta = q.w * q.csh;
+        if (vertex_has_via(d, v)) {
+            d.T[i] = map_T_vertex(d, v);
+            r[p] += beta * d.T[i];
+        } else {
+            r[p] += beta * r[i] / D[i];
+            D[p] -= beta * beta / D[i];
+        }
+    }
+    const int v0 = d.vert[o0];
+    d.T[o0] = vertex_has_via(d, v0) ? map_T_vertex(d, v0) : r[o0] / D[o0];
+    // root to leaves
+    for (int i = o0 + 1; i < o1; ++i) {
+        const int v = d.vert[i];
+        if (v < 0 || vertex_has_via(d, v)) continue;
+        const int p = d.parent[i - N + 1];
+        const SegHeat q = seg_heat(d, d.seg[i], j);
+        d.T[i] = (r[i] + q.w * q.csh * d.T[p]) / D[i];
+    }
+}
+
+// One thread per interior node: the segment's steady profile between its
+// end temperatures.  The interior node at walk position q (1..N-1) of a
+// segment lies q nodes after the segment's first vertex node and N - q
+// before its second.
+EM_KERNEL void k_joule_nodes(Dev d, const double *j)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.ns || d.vert[i] >= 0) return;
+    const int e = d.seg[i], N = d.N, kp = d.kpos[i];
+    const int q = d.dir[i] > 0 ? kp : N - kp;
+    const int sw = i + N - q;
+    const int su = d.parent[sw - N + 1];
+    const double T1 = d.dir[i] > 0 ? d.T[su] : d.T[sw];    // res_a end
+    const double T2 = d.dir[i] > 0 ? d.T[sw] : d.T[su];    // res_b end
+    const SegHeat h = seg_heat(d, e, j);
+    const double hl = 0.5 * d.len[e] / h.G;                // L / 2G
+    const double x = ((double)kp / N - 0.5) * d.len[e] / h.G;
+    const double ax = fabs(x);
+    // cosh(x)/cosh(hl) and sinh(x)/sinh(hl) without overflow
+    const double ed = exp(ax - hl);
+    const double ch = ed * (1.0 + exp(-2.0 * ax)) / (1.0 + exp(-2.0 * hl));
+    double sh = ed * expm1(-2.0 * ax) / expm1(-2.0 * hl);
+    if (x < 0) sh = -sh;
+    d.T[i] = h.c + (0.5 * (T1 + T2) - h.c) * ch + 0.5 * (T2 - T1) * sh;
+}
+
+// ------------------------------------------------------------------------
 // Per-edge statics for the edge (parent(i), i): diffusivity at the edge
 // midpoint temperature, kappa = D0 exp(-Ea/kT) B Omega/(kT) (eqs. 10-11),
 // conductance g0 = a kappa/dx, Robin weight a kappa/delta (eq. 20), and the
@@ -970,6 +1098,11 @@ EM_KERNEL void k_catchup_done(Dev d, int step_lim)
 void launch_node_T(const Dev &d, hipStream_t st)
 {
     k_node_T<<<nblocks(d.ns), 256, 0, st>>>(d);
+}
+void launch_joule_T(const Dev &d, const double *j, double *D, double *r, hipStream_t st)
+{
+    k_joule_vertices<<<nblocks(d.n_trees, 64), 64, 0, st>>>(d, j, D, r);
+    k_joule_nodes<<<nblocks(d.ns), 256, 0, st>>>(d, j);
 }
 void launch_edge_static(const Dev &d, hipStream_t st)
 {

@@ -70,10 +70,12 @@ class Grid:
 def default_material() -> dict:
     """Cu constants of the tiny trees workload plus the values the paper
     leaves open (heat of transport, residual stress, void-interface
-    thickness, Ta liner): SI units, activation energies in eV."""
+    thickness, Ta liner, the thermal block of the Joule pre-pass: bulk Cu and
+    SiO2 conductivities, 0.2 um dielectric): SI units, activation energies in
+    eV."""
     return dict(B=28e9, Omega=1.18e-29, Z=1.0, rho_cu=RHO_CU, Ea_eV=0.85,
                 D0=7.56e-5, sigma_crit=400e6, Q_eV=0.1, sigma_T=0.0,
-                delta=1e-9, rho_ta=2e-7, h_ta=5e-9)
+                delta=1e-9, rho_ta=2e-7, h_ta=5e-9, k_cu=400.0, k_ild=1.4, t_ild=0.2e-6)
 
 
 def default_run(**over) -> dict:
@@ -83,7 +85,7 @@ def default_run(**over) -> dict:
     horizon = 10 * 365.25 * 86400.0
     r = dict(intervals_per_seg=20, n_steps=2000, dt=horizon / 2000, ir_every=100,
              fail_frac=0.10, cg_rtol=1e-11, cg_max_iter=20000, prec=0, screen=1,
-             max_voids_per_tree=4, T_ambient=378.0)
+             max_voids_per_tree=4, T_ambient=378.0, joule=0)
     r.update(over)
     return r
 

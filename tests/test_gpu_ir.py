@@ -126,3 +126,27 @@ def test_condensed_resolve_after_state_change(em, oracle_mod):
     with pytest.raises(em.EmError):
         B.set_seg_state(0, bad, np.zeros(g.n_res, np.uint8))
     B.close()
+
+
+def test_single_pad_with_dangling_chains(em, oracle_mod):
+    # one pad feeding open-ended wires: condensation would leave the pad
+    # alone (no reduced edge), so the nodal system is solved; against the
+    # direct solve and the ladder's closed form (node k sits below the pad by
+    # R times the current still flowing past it)
+    from cases import ladder_grid
+    n, R = 40, 2.0
+    sinks = np.linspace(1e-5, 5e-5, n)
+    g = ladder_grid(n, R=R, sinks=sinks)
+    print("ir single pad ladder", flush=True)
+    B = em.Batch(g, material(), synth.default_run(prec=0, cg_rtol=1e-14, cg_max_iter=20000))
+    drop = B.ir_solve()[0]
+    u = B.voltages(0)
+    info = B.info()
+    B.close()
+    assert info["ir_sys_nodes"] == g.n_nodes
+    passing = np.cumsum(sinks[::-1])[::-1]                 # current through resistor k -> k+1
+    u_cf = g.vdd - np.concatenate([[0.0], np.cumsum(R * passing)])
+    u_o, _, _, d_o = oracle_mod.ir_solve(g, g.res_R0)
+    assert np.max(np.abs(u_o - u_cf)) <= 1e-12
+    assert np.max(np.abs(u - u_cf)) <= 1e-10 * g.vdd
+    assert abs(drop - d_o) <= 1e-9 * d_o
