@@ -20,6 +20,7 @@ against the FP64 oracle on 64 samples) and on the 32x32 mesh.
 from __future__ import annotations
 
 import argparse
+import copy
 import json
 import os
 import sys
@@ -244,8 +245,10 @@ def thermal_leg(args):
     """Equal-average thermal maps (the paper's thermal-profile observation):
     the mc_grid network under a uniform map, four hotspots over the wires of
     highest current density, the same hotspots over the wires of lowest
-    current density, and the latter 5 K hotter on average; Monte Carlo to TTF
-    for each (256 samples)."""
+    current density, the latter 5 K hotter on average, and no map at all
+    (Joule heating over the uniform ambient); each with the Joule-heating
+    pre-pass, Monte Carlo to TTF for each (256 samples; batch creation, which
+    runs the pre-pass, inside the timed region)."""
     import numpy as np
     import torch
     import paper_2604_10743_amd as P
@@ -260,24 +263,32 @@ def thermal_leg(args):
     hot = synth.hotspot_centers(g, j, 4, 150e-6, highest=True)
     cold = synth.hotspot_centers(g, j, 4, 150e-6, highest=False)
     out = {"workload": "mc_grid network, 256 samples per map, hotspots 4 x +60 K (sigma 60 um, 150 um apart), "
-                       "die-average 335 K (hotter variant 340 K)", "maps": {}}
+                       "die-average 335 K (hotter variant 340 K); Joule-heating pre-pass on every map "
+                       "(k_cu 400, k_ILD 1.4 W/(m K), t_ILD 0.2 um)", "maps": {}}
     yr = 365.25 * 86400.0
     t_all = 0.0
-    for name, h in synth.thermal_variants(g, hot, cold, 335.0, 60.0, 60e-6, hotter_K=5.0).items():
+    maps = synth.thermal_variants(g, hot, cold, 335.0, 60.0, 60e-6, hotter_K=5.0)
+    maps["joule_only"] = copy.deepcopy(maps["uniform"])
+    maps["joule_only"].tmap = None
+    for name, h in maps.items():
+        rn = dict(run, joule=1, T_ambient=335.0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        Bm = P.Batch(h, mat, run, mc)
+        Bm = P.Batch(h, mat, rn, mc)
         res = Bm.run_to_ttf()
         torch.cuda.synchronize()
         t_all += time.perf_counter() - t0
+        Tn = Bm.node_state(0)[0]
         ttf = np.array([r["ttf_s"] for r in res if r["failed"]])
-        out["maps"][name] = {"mean_T_K": float(h.tmap.mean()), "max_T_K": float(h.tmap.max()),
+        out["maps"][name] = {"map_mean_K": float(h.tmap.mean()) if h.tmap is not None else 335.0,
+                             "map_max_K": float(h.tmap.max()) if h.tmap is not None else 335.0,
+                             "wire_T_mean_K": float(Tn.mean()), "wire_T_max_K": float(Tn.max()),
                              "n_fail": int(ttf.size), "n_censored": int(len(res) - ttf.size),
                              "ttf_mean_y": float(ttf.mean() / yr) if ttf.size else None,
                              "nucleated_trees_per_sample": float(np.mean([r["n_nucleated_trees"] for r in res])),
                              "final_drop_mean": float(np.mean([r["final_drop"] for r in res]))}
         Bm.close()
-    out["samples_per_s"] = 4 * 256 / t_all
+    out["samples_per_s"] = len(maps) * 256 / t_all
     return out
 
 
