@@ -159,15 +159,24 @@ typedef struct {
                                     from the map directly. */
 } em_run_params;
 
-/* Monte Carlo (Sec. IV-F): per-segment unit-mean lognormal multipliers on
- * the diffusivity and the critical stress, coefficient of variation cov_*,
- * drawn from Philox-4x32-10 with counter (segment, sample, param, 0) and key
- * (seed low word, seed high word), param 0 = kappa, 1 = sigma_crit. */
+/* Monte Carlo (Sec. IV-F): unit-mean lognormal multipliers with coefficient
+ * of variation cov_*, drawn from Philox-4x32-10 with counter (index, sample,
+ * param, 0) and key (seed low word, seed high word):
+ *   param 0  kappa (diffusivity), per wire segment;
+ *   param 1  sigma_crit, per wire segment;
+ *   param 2  resistivity, per wire segment: the segment's resistance R0, its
+ *            electron-wind drive (eZ rho j / Omega) and the copper term of the
+ *            liner resistance change (eq. 17) scale with it; vias keep R0;
+ *   param 3  current loading, per node: the node's sink current scales with it.
+ * The paper's study perturbs kappa and sigma_crit; resistivity and loading are
+ * two of the further sampled inputs it names for the same flow.  With
+ * cov_rho = cov_load = 0 every sample starts on the nominal network. */
 typedef struct {
     uint32_t struct_size;
     int32_t n_samples;
     uint64_t seed;
     double cov_kappa, cov_scrit;
+    double cov_rho, cov_load;
 } em_mc_params;
 
 typedef struct {
@@ -310,7 +319,8 @@ em_status em_get_screen(em_batch *b, int32_t sample, uint8_t *tree_mortal, uint8
 /* Test hook: place a void at stress node `node` of `tree` in `sample` as a
  * nucleation there would (host segment and failure mode chosen the same way). */
 em_status em_inject_void(em_batch *b, int32_t sample, int32_t tree, int32_t node);
-/* Per-(sample, segment) Monte Carlo multipliers, xi [n_res]; param 0 kappa, 1 sigma_crit. */
+/* Monte Carlo multipliers of one sample: param 0 kappa, 1 sigma_crit, 2 resistivity
+ * (xi [n_res]; 1 for vias and where the CoV is 0), 3 current loading (xi [n_nodes]). */
 em_status em_get_xi(em_batch *b, int32_t sample, int32_t param, double *xi);
 /* Failed segments of one sample (dR > 0 or open; the set counted by
  * em_ttf_result.n_failed_segs), ascending: *n = their number, the first

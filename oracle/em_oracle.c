@@ -69,7 +69,16 @@ typedef struct {
     /* stress-node temperatures [ns] from the Joule-heating pre-pass (Sec. II-A,
      * oracle/thermal.py); NULL: sampled from the map as below */
     const double *T_stress;
+    /* per-segment resistivity multipliers of the sample (Sec. IV-F sampled
+     * input); NULL means 1.  They scale the electron-wind drive and the
+     * copper term of eq. 17 (the IR resistances are scaled by the caller). */
+    const double *xi_r;
 } ora_problem;
+
+static double seg_rho(const ora_problem *P, int e)
+{
+    return P->rho * (P->xi_r ? P->xi_r[e] : 1.0);
+}
 
 static int res_is_wire(const ora_problem *P, int r)
 {
@@ -391,7 +400,7 @@ void ora_set_j(ora_state *S, const double *jseg)
         int e = S->seg[i];
         double dx = P->len[e] / P->N;
         double Te = 0.5 * (S->T[i] + S->T[p]);
-        double Sd = ORA_E * P->Z * P->rho * jseg[e] / P->Omega;
+        double Sd = ORA_E * P->Z * seg_rho(P, e) * jseg[e] / P->Omega;
         double Md = S->dir[i] * (P->Q_eV * ORA_E / (P->Omega * Te)) * (S->T[i] - S->T[p]) / dx;
         double phi = S->dir[i] * S->g[i] * dx * (Sd + Md);
         S->phi[i] = phi;
@@ -417,7 +426,7 @@ void ora_screen(ora_state *S, unsigned char *tree_mortal, unsigned char *seg_mor
             int p = S->parent[i], e = S->seg[i];
             double dx = P->len[e] / P->N;
             double Te = 0.5 * (S->T[i] + S->T[p]);
-            double Sd = ORA_E * P->Z * P->rho * S->jseg[e] / P->Omega;
+            double Sd = ORA_E * P->Z * seg_rho(P, e) * S->jseg[e] / P->Omega;
             double Md = S->dir[i] * (P->Q_eV * ORA_E / (P->Omega * Te)) * (S->T[i] - S->T[p]) / dx;
             psi[i] = psi[p] + S->dir[i] * dx * (Sd + Md);
         }
@@ -466,9 +475,9 @@ double ora_late_dR(double l, double W, double H, double h_ta, double rho_ta, dou
     return ex * (rho_ta / (h_ta * (2 * H + W)) - rho_cu / (W * H));
 }
 
-static double late_dR(const ora_problem *P, double l, double W, double H)
+static double late_dR(const ora_problem *P, int e, double l, double W, double H)
 {
-    return ora_late_dR(l, W, H, P->h_ta, P->rho_ta, P->rho);
+    return ora_late_dR(l, W, H, P->h_ta, P->rho_ta, seg_rho(P, e));
 }
 
 /* Host segment of a new void: the node's own segment for an interior node;
@@ -498,7 +507,7 @@ static void refresh_dR(ora_state *S)
     for (int t = 0; t < S->n_trees; ++t)
         for (int k = 0; k < S->nv[t]; ++k) {
             int q = t * mv + k, e = S->vseg[q];
-            if (!S->vearly[q]) S->dR[e] += late_dR(P, S->vlen[q], P->w[e], P->h[e]);
+            if (!S->vearly[q]) S->dR[e] += late_dR(P, e, S->vlen[q], P->w[e], P->h[e]);
         }
 }
 

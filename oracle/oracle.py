@@ -23,6 +23,7 @@ Parity unpinned: nothing here reproduces a number of the paper's own designs
 from __future__ import annotations
 
 import ctypes as C
+import dataclasses
 import os
 import subprocess
 
@@ -82,7 +83,7 @@ class _Problem(C.Structure):
         ("Ea_eV", C.c_double), ("D0", C.c_double), ("scrit", C.c_double), ("Q_eV", C.c_double),
         ("sigT", C.c_double), ("delta", C.c_double), ("rho_ta", C.c_double), ("h_ta", C.c_double),
         ("N", C.c_int), ("dt", C.c_double), ("max_voids", C.c_int),
-        ("xi_k", C.c_void_p), ("xi_s", C.c_void_p), ("T_stress", C.c_void_p),
+        ("xi_k", C.c_void_p), ("xi_s", C.c_void_p), ("T_stress", C.c_void_p), ("xi_r", C.c_void_p),
     ]
 
 
@@ -110,7 +111,7 @@ class _Keep:
         return a
 
 
-def make_problem(grid, mat, run, xi_k=None, xi_s=None, T_stress=None):
+def make_problem(grid, mat, run, xi_k=None, xi_s=None, T_stress=None, xi_r=None):
     keep = _Keep()
     P = _Problem()
     P.n_nodes = grid.n_nodes
@@ -133,6 +134,7 @@ def make_problem(grid, mat, run, xi_k=None, xi_s=None, T_stress=None):
     P.max_voids = int(run["max_voids_per_tree"])
     P.xi_k = _pi(keep(xi_k, np.float64)); P.xi_s = _pi(keep(xi_s, np.float64))
     P.T_stress = _pi(keep(T_stress, np.float64))
+    P.xi_r = _pi(keep(xi_r, np.float64))
     return P, keep
 
 
@@ -186,10 +188,10 @@ class SampleSim:
     """One sample's stress/void state (wraps the C oracle)."""
 
     def __init__(self, grid, mat, run, topo: Topology, xi_k=None, xi_s=None, cap_events=1 << 16,
-                 T_stress=None):
+                 T_stress=None, xi_r=None):
         L = lib()
         self.grid, self.mat, self.run, self.topo = grid, mat, run, topo
-        self.P, self.keep = make_problem(grid, mat, run, xi_k, xi_s, T_stress)
+        self.P, self.keep = make_problem(grid, mat, run, xi_k, xi_s, T_stress, xi_r)
         t = topo
         self._t = [np.ascontiguousarray(a, np.int32) for a in
                    (t.tree_off, t.parent, t.seg, t.dir, t.vert, t.kpos, t.seg_tree)]
@@ -320,10 +322,28 @@ def ir_solve(grid, R, open_mask=None):
 # Full pipeline for one sample
 # ----------------------------------------------------------------------------
 def sample_xi(grid, mc, sample):
+    """Diffusivity and critical-stress multipliers of one sample, per segment."""
     if mc is None:
         return None, None
     return (lognormal_xi(mc["seed"], sample, grid.n_res, 0, mc["cov_kappa"]),
             lognormal_xi(mc["seed"], sample, grid.n_res, 1, mc["cov_scrit"]))
+
+
+def sample_inputs(grid, mc, sample):
+    """The sampled network of one sample (Sec. IV-F: any input stamped into
+    the per-sample netlist): resistivity multipliers per wire segment (param
+    2; vias keep their resistance) and sink currents scaled per node by the
+    loading multipliers (param 3).  Returns (xi_r or None, R0, sinks)."""
+    R0 = grid.res_R0.astype(np.float64)
+    sinks = None if grid.sink_I is None else np.asarray(grid.sink_I, np.float64)
+    xi_r = None
+    if mc is not None and mc.get("cov_rho", 0.0) > 0:
+        wire = (grid.res_is_via == 0) & (grid.layer[grid.res_a] == grid.layer[grid.res_b])
+        xi_r = np.where(wire, lognormal_xi(mc["seed"], sample, grid.n_res, 2, mc["cov_rho"]), 1.0)
+        R0 = R0 * xi_r
+    if mc is not None and mc.get("cov_load", 0.0) > 0 and grid.seg_j is None:
+        sinks = sinks * lognormal_xi(mc["seed"], sample, grid.n_nodes, 3, mc["cov_load"])
+    return xi_r, R0, sinks
 
 
 def run_sample(grid, mat, run, mc=None, sample=0, topo=None, keep_sim=False, max_outer=None):
@@ -334,16 +354,23 @@ def run_sample(grid, mat, run, mc=None, sample=0, topo=None, keep_sim=False, max
     N = int(run["intervals_per_seg"])
     topo = topo or topology(grid, N)
     xi_k, xi_s = sample_xi(grid, mc, sample)
+    xi_r, R0, sinks = sample_inputs(grid, mc, sample)
     trees_only = grid.seg_j is not None
+    gs = grid
     if not trees_only:
-        R0 = grid.res_R0.astype(np.float64)
-        u, I, j, d0 = ir_solve(grid, R0)
+        gs = dataclasses.replace(grid, sink_I=sinks)        # this sample's loading
+        u, I, j, d0 = ir_solve(gs, R0)
     T_stress = None
     if run.get("joule", 0):
         # one-time thermal pre-pass with the currents of the nominal network
-        T_stress = thermal.node_temperatures(grid, mat, float(run.get("T_ambient", 300.0)), topo,
-                                             grid.seg_j if trees_only else j)
-    sim = SampleSim(grid, mat, run, topo, xi_k, xi_s, T_stress=T_stress)
+        if trees_only:
+            j_nom = grid.seg_j
+        elif not (mc is not None and (mc.get("cov_rho", 0.0) > 0 or mc.get("cov_load", 0.0) > 0)):
+            j_nom = j
+        else:
+            j_nom = ir_solve(grid, grid.res_R0.astype(np.float64))[2]
+        T_stress = thermal.node_temperatures(grid, mat, float(run.get("T_ambient", 300.0)), topo, j_nom)
+    sim = SampleSim(grid, mat, run, topo, xi_k, xi_s, T_stress=T_stress, xi_r=xi_r)
     n_steps, K = int(run["n_steps"]), int(run["ir_every"])
     res = dict(sample=sample)
     if trees_only:
@@ -380,7 +407,7 @@ def run_sample(grid, mat, run, mc=None, sample=0, topo=None, keep_sim=False, max
                 sim.steps(nst, done)
                 done += nst
                 dR, op = sim.seg_state()
-                u, I, j, dk = ir_solve(grid, R0 + dR, op)
+                u, I, j, dk = ir_solve(gs, R0 + dR, op)
                 drops.append(dk)
                 t = done * float(run["dt"])
                 res["final_drop"] = dk

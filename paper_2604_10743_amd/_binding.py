@@ -72,7 +72,8 @@ class RunParams(C.Structure):
 
 class MCParams(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("n_samples", C.c_int32), ("seed", C.c_uint64),
-                ("cov_kappa", C.c_double), ("cov_scrit", C.c_double)]
+                ("cov_kappa", C.c_double), ("cov_scrit", C.c_double), ("cov_rho", C.c_double),
+                ("cov_load", C.c_double)]
 
 
 class TTFResult(C.Structure):
@@ -209,7 +210,8 @@ class Batch:
         if mc is not None:
             mcp = MCParams(struct_size=C.sizeof(MCParams), n_samples=int(mc["n_samples"]),
                            seed=int(mc["seed"]), cov_kappa=float(mc["cov_kappa"]),
-                           cov_scrit=float(mc["cov_scrit"]))
+                           cov_scrit=float(mc["cov_scrit"]), cov_rho=float(mc.get("cov_rho", 0.0)),
+                           cov_load=float(mc.get("cov_load", 0.0)))
         self._alloc = None
         if torch_alloc:
             dev = torch.cuda.current_device()
@@ -370,7 +372,7 @@ class Batch:
         self._chk(lib().em_inject_void(self._h, C.c_int32(sample), C.c_int32(tree), C.c_int32(node)))
 
     def xi(self, sample: int = 0, param: int = 0) -> np.ndarray:
-        x = np.zeros(self.n_res)
+        x = np.zeros(self.info()["n_nodes"] if param == 3 else self.n_res)
         self._chk(lib().em_get_xi(self._h, C.c_int32(sample), C.c_int32(param), _ptr(x)))
         return x
 

@@ -22,7 +22,7 @@ struct em_batch {
     em_run_params run;
     int S = 1;
     uint64_t seed = 0;
-    double cov_k = 0, cov_s = 0;
+    double cov_k = 0, cov_s = 0, cov_r = 0, cov_l = 0;
     bool trees_only = false;
     bool fp32 = false;
     hipStream_t stream = nullptr;
@@ -309,7 +309,8 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
             return fail(b, EM_ERR_ARG, "Joule pre-pass needs positive finite k_cu, k_ild and t_ild");
     }
     if (mc && (mc->n_samples < 1 || mc->n_samples > 65535 || mc->cov_kappa < 0 || mc->cov_scrit < 0 || !std::isfinite(mc->cov_kappa) ||
-               !std::isfinite(mc->cov_scrit)))
+               !std::isfinite(mc->cov_scrit) || !(mc->cov_rho >= 0) || !(mc->cov_load >= 0) ||
+               !std::isfinite(mc->cov_rho) || !std::isfinite(mc->cov_load)))
         return fail(b, EM_ERR_ARG, "bad Monte Carlo parameters");
     return EM_OK;
 }
@@ -534,11 +535,12 @@ void fold_timers(em_batch *b)
 }
 
 // The steady-state screen; with the nominal resistances every sample has
-// the same current densities and the steady stress is computed once per tree.
+// the same current densities and the steady stress is computed once per tree
+// (not under resistivity variation: the electron-wind drive differs per sample).
 em_status run_screen(em_batch *b, bool apply)
 {
     Dev &d = b->d;
-    if (b->nominal || b->trees_only) {
+    if ((b->nominal || b->trees_only) && !d.xi_r) {
         HIPCHK(b, hipMemsetAsync(d.tree_mortal, 0, (size_t)d.n_trees * d.S, b->stream));
         HIPCHK(b, hipMemsetAsync(d.seg_mortal, 0, (size_t)d.n_res * d.S, b->stream));
         launch_screen_shared(d, apply, b->stream);
@@ -829,7 +831,12 @@ static em_status joule_prepass(em_batch *b)
     Dev &d = b->d;
     hipStream_t st = b->stream;
     if (!b->trees_only) {
+        // the nominal network: sampled resistivity and loading left out
+        double *xr = d.xi_r, *ss = d.sink_s;
+        d.xi_r = nullptr; d.sink_s = nullptr;
+        b->nominal = true;
         em_status s = em_ir_solve(b, nullptr);
+        d.xi_r = xr; d.sink_s = ss;
         if (s != EM_OK) return s;
     }
     double *scr = (double *)dalloc(b, 16 * (size_t)d.ns);
@@ -863,6 +870,8 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     b->cov_k = mc ? mc->cov_kappa : 0.0;
     b->cov_s = mc ? mc->cov_scrit : 0.0;
     b->trees_only = g->seg_j != nullptr;
+    b->cov_r = mc ? mc->cov_rho : 0.0;
+    b->cov_l = (mc && !b->trees_only) ? mc->cov_load : 0.0;     // no sinks in trees-only mode
     b->fp32 = r->prec == EM_FP32;
     b->stream = (hipStream_t)hip_stream;
     if (alloc && alloc->alloc && alloc->free) { b->alloc = *alloc; b->has_alloc = true; }
@@ -1074,6 +1083,10 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     AL(d.psi, double, NS);
     if (b->n_generic_trees > 0) { AL(d.wsp, double, NS); } else { d.wsp = nullptr; }
     AL(d.xi_k, double, RS); AL(d.xi_s, double, RS);
+    d.xi_r = nullptr;
+    if (b->cov_r > 0) AL(d.xi_r, double, RS);
+    d.sink_s = nullptr;
+    if (b->cov_l > 0) AL(d.sink_s, double, (size_t)S * nn);
     AL(d.jseg, double, RS);
     if (S > 1) AL(d.jT, double, RS);
     AL(d.dR, double, RS); AL(d.open, uint8_t, RS); AL(d.seg_mortal, uint8_t, RS);
@@ -1212,7 +1225,8 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     launch_node_T(d, stq);
     launch_edge_static(d, stq);
     launch_node_V(d, b->fp32, stq);
-    launch_draws(d, b->seed, b->cov_k, b->cov_s, stq);
+    launch_draws(d, b->seed, b->cov_k, b->cov_s, b->cov_r, b->cov_l, stq);
+    b->nominal = !d.xi_r && !d.sink_s;
     launch_node_sc(d, b->fp32, stq);
     launch_set_sigma_T(d, b->fp32, stq);
     LAUNCHCHK(b);
@@ -1461,7 +1475,7 @@ em_status em_reset(em_batch *b)
     HIPCHK(b, hipMemsetAsync(d.inst_active, 1, IS, st));
     HIPCHK(b, hipMemsetAsync(d.sample_active, 1, d.S, st));
     b->act_dirty = true;
-    b->nominal = true;
+    b->nominal = !d.xi_r && !d.sink_s;     // samples differ from t = 0 under R / load variation
     HIPCHK(b, hipMemsetAsync(d.dR, 0, 8 * RS, st));
     HIPCHK(b, hipMemsetAsync(d.open, 0, RS, st));
     HIPCHK(b, hipMemsetAsync(d.ev_count, 0, 4, st));
@@ -1901,12 +1915,24 @@ em_status em_restore(em_batch *b, const void *host_buf, size_t n)
 
 em_status em_get_xi(em_batch *b, int32_t sample, int32_t param, double *xi)
 {
-    if (!b || !xi || sample < 0 || sample >= b->S || (param != 0 && param != 1))
+    if (!b || !xi || sample < 0 || sample >= b->S || param < 0 || param > 3)
         return fail(b, EM_ERR_ARG, "bad arguments");
     const int S = b->S;
+    const Dev &d = b->d;
+    if (param == 3) {               // loading: per node, the sampled sink over the nominal one
+        std::vector<double> snk(b->n_nodes), ss(b->n_nodes);
+        if (!d.sink_s) { for (int v = 0; v < b->n_nodes; ++v) xi[v] = 1.0; return EM_OK; }
+        HIPCHK(b, hipMemcpyAsync(snk.data(), d.sink, 8 * snk.size(), hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(b, hipMemcpyAsync(ss.data(), d.sink_s + (size_t)sample * b->n_nodes, 8 * ss.size(),
+                                 hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(b, hipStreamSynchronize(b->stream));
+        for (int v = 0; v < b->n_nodes; ++v) xi[v] = snk[v] != 0.0 ? ss[v] / snk[v] : 1.0;
+        return EM_OK;
+    }
+    const double *src = param == 0 ? d.xi_k : param == 1 ? d.xi_s : d.xi_r;
+    if (!src) { for (int e = 0; e < b->n_res; ++e) xi[e] = 1.0; return EM_OK; }
     std::vector<double> tmp((size_t)b->n_res * S);
-    HIPCHK(b, hipMemcpyAsync(tmp.data(), param == 0 ? b->d.xi_k : b->d.xi_s, 8 * tmp.size(),
-                             hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipMemcpyAsync(tmp.data(), src, 8 * tmp.size(), hipMemcpyDeviceToHost, b->stream));
     HIPCHK(b, hipStreamSynchronize(b->stream));
     for (int e = 0; e < b->n_res; ++e) xi[e] = tmp[(size_t)e * S + sample];
     return EM_OK;

@@ -40,7 +40,8 @@ struct Dev {
     const double *len, *w, *h, *R0;
     const uint8_t *is_wire;             // 1 for a wire segment
     const double *sink;
-    double *sink_s;                     // [S][n_nodes] per-sample sinks (condensed system), or null
+    double *sink_s;                     // [S][n_nodes] per-sample sinks (condensed system; nodal
+                                        // network under loading variation), or null
     const uint8_t *is_pad;              // [n_nodes]
     const int *ninc_off, *ninc_res, *ninc_nbr;   // node incidence (all resistors)
     // temperature inputs
@@ -71,6 +72,7 @@ struct Dev {
     double *wsp;                        // stepping workspace [node][S] (generic tree kernel)
     // ---- Monte Carlo draws [res][S] ----
     double *xi_k, *xi_s;
+    double *xi_r;                       // resistivity multipliers (1 for vias), or null
     // ---- per (sample, segment) ----
     double *jseg;                       // [S][res]
     double *jT;                         // [res][S] transposed copy of jseg for the forcing update (S > 1)
@@ -206,7 +208,8 @@ void launch_node_T(const Dev &d, hipStream_t st);
 void launch_joule_T(const Dev &d, const double *j, double *D, double *r, hipStream_t st);
 void launch_edge_static(const Dev &d, hipStream_t st);
 void launch_node_V(const Dev &d, bool fp32, hipStream_t st);   // also per-tree volume
-void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, hipStream_t st);
+void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, double cov_r, double cov_l,
+                  hipStream_t st);
 void launch_node_sc(const Dev &d, bool fp32, hipStream_t st);
 void launch_update_f(const Dev &d, bool fp32, hipStream_t st);
 void launch_factor(const Dev &d, bool fp32, hipStream_t st);

@@ -141,6 +141,12 @@ __device__ inline void chain_scan(const Cond &c, const double *G, int ch, int &k
     }
 }
 
+// Sink current of node x in sample s (per-sample under loading variation).
+__device__ inline double sink_at(const Dev &d, int s, int x)
+{
+    return d.sink_s ? d.sink_s[(size_t)s * d.n_nodes + x] : d.sink[x];
+}
+
 // Per (chain, sample): reduced-edge conductance and the currents the chain
 // draws from its two terminals.
 __global__ __launch_bounds__(CH_BS) void k_chain_reduce(Dev d, Dev r, Cond c)
@@ -160,7 +166,7 @@ __global__ __launch_bounds__(CH_BS) void k_chain_reduce(Dev d, Dev r, Cond c)
         double P = 0.0;
         for (int j = 1; j <= m; ++j) {
             P += 1.0 / G[c.e[e0 + j - 1]];
-            const double I = d.sink[c.v[v0 + j - 1]];
+            const double I = sink_at(d, s, c.v[v0 + j - 1]);
             IA += I * (Rt - P);
             IB += I * P;
         }
@@ -169,9 +175,9 @@ __global__ __launch_bounds__(CH_BS) void k_chain_reduce(Dev d, Dev r, Cond c)
         geq = 1.0 / Rt;
     } else {
         const int a_end = (!two && k1 < 0) ? m : k1;      // nodes 1..a_end hang from A
-        for (int j = 1; j <= a_end; ++j) IA += d.sink[c.v[v0 + j - 1]];
+        for (int j = 1; j <= a_end; ++j) IA += sink_at(d, s, c.v[v0 + j - 1]);
         if (two)
-            for (int j = k2 + 1; j <= m; ++j) IB += d.sink[c.v[v0 + j - 1]];
+            for (int j = k2 + 1; j <= m; ++j) IB += sink_at(d, s, c.v[v0 + j - 1]);
     }
     if (c.cred[ch] >= 0) r.G[(size_t)s * r.n_res + c.cred[ch]] = geq;
     c.cinj[((size_t)s * c.n_chain + ch) * 2 + 0] = IA;
@@ -187,7 +193,7 @@ __global__ __launch_bounds__(CH_BS) void k_red_assemble(Dev d, Dev r, Cond c)
     const int s = (int)(g / c.n_term), t = (int)(g % c.n_term);
     if (!d.g_chg_s[s]) return;
     const int node = c.term_node[t];
-    double acc = d.sink[node];
+    double acc = sink_at(d, s, node);
     const double *ci = c.cinj + (size_t)s * c.n_chain * 2;
     for (int k = c.tce_off[t]; k < c.tce_off[t + 1]; ++k) acc += ci[c.tce[k]];
     r.sink_s[g] = acc;
@@ -239,7 +245,7 @@ __global__ __launch_bounds__(CH_BS) void k_chain_backsub(Dev d, Cond c)
             const int x = c.v[v0 + j - 1];
             u[x] = lv ? uA + (uB - uA) * (P / Rt) + vj : 0.0;
             live[x] = lv ? 1 : 0;
-            i -= d.sink[x];
+            i -= sink_at(d, s, x);
         }
         return;
     }
@@ -251,7 +257,7 @@ __global__ __launch_bounds__(CH_BS) void k_chain_backsub(Dev d, Cond c)
             const int x = c.v[v0 + j - 1];
             u[x] = lA ? uj : 0.0;
             live[x] = lA ? 1 : 0;
-            i -= d.sink[x];
+            i -= sink_at(d, s, x);
         }
     }
     const int b_start = two ? k2 + 1 : m + 1;             // nodes b_start..m hang from B
@@ -267,7 +273,7 @@ __global__ __launch_bounds__(CH_BS) void k_chain_backsub(Dev d, Cond c)
             const int x = c.v[v0 + j - 1];
             u[x] = lB ? uj : 0.0;
             live[x] = lB ? 1 : 0;
-            i -= d.sink[x];
+            i -= sink_at(d, s, x);
         }
     }
 }

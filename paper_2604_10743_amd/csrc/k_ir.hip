@@ -86,7 +86,8 @@ EM_KERNEL void k_ir_conductance(Dev d)
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long long)d.S * d.n_res) return;
     int r = (int)(g % d.n_res);
-    const double Gn = d.open[g] ? 0.0 : 1.0 / (d.R0[r] + d.dR[g]);
+    const double R0 = d.xi_r ? d.R0[r] * d.xi_r[(size_t)r * d.S + g / d.n_res] : d.R0[r];
+    const double Gn = d.open[g] ? 0.0 : 1.0 / (R0 + d.dR[g]);
     if (Gn != d.G[g]) {
         d.G[g] = Gn;
         *d.g_changed = 1u;

@@ -281,13 +281,29 @@ __device__ inline double lognormal_xi(uint64_t seed, int sample, int segment, in
     return exp(-0.5 * s2 + sqrt(s2) * z);
 }
 
-EM_KERNEL void k_draws(Dev d, uint64_t seed, double cov_k, double cov_s, int use_mc)
+EM_KERNEL void k_draws(Dev d, uint64_t seed, double cov_k, double cov_s, double cov_r, int use_mc)
 {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long long)d.n_res * d.S) return;
     int s = (int)(g % d.S), e = (int)(g / d.S);
     d.xi_k[g] = use_mc ? lognormal_xi(seed, s, e, 0, cov_k) : 1.0;
     d.xi_s[g] = use_mc ? lognormal_xi(seed, s, e, 1, cov_s) : 1.0;
+    if (d.xi_r) d.xi_r[g] = d.is_wire[e] ? lognormal_xi(seed, s, e, 2, cov_r) : 1.0;
+}
+
+// Per-sample sinks under current-loading variation: [S][n_nodes].
+EM_KERNEL void k_draws_load(Dev d, uint64_t seed, double cov_l)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)d.n_nodes * d.S) return;
+    int s = (int)(g / d.n_nodes), v = (int)(g % d.n_nodes);
+    d.sink_s[g] = d.sink[v] * lognormal_xi(seed, s, v, 3, cov_l);
+}
+
+// Resistivity multiplier of wire segment e in sample s (1 without that variation).
+__device__ inline double xi_rho(const Dev &d, int e, int s)
+{
+    return d.xi_r ? d.xi_r[(size_t)e * d.S + s] : 1.0;
 }
 
 // Critical stress of a node: sigma_crit x the smallest multiplier over the
@@ -319,7 +335,7 @@ __device__ inline double edge_phi(const Dev &d, int i, int s)
 {
     int e = d.seg[i];
     double j = d.S == 1 ? d.jseg[e] : d.jT[(size_t)e * d.S + s];
-    double Sd = E_CHG * d.Z * d.rho * j / d.Omega;
+    double Sd = E_CHG * d.Z * d.rho * xi_rho(d, e, s) * j / d.Omega;
     return d.dir[i] * d.xi_k[(size_t)e * d.S + s] * d.gdx0[i] * (Sd + d.mdrv[i]);
 }
 
@@ -511,7 +527,7 @@ __device__ void steady_stress_wave(const Dev &d, int t, int s, int lane)
         if (ok && i > i0) {
             const int e = d.seg[i];
             const double dx = d.len[e] / d.N;
-            const double Sd = E_CHG * d.Z * d.rho * d.jseg[(size_t)s * d.n_res + e] / d.Omega;
+            const double Sd = E_CHG * d.Z * d.rho * xi_rho(d, e, s) * d.jseg[(size_t)s * d.n_res + e] / d.Omega;
             v = d.dir[i] * dx * (Sd + d.mdrv[i]);
             a = d.parent[i];
         }
@@ -603,11 +619,11 @@ EM_KERNEL void k_screen_activate(Dev d)
 // ------------------------------------------------------------------------
 // Late-failure resistance (eq. 17) with V_v - V_crit = (l - W) W H.
 // ------------------------------------------------------------------------
-__device__ inline double late_dR(const Dev &d, double l, double W, double H)
+__device__ inline double late_dR(const Dev &d, double l, double W, double H, double rho_cu)
 {
     double ex = l - W;
     if (ex <= 0) return 0.0;
-    return ex * (d.rho_ta / (d.h_ta * (2 * H + W)) - d.rho / (W * H));
+    return ex * (d.rho_ta / (d.h_ta * (2 * H + W)) - rho_cu / (W * H));
 }
 
 // Host segment of a void at node v: its own segment for an interior node; at
@@ -827,7 +843,7 @@ EM_KERNEL void k_void_dR(Dev d)
         int q = inst * MAXV + k;
         if (d.vearly[q]) continue;
         int e = d.vseg[q];
-        dR[e] += late_dR(d, d.vlen[q], d.w[e], d.h[e]);
+        dR[e] += late_dR(d, d.vlen[q], d.w[e], d.h[e], d.rho * xi_rho(d, e, s));
     }
 }
 
@@ -1113,10 +1129,12 @@ void launch_node_V(const Dev &d, bool fp32, hipStream_t st)
     k_node_V<<<nblocks(d.ns), 256, 0, st>>>(d, fp32 ? 1 : 0);
     k_tree_V<<<nblocks(d.n_trees), 256, 0, st>>>(d);
 }
-void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, hipStream_t st)
+void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, double cov_r, double cov_l,
+                  hipStream_t st)
 {
     int use = (cov_k != 0.0 || cov_s != 0.0) ? 1 : 0;
-    k_draws<<<nblocks((long long)d.n_res * d.S), 256, 0, st>>>(d, seed, cov_k, cov_s, use);
+    k_draws<<<nblocks((long long)d.n_res * d.S), 256, 0, st>>>(d, seed, cov_k, cov_s, cov_r, use);
+    if (d.sink_s) k_draws_load<<<nblocks((long long)d.n_nodes * d.S), 256, 0, st>>>(d, seed, cov_l);
 }
 void launch_node_sc(const Dev &d, bool fp32, hipStream_t st)
 {

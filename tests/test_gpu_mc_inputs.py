@@ -1,0 +1,94 @@
+"""Monte Carlo over resistivity and current loading (Sec. IV-F sampled inputs)
+on the GPU against the FP64 oracle: the draws, the per-sample initial IR
+solve, full runs to time-to-failure (FP64 and FP32), and the Joule pre-pass
+still taking the nominal network's currents."""
+import numpy as np
+import pytest
+
+from paper_2604_10743_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+VAR = dict(cov_rho=0.1, cov_load=0.15)
+
+
+@pytest.fixture(scope="module")
+def em():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2604_10743_amd as P
+    return P
+
+
+def test_draws_and_initial_drops(em, oracle_mod):
+    g, mat, rn, mc = synth.workload("mc_grid")
+    mc = dict(mc, n_samples=70, **VAR)
+    rn = dict(rn, prec=0, cg_rtol=1e-13)
+    print("mc inputs: draws and t=0 drops", flush=True)
+    B = em.Batch(g, mat, rn, mc)
+    drops = B.ir_solve()
+    for s in (0, 1, 63, 69):
+        xi_r, R0, sinks = oracle_mod.sample_inputs(g, mc, s)
+        assert np.allclose(B.xi(s, 2), xi_r, rtol=1e-14, atol=0)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            ld = np.where(g.sink_I != 0, sinks / g.sink_I, 1.0)
+        assert np.allclose(B.xi(s, 3), ld, rtol=1e-14, atol=0)
+        gs = synth.Grid(**{**g.__dict__, "sink_I": sinks})
+        u_o, _, j_o, d_o = oracle_mod.ir_solve(gs, R0)
+        assert abs(drops[s] - d_o) <= 1e-9 * d_o, s
+        assert np.max(np.abs(B.voltages(s) - u_o)) <= 1e-9 * g.vdd, s
+        assert np.max(np.abs(B.seg_j(s) - j_o)) <= 1e-7 * np.max(np.abs(j_o)), s
+    assert np.std(drops) > 1e-3 * np.mean(drops)             # samples differ from t = 0
+    B.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_run_to_ttf_matches_oracle(em, oracle_mod, prec):
+    g, mat, rn, mc = synth.workload("mc_grid")
+    S = 32
+    mc = dict(mc, n_samples=S, **VAR)
+    rn = dict(rn, prec=prec)
+    print(f"mc inputs: run prec {prec}", flush=True)
+    B = em.Batch(g, mat, rn, mc)
+    res = B.run_to_ttf()
+    segs = {s: B.failed_segments(s) for s in range(0, S, 4)}
+    B.close()
+    topo = oracle_mod.topology(g, rn["intervals_per_seg"])
+    tol = 1e-6 if prec == 0 else 1e-3
+    n_cmp = n_fail = 0
+    for s in range(0, S, 4):
+        ref = oracle_mod.run_sample(g, mat, rn, mc, s, topo=topo)
+        r = res[s]
+        if prec == 1 and np.min(np.abs(np.asarray(ref["drops"]) - rn["fail_frac"])) < 2e-3 * rn["fail_frac"]:
+            continue
+        n_cmp += 1
+        n_fail += ref["failed"]
+        assert abs(r["init_drop"] - ref["init_drop"]) <= 1e-9 * ref["init_drop"], s
+        assert r["failed"] == ref["failed"], s
+        assert abs(r["final_drop"] - ref["final_drop"]) <= tol * ref["final_drop"], s
+        if ref["failed"]:
+            assert abs(r["ttf_s"] - ref["ttf"]) <= tol * ref["ttf"], s
+            assert r["outer_idx"] == ref["outer_idx"], s
+        assert np.array_equal(segs[s], ref["failed_segs"]), s
+    assert n_cmp >= 6 and n_fail >= 1
+
+
+def test_prepass_uses_nominal_currents(em):
+    g, mat, rn, mc = synth.workload("mc_grid")
+    mat = dict(mat, k_ild=0.1)
+    rn = dict(rn, joule=1, prec=0)
+    print("mc inputs: pre-pass field", flush=True)
+    A = em.Batch(g, mat, rn, dict(mc, n_samples=3))
+    B = em.Batch(g, mat, rn, dict(mc, n_samples=3, **VAR))
+    assert np.array_equal(A.node_state(0)[0], B.node_state(2)[0])
+    d_a, d_b = A.ir_solve(), B.ir_solve()
+    assert np.all(d_a == d_a[0]) and np.std(d_b) > 0      # the varied batch still varies
+    A.close()
+    B.close()
+
+
+def test_bad_variation_is_rejected(em):
+    g, mat, rn, mc = synth.workload("mc_grid")
+    for bad in (dict(cov_rho=-0.1), dict(cov_load=float("nan"))):
+        with pytest.raises(em.EmError):
+            em.Batch(g, mat, rn, dict(mc, n_samples=2, **bad))

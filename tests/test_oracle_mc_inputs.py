@@ -1,0 +1,83 @@
+"""Pins of the oracle's further Monte Carlo inputs (Sec. IV-F: resistivity
+and current loading stamped into each sample's network): the draws' unit
+mean and CoV, vias keep their resistance, the electron-wind drive and hence
+the steady stress scale exactly with a segment's resistivity, the liner
+formula's copper term takes the sampled resistivity, and a sample's pads
+deliver exactly its own (scaled) sink currents."""
+import math
+
+import numpy as np
+
+from cases import material, run, tree_from_edges
+from paper_2604_10743_amd import synth
+
+UM = 1e-6
+
+
+def test_param2_and_param3_draw_statistics(oracle_mod):
+    for param in (2, 3):
+        xi = oracle_mod.lognormal_xi(777, 5, 200000, param, 0.1)
+        assert abs(xi.mean() - 1.0) < 4 * 0.1 / math.sqrt(xi.size)
+        assert abs(xi.std() / xi.mean() - 0.1) < 0.002
+        assert not np.allclose(xi[:100], oracle_mod.lognormal_xi(777, 5, 100, 0, 0.1))
+
+
+def test_sampled_network_keeps_vias_and_scales_wires(oracle_mod):
+    g = synth.pg_grid(11, n=24, via_every=8, pad_lattice=2, sink_scale=1.0, seg_range=(10, 23))
+    mc = dict(seed=3, cov_kappa=0.2, cov_scrit=0.2, cov_rho=0.15, cov_load=0.1)
+    xi_r, R0, sinks = oracle_mod.sample_inputs(g, mc, 4)
+    wire = (g.res_is_via == 0) & (g.layer[g.res_a] == g.layer[g.res_b])
+    assert np.all(xi_r[~wire] == 1.0) and np.all(R0[~wire] == g.res_R0[~wire])
+    assert np.allclose(R0[wire] / g.res_R0[wire], xi_r[wire], rtol=1e-15)
+    assert np.std(xi_r[wire]) > 0.05
+    load = sinks[g.sink_I > 0] / g.sink_I[g.sink_I > 0]
+    assert abs(np.std(load) / np.mean(load) - 0.1) < 0.03
+    # the sample's pads deliver its own sink total (KCL on the sampled network)
+    gs = synth.Grid(**{**g.__dict__, "sink_I": sinks})
+    u, I, j, drop = oracle_mod.ir_solve(gs, R0)
+    pads = set(int(p) for p in g.pad_node)
+    pad_current = sum(I[r] * ((g.res_a[r] in pads) - (g.res_b[r] in pads)) for r in range(g.n_res))
+    assert abs(pad_current - sinks.sum()) < 1e-10 * sinks.sum()
+    # without the CoVs the sampled network is the nominal one
+    xi0, R00, s00 = oracle_mod.sample_inputs(g, dict(mc, cov_rho=0.0, cov_load=0.0), 4)
+    assert xi0 is None and np.array_equal(R00, g.res_R0) and np.array_equal(s00, g.sink_I)
+
+
+def test_steady_stress_scales_with_segment_resistivity(oracle_mod):
+    # uniform temperature (no thermomigration): sigma_ss - sigma_T is a sum
+    # of dx * eZ rho xi_e j_e / Omega along the tree, so per-segment
+    # multipliers act segment by segment; all equal to c scale it by c
+    edges = [(0, 1), (1, 2), (1, 3), (3, 4)]
+    g = tree_from_edges(5, edges, L=[10 * UM, 20 * UM, 15 * UM, 5 * UM], w=0.4 * UM, h=0.2 * UM,
+                        j=[2e10, -1e10, 3e10, 1e10], T=378.0)
+    N = 10
+    topo = oracle_mod.topology(g, N)
+    rn = run(intervals_per_seg=N)
+
+    def sigma_ss(xi_r):
+        sim = oracle_mod.SampleSim(g, material(), rn, topo, xi_r=xi_r)
+        sim.set_j(g.seg_j)
+        return sim.screen()[2]
+
+    base = sigma_ss(None)
+    assert np.max(np.abs(sigma_ss(np.full(g.n_res, 1.7)) - 1.7 * base)) <= 1e-12 * np.max(np.abs(base))
+    # one segment's multiplier equals multiplying that segment's current density
+    xi = np.ones(g.n_res); xi[2] = 1.3
+    g2 = tree_from_edges(5, edges, L=[10 * UM, 20 * UM, 15 * UM, 5 * UM], w=0.4 * UM, h=0.2 * UM,
+                         j=[2e10, -1e10, 3e10 * 1.3, 1e10], T=378.0)
+    sim = oracle_mod.SampleSim(g2, material(), rn, topo)
+    sim.set_j(g2.seg_j)
+    assert np.max(np.abs(sigma_ss(xi) - sim.screen()[2])) <= 1e-12 * np.max(np.abs(base))
+
+
+def test_liner_formula_takes_sampled_resistivity(oracle_mod):
+    # eq. 17 with V_v - V_crit = (l - W) W H; copper term with rho_Cu xi
+    import ctypes as C
+    L = oracle_mod.lib()
+    f = L.ora_late_dR
+    f.restype = C.c_double
+    f.argtypes = [C.c_double] * 6
+    l, W, H, h_ta, rho_ta, rho = 3e-6, 0.5e-6, 0.2e-6, 5e-9, 2e-7, 2.25e-8
+    for xi in (0.8, 1.0, 1.25):
+        hand = (l - W) * (rho_ta / (h_ta * (2 * H + W)) - rho * xi / (W * H))
+        assert abs(f(l, W, H, h_ta, rho_ta, rho * xi) - hand) <= 1e-12 * abs(hand)
