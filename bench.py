@@ -153,22 +153,31 @@ MC_DESC = {
 }
 
 
-def mc_leg(args, name, oracle, plain):
+# further sampled inputs of the Monte Carlo leg with them (Sec. IV-F)
+MC_VAR = {"cov_rho": 0.1, "cov_load": 0.15}
+
+
+def mc_leg(args, name, oracle, plain, var=None, joule=False):
     """Monte Carlo samples/s to TTF: batch creation and the run of every
     sample to its 10 % IR-drop failure or the 10-year horizon, FP32 stepping,
     steady-state screen on.  One untimed run first (code paths warm), then the
     timed one.  With ``oracle``: every 16th sample (64) recomputed by the FP64
     CPU oracle, compared and timed (the CPU baseline of this metric).  With
     ``plain``: the plain FP64 GPU form (generic tree kernel, no screen,
-    Jacobi-CG on the nodal system) on a subset of the samples."""
+    Jacobi-CG on the nodal system) on a subset of the samples.  ``var``: further
+    sampled inputs (resistivity / current-loading CoV); ``joule``: with the
+    Joule-heating thermal pre-pass (inside the timed batch creation)."""
     import numpy as np
     import torch
     import paper_2604_10743_amd as P
     from paper_2604_10743_amd import synth
 
     g, mat, run, mc = synth.workload(name)
-    mc = dict(mc, n_samples=args.mc_samples)
+    mc = dict(mc, n_samples=args.mc_samples, **(var or {}))
+    if joule:
+        run = dict(run, joule=1)
     S = mc["n_samples"]
+    extra = "".join(f", {k[4:]} CoV {v:g}" for k, v in (var or {}).items()) + (", Joule pre-pass" if joule else "")
 
     def one(run_, mc_):
         torch.cuda.synchronize()
@@ -187,7 +196,7 @@ def mc_leg(args, name, oracle, plain):
     ttf = np.array([r["ttf_s"] for r in res if r["failed"]])
     yr = 365.25 * 86400.0
     o = {"metric": "MC samples/s to TTF", "value": S / wall, "unit": "samples/s",
-         "workload": f"{name}: {MC_DESC[name]}; {S} samples, 20% lognormal CoV on kappa and sigma_crit, "
+         "workload": f"{name}: {MC_DESC[name]}; {S} samples, 20% lognormal CoV on kappa and sigma_crit{extra}, "
                      "2000 BE steps over 10 y, IR re-solve every 100 steps, FP32 stepping, screen on",
          "wall_s": wall, "n_fail": int(ttf.size), "n_censored": int(S - ttf.size),
          "ttf_mean_y": float(ttf.mean() / yr) if ttf.size else None,
@@ -337,7 +346,9 @@ def main():
 
     if args.only_mc:
         out = {"mc": mc_leg(args, "mc_grid", oracle=False, plain=False),
-               "mc_mesh": mc_leg(args, "mc_mesh", oracle=False, plain=False)}
+               "mc_mesh": mc_leg(args, "mc_mesh", oracle=False, plain=False),
+               "mc_rho_load": mc_leg(args, "mc_grid", oracle=False, plain=False, var=MC_VAR),
+               "mc_joule": mc_leg(args, "mc_grid", oracle=False, plain=False, joule=True)}
         print(json.dumps(out), flush=True)
         return
 
@@ -407,6 +418,8 @@ def main():
         out["mc"] = mc_leg(args, "mc_grid", oracle=not args.no_cpu, plain=not args.no_plain)
         log("bench: mc (mc_grid) done")
         out["mc_mesh"] = mc_leg(args, "mc_mesh", oracle=False, plain=False)
+        out["mc_rho_load"] = mc_leg(args, "mc_grid", oracle=False, plain=False, var=MC_VAR)
+        out["mc_joule"] = mc_leg(args, "mc_grid", oracle=False, plain=False, joule=True)
         log("bench: mc (mc_mesh) done")
 
     if not args.no_mc:
