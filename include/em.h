@@ -144,6 +144,12 @@ typedef struct {
                                     tree), or one of those (at most 512 in FP64) that holds it.
                                     Results do not depend on it (instances never share a
                                     reduction: the couplings across their boundaries are zero). */
+    int32_t chain_occ;           /* register budget of the resident chain kernel: 0 or 1 as many
+                                    registers as it uses (one or two workgroups per compute unit);
+                                    4 at most 128 VGPRs (four waves per SIMD: four 256-lane or two
+                                    512-lane workgroups share a compute unit, some values spill),
+                                    FP32 with 256 or 512 lanes only.  Pays when a launch holds
+                                    few instances (Monte Carlo after the screen).  Same results. */
     int32_t joule;               /* 1: one-time Joule-heating thermal pre-pass at batch creation
                                     (Sec. II-A): the currents of a nominal IR solve (or the
                                     prescribed seg_j) heat every wire segment; each segment's
@@ -295,10 +301,11 @@ em_status em_set_seg_state(em_batch *b, int32_t sample, const double *dR, const 
  * choice beyond the rounding of the IR dot products.  out may be NULL. */
 typedef struct {
     int32_t chain_wg;            /* chosen lanes per workgroup */
+    int32_t chain_occ;           /* chosen register budget (em_run_params.chain_occ) */
     int32_t ir_launch;           /* chosen IR launch shape (1, 2 or 3; 0: not tuned) */
-    int32_t n_wg;                /* candidates tried */
-    int32_t wg[4];
-    double wg_ms[4];             /* stream time of the n_steps steps per candidate */
+    int32_t n_wg;                /* chain-kernel candidates tried */
+    int32_t wg[8], occ[8];       /* each candidate's lanes per workgroup and register budget */
+    double wg_ms[8];             /* stream time of the n_steps steps per candidate */
     double ir_ms[3];             /* cold IR solve: multi-kernel, one workgroup per sample from HBM,
                                     from LDS (-1: not tried) */
 } em_tune_info;

@@ -67,7 +67,7 @@ class RunParams(C.Structure):
                 ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32), ("prec", C.c_int32),
                 ("screen", C.c_int32), ("max_voids_per_tree", C.c_int32), ("T_ambient", C.c_double),
                 ("stepper", C.c_int32), ("ir_precond", C.c_int32), ("ir_launch", C.c_int32),
-                ("chain_wg", C.c_int32), ("joule", C.c_int32)]
+                ("chain_wg", C.c_int32), ("chain_occ", C.c_int32), ("joule", C.c_int32)]
 
 
 class MCParams(C.Structure):
@@ -96,8 +96,9 @@ class Info(C.Structure):
 
 
 class TuneInfo(C.Structure):
-    _fields_ = [("chain_wg", C.c_int32), ("ir_launch", C.c_int32), ("n_wg", C.c_int32),
-                ("wg", C.c_int32 * 4), ("wg_ms", C.c_double * 4), ("ir_ms", C.c_double * 3)]
+    _fields_ = [("chain_wg", C.c_int32), ("chain_occ", C.c_int32), ("ir_launch", C.c_int32),
+                ("n_wg", C.c_int32), ("wg", C.c_int32 * 8), ("occ", C.c_int32 * 8),
+                ("wg_ms", C.c_double * 8), ("ir_ms", C.c_double * 3)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -205,6 +206,7 @@ class Batch:
                       T_ambient=float(run["T_ambient"]), stepper=int(run.get("stepper", 0)),
                       ir_precond=int(run.get("ir_precond", 2)),
                       ir_launch=int(run.get("ir_launch", 0)), chain_wg=int(run.get("chain_wg", 0)),
+                      chain_occ=int(run.get("chain_occ", 0)),
                       joule=int(run.get("joule", 0)))
         mcp = None
         if mc is not None:
@@ -329,8 +331,9 @@ class Batch:
         t = TuneInfo()
         self._chk(lib().em_autotune(self._h, C.c_int32(n_steps), C.byref(t)))
         n = t.n_wg
-        return {"chain_wg": t.chain_wg, "ir_launch": t.ir_launch,
-                "wg_ms": {int(t.wg[k]): float(t.wg_ms[k]) for k in range(n)},
+        return {"chain_wg": t.chain_wg, "chain_occ": t.chain_occ, "ir_launch": t.ir_launch,
+                "wg_ms": {int(t.wg[k]): float(t.wg_ms[k]) for k in range(n) if t.occ[k] == 1},
+                "wg_ms_occ4": {int(t.wg[k]): float(t.wg_ms[k]) for k in range(n) if t.occ[k] == 4},
                 "ir_ms": {1: float(t.ir_ms[0]), 3: float(t.ir_ms[1]), 2: float(t.ir_ms[2])}}
 
     def set_seg_state(self, sample: int, dR, open_):

@@ -90,6 +90,8 @@ struct em_batch {
     std::vector<int> chain_L;           // lanes per instance of a chain tree (0: generic tree)
     std::vector<int> tree_perm_h;
     int chain_wg = 0;
+    int chain_occ = 1;                  // chain kernel register budget: 1 default, 4 (128 VGPRs)
+    bool psi_shared = false;            // steady stress of the last screen only in column 0 (shared screen)
     std::vector<int> wg_cand;           // chain workgroup sizes that hold the longest chain tree
     long long lanes_cap = 0;            // lanes allocated for the chain kernel's table
     int *res_cnt = nullptr;             // [S][2] per-sample result counts (device)
@@ -544,8 +546,10 @@ em_status run_screen(em_batch *b, bool apply)
         HIPCHK(b, hipMemsetAsync(d.tree_mortal, 0, (size_t)d.n_trees * d.S, b->stream));
         HIPCHK(b, hipMemsetAsync(d.seg_mortal, 0, (size_t)d.n_res * d.S, b->stream));
         launch_screen_shared(d, apply, b->stream);
+        b->psi_shared = true;
     } else {
         launch_screen(d, apply, b->stream);
+        b->psi_shared = false;
     }
     LAUNCHCHK(b);
     if (apply) b->act_dirty = true;
@@ -624,6 +628,7 @@ em_status ensure_active(em_batch *b)
     std::vector<int> pi, pL;
     std::vector<long long> po;
     d.chain_wg = cWG;
+    d.chain_occ = b->chain_occ;
     long long n_lanes = place_chain_lanes(b->tree_perm_h, b->chain_L, S, cWG, ia.data(), sa.data(), &pi, &po, &pL);
     if (n_lanes > b->lanes_cap)      // the full layout of any candidate size always fits
         n_lanes = place_chain_lanes(b->tree_perm_h, b->chain_L, S, cWG, nullptr, nullptr, &pi, &po, &pL);
@@ -740,12 +745,22 @@ em_status sur_buffers(em_batch *b)
 
 // Features of every (tree, sample) with the current densities: the screen's
 // steady stress is refreshed first (without changing the active set).
+// Every sample's column of the steady stress (after a shared screen only
+// column 0 was written).
+void materialize_psi(em_batch *b)
+{
+    if (!b->psi_shared) return;
+    launch_psi_bcast(b->d, b->stream);
+    b->psi_shared = false;
+}
+
 em_status features_impl(em_batch *b, float *X, bool screen_current = false, bool candidates_only = false)
 {
     if (!screen_current) {
         em_status rc = run_screen(b, false);
         if (rc != EM_OK) return rc;
     }
+    materialize_psi(b);
     launch_features(b->d, X, candidates_only, b->stream);
     LAUNCHCHK(b);
     return EM_OK;
@@ -983,6 +998,9 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
                                        "(1024 FP32, 512 FP64) holding the longest chain tree");
         cWG = r->chain_wg;
     }
+    if (r->chain_occ != 0 && r->chain_occ != 1 &&
+        !(r->chain_occ == 4 && b->fp32 && (cWG == 256 || cWG == 512)))
+        return fail(b, EM_ERR_ARG, "chain_occ must be 0, 1, or 4 (FP32 with 256 or 512 lanes)");
     // placement of each chain instance: first lane (global) and lane count;
     // the per-lane table itself is expanded on the device.  The table is
     // allocated for the largest of the candidate sizes' layouts.
@@ -1045,11 +1063,13 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     b->n_generic_trees = 0;
     for (int t = 0; t < nt; ++t) b->n_generic_trees += tree_chain[t] ? 0 : 1;
     b->chain_wg = cWG;
+    b->chain_occ = r->chain_occ == 4 ? 4 : 1;
     b->wg_cand = wg_cand;
     b->lanes_cap = lanes_cap;
     b->tree_perm_h = tree_perm;
     b->chain_L = chain_L;
     d.chain_wg = cWG;
+    d.chain_occ = b->chain_occ;
     {
         const size_t ISb = (size_t)nt * S;
         AL(b->act_inst, int, ISb); AL(b->pl_inst, int, ISb); AL(b->pl_L, int, ISb);
@@ -1400,6 +1420,7 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
                 // (only ever brought forward), then activation of those due
                 const int nl = b->n_def_list;
                 if (nl > 0 && !b->ir_unchanged) {
+                    materialize_psi(b);
                     launch_reeval_features(d, nl, d.feat, st);
                     LAUNCHCHK(b);
                     int irc = mlp_forward_async(b->sur, d.feat, nl, b->sur_y, st);
@@ -1553,9 +1574,15 @@ em_status em_autotune(em_batch *b, int32_t n_steps, em_tune_info *out)
     // chain-kernel workgroup size: n_steps steps of the screened instances
     if (rc == EM_OK && b->d.n_chain_wg >= 0) {
         double best = 1e300;
-        int best_w = b->chain_wg;
-        for (size_t k = 0; k < b->wg_cand.size() && k < 4 && rc == EM_OK; ++k) {
-            b->chain_wg = b->wg_cand[k];
+        int best_w = b->chain_wg, best_o = b->chain_occ;
+        std::vector<std::pair<int, int>> cand;          // (lanes, register budget)
+        for (int w : b->wg_cand) {
+            cand.push_back({w, 1});
+            if (b->fp32 && (w == 256 || w == 512)) cand.push_back({w, 4});
+        }
+        for (size_t k = 0; k < cand.size() && k < 8 && rc == EM_OK; ++k) {
+            b->chain_wg = cand[k].first;
+            b->chain_occ = cand[k].second;
             for (int rep = 0; rep < 2 && rc == EM_OK; ++rep) {
                 if ((rc = em_reset(b)) != EM_OK) break;
                 if (!b->trees_only && (rc = ir_solve_impl(b)) != EM_OK) break;
@@ -1569,13 +1596,16 @@ em_status em_autotune(em_batch *b, int32_t n_steps, em_tune_info *out)
                 if ((rc = stream_ms(ms)) != EM_OK) break;
                 if (rep == 1) {
                     info.wg[info.n_wg] = b->chain_wg;
+                    info.occ[info.n_wg] = b->chain_occ;
                     info.wg_ms[info.n_wg++] = ms;
-                    if (ms < best) { best = ms; best_w = b->chain_wg; }
+                    if (ms < best) { best = ms; best_w = b->chain_wg; best_o = b->chain_occ; }
                 }
             }
         }
         b->chain_wg = best_w;
+        b->chain_occ = best_o;
         info.chain_wg = best_w;
+        info.chain_occ = best_o;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1752,7 +1782,8 @@ em_status em_get_screen(em_batch *b, int32_t sample, uint8_t *tree_mortal, uint8
         std::vector<double> tmp((size_t)b->ns * S);
         HIPCHK(b, hipMemcpyAsync(tmp.data(), b->d.psi, 8 * tmp.size(), hipMemcpyDeviceToHost, st));
         HIPCHK(b, hipStreamSynchronize(st));
-        for (int i = 0; i < b->ns; ++i) sigma_ss[i] = tmp[(size_t)i * S + sample];
+        const int col = b->psi_shared ? 0 : sample;      // a shared screen wrote column 0 only
+        for (int i = 0; i < b->ns; ++i) sigma_ss[i] = tmp[(size_t)i * S + col];
     }
     HIPCHK(b, hipStreamSynchronize(st));
     return EM_OK;

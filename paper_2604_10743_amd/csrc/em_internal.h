@@ -62,6 +62,7 @@ struct Dev {
     const int *lane_inst, *lane_blk;    // chain kernel lanes: instance, block index
     int n_chain_wg;                     // workgroups of the chain kernel's launch
     int chain_wg;                       // its lanes per workgroup (256, 512 or the precision's maximum)
+    int chain_occ;                      // 1, or 4: register budget of 128 VGPRs (FP32, 256/512 lanes)
     // ---- per stress node statics (FP64) ----
     double *T, *V, *g0, *rob0, *gdx0, *mdrv;
     double *tree_V;                     // [n_trees] total control volume
@@ -217,6 +218,8 @@ void launch_screen(const Dev &d, bool apply, hipStream_t st);
 // the screen when every sample has the same current densities (sample 0's);
 // tree_mortal and seg_mortal zeroed by the caller
 void launch_screen_shared(const Dev &d, bool apply, hipStream_t st);
+// copy the shared screen's steady stress (column 0) to every sample's column
+void launch_psi_bcast(const Dev &d, hipStream_t st);
 void launch_step(const Dev &d, bool fp32, int n_steps, int step0, hipStream_t st);
 void launch_void_dR(const Dev &d, hipStream_t st);
 void launch_chain(const Dev &d, const Dev *d_dev, bool fp32, int n_steps, int step0, hipStream_t st);

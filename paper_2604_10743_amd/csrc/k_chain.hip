@@ -82,8 +82,11 @@ __device__ inline double edge_dtg(const Dev *d, int i, int s, double dt)
     return dt * d->xi_k[(size_t)d->seg[i] * d->S + s] * d->g0[i];
 }
 
-template <typename R, int M, int WG>
-__global__ __launch_bounds__(WG) void k_chain(ChainHot h)
+// OCC: waves per SIMD the register budget must allow (1: as many registers
+// as the kernel wants; 4: at most 128 VGPRs, so that several workgroups share
+// a CU when the launch holds few instances).
+template <typename R, int M, int WG, int OCC>
+__global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
 {
     constexpr int LEV = Log2<WG>::v;
     __shared__ R s_al[LEV][WG];
@@ -629,13 +632,20 @@ void launch_chain(const Dev &d, const Dev *d_dev, bool fp32, int n_steps, int st
     h.dt = d.dt;
     // the batch's workgroup size (lanes): the smallest that holds its longest
     // chain, or the one the autotuner measured fastest
+    const bool dense = d.chain_occ == 4;    // FP32 256/512 lanes only (checked at creation)
     if (fp32) {
-        if (d.chain_wg == 256) k_chain<float, CHAIN_M32, 256><<<d.n_chain_wg, 256, 0, st>>>(h);
-        else if (d.chain_wg == 512) k_chain<float, CHAIN_M32, 512><<<d.n_chain_wg, 512, 0, st>>>(h);
-        else k_chain<float, CHAIN_M32, CHAIN_WG32><<<d.n_chain_wg, CHAIN_WG32, 0, st>>>(h);
+        if (d.chain_wg == 256) {
+            if (dense) k_chain<float, CHAIN_M32, 256, 4><<<d.n_chain_wg, 256, 0, st>>>(h);
+            else k_chain<float, CHAIN_M32, 256, 1><<<d.n_chain_wg, 256, 0, st>>>(h);
+        } else if (d.chain_wg == 512) {
+            if (dense) k_chain<float, CHAIN_M32, 512, 4><<<d.n_chain_wg, 512, 0, st>>>(h);
+            else k_chain<float, CHAIN_M32, 512, 1><<<d.n_chain_wg, 512, 0, st>>>(h);
+        } else {
+            k_chain<float, CHAIN_M32, CHAIN_WG32, 1><<<d.n_chain_wg, CHAIN_WG32, 0, st>>>(h);
+        }
     } else {
-        if (d.chain_wg == 256) k_chain<double, CHAIN_M64, 256><<<d.n_chain_wg, 256, 0, st>>>(h);
-        else k_chain<double, CHAIN_M64, CHAIN_WG64><<<d.n_chain_wg, CHAIN_WG64, 0, st>>>(h);
+        if (d.chain_wg == 256) k_chain<double, CHAIN_M64, 256, 1><<<d.n_chain_wg, 256, 0, st>>>(h);
+        else k_chain<double, CHAIN_M64, CHAIN_WG64, 1><<<d.n_chain_wg, CHAIN_WG64, 0, st>>>(h);
     }
 }
 

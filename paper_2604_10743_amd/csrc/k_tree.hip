@@ -7,6 +7,7 @@
 // [node][sample] accesses.  With S == 1 lanes are trees, ordered largest
 // first so that a wavefront holds trees of similar size.
 #include "em_internal.h"
+#include <algorithm>
 #include <cmath>
 
 namespace em {
@@ -242,13 +243,17 @@ EM_KERNEL void k_node_V(Dev d, int fp32)
 }
 
 // Total control volume of each tree (fixed summation order).
+// One wavefront per tree: strided partial sums, then a fixed butterfly.
 EM_KERNEL void k_tree_V(Dev d)
 {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (t >= d.n_trees) return;
     double s = 0.0;
-    for (int i = d.tree_off[t]; i < d.tree_off[t + 1]; ++i) s += d.V[i];
-    d.tree_V[t] = s;
+    for (int i = d.tree_off[t] + lane; i < d.tree_off[t + 1]; i += 64) s += d.V[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) d.tree_V[t] = s;
 }
 
 // ------------------------------------------------------------------------
@@ -324,6 +329,17 @@ EM_KERNEL void k_node_sc(Dev d)
     if (g >= (long long)d.ns * d.S) return;
     int s = (int)(g % d.S), i = (int)(g / d.S);
     ((R *)d.sc)[g] = (R)node_scrit(d, i, s);
+}
+
+// The same with one node per block row (node uniform across the block, so
+// its topology is read once) and samples along x; for many samples.
+template <typename R>
+EM_KERNEL void k_node_sc_rows(Dev d)
+{
+    const int i = blockIdx.y + blockIdx.z * 65535;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.ns || s >= d.S) return;
+    ((R *)d.sc)[(size_t)i * d.S + s] = (R)node_scrit(d, i, s);
 }
 
 // ------------------------------------------------------------------------
@@ -595,19 +611,38 @@ EM_KERNEL void k_screen_ss0(Dev d)
     steady_stress_wave(d, d.tree_perm[slot], 0, lane);
 }
 
-EM_KERNEL void k_screen_bcast(Dev d)
+// Every sample's verdict from sample 0's steady stress.  The steady stress
+// itself stays in column 0 until a reader needs every column (k_psi_bcast).
+__device__ inline void screen_verdict(const Dev &d, int i, int s)
 {
-    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (long long)d.ns * d.S) return;
-    const int S = d.S, i = (int)(g / S), s = (int)(g % S);
+    const int S = d.S;
     const double v = d.psi[(size_t)i * S];
-    if (s) d.psi[g] = v;
     if (isfinite(v) && v > node_scrit(d, i, s)) {
         d.tree_mortal[(size_t)d.ntree[i] * S + s] = 1;
         uint8_t *sm = d.seg_mortal + (size_t)s * d.n_res;
         if (d.parent[i] >= 0) sm[d.seg[i]] = 1;
         for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k) sm[d.seg[d.child[k]]] = 1;
     }
+}
+// one node per block row (its topology read once per block), samples along x
+EM_KERNEL void k_screen_bcast_rows(Dev d)
+{
+    const int i = blockIdx.y + blockIdx.z * 65535;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d.ns && s < d.S) screen_verdict(d, i, s);
+}
+EM_KERNEL void k_screen_bcast_flat(Dev d)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < (long long)d.ns * d.S) screen_verdict(d, (int)(g / d.S), (int)(g % d.S));
+}
+
+EM_KERNEL void k_psi_bcast(Dev d)
+{
+    const int i = blockIdx.y + blockIdx.z * 65535;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.ns || s >= d.S || s == 0) return;
+    d.psi[(size_t)i * d.S + s] = d.psi[(size_t)i * d.S];
 }
 
 EM_KERNEL void k_screen_activate(Dev d)
@@ -1127,7 +1162,7 @@ void launch_edge_static(const Dev &d, hipStream_t st)
 void launch_node_V(const Dev &d, bool fp32, hipStream_t st)
 {
     k_node_V<<<nblocks(d.ns), 256, 0, st>>>(d, fp32 ? 1 : 0);
-    k_tree_V<<<nblocks(d.n_trees), 256, 0, st>>>(d);
+    k_tree_V<<<nblocks(d.n_trees, 4), 256, 0, st>>>(d);
 }
 void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, double cov_r, double cov_l,
                   hipStream_t st)
@@ -1136,8 +1171,23 @@ void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, doubl
     k_draws<<<nblocks((long long)d.n_res * d.S), 256, 0, st>>>(d, seed, cov_k, cov_s, cov_r, use);
     if (d.sink_s) k_draws_load<<<nblocks((long long)d.n_nodes * d.S), 256, 0, st>>>(d, seed, cov_l);
 }
+// grid of one block row per node (rows beyond 65535 folded into z) and the
+// samples along x
+static dim3 node_rows_grid(const Dev &d, int bs)
+{
+    return dim3((unsigned)((d.S + bs - 1) / bs), (unsigned)std::min(d.ns, 65535),
+                (unsigned)((d.ns + 65534) / 65535));
+}
+static int rows_bs(const Dev &d) { return d.S >= 256 ? 256 : d.S >= 128 ? 128 : 64; }
+
 void launch_node_sc(const Dev &d, bool fp32, hipStream_t st)
 {
+    if (d.S >= 64) {
+        const int bs = rows_bs(d);
+        if (fp32) k_node_sc_rows<float><<<node_rows_grid(d, bs), bs, 0, st>>>(d);
+        else k_node_sc_rows<double><<<node_rows_grid(d, bs), bs, 0, st>>>(d);
+        return;
+    }
     long long n = (long long)d.ns * d.S;
     if (fp32) k_node_sc<float><<<nblocks(n), 256, 0, st>>>(d);
     else k_node_sc<double><<<nblocks(n), 256, 0, st>>>(d);
@@ -1162,8 +1212,19 @@ void launch_screen(const Dev &d, bool apply, hipStream_t st)
 void launch_screen_shared(const Dev &d, bool apply, hipStream_t st)
 {
     k_screen_ss0<<<nblocks((long long)d.n_trees, 4), 256, 0, st>>>(d);
-    k_screen_bcast<<<nblocks((long long)d.ns * d.S), 256, 0, st>>>(d);
+    if (d.S >= 64) {
+        const int bs = rows_bs(d);
+        k_screen_bcast_rows<<<node_rows_grid(d, bs), bs, 0, st>>>(d);
+    } else {
+        k_screen_bcast_flat<<<nblocks((long long)d.ns * d.S), 256, 0, st>>>(d);
+    }
     if (apply) k_screen_activate<<<nblocks((long long)d.n_trees * d.S), 256, 0, st>>>(d);
+}
+void launch_psi_bcast(const Dev &d, hipStream_t st)
+{
+    if (d.S < 2) return;
+    const int bs = rows_bs(d);
+    k_psi_bcast<<<node_rows_grid(d, bs), bs, 0, st>>>(d);
 }
 void launch_step(const Dev &d, bool fp32, int n_steps, int step0, hipStream_t st)
 {

@@ -200,20 +200,22 @@ def test_chain_workgroup_sizes_give_identical_results(em, prec):
     # of the state, with the same nucleation sites.
     g, mat, rn, _ = synth.workload("tiny_trees")
     mc = dict(n_samples=8, seed=5, cov_kappa=0.2, cov_scrit=0.2)
-    sizes = (256, 512, 1024) if prec == 1 else (256, 512)
+    # (lanes, register budget); the 128-VGPR forms run the same arithmetic
+    sizes = ((256, 1), (512, 1), (256, 4), (512, 4), (1024, 1)) if prec == 1 else ((256, 1), (512, 1))
     out = []
-    for w in sizes:
-        B = em.Batch(g, mat, dict(rn, prec=prec, chain_wg=w), mc)
+    for w, occ in sizes:
+        B = em.Batch(g, mat, dict(rn, prec=prec, chain_wg=w, chain_occ=occ), mc)
         B.stress_step(1000)
         ev = B.events()
         ev = ev[np.lexsort(ev.T[::-1])] if len(ev) else ev
         out.append(([B.stress(s) for s in range(8)], ev))
         B.close()
     assert len(out[0][1]) > 0
-    for st, ev in out[1:2]:
+    n_exact = 4 if prec == 1 else 2
+    for st, ev in out[1:n_exact]:
         assert all(np.array_equal(a, b) for a, b in zip(st, out[0][0]))
         assert np.array_equal(ev, out[0][1])
-    for st, ev in out[2:]:
+    for st, ev in out[n_exact:]:
         for a, b in zip(st, out[0][0]):
             assert np.max(np.abs(a - b)) <= 1e-4 * np.max(np.abs(b))
         site = [0, 1, 3]                                   # sample, tree, node
@@ -221,6 +223,10 @@ def test_chain_workgroup_sizes_give_identical_results(em, prec):
         assert np.max(np.abs(ev[:, 2] - out[0][1][:, 2])) <= 20
     with pytest.raises(em.EmError):
         em.Batch(g, mat, dict(rn, prec=0, chain_wg=1024), mc)     # above the FP64 maximum
+    for bad in (dict(prec=0, chain_wg=256, chain_occ=4), dict(prec=1, chain_wg=1024, chain_occ=4),
+                dict(prec=1, chain_wg=256, chain_occ=2)):
+        with pytest.raises(em.EmError):
+            em.Batch(g, mat, dict(rn, **bad), mc)
 
 
 def test_autotune_keeps_results_and_resets(em):
