@@ -142,7 +142,11 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
     R scmin = (R)INFINITY;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
+        // nodes past cnt (a short last block, an idle lane) keep zeros here:
+        // the step below computes them without branches, and zero pivots and
+        // multipliers map them to zero increments
         sg[j] = 0; fv[j] = 0; w[j] = 0; dinv[j] = 0; al[j] = 0; be[j] = 0;
+        if constexpr (LO) sl[j] = 0.f;
         if (j < cnt) {
             size_t x = (size_t)(start + j) * S + s;
             sg[j] = sig[x];
@@ -166,12 +170,17 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
     }
     int nv = act ? d->nv[inst] : 0;
     unsigned vmask = 0;             // block nodes carrying a void
+    // a void node's row has no drive (its Robin row replaces it): its dt*f
+    // register is zeroed here once (the void growth reads it from memory)
     auto refresh_vmask = [&]() {
         vmask = 0;
         for (int k = 0; k < nv; ++k) {
             int jv = d->vnode[inst * MAXV + k] - start;
             if (jv >= 0 && jv < cnt) vmask |= 1u << jv;
         }
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            if ((vmask >> j) & 1u) fv[j] = 0;
     };
     if (act) refresh_vmask();
     auto e_first = [&]() -> R {     // coupling from the separator to what follows it
@@ -323,19 +332,21 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
     for (int st = 0; st < h.n_steps; ++st) {
         // 1. residual dt (A sigma + f) in FP64 (flux differences are exact),
         //    rounded once for the solve: the step solves for the increment
+        //    Each edge's flux dt g (s_right - s_left) is formed once and
+        //    enters its two nodes with opposite signs.  Every node, past cnt
+        //    too (finite values, zero increments below).
         R y[M];
-        double r0_part = 0.0;
+        double r0_part = 0.0, qprev = 0.0;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             y[j] = 0;
-            if (j < cnt) {
-                const double sj = sv(j);
-                double r = ((vmask >> j) & 1u) ? 0.0 : (double)fv[j];
-                const double sr = (j + 1 < cnt) ? sv(j + 1) : (LO ? (double)sn + (double)snl : (double)sn);
-                r += (double)gE[j + 1] * (sr - sj);
-                if (j > 0) r += (double)gE[j] * (sv(j - 1) - sj);
-                if (j == 0) r0_part = r; else y[j] = (R)r;
-            }
+            const double sj = sv(j);
+            const double sr = (j + 1 < cnt) ? sv(j + 1) : (LO ? (double)sn + (double)snl : (double)sn);
+            const double qn = (double)gE[j + 1] * (sr - sj);
+            double r = (double)fv[j] + qn;
+            if (j > 0) r -= qprev;
+            qprev = qn;
+            if (j == 0) r0_part = r; else y[j] = (R)r;
         }
         if (vmask) {                           // Robin sinks at void nodes
             for (int k = 0; k < nv; ++k) {
@@ -350,19 +361,20 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
                     }
             }
         }
-        // 2. interior solve with zero separator values (y overwrites the rhs)
+        // 2. interior solve with zero separator values (y overwrites the rhs).
+        //    Past cnt: w = dinv = 0, so the backward sweep leaves y = 0 there
+        //    and carries yn = 0 into the last node (whose coupling to the next
+        //    block is the separator's, not the interior solve's).
         R yp = 0;
 #pragma unroll
-        for (int j = 1; j < M; ++j)
-            if (j < cnt) { yp = (j == 1) ? y[1] : y[j] + w[j] * yp; y[j] = yp; }
+        for (int j = 1; j < M; ++j) { yp = (j == 1) ? y[1] : y[j] + w[j] * yp; y[j] = yp; }
         R yn = 0;
 #pragma unroll
-        for (int j = M - 1; j >= 1; --j)
-            if (j < cnt) {
-                const R uj = (j + 1 < cnt) ? gE[j + 1] * dinv[j] : (R)0;
-                yn = y[j] * dinv[j] + uj * yn;
-                y[j] = yn;
-            }
+        for (int j = M - 1; j >= 1; --j) {
+            const R uj = gE[j + 1] * dinv[j];
+            yn = y[j] * dinv[j] + uj * yn;
+            y[j] = yn;
+        }
         R yF = 0, yL = 0, sL = sg[0];
         float sLl = 0.f;
         if constexpr (LO) sLl = sl[0];
@@ -399,11 +411,13 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
             const int dd = 1 << l;
             s_x[buf][lane] = Rk;
             lds_barrier();
+            // both neighbours read unconditionally (indices clamped into the
+            // workgroup; every lane wrote a finite value): a missing coupling
+            // has a zero multiplier
             const R al_l = s_al[l][lane], ga_l = s_ga[l][lane];
-            R nr = Rk;
-            if (al_l != (R)0) nr += al_l * s_x[buf][lane - dd];
-            if (ga_l != (R)0) nr += ga_l * s_x[buf][lane + dd];
-            Rk = nr;
+            const R xm = s_x[buf][lane >= dd ? lane - dd : 0];
+            const R xp = s_x[buf][lane + dd < WG ? lane + dd : WG - 1];
+            Rk = Rk + al_l * xm + ga_l * xp;
             buf ^= 1;
         }
         const R xk = Rk * dfin;
@@ -419,16 +433,14 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
             };
             put(0, sv(0) + (double)xk);
 #pragma unroll
-            for (int j = 1; j < M; ++j)
-                if (j < cnt) put(j, sv(j) + (double)(y[j] + al[j] * xk + be[j] * xn));
+            for (int j = 1; j < M; ++j) put(j, sv(j) + (double)(y[j] + al[j] * xk + be[j] * xn));
             const double v = (double)sn + (double)snl + (double)xn;
             sn = (R)v;
             snl = (float)(v - (double)sn);
         } else {
             sg[0] += xk;
 #pragma unroll
-            for (int j = 1; j < M; ++j)
-                if (j < cnt) sg[j] += y[j] + al[j] * xk + be[j] * xn;
+            for (int j = 1; j < M; ++j) sg[j] += y[j] + al[j] * xk + be[j] * xn;
             sn += xn;
         }
 
@@ -438,12 +450,13 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
                 const int q = inst * MAXV + k;
                 const int jv = d->vnode[q] - start;
                 if (jv < 0 || jv >= cnt) continue;
-                R sh = 0, fvv = 0;
+                R sh = 0;
+                const R fvv = dtf_g[(size_t)(start + jv) * S + s];
                 float slo = 0.f;
 #pragma unroll
                 for (int j = 0; j < M; ++j)
                     if (j == jv) {
-                        sh = sg[j]; fvv = fv[j];
+                        sh = sg[j];
                         if constexpr (LO) slo = sl[j];
                     }
                 double svv = (double)sh;
