@@ -30,17 +30,26 @@ __device__ inline double wg_wave_sum(double v)
 }
 
 // Sum over the workgroup, returned to every thread (fixed summation order).
+// The wavefront partials alternate between two halves of the buffer from
+// call to call, so one barrier per call suffices: a half is written again
+// only after every thread has passed the next call's barrier, that is after
+// it read the half.  Every thread makes the same sequence of calls.
+struct WgRed {
+    double *buf;                        // 2 * (BS / 64) doubles
+    int par;
+};
 template <int BS>
-__device__ inline double wg_sum(double v, double *red)
+__device__ inline double wg_sum(double v, WgRed &red)
 {
     v = wg_wave_sum(v);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) red[w] = v;
+    double *b = red.buf + red.par * (BS / 64);
+    red.par ^= 1;
+    if (lane == 0) b[w] = v;
     __syncthreads();
     double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < BS / 64; ++k) acc += red[k];
-    __syncthreads();
+    for (int k = 0; k < BS / 64; ++k) acc += b[k];
     return acc;
 }
 
@@ -122,7 +131,7 @@ struct LdsLevels {
 // z = M^-1 r by one V-cycle; returns r.z (every thread).  When setp is set
 // p also receives z (start of a solve).
 template <int BS, class Lev>
-__device__ double wg_vcycle(const L0View &S0, const Amg &a, const Lev &lv, bool setp, double *red)
+__device__ double wg_vcycle(const L0View &S0, const Amg &a, const Lev &lv, bool setp, WgRed &red)
 {
     const int T = threadIdx.x, n = S0.n, nl = a.nlev;
     const double om = a.omega, al = a.alpha;
@@ -154,16 +163,22 @@ __device__ double wg_vcycle(const L0View &S0, const Amg &a, const Lev &lv, bool 
     {
         const LView C = lv.lev(nl);
         const double *Ai = a.dense ? lv.Ainv() : nullptr;
-        for (int i = T; i < C.n; i += BS) {
-            double v;
-            if (Ai) {
+        if (Ai) {
+            // eight lanes per row (aligned groups of one wavefront, active or
+            // idle together), each a strided part of the row's dot product
+            constexpr int TPR = 8;
+            for (int idx = T; idx < C.n * TPR; idx += BS) {
+                const int i = idx / TPR, part = idx - i * TPR;
                 const double *row = Ai + (size_t)i * C.n;
-                v = 0.0;
-                for (int j = 0; j < C.n; ++j) v += row[j] * C.b[j];
-            } else {
-                v = C.b[i] / C.D[i];
+                double v = 0.0;
+                for (int j = part; j < C.n; j += TPR) v += row[j] * C.b[j];
+                v += __shfl_xor(v, 4, 64);
+                v += __shfl_xor(v, 2, 64);
+                v += __shfl_xor(v, 1, 64);
+                if (part == 0) C.x[i] = v;
             }
-            C.x[i] = v;
+        } else {
+            for (int i = T; i < C.n; i += BS) C.x[i] = C.b[i] / C.D[i];
         }
         __syncthreads();
     }
@@ -210,10 +225,11 @@ __device__ double wg_vcycle(const L0View &S0, const Amg &a, const Lev &lv, bool 
 // *done when ||r||^2 <= tol2.
 template <int BS, class Lev>
 __device__ int wg_pcg(const L0View &S0, const Amg &a, const Lev &lv, double tol2, int max_iter, bool *done,
-                      double *red)
+                      double *red_buf)
 {
     const int T = threadIdx.x, n = S0.n;
     double *u = S0.u, *r = S0.r, *z = S0.z, *p = S0.p, *q = S0.q;
+    WgRed red{red_buf, 0};
     double rz = wg_vcycle<BS>(S0, a, lv, true, red);
     int it = 0;
     *done = false;
@@ -256,7 +272,7 @@ __device__ int wg_pcg(const L0View &S0, const Amg &a, const Lev &lv, double tol2
 __global__ __launch_bounds__(WG_BS, 8) void k_ir_pcg_wg(Dev d, const Amg *__restrict__ ap, double rtol,
                                                        int max_iter)
 {
-    __shared__ double red[WG_BS / 64];
+    __shared__ double red[2 * (WG_BS / 64)];
     const int s = blockIdx.x;
     if (d.conv[s]) {
         if (threadIdx.x == 0) d.ir_iters[s] = 0;
@@ -305,7 +321,7 @@ __global__ __launch_bounds__(LDS_BS) void k_ir_pcg_lds(Dev d, const Amg *__restr
                                                        double rtol, int max_iter)
 {
     extern __shared__ __align__(16) char sm[];
-    __shared__ double red[LDS_BS / 64];
+    __shared__ double red[2 * (LDS_BS / 64)];
     const int s = blockIdx.x;
     if (d.conv[s]) {
         if (threadIdx.x == 0) d.ir_iters[s] = 0;
