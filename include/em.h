@@ -163,6 +163,13 @@ typedef struct {
                                     nodes then take the profile's values; the field is fixed for
                                     the batch (resets keep it).  0: node temperatures sampled
                                     from the map directly. */
+    double dt_growth;            /* time grid of em_run_to_ttf (the paper's non-uniform inner
+                                    grid with a factor per step size, Sec. IV-E): aging interval
+                                    k (ir_every steps, k = 0, 1, ...) steps with dt * dt_growth^k.
+                                    0 or 1: uniform.  The backward-Euler factors are rebuilt at
+                                    each change of step size.  Not with a learned screen attached
+                                    (its catch-up replay assumes uniform steps: EM_ERR_STATE).
+                                    em_stress_step always uses dt. */
 } em_run_params;
 
 /* Monte Carlo (Sec. IV-F): unit-mean lognormal multipliers with coefficient

@@ -511,6 +511,13 @@ static void refresh_dR(ora_state *S)
         }
 }
 
+/* Step size of the following ora_steps calls (a non-uniform time grid is a
+ * sequence of calls with their own dt; nothing here depends on a previous dt). */
+void ora_set_dt(ora_state *S, double dt)
+{
+    S->P.dt = dt;
+}
+
 /* Advance every active tree by n_steps backward-Euler steps starting at step
  * index step0.  After each step: grow existing voids, then test nucleation. */
 int ora_steps(ora_state *S, int n_steps, int step0)

@@ -66,7 +66,7 @@ def lib():
         for fn in ("ora_destroy", "ora_set_j", "ora_screen", "ora_set_active", "ora_steps",
                    "ora_get_sigma", "ora_set_sigma", "ora_get_node_arrays", "ora_get_seg_state",
                    "ora_get_voids", "ora_get_events", "ora_n_events", "ora_n_suppressed",
-                   "ora_inject_void"):
+                   "ora_inject_void", "ora_set_dt"):
             getattr(L, fn).argtypes = None
     return _lib
 
@@ -227,6 +227,9 @@ class SampleSim:
 
     def steps(self, n, step0=0):
         return lib().ora_steps(self._h, C.c_int(n), C.c_int(step0))
+
+    def set_dt(self, dt):
+        lib().ora_set_dt(self._h, C.c_double(dt))
 
     def sigma(self):
         s = np.zeros(self.topo.n_stress)
@@ -391,6 +394,9 @@ def run_sample(grid, mat, run, mc=None, sample=0, topo=None, keep_sim=False, max
             sim.set_active(tm)
             res["tree_mortal"], res["seg_mortal"] = tm, sm
         fail = float(run["fail_frac"])
+        # time grid: interval k (ir_every steps) steps with dt * dt_growth^k
+        growth = float(run.get("dt_growth", 0.0)) or 1.0
+        t_now = 0.0
         t_prev, d_prev = 0.0, d0
         done = 0
         res.update(ttf=float("nan"), failed=0, outer_idx=0, final_drop=d0)
@@ -402,14 +408,17 @@ def run_sample(grid, mat, run, mc=None, sample=0, topo=None, keep_sim=False, max
             while done < n_steps:
                 if max_outer is not None and k >= max_outer:
                     break
+                dt_k = float(run["dt"]) * growth ** k
                 k += 1
                 nst = min(K, n_steps - done)
+                sim.set_dt(dt_k)
                 sim.steps(nst, done)
                 done += nst
+                t_now += nst * dt_k
                 dR, op = sim.seg_state()
                 u, I, j, dk = ir_solve(gs, R0 + dR, op)
                 drops.append(dk)
-                t = done * float(run["dt"])
+                t = t_now
                 res["final_drop"] = dk
                 res["outer_idx"] = k
                 if dk >= fail:

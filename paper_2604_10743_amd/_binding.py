@@ -67,7 +67,8 @@ class RunParams(C.Structure):
                 ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32), ("prec", C.c_int32),
                 ("screen", C.c_int32), ("max_voids_per_tree", C.c_int32), ("T_ambient", C.c_double),
                 ("stepper", C.c_int32), ("ir_precond", C.c_int32), ("ir_launch", C.c_int32),
-                ("chain_wg", C.c_int32), ("chain_occ", C.c_int32), ("joule", C.c_int32)]
+                ("chain_wg", C.c_int32), ("chain_occ", C.c_int32), ("joule", C.c_int32),
+                ("dt_growth", C.c_double)]
 
 
 class MCParams(C.Structure):
@@ -207,7 +208,7 @@ class Batch:
                       ir_precond=int(run.get("ir_precond", 2)),
                       ir_launch=int(run.get("ir_launch", 0)), chain_wg=int(run.get("chain_wg", 0)),
                       chain_occ=int(run.get("chain_occ", 0)),
-                      joule=int(run.get("joule", 0)))
+                      joule=int(run.get("joule", 0)), dt_growth=float(run.get("dt_growth", 0.0)))
         mcp = None
         if mc is not None:
             mcp = MCParams(struct_size=C.sizeof(MCParams), n_samples=int(mc["n_samples"]),

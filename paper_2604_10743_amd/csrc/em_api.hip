@@ -303,7 +303,8 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
         r->cg_max_iter < 1 || !(r->cg_rtol > 0) || (r->prec != EM_FP64 && r->prec != EM_FP32) ||
         r->max_voids_per_tree < 0 || r->max_voids_per_tree > MAXV || !(r->T_ambient > 0) ||
         r->stepper < 0 || r->stepper > 1 || r->ir_precond < 0 || r->ir_precond > 2 ||
-        r->ir_launch < 0 || r->ir_launch > 3 || r->joule < 0 || r->joule > 1)
+        r->ir_launch < 0 || r->ir_launch > 3 || r->joule < 0 || r->joule > 1 ||
+        !(r->dt_growth >= 0) || !std::isfinite(r->dt_growth))
         return fail(b, EM_ERR_ARG, "bad run parameters (max_voids_per_tree <= 4)");
     if (r->joule) {
         const double tv[] = {m->k_cu, m->k_ild, m->t_ild};
@@ -1377,10 +1378,34 @@ em_status em_stress_step(em_batch *b, int32_t n_steps, int32_t *n_events)
     return EM_OK;
 }
 
+// Step size of aging interval k of em_run_to_ttf (geometric time grid).
+static double interval_dt(const em_batch *b, int k)
+{
+    const double g = b->run.dt_growth > 0 ? b->run.dt_growth : 1.0;
+    return g == 1.0 ? b->run.dt : b->run.dt * std::pow(g, (double)k);
+}
+
+// A new backward-Euler step size: the generic kernel's factors and dt * f
+// follow (the chain kernel factors at every launch from the step size it is
+// given).
+static em_status set_step_size(em_batch *b, double dt)
+{
+    if (b->d.dt == dt) return EM_OK;
+    b->d.dt = dt;
+    HIPCHK(b, hipMemcpyAsync(b->d_dev, &b->d, sizeof(Dev), hipMemcpyHostToDevice, b->stream));
+    launch_factor(b->d, b->fp32, b->stream);
+    LAUNCHCHK(b);
+    b->forcing_stale = true;
+    return EM_OK;
+}
+
 em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
 {
     if (!b || !out) return fail(b, EM_ERR_ARG, "null output");
     if (b->trees_only) return fail(b, EM_ERR_STATE, "trees-only batch has no IR coupling");
+    const bool graded = b->run.dt_growth > 0 && b->run.dt_growth != 1.0;
+    if (graded && b->sur)
+        return fail(b, EM_ERR_STATE, "a graded time grid cannot be combined with the learned screen");
     Dev &d = b->d;
     hipStream_t st = b->stream;
     const int S = b->S;
@@ -1411,6 +1436,7 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
     unsigned int *hcnt = (unsigned int *)(h + cnt_off);
     unsigned int n_activated = 0;
     int done = 0, k = 0;
+    double t_now = 0.0;                   // time at the end of the last interval
     while (done < n_steps) {
         if (sur) {
             HIPCHK(b, hipMemcpyAsync(b->jhist + (size_t)k * S * b->n_res, d.jseg, 8 * (size_t)S * b->n_res,
@@ -1446,19 +1472,23 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
             if (rc != EM_OK) return rc;
         }
         int nst = std::min(K, n_steps - done);
+        const double dt_k = interval_dt(b, k);
+        if ((rc = set_step_size(b, dt_k)) != EM_OK) return rc;
         rc = timed_step(b, nst, done);
         if (rc != EM_OK) return rc;
         done += nst;
+        t_now += nst * dt_k;
         ++k;
         rc = sync_open_dirty(b);
         if (rc != EM_OK) return rc;
         fold_timers(b);
         rc = timed_ir(b);
         if (rc != EM_OK) return rc;
-        launch_ttf_update(d, fail_frac, k, done * b->run.dt, st);
+        launch_ttf_update(d, fail_frac, k, graded ? t_now : done * b->run.dt, st);
         LAUNCHCHK(b);
     }
     b->n_outer_done = k;
+    if ((rc = set_step_size(b, b->run.dt)) != EM_OK) return rc;   // em_stress_step steps with dt
     // per-sample results
     std::vector<double> ttf(S), fd(S), idr(S);
     std::vector<int> failed(S), oidx(S), cnt(2 * (size_t)S);
@@ -1508,6 +1538,10 @@ em_status em_reset(em_batch *b)
         HIPCHK(b, hipMemsetAsync(d.sur_cnt, 0, 32, st));
     }
     b->n_def_list = 0;
+    if (d.dt != b->run.dt) {               // a graded run left its last step size
+        d.dt = b->run.dt;
+        HIPCHK(b, hipMemcpyAsync(b->d_dev, &d, sizeof(Dev), hipMemcpyHostToDevice, st));
+    }
     launch_fill_f64(d.u, VS, d.vdd, st);
     launch_set_sigma_T(d, b->fp32, st);
     launch_factor(d, b->fp32, st);

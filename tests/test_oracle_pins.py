@@ -143,6 +143,40 @@ def test_be_exact_discrete_modes(oracle_mod):
         assert np.max(np.abs(got - expect)) / np.max(np.abs(sig_ss)) < 1e-11
 
 
+def test_be_exact_discrete_modes_variable_step(oracle_mod):
+    # a non-uniform time grid: each block of steps with its own dt multiplies
+    # mode k by (1 + dt_m lambda_k)^-n_m
+    S, N, Lseg, j = 4, 16, 10e-6, 2e10
+    g = line_grid(S=S, L=Lseg, j=j)
+    mat = material(sigma_crit=1e30)
+    kap, *_ = _kappa_from_oracle(oracle_mod, g, mat, run(intervals_per_seg=N))
+    Ltot = S * Lseg
+    tau = Ltot ** 2 / (math.pi ** 2 * kap)
+    rn = run(dt=tau / 200, max_voids_per_tree=0, intervals_per_seg=N)
+    topo = oracle_mod.topology(g, N)
+    sim = oracle_mod.SampleSim(g, mat, rn, topo)
+    sim.set_j(g.seg_j)
+    n = S * N
+    dx = Ltot / n
+    x = np.arange(n + 1) * dx
+    sig_ss = E * 1.0 * 2.25e-8 * j / 1.18e-29 * (x - Ltot / 2)
+    Vw = np.full(n + 1, 1.0); Vw[0] = Vw[-1] = 0.5
+    k = np.arange(n + 1)
+    lam = 4 * kap / dx ** 2 * np.sin(k * np.pi / (2 * n)) ** 2
+    modes = np.cos(np.outer(k, np.arange(n + 1)) * np.pi / n)
+    c = (modes * Vw) @ (-sig_ss) / ((modes ** 2) @ Vw)
+    decay = np.ones(n + 1)
+    done = 0
+    for m, nsteps in enumerate((3, 5, 8, 13)):
+        dt_m = tau / 200 * 1.7 ** m
+        sim.set_dt(dt_m)
+        sim.steps(nsteps, done)
+        done += nsteps
+        decay *= (1 + dt_m * lam) ** (-nsteps)
+        expect = sig_ss + (c * decay) @ modes
+        assert np.max(np.abs(sim.sigma() - expect)) / np.max(np.abs(sig_ss)) < 1e-11
+
+
 def test_be_converges_to_korhonen_series(oracle_mod):
     # continuous solution of eqs. 11-13 for a blocked line under constant j:
     # sigma(L,t) = (S L/2)[1 - (8/pi^2) sum_odd exp(-n^2 pi^2 kappa t/L^2)/n^2]
