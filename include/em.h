@@ -60,7 +60,8 @@ typedef enum { EM_FP64 = 0, EM_FP32 = 1 } em_precision;
  * else per-node node_T (interior FD points interpolate along the segment),
  * else the uniform em_run_params.T_ambient.  seg_j != NULL switches the batch
  * to trees-only mode: per-resistor current density prescribed (A/m^2, signed
- * along res_a -> res_b), no IR solve and no time-to-failure. */
+ * along res_a -> res_b), no IR solve and no time-to-failure.  A netlist
+ * without any wire segment is rejected (EM_ERR_ARG). */
 typedef struct {
     uint32_t struct_size;           /* sizeof(em_grid_desc) */
     int32_t n_nodes;

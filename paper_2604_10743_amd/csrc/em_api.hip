@@ -270,15 +270,18 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
     if (g->n_nodes <= 0 || g->n_res <= 0 || !g->xy || !g->layer || !g->res_a || !g->res_b ||
         !g->res_len || !g->res_w || !g->res_h || !g->res_is_via || !g->res_R0)
         return fail(b, EM_ERR_ARG, "netlist arrays missing or empty");
+    int n_wire = 0;
     for (int i = 0; i < g->n_res; ++i) {
         int a = g->res_a[i], c = g->res_b[i];
         if (a < 0 || a >= g->n_nodes || c < 0 || c >= g->n_nodes) return fail(b, EM_ERR_ARG, "resistor node out of range");
         bool wire = !g->res_is_via[i] && g->layer[a] == g->layer[c];
+        n_wire += wire ? 1 : 0;
         if (!(g->res_R0[i] > 0) || !std::isfinite(g->res_R0[i])) return fail(b, EM_ERR_ARG, "R0 must be positive and finite");
         if (wire && (!(g->res_len[i] > 0) || !(g->res_w[i] > 0) || !(g->res_h[i] > 0) ||
                      !std::isfinite(g->res_len[i]) || !std::isfinite(g->res_w[i]) || !std::isfinite(g->res_h[i])))
             return fail(b, EM_ERR_ARG, "wire geometry must be positive and finite");
     }
+    if (n_wire == 0) return fail(b, EM_ERR_ARG, "no wire segment (every resistor is a via): nothing to age");
     if (!finite_all(g->xy, 2 * (size_t)g->n_nodes)) return fail(b, EM_ERR_ARG, "non-finite coordinates");
     if (g->node_T && !finite_all(g->node_T, g->n_nodes)) return fail(b, EM_ERR_ARG, "non-finite node_T");
     if (g->tmap) {
