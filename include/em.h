@@ -144,7 +144,10 @@ typedef struct {
                                     (the smallest of 256, 512, 1024 that holds the longest chain
                                     tree), or one of those (at most 512 in FP64) that holds it.
                                     Results do not depend on it (instances never share a
-                                    reduction: the couplings across their boundaries are zero). */
+                                    reduction: the couplings across their boundaries are zero),
+                                    except that the FP32 1024-lane form keeps no low part of the
+                                    stress state (no registers for it) and agrees with the
+                                    others to float rounding of the state. */
     int32_t chain_occ;           /* register budget of the resident chain kernel: 0 or 1 as many
                                     registers as it uses (one or two workgroups per compute unit);
                                     4 at most 128 VGPRs (four waves per SIMD: four 256-lane or two
