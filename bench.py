@@ -37,6 +37,25 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def _oracle_trees_worker(job):
+    """One host process of the all-core oracle baseline: the pg400 grid, the
+    nominal currents j, 100 BE steps of trees [t0, t1); returns node-steps."""
+    t0, t1, j, n_steps = job
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    from oracle import oracle as O
+    from paper_2604_10743_amd import synth
+    g, mat, run, _ = synth.workload("pg400_fp64")
+    topo = O.topology(g, run["intervals_per_seg"])
+    sim = O.SampleSim(g, mat, run, topo)
+    sim.set_j(j)
+    act = np.zeros(topo.n_trees, np.uint8)
+    act[t0:t1] = 1
+    sim.set_active(act)
+    sim.steps(n_steps, 0)
+    return int(topo.tree_off[t1] - topo.tree_off[t0]) * n_steps
+
+
 def measured_traffic(kernel_src: str, profile_md: str):
     """HBM bytes per launch from the committed PMC summary, or None when the
     kernel source changed since the counters were taken."""
@@ -469,6 +488,23 @@ def main():
                                          f"first {n_tr} of {topo.n_trees} trees ({ns_c} node-steps), "
                                          f"{tc:.1f} s incl. setup"}
         log("bench: cpu baseline done")
+        # the same oracle on every host core: the trees split over processes
+        # (spawned: no GPU state in them), each building the grid itself
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        n_proc = max(1, min(16, os.cpu_count() or 1))
+        bounds = np.linspace(0, topo.n_trees, n_proc + 1).astype(int)
+        jobs = [(int(bounds[k]), int(bounds[k + 1]), j, run["ir_every"]) for k in range(n_proc)
+                if bounds[k + 1] > bounds[k]]
+        t0 = time.perf_counter()
+        with cf.ProcessPoolExecutor(max_workers=len(jobs), mp_context=mp.get_context("spawn")) as ex:
+            ns_all = sum(ex.map(_oracle_trees_worker, jobs))
+        ta = time.perf_counter() - t0
+        out["cpu_baseline"]["all_cores"] = {
+            "value": ns_all / ta, "unit": "node-steps/s", "cores": len(jobs),
+            "sample": f"pg400, FP64 oracle, {run['ir_every']} BE steps of all {topo.n_trees} trees split over "
+                      f"{len(jobs)} processes ({ns_all} node-steps), {ta:.1f} s incl. each process's setup"}
+        log("bench: cpu baseline (all cores) done")
     print(json.dumps(out), flush=True)
 
 
