@@ -92,3 +92,34 @@ def test_bad_variation_is_rejected(em):
     for bad in (dict(cov_rho=-0.1), dict(cov_load=float("nan"))):
         with pytest.raises(em.EmError):
             em.Batch(g, mat, rn, dict(mc, n_samples=2, **bad))
+
+
+def test_trees_only_resistivity_variation_matches_oracle(em, oracle_mod):
+    # prescribed currents: the sampled resistivity scales each segment's
+    # electron-wind drive, so the screen and the stress differ per sample
+    g, mat, rn, _ = synth.workload("tiny_trees")
+    rn = dict(rn, screen=1)
+    mc = dict(n_samples=6, seed=17, cov_kappa=0.2, cov_scrit=0.2, cov_rho=0.15, cov_load=0.0)
+    print("mc inputs: trees-only resistivity", flush=True)
+    B = em.Batch(g, mat, rn, mc)
+    tm = B.screen()                               # applied: immortal instances are not stepped
+    B.stress_step(rn["n_steps"])
+    ev = B.events()
+    topo = oracle_mod.topology(g, rn["intervals_per_seg"])
+    n_diff = 0
+    for s in range(6):
+        ref = oracle_mod.run_sample(g, mat, rn, mc, s, topo=topo)
+        assert np.array_equal(tm[s], ref["tree_mortal"]), s
+        n_diff += int(not np.array_equal(tm[s], tm[0]))
+        got = B.stress(s)
+        for t in range(topo.n_trees):
+            i0, i1 = topo.tree_off[t], topo.tree_off[t + 1]
+            scale = np.max(np.abs(ref["sigma"][i0:i1])) or 1.0
+            assert np.max(np.abs(got[i0:i1] - ref["sigma"][i0:i1])) <= 1e-9 * scale, (s, t)
+        mine = ev[ev[:, 0] == s][:, [1, 2, 3]]
+        mine = mine[np.lexsort(mine.T[::-1])]
+        theirs = np.asarray(ref["events"])[:, [0, 1, 2]]
+        theirs = theirs[np.lexsort(theirs.T[::-1])]
+        assert np.array_equal(mine, theirs), s
+    B.close()
+    assert n_diff >= 1                            # the verdicts differ between samples
