@@ -184,7 +184,12 @@ typedef struct {
  *   param 2  resistivity, per wire segment: the segment's resistance R0, its
  *            electron-wind drive (eZ rho j / Omega) and the copper term of the
  *            liner resistance change (eq. 17) scale with it; vias keep R0;
- *   param 3  current loading, per node: the node's sink current scales with it.
+ *   param 3  current loading, per node: the node's sink current scales with it;
+ *   param 4  activation energy, per wire segment: an offset dEa ~ N(0, sd_ea_eV)
+ *            (standard normal from the same counter and Box-Muller branch)
+ *            multiplies the segment's diffusivity by exp(-dEa / (k_B T)), T the
+ *            map temperature at the segment's midpoint (T_ambient without
+ *            thermal data); the factor joins the kappa multiplier.
  * The paper's study perturbs kappa and sigma_crit; resistivity and loading are
  * two of the further sampled inputs it names for the same flow.  With
  * cov_rho = cov_load = 0 every sample starts on the nominal network. */
@@ -194,6 +199,7 @@ typedef struct {
     uint64_t seed;
     double cov_kappa, cov_scrit;
     double cov_rho, cov_load;
+    double sd_ea_eV;             /* activation-energy spread, eV, 0 <= sd < 1 */
 } em_mc_params;
 
 typedef struct {
@@ -337,7 +343,8 @@ em_status em_get_screen(em_batch *b, int32_t sample, uint8_t *tree_mortal, uint8
 /* Test hook: place a void at stress node `node` of `tree` in `sample` as a
  * nucleation there would (host segment and failure mode chosen the same way). */
 em_status em_inject_void(em_batch *b, int32_t sample, int32_t tree, int32_t node);
-/* Monte Carlo multipliers of one sample: param 0 kappa, 1 sigma_crit, 2 resistivity
+/* Monte Carlo multipliers of one sample: param 0 kappa (with the activation-energy
+ * factor when sd_ea_eV > 0), 1 sigma_crit, 2 resistivity
  * (xi [n_res]; 1 for vias and where the CoV is 0), 3 current loading (xi [n_nodes]). */
 em_status em_get_xi(em_batch *b, int32_t sample, int32_t param, double *xi);
 /* Failed segments of one sample (dR > 0 or open; the set counted by

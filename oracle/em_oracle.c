@@ -231,6 +231,24 @@ void ora_fill_xi(uint64_t seed, int sample, int n_seg, int param, double cov, do
     for (int e = 0; e < n_seg; ++e) out[e] = ora_lognormal_xi(seed, sample, e, param, cov);
 }
 
+/* Standard normal deviate of counter (index, sample, param, 0): the same
+ * Box-Muller branch as above, without the lognormal map. */
+double ora_normal_z(uint64_t seed, int sample, int index, int param)
+{
+    uint32_t ctr[4] = {(uint32_t)index, (uint32_t)sample, (uint32_t)param, 0u};
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    ora_philox4x32_10(ctr, key, x);
+    double u1 = ((double)x[0] + 1.0) * (1.0 / 4294967296.0);
+    double u2 = (double)x[1] * (1.0 / 4294967296.0);
+    return sqrt(-2.0 * log(u1)) * cos(2.0 * ORA_PI * u2);
+}
+
+void ora_fill_normal(uint64_t seed, int sample, int n, int param, double *out)
+{
+    for (int e = 0; e < n; ++e) out[e] = ora_normal_z(seed, sample, e, param);
+}
+
 /* ======================================================================== */
 /* One sample's state.                                                      */
 /* ======================================================================== */

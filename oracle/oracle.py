@@ -63,6 +63,9 @@ def lib():
         L.ora_lognormal_xi.restype = C.c_double
         L.ora_lognormal_xi.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_double]
         L.ora_fill_xi.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_double, C.c_void_p]
+        L.ora_normal_z.restype = C.c_double
+        L.ora_normal_z.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_int]
+        L.ora_fill_normal.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_void_p]
         for fn in ("ora_destroy", "ora_set_j", "ora_screen", "ora_set_active", "ora_steps",
                    "ora_get_sigma", "ora_set_sigma", "ora_get_node_arrays", "ora_get_seg_state",
                    "ora_get_voids", "ora_get_events", "ora_n_events", "ora_n_suppressed",
@@ -181,6 +184,14 @@ def lognormal_xi(seed: int, sample: int, n_seg: int, param: int, cov: float) -> 
     L = lib()
     out = np.zeros(n_seg)
     L.ora_fill_xi(C.c_uint64(seed), sample, n_seg, param, C.c_double(cov), _p(out))
+    return out
+
+
+def normal_z(seed: int, sample: int, n: int, param: int) -> np.ndarray:
+    """Standard normal deviates of counters (0..n-1, sample, param, 0)."""
+    L = lib()
+    out = np.zeros(n)
+    L.ora_fill_normal(C.c_uint64(seed), sample, n, param, _p(out))
     return out
 
 
@@ -324,12 +335,26 @@ def ir_solve(grid, R, open_mask=None):
 # ----------------------------------------------------------------------------
 # Full pipeline for one sample
 # ----------------------------------------------------------------------------
-def sample_xi(grid, mc, sample):
-    """Diffusivity and critical-stress multipliers of one sample, per segment."""
+K_B_EV = 1.380649e-23 / 1.602176634e-19        # Boltzmann constant, eV/K
+
+
+def sample_xi(grid, mc, sample, T_amb=300.0):
+    """Diffusivity and critical-stress multipliers of one sample, per segment.
+
+    An activation-energy spread sd_ea_eV > 0 draws dEa ~ N(0, sd) per wire
+    segment (param 4); the diffusivity D0 exp(-(Ea + dEa)/(k_B T)) then carries
+    the extra factor exp(-dEa/(k_B T)), taken at the segment midpoint's map
+    temperature and folded into the diffusivity multiplier."""
     if mc is None:
         return None, None
-    return (lognormal_xi(mc["seed"], sample, grid.n_res, 0, mc["cov_kappa"]),
-            lognormal_xi(mc["seed"], sample, grid.n_res, 1, mc["cov_scrit"]))
+    xi_k = lognormal_xi(mc["seed"], sample, grid.n_res, 0, mc["cov_kappa"])
+    sd = float(mc.get("sd_ea_eV", 0.0))
+    if sd > 0:
+        wire = (grid.res_is_via == 0) & (grid.layer[grid.res_a] == grid.layer[grid.res_b])
+        z = normal_z(mc["seed"], sample, grid.n_res, 4)
+        for e in np.nonzero(wire)[0]:
+            xi_k[e] *= np.exp(-sd * z[e] / (K_B_EV * thermal.midpoint_map_T(grid, T_amb, int(e))))
+    return xi_k, lognormal_xi(mc["seed"], sample, grid.n_res, 1, mc["cov_scrit"])
 
 
 def sample_inputs(grid, mc, sample):
@@ -356,7 +381,7 @@ def run_sample(grid, mat, run, mc=None, sample=0, topo=None, keep_sim=False, max
     init_drop, final_drop, failed_segs, n_nucleated_trees, events, sigma."""
     N = int(run["intervals_per_seg"])
     topo = topo or topology(grid, N)
-    xi_k, xi_s = sample_xi(grid, mc, sample)
+    xi_k, xi_s = sample_xi(grid, mc, sample, float(run.get("T_ambient", 300.0)))
     xi_r, R0, sinks = sample_inputs(grid, mc, sample)
     trees_only = grid.seg_j is not None
     gs = grid

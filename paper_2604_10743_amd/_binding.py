@@ -74,7 +74,7 @@ class RunParams(C.Structure):
 class MCParams(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("n_samples", C.c_int32), ("seed", C.c_uint64),
                 ("cov_kappa", C.c_double), ("cov_scrit", C.c_double), ("cov_rho", C.c_double),
-                ("cov_load", C.c_double)]
+                ("cov_load", C.c_double), ("sd_ea_eV", C.c_double)]
 
 
 class TTFResult(C.Structure):
@@ -214,7 +214,7 @@ class Batch:
             mcp = MCParams(struct_size=C.sizeof(MCParams), n_samples=int(mc["n_samples"]),
                            seed=int(mc["seed"]), cov_kappa=float(mc["cov_kappa"]),
                            cov_scrit=float(mc["cov_scrit"]), cov_rho=float(mc.get("cov_rho", 0.0)),
-                           cov_load=float(mc.get("cov_load", 0.0)))
+                           cov_load=float(mc.get("cov_load", 0.0)), sd_ea_eV=float(mc.get("sd_ea_eV", 0.0)))
         self._alloc = None
         if torch_alloc:
             dev = torch.cuda.current_device()

@@ -22,7 +22,7 @@ struct em_batch {
     em_run_params run;
     int S = 1;
     uint64_t seed = 0;
-    double cov_k = 0, cov_s = 0, cov_r = 0, cov_l = 0;
+    double cov_k = 0, cov_s = 0, cov_r = 0, cov_l = 0, sd_ea = 0;
     bool trees_only = false;
     bool fp32 = false;
     hipStream_t stream = nullptr;
@@ -316,7 +316,8 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
     }
     if (mc && (mc->n_samples < 1 || mc->n_samples > 65535 || mc->cov_kappa < 0 || mc->cov_scrit < 0 || !std::isfinite(mc->cov_kappa) ||
                !std::isfinite(mc->cov_scrit) || !(mc->cov_rho >= 0) || !(mc->cov_load >= 0) ||
-               !std::isfinite(mc->cov_rho) || !std::isfinite(mc->cov_load)))
+               !std::isfinite(mc->cov_rho) || !std::isfinite(mc->cov_load) || !(mc->sd_ea_eV >= 0) ||
+               !(mc->sd_ea_eV < 1.0)))
         return fail(b, EM_ERR_ARG, "bad Monte Carlo parameters");
     return EM_OK;
 }
@@ -891,6 +892,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     b->trees_only = g->seg_j != nullptr;
     b->cov_r = mc ? mc->cov_rho : 0.0;
     b->cov_l = (mc && !b->trees_only) ? mc->cov_load : 0.0;     // no sinks in trees-only mode
+    b->sd_ea = mc ? mc->sd_ea_eV : 0.0;
     b->fp32 = r->prec == EM_FP32;
     b->stream = (hipStream_t)hip_stream;
     if (alloc && alloc->alloc && alloc->free) { b->alloc = *alloc; b->has_alloc = true; }
@@ -1249,7 +1251,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     launch_node_T(d, stq);
     launch_edge_static(d, stq);
     launch_node_V(d, b->fp32, stq);
-    launch_draws(d, b->seed, b->cov_k, b->cov_s, b->cov_r, b->cov_l, stq);
+    launch_draws(d, b->seed, b->cov_k, b->cov_s, b->cov_r, b->cov_l, b->sd_ea, stq);
     b->nominal = !d.xi_r && !d.sink_s;
     launch_node_sc(d, b->fp32, stq);
     launch_set_sigma_T(d, b->fp32, stq);

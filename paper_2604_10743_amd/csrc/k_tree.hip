@@ -274,24 +274,36 @@ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
     }
 }
 
-__device__ inline double lognormal_xi(uint64_t seed, int sample, int segment, int param, double cov)
+// standard normal deviate of counter (index, sample, param, 0)
+__device__ inline double normal_z(uint64_t seed, int sample, int index, int param)
 {
-    if (cov == 0.0) return 1.0;
-    uint32_t c[4] = {(uint32_t)segment, (uint32_t)sample, (uint32_t)param, 0u};
+    uint32_t c[4] = {(uint32_t)index, (uint32_t)sample, (uint32_t)param, 0u};
     philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
     double u1 = ((double)c[0] + 1.0) * (1.0 / 4294967296.0);
     double u2 = (double)c[1] * (1.0 / 4294967296.0);
-    double z = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+    return sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+
+__device__ inline double lognormal_xi(uint64_t seed, int sample, int segment, int param, double cov)
+{
+    if (cov == 0.0) return 1.0;
+    const double z = normal_z(seed, sample, segment, param);
     double s2 = log(1.0 + cov * cov);
     return exp(-0.5 * s2 + sqrt(s2) * z);
 }
 
-EM_KERNEL void k_draws(Dev d, uint64_t seed, double cov_k, double cov_s, double cov_r, int use_mc)
+// The activation-energy offset dEa ~ N(0, sd_ea) of a wire segment (param 4)
+// scales its diffusivity by exp(-dEa / (k_B T)), T the map temperature at the
+// segment's midpoint; it joins the kappa multiplier.
+EM_KERNEL void k_draws(Dev d, uint64_t seed, double cov_k, double cov_s, double cov_r, double sd_ea, int use_mc)
 {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long long)d.n_res * d.S) return;
     int s = (int)(g % d.S), e = (int)(g / d.S);
-    d.xi_k[g] = use_mc ? lognormal_xi(seed, s, e, 0, cov_k) : 1.0;
+    double xk = use_mc ? lognormal_xi(seed, s, e, 0, cov_k) : 1.0;
+    if (sd_ea > 0.0 && d.is_wire[e])
+        xk *= exp(-sd_ea * normal_z(seed, s, e, 4) / ((K_B / E_CHG) * map_T_mid(d, e)));
+    d.xi_k[g] = xk;
     d.xi_s[g] = use_mc ? lognormal_xi(seed, s, e, 1, cov_s) : 1.0;
     if (d.xi_r) d.xi_r[g] = d.is_wire[e] ? lognormal_xi(seed, s, e, 2, cov_r) : 1.0;
 }
@@ -1165,10 +1177,10 @@ void launch_node_V(const Dev &d, bool fp32, hipStream_t st)
     k_tree_V<<<nblocks(d.n_trees, 4), 256, 0, st>>>(d);
 }
 void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, double cov_r, double cov_l,
-                  hipStream_t st)
+                  double sd_ea, hipStream_t st)
 {
     int use = (cov_k != 0.0 || cov_s != 0.0) ? 1 : 0;
-    k_draws<<<nblocks((long long)d.n_res * d.S), 256, 0, st>>>(d, seed, cov_k, cov_s, cov_r, use);
+    k_draws<<<nblocks((long long)d.n_res * d.S), 256, 0, st>>>(d, seed, cov_k, cov_s, cov_r, sd_ea, use);
     if (d.sink_s) k_draws_load<<<nblocks((long long)d.n_nodes * d.S), 256, 0, st>>>(d, seed, cov_l);
 }
 // grid of one block row per node (rows beyond 65535 folded into z) and the

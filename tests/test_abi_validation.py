@@ -93,6 +93,8 @@ CASES = {
     "bad Monte Carlo (samples)": lambda g, m, r, mc: mc.__setitem__("n_samples", 0),
     "bad Monte Carlo (cov)": lambda g, m, r, mc: mc.__setitem__("cov_kappa", -0.1),
     "bad Monte Carlo (rho)": lambda g, m, r, mc: mc.__setitem__("cov_rho", math.nan),
+    "bad Monte Carlo (Ea spread)": lambda g, m, r, mc: mc.__setitem__("sd_ea_eV", -0.01),
+    "bad Monte Carlo (Ea spread, huge)": lambda g, m, r, mc: mc.__setitem__("sd_ea_eV", 2.0),
 }
 
 

@@ -1,7 +1,7 @@
-"""Monte Carlo over resistivity and current loading (Sec. IV-F sampled inputs)
-on the GPU against the FP64 oracle: the draws, the per-sample initial IR
-solve, full runs to time-to-failure (FP64 and FP32), and the Joule pre-pass
-still taking the nominal network's currents."""
+"""Monte Carlo over resistivity, current loading and activation energy
+(Sec. IV-F sampled inputs) on the GPU against the FP64 oracle: the draws, the
+per-sample initial IR solve, full runs to time-to-failure (FP64 and FP32),
+and the Joule pre-pass still taking the nominal network's currents."""
 import numpy as np
 import pytest
 
@@ -123,3 +123,33 @@ def test_trees_only_resistivity_variation_matches_oracle(em, oracle_mod):
         assert np.array_equal(mine, theirs), s
     B.close()
     assert n_diff >= 1                            # the verdicts differ between samples
+
+
+def test_activation_energy_draws_and_runs_match_oracle(em, oracle_mod):
+    # dEa ~ N(0, 0.01 eV) per wire segment under the hotspot map
+    g, mat, rn, mc = synth.workload("mc_grid")
+    S = 24
+    mc = dict(mc, n_samples=S, sd_ea_eV=0.01)
+    rn = dict(rn, prec=0)
+    print("mc inputs: activation energy", flush=True)
+    B = em.Batch(g, mat, rn, mc)
+    for s in (0, 5, 23):
+        xk, xs = oracle_mod.sample_xi(g, mc, s, T_amb=rn["T_ambient"])
+        assert np.allclose(B.xi(s, 0), xk, rtol=1e-13, atol=0), s
+        assert np.allclose(B.xi(s, 1), xs, rtol=1e-13, atol=0), s
+    res = B.run_to_ttf()
+    segs = {s: B.failed_segments(s) for s in range(0, S, 3)}
+    B.close()
+    topo = oracle_mod.topology(g, rn["intervals_per_seg"])
+    n_fail = 0
+    for s in range(0, S, 3):
+        ref = oracle_mod.run_sample(g, mat, rn, mc, s, topo=topo)
+        r = res[s]
+        n_fail += ref["failed"]
+        assert r["failed"] == ref["failed"], s
+        assert abs(r["final_drop"] - ref["final_drop"]) <= 1e-6 * ref["final_drop"], s
+        if ref["failed"]:
+            assert abs(r["ttf_s"] - ref["ttf"]) <= 1e-6 * ref["ttf"], s
+            assert r["outer_idx"] == ref["outer_idx"], s
+        assert np.array_equal(segs[s], ref["failed_segs"]), s
+    assert n_fail >= 1

@@ -81,3 +81,57 @@ def test_liner_formula_takes_sampled_resistivity(oracle_mod):
     for xi in (0.8, 1.0, 1.25):
         hand = (l - W) * (rho_ta / (h_ta * (2 * H + W)) - rho * xi / (W * H))
         assert abs(f(l, W, H, h_ta, rho_ta, rho * xi) - hand) <= 1e-12 * abs(hand)
+
+
+def test_param4_normal_draw_statistics_and_counter(oracle_mod):
+    # Box-Muller normals: moments and a Kolmogorov-Smirnov distance against
+    # the normal CDF; the deviate is the one the lognormal of the same
+    # counter maps (xi = exp(-s2/2 + sqrt(s2) z))
+    z = oracle_mod.normal_z(4242, 9, 200000, 4)
+    n = z.size
+    assert abs(z.mean()) < 4 / math.sqrt(n) and abs(z.std() - 1.0) < 0.01
+    zs = np.sort(z)
+    cdf = 0.5 * (1.0 + np.array([math.erf(v / math.sqrt(2.0)) for v in zs[::50]]))
+    emp = (np.arange(0, n, 50) + 1) / n
+    assert np.max(np.abs(cdf - emp)) < 1.6 / math.sqrt(n) + 50 / n
+    s2 = math.log(1.0 + 0.3 ** 2)
+    xi = oracle_mod.lognormal_xi(4242, 9, 1000, 4, 0.3)
+    assert np.allclose((np.log(xi) + 0.5 * s2) / math.sqrt(s2), z[:1000], rtol=0, atol=1e-12)
+
+
+def test_activation_energy_offset_is_an_arrhenius_factor(oracle_mod):
+    # D = D0 exp(-(Ea + dEa)/(k_B T)): the diffusivity multiplier changes by
+    # exactly D(Ea + dEa)/D(Ea) per wire segment, vias untouched; at uniform T
+    # the log-factor is normal with spread sd/(k_B T), mean exp((sd/k_B T)^2/2)
+    g = synth.pg_grid(11, n=24, via_every=8, pad_lattice=2, sink_scale=1.0, seg_range=(10, 23))
+    g = synth.Grid(**{**g.__dict__, "tmap": None, "node_T": None})
+    wire = (g.res_is_via == 0) & (g.layer[g.res_a] == g.layer[g.res_b])
+    kT = 1.380649e-23 * 350.0 / 1.602176634e-19
+    sd = 0.6 * kT
+    base = dict(seed=21, cov_kappa=0.2, cov_scrit=0.2)
+    k0, s0 = oracle_mod.sample_xi(g, base, 3, T_amb=350.0)
+    k1, s1 = oracle_mod.sample_xi(g, dict(base, sd_ea_eV=sd), 3, T_amb=350.0)
+    assert np.array_equal(s0, s1) and np.array_equal(k0[~wire], k1[~wire])
+    dEa = sd * oracle_mod.normal_z(21, 3, g.n_res, 4)[wire]
+    D = lambda Ea: np.exp(-Ea / kT)                          # Arrhenius at 350 K, D0 = 1
+    assert np.allclose(k1[wire] / k0[wire], D(0.85 + dEa) / D(0.85), rtol=1e-13)
+    f = k1[wire] / k0[wire]
+    assert abs(np.std(np.log(f)) - 0.6) < 0.08
+    assert abs(np.mean(f) / math.exp(0.18) - 1.0) < 0.1
+
+
+def test_activation_energy_factor_takes_the_midpoint_map_temperature(oracle_mod):
+    # hot segments (a hotspot map) see a smaller spread in log D: k_B T log f
+    # is -dEa whatever the temperature
+    g, mat, rn, mc = synth.workload("mc_grid")
+    assert g.tmap is not None
+    from oracle import thermal
+    sd = 0.01
+    k0, _ = oracle_mod.sample_xi(g, mc, 2, T_amb=rn["T_ambient"])
+    k1, _ = oracle_mod.sample_xi(g, dict(mc, sd_ea_eV=sd), 2, T_amb=rn["T_ambient"])
+    wire = np.nonzero((g.res_is_via == 0) & (g.layer[g.res_a] == g.layer[g.res_b]))[0]
+    T = np.array([thermal.midpoint_map_T(g, rn["T_ambient"], int(e)) for e in wire])
+    assert np.ptp(T) > 5.0
+    kB = 1.380649e-23 / 1.602176634e-19
+    dEa = -kB * T * np.log(k1[wire] / k0[wire])
+    assert np.allclose(dEa, sd * oracle_mod.normal_z(mc["seed"], 2, g.n_res, 4)[wire], rtol=0, atol=1e-15)
