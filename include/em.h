@@ -174,6 +174,13 @@ typedef struct {
                                     each change of step size.  Not with a learned screen attached
                                     (its catch-up replay assumes uniform steps: EM_ERR_STATE).
                                     em_stress_step always uses dt. */
+    int32_t chain_m;             /* stress nodes per lane of the resident chain kernel: 0
+                                    automatic, 8, or 9 (FP32 with 1024-lane workgroups only).
+                                    Automatic takes 8 unless every layout needs 1024-lane
+                                    workgroups (one per compute unit) and 9-node blocks pack the
+                                    chain instances into fewer rounds of the chip (rounds times
+                                    block length smaller).  Lanes hold whole blocks; results agree
+                                    to float rounding of the state. */
 } em_run_params;
 
 /* Monte Carlo (Sec. IV-F): unit-mean lognormal multipliers with coefficient
@@ -238,6 +245,9 @@ typedef struct {
     int32_t ir_sys_edges;  /* its resistors (or reduced edges) */
     int64_t cg_sample_iters; /* PCG iterations summed over samples (one-kernel form: counted in
                               blocks of the graph's iterations per unconverged sample) */
+    int32_t chain_m;       /* stress nodes per lane of the chain kernel */
+    int32_t chain_wg;      /* its lanes per workgroup */
+    int32_t n_chain_wg;    /* workgroups of its present lane layout */
 } em_info;
 
 /* Allocator hook: device memory for the batch (e.g. a framework's caching

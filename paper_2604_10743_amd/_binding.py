@@ -68,7 +68,7 @@ class RunParams(C.Structure):
                 ("screen", C.c_int32), ("max_voids_per_tree", C.c_int32), ("T_ambient", C.c_double),
                 ("stepper", C.c_int32), ("ir_precond", C.c_int32), ("ir_launch", C.c_int32),
                 ("chain_wg", C.c_int32), ("chain_occ", C.c_int32), ("joule", C.c_int32),
-                ("dt_growth", C.c_double)]
+                ("dt_growth", C.c_double), ("chain_m", C.c_int32)]
 
 
 class MCParams(C.Structure):
@@ -93,7 +93,8 @@ class Info(C.Structure):
                 ("n_deferred", C.c_int64), ("n_activated", C.c_int64), ("n_late", C.c_int64),
                 ("n_violations", C.c_int64),
                 ("surrogate_ms", C.c_double), ("ir_sys_nodes", C.c_int32), ("ir_sys_edges", C.c_int32),
-                ("cg_sample_iters", C.c_int64)]
+                ("cg_sample_iters", C.c_int64), ("chain_m", C.c_int32), ("chain_wg", C.c_int32),
+                ("n_chain_wg", C.c_int32)]
 
 
 class TuneInfo(C.Structure):
@@ -208,7 +209,8 @@ class Batch:
                       ir_precond=int(run.get("ir_precond", 2)),
                       ir_launch=int(run.get("ir_launch", 0)), chain_wg=int(run.get("chain_wg", 0)),
                       chain_occ=int(run.get("chain_occ", 0)),
-                      joule=int(run.get("joule", 0)), dt_growth=float(run.get("dt_growth", 0.0)))
+                      joule=int(run.get("joule", 0)), dt_growth=float(run.get("dt_growth", 0.0)),
+                      chain_m=int(run.get("chain_m", 0)))
         mcp = None
         if mc is not None:
             mcp = MCParams(struct_size=C.sizeof(MCParams), n_samples=int(mc["n_samples"]),

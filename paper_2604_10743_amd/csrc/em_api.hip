@@ -90,6 +90,7 @@ struct em_batch {
     std::vector<int> chain_L;           // lanes per instance of a chain tree (0: generic tree)
     std::vector<int> tree_perm_h;
     int chain_wg = 0;
+    int chain_m = 8;                    // stress nodes per lane of the chain kernel
     int chain_occ = 1;                  // chain kernel register budget: 1 default, 4 (128 VGPRs)
     bool psi_shared = false;            // steady stress of the last screen only in column 0 (shared screen)
     std::vector<int> wg_cand;           // chain workgroup sizes that hold the longest chain tree
@@ -561,32 +562,57 @@ em_status run_screen(em_batch *b, bool apply)
     return EM_OK;
 }
 
-// Lane layout of the chain kernel: instances of chain trees in tree_perm
-// order (samples consecutive), L lanes each, never straddling a workgroup of
-// cWG lanes; only the active ones when flags are given.  Returns the lane
-// count (whole workgroups) and, when asked, each placed instance's id, first
-// lane and lane count.
+// Lane layout of the chain kernel: instances of chain trees, L lanes each,
+// never straddling a workgroup of cWG lanes; only the active ones when flags
+// are given.  Best-fit decreasing: trees in tree_perm order (largest first),
+// each tree's instances go to the open workgroups with the fewest free lanes
+// that still hold one (as many per workgroup as fit), then to new ones.
+// Every workgroup runs the same number of steps in about the same time, so
+// fewer workgroups means fewer rounds of the chip.  Returns the lane count
+// (whole workgroups) and, when asked, each placed instance's id, first lane
+// and lane count.
 long long place_chain_lanes(const std::vector<int> &perm, const std::vector<int> &chain_L, int S, int cWG,
                             const uint8_t *ia, const uint8_t *sa, std::vector<int> *pi,
                             std::vector<long long> *po, std::vector<int> *pL)
 {
     if (pi) { pi->clear(); po->clear(); pL->clear(); }
-    long long n = 0;
-    int fill = 0;
+    std::vector<std::vector<int>> open(cWG + 1);     // open[c]: workgroups with c free lanes
+    std::vector<int> fill;                           // lanes used per workgroup
+    std::vector<int> items;
     for (int t : perm) {
         const int L = chain_L[t];
         if (L == 0) continue;
+        items.clear();
         for (int s = 0; s < S; ++s) {
             const size_t inst = (size_t)t * S + s;
             if (ia && !(ia[inst] && sa[s])) continue;
-            if (fill + L > cWG) { n += cWG - fill; fill = 0; }
-            if (pi) { pi->push_back((int)inst); po->push_back(n); pL->push_back(L); }
-            n += L;
-            fill += L;
+            items.push_back((int)inst);
+        }
+        size_t k = 0;
+        auto put = [&](int wg, size_t q) {
+            for (size_t r = 0; r < q; ++r, ++k) {
+                if (pi) {
+                    pi->push_back(items[k]);
+                    po->push_back((long long)wg * cWG + fill[wg]);
+                    pL->push_back(L);
+                }
+                fill[wg] += L;
+            }
+            if (cWG - fill[wg] > 0) open[cWG - fill[wg]].push_back(wg);
+        };
+        for (int c = L; c <= cWG && k < items.size(); ++c) {
+            while (!open[c].empty() && k < items.size()) {
+                const int wg = open[c].back();
+                open[c].pop_back();
+                put(wg, std::min(items.size() - k, (size_t)(c / L)));
+            }
+        }
+        while (k < items.size()) {
+            fill.push_back(0);
+            put((int)fill.size() - 1, std::min(items.size() - k, (size_t)(cWG / L)));
         }
     }
-    if (fill > 0) n += cWG - fill;
-    return n;
+    return (long long)fill.size() * cWG;
 }
 
 // Active-instance compaction (after the screen, the learned screen's
@@ -976,12 +1002,15 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     // Chains (every FD node's parent is its predecessor: a straight wire
     // rooted at an end) that fit one workgroup go to the resident chain
     // kernel; instances are packed into workgroups without straddling.
-    const int cM = b->fp32 ? CHAIN_M32 : CHAIN_M64;
     const int cWGmax = b->fp32 ? CHAIN_WG32 : CHAIN_WG64;
     std::vector<uint8_t> tree_chain(nt, 0);
     std::vector<int> chain_L(nt, 0);
     int need = 1;
-    if (r->stepper == 0) {
+    auto chain_layout = [&](int cM) {
+        std::fill(tree_chain.begin(), tree_chain.end(), 0);
+        std::fill(chain_L.begin(), chain_L.end(), 0);
+        need = 1;
+        if (r->stepper != 0) return;
         for (int t = 0; t < nt; ++t) {
             int i0 = P.tree_off[t], i1 = P.tree_off[t + 1];
             const int L = (i1 - i0 + cM - 1) / cM;
@@ -991,12 +1020,37 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
             tree_chain[t] = chain;
             if (chain) { chain_L[t] = L; need = std::max(need, L); }
         }
+    };
+    // nodes per lane: 8, or in FP32 9 where every layout needs 1024-lane
+    // workgroups (one per compute unit) and the 9-node blocks take fewer
+    // rounds of the chip, weighting a round by its block length
+    int cM = b->fp32 ? CHAIN_M32 : CHAIN_M64;
+    if (r->chain_m != 0 && r->chain_m != cM && !(b->fp32 && r->chain_m == CHAIN_M32W))
+        return fail(b, EM_ERR_ARG, "chain_m must be 0, 8, or 9 (FP32 with 1024-lane workgroups)");
+    chain_layout(cM);
+    const bool wide_ok = b->fp32 && (r->chain_wg == 0 || r->chain_wg == CHAIN_WG32);
+    if (r->chain_m == CHAIN_M32W) {
+        if (!wide_ok) return fail(b, EM_ERR_ARG, "chain_m 9 needs 1024-lane workgroups");
+        cM = CHAIN_M32W;
+        chain_layout(cM);
+    } else if (r->chain_m == 0 && wide_ok && need > CHAIN_WG32 / 2) {
+        int n_cu = 0, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu <= 0)
+            n_cu = 256;
+        const long long r8 = (place_chain_lanes(tree_perm, chain_L, S, CHAIN_WG32, nullptr, nullptr, nullptr,
+                                                nullptr, nullptr) / CHAIN_WG32 + n_cu - 1) / n_cu;
+        chain_layout(CHAIN_M32W);
+        const long long r9 = (place_chain_lanes(tree_perm, chain_L, S, CHAIN_WG32, nullptr, nullptr, nullptr,
+                                                nullptr, nullptr) / CHAIN_WG32 + n_cu - 1) / n_cu;
+        if (r9 * CHAIN_M32W < r8 * CHAIN_M32) cM = CHAIN_M32W;
+        else chain_layout(cM);
     }
     // workgroup sizes that hold the longest chain tree; the smallest unless
     // the caller (or the autotuner) names one
     std::vector<int> wg_cand;
     for (int w = 256; w <= cWGmax; w *= 2)
-        if (w >= need) wg_cand.push_back(w);
+        if (w >= need && (cM == CHAIN_M32 || cM == CHAIN_M64 || w == CHAIN_WG32)) wg_cand.push_back(w);
     int cWG = wg_cand.front();
     if (r->chain_wg != 0) {
         if (std::find(wg_cand.begin(), wg_cand.end(), r->chain_wg) == wg_cand.end())
@@ -1069,6 +1123,8 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     b->n_generic_trees = 0;
     for (int t = 0; t < nt; ++t) b->n_generic_trees += tree_chain[t] ? 0 : 1;
     b->chain_wg = cWG;
+    b->chain_m = cM;
+    d.chain_m = cM;
     b->chain_occ = r->chain_occ == 4 ? 4 : 1;
     b->wg_cand = wg_cand;
     b->lanes_cap = lanes_cap;
@@ -1317,6 +1373,9 @@ em_status em_get_info(em_batch *b, em_info *info)
     info->cg_iters_total = b->cg_iters_total;
     info->ir_ms = b->ir_ms;
     info->cg_sample_iters = b->cg_sample_iters;
+    info->chain_m = b->chain_m;
+    info->chain_wg = b->chain_wg;
+    info->n_chain_wg = b->d.n_chain_wg;
     info->ir_sys_nodes = b->condensed ? b->n_term : b->n_nodes;
     info->ir_sys_edges = b->condensed ? b->n_redge : b->n_res;
     unsigned int sc[8] = {0, 0, 0, 0, 0, 0, 0, 0};

@@ -21,6 +21,7 @@ constexpr double K_B = 1.380649e-23;
 constexpr int EV_WORDS = 5;             // sample, tree, step, node, host segment
 // resident chain kernel: nodes per lane and the largest lanes per workgroup
 #define CHAIN_M32 8
+#define CHAIN_M32W 9                    // FP32 blocks of the 1024-lane form when they save rounds
 #define CHAIN_WG32 1024
 #define CHAIN_M64 8
 #define CHAIN_WG64 512
@@ -62,6 +63,7 @@ struct Dev {
     const int *lane_inst, *lane_blk;    // chain kernel lanes: instance, block index
     int n_chain_wg;                     // workgroups of the chain kernel's launch
     int chain_wg;                       // its lanes per workgroup (256, 512 or the precision's maximum)
+    int chain_m;                        // stress nodes per lane (CHAIN_M32/CHAIN_M64, or CHAIN_M32W)
     int chain_occ;                      // 1, or 4: register budget of 128 VGPRs (FP32, 256/512 lanes)
     // ---- per stress node statics (FP64) ----
     double *T, *V, *g0, *rob0, *gdx0, *mdrv;

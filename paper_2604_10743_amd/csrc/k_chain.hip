@@ -92,11 +92,17 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
     __shared__ R s_al[LEV][WG];
     __shared__ R s_ga[LEV][WG];
     __shared__ R s_x[2][WG];
+    // separator exchange of the per-step reduction, padded by WG/2 zeros on
+    // each side: the neighbours at lane -+ 2^l are read at a constant offset
+    // from one lane address (no per-level index registers, no clamping)
+    __shared__ R s_xp[2][2 * WG];
     __shared__ R s_e[3][WG];
     __shared__ double s_q[WG];
 
     const Dev *d = h.dev;
     const int lane = threadIdx.x;
+    s_xp[0][lane] = 0; s_xp[0][lane + WG] = 0;
+    s_xp[1][lane] = 0; s_xp[1][lane + WG] = 0;      // pads stay zero (ordered by the barriers below)
     const size_t gl = (size_t)blockIdx.x * WG + lane;
     const int S = h.S;
     const int inst = h.lane_inst[gl];
@@ -409,14 +415,15 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
 #pragma unroll
         for (int l = 0; l < LEV; ++l) {
             const int dd = 1 << l;
-            s_x[buf][lane] = Rk;
+            constexpr int P = WG / 2;
+            s_xp[buf][P + lane] = Rk;
             lds_barrier();
-            // both neighbours read unconditionally (indices clamped into the
-            // workgroup; every lane wrote a finite value): a missing coupling
-            // has a zero multiplier
+            // both neighbours read unconditionally (past the workgroup's ends
+            // the zero pads; every lane wrote a finite value): a missing
+            // coupling has a zero multiplier
             const R al_l = s_al[l][lane], ga_l = s_ga[l][lane];
-            const R xm = s_x[buf][lane >= dd ? lane - dd : 0];
-            const R xp = s_x[buf][lane + dd < WG ? lane + dd : WG - 1];
+            const R xm = s_xp[buf][P + lane - dd];
+            const R xp = s_xp[buf][P + lane + dd];
             Rk = Rk + al_l * xm + ga_l * xp;
             buf ^= 1;
         }
@@ -654,7 +661,10 @@ void launch_chain(const Dev &d, const Dev *d_dev, bool fp32, int n_steps, int st
             if (dense) k_chain<float, CHAIN_M32, 512, 4><<<d.n_chain_wg, 512, 0, st>>>(h);
             else k_chain<float, CHAIN_M32, 512, 1><<<d.n_chain_wg, 512, 0, st>>>(h);
         } else {
-            k_chain<float, CHAIN_M32, CHAIN_WG32, 1><<<d.n_chain_wg, CHAIN_WG32, 0, st>>>(h);
+            if (d.chain_m == CHAIN_M32W)
+                k_chain<float, CHAIN_M32W, CHAIN_WG32, 1><<<d.n_chain_wg, CHAIN_WG32, 0, st>>>(h);
+            else
+                k_chain<float, CHAIN_M32, CHAIN_WG32, 1><<<d.n_chain_wg, CHAIN_WG32, 0, st>>>(h);
         }
     } else {
         if (d.chain_wg == 256) k_chain<double, CHAIN_M64, 256, 1><<<d.n_chain_wg, 256, 0, st>>>(h);

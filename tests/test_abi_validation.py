@@ -89,6 +89,10 @@ CASES = {
     "bad run parameters (launch)": lambda g, m, r, mc: r.__setitem__("ir_launch", 4),
     "bad run parameters (joule)": lambda g, m, r, mc: r.__setitem__("joule", 2),
     "bad run parameters (growth)": lambda g, m, r, mc: r.__setitem__("dt_growth", math.inf),
+    "bad run parameters (chain_m)": lambda g, m, r, mc: r.__setitem__("chain_m", 7),
+    "bad run parameters (chain_m FP64)": lambda g, m, r, mc: (r.__setitem__("chain_m", 9), r.__setitem__("prec", 0)),
+    "bad run parameters (chain_m lanes)": lambda g, m, r, mc: (r.__setitem__("chain_m", 9),
+                                                              r.__setitem__("chain_wg", 512)),
     "Joule thermal block": lambda g, m, r, mc: (r.__setitem__("joule", 1), m.__setitem__("k_ild", 0.0)),
     "bad Monte Carlo (samples)": lambda g, m, r, mc: mc.__setitem__("n_samples", 0),
     "bad Monte Carlo (cov)": lambda g, m, r, mc: mc.__setitem__("cov_kappa", -0.1),

@@ -229,6 +229,56 @@ def test_chain_workgroup_sizes_give_identical_results(em, prec):
             em.Batch(g, mat, dict(rn, **bad), mc)
 
 
+def test_nine_node_blocks_match_oracle_and_pack(em, oracle_mod):
+    # FP32 1024-lane chain kernel with 8- and 9-node lane blocks: chains of
+    # 8201 nodes (912 lanes of 9 nodes; too long for 8-node blocks, which send
+    # it to the generic kernel), 6001, 4601 (exactly 512 lanes) and short ones,
+    # three samples each, against the FP64 oracle; the instances are packed
+    # best-fit into no more workgroups than filling them in order would take
+    segs = [410, 300, 230, 17, 3]
+    g = _lines(segs)
+    mat = material(sigma_crit=1e12)
+    N = 20
+    rn = run(prec=1, intervals_per_seg=N, dt=2e5, max_voids_per_tree=0)
+    mc = dict(n_samples=3, seed=9, cov_kappa=0.2, cov_scrit=0.0)
+    topo = oracle_mod.topology(g, N)
+    nodes = np.diff(topo.tree_off)
+    out = {}
+    for m in (8, 9):
+        print(f"chain_m {m}", flush=True)
+        B = em.Batch(g, mat, dict(rn, chain_m=m), mc)
+        B.stress_step(60)
+        info = B.info()
+        assert info["chain_m"] == m and info["chain_wg"] == 1024
+        out[m] = [B.stress(s) for s in range(3)]
+        B.close()
+        lanes = [-(-int(n) // m) for n in nodes if -(-int(n) // m) <= 1024]
+        nf, fill = 1, 0
+        for L in sorted(lanes, reverse=True) * 3:
+            if fill + L > 1024:
+                nf, fill = nf + 1, 0
+            fill += L
+        assert -(-3 * sum(lanes) // 1024) <= info["n_chain_wg"] <= nf, (m, info["n_chain_wg"], nf)
+    for s in range(3):
+        xk, xs = oracle_mod.sample_xi(g, mc, s)
+        sim = oracle_mod.SampleSim(g, mat, dict(rn, prec=0), topo, xk, xs)
+        sim.set_j(g.seg_j)
+        sim.set_active(np.ones(topo.n_trees, np.uint8))
+        sim.steps(60, 0)
+        so = sim.sigma()
+        for m in (8, 9):
+            per = [_per_tree_rel(out[m][s], so, topo.tree_off[t:t + 2]) for t in range(topo.n_trees)]
+            print(f"sample {s} blocks {m}: errors {[f'{e:.1e}' for e in per]}", flush=True)
+            for n, e in zip(nodes, per):
+                # float state and factors: the error grows with the step
+                # matrix's conditioning, about the chain length squared
+                # (measured 8.2e-5 at 4101 nodes, 2.2e-4 at 6001)
+                assert e <= max(1e-5, 1e-11 * float(n) ** 2), (m, s, n, e)
+    for bad in (dict(chain_m=7), dict(chain_m=9, prec=0), dict(chain_m=9, chain_wg=512)):
+        with pytest.raises(em.EmError):
+            em.Batch(g, mat, dict(rn, **bad), mc)
+
+
 def test_autotune_keeps_results_and_resets(em):
     g, mat, rn, mc = synth.workload("mc_grid")
     rn = dict(rn, prec=0)
