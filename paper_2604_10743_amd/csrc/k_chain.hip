@@ -132,10 +132,11 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
     const R *dtf_g = (const R *)h.dtf;
     const R *sc_g = (const R *)h.sc;
     const R *Vr_g = (const R *)h.Vr;
+    const R *Vr_b = Vr_g + start;   // this lane's block: one base address, constant offsets
     const double dt = h.dt;
 
     // ---- per-lane node data (registers for the whole launch) ----
-    R sg[M], fv[M], w[M], dinv[M], al[M], be[M];
+    R sg[M], fv[M], dinv[M], al[M], be[M];
     // FP32 form: the state carries a float low part sl (sg + sl), which keeps
     // the increments that fall below half an ulp of sg (near saturation the
     // per-step increments shrink to a few Pa and float alone would stall the
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
         // nodes past cnt (a short last block, an idle lane) keep zeros here:
         // the step below computes them without branches, and zero pivots and
         // multipliers map them to zero increments
-        sg[j] = 0; fv[j] = 0; w[j] = 0; dinv[j] = 0; al[j] = 0; be[j] = 0;
+        sg[j] = 0; fv[j] = 0; dinv[j] = 0; al[j] = 0; be[j] = 0;
         if constexpr (LO) sl[j] = 0.f;
         if (j < cnt) {
             size_t x = (size_t)(start + j) * S + s;
@@ -198,9 +199,9 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
     // ---- factorisation (interior Thomas, alpha/beta, reduced row, PCR) ----
     R dfin = 1;
     auto factor = [&]() {
-        R Dg[M];
+        R Dg[M], w[M];       // forward multipliers w[j] = gE[j] dinv[j-1] (recomputed per step)
 #pragma unroll
-        for (int j = 0; j < M; ++j) Dg[j] = (j < cnt ? Vr_g[start + j] : (R)0) + gE[j] + gE[j + 1];
+        for (int j = 0; j < M; ++j) Dg[j] = (j < cnt ? Vr_b[j] : (R)0) + gE[j] + gE[j + 1];
         for (int k = 0; k < nv; ++k) {          // Robin rows of the block's voids
             int jv = d->vnode[inst * MAXV + k] - start;
             R rw = (R)(dt * d->vrob[inst * MAXV + k]);
@@ -312,7 +313,7 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
     auto content = [&]() -> double {
         double q = 0.0;
 #pragma unroll
-        for (int j = 0; j < M; ++j) if (j < cnt) q += (double)Vr_g[start + j] * sv(j);
+        for (int j = 0; j < M; ++j) if (j < cnt) q += (double)Vr_b[j] * sv(j);
         if (vmask) {
             for (int k = 0; k < nv; ++k) {
                 int jv = d->vnode[inst * MAXV + k] - start;
@@ -323,7 +324,7 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
     };
     double vs = 0.0;
 #pragma unroll
-    for (int j = 0; j < M; ++j) if (j < cnt) vs += (double)Vr_g[start + j];
+    for (int j = 0; j < M; ++j) if (j < cnt) vs += (double)Vr_b[j];
     const double Vtot = seg_sum(vs);
     const double Q0 = seg_sum(content());
     // stress at the next block's separator (kept in step with that lane)
@@ -373,7 +374,7 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
         //    block is the separator's, not the interior solve's).
         R yp = 0;
 #pragma unroll
-        for (int j = 1; j < M; ++j) { yp = (j == 1) ? y[1] : y[j] + w[j] * yp; y[j] = yp; }
+        for (int j = 1; j < M; ++j) { yp = (j == 1) ? y[1] : y[j] + (gE[j] * dinv[j - 1]) * yp; y[j] = yp; }
         R yn = 0;
 #pragma unroll
         for (int j = M - 1; j >= 1; --j) {
