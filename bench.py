@@ -32,10 +32,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, TFLOP/s
-# BE step of a chain node with the factorisation reused: edge flux g (s_j+1 - s_j)
-# (2), residual dt f + q_j - q_j-1 (2), forward sweep (2), backward sweep (3),
-# state update (1)
-FLOPS_PER_NODE_STEP = 10
+# BE step of a node with the factorisation reused: right-hand side V s + dt f,
+# forward elimination, back substitution -- about four fused multiply-adds
+FLOPS_PER_NODE_STEP = 8
 BYTES_PER_NODE_STEP = {0: 40.0, 1: 20.0}   # sigma r/w, 1/d, l, dt*f (FP64 / FP32)
 
 
