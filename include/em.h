@@ -142,7 +142,8 @@ typedef struct {
                                     the dot products differs. */
     int32_t chain_wg;            /* lanes per workgroup of the resident chain kernel: 0 automatic
                                     (the smallest of 256, 512, 1024 that holds the longest chain
-                                    tree), or one of those (at most 512 in FP64) that holds it.
+                                    tree; 1024 with 9-node blocks, see chain_m), or one of those
+                                    (at most 512 in FP64) that holds it.
                                     Results do not depend on it (instances never share a
                                     reduction: the couplings across their boundaries are zero),
                                     except that the FP32 1024-lane form keeps no low part of the

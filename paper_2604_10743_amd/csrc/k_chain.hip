@@ -358,8 +358,8 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
         if (vmask) {                           // Robin sinks at void nodes
             for (int k = 0; k < nv; ++k) {
                 const int jv = d->vnode[inst * MAXV + k] - start;
+                const double rb = dt * d->vrob[inst * MAXV + k];     // loaded with the node
                 if (jv < 0 || jv >= cnt) continue;
-                const double rb = dt * d->vrob[inst * MAXV + k];
 #pragma unroll
                 for (int j = 0; j < M; ++j)
                     if (j == jv) {
@@ -455,11 +455,18 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
         // void growth on the lanes owning void nodes (eq. 15 accounting)
         if (vmask) {
             for (int k = 0; k < nv; ++k) {
+                // every load of the void's record issued before the test and
+                // the stores: two dependent rounds (record, then its node's
+                // drive and its segment's geometry) instead of a chain
                 const int q = inst * MAXV + k;
                 const int jv = d->vnode[q] - start;
+                const int e = d->vseg[q];
+                const double vol0 = d->vvol[q], rob = d->vrob[q];
+                const int phase = d->vphase[q];
                 if (jv < 0 || jv >= cnt) continue;
-                R sh = 0;
                 const R fvv = dtf_g[(size_t)(start + jv) * S + s];
+                const double W = d->w[e], H = d->h[e], Le = d->len[e];
+                R sh = 0;
                 float slo = 0.f;
 #pragma unroll
                 for (int j = 0; j < M; ++j)
@@ -469,13 +476,11 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
                     }
                 double svv = (double)sh;
                 if constexpr (LO) svv += (double)slo;
-                const double vol = d->vvol[q] + (dt * d->vrob[q] * svv + (double)fvv) / d->B;
+                const double vol = vol0 + (dt * rob * svv + (double)fvv) / d->B;
                 d->vvol[q] = vol;
-                const int e = d->vseg[q];
-                const double W = d->w[e], H = d->h[e];
-                const double l = fmin(vol / (W * H), d->len[e]);
+                const double l = fmin(vol / (W * H), Le);
                 d->vlen[q] = l;
-                if (d->vphase[q] == 0 && l >= W) {
+                if (phase == 0 && l >= W) {
                     d->vphase[q] = 1;
                     if (d->vearly[q]) {
                         d->open[(size_t)s * d->n_res + e] = 1;
