@@ -284,12 +284,13 @@ __device__ inline double amg_Av(const AmgLevel &L, int s, int I, const double *v
     return a;
 }
 
+// Per-element bodies of the V-cycle, shared by the per-level kernels and the
+// one-workgroup tail below (same arithmetic, same order).
+
 // b = sum of the finer level's residual w over the members; pre-smoothing
 // from zero, x = omega b / D.
-__global__ __launch_bounds__(AMG_BS) void k_amg_restrict(Dev d, AmgLevel L, const double *wf, double omega)
+__device__ inline void amg_restrict_one(const AmgLevel &L, const double *wf, double omega, int s, int I)
 {
-    int I = blockIdx.x * AMG_BS + threadIdx.x, s = blockIdx.y;
-    if (I >= L.n || d.conv[s]) return;
     const double *w = wf + (size_t)s * L.nf;
     double acc = 0.0;
     for (int k = L.mem_off[I]; k < L.mem_off[I + 1]; ++k) acc += w[L.mem[k]];
@@ -299,43 +300,35 @@ __global__ __launch_bounds__(AMG_BS) void k_amg_restrict(Dev d, AmgLevel L, cons
 }
 
 // w = b - A x
-__global__ __launch_bounds__(AMG_BS) void k_amg_res(Dev d, AmgLevel L)
+__device__ inline void amg_res_one(const AmgLevel &L, int s, int I)
 {
-    int I = blockIdx.x * AMG_BS + threadIdx.x, s = blockIdx.y;
-    if (I >= L.n || d.conv[s]) return;
     size_t x = (size_t)s * L.n + I;
     L.w[x] = L.b[x] - amg_Av(L, s, I, L.x + (size_t)s * L.n);
 }
 
 // coarsest level: x = A^-1 b (dense), or b / D
-__global__ __launch_bounds__(AMG_BS) void k_amg_coarse_solve(Dev d, AmgLevel C, const double *Ainv, int dense)
+__device__ inline void amg_coarse_one(const AmgLevel &C, const double *Ainv, int dense, int s, int i)
 {
-    int s = blockIdx.x;
-    if (d.conv[s]) return;
     const int n = C.n;
-    for (int i = threadIdx.x; i < n; i += AMG_BS) {
-        size_t x = (size_t)s * n + i;
-        double v;
-        if (dense) {
-            const double *row = Ainv + ((size_t)s * n + i) * n;
-            const double *b = C.b + (size_t)s * n;
-            v = 0.0;
-            for (int j = 0; j < n; ++j) v += row[j] * b[j];
-        } else {
-            v = C.b[x] / C.D[x];
-        }
-        C.x[x] = v;
+    size_t x = (size_t)s * n + i;
+    double v;
+    if (dense) {
+        const double *row = Ainv + ((size_t)s * n + i) * n;
+        const double *b = C.b + (size_t)s * n;
+        v = 0.0;
+        for (int j = 0; j < n; ++j) v += row[j] * b[j];
+    } else {
+        v = C.b[x] / C.D[x];
     }
+    C.x[x] = v;
 }
 
 // Up-sweep at a coarse level: y = x + alpha P rc, formed on the fly for the
 // node and its neighbours, then post-smoothing out = y + omega (b - A y) / D.
 // out (the level's result) is the level's y array.
-__global__ __launch_bounds__(AMG_BS) void k_amg_up(Dev d, AmgLevel L, AmgLevel C, const double *rc,
-                                                   double alpha, double omega)
+__device__ inline void amg_up_one(const AmgLevel &L, const AmgLevel &C, const double *rc, double alpha,
+                                  double omega, int s, int I)
 {
-    int I = blockIdx.x * AMG_BS + threadIdx.x, s = blockIdx.y;
-    if (I >= L.n || d.conv[s]) return;
     const double *xl = L.x + (size_t)s * L.n, *W = L.W + (size_t)s * L.ne;
     const double *rcs = rc + (size_t)s * C.n;
     auto yv = [&](int J) {
@@ -347,6 +340,71 @@ __global__ __launch_bounds__(AMG_BS) void k_amg_up(Dev d, AmgLevel L, AmgLevel C
     double a = Dd * yi;
     for (int k = L.adj_off[I]; k < L.adj_off[I + 1]; ++k) a -= W[L.adj_e[k]] * yv(L.adj_nbr[k]);
     L.y[x] = yi + omega * (L.b[x] - a) / Dd;
+}
+
+__global__ __launch_bounds__(AMG_BS) void k_amg_restrict(Dev d, AmgLevel L, const double *wf, double omega)
+{
+    int I = blockIdx.x * AMG_BS + threadIdx.x, s = blockIdx.y;
+    if (I >= L.n || d.conv[s]) return;
+    amg_restrict_one(L, wf, omega, s, I);
+}
+
+__global__ __launch_bounds__(AMG_BS) void k_amg_res(Dev d, AmgLevel L)
+{
+    int I = blockIdx.x * AMG_BS + threadIdx.x, s = blockIdx.y;
+    if (I >= L.n || d.conv[s]) return;
+    amg_res_one(L, s, I);
+}
+
+__global__ __launch_bounds__(AMG_BS) void k_amg_coarse_solve(Dev d, AmgLevel C, const double *Ainv, int dense)
+{
+    int s = blockIdx.x;
+    if (d.conv[s]) return;
+    for (int i = threadIdx.x; i < C.n; i += AMG_BS) amg_coarse_one(C, Ainv, dense, s, i);
+}
+
+__global__ __launch_bounds__(AMG_BS) void k_amg_up(Dev d, AmgLevel L, AmgLevel C, const double *rc,
+                                                   double alpha, double omega)
+{
+    int I = blockIdx.x * AMG_BS + threadIdx.x, s = blockIdx.y;
+    if (I >= L.n || d.conv[s]) return;
+    amg_up_one(L, C, rc, alpha, omega, s, I);
+}
+
+// The small levels lt..nlev of a V-cycle in one workgroup per sample: their
+// per-level launches cost far more than their work.  Phases are separated by
+// workgroup barriers; each element is computed by the same body as in the
+// per-level kernels.
+constexpr int AMG_TAIL_LEV = 8;          // levels a tail holds
+constexpr int AMG_TAIL_N = 512;          // largest level a tail starts at
+struct AmgTail {
+    int lt, nlev, dense;
+    double omega, alpha;
+    const double *Ainv;
+    AmgLevel lev[AMG_TAIL_LEV];          // lev[k] = level lt + k
+};
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_amg_tail(Dev d, AmgTail t)
+{
+    const int s = blockIdx.x, T = threadIdx.x;
+    if (d.conv[s]) return;                      // the same for the whole workgroup
+    const int top = t.nlev - t.lt;              // index of the coarsest level in t.lev
+    for (int k = 0; k < top; ++k) {
+        const AmgLevel &L = t.lev[k], &C = t.lev[k + 1];
+        for (int I = T; I < L.n; I += BS) amg_res_one(L, s, I);
+        __syncthreads();
+        for (int I = T; I < C.n; I += BS) amg_restrict_one(C, L.w, t.omega, s, I);
+        __syncthreads();
+    }
+    for (int i = T; i < t.lev[top].n; i += BS) amg_coarse_one(t.lev[top], t.Ainv, t.dense, s, i);
+    __syncthreads();
+    for (int k = top - 1; k >= 0; --k) {
+        const AmgLevel &L = t.lev[k], &C = t.lev[k + 1];
+        const double *rc = (k + 1 == top) ? C.x : C.y;
+        for (int I = T; I < L.n; I += BS) amg_up_one(L, C, rc, t.alpha, t.omega, s, I);
+        __syncthreads();
+    }
 }
 
 static inline dim3 grid_of(int n, int S) { return dim3((n + AMG_BS - 1) / AMG_BS, S); }
@@ -365,16 +423,28 @@ void launch_amg_setup(const Dev &d, const Amg &a, hipStream_t st)
 void launch_amg_vcycle(const Dev &d, const Amg &a, bool init, hipStream_t st)
 {
     const int L = a.nlev;
+    // first level small enough for the one-workgroup tail (two levels at least)
+    int lt = L;
+    for (int l = 1; l < L; ++l)
+        if (a.lev[l].n <= AMG_TAIL_N && L - l + 1 <= AMG_TAIL_LEV) { lt = l; break; }
     if (init) launch_amg_pre0(d, a.omega, st);
     launch_amg_res0(d, a.l0.w0, st);
     k_amg_restrict<<<grid_of(a.lev[1].n, d.S), AMG_BS, 0, st>>>(d, a.lev[1], a.l0.w0, a.omega);
-    for (int l = 1; l < L; ++l) {
+    for (int l = 1; l < lt; ++l) {
         k_amg_res<<<grid_of(a.lev[l].n, d.S), AMG_BS, 0, st>>>(d, a.lev[l]);
         k_amg_restrict<<<grid_of(a.lev[l + 1].n, d.S), AMG_BS, 0, st>>>(d, a.lev[l + 1], a.lev[l].w, a.omega);
     }
-    k_amg_coarse_solve<<<d.S, AMG_BS, 0, st>>>(d, a.lev[L], a.Ainv, a.dense);
+    if (lt < L) {
+        AmgTail t;
+        t.lt = lt; t.nlev = L; t.dense = a.dense; t.omega = a.omega; t.alpha = a.alpha; t.Ainv = a.Ainv;
+        for (int l = lt; l <= L; ++l) t.lev[l - lt] = a.lev[l];
+        if (d.S < 64) k_amg_tail<1024><<<d.S, 1024, 0, st>>>(d, t);
+        else k_amg_tail<AMG_BS><<<d.S, AMG_BS, 0, st>>>(d, t);
+    } else {
+        k_amg_coarse_solve<<<d.S, AMG_BS, 0, st>>>(d, a.lev[L], a.Ainv, a.dense);
+    }
     // result of level l: x at the coarsest level, y above it
-    for (int l = L - 1; l >= 1; --l)
+    for (int l = lt - 1; l >= 1; --l)
         k_amg_up<<<grid_of(a.lev[l].n, d.S), AMG_BS, 0, st>>>(d, a.lev[l], a.lev[l + 1],
                                                              l + 1 == L ? a.lev[l + 1].x : a.lev[l + 1].y,
                                                              a.alpha, a.omega);
