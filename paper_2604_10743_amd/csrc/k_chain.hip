@@ -654,7 +654,7 @@ void launch_chain(const Dev &d, const Dev *d_dev, bool fp32, int n_steps, int st
     h.lane_inst = d.lane_inst; h.lane_blk = d.lane_blk; h.tree_off = d.tree_off;
     h.sample_active = d.sample_active; h.inst_active = d.inst_active;
     h.dev = d_dev;
-    h.S = d.S; h.n_steps = n_steps; h.step0 = step0; h.proj_every = 8;
+    h.S = d.S; h.n_steps = n_steps; h.step0 = step0; h.proj_every = 16;
     h.dt = d.dt;
     // the batch's workgroup size (lanes): the smallest that holds its longest
     // chain, or the one the autotuner measured fastest
