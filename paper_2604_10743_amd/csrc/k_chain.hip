@@ -34,6 +34,21 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Workgroup-wide OR with one barrier: each wavefront's vote in its own LDS
+// word, then every lane ORs the words.  A caller needs at least one other
+// barrier between two calls (the words are rewritten by the next call).
+template <int WG>
+__device__ __forceinline__ bool wg_any(bool p, unsigned *s_w, int lane)
+{
+    const bool wave = __any(p ? 1 : 0) != 0;
+    if ((lane & 63) == 0) s_w[lane >> 6] = wave ? 1u : 0u;
+    lds_barrier();
+    unsigned a = 0;
+#pragma unroll
+    for (int w = 0; w < WG / 64; ++w) a |= s_w[w];
+    return a != 0;
+}
+
 template <int N>
 struct Log2 { static constexpr int v = 1 + Log2<N / 2>::v; };
 template <>
@@ -98,6 +113,7 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
     __shared__ R s_xp[2][2 * WG];
     __shared__ R s_e[3][WG];
     __shared__ double s_q[WG];
+    __shared__ unsigned s_vote[WG / 64];
 
     const Dev *d = h.dev;
     const int lane = threadIdx.x;
@@ -517,7 +533,7 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
                 }
             }
         }
-        if (__syncthreads_or(cand ? 1 : 0)) {
+        if (wg_any<WG>(cand, s_vote, lane)) {    // the step's reduction barriers separate two calls
             // peak candidate per instance, then the lowest node within the tie window
             if constexpr (LO) {
                 double lm = -INFINITY;
