@@ -10,7 +10,7 @@
  * Sec. IV-D), void volume by atom conservation (eq. 15), incubation (eq. 16),
  * early/late failure (Sec. IV-C, eq. 17); periodic IR-drop re-solves of the
  * nodal system M u = P I (eq. 8) closing the loop to time-to-failure (Fig. 2),
- * the optional steady-state immortality screen (Sec. II-B) and Monte Carlo
+ * the optional steady-state immortality screen (Sec. III-B) and Monte Carlo
  * over diffusivity and critical stress (Sec. IV-F).
  *
  * Conventions for every entry point:
@@ -46,7 +46,8 @@ typedef enum {
     EM_ERR_HIP = 3,       /* a HIP runtime call or kernel failed */
     EM_ERR_NOCONV = 4,    /* conjugate gradients missed cg_rtol within cg_max_iter */
     EM_ERR_STATE = 5,     /* call out of order (e.g. a step on a batch with no currents) */
-    EM_ERR_OVERFLOW = 6   /* event ring overflowed (events beyond its capacity were dropped) */
+    EM_ERR_OVERFLOW = 6   /* event ring overflowed (events beyond its capacity were dropped);
+                             the per-instance void cap is not an error, see em_info.n_void_capped */
 } em_status;
 
 typedef enum { EM_FP64 = 0, EM_FP32 = 1 } em_precision;
@@ -98,7 +99,7 @@ typedef struct {
     double delta;      /* void-interface thickness of the Robin row, m */
     double rho_ta;     /* liner resistivity, ohm m */
     double h_ta;       /* liner thickness, m */
-    /* Thermal block of the Joule-heating pre-pass (Sec. II-A, eqs. 2-4; read
+    /* Thermal block of the Joule-heating pre-pass (Sec. III-A, eqs. 2-4; read
      * only when em_run_params.joule != 0): wire and dielectric thermal
      * conductivities (W/(m K)) and the dielectric thickness t_ILD (m).  The
      * wire thickness t_cu of eq. 2 is each segment's res_h. */
@@ -156,7 +157,7 @@ typedef struct {
                                     FP32 with 256 or 512 lanes only.  Pays when a launch holds
                                     few instances (Monte Carlo after the screen).  Same results. */
     int32_t joule;               /* 1: one-time Joule-heating thermal pre-pass at batch creation
-                                    (Sec. II-A): the currents of a nominal IR solve (or the
+                                    (Sec. III-A): the currents of a nominal IR solve (or the
                                     prescribed seg_j) heat every wire segment; each segment's
                                     steady profile solves k T'' + j^2 rho = k (T - T0)/Gamma^2,
                                     Gamma^2 = t_cu t_ILD k_cu / k_ILD, between its end
@@ -182,6 +183,19 @@ typedef struct {
                                     chain instances into fewer rounds of the chip (rounds times
                                     block length smaller).  Lanes hold whole blocks; results agree
                                     to float rounding of the state. */
+    double guard_band;           /* FP32 runs of em_run_to_ttf: relative guard band around the
+                                    failure threshold (0 = off).  A sample whose worst drop at any
+                                    re-solve up to its retirement lies within
+                                    guard_band x fail_frac of fail_frac has its failure decision
+                                    and time bracket determined by stress values that FP32
+                                    stepping does not resolve; after the FP32 run every such
+                                    sample is run again from t = 0 in FP64 (an internal batch over
+                                    those Monte Carlo sample indices, same inputs) and its
+                                    em_ttf_result, resistance changes and opens are replaced by
+                                    the FP64 run's (em_ttf_result.redecided = 1).  Its stress,
+                                    voids and events keep the FP32 run's values.  The re-run has
+                                    no learned screen (whose replay reproduces the unscreened run).
+                                    Ignored in FP64 and in trees-only mode. */
 } em_run_params;
 
 /* Monte Carlo (Sec. IV-F): unit-mean lognormal multipliers with coefficient
@@ -208,6 +222,10 @@ typedef struct {
     double cov_kappa, cov_scrit;
     double cov_rho, cov_load;
     double sd_ea_eV;             /* activation-energy spread, eV, 0 <= sd < 1 */
+    const int32_t *sample_ids;   /* [n_samples] host, or NULL: the Monte Carlo sample index
+                                    (the Philox counter's sample word) of each batch sample;
+                                    NULL = 0 .. n_samples-1.  Entries >= 0, copied at creation.
+                                    Lets a batch re-run any subset of a study's samples. */
 } em_mc_params;
 
 typedef struct {
@@ -218,6 +236,8 @@ typedef struct {
     int32_t outer_idx;     /* IR re-solves done (the one that failed, if failed) */
     int32_t n_nucleated_trees;
     int32_t n_failed_segs; /* segments with dR > 0 or open */
+    int32_t redecided;     /* 1: the FP32 run came within the guard band of the threshold and
+                              this result is that of the FP64 re-run (em_run_params.guard_band) */
 } em_ttf_result;
 
 typedef struct {
@@ -249,6 +269,12 @@ typedef struct {
     int32_t chain_m;       /* stress nodes per lane of the chain kernel */
     int32_t chain_wg;      /* its lanes per workgroup */
     int32_t n_chain_wg;    /* workgroups of its present lane layout */
+    int32_t n_redecided;   /* samples of the last em_run_to_ttf re-run in FP64 (guard band) */
+    int64_t n_void_capped; /* nucleation candidates not turned into a void because their
+                              (tree, sample) already held max_voids_per_tree voids, summed over
+                              instances since creation or reset.  Reaching the cap is not an
+                              error: the run continues with the voids it has (the paper gives no
+                              cap; the cap bounds the per-instance void records) */
 } em_info;
 
 /* Allocator hook: device memory for the batch (e.g. a framework's caching
@@ -259,12 +285,23 @@ typedef struct {
     void *ctx;
 } em_allocator;
 
-/* Build a batch: copies the netlist, partitions it into wire trees (same-layer
- * components, root = lowest vertex, depth-first in ascending segment order,
- * each segment refined into intervals_per_seg FD intervals), and on the device
- * evaluates temperatures, diffusivities, control volumes, Monte Carlo draws
- * (mc == NULL: one nominal sample) and the tree factors.  Stress starts at
- * sigma_T.  hip_stream: a hipStream_t, or NULL for the null stream. */
+/* Build a batch (Sec. IV-A and Fig. 2: the flow's three inputs -- extracted
+ * power-grid netlist, material and numerical parameters, optional thermal map
+ * -- and the partition of the netlist into wire trees; Sec. IV-F for the
+ * Monte Carlo draws): copies the netlist, partitions it into wire trees
+ * (same-layer components, root = lowest vertex, depth-first in ascending
+ * segment order, each segment refined into intervals_per_seg FD intervals),
+ * and on the device evaluates temperatures, diffusivities, control volumes,
+ * Monte Carlo draws (mc == NULL: one nominal sample) and the tree factors.
+ * Stress starts at sigma_T.  hip_stream: a hipStream_t, or NULL for the null
+ * stream.  *out receives the batch (NULL on failure); errors: EM_ERR_ARG for
+ * a NULL or inconsistent argument, a struct_size other than this library's
+ * sizeof of that struct, non-finite or non-positive geometry, a wire component with a
+ * cycle or a netlist without wire segments; EM_ERR_OOM when device or pinned
+ * host memory runs out; EM_ERR_HIP for a failing HIP call.  The paper
+ * re-partitions the degraded netlist at every aging step; the partition is
+ * fixed here (resistance changes never alter which segments share a layer
+ * component), so it is done once. */
 em_status em_batch_create(const em_grid_desc *grid, const em_material *mat,
                           const em_run_params *run, const em_mc_params *mc,
                           const em_allocator *alloc, void *hip_stream, em_batch **out);
@@ -280,7 +317,7 @@ const char *em_last_error(const em_batch *b);
  * be NULL.  Trees-only batches: EM_ERR_STATE. */
 em_status em_ir_solve(em_batch *b, double *max_drop);
 
-/* Steady-state immortality screen (Sec. II-B) with the current densities of
+/* Steady-state immortality screen (Sec. III-B) with the current densities of
  * the last IR solve (or the prescribed ones): a tree is kept for stepping iff
  * some node's zero-flux steady stress exceeds its critical stress.
  * tree_mortal: [n_samples][n_trees] host, may be NULL. */
@@ -389,7 +426,7 @@ em_status em_restore(em_batch *b, const void *host_buf, size_t n);
  * of Sec. III-D at edge-midpoint temperature, times the Monte Carlo
  * multiplier); log10 mean diffusivity of the edges at the peak node p/1e-15;
  * r = peak over nodes of the zero-flux steady stress of the screen
- * (Sec. II-B) / node critical stress, clamped to [-10, 10] (p = first node of
+ * (Sec. III-B) / node critical stress, clamped to [-10, 10] (p = first node of
  * the largest ratio); log10 max(r - 1, 1e-6); log10(Lpk^2 / (pi^2 kappa_pk)
  * / 1 s) - 8 with Lpk the difference of root distances from p to the nearest
  * node whose steady stress is at or below sigma_T (floored at 0.1 um);

@@ -10,14 +10,14 @@
  * Every routine follows the paper's definitions in the paper's order, with
  * scalar loops and no blocking or fusion:
  *   - topology           : wire trees of the extracted netlist (Sec. IV-A)
- *   - node temperatures  : sampled from the thermal map (Sec. II-A), or given
+ *   - node temperatures  : sampled from the thermal map (Sec. III-A), or given
  *                          by the Joule-heating pre-pass (oracle/thermal.py)
  *   - diffusivity        : kappa = D_a(T) B Omega / (k_B T), D_a = D0 exp(-Ea/k_B T)
  *                          (Korhonen PDE, eqs. 10-13)
  *   - descriptor system  : C dsigma/dt = A sigma + f (eq. 18), vertex-centred
  *                          finite volume on the tree graph, blocking ends
  *   - screen             : zero-flux steady state, classify against sigma_crit
- *                          (Sec. II-B)
+ *                          (Sec. III-B)
  *   - BE step            : (C - dt A) sigma^{n+1} = C sigma^n + dt f, solved
  *                          exactly by Gaussian elimination in leaf-to-root order
  *   - nucleation         : peak-stress node with sigma >= sigma_crit; Robin row
@@ -66,7 +66,7 @@ typedef struct {
     int max_voids;
     /* per-segment Monte Carlo multipliers; NULL means 1 */
     const double *xi_k, *xi_s;
-    /* stress-node temperatures [ns] from the Joule-heating pre-pass (Sec. II-A,
+    /* stress-node temperatures [ns] from the Joule-heating pre-pass (Sec. III-A,
      * oracle/thermal.py); NULL: sampled from the map as below */
     const double *T_stress;
     /* per-segment resistivity multipliers of the sample (Sec. IV-F sampled
@@ -427,7 +427,7 @@ void ora_set_j(ora_state *S, const double *jseg)
     }
 }
 
-/* Steady-state screen (Sec. II-B): the zero-flux steady state satisfies
+/* Steady-state screen (Sec. III-B): the zero-flux steady state satisfies
  * sigma_child - sigma_parent = dir dx (S + M) on every edge, independent of
  * kappa; the constant follows from conservation, sum V sigma = sum V sigma_T.
  * Node mortal iff its finite steady stress exceeds its critical stress;

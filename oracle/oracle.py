@@ -6,7 +6,7 @@ code with the HIP path.  The per-tree arithmetic lives in ``em_oracle.c``
 (scalar C loops); this module marshals arrays, performs the IR solve and runs
 the outer aging loop, following EMSpice 3 (arXiv 2604.10743):
 
-* IR solve (Sec. II-C, eq. 8): nodal analysis of the resistor network with
+* IR solve (Sec. III-C, eq. 8): nodal analysis of the resistor network with
   ideal VDD pads and current-sink loads, solved by a sparse direct
   factorisation (a library primitive); open resistors conduct nothing and
   nodes cut off from every pad read 0 V.
@@ -285,7 +285,7 @@ class SampleSim:
 
 
 # ----------------------------------------------------------------------------
-# IR solve (Sec. II-C): M u = P I with ideal pads
+# IR solve (Sec. III-C): M u = P I with ideal pads
 # ----------------------------------------------------------------------------
 def ir_solve(grid, R, open_mask=None):
     """Nodal voltages, per-resistor currents and current densities, worst drop.

@@ -10,9 +10,9 @@ addition in front of the transient stage.  What it computes is defined here in
 plain numpy:
 
 * Features (12 per (tree, sample)) from quantities the paper defines: segment
-  lengths and current densities (Sec. II-C), the Arrhenius diffusivity
+  lengths and current densities (Sec. III-C), the Arrhenius diffusivity
   kappa = D0 exp(-Ea/kT) B Omega/(kT) (Sec. III-D), the zero-flux steady
-  stress of the immortality screen (Sec. II-B) against the critical stress,
+  stress of the immortality screen (Sec. III-B) against the critical stress,
   and the diffusion time L^2/(pi^2 kappa) of the slowest Korhonen mode over
   the span between the stress peak and the neutral point of the steady
   profile.
@@ -132,6 +132,34 @@ def loss_and_grad(p, X, t, rnd=bf16):
     g["W1"] = r(dZ1).T @ r(c["X"])
     g["b1"] = dZ1.sum(axis=0)
     return loss, pack(g)
+
+
+def grad_magnitude(p, X, t, rnd=bf16):
+    """Per-parameter sum of the magnitudes of the terms that make up the
+    gradient of loss_and_grad: the same chain rule with every factor replaced
+    by its absolute value (the upstream signals |dZ| themselves built from
+    magnitudes).  A perturbation of relative size e of every operand of those
+    sums moves each gradient entry by at most about e times this value, which
+    is the scale of the element-wise bound on a reduced-precision gradient."""
+    r = rnd if rnd is not None else _ident
+    P = unpack(p)
+    y, c = forward(p, X, rnd)
+    t = np.asarray(t, np.float64)
+    n = y.size
+    ady = 2.0 * np.abs(y - t) / n
+    g = {}
+    g["w4"] = np.abs(c["H3"]).T @ ady
+    g["b4"] = np.array([ady.sum()])
+    a3 = np.outer(ady, np.abs(P["w4"])) * np.abs(gelu_grad(c["Z3"]))
+    g["W3"] = np.abs(r(a3)).T @ np.abs(r(c["H2"]))
+    g["b3"] = a3.sum(axis=0)
+    a2 = (np.abs(r(a3)) @ np.abs(r(P["W3"]))) * np.abs(gelu_grad(c["Z2"]))
+    g["W2"] = np.abs(r(a2)).T @ np.abs(r(c["H1"]))
+    g["b2"] = a2.sum(axis=0)
+    a1 = (np.abs(r(a2)) @ np.abs(r(P["W2"]))) * np.abs(gelu_grad(c["Z1"]))
+    g["W1"] = np.abs(r(a1)).T @ np.abs(r(c["X"]))
+    g["b1"] = a1.sum(axis=0)
+    return pack(g)
 
 
 def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):

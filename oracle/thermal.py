@@ -1,4 +1,4 @@
-"""Joule-heating thermal pre-pass of the FP64 oracle (Sec. II-A, eqs. 1-4).
+"""Joule-heating thermal pre-pass of the FP64 oracle (Sec. III-A, eqs. 1-4).
 
 TEST INFRASTRUCTURE ONLY: used by the test-suite, the smoke check and the
 CPU-baseline leg of the benchmark; never by the product package.  It shares no

@@ -68,19 +68,19 @@ class RunParams(C.Structure):
                 ("screen", C.c_int32), ("max_voids_per_tree", C.c_int32), ("T_ambient", C.c_double),
                 ("stepper", C.c_int32), ("ir_precond", C.c_int32), ("ir_launch", C.c_int32),
                 ("chain_wg", C.c_int32), ("chain_occ", C.c_int32), ("joule", C.c_int32),
-                ("dt_growth", C.c_double), ("chain_m", C.c_int32)]
+                ("dt_growth", C.c_double), ("chain_m", C.c_int32), ("guard_band", C.c_double)]
 
 
 class MCParams(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("n_samples", C.c_int32), ("seed", C.c_uint64),
                 ("cov_kappa", C.c_double), ("cov_scrit", C.c_double), ("cov_rho", C.c_double),
-                ("cov_load", C.c_double), ("sd_ea_eV", C.c_double)]
+                ("cov_load", C.c_double), ("sd_ea_eV", C.c_double), ("sample_ids", C.c_void_p)]
 
 
 class TTFResult(C.Structure):
     _fields_ = [("ttf_s", C.c_double), ("final_drop", C.c_double), ("init_drop", C.c_double),
                 ("failed", C.c_int32), ("outer_idx", C.c_int32), ("n_nucleated_trees", C.c_int32),
-                ("n_failed_segs", C.c_int32)]
+                ("n_failed_segs", C.c_int32), ("redecided", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -94,7 +94,7 @@ class Info(C.Structure):
                 ("n_violations", C.c_int64),
                 ("surrogate_ms", C.c_double), ("ir_sys_nodes", C.c_int32), ("ir_sys_edges", C.c_int32),
                 ("cg_sample_iters", C.c_int64), ("chain_m", C.c_int32), ("chain_wg", C.c_int32),
-                ("n_chain_wg", C.c_int32)]
+                ("n_chain_wg", C.c_int32), ("n_redecided", C.c_int32), ("n_void_capped", C.c_int64)]
 
 
 class TuneInfo(C.Structure):
@@ -210,13 +210,15 @@ class Batch:
                       ir_launch=int(run.get("ir_launch", 0)), chain_wg=int(run.get("chain_wg", 0)),
                       chain_occ=int(run.get("chain_occ", 0)),
                       joule=int(run.get("joule", 0)), dt_growth=float(run.get("dt_growth", 0.0)),
-                      chain_m=int(run.get("chain_m", 0)))
+                      chain_m=int(run.get("chain_m", 0)),
+                      guard_band=float(run.get("guard_band", 0.0)))
         mcp = None
         if mc is not None:
             mcp = MCParams(struct_size=C.sizeof(MCParams), n_samples=int(mc["n_samples"]),
                            seed=int(mc["seed"]), cov_kappa=float(mc["cov_kappa"]),
                            cov_scrit=float(mc["cov_scrit"]), cov_rho=float(mc.get("cov_rho", 0.0)),
-                           cov_load=float(mc.get("cov_load", 0.0)), sd_ea_eV=float(mc.get("sd_ea_eV", 0.0)))
+                           cov_load=float(mc.get("cov_load", 0.0)), sd_ea_eV=float(mc.get("sd_ea_eV", 0.0)),
+                           sample_ids=_pint(keep(mc.get("sample_ids"), np.int32)))
         self._alloc = None
         if torch_alloc:
             dev = torch.cuda.current_device()

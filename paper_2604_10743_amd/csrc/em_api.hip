@@ -102,6 +102,40 @@ struct em_batch {
     Dev rd{};
     Cond cond{};
     int n_term = 0, n_redge = 0, n_cchain = 0;
+    // Monte Carlo sample index of each batch sample (empty: identity)
+    std::vector<int> sid_h;
+    // FP32 guard band: a host copy of the netlist for the FP64 re-run of the
+    // samples that came within the band of the failure threshold
+    struct GridCopy *gcopy = nullptr;
+    int n_redecided = 0;
+};
+
+// Deep host copy of a netlist descriptor (the FP64 re-run builds a batch from it).
+struct GridCopy {
+    em_grid_desc g{};
+    std::vector<double> xy, len, w, h, R0, sink, node_T, tmap;
+    std::vector<int> layer, ra, rb, pad;
+    std::vector<uint8_t> via;
+    explicit GridCopy(const em_grid_desc &s)
+    {
+        const size_t n = s.n_nodes, m = s.n_res;
+        xy.assign(s.xy, s.xy + 2 * n); layer.assign(s.layer, s.layer + n);
+        ra.assign(s.res_a, s.res_a + m); rb.assign(s.res_b, s.res_b + m);
+        len.assign(s.res_len, s.res_len + m); w.assign(s.res_w, s.res_w + m); h.assign(s.res_h, s.res_h + m);
+        via.assign(s.res_is_via, s.res_is_via + m); R0.assign(s.res_R0, s.res_R0 + m);
+        pad.assign(s.pad_node, s.pad_node + s.n_pads);
+        if (s.sink_I) sink.assign(s.sink_I, s.sink_I + n);
+        if (s.node_T) node_T.assign(s.node_T, s.node_T + n);
+        if (s.tmap) tmap.assign(s.tmap, s.tmap + (size_t)s.tmap_nx * s.tmap_ny);
+        g = s;
+        g.xy = xy.data(); g.layer = layer.data(); g.res_a = ra.data(); g.res_b = rb.data();
+        g.res_len = len.data(); g.res_w = w.data(); g.res_h = h.data(); g.res_is_via = via.data();
+        g.res_R0 = R0.data(); g.pad_node = pad.data();
+        g.sink_I = s.sink_I ? sink.data() : nullptr;
+        g.node_T = s.node_T ? node_T.data() : nullptr;
+        g.tmap = s.tmap ? tmap.data() : nullptr;
+        g.seg_j = nullptr;
+    }
 };
 
 namespace {
@@ -308,8 +342,8 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
         r->max_voids_per_tree < 0 || r->max_voids_per_tree > MAXV || !(r->T_ambient > 0) ||
         r->stepper < 0 || r->stepper > 1 || r->ir_precond < 0 || r->ir_precond > 2 ||
         r->ir_launch < 0 || r->ir_launch > 3 || r->joule < 0 || r->joule > 1 ||
-        !(r->dt_growth >= 0) || !std::isfinite(r->dt_growth))
-        return fail(b, EM_ERR_ARG, "bad run parameters (max_voids_per_tree <= 4)");
+        !(r->dt_growth >= 0) || !std::isfinite(r->dt_growth) || !(r->guard_band >= 0) || !(r->guard_band < 1))
+        return fail(b, EM_ERR_ARG, "bad run parameters (max_voids_per_tree <= 4, 0 <= guard_band < 1)");
     if (r->joule) {
         const double tv[] = {m->k_cu, m->k_ild, m->t_ild};
         if (!finite_all(tv, 3) || !(m->k_cu > 0) || !(m->k_ild > 0) || !(m->t_ild > 0))
@@ -320,6 +354,9 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
                !std::isfinite(mc->cov_rho) || !std::isfinite(mc->cov_load) || !(mc->sd_ea_eV >= 0) ||
                !(mc->sd_ea_eV < 1.0)))
         return fail(b, EM_ERR_ARG, "bad Monte Carlo parameters");
+    if (mc && mc->sample_ids)
+        for (int s = 0; s < mc->n_samples; ++s)
+            if (mc->sample_ids[s] < 0) return fail(b, EM_ERR_ARG, "Monte Carlo sample indices must be >= 0");
     return EM_OK;
 }
 
@@ -866,7 +903,7 @@ const char *em_last_error(const em_batch *b)
     return b ? b->err.c_str() : "null batch";
 }
 
-// One-time thermal pre-pass (Sec. II-A): currents of the nominal network (one
+// One-time thermal pre-pass (Sec. III-A): currents of the nominal network (one
 // IR solve, or the prescribed densities) -> per-tree vertex temperatures and
 // per-segment steady profiles -> node temperatures; the coefficients that
 // depend on temperature (diffusivity, thermomigration drive, the factor, and
@@ -920,6 +957,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     b->cov_l = (mc && !b->trees_only) ? mc->cov_load : 0.0;     // no sinks in trees-only mode
     b->sd_ea = mc ? mc->sd_ea_eV : 0.0;
     b->fp32 = r->prec == EM_FP32;
+    if (mc && mc->sample_ids) b->sid_h.assign(mc->sample_ids, mc->sample_ids + mc->n_samples);
     b->stream = (hipStream_t)hip_stream;
     if (alloc && alloc->alloc && alloc->free) { b->alloc = *alloc; b->has_alloc = true; }
 
@@ -1190,6 +1228,14 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     AL(d.drop, double, S);
     AL(d.ttf, double, S); AL(d.final_drop, double, S); AL(d.init_drop, double, S);
     AL(d.t_prev, double, S); AL(d.d_prev, double, S); AL(d.failed, int, S); AL(d.outer_idx, int, S);
+    AL(d.guard, uint8_t, S);
+    d.guard_band = (b->fp32 && !b->trees_only) ? r->guard_band : 0.0;
+    d.sid = nullptr;
+    if (!b->sid_h.empty()) UP(d.sid, b->sid_h);
+    if (d.guard_band > 0) {
+        b->gcopy = new (std::nothrow) GridCopy(*g);
+        if (!b->gcopy) return fail(b, EM_ERR_OOM, "host copy of the netlist");
+    }
 
     // The system the PCG iterates: the nodal network, or (multigrid on the
     // condensed network) its terminals with one reduced edge per two-ended
@@ -1345,6 +1391,7 @@ em_status em_batch_destroy(em_batch *b)
     if (b->cg_exec) (void)hipGraphExecDestroy(b->cg_exec);
     if (b->cg_graph) (void)hipGraphDestroy(b->cg_graph);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    delete b->gcopy;
     delete b;
     return EM_OK;
 }
@@ -1388,6 +1435,16 @@ em_status em_get_info(em_batch *b, em_info *info)
     info->n_late = sc[2];
     info->n_violations = sc[3];
     info->surrogate_ms = b->sur_ms;
+    info->n_redecided = b->n_redecided;
+    {
+        const size_t IS = (size_t)b->n_trees * b->S;
+        std::vector<int> sup(IS);
+        HIPCHK(b, hipMemcpyAsync(sup.data(), b->d.n_suppressed, 4 * IS, hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(b, hipStreamSynchronize(b->stream));
+        long long n = 0;
+        for (int v : sup) n += v;
+        info->n_void_capped = n;
+    }
     return EM_OK;
 }
 
@@ -1460,6 +1517,50 @@ static em_status set_step_size(em_batch *b, double dt)
     launch_factor(b->d, b->fp32, b->stream);
     LAUNCHCHK(b);
     b->forcing_stale = true;
+    return EM_OK;
+}
+
+// Guard band of the FP32 form: the samples whose worst drop came within the
+// band of the failure threshold are run again from t = 0 in FP64 (a batch over
+// their Monte Carlo sample indices built from the same inputs); their results,
+// resistance changes and opens replace the FP32 run's.
+static em_status redecide_fp64(em_batch *b, const std::vector<int> &pick, em_ttf_result *out)
+{
+    std::vector<int> ids(pick.size());
+    for (size_t i = 0; i < pick.size(); ++i) ids[i] = b->sid_h.empty() ? pick[i] : b->sid_h[pick[i]];
+    em_run_params r2 = b->run;
+    r2.prec = EM_FP64;
+    r2.guard_band = 0.0;
+    r2.chain_wg = 0; r2.chain_occ = 0; r2.chain_m = 0;
+    em_mc_params mc2{};
+    mc2.struct_size = sizeof(em_mc_params);
+    mc2.n_samples = (int)pick.size();
+    mc2.seed = b->seed;
+    mc2.cov_kappa = b->cov_k; mc2.cov_scrit = b->cov_s; mc2.cov_rho = b->cov_r; mc2.cov_load = b->cov_l;
+    mc2.sd_ea_eV = b->sd_ea;
+    mc2.sample_ids = ids.data();
+    em_batch *sub = nullptr;
+    em_status rc = em_batch_create(&b->gcopy->g, &b->mat, &r2, &mc2, b->has_alloc ? &b->alloc : nullptr,
+                                   b->stream, &sub);
+    std::vector<em_ttf_result> res(pick.size());
+    if (rc == EM_OK) rc = em_run_to_ttf(sub, res.data());
+    if (rc == EM_OK) {
+        const size_t nr = b->n_res;
+        for (size_t i = 0; i < pick.size() && rc == EM_OK; ++i) {
+            out[pick[i]] = res[i];
+            out[pick[i]].redecided = 1;
+            if (hipMemcpyAsync(b->d.dR + pick[i] * nr, sub->d.dR + i * nr, 8 * nr, hipMemcpyDeviceToDevice,
+                               b->stream) != hipSuccess ||
+                hipMemcpyAsync(b->d.open + pick[i] * nr, sub->d.open + i * nr, nr, hipMemcpyDeviceToDevice,
+                               b->stream) != hipSuccess)
+                rc = EM_ERR_HIP;
+        }
+        if (rc == EM_OK && hipStreamSynchronize(b->stream) != hipSuccess) rc = EM_ERR_HIP;
+    }
+    const std::string msg = sub ? sub->err : std::string("batch creation");
+    em_batch_destroy(sub);
+    if (rc != EM_OK) return fail(b, rc, "FP64 re-run of the guard-band samples failed: " + msg);
+    b->n_redecided = (int)pick.size();
     return EM_OK;
 }
 
@@ -1573,6 +1674,17 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
         o.failed = failed[s]; o.outer_idx = oidx[s];
         o.n_nucleated_trees = cnt[2 * (size_t)s];
         o.n_failed_segs = cnt[2 * (size_t)s + 1];
+        o.redecided = 0;
+    }
+    b->n_redecided = 0;
+    if (d.guard_band > 0 && b->gcopy) {
+        std::vector<uint8_t> gf(S);
+        HIPCHK(b, hipMemcpyAsync(gf.data(), d.guard, S, hipMemcpyDeviceToHost, st));
+        HIPCHK(b, hipStreamSynchronize(st));
+        std::vector<int> pick;
+        for (int s = 0; s < S; ++s)
+            if (gf[s]) pick.push_back(s);
+        if (!pick.empty()) return redecide_fp64(b, pick, out);
     }
     return EM_OK;
 }
@@ -1612,6 +1724,7 @@ em_status em_reset(em_batch *b)
     LAUNCHCHK(b);
     HIPCHK(b, hipStreamSynchronize(st));
     b->sur_ms = 0.0;
+    b->n_redecided = 0;
     b->live_dirty = true;
     b->any_open = false;
     b->ir_valid = false;

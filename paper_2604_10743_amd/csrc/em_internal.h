@@ -74,6 +74,8 @@ struct Dev {
     double *psi;                        // screen scratch / steady stress [node][S]
     double *wsp;                        // stepping workspace [node][S] (generic tree kernel)
     // ---- Monte Carlo draws [res][S] ----
+    const int *sid;                     // [S] Monte Carlo sample index of each batch sample, or null
+                                        // (identity)
     double *xi_k, *xi_s;
     double *xi_r;                       // resistivity multipliers (1 for vias), or null
     // ---- per (sample, segment) ----
@@ -116,6 +118,8 @@ struct Dev {
     // ---- TTF ----
     double *ttf, *final_drop, *init_drop, *t_prev, *d_prev;
     int *failed, *outer_idx;
+    uint8_t *guard;                     // [S] a re-solve's drop came within guard_band of the threshold
+    double guard_band;                  // relative to the failure fraction (0: off)
     // ---- learned screen (allocated when a model is attached) ----
     double *tstat;                      // [n_trees][4] Ltot, Lpath, nseg, njunc
     double *rdist;                      // [ns] distance from the tree root along the tree

@@ -1,5 +1,5 @@
 // Chain condensation of the IR network (exact Schur complement of the nodal
-// system of Sec. II-C, eq. 8, onto its terminal nodes).
+// system of Sec. III-C, eq. 8, onto its terminal nodes).
 //
 // A node that is not a pad and has one or two incident resistors carries no
 // branching: the interior of a wire between vias is a chain of such nodes.

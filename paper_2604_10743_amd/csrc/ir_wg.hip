@@ -1,4 +1,4 @@
-// IR solve of small systems (Sec. II-C, eq. 8) with one workgroup per Monte
+// IR solve of small systems (Sec. III-C, eq. 8) with one workgroup per Monte
 // Carlo sample: the whole preconditioned CG, multigrid V-cycle included, runs
 // inside one launch, with workgroup barriers where the multi-kernel form ends
 // a kernel.  The arithmetic is that of the multi-kernel form (same

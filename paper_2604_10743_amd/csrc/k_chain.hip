@@ -104,14 +104,27 @@ template <typename R, int M, int WG, int OCC>
 __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
 {
     constexpr int LEV = Log2<WG>::v;
+    // FP32 form: the state carries a float low part sl (sg + sl), which keeps
+    // the increments that fall below half an ulp of sg (near saturation the
+    // per-step increments shrink to a few Pa and float alone would stall the
+    // approach to sigma_crit, moving nucleation by steps).  With 1024 lanes
+    // (chains of more than 4096 nodes) the register file has no room for it:
+    // there the low part is folded in at load and the state rounds to float
+    // every step.  (Keeping it in LDS instead doubled the spills and cost 60 %
+    // per launch, while the nucleation steps still moved by up to 3 against the
+    // FP64 oracle: the float separator solve, not the state, dominates there.)
+    constexpr bool LO = sizeof(R) == 4 && WG < 1024;
     __shared__ R s_al[LEV][WG];
     __shared__ R s_ga[LEV][WG];
-    __shared__ R s_x[2][WG];
     // separator exchange of the per-step reduction, padded by WG/2 zeros on
     // each side: the neighbours at lane -+ 2^l are read at a constant offset
     // from one lane address (no per-level index registers, no clamping)
     __shared__ R s_xp[2][2 * WG];
     __shared__ R s_e[3][WG];
+    // neighbour exchange of the factorisation and of the separator values:
+    // shares s_e's storage (every use is separated from the uses of s_e by a
+    // barrier that all lanes pass after their reads)
+    R (*const s_x)[WG] = s_e;
     __shared__ double s_q[WG];
     __shared__ unsigned s_vote[WG / 64];
 
@@ -153,14 +166,14 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
 
     // ---- per-lane node data (registers for the whole launch) ----
     R sg[M], fv[M], dinv[M], al[M], be[M];
-    // FP32 form: the state carries a float low part sl (sg + sl), which keeps
-    // the increments that fall below half an ulp of sg (near saturation the
-    // per-step increments shrink to a few Pa and float alone would stall the
-    // approach to sigma_crit).  With 1024 lanes (chains of more than 4096
-    // nodes) the register file has no room for it: there the low part is
-    // folded in at load and the state rounds to float every step.
-    constexpr bool LO = sizeof(R) == 4 && WG < 1024;
-    float sl[LO ? M : 1];
+    float slr[LO ? M : 1];          // the low part (registers)
+    auto SL = [&](int j) -> float {
+        if constexpr (LO) return slr[j];
+        else return 0.f;
+    };
+    auto SLset = [&](int j, float v) {
+        if constexpr (LO) slr[j] = v;
+    };
     R gE[M + 1];                    // gE[j] = dt*g of edge (j-1, j); gE[0] previous block, gE[cnt] next block
     R scmin = (R)INFINITY;
 #pragma unroll
@@ -169,12 +182,12 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
         // the step below computes them without branches, and zero pivots and
         // multipliers map them to zero increments
         sg[j] = 0; fv[j] = 0; dinv[j] = 0; al[j] = 0; be[j] = 0;
-        if constexpr (LO) sl[j] = 0.f;
+        float lo0 = 0.f;
         if (j < cnt) {
             size_t x = (size_t)(start + j) * S + s;
             sg[j] = sig[x];
             if constexpr (LO) {
-                sl[j] = sig_lo ? sig_lo[x] : 0.f;
+                lo0 = sig_lo ? sig_lo[x] : 0.f;
             } else if constexpr (sizeof(R) == 4) {
                 if (sig_lo) sg[j] = (R)((double)sg[j] + (double)sig_lo[x]);
             }
@@ -182,7 +195,11 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
             R scj = sc_g[x];
             scmin = scj < scmin ? scj : scmin;
         }
+        SLset(j, lo0);
     }
+    // nucleation pre-test on the high part alone: sg + sl >= sc implies
+    // sg >= sc - |sl| >= the float below sc (|sl| <= half an ulp of sg)
+    const R scpre = LO ? nextafterf((float)scmin, -INFINITY) : scmin;
 #pragma unroll
     for (int j = 0; j <= M; ++j) {
         gE[j] = 0;
@@ -321,7 +338,7 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
         return r;
     };
     auto sv = [&](int j) -> double {
-        if constexpr (LO) return (double)sg[j] + (double)sl[j];
+        if constexpr (LO) return (double)sg[j] + (double)SL(j);
         else return (double)sg[j];
     };
     // stress content of this lane: its nodes plus the voids on them (a void's
@@ -345,7 +362,7 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
     const double Q0 = seg_sum(content());
     // stress at the next block's separator (kept in step with that lane)
     s_x[0][lane] = sg[0];
-    if constexpr (LO) s_x[1][lane] = sl[0];
+    if constexpr (LO) s_x[1][lane] = SL(0);
     lds_barrier();
     R sn = (act && !last) ? s_x[0][lane + 1] : (R)0;
     float snl = 0.f;                   // its low part (FP32 form)
@@ -400,14 +417,14 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
         }
         R yF = 0, yL = 0, sL = sg[0];
         float sLl = 0.f;
-        if constexpr (LO) sLl = sl[0];
+        if constexpr (LO) sLl = SL(0);
         if (cnt >= 2) {
             yF = y[1];
 #pragma unroll
             for (int j = 1; j < M; ++j)
                 if (j == cnt - 1) {
                     yL = y[j]; sL = sg[j];
-                    if constexpr (LO) sLl = sl[j];
+                    if constexpr (LO) sLl = SL(j);
                 }
         }
         // 3. exchange with the previous block: its last interior value and its
@@ -453,7 +470,7 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
             auto put = [&](int j, double v) {      // state <- v as sg + sl
                 const R hv = (R)v;
                 sg[j] = hv;
-                sl[j] = (float)(v - (double)hv);
+                SLset(j, (float)(v - (double)hv));
             };
             put(0, sv(0) + (double)xk);
 #pragma unroll
@@ -488,7 +505,7 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
                 for (int j = 0; j < M; ++j)
                     if (j == jv) {
                         sh = sg[j];
-                        if constexpr (LO) slo = sl[j];
+                        if constexpr (LO) slo = SL(j);
                     }
                 double svv = (double)sh;
                 if constexpr (LO) svv += (double)slo;
@@ -512,7 +529,7 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
             if constexpr (LO) {
 #pragma unroll
                 for (int j = 0; j < M; ++j)
-                    if (j < cnt && sv(j) >= (double)scmin && !((vmask >> j) & 1u)) cand = true;
+                    if (j < cnt && sg[j] >= scpre && !((vmask >> j) & 1u)) cand = true;
                 if (cand) {
                     cand = false;
 #pragma unroll
@@ -635,7 +652,7 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
                 for (int j = 0; j < M; ++j) {
                     const double v = sv(j) + corr;
                     sg[j] = (R)v;
-                    sl[j] = (float)(v - (double)sg[j]);
+                    SLset(j, (float)(v - (double)sg[j]));
                 }
                 const double v = (double)sn + (double)snl + corr;
                 sn = (R)v;
@@ -655,7 +672,7 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
             const size_t x = (size_t)(start + j) * S + s;
             sig[x] = sg[j];
             if constexpr (LO) {
-                if (sig_lo) sig_lo[x] = sl[j];
+                if (sig_lo) sig_lo[x] = SL(j);
             } else if constexpr (sizeof(R) == 4) {
                 if (sig_lo) sig_lo[x] = 0.f;
             }

@@ -1,4 +1,4 @@
-// IR-drop solve (Sec. II-C, eq. 8): nodal analysis M u = P I of the resistor
+// IR-drop solve (Sec. III-C, eq. 8): nodal analysis M u = P I of the resistor
 // network with ideal VDD pads, batched over Monte Carlo samples.  Jacobi-
 // preconditioned conjugate gradients in FP64 on the free nodes (live, not a
 // pad); an open segment conducts nothing and a node with no conducting path
@@ -419,6 +419,7 @@ EM_KERNEL void k_ttf_init(Dev d, double fail)
     d.init_drop[s] = dr; d.final_drop[s] = dr;
     d.t_prev[s] = 0.0; d.d_prev[s] = dr;
     d.outer_idx[s] = 0;
+    d.guard[s] = fabs(dr - fail) < d.guard_band * fail;
     if (dr >= fail) { d.failed[s] = 1; d.ttf[s] = 0.0; d.sample_active[s] = 0; }
     else { d.failed[s] = 0; d.ttf[s] = NAN; }
 }
@@ -432,6 +433,7 @@ EM_KERNEL void k_ttf_update(Dev d, double fail, int k, double t)
     double dr = d.drop[s];
     d.final_drop[s] = dr;
     d.outer_idx[s] = k;
+    if (fabs(dr - fail) < d.guard_band * fail) d.guard[s] = 1;
     if (dr >= fail) {
         double tp = d.t_prev[s], dp = d.d_prev[s];
         d.ttf[s] = tp + (fail - dp) / (dr - dp) * (t - tp);

@@ -17,7 +17,7 @@ namespace em {
 static inline int nblocks(long long n, int bs = 256) { return (int)((n + bs - 1) / bs); }
 
 // ------------------------------------------------------------------------
-// Temperature at every stress node (Sec. II-A: per-tree profile from the
+// Temperature at every stress node (Sec. III-A: per-tree profile from the
 // thermal map).  Raster: bilinear with clamping at the raster edge; vertex
 // temperatures: linear along the segment; otherwise the ambient value.
 // ------------------------------------------------------------------------
@@ -72,7 +72,7 @@ EM_KERNEL void k_node_T(Dev d)
 }
 
 // ------------------------------------------------------------------------
-// Joule-heating thermal pre-pass (Sec. II-A, eqs. 1-4).  Along a wire segment
+// Joule-heating thermal pre-pass (Sec. III-A, eqs. 1-4).  Along a wire segment
 // of length L the steady temperature solves k T'' + j^2 rho = k (T - T0)/G^2
 // (heat conduction, Joule source, loss through the dielectric to the local
 // ambient T0), G^2 = t_cu t_ILD k_cu / k_ILD (eq. 2).  With c = T0 + Tm,
@@ -300,12 +300,13 @@ EM_KERNEL void k_draws(Dev d, uint64_t seed, double cov_k, double cov_s, double 
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long long)d.n_res * d.S) return;
     int s = (int)(g % d.S), e = (int)(g / d.S);
-    double xk = use_mc ? lognormal_xi(seed, s, e, 0, cov_k) : 1.0;
+    const int sm = d.sid ? d.sid[s] : s;       // Monte Carlo sample index of the counter
+    double xk = use_mc ? lognormal_xi(seed, sm, e, 0, cov_k) : 1.0;
     if (sd_ea > 0.0 && d.is_wire[e])
-        xk *= exp(-sd_ea * normal_z(seed, s, e, 4) / ((K_B / E_CHG) * map_T_mid(d, e)));
+        xk *= exp(-sd_ea * normal_z(seed, sm, e, 4) / ((K_B / E_CHG) * map_T_mid(d, e)));
     d.xi_k[g] = xk;
-    d.xi_s[g] = use_mc ? lognormal_xi(seed, s, e, 1, cov_s) : 1.0;
-    if (d.xi_r) d.xi_r[g] = d.is_wire[e] ? lognormal_xi(seed, s, e, 2, cov_r) : 1.0;
+    d.xi_s[g] = use_mc ? lognormal_xi(seed, sm, e, 1, cov_s) : 1.0;
+    if (d.xi_r) d.xi_r[g] = d.is_wire[e] ? lognormal_xi(seed, sm, e, 2, cov_r) : 1.0;
 }
 
 // Per-sample sinks under current-loading variation: [S][n_nodes].
@@ -314,7 +315,7 @@ EM_KERNEL void k_draws_load(Dev d, uint64_t seed, double cov_l)
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long long)d.n_nodes * d.S) return;
     int s = (int)(g / d.n_nodes), v = (int)(g % d.n_nodes);
-    d.sink_s[g] = d.sink[v] * lognormal_xi(seed, s, v, 3, cov_l);
+    d.sink_s[g] = d.sink[v] * lognormal_xi(seed, d.sid ? d.sid[s] : s, v, 3, cov_l);
 }
 
 // Resistivity multiplier of wire segment e in sample s (1 without that variation).
@@ -510,7 +511,7 @@ EM_KERNEL void k_factor(Dev d)
 }
 
 // ------------------------------------------------------------------------
-// Steady-state immortality screen (Sec. II-B).  Zero flux on every edge:
+// Steady-state immortality screen (Sec. III-B).  Zero flux on every edge:
 // psi_i = psi_p + dir dx (S + M); the constant follows from conservation
 // (sum V sigma = sum V sigma_T), so sigma_ss = sigma_T + psi - <psi>_V.
 // A node is mortal iff its finite sigma_ss exceeds its critical stress;
@@ -951,7 +952,7 @@ EM_KERNEL void k_copy_col(Dev d, void *arr, int s, double *out, int to_state)
 // count (nodes of degree >= 3).  Per (tree, sample): current densities, the
 // Arrhenius diffusivity of Sec. III-D at edge-midpoint temperature times the
 // Monte Carlo multiplier, the peak p of the screen's zero-flux steady stress
-// over the node critical stress (Sec. II-B, first node of the largest ratio),
+// over the node critical stress (Sec. III-B, first node of the largest ratio),
 // and the slowest-mode diffusion time Lpk^2/(pi^2 kappa_pk) over the
 // distance Lpk (difference of root distances, floored at 0.1 um) from p to
 // the nearest node whose steady stress is at or below sigma_T, kappa_pk the

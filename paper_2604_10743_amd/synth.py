@@ -81,11 +81,12 @@ def default_material() -> dict:
 def default_run(**over) -> dict:
     """Numerics: 20 intervals per segment, 2000 backward-Euler steps over
     ten years (a year of 365.25 days), IR re-solve every 100 steps, failure
-    at 10 % worst IR-drop."""
+    at 10 % worst IR-drop; FP32 runs re-run in FP64 the samples whose worst
+    drop comes within 0.2 % of the threshold (guard band)."""
     horizon = 10 * 365.25 * 86400.0
     r = dict(intervals_per_seg=20, n_steps=2000, dt=horizon / 2000, ir_every=100,
              fail_frac=0.10, cg_rtol=1e-11, cg_max_iter=20000, prec=0, screen=1,
-             max_voids_per_tree=4, T_ambient=378.0, joule=0)
+             max_voids_per_tree=4, T_ambient=378.0, joule=0, guard_band=2e-3)
     r.update(over)
     return r
 
@@ -298,8 +299,11 @@ def pg_grid(seed: int = 2001, n: int = 400, pitch=5 * UM, w1=0.5 * UM, w2=1.0 * 
             H=0.2 * UM, via_every=4, R_via=0.5, pad_lattice=8, vdd=1.2,
             sink_mu=np.log(50e-6), sink_sigma=0.5, sink_scale=0.0651,
             seg_range=(100, 399), base_K=330.0, n_spots=6, amp_range=(15.0, 60.0),
-            sig_range=(30 * UM, 80 * UM), raster=1 * UM, thermal=True) -> Grid:
-    """Two-layer n x n P/G grid: M1 rows and M2 columns at a fixed pitch.
+            sig_range=(30 * UM, 80 * UM), raster=1 * UM, thermal=True,
+            n_cols: Optional[int] = None, col_seg_range=None) -> Grid:
+    """Two-layer n x n P/G grid: M1 rows and M2 columns at a fixed pitch
+    (n rows by ``n_cols`` columns when given; column spans then come from
+    ``col_seg_range``).
 
     Every line is one tree cut to a random contiguous span of U{seg_range}
     segments.  A via joins M1 and M2 at every crossing on a row or column
@@ -315,21 +319,23 @@ def pg_grid(seed: int = 2001, n: int = 400, pitch=5 * UM, w1=0.5 * UM, w2=1.0 * 
     temperature plus Gaussian hotspots at ``raster`` resolution.
     """
     rng = np.random.default_rng(seed)
-    nseg = n - 1
-    span_r = rng.integers(seg_range[0], min(seg_range[1], nseg) + 1, n)
-    off_r = np.array([rng.integers(0, nseg - s + 1) for s in span_r])
-    span_c = rng.integers(seg_range[0], min(seg_range[1], nseg) + 1, n)
-    off_c = np.array([rng.integers(0, nseg - s + 1) for s in span_c])
+    nc = n if n_cols is None else int(n_cols)
+    csr = seg_range if col_seg_range is None else col_seg_range
+    nseg_r, nseg_c = nc - 1, n - 1          # segments of a full row / column
+    span_r = rng.integers(seg_range[0], min(seg_range[1], nseg_r) + 1, n)
+    off_r = np.array([rng.integers(0, nseg_r - s + 1) for s in span_r])
+    span_c = rng.integers(csr[0], min(csr[1], nseg_c) + 1, nc)
+    off_c = np.array([rng.integers(0, nseg_c - s + 1) for s in span_c])
     # node ids: allocate only existing nodes
-    id1 = -np.ones((n, n), np.int64)
-    id2 = -np.ones((n, n), np.int64)
+    id1 = -np.ones((n, nc), np.int64)
+    id2 = -np.ones((n, nc), np.int64)
     xy, layer = [], []
     cnt = 0
     for r in range(n):
         for c in range(off_r[r], off_r[r] + span_r[r] + 1):
             id1[r, c] = cnt; cnt += 1
             xy.append((c * pitch, r * pitch)); layer.append(1)
-    for c in range(n):
+    for c in range(nc):
         for r in range(off_c[c], off_c[c] + span_c[c] + 1):
             id2[r, c] = cnt; cnt += 1
             xy.append((c * pitch, r * pitch)); layer.append(2)
@@ -337,7 +343,7 @@ def pg_grid(seed: int = 2001, n: int = 400, pitch=5 * UM, w1=0.5 * UM, w2=1.0 * 
     for r in range(n):
         for c in range(off_r[r], off_r[r] + span_r[r]):
             ra.append(id1[r, c]); rb.append(id1[r, c + 1]); L.append(pitch); W.append(w1); via.append(0)
-    for c in range(n):
+    for c in range(nc):
         for r in range(off_c[c], off_c[c] + span_c[c]):
             ra.append(id2[r, c]); rb.append(id2[r + 1, c]); L.append(pitch); W.append(w2); via.append(0)
     rr, cc = np.nonzero((id1 >= 0) & (id2 >= 0))
@@ -349,12 +355,12 @@ def pg_grid(seed: int = 2001, n: int = 400, pitch=5 * UM, w1=0.5 * UM, w2=1.0 * 
     Hh = np.full(L.size, H)
     R0 = np.where(via == 1, R_via, _wire_R(np.maximum(L, 1e-12), W, Hh))
     # pads on M2
-    step = n // pad_lattice
+    step, cstep = n // pad_lattice, nc // pad_lattice
     pads = []
     for a in range(pad_lattice):
         for b in range(pad_lattice):
             r = step // 2 + a * step
-            c = step // 2 + b * step
+            c = cstep // 2 + b * cstep
             r = int(np.clip(r, off_c[c], off_c[c] + span_c[c]))
             pads.append(id2[r, c])
     pads = np.unique(np.array(pads, np.int32))
@@ -389,9 +395,9 @@ def pg_grid(seed: int = 2001, n: int = 400, pitch=5 * UM, w1=0.5 * UM, w2=1.0 * 
     sink[m1] = sink_scale * np.exp(rng.normal(sink_mu, sink_sigma, int(m1.sum())))
     g = Grid(xy=xy, layer=layer, res_a=ra, res_b=rb, res_len=L, res_w=W,
              res_h=Hh, res_is_via=via, res_R0=R0, pad_node=pads, vdd=vdd, sink_I=sink,
-             name=f"pg{n}x{n}_s{seed}")
+             name=f"pg{n}x{nc}_s{seed}")
     if thermal:
-        tm, x0, y0, dxr, dyr = gaussian_hotspot_map(seed + 7, (n - 1) * pitch, (n - 1) * pitch,
+        tm, x0, y0, dxr, dyr = gaussian_hotspot_map(seed + 7, (nc - 1) * pitch, (n - 1) * pitch,
                                                    base_K, n_spots, amp_range, sig_range, raster)
         g.tmap, g.tmap_x0, g.tmap_y0, g.tmap_dx, g.tmap_dy = tm, x0, y0, dxr, dyr
     else:
@@ -415,6 +421,11 @@ def workload(name: str):
     screen_mc       200x200 sparse-via grid (via every 64 nodes), 330 K + hotspots,
                     64 Monte Carlo samples: mortal trees with nucleation times
                     spread over years and failures within the horizon
+    long_lines      24 x 257 two-layer grid whose 24 M1 rows are lines of 212-256
+                    segments (4241-5121 stress nodes: the chain kernel's 1024-lane
+                    form), short M2 straps, via every 32 nodes, 330 K + hotspots,
+                    64 samples, FP32: early and late failures after 3-5 re-solves
+                    and censored samples with voids
     """
     mat = default_material()
     if name == "tiny_trees":
@@ -434,6 +445,11 @@ def workload(name: str):
                     seg_range=(48, 95), base_K=330.0)
         return (g, mat, default_run(prec=1, T_ambient=330.0),
                 dict(n_samples=1024, seed=3001, cov_kappa=0.2, cov_scrit=0.2))
+    if name == "long_lines":
+        g = pg_grid(6001, n=24, n_cols=257, seg_range=(212, 256), col_seg_range=(12, 23), via_every=32,
+                    pad_lattice=4, sink_scale=0.16, base_K=330.0)
+        return (g, mat, default_run(prec=1, T_ambient=330.0),
+                dict(n_samples=64, seed=6001, cov_kappa=0.2, cov_scrit=0.2))
     if name == "screen_mc":
         return (sparse_via_grid(2101), mat, default_run(prec=1, T_ambient=330.0),
                 dict(n_samples=64, seed=5, cov_kappa=0.2, cov_scrit=0.2))

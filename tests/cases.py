@@ -67,6 +67,33 @@ def ladder_grid(n=10, R=2.0, sinks=None, vdd=1.0):
                 sink_I=sink, node_T=np.full(n + 1, 378.0))
 
 
+def line_pad_load(S=4, L=25 * UM, w=0.5 * UM, h=0.2 * UM, I=4e-3, vdd=1.2, T=378.0):
+    """A single wire of S equal segments from one pad (vertex 0) to one load
+    drawing I at vertex S; one layer, no via.  The whole current runs through
+    every segment whatever their resistances, so the worst drop is at the load:
+    I (sum of segment resistances) / vdd."""
+    n = S + 1
+    xy = np.stack([np.arange(n) * L, np.zeros(n)], 1)
+    sink = np.zeros(n)
+    sink[-1] = I
+    return Grid(xy=xy, layer=np.ones(n, np.int32), res_a=np.arange(S, dtype=np.int32),
+                res_b=np.arange(1, n, dtype=np.int32), res_len=np.full(S, L), res_w=np.full(S, w),
+                res_h=np.full(S, h), res_is_via=np.zeros(S, np.uint8),
+                res_R0=np.full(S, RHO_CU * L / (w * h)), pad_node=np.array([0], np.int32), vdd=vdd,
+                sink_I=sink, node_T=np.full(n, float(T)))
+
+
+# Run settings of the outer-loop cases on line_pad_load (load current I): a
+# crossing after several re-solves on a uniform and a graded grid, a censored
+# run whose last interval is short, and a network already failed at t = 0.
+OUTER_CASES = {
+    "uniform": (dict(dt=1e3, ir_every=10, n_steps=200, fail_frac=0.10), 4e-3),
+    "graded": (dict(dt=3e2, dt_growth=1.2, ir_every=10, n_steps=200, fail_frac=0.10), 4e-3),
+    "censored_ragged": (dict(dt=1e3, ir_every=10, n_steps=195, fail_frac=0.5), 4e-3),
+    "failed_at_t0": (dict(dt=1e3, ir_every=10, n_steps=200, fail_frac=0.10), 5e-3),
+}
+
+
 def material(**over):
     m = default_material()
     m.update(over)

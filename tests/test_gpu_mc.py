@@ -1,11 +1,13 @@
 """Batched Monte Carlo at full size against the FP64 oracle: the 96x96
 sparse-via grid with 1024 samples (20 % lognormal variation in kappa and
 sigma_crit), run in one FP32 batch exactly as the benchmark runs it; every
-16th sample (64 samples) is recomputed by the oracle one by one."""
-import math
-
+16th sample (64 samples) is recomputed by the oracle one by one; samples
+whose worst drop came within the guard band of the threshold were re-run by
+the library in FP64 and are held to the FP64 tolerance."""
 import numpy as np
 import pytest
+
+import ttf_check
 
 from paper_2604_10743_amd import synth
 
@@ -29,23 +31,12 @@ def test_mc_grid_1024_samples_vs_oracle(em, oracle_mod):
     B.close()
     topo = oracle_mod.topology(g, rn["intervals_per_seg"])
     n_fail = n_cmp = 0
+    info_redecided = sum(r["redecided"] for r in res)
     for s in range(0, 1024, 16):
         ref = oracle_mod.run_sample(g, mat, rn, mc, s, topo=topo)
-        r = res[s]
-        # a failure decision whose FP64 drop lies within 0.2 % of the
-        # threshold at some re-solve is not decided reliably in FP32
-        if np.min(np.abs(np.asarray(ref["drops"]) - rn["fail_frac"])) < 2e-3 * rn["fail_frac"]:
-            continue
         n_cmp += 1
-        assert r["failed"] == ref["failed"], s
         n_fail += ref["failed"]
-        assert abs(r["init_drop"] - ref["init_drop"]) <= 1e-9 * ref["init_drop"], s
-        assert abs(r["final_drop"] - ref["final_drop"]) <= 1e-3 * ref["final_drop"], s
-        if ref["failed"]:
-            assert abs(r["ttf_s"] - ref["ttf"]) <= 1e-3 * ref["ttf"], s
-            assert r["outer_idx"] == ref["outer_idx"], s
-        else:
-            assert math.isnan(r["ttf_s"]), s
-        assert np.array_equal(segs[s], ref["failed_segs"]), s
-    print(f"compared {n_cmp} of 64 samples, {n_fail} failed", flush=True)
-    assert n_cmp >= 60 and 10 <= n_fail <= n_cmp - 10
+        ttf_check.check(res[s], ref, segs[s], rn["prec"], rn, s)
+    print(f"compared {n_cmp} of 64 samples, {n_fail} failed; {info_redecided} of 1024 re-run in FP64",
+          flush=True)
+    assert 10 <= n_fail <= n_cmp - 10

@@ -10,7 +10,9 @@ import sys
 import numpy as np
 import pytest
 
-from cases import line_grid, material, run, tree_from_edges
+import ttf_check
+
+from cases import OUTER_CASES, line_grid, line_pad_load, material, run, tree_from_edges
 from paper_2604_10743_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -323,19 +325,11 @@ def test_mc_run_fp32_vs_oracle(em, oracle_mod):
     for s in range(0, 96, 6):
         ref = oracle_mod.run_sample(g, mat, rn, mc, s, topo=topo)
         r = res[s]
-        # guard band: a failure decision whose FP64 drop lies within 0.2 % of
-        # the threshold is not decided reliably from FP32 stress; skip it
-        if np.min(np.abs(np.asarray(ref["drops"]) - rn["fail_frac"])) < 2e-3 * rn["fail_frac"]:
-            continue
         n_cmp += 1
-        assert r["failed"] == ref["failed"], s
         n_fail += ref["failed"]
-        assert abs(r["final_drop"] - ref["final_drop"]) <= 1e-3 * ref["final_drop"], s
-        if ref["failed"]:
-            assert abs(r["ttf_s"] - ref["ttf"]) <= 1e-3 * ref["ttf"], s
         dR, op = B.seg_state(s)
-        assert np.array_equal(np.nonzero((dR > 0) | (op != 0))[0], ref["failed_segs"]), s
-    assert n_fail > 0 and n_cmp >= 12
+        ttf_check.check(r, ref, np.nonzero((dR > 0) | (op != 0))[0], 1, rn, s)
+    assert n_fail > 0 and n_cmp == 16
 
 
 # ----------------------------------------------------------------- FP32 forms
@@ -408,3 +402,73 @@ def test_pg400_full_size_fp32_sampled_trees(em, oracle_mod):
         worst = max(worst, np.max(np.abs(sig[sl] - ref[sl])) / np.max(np.abs(ref[sl])))
     print(f"pg400 sampled trees: worst per-tree relative error {worst:.3e}, drop {drop:.6f} vs {d_o:.6f}")
     assert worst <= TOL_FP32_LONG_CHAIN
+
+
+# ------------------------------------------------- outer loop, both forms
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("case", ["uniform", "graded", "censored_ragged", "failed_at_t0"])
+def test_outer_loop_cases_vs_oracle(em, oracle_mod, case, prec):
+    """The pad-to-load line of the oracle's outer-loop pins: a crossing after
+    several re-solves (uniform and graded grids), a censored run with a ragged
+    last interval, and a failure at t = 0."""
+    over, I = OUTER_CASES[case]
+    g = line_pad_load(I=I, vdd=1.2 if case != "failed_at_t0" else 1.0)
+    mat = material(sigma_crit=200e6)
+    rn = run(intervals_per_seg=10, screen=1, prec=prec, **over)
+    _flush(f"outer loop {case} prec {prec}")
+    B = em.Batch(g, mat, rn)
+    r = B.run_to_ttf()[0]
+    segs = B.failed_segments(0)
+    B.close()
+    ref = oracle_mod.run_sample(g, mat, rn)
+    ttf_check.check(r, ref, segs, prec, rn, case)
+
+
+# ------------------------------- FP32 1024-lane chain form through failure
+@pytest.mark.parametrize("chain_m", [8, 9])
+def test_long_lines_fp32_1024_lane_form_to_ttf(em, oracle_mod, chain_m):
+    """Lines of 4241-5121 stress nodes take the chain kernel's 1024-lane form
+    (8- or 9-node lane blocks).  Every sample runs through nucleation, void
+    growth, early and late failure and re-solves to its TTF or the horizon,
+    against the FP64 oracle: TTF and final drop within 1e-3 (1e-6 for samples
+    re-run in FP64 by the guard band), identical failure flags, re-solve
+    indices and failed-segment sets, the same nucleation sites, and their
+    steps within 3 of the oracle's."""
+    g, mat, rn, mc = synth.workload("long_lines")
+    S = 16
+    mc = dict(mc, n_samples=S)
+    rn = dict(rn, chain_m=chain_m)
+    _flush(f"long lines fp32 chain_m {chain_m}")
+    B = em.Batch(g, mat, rn, mc)
+    inf = B.info()
+    assert inf["chain_wg"] == 1024 and inf["chain_m"] == chain_m
+    res = B.run_to_ttf()
+    segs = {s: B.failed_segments(s) for s in range(S)}
+    ev = B.events()
+    B.close()
+    topo = oracle_mod.topology(g, rn["intervals_per_seg"])
+    sizes = np.diff(topo.tree_off)
+    n_fail = n_big = max_shift = 0
+    for s in range(S):
+        ref = oracle_mod.run_sample(g, mat, rn, mc, s, topo=topo)
+        ttf_check.check(res[s], ref, segs[s], 1, rn, s)
+        n_fail += ref["failed"]
+        if res[s]["redecided"]:
+            continue
+        # nucleation sites (tree, node) identical; steps compared where the
+        # run had not yet retired the sample
+        mine = sorted((int(e[1]), int(e[3]), int(e[2])) for e in ev if e[0] == s)
+        theirs = sorted((int(e[0]), int(e[2]), int(e[1])) for e in ref["events"])
+        assert [m[:2] for m in mine] == [t[:2] for t in theirs], s
+        for m, t in zip(mine, theirs):
+            max_shift = max(max_shift, abs(m[2] - t[2]))
+            n_big += sizes[m[0]] > 4096
+    print(f"chain_m {chain_m}: {n_fail} of {S} failed, {n_big} nucleations on >4096-node lines, "
+          f"max nucleation-step shift {max_shift}, {sum(r['redecided'] for r in res)} re-run in FP64",
+          flush=True)
+    assert n_big >= 16 and 4 <= n_fail <= S - 2
+    # this form rounds its state to float every step and solves the separator
+    # system in float: a slowly saturating node crosses sigma_crit a few steps
+    # off the FP64 oracle (measured 3 for 9-node and 8-node blocks; 1 with the
+    # low part kept, which this form has no registers for)
+    assert max_shift <= 3

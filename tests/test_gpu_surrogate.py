@@ -20,6 +20,17 @@ pytestmark = pytest.mark.gpu
 # x (a few flipped units); 2e-3 x (1 + |y|) bounds that with margin.
 Y_TOL = 2e-3
 G_TOL = 2e-2          # relative 2-norm error per parameter block
+# Element-wise gradient bound.  Each gradient entry is a sum of products whose
+# operands both sides round at the same points; they differ by float32 vs
+# float64 accumulation (relative <= n 2^-24 ~ 2e-5 of the sum of |terms| for
+# n = 300 rows) and by operands that round to the neighbouring bfloat16 value
+# (2^-8 relative of that operand) because their float32 value moved across a
+# rounding boundary -- in the entry's own sum or upstream, where the moved
+# signal is itself bounded by the magnitude sums.  A few such flips per entry
+# stay below 2^-6 of the entry's magnitude sum (oracle grad_magnitude), plus
+# an absolute floor of 1e-6 of the largest gradient for entries whose terms
+# all vanish.
+G_ELEM = 2.0 ** -6
 
 
 @pytest.fixture(scope="module")
@@ -61,13 +72,19 @@ def test_mlp_grad_matches_oracle(P, SO):
     loss, g = m.grad(X, t)
     lo, go = SO.loss_and_grad(p.astype(np.float64), X.astype(np.float64), t.astype(np.float64))
     assert abs(loss - lo) <= 1e-3 * lo
+    mag = SO.grad_magnitude(p.astype(np.float64), X.astype(np.float64), t.astype(np.float64))
+    floor = 1e-6 * np.max(np.abs(go))
     o = 0
     for name, shp in SO.SHAPES:
         k = int(np.prod(shp))
-        a, b = g[o:o + k].astype(np.float64), go[o:o + k]
+        a, b, mg = g[o:o + k].astype(np.float64), go[o:o + k], mag[o:o + k]
         rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
-        print(f"grad {name}: rel err {rel:.2e}")
+        ratio = np.abs(a - b) / (mg + floor)
+        print(f"grad {name}: rel 2-norm err {rel:.2e}, max |dg| / magnitude {ratio.max():.2e}, "
+              f"median |g| / magnitude {np.median(np.abs(b) / (mg + floor)):.2e}")
         assert rel <= G_TOL, name
+        bad = np.nonzero(np.abs(a - b) > G_ELEM * mg + floor)[0]
+        assert bad.size == 0, (name, bad[:8], a[bad[:8]], b[bad[:8]])
         o += k
     m.close()
 

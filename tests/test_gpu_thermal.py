@@ -7,6 +7,8 @@ temperature, decides how many samples fail."""
 import numpy as np
 import pytest
 
+import ttf_check
+
 from paper_2604_10743_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -46,16 +48,10 @@ def test_hotspot_map_run_matches_oracle(em, oracle_mod, variants):
     for s in range(0, 64, 8):
         ref = oracle_mod.run_sample(g, mat, rn, mc, s, topo=topo)
         r = res[s]
-        if np.min(np.abs(np.asarray(ref["drops"]) - rn["fail_frac"])) < 2e-3 * rn["fail_frac"]:
-            continue
         n_cmp += 1
         n_fail += ref["failed"]
-        assert r["failed"] == ref["failed"], s
-        assert abs(r["final_drop"] - ref["final_drop"]) <= 1e-3 * ref["final_drop"], s
-        if ref["failed"]:
-            assert abs(r["ttf_s"] - ref["ttf"]) <= 1e-3 * ref["ttf"], s
-        assert np.array_equal(segs[s], ref["failed_segs"]), s
-    assert n_cmp >= 6 and n_fail >= 3
+        ttf_check.check(r, ref, segs[s], rn["prec"], rn, s)
+    assert n_cmp == 8 and n_fail >= 3
 
 
 def test_equal_average_maps_differ_in_lifetime(em, variants):

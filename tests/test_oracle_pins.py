@@ -11,7 +11,7 @@ import os
 import numpy as np
 import pytest
 
-from cases import ladder_grid, line_grid, material, run, tree_from_edges
+from cases import OUTER_CASES, ladder_grid, line_grid, line_pad_load, material, run, tree_from_edges
 from paper_2604_10743_amd import synth
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -548,19 +548,102 @@ def test_ir_open_circuit_isolates(oracle_mod):
 
 
 # --------------------------------------------------------------------------
-# Outer loop: TTF interpolation, censoring
+# Outer loop (Fig. 2; reading R15): bracketing re-solves, time accounting on
+# uniform and graded grids, the stop rule, censoring, the final drop.  The
+# drops are computed outside the oracle's loop: its pinned stepping is run
+# interval by interval, every void's length follows from its volume, eq. 17 is
+# evaluated by hand, and the worst drop of the single pad-to-load line is the
+# closed form I (sum of R) / vdd (the whole load current crosses every
+# segment whatever the resistances, so it holds through every change of R).
 # --------------------------------------------------------------------------
-def test_ttf_linear_interpolation(oracle_mod):
-    g = synth.two_layer_mesh(1001, nr=8, nc=8, sink_mu=np.log(3e-3))
-    mat = material()
-    rn = run(n_steps=400, ir_every=50, dt=2e5, screen=1)
+def _eq17_per_metre(mat, W, H):
+    return mat["rho_ta"] / (mat["h_ta"] * (2 * H + W)) - mat["rho_cu"] / (W * H)
+
+
+def _outer_by_hand(oracle_mod, g, mat, rn, I):
+    N, K, n_steps = rn["intervals_per_seg"], rn["ir_every"], rn["n_steps"]
+    growth = rn.get("dt_growth", 0.0) or 1.0
+    W, H, L = g.res_w[0], g.res_h[0], g.res_len[0]
+    topo = oracle_mod.topology(g, N)
+    sim = oracle_mod.SampleSim(g, mat, rn, topo)
+    sim.set_j(np.full(g.n_res, I / (W * H)))          # pad -> load along every res_a -> res_b
+    drops, times, steps = [I * g.res_R0.sum() / g.vdd], [0.0], [0]
+    done, k = 0, 0
+    while done < n_steps:
+        nst = min(K, n_steps - done)
+        sim.set_dt(rn["dt"] * growth ** k)
+        sim.steps(nst, done)
+        done += nst
+        k += 1
+        iv, dv = sim.voids()
+        dR = np.zeros(g.n_res)
+        for (tree, node, seg, phase, step, early), (vol, _) in zip(iv, dv):
+            assert early == 0                          # one layer: no via above any vertex
+            l_v = min(vol / (W * H), L)
+            dR[seg] += max(0.0, l_v - W) * _eq17_per_metre(mat, W, H)
+        dR_or, op = sim.seg_state()
+        assert not op.any()
+        assert np.allclose(dR_or, dR, rtol=1e-12, atol=1e-15)
+        drops.append(I * (g.res_R0 + dR).sum() / g.vdd)
+        steps.append(done)
+        # interval end time, from the closed form of the geometric series of
+        # full intervals plus the partial last one
+        full = done // K
+        t = K * rn["dt"] * (full if growth == 1.0 else (growth ** full - 1.0) / (growth - 1.0))
+        t += (done - full * K) * rn["dt"] * growth ** full
+        times.append(t)
+    return np.array(drops), np.array(times), np.array(steps)
+
+
+def _expect(drops, times, f):
+    hit = np.nonzero(drops[1:] >= f)[0]
+    if drops[0] >= f:
+        return dict(failed=1, ttf=0.0, outer_idx=0, final_drop=drops[0])
+    if hit.size == 0:
+        return dict(failed=0, ttf=float("nan"), outer_idx=len(drops) - 1, final_drop=drops[-1])
+    k = int(hit[0]) + 1
+    ttf = times[k - 1] + (f - drops[k - 1]) / (drops[k] - drops[k - 1]) * (times[k] - times[k - 1])
+    return dict(failed=1, ttf=ttf, outer_idx=k, final_drop=drops[k])
+
+
+@pytest.mark.parametrize("case", sorted(OUTER_CASES))
+def test_outer_loop_against_hand_drops(oracle_mod, case):
+    over, I = OUTER_CASES[case]
+    g = line_pad_load(I=I, vdd=1.2 if case != "failed_at_t0" else 1.0)
+    mat = material(sigma_crit=200e6)
+    rn = run(intervals_per_seg=10, screen=1, **over)
     r = oracle_mod.run_sample(g, mat, rn)
-    d = r["drops"]
-    if r["failed"] and r["outer_idx"] > 0:
-        k = r["outer_idx"]
-        t = np.arange(len(d)) * 50 * 2e5
-        expect = t[k - 1] + (0.1 - d[k - 1]) / (d[k] - d[k - 1]) * (t[k] - t[k - 1])
-        assert abs(r["ttf"] - expect) <= 1e-12 * expect
-        assert d[k] >= 0.1 > d[k - 1]
-    else:
-        assert np.all(d < 0.1) or r["init_drop"] >= 0.1
+    drops, times, steps = _outer_by_hand(oracle_mod, g, mat, rn, I)
+    e = _expect(drops, times, rn["fail_frac"])
+    assert r["failed"] == e["failed"] and r["outer_idx"] == e["outer_idx"]
+    assert abs(r["init_drop"] - drops[0]) <= 1e-12
+    assert abs(r["final_drop"] - e["final_drop"]) <= 1e-10 * e["final_drop"]
+    k = e["outer_idx"]
+    assert np.allclose(r["drops"], drops[:k + 1], rtol=1e-10, atol=0)
+    if case == "failed_at_t0":
+        assert r["ttf"] == 0.0 and k == 0
+        return
+    if case == "censored_ragged":
+        assert math.isnan(r["ttf"]) and k == 20 and steps[-1] == 195
+        # the drop grew over the run: the final drop is that of step 195,
+        # not of the last full interval
+        assert drops[-1] > drops[-2] > drops[0]
+        return
+    # a crossing after at least two re-solves, with the drop already rising
+    # before it: the bracket, the times and the stop rule all matter
+    assert k >= 3 and drops[k - 1] > drops[0] and drops[k - 1] < rn["fail_frac"] <= drops[k]
+    assert abs(r["ttf"] - e["ttf"]) <= 1e-9 * e["ttf"]
+    assert times[k - 1] < r["ttf"] <= times[k]
+    # sensitivity: a bracket one re-solve late, the uniform clock on the
+    # graded grid, or a stop one interval late would each move the answer by
+    # far more than the tolerance above
+    f = rn["fail_frac"]
+    late = times[k] + (f - drops[k]) / (drops[k + 1] - drops[k]) * (times[k + 1] - times[k]) \
+        if k + 1 < len(drops) else np.inf
+    assert abs(late - e["ttf"]) > 1e-3 * e["ttf"]
+    if case == "graded":
+        t_uni = steps * rn["dt"]
+        ttf_uni = t_uni[k - 1] + (f - drops[k - 1]) / (drops[k] - drops[k - 1]) * (t_uni[k] - t_uni[k - 1])
+        assert abs(ttf_uni - e["ttf"]) > 1e-2 * e["ttf"]
+    if k + 1 < len(drops):
+        assert abs(drops[k + 1] - e["final_drop"]) > 1e-3 * e["final_drop"]

@@ -1,4 +1,4 @@
-"""Pins of the oracle's Joule-heating pre-pass (Sec. II-A, eqs. 2-4) against
+"""Pins of the oracle's Joule-heating pre-pass (Sec. III-A, eqs. 2-4) against
 the heat equation itself and textbook closed forms: the segment profile
 solves k T'' + j^2 rho = k (T - T0)/Gamma^2 with its end values; the end
 gradients are the profile's derivatives; a multi-segment line, solved through

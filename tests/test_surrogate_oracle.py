@@ -14,6 +14,7 @@ import pytest
 
 from cases import UM, line_grid, material, run, tree_from_edges
 from oracle import surrogate_oracle as SO
+from paper_2604_10743_amd import synth
 
 
 # ---------------------------------------------------------------- bfloat16
@@ -190,3 +191,22 @@ def test_activation_interval_hand_values():
     K, dt, m = 100, 1.0, 2.0                 # margin x t_{k+1} = 200 (k + 1)
     th = np.array([1.0, 200.0, 200.0001, 400.0, 1e4])
     assert list(SO.activation_interval(th, m, K, dt)) == [0, 0, 1, 1, 49]
+
+
+def test_grad_magnitude_bounds_gradient():
+    # the magnitude sums bound every gradient entry, with equality where all
+    # terms share a sign: a single row through a network with non-negative
+    # weights and inputs has no cancellation in the output-layer gradients
+    from oracle import surrogate_oracle as SO
+    rng = np.random.default_rng(5)
+    p = synth.init_mlp_params(11)
+    X, t = rng.standard_normal((64, 12)), rng.standard_normal(64)
+    _, g = SO.loss_and_grad(p, X, t)
+    mg = SO.grad_magnitude(p, X, t)
+    assert np.all(mg >= np.abs(g) - 1e-15 * np.abs(g).max())
+    p1 = np.abs(p)
+    X1, t1 = np.abs(X[:1]), np.array([-50.0])
+    _, g1 = SO.loss_and_grad(p1, X1, t1)
+    m1 = SO.grad_magnitude(p1, X1, t1)
+    o = sum(int(np.prod(s)) for n, s in SO.SHAPES if n not in ("w4", "b4"))
+    assert np.allclose(m1[o:], np.abs(g1[o:]), rtol=1e-12, atol=0)
