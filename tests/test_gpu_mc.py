@@ -40,3 +40,31 @@ def test_mc_grid_1024_samples_vs_oracle(em, oracle_mod):
     print(f"compared {n_cmp} of 64 samples, {n_fail} failed; {info_redecided} of 1024 re-run in FP64",
           flush=True)
     assert 10 <= n_fail <= n_cmp - 10
+
+
+def test_mc_mesh_1024_samples_vs_oracle(em, oracle_mod):
+    """The 32x32 mesh with cut M1 rows (the cfg3 grid), 1024 samples in one
+    FP32 batch as benchmarked; every 64th sample recomputed by the oracle.
+    Every sample is censored on this redundant mesh (a via at every
+    crossing), so the comparison is of final drops, void-driven resistance
+    changes (failed-segment sets) and nucleation sites."""
+    g, mat, rn, mc = synth.workload("mc_mesh")
+    print("mc_mesh 1024 samples FP32", flush=True)
+    B = em.Batch(g, mat, rn, mc)
+    res = B.run_to_ttf()
+    picks = range(0, 1024, 64)
+    segs = {s: B.failed_segments(s) for s in picks}
+    ev = B.events()
+    B.close()
+    topo = oracle_mod.topology(g, rn["intervals_per_seg"])
+    n_seg = n_nuc = 0
+    for s in picks:
+        ref = oracle_mod.run_sample(g, mat, rn, mc, s, topo=topo)
+        ttf_check.check(res[s], ref, segs[s], rn["prec"], rn, s)
+        mine = sorted((int(e[1]), int(e[3])) for e in ev if e[0] == s)
+        theirs = sorted((int(e[0]), int(e[2])) for e in ref["events"])
+        assert mine == theirs, s
+        n_seg += len(segs[s])
+        n_nuc += len(theirs)
+    print(f"mc_mesh: {n_nuc} nucleations, {n_seg} failed segments over {len(picks)} samples", flush=True)
+    assert n_nuc > 0
