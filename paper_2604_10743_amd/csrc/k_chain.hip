@@ -111,8 +111,8 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
     // (chains of more than 4096 nodes) the register file has no room for it:
     // there the low part is folded in at load and the state rounds to float
     // every step.  (Keeping it in LDS instead doubled the spills and cost 60 %
-    // per launch, while the nucleation steps still moved by up to 3 against the
-    // FP64 oracle: the float separator solve, not the state, dominates there.)
+    // per launch, while the nucleation steps still moved by up to 3 against
+    // FP64 stepping: the float separator solve, not the state, dominates there.)
     constexpr bool LO = sizeof(R) == 4 && WG < 1024;
     __shared__ R s_al[LEV][WG];
     __shared__ R s_ga[LEV][WG];
