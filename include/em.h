@@ -456,6 +456,24 @@ em_status em_mlp_grad(em_mlp *m, const float *X, const float *t, int32_t n, floa
  * the call does not synchronise). */
 em_status em_mlp_train_step(em_mlp *m, const float *X, const float *t, int32_t n, float lr, float *loss);
 
+/* ---- allocation-free entry point ----
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * em_mlp_forward_noalloc computes y [n] = model(X) exactly as em_mlp_forward
+ * does (same kernels, same result bit for bit), but keeps the activations in a
+ * fixed device array of the library instead of the model's buffers, which
+ * em_mlp_forward grows with hipMalloc when n grows.  X [n][12] and y [n] are
+ * caller-owned DEVICE pointers; 1 <= n <= em_mlp_noalloc_max_rows() (4096),
+ * else EM_ERR_ARG.  Asynchronous on the model's stream (no synchronisation);
+ * no device or pinned memory is allocated or freed.  The array (17 MB) exists
+ * once per GPU that runs the call and is held until the process ends; every
+ * call on that GPU, from any model or thread, uses the same array, so calls
+ * that overlap on one GPU race (serialise them, e.g. on one stream), and each
+ * call overwrites what the last one left there.  Errors: EM_ERR_ARG for a NULL
+ * pointer or a bad n, EM_ERR_HIP when a HIP call fails. */
+int32_t em_mlp_noalloc_max_rows(void);
+em_status em_mlp_forward_noalloc(em_mlp *m, const float *X, int32_t n, float *y);
+
 /* Features of every (tree, sample) for the current densities, written to X
  * (DEVICE, [n_trees * n_samples][12], row tree * n_samples + sample).
  * Refreshes the screen verdict (em_get_screen) without changing which trees

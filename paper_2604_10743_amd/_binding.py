@@ -29,7 +29,8 @@ API = ["em_batch_create", "em_batch_destroy", "em_get_info", "em_last_error", "e
        "em_reset", "em_mlp_create", "em_mlp_destroy", "em_mlp_last_error", "em_mlp_num_params",
        "em_mlp_set_params", "em_mlp_get_params", "em_mlp_forward", "em_mlp_grad",
        "em_mlp_train_step", "em_features", "em_surrogate_screen", "em_get_surrogate",
-       "em_first_nucleation", "em_get_failed_segments", "em_snapshot", "em_restore", "em_autotune"]
+       "em_first_nucleation", "em_get_failed_segments", "em_snapshot", "em_restore", "em_autotune",
+       "em_mlp_forward_noalloc", "em_mlp_noalloc_max_rows"]
 
 
 # Thermal block used when a material dict leaves it out (only read with joule=1):
@@ -486,6 +487,20 @@ class MLP:
         self._chk(lib().em_mlp_forward(self._h, C.c_void_p(X.data_ptr()), C.c_int32(n),
                                        C.c_void_p(y.data_ptr())))
         return y
+
+    def forward_noalloc(self, X, y):
+        """y[:n] = model(X) through the allocation-free entry point: X [n][12]
+        and y [>= n] are caller-owned float32 device tensors; the call
+        allocates nothing and does not synchronise the model's stream."""
+        n = int(X.shape[0])
+        assert X.is_cuda and y.is_cuda and X.dtype == y.dtype == self._torch.float32 and y.numel() >= n
+        assert X.is_contiguous() and y.is_contiguous() and tuple(X.shape[1:]) == (12,)
+        self._chk(lib().em_mlp_forward_noalloc(self._h, C.c_void_p(X.data_ptr()), C.c_int32(n),
+                                               C.c_void_p(y.data_ptr())))
+
+    @staticmethod
+    def noalloc_max_rows() -> int:
+        return int(lib().em_mlp_noalloc_max_rows())
 
     def grad(self, X, t):
         X, t = self._dev(X), self._dev(t)

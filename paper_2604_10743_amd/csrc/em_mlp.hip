@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -343,16 +344,29 @@ void gemm(em_mlp *m, int epi, const float *A, long long sam, long long sak, cons
     if (ws) k_splitk_sum<<<cdiv((long long)M * N, 256), 256, 0, st>>>(ws, splits, C, M, N, ldc);
 }
 
-// forward pass into the activation buffers (X: device [n][12])
-void forward(em_mlp *m, const float *X, int n, hipStream_t st)
+// Activation buffers of one forward pass: padded input, pre-activations Z
+// (kept for the backward pass; one shared buffer when only y is wanted) and
+// post-activations H of the three hidden layers, output y.
+struct Act {
+    float *Xp, *Z1, *H1, *Z2, *H2, *Z3, *H3, *y;
+};
+
+// forward pass into the given activation buffers (X: device [n][12])
+void forward_into(em_mlp *m, const float *X, int n, const Act &a, hipStream_t st)
 {
-    k_pad_x<<<cdiv((long long)n * KF, 256), 256, 0, st>>>(X, m->Xp, n);
+    k_pad_x<<<cdiv((long long)n * KF, 256), 256, 0, st>>>(X, a.Xp, n);
     k_w1_pad<<<cdiv(HID * KF, 256), 256, 0, st>>>(m->p, m->W1p);
     // Z1 = X W1^T + b1 : B(k, n) = W1p[n][k]
-    gemm(m, EPI_BIAS_GELU, m->Xp, KF, 1, m->W1p, 1, KF, m->Z1, HID, n, HID, KF, m->p + OB1, m->H1, nullptr, st);
-    gemm(m, EPI_BIAS_GELU, m->H1, HID, 1, m->p + OW2, 1, HID, m->Z2, HID, n, HID, HID, m->p + OB2, m->H2, nullptr, st);
-    gemm(m, EPI_BIAS_GELU, m->H2, HID, 1, m->p + OW3, 1, HID, m->Z3, HID, n, HID, HID, m->p + OB3, m->H3, nullptr, st);
-    k_out<<<cdiv(n, 4), 256, 0, st>>>(m->H3, m->p + OW4, m->p + OB4, m->y, n);
+    gemm(m, EPI_BIAS_GELU, a.Xp, KF, 1, m->W1p, 1, KF, a.Z1, HID, n, HID, KF, m->p + OB1, a.H1, nullptr, st);
+    gemm(m, EPI_BIAS_GELU, a.H1, HID, 1, m->p + OW2, 1, HID, a.Z2, HID, n, HID, HID, m->p + OB2, a.H2, nullptr, st);
+    gemm(m, EPI_BIAS_GELU, a.H2, HID, 1, m->p + OW3, 1, HID, a.Z3, HID, n, HID, HID, m->p + OB3, a.H3, nullptr, st);
+    k_out<<<cdiv(n, 4), 256, 0, st>>>(a.H3, m->p + OW4, m->p + OB4, a.y, n);
+}
+
+// forward pass into the model's own activation buffers
+void forward(em_mlp *m, const float *X, int n, hipStream_t st)
+{
+    forward_into(m, X, n, Act{m->Xp, m->Z1, m->H1, m->Z2, m->H2, m->Z3, m->H3, m->y}, st);
 }
 
 // gradient of the mean squared error into m->g; the loss (when asked for)
@@ -411,7 +425,71 @@ int mlp_forward_async(em_mlp *m, const float *X, int n, float *y, hipStream_t st
 }
 }  // namespace em
 
+// ---------------------------------------------------------------------------
+// Allocation-free forward pass.  The activations live in a file-scope device
+// array instead of the model's row-sized buffers (which em_mlp_forward grows
+// with hipMalloc): padded input, one pre-activation buffer shared by the three
+// layers (the backward pass is not run here), and the three post-activation
+// buffers, each sized for NOALLOC_MAX_ROWS rows.  Every kernel guards its row
+// loads and stores with n, so the array needs no clearing between calls.  In
+// host code `scratch` names a host-side stand-in: kernels receive the device
+// address that hipGetSymbolAddress returns, looked up once per device.
+// ---------------------------------------------------------------------------
+constexpr int NOALLOC_MAX_ROWS = 4096;
+constexpr size_t NOALLOC_FLOATS = (size_t)NOALLOC_MAX_ROWS * (KF + 4 * HID);   // 17.0 MB
+static __device__ __align__(256) float scratch[NOALLOC_FLOATS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_dev[MAX_DEVICES] = {};     // device address of `scratch`, per device
+
+// The scratch array of the device that runs `st`, set up on the first call
+// on that device (with that device current, restored afterwards).
+hipError_t scratch_of_stream(hipStream_t st, float **out)
+{
+    int dev = 0;
+    hipError_t e = st ? hipStreamGetDevice(st, &dev) : hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        int cur = 0;
+        if ((e = hipGetDevice(&cur)) != hipSuccess) return e;
+        if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) {
+            hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = (float *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+}  // namespace
+
 extern "C" {
+
+int32_t em_mlp_noalloc_max_rows(void) { return NOALLOC_MAX_ROWS; }
+
+em_status em_mlp_forward_noalloc(em_mlp *m, const float *X, int32_t n, float *y)
+{
+    if (!m || !X || !y || n <= 0) return mfail(m, EM_ERR_ARG, "bad forward arguments");
+    if (n > NOALLOC_MAX_ROWS)
+        return mfail(m, EM_ERR_ARG, "em_mlp_forward_noalloc: more rows than its scratch holds "
+                                    "(em_mlp_noalloc_max_rows)");
+    float *base = nullptr;
+    MCHK(m, scratch_of_stream(m->stream, &base));
+    const size_t R = NOALLOC_MAX_ROWS;
+    float *Xp = base, *Z = Xp + R * KF, *H1 = Z + R * HID, *H2 = H1 + R * HID, *H3 = H2 + R * HID;
+    forward_into(m, X, n, Act{Xp, Z, H1, Z, H2, Z, H3, y}, m->stream);
+    MCHK(m, hipGetLastError());
+    return EM_OK;
+}
 
 em_status em_mlp_create(void *hip_stream, em_mlp **out)
 {
