@@ -1,22 +1,26 @@
 """Benchmark of the coupled EM/TM stress + IR-drop hot path on one MI355X.
 
-A step is one full pass of the hot path over the 400x400 two-layer P/G grid:
-IR solve, backward-Euler stress stepping of every tree (2000 steps over ten
-years, FP32 stress with FP64 void/dR accumulators), nucleation and void
-growth, resistance write-back and an IR re-solve every 100 steps, until the
-10 % IR-drop failure or the horizon.  The batch is built (netlist copied,
-trees partitioned, statics evaluated) before the timed region; each timed
-step resets it to t = 0 and runs it to time-to-failure.
+A step is one full pass of the hot path over the four-layer full-chip grid
+(2000x2000 routing grid, 84k trees, 8.8M stress nodes): IR solve,
+backward-Euler stress stepping of every tree (2000 steps over ten years,
+FP32 stress with FP64 void/dR accumulators), nucleation and void growth,
+resistance write-back and an IR re-solve every 50 steps, until the 10 %
+IR-drop failure or the horizon.  The batch is built (netlist copied, trees
+partitioned, statics and the Joule pre-pass evaluated) before the timed
+region; each timed step resets it to t = 0 and runs it to time-to-failure.
 
 Prints ONE JSON line (rank 0).  Metric: stress-node-steps/s (sum over stepped
 trees of stress nodes x steps, divided by wall time).  Also reported: the
 roofline of the dominant kernel (the stepping kernel, timed with HIP events on
-its own stream inside the library; against the streamed HBM roofline, or the
-FP32 vector-ALU bound where the resident kernel beats the former), the plain FP64 GPU form (one tree per
-lane, FP64) over one aging interval, the FP64 oracle on host cores over a
-bounded sample of the same workload, and Monte Carlo samples/s to TTF with 1024
-samples on the 96x96 sparse-via grid (failures within the horizon; checked
-against the FP64 oracle on 64 samples) and on the 32x32 mesh.
+its stream inside the library; against the streamed HBM roofline, or the FP32
+vector-ALU bound where the resident kernel beats the former), the plain FP64
+GPU form (one tree per lane, FP64) over one aging interval, the FP64 oracle on
+host cores over a bounded sample of the same workload, the same measurement
+on the 400x400 two-layer grid with and without voids, and Monte Carlo
+samples/s to TTF: 64 samples of the full chip, 1024 samples of the 96x96
+sparse-via grid (failures within the horizon; checked against the FP64
+oracle on 64 samples), the 32x32 mesh, further sampled inputs, a thermal-map
+sweep and the learned screen.
 """
 from __future__ import annotations
 
@@ -42,23 +46,45 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def _oracle_grid(name):
+    """The CPU baseline's input: the named workload's grid in trees-only mode
+    with seeded prescribed current densities (the stepping cost does not
+    depend on their values), FP64 numerics."""
+    from paper_2604_10743_amd import synth
+    g, mat, run, _ = synth.workload(name)
+    run = dict(run, prec=0, joule=0)
+    return synth.with_prescribed_j(g, synth.seeded_current_density(g, 777)), mat, run
+
+
 def _oracle_trees_worker(job):
-    """One host process of the all-core oracle baseline: the pg400 grid, the
-    nominal currents j, 100 BE steps of trees [t0, t1); returns node-steps."""
-    t0, t1, j, n_steps = job
+    """One host process of the all-core oracle baseline: BE steps of trees
+    [t0, t1) of the named workload; returns node-steps."""
+    name, t0, t1, n_steps = job
     import numpy as np
     sys.path.insert(0, ROOT)
     from oracle import oracle as O
-    from paper_2604_10743_amd import synth
-    g, mat, run, _ = synth.workload("pg400_fp64")
+    g, mat, run = _oracle_grid(name)
     topo = O.topology(g, run["intervals_per_seg"])
     sim = O.SampleSim(g, mat, run, topo)
-    sim.set_j(j)
+    sim.set_j(g.seg_j)
     act = np.zeros(topo.n_trees, np.uint8)
     act[t0:t1] = 1
     sim.set_active(act)
     sim.steps(n_steps, 0)
     return int(topo.tree_off[t1] - topo.tree_off[t0]) * n_steps
+
+
+def host_cpu():
+    """Host CPU model and logical core count (for the oracle baselines)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "logical_cores": os.cpu_count()}
 
 
 def measured_traffic(kernel_src: str, profile_md: str):
@@ -174,6 +200,8 @@ MC_DESC = {
     "mc_grid": "96x96 two-layer sparse-via P/G grid (via every 32 nodes, 16 pads, 12309 nodes, "
                "169 line trees), 330 K + 6 hotspots, worst initial drop 7 %",
     "mc_mesh": "32x32 two-layer mesh with 4 corner pads, M1 rows cut into 213 trees, 378 K",
+    "fullchip": "the full-chip grid of the headline (84k trees, 8.8M stress nodes, 515k grid nodes), "
+                "340 K + 12 hotspots with the Joule pre-pass, IR re-solve every 50 steps",
 }
 
 
@@ -181,7 +209,7 @@ MC_DESC = {
 MC_VAR = {"cov_rho": 0.1, "cov_load": 0.15}
 
 
-def mc_leg(args, name, oracle, plain, var=None, joule=False):
+def mc_leg(args, name, oracle, plain, var=None, joule=False, n_samples=None):
     """Monte Carlo samples/s to TTF: batch creation and the run of every
     sample to its 10 % IR-drop failure or the 10-year horizon, FP32 stepping,
     steady-state screen on.  One untimed run first (code paths warm), then the
@@ -197,7 +225,7 @@ def mc_leg(args, name, oracle, plain, var=None, joule=False):
     from paper_2604_10743_amd import synth
 
     g, mat, run, mc = synth.workload(name)
-    mc = dict(mc, n_samples=args.mc_samples, **(var or {}))
+    mc = dict(mc, n_samples=n_samples or args.mc_samples, **(var or {}))
     if joule:
         run = dict(run, joule=1)
     S = mc["n_samples"]
@@ -221,7 +249,7 @@ def mc_leg(args, name, oracle, plain, var=None, joule=False):
     yr = 365.25 * 86400.0
     o = {"metric": "MC samples/s to TTF", "value": S / wall, "unit": "samples/s",
          "workload": f"{name}: {MC_DESC[name]}; {S} samples, 20% lognormal CoV on kappa and sigma_crit{extra}, "
-                     "2000 BE steps over 10 y, IR re-solve every 100 steps, FP32 stepping, screen on",
+                     f"2000 BE steps over 10 y, IR re-solve every {run['ir_every']} steps, FP32 stepping, screen on",
          "wall_s": wall, "n_fail": int(ttf.size), "n_censored": int(S - ttf.size),
          "ttf_mean_y": float(ttf.mean() / yr) if ttf.size else None,
          "ttf_cov": float(ttf.std(ddof=1) / ttf.mean()) if ttf.size > 1 else None,
@@ -271,6 +299,196 @@ def mc_leg(args, name, oracle, plain, var=None, joule=False):
                                          "Jacobi-preconditioned CG on the nodal system",
                                "speedup_of_value": (S / wall) / (Sp / wp)}
     return o
+
+
+STEP_DESC = {
+    "fullchip": "fullchip: 2000x2000 routing grid (1 um tracks, 2 mm die), 4 metal layers (M1/M2 stripes "
+                "every 4th track cut into trees of 2-8 segments, M3/M4 every 20th track cut into lines of "
+                "20-60 segments), 8 VDD pads, thermal map 340 K + 12 hotspots (+20..70 K) with the "
+                "Joule-heating pre-pass, 2000 BE steps over 10 y, IR re-solve every 50 steps, run to the "
+                "first 10 % IR-drop failure or the horizon",
+    "pg400": "pg400: 400x400 two-layer P/G grid, 798 line trees, 2000 BE steps over 10 y, IR re-solve every "
+             "100 steps, thermal map 330 K + 6 hotspots",
+}
+PROFILE_OF = {"fullchip": "profiles/k_chain_fullchip.md", "pg400": "profiles/k_chain_pg400.md"}
+
+
+def stepping_leg(args, name, headline):
+    """Stress-node-steps/s of one sample's full coupled run (IR solve, every
+    tree stepped -- the steady-state screen off, as the plain method without
+    its optional pruning --, nucleation, void growth, resistance write-back,
+    IR re-solves, to failure or the horizon).  The batch is built before the
+    timed region; each timed step resets it to t = 0 and runs it to TTF.  The
+    roofline is that of the stepping kernel (HIP events around each launch
+    inside the library); for the headline also the plain FP64 GPU form and
+    the FP64 oracle on host cores."""
+    import numpy as np
+    import torch
+    import paper_2604_10743_amd as P
+    from paper_2604_10743_amd import synth
+
+    g, mat, run, _ = synth.workload(name)
+    run = dict(run, prec=args.prec, screen=0)
+    log(f"bench: building batch for {g.name} ({g.n_nodes} nodes, {g.n_res} resistors)")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B = P.Batch(g, mat, run)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    info = B.info()
+    log(f"bench: {info['n_trees']} trees, {info['n_stress']} stress nodes, setup {t_setup:.2f} s")
+    steps = args.steps if headline else max(1, min(args.steps, 2))
+    warm = args.warmup if headline else 1
+    for w in range(warm):
+        B.reset()
+        B.run_to_ttf()
+    torch.cuda.synchronize()
+    B.reset()
+    t0 = time.perf_counter()
+    results = None
+    for k in range(steps):
+        if k:
+            B.reset()
+        results = B.run_to_ttf()
+        if headline:
+            log(f"bench: step {k + 1}/{steps} done")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # counters are cleared by reset: every step replays the same run, so the
+    # last step's counters times the step count is exact
+    i1 = B.info()
+    value = i1["node_steps"] * steps / wall
+    bytes_ns = BYTES_PER_NODE_STEP[args.prec]
+    step_ms = i1["step_kernel_ms"]
+    launches = i1["step_launches"]
+    achieved = (bytes_ns * i1["node_steps"] / 1e9) / (step_ms / 1e3) if step_ms > 0 else None
+    traffic = (measured_traffic("paper_2604_10743_amd/csrc/k_chain.hip", PROFILE_OF[name])
+               if args.prec == 1 else None)
+    kernel = (f"k_chain<float,{i1['chain_m']},{i1['chain_wg']}>" if args.prec == 1 else "k_chain<double>")
+    streamed = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                "bytes_per_node_step": bytes_ns}
+    if achieved and achieved > HBM_PEAK_GBS:
+        # the resident kernel moves its state once per launch and can beat any
+        # streaming stepper: then it is measured against the vector-ALU bound
+        tf = FLOPS_PER_NODE_STEP * i1["node_steps"] / (step_ms / 1e3) / 1e12
+        roofline = {"bound": "alu", "achieved": tf, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": tf / FP32_VALU_PEAK_TFLOPS, "flops_per_node_step": FLOPS_PER_NODE_STEP,
+                    "streamed_hbm": streamed}
+    else:
+        roofline = dict(streamed)
+    roofline.update({"traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-scaled)",
+                     "kernel": kernel, "launches_per_step": launches,
+                     "avg_launch_ms": step_ms / max(launches, 1), "workgroups": i1["n_chain_wg"],
+                     "algorithmic_bytes_per_launch": bytes_ns * i1["node_steps"] / max(launches, 1)})
+    r0 = results[0]
+    out = {
+        "metric": "stress-node-steps/s", "value": value, "unit": "node-steps/s", "n_gpus": 1,
+        "steps": steps, "warmup": warm, "ms_per_step": wall / steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.prec == 1 else "f64", "data": "synthetic",
+        "config": {"workload": f"{STEP_DESC[name]}; {info['n_trees']} trees, {info['n_stress']} stress nodes, "
+                               f"{info['n_nodes']} grid nodes; steady-state screen off (every tree stepped), "
+                               "FP32 stress with FP64 void volumes, resistance changes, IR and TTF",
+                   "node_steps_per_step": i1["node_steps"], "setup_s": t_setup,
+                   "ir_ms_per_step": i1["ir_ms"], "cg_iters_per_step": i1["cg_iters_total"],
+                   "ir_system_nodes": i1["ir_sys_nodes"], "step_kernel_ms_per_step": step_ms,
+                   "ttf_s": r0["ttf_s"], "final_drop": r0["final_drop"], "init_drop": r0["init_drop"],
+                   "outer_idx": r0["outer_idx"], "n_nucleated_trees": r0["n_nucleated_trees"],
+                   "n_failed_segs": r0["n_failed_segs"]},
+        "roofline": roofline,
+    }
+    B.close()
+    if headline and not args.no_plain:
+        # the plain FP64 GPU FDTD form (generic tree kernel, one (tree) per
+        # lane, FP64) on one aging interval of the same workload
+        Bp = P.Batch(g, mat, dict(run, prec=0, stepper=1, joule=0))
+        Bp.ir_solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Bp.stress_step(run["ir_every"])
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        ip = Bp.info()
+        out["plain_fp64_gpu"] = {"value": ip["node_steps"] / tp, "unit": "node-steps/s",
+                                 "sample": f"{name}, {run['ir_every']} BE steps of every tree, FP64, "
+                                           "one (tree) per lane tree-elimination kernel",
+                                 "speedup_of_value": value / (ip["node_steps"] / tp)}
+        Bp.close()
+        log("bench: plain fp64 done")
+    if headline and not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_stepping(name, run["ir_every"])
+        log("bench: cpu baseline done")
+    return out
+
+
+def cpu_baseline_stepping(name, n_steps):
+    """The FP64 oracle stepping every tree of the workload for one aging
+    interval (seeded prescribed currents in trees-only mode: the oracle's
+    sparse direct IR solve does not finish on the full-chip grid in 20
+    minutes, so it is left out and the figure is stepping only), on one core
+    and with the trees split over every host core."""
+    import numpy as np
+    from oracle import oracle as O
+    O.build(force=False)
+    g, mat, run = _oracle_grid(name)
+    topo = O.topology(g, run["intervals_per_seg"])
+    t0 = time.perf_counter()
+    sim = O.SampleSim(g, mat, run, topo)
+    sim.set_j(g.seg_j)
+    sim.steps(n_steps, 0)
+    t1 = time.perf_counter() - t0
+    ns = int(topo.n_stress) * n_steps
+    out = {"value": ns / t1, "unit": "node-steps/s", "cores": 1, "kind": "oracle", "cpu": host_cpu(),
+           "sample": f"{name}: FP64 oracle BE stepping of all {topo.n_trees} trees ({topo.n_stress} stress "
+                     f"nodes) for one aging interval of {n_steps} steps, seeded prescribed currents, "
+                     f"{t1:.1f} s on one core; IR solve excluded (the GPU value includes its IR re-solves)"}
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    n_proc = max(1, min(16, os.cpu_count() or 1))
+    bounds = np.linspace(0, topo.n_trees, n_proc + 1).astype(int)
+    jobs = [(name, int(bounds[k]), int(bounds[k + 1]), n_steps) for k in range(n_proc) if bounds[k + 1] > bounds[k]]
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=len(jobs), mp_context=mp.get_context("spawn")) as ex:
+        ns_all = sum(ex.map(_oracle_trees_worker, jobs))
+    ta = time.perf_counter() - t0
+    out["all_cores"] = {"value": ns_all / ta, "unit": "node-steps/s", "cores": len(jobs),
+                        "sample": f"the same interval with the trees split over {len(jobs)} spawned processes "
+                                  f"({ns_all} node-steps, {ta:.1f} s incl. each process's setup)"}
+    return out
+
+
+def voids_leg(args):
+    """pg400 with voids: the critical stress lowered to 200 MPa so that the
+    mortal lines nucleate within the horizon, steady-state screen on; void
+    growth, liner resistance changes and IR re-solves run inside the timed
+    region (one untimed run first)."""
+    import numpy as np
+    import torch
+    import paper_2604_10743_amd as P
+    from paper_2604_10743_amd import synth
+
+    g, mat, run, _ = synth.workload("pg400")
+    mat = dict(mat, sigma_crit=200e6)
+    run = dict(run, prec=args.prec, screen=1)
+    B = P.Batch(g, mat, run)
+    B.run_to_ttf()
+    B.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = B.run_to_ttf()[0]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    i = B.info()
+    B.close()
+    return {"metric": "stress-node-steps/s", "value": i["node_steps"] / wall, "unit": "node-steps/s",
+            "workload": "pg400 with sigma_crit 200 MPa, screen on, FP32, one run to failure or the horizon",
+            "wall_ms": wall * 1e3, "ir_ms": i["ir_ms"], "step_kernel_ms": i["step_kernel_ms"],
+            "cg_iters": i["cg_iters_total"], "node_steps": i["node_steps"], "ttf_s": r["ttf_s"],
+            "failed": r["failed"], "outer_idx": r["outer_idx"], "init_drop": r["init_drop"],
+            "final_drop": r["final_drop"], "n_nucleated_trees": r["n_nucleated_trees"],
+            "n_failed_segs": r["n_failed_segs"]}
 
 
 def thermal_leg(args):
@@ -336,6 +554,10 @@ def main():
                     help="run only the Monte Carlo legs (no oracle, no plain form) and print them")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--mc-samples", type=int, default=1024)
+    ap.add_argument("--fc-samples", type=int, default=64, help="Monte Carlo samples of the full-chip leg")
+    ap.add_argument("--workload", default="fullchip", choices=sorted(STEP_DESC),
+                    help="workload of the headline stepping measurement")
+    ap.add_argument("--only-headline", action="store_true", help="run the headline measurement only")
     ap.add_argument("--no-sur", action="store_true", help="skip the learned-screen leg")
     ap.add_argument("--sur-grids", type=int, default=24, help="label grids for the learned screen")
     ap.add_argument("--sur-label-samples", type=int, default=128)
@@ -375,159 +597,30 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
-    g, mat, run, _ = synth.workload("pg400")
-    run = dict(run, prec=args.prec, screen=0)
-    log(f"bench: building batch for {g.name} ({g.n_nodes} nodes, {g.n_res} resistors)")
-    t0 = time.perf_counter()
-    B = P.Batch(g, mat, run)
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t0
-    info = B.info()
-    log(f"bench: {info['n_trees']} trees, {info['n_stress']} stress nodes, setup {t_setup:.2f} s")
-
-    for w in range(args.warmup):
-        B.reset()
-        B.run_to_ttf()
-        log(f"bench: warmup {w + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    B.reset()
-    i0 = B.info()
-    t0 = time.perf_counter()
-    results = None
-    for k in range(args.steps):
-        if k:
-            B.reset()
-        results = B.run_to_ttf()
-        log(f"bench: step {k + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    # counters are cleared by reset: accumulate per step instead
-    # (node_steps of the last step x steps is exact: every step replays the same run)
-    i1 = B.info()
-    node_steps_total = i1["node_steps"] * args.steps
-    value = node_steps_total / wall
-    bytes_ns = BYTES_PER_NODE_STEP[args.prec]
-    step_ms = i1["step_kernel_ms"]
-    launches = i1["step_launches"]
-    achieved = (bytes_ns * i1["node_steps"] / 1e9) / (step_ms / 1e3) if step_ms > 0 else None
-    traffic = (measured_traffic("paper_2604_10743_amd/csrc/k_chain.hip", "profiles/k_chain_pg400.md")
-               if args.prec == 1 else None)
-    kernel = (f"k_chain<float,{i1['chain_m']},{i1['chain_wg']}>" if args.prec == 1 else "k_step<double>")
-    streamed = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                "bytes_per_node_step": bytes_ns}
-    if achieved and achieved > HBM_PEAK_GBS:
-        # the resident kernel moves its state once per launch and beats any
-        # streaming stepper: measure it against the vector-ALU bound instead
-        tf = FLOPS_PER_NODE_STEP * i1["node_steps"] / (step_ms / 1e3) / 1e12
-        roofline = {"bound": "alu", "achieved": tf, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": tf / FP32_VALU_PEAK_TFLOPS, "flops_per_node_step": FLOPS_PER_NODE_STEP,
-                    "streamed_hbm": streamed}
-    else:
-        roofline = dict(streamed)
-    roofline.update({"traffic": traffic,
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-scaled)",
-                     "kernel": kernel, "launches_per_step": launches,
-                     "avg_launch_ms": step_ms / max(launches, 1), "workgroups": i1["n_chain_wg"]})
-    r0 = results[0]
-    out = {
-        "metric": "stress-node-steps/s", "value": value, "unit": "node-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if args.prec == 1 else "f64", "data": "synthetic",
-        "config": {"workload": f"pg400: 400x400 two-layer P/G grid, {info['n_trees']} line trees, "
-                               f"{info['n_stress']} stress nodes, 2000 BE steps over 10 y, "
-                               "IR re-solve every 100 steps, thermal map 330 K + 6 hotspots, "
-                               "screen off (every tree stepped)",
-                   "node_steps_per_step": i1["node_steps"], "setup_s": t_setup,
-                   "ir_ms_per_step": i1["ir_ms"], "cg_iters_per_step": i1["cg_iters_total"],
-                   "ttf_s": r0["ttf_s"], "final_drop": r0["final_drop"], "init_drop": r0["init_drop"],
-                   "n_nucleated_trees": r0["n_nucleated_trees"]},
-        "roofline": roofline,
-    }
-    B.close()
-
+    out = stepping_leg(args, args.workload, headline=True)
+    log(f"bench: headline ({args.workload}) done")
+    if args.only_headline:
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload != "pg400":
+        out["pg400"] = stepping_leg(args, "pg400", headline=False)
+        log("bench: pg400 done")
+    out["pg400_voids"] = voids_leg(args)
+    log("bench: pg400 with voids done")
     if not args.no_mc:
+        out["fullchip_mc"] = mc_leg(args, "fullchip", oracle=False, plain=False, n_samples=args.fc_samples)
+        log("bench: fullchip mc done")
         out["mc"] = mc_leg(args, "mc_grid", oracle=not args.no_cpu, plain=not args.no_plain)
         log("bench: mc (mc_grid) done")
         out["mc_mesh"] = mc_leg(args, "mc_mesh", oracle=False, plain=False)
         out["mc_rho_load"] = mc_leg(args, "mc_grid", oracle=False, plain=False, var=MC_VAR)
         out["mc_joule"] = mc_leg(args, "mc_grid", oracle=False, plain=False, joule=True)
-        log("bench: mc (mc_mesh) done")
-
-    if not args.no_mc:
+        log("bench: mc (mc_mesh, variations) done")
         out["thermal_sweep"] = thermal_leg(args)
         log("bench: thermal sweep done")
-
     if not args.no_sur:
         out["surrogate"] = surrogate_leg(args)
         log("bench: surrogate done")
-
-    if not args.no_plain:
-        # the plain FP64 GPU FDTD form (generic tree kernel, FP64) on one aging
-        # interval of the same workload, for the speedup of the batched form
-        Bp = P.Batch(g, mat, dict(run, prec=0, stepper=1))
-        Bp.ir_solve()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        Bp.stress_step(run["ir_every"])
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - t0
-        ip = Bp.info()
-        out["plain_fp64_gpu"] = {"value": ip["node_steps"] / tp, "unit": "node-steps/s",
-                                 "sample": f"pg400, {run['ir_every']} BE steps of every tree, FP64, "
-                                           "one (tree) per lane tree-elimination kernel",
-                                 "speedup_of_value": value / (ip["node_steps"] / tp)}
-        Bp.close()
-        log("bench: plain fp64 done")
-
-    if not args.no_cpu:
-        import numpy as np
-        from oracle import oracle as O
-        O.build(force=False)
-        topo = O.topology(g, run["intervals_per_seg"])
-        # one aging interval of pg400 as the GPU job counts it: the IR solve
-        # plus ir_every BE steps of every tree.  One core steps the first
-        # quarter of the trees (the rest scales with their node count).
-        n_tr = max(1, topo.n_trees // 4)
-        t0 = time.perf_counter()
-        u, I, j, d0 = O.ir_solve(g, g.res_R0)
-        t_ir = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        sim = O.SampleSim(g, mat, run, topo)
-        sim.set_j(j)
-        act = np.zeros(topo.n_trees, np.uint8)
-        act[:n_tr] = 1
-        sim.set_active(act)
-        sim.steps(run["ir_every"], 0)
-        t_st = time.perf_counter() - t0
-        ns_c = int(topo.tree_off[n_tr]) * run["ir_every"]
-        ns_full = int(topo.tree_off[topo.n_trees]) * run["ir_every"]
-        t_full = t_ir + t_st * ns_full / ns_c
-        out["cpu_baseline"] = {"value": ns_full / t_full, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
-                               "sample": f"pg400, FP64 oracle, one aging interval: IR solve (sparse direct, "
-                                         f"{t_ir:.1f} s) + {run['ir_every']} BE steps of the first {n_tr} of "
-                                         f"{topo.n_trees} trees ({ns_c} node-steps, {t_st:.1f} s), stepping "
-                                         f"time scaled to all {ns_full} node-steps by node count"}
-        log("bench: cpu baseline done")
-        # the same oracle on every host core: the trees split over processes
-        # (spawned: no GPU state in them), each building the grid itself
-        import concurrent.futures as cf
-        import multiprocessing as mp
-        n_proc = max(1, min(16, os.cpu_count() or 1))
-        bounds = np.linspace(0, topo.n_trees, n_proc + 1).astype(int)
-        jobs = [(int(bounds[k]), int(bounds[k + 1]), j, run["ir_every"]) for k in range(n_proc)
-                if bounds[k + 1] > bounds[k]]
-        t0 = time.perf_counter()
-        with cf.ProcessPoolExecutor(max_workers=len(jobs), mp_context=mp.get_context("spawn")) as ex:
-            ns_all = sum(ex.map(_oracle_trees_worker, jobs))
-        ta = time.perf_counter() - t0
-        out["cpu_baseline"]["all_cores"] = {
-            "value": ns_all / (t_ir + ta), "unit": "node-steps/s", "cores": len(jobs),
-            "sample": f"pg400, FP64 oracle, one aging interval: the same IR solve on one core ({t_ir:.1f} s) + "
-                      f"{run['ir_every']} BE steps of all {topo.n_trees} trees split over {len(jobs)} processes "
-                      f"({ns_all} node-steps, {ta:.1f} s incl. each process's setup)"}
-        log("bench: cpu baseline (all cores) done")
     print(json.dumps(out), flush=True)
 
 

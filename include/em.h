@@ -296,7 +296,9 @@ typedef struct {
  * Stress starts at sigma_T.  hip_stream: a hipStream_t, or NULL for the null
  * stream.  *out receives the batch (NULL on failure); errors: EM_ERR_ARG for
  * a NULL or inconsistent argument, a struct_size other than this library's
- * sizeof of that struct, non-finite or non-positive geometry, a wire component with a
+ * sizeof of that struct, more than 2^31 - 2^20 stress nodes, resistors, node
+ * incidences or trees times samples (split a larger Monte Carlo study into
+ * batches over em_mc_params.sample_ids), non-finite or non-positive geometry, a wire component with a
  * cycle or a netlist without wire segments; EM_ERR_OOM when device or pinned
  * host memory runs out; EM_ERR_HIP for a failing HIP call.  The paper
  * re-partitions the degraded netlist at every aging step; the partition is

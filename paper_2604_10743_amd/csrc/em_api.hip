@@ -973,8 +973,15 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     b->vert = P.vert; b->kpos = P.kpos; b->seg_tree = P.seg_tree;
     const int ns = b->ns, nt = b->n_trees, S = b->S, nr = g->n_res, nn = g->n_nodes;
     for (int t = 0; t < nt; ++t) b->max_tree_nodes = std::max(b->max_tree_nodes, P.tree_off[t + 1] - P.tree_off[t]);
-    if ((long long)nt * S > (1LL << 31) - 1024 || (long long)ns * S > (1LL << 40))
-        return fail(b, EM_ERR_ARG, "batch too large");
+    // element counts of the [node][sample], [resistor][sample], [sample][node]
+    // and per-incidence arrays stay below 2^31 (the kernels' 32-bit element
+    // arithmetic); larger Monte Carlo studies run as several batches over
+    // disjoint em_mc_params.sample_ids
+    const long long lim = (1LL << 31) - (1LL << 20);
+    if ((long long)nt * S > lim || (long long)ns * S > lim || (long long)g->n_res * S > lim ||
+        (long long)g->n_nodes * S > lim || 2LL * g->n_res * S > lim)
+        return fail(b, EM_ERR_ARG, "batch too large: stress nodes, resistors or incidences x samples must stay "
+                                   "below 2^31 (split the samples over batches with em_mc_params.sample_ids)");
 
     // children of each stress node, ascending
     std::vector<int> child_off(ns + 1, 0), child;
@@ -1311,7 +1318,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
         if (a.nlev >= 1) {
             a.l0.ne0 = (int)H.e0_res.size();
             UP(a.l0.e0_res, H.e0_res); UP(a.l0.e0_a, H.e0_a); UP(a.l0.e0_b, H.e0_b);
-            AL(a.l0.w0, double, XS);
+            AL(a.l0.w0, mgreal, XS);
             for (int l = 1; l <= a.nlev; ++l) {
                 const AmgHostLevel &h = H.lev[l];
                 AmgLevel &L = a.lev[l];
@@ -1320,13 +1327,14 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
                 UP(L.int_off, h.int_off); UP(L.int_e, h.int_e);
                 UP(L.src_off, h.src_off); UP(L.src_e, h.src_e);
                 UP(L.adj_off, h.adj_off); UP(L.adj_nbr, h.adj_nbr); UP(L.adj_e, h.adj_e);
-                AL(L.D, double, (size_t)S * h.n); AL(L.W, double, (size_t)S * std::max(h.ne, 1));
-                AL(L.b, double, (size_t)S * h.n); AL(L.x, double, (size_t)S * h.n);
-                AL(L.y, double, (size_t)S * h.n); AL(L.w, double, (size_t)S * h.n);
+                AL(L.D, mgreal, (size_t)S * h.n); AL(L.W, mgreal, (size_t)S * std::max(h.ne, 1));
+                AL(L.Wa, mgreal, (size_t)S * std::max(2 * h.ne, 1));
+                AL(L.b, mgreal, (size_t)S * h.n); AL(L.x, mgreal, (size_t)S * h.n);
+                AL(L.y, mgreal, (size_t)S * h.n); AL(L.w, mgreal, (size_t)S * h.n);
             }
             const int nc = a.lev[a.nlev].n;
             a.dense = nc <= AMG_NC_MAX ? 1 : 0;
-            if (a.dense) AL(a.Ainv, double, (size_t)S * nc * nc);
+            if (a.dense) AL(a.Ainv, mgreal, (size_t)S * nc * nc);
             b->use_amg = true;
             a.omega = 0.9;          // Jacobi weight and coarse-correction scale chosen by
             a.alpha = 1.4;          // measurement (PCG iterations on the P/G grids)

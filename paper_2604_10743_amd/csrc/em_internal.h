@@ -139,6 +139,13 @@ struct Dev {
 constexpr int AMG_MAXLEV = 16;
 constexpr int AMG_NC_MAX = 88;          // coarsest level inverted densely when this small
 
+// Storage type of the multigrid preconditioner (operators, V-cycle vectors,
+// coarsest inverse, level-0 scratch): float halves its memory traffic; every
+// operation on it runs in double and the CG itself (iterate, residual,
+// search direction, its operator, dot products, stopping rule) stays FP64,
+// so the precision of the solution is set by the CG's FP64 residual alone.
+using mgreal = float;
+
 struct AmgLevel {
     int n, ne, nf, nef;                 // nodes, edges of this level; nodes, edges of the finer one
     int nmem;                           // member entries (mem_off[n])
@@ -147,21 +154,23 @@ struct AmgLevel {
     const int *int_off, *int_e;         // finer edges inside each node
     const int *src_off, *src_e;         // finer edges merged into each edge
     const int *adj_off, *adj_nbr, *adj_e;   // this level's graph (both directions)
-    double *D, *W;                      // [S][n] diagonal, [S][ne] edge conductance
-    double *b, *x, *y, *w;              // [S][n] V-cycle vectors
+    mgreal *D, *W;                      // [S][n] diagonal, [S][ne] edge conductance
+    mgreal *Wa;                         // [S][2 ne] conductance of each adjacency entry (W[adj_e]),
+                                        // contiguous per node as the V-cycle's rows read it
+    mgreal *b, *x, *y, *w;              // [S][n] V-cycle vectors
 };
 
 struct Amg0 {                           // level-0 edges: resistors with both ends off the pads
     int ne0;
     const int *e0_res, *e0_a, *e0_b;
-    double *w0;                         // [S][n_nodes] level-0 scratch
+    mgreal *w0;                         // [S][n_nodes] level-0 scratch
 };
 
 struct Amg {
     int nlev = 0;                       // coarse levels 1..nlev
     AmgLevel lev[AMG_MAXLEV + 1];
     Amg0 l0;
-    double *Ainv = nullptr;             // [S][n][n] inverse of the coarsest operator (dense case)
+    mgreal *Ainv = nullptr;             // [S][n][n] inverse of the coarsest operator (dense case)
     int dense = 0;
     double omega = 2.0 / 3.0, alpha = 1.0;
 };
@@ -255,8 +264,8 @@ void launch_ir_finish(const Dev &d, hipStream_t st);      // u, j, drop
 // z = M^-1 r (init: also pre-smoothing and p = z), partial r.z
 void launch_ir_finalize_rz(const Dev &d, hipStream_t st);
 void launch_amg_pre0(const Dev &d, double omega, hipStream_t st);
-void launch_amg_res0(const Dev &d, double *w0, hipStream_t st);
-void launch_amg_post0(const Dev &d, double *w0, const AmgLevel &L1, const double *r1, double alpha,
+void launch_amg_res0(const Dev &d, mgreal *w0, hipStream_t st);
+void launch_amg_post0(const Dev &d, mgreal *w0, const AmgLevel &L1, const mgreal *r1, double alpha,
                       double omega, bool init, hipStream_t st);
 void launch_amg_setup(const Dev &d, const Amg &a, hipStream_t st);
 void launch_amg_vcycle(const Dev &d, const Amg &a, bool init, hipStream_t st);

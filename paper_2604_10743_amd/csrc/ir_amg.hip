@@ -239,9 +239,18 @@ __global__ __launch_bounds__(AMG_BS) void k_amg_asm_edges(Dev d, Amg0 z, AmgLeve
     L.W[(size_t)s * L.ne + E] = acc;
 }
 
+// Conductances in adjacency order: row I's couplings contiguous, as the
+// residual and smoothing passes read them (the edge numbering scatters them).
+__global__ __launch_bounds__(AMG_BS) void k_amg_asm_adj(Dev d, AmgLevel L)
+{
+    int k = blockIdx.x * AMG_BS + threadIdx.x, s = blockIdx.y;
+    if (k >= 2 * L.ne || d.conv[s]) return;
+    L.Wa[(size_t)s * 2 * L.ne + k] = L.W[(size_t)s * L.ne + L.adj_e[k]];
+}
+
 // Dense inverse of the coarsest operator of one sample (Gauss-Jordan in LDS,
 // no pivoting: the operator is symmetric positive definite), symmetrised.
-__global__ __launch_bounds__(AMG_BS) void k_amg_coarse_inv(AmgLevel C, double *Ainv, const uint8_t *conv)
+__global__ __launch_bounds__(AMG_BS) void k_amg_coarse_inv(AmgLevel C, mgreal *Ainv, const uint8_t *conv)
 {
     __shared__ double A[AMG_NC_MAX][AMG_NC_MAX];
     __shared__ double prow[AMG_NC_MAX], pcol[AMG_NC_MAX];
@@ -269,18 +278,18 @@ __global__ __launch_bounds__(AMG_BS) void k_amg_coarse_inv(AmgLevel C, double *A
         }
         __syncthreads();
     }
-    double *O = Ainv + (size_t)s * n * n;
+    mgreal *O = Ainv + (size_t)s * n * n;
     for (int q = t; q < n * n; q += AMG_BS) {
         int i = q / n, j = q % n;
         O[q] = 0.5 * (A[i][j] + A[j][i]);
     }
 }
 
-__device__ inline double amg_Av(const AmgLevel &L, int s, int I, const double *v)
+__device__ inline double amg_Av(const AmgLevel &L, int s, int I, const mgreal *v)
 {
-    const double *W = L.W + (size_t)s * L.ne;
-    double a = L.D[(size_t)s * L.n + I] * v[I];
-    for (int k = L.adj_off[I]; k < L.adj_off[I + 1]; ++k) a -= W[L.adj_e[k]] * v[L.adj_nbr[k]];
+    const mgreal *Wa = L.Wa + (size_t)s * 2 * L.ne;
+    double a = (double)L.D[(size_t)s * L.n + I] * (double)v[I];
+    for (int k = L.adj_off[I]; k < L.adj_off[I + 1]; ++k) a -= (double)Wa[k] * (double)v[L.adj_nbr[k]];
     return a;
 }
 
@@ -289,9 +298,9 @@ __device__ inline double amg_Av(const AmgLevel &L, int s, int I, const double *v
 
 // b = sum of the finer level's residual w over the members; pre-smoothing
 // from zero, x = omega b / D.
-__device__ inline void amg_restrict_one(const AmgLevel &L, const double *wf, double omega, int s, int I)
+__device__ inline void amg_restrict_one(const AmgLevel &L, const mgreal *wf, double omega, int s, int I)
 {
-    const double *w = wf + (size_t)s * L.nf;
+    const mgreal *w = wf + (size_t)s * L.nf;
     double acc = 0.0;
     for (int k = L.mem_off[I]; k < L.mem_off[I + 1]; ++k) acc += w[L.mem[k]];
     size_t x = (size_t)s * L.n + I;
@@ -307,18 +316,18 @@ __device__ inline void amg_res_one(const AmgLevel &L, int s, int I)
 }
 
 // coarsest level: x = A^-1 b (dense), or b / D
-__device__ inline void amg_coarse_one(const AmgLevel &C, const double *Ainv, int dense, int s, int i)
+__device__ inline void amg_coarse_one(const AmgLevel &C, const mgreal *Ainv, int dense, int s, int i)
 {
     const int n = C.n;
     size_t x = (size_t)s * n + i;
     double v;
     if (dense) {
-        const double *row = Ainv + ((size_t)s * n + i) * n;
-        const double *b = C.b + (size_t)s * n;
+        const mgreal *row = Ainv + ((size_t)s * n + i) * n;
+        const mgreal *b = C.b + (size_t)s * n;
         v = 0.0;
-        for (int j = 0; j < n; ++j) v += row[j] * b[j];
+        for (int j = 0; j < n; ++j) v += (double)row[j] * (double)b[j];
     } else {
-        v = C.b[x] / C.D[x];
+        v = (double)C.b[x] / (double)C.D[x];
     }
     C.x[x] = v;
 }
@@ -326,23 +335,23 @@ __device__ inline void amg_coarse_one(const AmgLevel &C, const double *Ainv, int
 // Up-sweep at a coarse level: y = x + alpha P rc, formed on the fly for the
 // node and its neighbours, then post-smoothing out = y + omega (b - A y) / D.
 // out (the level's result) is the level's y array.
-__device__ inline void amg_up_one(const AmgLevel &L, const AmgLevel &C, const double *rc, double alpha,
+__device__ inline void amg_up_one(const AmgLevel &L, const AmgLevel &C, const mgreal *rc, double alpha,
                                   double omega, int s, int I)
 {
-    const double *xl = L.x + (size_t)s * L.n, *W = L.W + (size_t)s * L.ne;
-    const double *rcs = rc + (size_t)s * C.n;
+    const mgreal *xl = L.x + (size_t)s * L.n, *Wa = L.Wa + (size_t)s * 2 * L.ne;
+    const mgreal *rcs = rc + (size_t)s * C.n;
     auto yv = [&](int J) {
         int K = C.agg[J];
-        return xl[J] + (K >= 0 ? alpha * rcs[K] : 0.0);
+        return (double)xl[J] + (K >= 0 ? alpha * (double)rcs[K] : 0.0);
     };
     size_t x = (size_t)s * L.n + I;
-    const double yi = yv(I), Dd = L.D[x];
+    const double yi = yv(I), Dd = (double)L.D[x];
     double a = Dd * yi;
-    for (int k = L.adj_off[I]; k < L.adj_off[I + 1]; ++k) a -= W[L.adj_e[k]] * yv(L.adj_nbr[k]);
+    for (int k = L.adj_off[I]; k < L.adj_off[I + 1]; ++k) a -= (double)Wa[k] * yv(L.adj_nbr[k]);
     L.y[x] = yi + omega * (L.b[x] - a) / Dd;
 }
 
-__global__ __launch_bounds__(AMG_BS) void k_amg_restrict(Dev d, AmgLevel L, const double *wf, double omega)
+__global__ __launch_bounds__(AMG_BS) void k_amg_restrict(Dev d, AmgLevel L, const mgreal *wf, double omega)
 {
     int I = blockIdx.x * AMG_BS + threadIdx.x, s = blockIdx.y;
     if (I >= L.n || d.conv[s]) return;
@@ -356,14 +365,14 @@ __global__ __launch_bounds__(AMG_BS) void k_amg_res(Dev d, AmgLevel L)
     amg_res_one(L, s, I);
 }
 
-__global__ __launch_bounds__(AMG_BS) void k_amg_coarse_solve(Dev d, AmgLevel C, const double *Ainv, int dense)
+__global__ __launch_bounds__(AMG_BS) void k_amg_coarse_solve(Dev d, AmgLevel C, const mgreal *Ainv, int dense)
 {
     int s = blockIdx.x;
     if (d.conv[s]) return;
     for (int i = threadIdx.x; i < C.n; i += AMG_BS) amg_coarse_one(C, Ainv, dense, s, i);
 }
 
-__global__ __launch_bounds__(AMG_BS) void k_amg_up(Dev d, AmgLevel L, AmgLevel C, const double *rc,
+__global__ __launch_bounds__(AMG_BS) void k_amg_up(Dev d, AmgLevel L, AmgLevel C, const mgreal *rc,
                                                    double alpha, double omega)
 {
     int I = blockIdx.x * AMG_BS + threadIdx.x, s = blockIdx.y;
@@ -380,7 +389,7 @@ constexpr int AMG_TAIL_N = 512;          // largest level a tail starts at
 struct AmgTail {
     int lt, nlev, dense;
     double omega, alpha;
-    const double *Ainv;
+    const mgreal *Ainv;
     AmgLevel lev[AMG_TAIL_LEV];          // lev[k] = level lt + k
 };
 
@@ -401,7 +410,7 @@ __global__ __launch_bounds__(BS) void k_amg_tail(Dev d, AmgTail t)
     __syncthreads();
     for (int k = top - 1; k >= 0; --k) {
         const AmgLevel &L = t.lev[k], &C = t.lev[k + 1];
-        const double *rc = (k + 1 == top) ? C.x : C.y;
+        const mgreal *rc = (k + 1 == top) ? C.x : C.y;
         for (int I = T; I < L.n; I += BS) amg_up_one(L, C, rc, t.alpha, t.omega, s, I);
         __syncthreads();
     }
@@ -415,7 +424,10 @@ void launch_amg_setup(const Dev &d, const Amg &a, hipStream_t st)
         const AmgLevel &L = a.lev[l];
         const AmgLevel &F = a.lev[l > 1 ? l - 1 : 1];
         k_amg_asm_nodes<<<grid_of(L.n, d.S), AMG_BS, 0, st>>>(d, a.l0, L, F, l);
-        if (L.ne > 0) k_amg_asm_edges<<<grid_of(L.ne, d.S), AMG_BS, 0, st>>>(d, a.l0, L, F, l);
+        if (L.ne > 0) {
+            k_amg_asm_edges<<<grid_of(L.ne, d.S), AMG_BS, 0, st>>>(d, a.l0, L, F, l);
+            k_amg_asm_adj<<<grid_of(2 * L.ne, d.S), AMG_BS, 0, st>>>(d, L);
+        }
     }
     if (a.dense) k_amg_coarse_inv<<<d.S, AMG_BS, 0, st>>>(a.lev[a.nlev], a.Ainv, d.conv);
 }

@@ -59,26 +59,28 @@ struct L0View {                         // level 0 (the iterated system) of one 
     const double *G, *D;                // incidence conductances, diagonal
     const uint8_t *fr;                  // free flags (LDS form), or null: live and not a pad
     const uint8_t *live, *is_pad;
-    double *u, *r, *z, *p, *q, *w0;
+    double *u, *r, *z, *p, *q;
+    mgreal *w0;
     __device__ bool free_(int i) const { return fr ? fr[i] != 0 : (live[i] && !is_pad[i]); }
     // (A v)_i at a free node (v vanishes off the free nodes)
-    __device__ double Av(int i, const double *v) const
+    template <typename V>
+    __device__ double Av(int i, const V *v) const
     {
-        double a = D[i] * v[i];
-        for (int k = off[i]; k < off[i + 1]; ++k) a -= G[k] * v[nbr[k]];
+        double a = D[i] * (double)v[i];
+        for (int k = off[i]; k < off[i + 1]; ++k) a -= G[k] * (double)v[nbr[k]];
         return a;
     }
 };
 
 struct LView {                          // coarse level l >= 1 of one sample
     int n;
-    const int *agg, *mem_off, *mem, *adj_off, *adj_nbr, *adj_e;
-    const double *D, *W;
-    double *b, *x, *y, *w;
-    __device__ double Av(int I, const double *v) const
+    const int *agg, *mem_off, *mem, *adj_off, *adj_nbr;
+    const mgreal *D, *Wa;               // diagonal; conductance of each adjacency entry
+    mgreal *b, *x, *y, *w;
+    __device__ double Av(int I, const mgreal *v) const
     {
-        double a = D[I] * v[I];
-        for (int k = adj_off[I]; k < adj_off[I + 1]; ++k) a -= W[adj_e[k]] * v[adj_nbr[k]];
+        double a = (double)D[I] * (double)v[I];
+        for (int k = adj_off[I]; k < adj_off[I + 1]; ++k) a -= (double)Wa[k] * (double)v[adj_nbr[k]];
         return a;
     }
 };
@@ -91,10 +93,10 @@ struct GlobalLevels {
     {
         const AmgLevel &L = a->lev[l];
         const size_t o = (size_t)s * L.n;
-        return LView{L.n, L.agg, L.mem_off, L.mem, L.adj_off, L.adj_nbr, L.adj_e,
-                     L.D + o, L.W + (size_t)s * L.ne, L.b + o, L.x + o, L.y + o, L.w + o};
+        return LView{L.n, L.agg, L.mem_off, L.mem, L.adj_off, L.adj_nbr,
+                     L.D + o, L.Wa + (size_t)s * 2 * L.ne, L.b + o, L.x + o, L.y + o, L.w + o};
     }
-    __device__ const double *Ainv() const
+    __device__ const mgreal *Ainv() const
     {
         const size_t nc = a->lev[a->nlev].n;
         return a->Ainv + (size_t)s * nc * nc;
@@ -106,7 +108,7 @@ struct LdsLayout {
     int bytes;
     int off, nbr, G, D, fr, u, r, z, p, q, w0;
     int agg[AMG_MAXLEV + 1], mem_off[AMG_MAXLEV + 1], mem[AMG_MAXLEV + 1], adj_off[AMG_MAXLEV + 1],
-        adj_nbr[AMG_MAXLEV + 1], adj_e[AMG_MAXLEV + 1], LD[AMG_MAXLEV + 1], LW[AMG_MAXLEV + 1],
+        adj_nbr[AMG_MAXLEV + 1], LD[AMG_MAXLEV + 1], LWa[AMG_MAXLEV + 1],
         b[AMG_MAXLEV + 1], x[AMG_MAXLEV + 1], y[AMG_MAXLEV + 1], w[AMG_MAXLEV + 1];
     int Ainv;
 };
@@ -120,12 +122,12 @@ struct LdsLevels {
         const LdsLayout &y = *ly;
         return LView{a->lev[l].n, (const int *)(sm + y.agg[l]), (const int *)(sm + y.mem_off[l]),
                      (const int *)(sm + y.mem[l]), (const int *)(sm + y.adj_off[l]),
-                     (const int *)(sm + y.adj_nbr[l]), (const int *)(sm + y.adj_e[l]),
-                     (const double *)(sm + y.LD[l]), (const double *)(sm + y.LW[l]),
-                     (double *)(sm + y.b[l]), (double *)(sm + y.x[l]), (double *)(sm + y.y[l]),
-                     (double *)(sm + y.w[l])};
+                     (const int *)(sm + y.adj_nbr[l]),
+                     (const mgreal *)(sm + y.LD[l]), (const mgreal *)(sm + y.LWa[l]),
+                     (mgreal *)(sm + y.b[l]), (mgreal *)(sm + y.x[l]), (mgreal *)(sm + y.y[l]),
+                     (mgreal *)(sm + y.w[l])};
     }
-    __device__ const double *Ainv() const { return (const double *)(sm + ly->Ainv); }
+    __device__ const mgreal *Ainv() const { return (const mgreal *)(sm + ly->Ainv); }
 };
 
 // z = M^-1 r by one V-cycle; returns r.z (every thread).  When setp is set
@@ -136,21 +138,22 @@ __device__ double wg_vcycle(const L0View &S0, const Amg &a, const Lev &lv, bool 
     const int T = threadIdx.x, n = S0.n, nl = a.nlev;
     const double om = a.omega, al = a.alpha;
     const double *r = S0.r;
-    double *z = S0.z, *w0 = S0.w0;
+    double *z = S0.z;
+    mgreal *w0 = S0.w0;
     // pre-smoothing from zero
     for (int i = T; i < n; i += BS) z[i] = S0.free_(i) ? om * r[i] / S0.D[i] : 0.0;
     __syncthreads();
     for (int i = T; i < n; i += BS) w0[i] = S0.free_(i) ? r[i] - S0.Av(i, z) : 0.0;
     __syncthreads();
     // down: restriction by member sums, pre-smoothing, residual
-    const double *wf = w0;
+    const mgreal *wf = w0;
     for (int l = 1; l <= nl; ++l) {
         const LView L = lv.lev(l);
         for (int I = T; I < L.n; I += BS) {
             double acc = 0.0;
             for (int k = L.mem_off[I]; k < L.mem_off[I + 1]; ++k) acc += wf[L.mem[k]];
             L.b[I] = acc;
-            L.x[I] = om * acc / L.D[I];
+            L.x[I] = om * acc / (double)L.D[I];
         }
         __syncthreads();
         if (l < nl) {
@@ -162,38 +165,38 @@ __device__ double wg_vcycle(const L0View &S0, const Amg &a, const Lev &lv, bool 
     // coarsest level
     {
         const LView C = lv.lev(nl);
-        const double *Ai = a.dense ? lv.Ainv() : nullptr;
+        const mgreal *Ai = a.dense ? lv.Ainv() : nullptr;
         if (Ai) {
             // eight lanes per row (aligned groups of one wavefront, active or
             // idle together), each a strided part of the row's dot product
             constexpr int TPR = 8;
             for (int idx = T; idx < C.n * TPR; idx += BS) {
                 const int i = idx / TPR, part = idx - i * TPR;
-                const double *row = Ai + (size_t)i * C.n;
+                const mgreal *row = Ai + (size_t)i * C.n;
                 double v = 0.0;
-                for (int j = part; j < C.n; j += TPR) v += row[j] * C.b[j];
+                for (int j = part; j < C.n; j += TPR) v += (double)row[j] * (double)C.b[j];
                 v += __shfl_xor(v, 4, 64);
                 v += __shfl_xor(v, 2, 64);
                 v += __shfl_xor(v, 1, 64);
                 if (part == 0) C.x[i] = v;
             }
         } else {
-            for (int i = T; i < C.n; i += BS) C.x[i] = C.b[i] / C.D[i];
+            for (int i = T; i < C.n; i += BS) C.x[i] = (double)C.b[i] / (double)C.D[i];
         }
         __syncthreads();
     }
     // up: prolongation of the coarse result, post-smoothing
     for (int l = nl - 1; l >= 1; --l) {
         const LView L = lv.lev(l), C = lv.lev(l + 1);
-        const double *rc = l + 1 == nl ? C.x : C.y;
+        const mgreal *rc = l + 1 == nl ? C.x : C.y;
         for (int I = T; I < L.n; I += BS) {
             auto yv = [&](int J) {
                 const int K = C.agg[J];
-                return L.x[J] + (K >= 0 ? al * rc[K] : 0.0);
+                return (double)L.x[J] + (K >= 0 ? al * (double)rc[K] : 0.0);
             };
-            const double yi = yv(I), Dd = L.D[I];
+            const double yi = yv(I), Dd = (double)L.D[I];
             double acc = Dd * yi;
-            for (int k = L.adj_off[I]; k < L.adj_off[I + 1]; ++k) acc -= L.W[L.adj_e[k]] * yv(L.adj_nbr[k]);
+            for (int k = L.adj_off[I]; k < L.adj_off[I + 1]; ++k) acc -= (double)L.Wa[k] * yv(L.adj_nbr[k]);
             L.y[I] = yi + om * (L.b[I] - acc) / Dd;
         }
         __syncthreads();
@@ -201,10 +204,10 @@ __device__ double wg_vcycle(const L0View &S0, const Amg &a, const Lev &lv, bool 
     // level 0: w0 = z0 + alpha P y1, then z = w0 + omega (r - A w0) / D
     {
         const LView L1 = lv.lev(1);
-        const double *r1 = nl == 1 ? L1.x : L1.y;
+        const mgreal *r1 = nl == 1 ? L1.x : L1.y;
         for (int i = T; i < n; i += BS) {
             const int J = L1.agg[i];
-            w0[i] = (S0.free_(i) && J >= 0) ? z[i] + al * r1[J] : 0.0;
+            w0[i] = (S0.free_(i) && J >= 0) ? z[i] + al * (double)r1[J] : 0.0;
         }
         __syncthreads();
     }
@@ -212,7 +215,7 @@ __device__ double wg_vcycle(const L0View &S0, const Amg &a, const Lev &lv, bool 
     for (int i = T; i < n; i += BS) {
         double zi = 0.0;
         if (S0.free_(i)) {
-            zi = w0[i] + om * (r[i] - S0.Av(i, w0)) / S0.D[i];
+            zi = (double)w0[i] + om * (r[i] - S0.Av(i, w0)) / S0.D[i];
             rz += r[i] * zi;
         }
         z[i] = zi;
@@ -310,8 +313,8 @@ __device__ inline void cp_i32(int *dst, const int *src, int n)
 {
     for (int i = threadIdx.x; i < n; i += BS) dst[i] = src[i];
 }
-template <int BS>
-__device__ inline void cp_f64(double *dst, const double *src, int n)
+template <int BS, typename T>
+__device__ inline void cp_arr(T *dst, const T *src, int n)
 {
     for (int i = threadIdx.x; i < n; i += BS) dst[i] = src[i];
 }
@@ -333,10 +336,10 @@ __global__ __launch_bounds__(LDS_BS) void k_ir_pcg_lds(Dev d, const Amg *__restr
     // load the sample's system and hierarchy
     cp_i32<LDS_BS>((int *)(sm + ly.off), d.ninc_off, n + 1);
     cp_i32<LDS_BS>((int *)(sm + ly.nbr), d.ninc_nbr, nnz);
-    cp_f64<LDS_BS>((double *)(sm + ly.G), d.G_inc + (size_t)s * nnz, nnz);
-    cp_f64<LDS_BS>((double *)(sm + ly.D), d.diag + o, n);
-    cp_f64<LDS_BS>((double *)(sm + ly.u), d.u + o, n);
-    cp_f64<LDS_BS>((double *)(sm + ly.r), d.r + o, n);
+    cp_arr<LDS_BS>((double *)(sm + ly.G), d.G_inc + (size_t)s * nnz, nnz);
+    cp_arr<LDS_BS>((double *)(sm + ly.D), d.diag + o, n);
+    cp_arr<LDS_BS>((double *)(sm + ly.u), d.u + o, n);
+    cp_arr<LDS_BS>((double *)(sm + ly.r), d.r + o, n);
     for (int i = threadIdx.x; i < n; i += LDS_BS)
         ((uint8_t *)(sm + ly.fr))[i] = (d.live[o + i] && !d.is_pad[i]) ? 1 : 0;
     for (int l = 1; l <= a.nlev; ++l) {
@@ -346,13 +349,12 @@ __global__ __launch_bounds__(LDS_BS) void k_ir_pcg_lds(Dev d, const Amg *__restr
         cp_i32<LDS_BS>((int *)(sm + ly.mem[l]), L.mem, L.nmem);
         cp_i32<LDS_BS>((int *)(sm + ly.adj_off[l]), L.adj_off, L.n + 1);
         cp_i32<LDS_BS>((int *)(sm + ly.adj_nbr[l]), L.adj_nbr, 2 * L.ne);
-        cp_i32<LDS_BS>((int *)(sm + ly.adj_e[l]), L.adj_e, 2 * L.ne);
-        cp_f64<LDS_BS>((double *)(sm + ly.LD[l]), L.D + (size_t)s * L.n, L.n);
-        cp_f64<LDS_BS>((double *)(sm + ly.LW[l]), L.W + (size_t)s * L.ne, L.ne);
+        cp_arr<LDS_BS>((mgreal *)(sm + ly.LD[l]), L.D + (size_t)s * L.n, L.n);
+        cp_arr<LDS_BS>((mgreal *)(sm + ly.LWa[l]), L.Wa + (size_t)s * 2 * L.ne, 2 * L.ne);
     }
     if (a.dense) {
         const int nc = a.lev[a.nlev].n;
-        cp_f64<LDS_BS>((double *)(sm + ly.Ainv), a.Ainv + (size_t)s * nc * nc, nc * nc);
+        cp_arr<LDS_BS>((mgreal *)(sm + ly.Ainv), a.Ainv + (size_t)s * nc * nc, nc * nc);
     }
     __syncthreads();
     L0View S0;
@@ -365,7 +367,7 @@ __global__ __launch_bounds__(LDS_BS) void k_ir_pcg_lds(Dev d, const Amg *__restr
     S0.live = nullptr;
     S0.is_pad = nullptr;
     S0.u = (double *)(sm + ly.u); S0.r = (double *)(sm + ly.r); S0.z = (double *)(sm + ly.z);
-    S0.p = (double *)(sm + ly.p); S0.q = (double *)(sm + ly.q); S0.w0 = (double *)(sm + ly.w0);
+    S0.p = (double *)(sm + ly.p); S0.q = (double *)(sm + ly.q); S0.w0 = (mgreal *)(sm + ly.w0);
     bool done;
     const int it = wg_pcg<LDS_BS>(S0, a, LdsLevels{sm, &ly, ap}, rtol * rtol * d.bb[s], max_iter, &done, red);
     for (int i = threadIdx.x; i < n; i += LDS_BS) d.u[o + i] = S0.u[i];
@@ -393,7 +395,7 @@ static LdsLayout lds_layout(const Dev &d, int nnz, const Amg &a)
     y.D = take(8LL * n);
     y.fr = take(n);
     y.u = take(8LL * n); y.r = take(8LL * n); y.z = take(8LL * n);
-    y.p = take(8LL * n); y.q = take(8LL * n); y.w0 = take(8LL * n);
+    y.p = take(8LL * n); y.q = take(8LL * n); y.w0 = take((long long)sizeof(mgreal) * n);
     for (int l = 1; l <= a.nlev; ++l) {
         const AmgLevel &L = a.lev[l];
         y.agg[l] = take(4LL * L.nf);
@@ -401,15 +403,15 @@ static LdsLayout lds_layout(const Dev &d, int nnz, const Amg &a)
         y.mem[l] = take(4LL * L.nmem);
         y.adj_off[l] = take(4LL * (L.n + 1));
         y.adj_nbr[l] = take(8LL * L.ne);
-        y.adj_e[l] = take(8LL * L.ne);
-        y.LD[l] = take(8LL * L.n);
-        y.LW[l] = take(8LL * L.ne);
-        y.b[l] = take(8LL * L.n); y.x[l] = take(8LL * L.n);
-        y.y[l] = take(8LL * L.n); y.w[l] = take(8LL * L.n);
+        const long long m = sizeof(mgreal);
+        y.LD[l] = take(m * L.n);
+        y.LWa[l] = take(2 * m * L.ne);
+        y.b[l] = take(m * L.n); y.x[l] = take(m * L.n);
+        y.y[l] = take(m * L.n); y.w[l] = take(m * L.n);
     }
     if (a.dense) {
         const long long nc = a.lev[a.nlev].n;
-        y.Ainv = take(8 * nc * nc);
+        y.Ainv = take((long long)sizeof(mgreal) * nc * nc);
     }
     y.bytes = at <= LDS_BYTES_MAX ? (int)at : 0;
     return y;

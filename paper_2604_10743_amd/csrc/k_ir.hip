@@ -281,16 +281,17 @@ EM_KERNEL void k_amg_pre0(Dev d, double omega)
 }
 
 // A v at free node i (v vanishes off the free nodes)
-__device__ inline double A0v(const Dev &d, int s, int i, const double *v)
+template <typename V>
+__device__ inline double A0v(const Dev &d, int s, int i, const V *v)
 {
     const double *Gi = d.G_inc + (size_t)s * d.ninc_off[d.n_nodes];
-    double a = d.diag[(size_t)s * d.n_nodes + i] * v[i];
-    for (int k = d.ninc_off[i]; k < d.ninc_off[i + 1]; ++k) a -= Gi[k] * v[d.ninc_nbr[k]];
+    double a = d.diag[(size_t)s * d.n_nodes + i] * (double)v[i];
+    for (int k = d.ninc_off[i]; k < d.ninc_off[i + 1]; ++k) a -= Gi[k] * (double)v[d.ninc_nbr[k]];
     return a;
 }
 
 // w0 = r - A z (z the pre-smoothed vector)
-EM_KERNEL void k_amg_res0(Dev d, double *w0)
+EM_KERNEL void k_amg_res0(Dev d, mgreal *w0)
 {
     int s = blockIdx.y, bx = blockIdx.x;
     if (d.conv[s]) return;
@@ -304,7 +305,7 @@ EM_KERNEL void k_amg_res0(Dev d, double *w0)
 }
 
 // w0 = z + alpha r1[agg] on the free nodes, 0 elsewhere (r1: level 1's result)
-EM_KERNEL void k_amg_prolong0(Dev d, double *w0, AmgLevel L1, const double *r1, double alpha)
+EM_KERNEL void k_amg_prolong0(Dev d, mgreal *w0, AmgLevel L1, const mgreal *r1, double alpha)
 {
     int s = blockIdx.y, bx = blockIdx.x;
     if (d.conv[s]) return;
@@ -313,17 +314,17 @@ EM_KERNEL void k_amg_prolong0(Dev d, double *w0, AmgLevel L1, const double *r1, 
         if (i >= d.n_nodes) break;
         size_t x = (size_t)s * d.n_nodes + i;
         int J = L1.agg[i];
-        w0[x] = (is_free(d, s, i) && J >= 0) ? d.z[x] + alpha * r1[(size_t)s * L1.n + J] : 0.0;
+        w0[x] = (is_free(d, s, i) && J >= 0) ? d.z[x] + alpha * (double)r1[(size_t)s * L1.n + J] : 0.0;
     }
 }
 
 // z = w0 + omega (r - A w0) / diag on the free nodes, 0 elsewhere; partial
 // r.z; at the start of a solve also p = z
-EM_KERNEL void k_amg_smooth0(Dev d, const double *w0, double omega, int init)
+EM_KERNEL void k_amg_smooth0(Dev d, const mgreal *w0, double omega, int init)
 {
     int s = blockIdx.y, bx = blockIdx.x;
     if (d.conv[s]) return;
-    const double *w = w0 + (size_t)s * d.n_nodes;
+    const mgreal *w = w0 + (size_t)s * d.n_nodes;
     double rz = 0.0;
     for (int c = 0; c < IR_NPT; ++c) {
         int i = bx * IR_NPB + c * IR_BS + threadIdx.x;
@@ -331,7 +332,7 @@ EM_KERNEL void k_amg_smooth0(Dev d, const double *w0, double omega, int init)
         size_t x = (size_t)s * d.n_nodes + i;
         double z = 0.0;
         if (is_free(d, s, i)) {
-            z = w[i] + omega * (d.r[x] - A0v(d, s, i, w)) / d.diag[x];
+            z = (double)w[i] + omega * (d.r[x] - A0v(d, s, i, w)) / d.diag[x];
             rz += d.r[x] * z;
         }
         d.z[x] = z;
@@ -504,11 +505,11 @@ void launch_amg_pre0(const Dev &d, double omega, hipStream_t st)
 {
     k_amg_pre0<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d, omega);
 }
-void launch_amg_res0(const Dev &d, double *w0, hipStream_t st)
+void launch_amg_res0(const Dev &d, mgreal *w0, hipStream_t st)
 {
     k_amg_res0<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d, w0);
 }
-void launch_amg_post0(const Dev &d, double *w0, const AmgLevel &L1, const double *r1, double alpha,
+void launch_amg_post0(const Dev &d, mgreal *w0, const AmgLevel &L1, const mgreal *r1, double alpha,
                       double omega, bool init, hipStream_t st)
 {
     k_amg_prolong0<<<dim3(d.ir_nblk, d.S), IR_BS, 0, st>>>(d, w0, L1, r1, alpha);

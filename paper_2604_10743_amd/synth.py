@@ -405,6 +405,115 @@ def pg_grid(seed: int = 2001, n: int = 400, pitch=5 * UM, w1=0.5 * UM, w2=1.0 * 
     return g
 
 
+def _cut_runs(rng, n_seg: int, span) -> np.ndarray:
+    """Keep-mask over a line of n_seg segments cut into pieces of U{span}
+    segments separated by single missing segments."""
+    keep = np.ones(n_seg, bool)
+    c = 0
+    while c < n_seg:
+        c += int(rng.integers(span[0], span[1] + 1))
+        if c < n_seg:
+            keep[c] = False
+            c += 1
+    return keep
+
+
+FULLCHIP_SINK_SCALE = 1.0
+
+
+def fullchip_grid(seed: int = 5001, n: int = 2000, pitch=1 * UM, e12: int = 4, e34: int = 20,
+                  w=(0.4 * UM, 0.6 * UM, 0.6 * UM, 1.0 * UM), H=(0.2 * UM, 0.2 * UM, 0.2 * UM, 0.2 * UM),
+                  cut12=(2, 8), cut34=(20, 60), R_via=(0.5, 0.5, 0.25), pad_lattice=4, via12_every=1,
+                  via23_every=1, via34_every=2, vdd=1.0,
+                  sink_mu=np.log(1e-6), sink_sigma=0.5, sink_scale=1.0, base_K=340.0, n_spots=12,
+                  amp_range=(20.0, 70.0), sig_range=(60 * UM, 200 * UM), raster=4 * UM) -> Grid:
+    """Four-layer P/G grid on an n x n routing grid of ``pitch`` tracks (a
+    2 mm die at the defaults): M1 rows and M2 columns on every e12-th track,
+    M3 rows and M4 columns on every e34-th track, each with a node at every
+    crossing of its own layer pair.  M1 and M2 stripes are cut into short
+    trees of U{cut12} segments, M3 and M4 stripes into lines of U{cut34}
+    segments, by single missing segments.  Vias: M1-M2 at the crossings on
+    a row or column index that is a multiple of via12_every; M2-M3 at the M3
+    nodes on a row or column index that is a multiple of via23_every; M3-M4
+    at the M3 nodes whose row and column indices are both multiples of
+    via34_every.  VDD pads on M4 at a
+    pad_lattice x pad_lattice lattice; lognormal sinks on every M1 node;
+    thermal raster = base + n_spots Gaussian hotspots.  Built with array
+    operations (about 5e5 nodes and 7e5 resistors at the defaults)."""
+    rng = np.random.default_rng(seed)
+    m, m3 = n // e12, n // e34
+    r34 = e34 // e12                               # M2 nodes per M3 node spacing
+    n12, n34 = m * m, m3 * m3
+    base = np.array([0, n12, 2 * n12, 2 * n12 + n34, 2 * n12 + 2 * n34])
+    ii, jj = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+    II, JJ = np.meshgrid(np.arange(m3), np.arange(m3), indexing="ij")
+    xy12 = np.stack([jj.ravel() * e12 * pitch, ii.ravel() * e12 * pitch], 1)
+    xy34 = np.stack([JJ.ravel() * e34 * pitch, II.ravel() * e34 * pitch], 1)
+    xy = np.concatenate([xy12, xy12, xy34, xy34])
+    layer = np.concatenate([np.full(n12, 1), np.full(n12, 2), np.full(n34, 3), np.full(n34, 4)]).astype(np.int32)
+    ra, rb, L, W, Hh, via, R = [], [], [], [], [], [], []
+
+    def wires(lay, mm, horizontal, span, spacing):
+        keep = np.stack([_cut_runs(rng, mm - 1, span) for _ in range(mm)])      # [line][segment]
+        li, sj = np.nonzero(keep)
+        if horizontal:
+            a, b = li * mm + sj, li * mm + sj + 1
+        else:
+            a, b = sj * mm + li, (sj + 1) * mm + li
+        k = lay - 1
+        ra.append(base[k] + a); rb.append(base[k] + b)
+        L.append(np.full(a.size, spacing)); W.append(np.full(a.size, w[k])); Hh.append(np.full(a.size, H[k]))
+        via.append(np.zeros(a.size, np.uint8))
+        R.append(RHO_CU * spacing / (w[k] * H[k]) * np.ones(a.size))
+
+    wires(1, m, True, cut12, e12 * pitch)
+    wires(2, m, False, cut12, e12 * pitch)
+    wires(3, m3, True, cut34, e34 * pitch)
+    wires(4, m3, False, cut34, e34 * pitch)
+
+    def vias(a, b, rv):
+        ra.append(a); rb.append(b)
+        L.append(np.zeros(a.size)); W.append(np.full(a.size, w[0])); Hh.append(np.full(a.size, H[0]))
+        via.append(np.ones(a.size, np.uint8)); R.append(np.full(a.size, rv))
+
+    v12 = np.nonzero(((ii.ravel() % via12_every) == 0) | ((jj.ravel() % via12_every) == 0))[0]
+    vias(base[0] + v12, base[1] + v12, R_via[0])
+    v23 = np.nonzero(((II.ravel() % via23_every) == 0) | ((JJ.ravel() % via23_every) == 0))[0]
+    m2_at_m3 = (II.ravel()[v23] * r34) * m + JJ.ravel()[v23] * r34
+    vias(base[1] + m2_at_m3, base[2] + v23, R_via[1])
+    v34 = ((II.ravel() % via34_every) == 0) & ((JJ.ravel() % via34_every) == 0)
+    vias(base[2] + np.nonzero(v34)[0], base[3] + np.nonzero(v34)[0], R_via[2])
+    ra = np.concatenate(ra).astype(np.int32); rb = np.concatenate(rb).astype(np.int32)
+    L = np.concatenate(L); W = np.concatenate(W); Hh = np.concatenate(Hh)
+    via = np.concatenate(via); R0 = np.concatenate(R)
+    step = m3 // pad_lattice
+    pi = step // 2 + step * np.arange(pad_lattice)
+    pads = (base[3] + (pi[:, None] * m3 + pi[None, :]).ravel()).astype(np.int32)
+    sink = np.zeros(xy.shape[0])
+    sink[:n12] = sink_scale * np.exp(rng.normal(sink_mu, sink_sigma, n12))
+    # keep only the components that reach a pad (sparse M3-M4 vias leave M4
+    # pieces without one)
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    nn = xy.shape[0]
+    _, lab = connected_components(sp.coo_matrix((np.ones(ra.size), (ra, rb)), shape=(nn, nn)), directed=False)
+    live = np.isin(lab, np.unique(lab[pads]))
+    remap = -np.ones(nn, np.int64)
+    remap[live] = np.arange(int(live.sum()))
+    kr = live[ra] & live[rb]
+    ra, rb = remap[ra[kr]].astype(np.int32), remap[rb[kr]].astype(np.int32)
+    L, W, Hh, via, R0 = L[kr], W[kr], Hh[kr], via[kr], R0[kr]
+    xy, layer, sink = xy[live], layer[live], sink[live]
+    pads = remap[pads].astype(np.int32)
+    g = Grid(xy=xy, layer=layer, res_a=ra, res_b=rb, res_len=L, res_w=W, res_h=Hh,
+             res_is_via=via, res_R0=R0, pad_node=pads, vdd=vdd, sink_I=sink,
+             name=f"fullchip{n}_s{seed}")
+    ext = (n - 1) * pitch
+    tm, x0, y0, dxr, dyr = gaussian_hotspot_map(seed + 7, ext, ext, base_K, n_spots, amp_range, sig_range, raster)
+    g.tmap, g.tmap_x0, g.tmap_y0, g.tmap_dx, g.tmap_dy = tm, x0, y0, dxr, dyr
+    return g
+
+
 # ----------------------------------------------------------------------------
 # Named workloads
 # ----------------------------------------------------------------------------
@@ -445,6 +554,10 @@ def workload(name: str):
                     seg_range=(48, 95), base_K=330.0)
         return (g, mat, default_run(prec=1, T_ambient=330.0),
                 dict(n_samples=1024, seed=3001, cov_kappa=0.2, cov_scrit=0.2))
+    if name == "fullchip":
+        g = fullchip_grid(5001, sink_scale=FULLCHIP_SINK_SCALE)
+        return (g, mat, default_run(prec=1, T_ambient=340.0, ir_every=50, joule=1),
+                dict(n_samples=256, seed=5001, cov_kappa=0.2, cov_scrit=0.2))
     if name == "long_lines":
         g = pg_grid(6001, n=24, n_cols=257, seg_range=(212, 256), col_seg_range=(12, 23), via_every=32,
                     pad_lattice=4, sink_scale=0.16, base_K=330.0)
@@ -566,6 +679,14 @@ def thermal_variants(g: Grid, hot_centers, cold_centers, mean_K: float, amp_K: f
         h.name = f"{g.name}_{name}"
         out[name] = h
     return out
+
+
+def seeded_current_density(g: Grid, seed: int, lo: float = 1e9, hi: float = 5e10) -> np.ndarray:
+    """Per-resistor current density +-U[lo, hi] A/m^2 with equiprobable sign
+    (zero on vias): prescribed currents of the tiny-trees kind for any grid."""
+    rng = np.random.default_rng(seed)
+    j = rng.uniform(lo, hi, g.n_res) * np.where(rng.random(g.n_res) < 0.5, -1.0, 1.0)
+    return np.where(g.res_is_via != 0, 0.0, j)
 
 
 def with_prescribed_j(g: Grid, seg_j: np.ndarray) -> Grid:
