@@ -304,7 +304,7 @@ def mc_leg(args, name, oracle, plain, var=None, joule=False, n_samples=None):
 STEP_DESC = {
     "fullchip": "fullchip: 2000x2000 routing grid (1 um tracks, 2 mm die), 4 metal layers (M1/M2 stripes "
                 "every 4th track cut into trees of 2-8 segments, M3/M4 every 20th track cut into lines of "
-                "20-60 segments), 8 VDD pads, thermal map 340 K + 12 hotspots (+20..70 K) with the "
+                "40-99 segments, M3-M4 vias every 4th node), 16 VDD pads on M4, thermal map 340 K + 12 hotspots (+20..70 K) with the "
                 "Joule-heating pre-pass, 2000 BE steps over 10 y, IR re-solve every 50 steps, run to the "
                 "first 10 % IR-drop failure or the horizon",
     "pg400": "pg400: 400x400 two-layer P/G grid, 798 line trees, 2000 BE steps over 10 y, IR re-solve every "

@@ -196,6 +196,12 @@ typedef struct {
                                     voids and events keep the FP32 run's values.  The re-run has
                                     no learned screen (whose replay reproduces the unscreened run).
                                     Ignored in FP64 and in trees-only mode. */
+    double guard_ttf;            /* with guard_band > 0: a failing FP32 sample is also re-run in
+                                    FP64 when its time to failure is ill-conditioned, i.e. a drop
+                                    error of guard_band x fail_frac at the bracketing re-solves
+                                    could move the interpolated TTF by more than guard_ttf
+                                    relative: guard_band fail_frac (t_k - t_k-1) >
+                                    guard_ttf TTF (drop_k - drop_k-1).  0 = off. */
 } em_run_params;
 
 /* Monte Carlo (Sec. IV-F): unit-mean lognormal multipliers with coefficient

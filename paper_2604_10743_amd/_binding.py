@@ -69,7 +69,8 @@ class RunParams(C.Structure):
                 ("screen", C.c_int32), ("max_voids_per_tree", C.c_int32), ("T_ambient", C.c_double),
                 ("stepper", C.c_int32), ("ir_precond", C.c_int32), ("ir_launch", C.c_int32),
                 ("chain_wg", C.c_int32), ("chain_occ", C.c_int32), ("joule", C.c_int32),
-                ("dt_growth", C.c_double), ("chain_m", C.c_int32), ("guard_band", C.c_double)]
+                ("dt_growth", C.c_double), ("chain_m", C.c_int32), ("guard_band", C.c_double),
+                ("guard_ttf", C.c_double)]
 
 
 class MCParams(C.Structure):
@@ -212,7 +213,8 @@ class Batch:
                       chain_occ=int(run.get("chain_occ", 0)),
                       joule=int(run.get("joule", 0)), dt_growth=float(run.get("dt_growth", 0.0)),
                       chain_m=int(run.get("chain_m", 0)),
-                      guard_band=float(run.get("guard_band", 0.0)))
+                      guard_band=float(run.get("guard_band", 0.0)),
+                      guard_ttf=float(run.get("guard_ttf", 0.0)))
         mcp = None
         if mc is not None:
             mcp = MCParams(struct_size=C.sizeof(MCParams), n_samples=int(mc["n_samples"]),

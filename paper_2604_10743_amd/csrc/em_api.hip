@@ -342,8 +342,10 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
         r->max_voids_per_tree < 0 || r->max_voids_per_tree > MAXV || !(r->T_ambient > 0) ||
         r->stepper < 0 || r->stepper > 1 || r->ir_precond < 0 || r->ir_precond > 2 ||
         r->ir_launch < 0 || r->ir_launch > 3 || r->joule < 0 || r->joule > 1 ||
-        !(r->dt_growth >= 0) || !std::isfinite(r->dt_growth) || !(r->guard_band >= 0) || !(r->guard_band < 1))
-        return fail(b, EM_ERR_ARG, "bad run parameters (max_voids_per_tree <= 4, 0 <= guard_band < 1)");
+        !(r->dt_growth >= 0) || !std::isfinite(r->dt_growth) || !(r->guard_band >= 0) || !(r->guard_band < 1) ||
+        !(r->guard_ttf >= 0) || !std::isfinite(r->guard_ttf))
+        return fail(b, EM_ERR_ARG, "bad run parameters (max_voids_per_tree <= 4, 0 <= guard_band < 1, "
+                                   "guard_ttf >= 0)");
     if (r->joule) {
         const double tv[] = {m->k_cu, m->k_ild, m->t_ild};
         if (!finite_all(tv, 3) || !(m->k_cu > 0) || !(m->k_ild > 0) || !(m->t_ild > 0))
@@ -1237,6 +1239,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     AL(d.t_prev, double, S); AL(d.d_prev, double, S); AL(d.failed, int, S); AL(d.outer_idx, int, S);
     AL(d.guard, uint8_t, S);
     d.guard_band = (b->fp32 && !b->trees_only) ? r->guard_band : 0.0;
+    d.guard_ttf = d.guard_band > 0 ? r->guard_ttf : 0.0;
     d.sid = nullptr;
     if (!b->sid_h.empty()) UP(d.sid, b->sid_h);
     if (d.guard_band > 0) {
@@ -1539,6 +1542,7 @@ static em_status redecide_fp64(em_batch *b, const std::vector<int> &pick, em_ttf
     em_run_params r2 = b->run;
     r2.prec = EM_FP64;
     r2.guard_band = 0.0;
+    r2.guard_ttf = 0.0;
     r2.chain_wg = 0; r2.chain_occ = 0; r2.chain_m = 0;
     em_mc_params mc2{};
     mc2.struct_size = sizeof(em_mc_params);

@@ -120,6 +120,7 @@ struct Dev {
     int *failed, *outer_idx;
     uint8_t *guard;                     // [S] a re-solve's drop came within guard_band of the threshold
     double guard_band;                  // relative to the failure fraction (0: off)
+    double guard_ttf;                   // relative TTF tolerance of the ill-conditioned-bracket rule
     // ---- learned screen (allocated when a model is attached) ----
     double *tstat;                      // [n_trees][4] Ltot, Lpath, nseg, njunc
     double *rdist;                      // [ns] distance from the tree root along the tree

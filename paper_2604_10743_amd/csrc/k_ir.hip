@@ -437,7 +437,11 @@ EM_KERNEL void k_ttf_update(Dev d, double fail, int k, double t)
     if (fabs(dr - fail) < d.guard_band * fail) d.guard[s] = 1;
     if (dr >= fail) {
         double tp = d.t_prev[s], dp = d.d_prev[s];
-        d.ttf[s] = tp + (fail - dp) / (dr - dp) * (t - tp);
+        const double ttf = tp + (fail - dp) / (dr - dp) * (t - tp);
+        d.ttf[s] = ttf;
+        // a drop error of guard_band x fail at either re-solve moves the
+        // interpolated time by about that over the bracket's drop increase
+        if (d.guard_ttf > 0.0 && d.guard_band * fail * (t - tp) > d.guard_ttf * ttf * (dr - dp)) d.guard[s] = 1;
         d.failed[s] = 1;
         d.sample_active[s] = 0;
     } else {

@@ -1,0 +1,111 @@
+"""The full-chip four-layer workload.
+
+Reduced size (the same generator on a 200x200 routing grid: 883 trees, 86k
+stress nodes; two hotspots of a width fitting the 0.2 mm die; critical stress
+200 MPa so that every sample nucleates): whole runs to TTF -- Joule pre-pass,
+IR re-solve every 50 steps, FP32 stepping -- against the FP64 oracle per
+sample, at the 10 % threshold (censored runs with voids) and at 8.55 %
+(crossings).
+
+Full size (the benchmark's grid: 84k trees, 8.7M stress nodes, 515k grid
+nodes), where the oracle's sparse direct IR solve does not finish: the tree
+partition bit-exact against the oracle's; Kirchhoff's current law of the GPU
+node voltages at every free node (evaluated here in FP64); and conservation
+of the stress content sum V sigma of every void-free tree after an aging
+interval, with the oracle's control volumes."""
+import numpy as np
+import pytest
+
+import ttf_check
+from paper_2604_10743_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+SMALL = dict(n=200, sink_scale=160.0, n_spots=2, sig_range=(15e-6, 40e-6))
+
+
+@pytest.fixture(scope="module")
+def em():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2604_10743_amd as P
+    return P
+
+
+@pytest.mark.parametrize("fail_frac", [0.10, 0.0855])
+def test_reduced_fullchip_vs_oracle(em, oracle_mod, fail_frac):
+    _, mat, rn, mc = synth.workload("fullchip")
+    g = synth.fullchip_grid(5001, **SMALL)
+    mat = dict(mat, sigma_crit=200e6)
+    rn = dict(rn, fail_frac=fail_frac)
+    S = 6
+    mc = dict(mc, n_samples=S)
+    print(f"reduced fullchip, fail_frac {fail_frac}", flush=True)
+    B = em.Batch(g, mat, rn, mc)
+    res = B.run_to_ttf()
+    segs = {s: B.failed_segments(s) for s in range(S)}
+    ev = B.events()
+    B.close()
+    topo = oracle_mod.topology(g, rn["intervals_per_seg"])
+    n_fail = n_nuc = 0
+    for s in range(S):
+        ref = oracle_mod.run_sample(g, mat, rn, mc, s, topo=topo)
+        ttf_check.check(res[s], ref, segs[s], rn["prec"], rn, s)
+        n_fail += ref["failed"]
+        if not res[s]["redecided"]:
+            mine = sorted((int(e[1]), int(e[3])) for e in ev if e[0] == s)
+            theirs = sorted((int(e[0]), int(e[2])) for e in ref["events"])
+            assert mine == theirs, s
+            n_nuc += len(theirs)
+    print(f"  {n_fail} of {S} failed, {n_nuc} nucleations compared", flush=True)
+    assert n_nuc >= S
+    if fail_frac < 0.1:
+        assert n_fail >= 1
+
+
+def test_fullchip_full_size_properties(em, oracle_mod):
+    g, mat, rn, _ = synth.workload("fullchip")
+    print("fullchip full size", flush=True)
+    B = em.Batch(g, mat, rn)
+    topo = oracle_mod.topology(g, rn["intervals_per_seg"])
+    t = B.topology()
+    for k in ("tree_off", "parent", "seg", "dir", "vert", "kpos", "seg_tree"):
+        assert np.array_equal(t[k], getattr(topo, k)), k
+    drop = B.ir_solve()[0]
+    u = B.voltages(0)
+    # Kirchhoff's current law at every free node, in FP64 from the GPU voltages
+    G = 1.0 / g.res_R0
+    I = (u[g.res_a] - u[g.res_b]) * G
+    net = np.zeros(g.n_nodes)
+    np.add.at(net, g.res_a, -I)
+    np.add.at(net, g.res_b, I)
+    pad = np.zeros(g.n_nodes, bool)
+    pad[g.pad_node] = True
+    # the nodal right-hand side: sinks, and the injection of every pad coupling
+    b = -g.sink_I.copy()
+    for p, q in ((g.res_a, g.res_b), (g.res_b, g.res_a)):
+        sel = ~pad[p] & pad[q]
+        np.add.at(b, p[sel], G[sel] * g.vdd)
+    resid = net[~pad] - g.sink_I[~pad]
+    kcl = np.linalg.norm(resid) / np.linalg.norm(b[~pad])
+    print(f"  drop {drop:.5f}, KCL residual {kcl:.2e}", flush=True)
+    assert kcl <= 1e-9
+    assert abs(drop - np.max((g.vdd - u) / g.vdd)) <= 1e-12
+    assert 0.05 < drop < 0.10
+    # one aging interval of every tree (screen off), then the stress content
+    # of each void-free tree against its initial (sigma_T = 0) value
+    B.stress_step(rn["ir_every"])
+    sig = B.stress(0)
+    nv = np.zeros(topo.n_trees, int)
+    for e in B.events():
+        nv[e[1]] += 1
+    B.close()
+    sim = oracle_mod.SampleSim(g, mat, dict(rn, joule=0), topo)
+    V = sim.node_arrays()["V"]
+    off = topo.tree_off
+    q = np.add.reduceat(V * sig, off[:-1])
+    scale = np.add.reduceat(V * np.abs(sig), off[:-1])
+    ok = (nv == 0) & (scale > 0)
+    rel = np.abs(q[ok]) / scale[ok]
+    print(f"  conservation over {ok.sum()} void-free trees: max rel {rel.max():.2e}", flush=True)
+    assert ok.sum() > 0.9 * topo.n_trees and rel.max() <= 1e-5

@@ -2,9 +2,10 @@
 (no arithmetic of the method here: only the comparison rules).
 
 Tolerances: FP64 stepping, and FP32 samples that the library re-ran in FP64
-because a worst drop came within the guard band of the failure threshold
-(em_run_params.guard_band), are held to 1e-6 relative on TTF and final drop;
-other FP32 samples to 1e-3.  The integers are compared exactly: failure flag,
+because a worst drop came within the guard band of the failure threshold or
+the time to failure was ill-conditioned (em_run_params.guard_band,
+guard_ttf), are held to 1e-6 relative on TTF and final drop; other FP32
+samples to 1e-3.  The integers are compared exactly: failure flag,
 re-solve index, failed-segment set.  A sample whose oracle drop lies within
 half the band of the threshold at some re-solve must have been re-run (the
 FP32 drop error, measured below 1e-4 relative, is far inside half the band),
