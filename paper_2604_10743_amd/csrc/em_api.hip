@@ -45,7 +45,9 @@ struct em_batch {
     int cg_iters_last = 0;
     int n_outer_done = 0;
     int step_counter = 0;         // steps taken through em_stress_step
-    int n_generic_trees = 0;      // trees stepped by the generic tree kernel
+    int n_generic_trees = 0;      // trees the chain kernel does not take
+    int n_br = 0;                 // of those, trees stepped by the workgroup tree kernel (stepper 0)
+    int br_max_nodes = 0;         // their largest node count
     int n_inc = 0;                // node-incidence entries of the iterated system
     // CG iterations captured once in a HIP graph and replayed in blocks
     hipStream_t cap_stream = nullptr;
@@ -747,7 +749,8 @@ em_status timed_step_dev(em_batch *b, const Dev &dd, int n_steps, int step0)
     b->nominal = false;                   // voids may grow from here on
     HIPCHK(b, hipEventRecord(b->ev_a, b->stream));
     if (dd.n_chain_wg > 0) launch_chain(dd, b->d_dev, b->fp32, n_steps, step0, b->stream);
-    if (b->n_generic_trees > 0) launch_step(dd, b->fp32, n_steps, step0, b->stream);
+    if (b->n_br > 0) launch_branch(dd, b->fp32, b->n_br, b->br_max_nodes, n_steps, step0, b->stream);
+    else if (b->n_generic_trees > 0) launch_step(dd, b->fp32, n_steps, step0, b->stream);
     LAUNCHCHK(b);
     HIPCHK(b, hipEventRecord(b->ev_b, b->stream));
     b->step_pending = true;
@@ -1169,6 +1172,56 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     d.n_chain_wg = (int)(n_lanes / cWG);
     b->n_generic_trees = 0;
     for (int t = 0; t < nt; ++t) b->n_generic_trees += tree_chain[t] ? 0 : 1;
+    // Heavy-path order of the other trees for the workgroup tree kernel
+    // (stepper 0): a node's path continues through its child with the
+    // largest subtree (lowest index on ties); paths are listed by light
+    // depth (the number of path changes from the root), head to bottom.
+    if (r->stepper == 0 && b->n_generic_trees > 0) {
+        std::vector<int> br_tree, br_nlev, br_lvl0, br_lvl, br_node(ns, 0), br_heavy(ns, -1), sz(ns, 0), ld(ns, 0);
+        for (int t = 0; t < nt; ++t) {
+            if (tree_chain[t]) continue;
+            const int i0 = P.tree_off[t], i1 = P.tree_off[t + 1];
+            for (int i = i1 - 1; i >= i0; --i) {
+                sz[i] += 1;
+                if (P.parent[i] >= 0) sz[P.parent[i]] += sz[i];
+            }
+            for (int i = i0; i < i1; ++i) {
+                int h = -1;
+                for (int k = child_off[i]; k < child_off[i + 1]; ++k) {
+                    const int c = child[k];
+                    if (h < 0 || sz[c] > sz[h]) h = c;
+                }
+                br_heavy[i] = h;
+            }
+            int nlev = 1;
+            std::vector<std::vector<int>> heads(1);
+            heads[0].push_back(i0);
+            ld[i0] = 0;
+            for (int i = i0 + 1; i < i1; ++i) {
+                const int p = P.parent[i];
+                ld[i] = ld[p] + (br_heavy[p] == i ? 0 : 1);
+                if (br_heavy[p] != i) {
+                    if (ld[i] >= nlev) { nlev = ld[i] + 1; heads.resize(nlev); }
+                    heads[ld[i]].push_back(i);
+                }
+            }
+            br_tree.push_back(t);
+            b->br_max_nodes = std::max(b->br_max_nodes, i1 - i0);
+            br_nlev.push_back(nlev);
+            br_lvl0.push_back((int)br_lvl.size());
+            int pos = i0;
+            for (int L = 0; L < nlev; ++L) {
+                br_lvl.push_back(pos - i0);
+                for (int h : heads[L])
+                    for (int i = h; i >= 0; i = br_heavy[i]) br_node[pos++] = i;
+            }
+            br_lvl.push_back(pos - i0);
+            if (pos != i1) return fail(b, EM_ERR_HIP, "heavy-path order does not cover the tree");
+        }
+        b->n_br = (int)br_tree.size();
+        UP(d.br_tree, br_tree); UP(d.br_nlev, br_nlev); UP(d.br_lvl0, br_lvl0); UP(d.br_lvl, br_lvl);
+        UP(d.br_node, br_node); UP(d.br_heavy, br_heavy);
+    }
     b->chain_wg = cWG;
     b->chain_m = cM;
     d.chain_m = cM;

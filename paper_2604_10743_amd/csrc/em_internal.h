@@ -61,6 +61,13 @@ struct Dev {
     const int *tree_perm;               // lane slot -> tree id (larger trees first)
     const uint8_t *tree_chain;          // tree stepped by the resident chain kernel
     const int *lane_inst, *lane_blk;    // chain kernel lanes: instance, block index
+    // workgroup tree stepper (trees the chain kernel does not take): heavy-path
+    // order of each such tree's nodes, level by level, at the tree's node range
+    const int *br_tree;                 // [n_br] tree id
+    const int *br_nlev, *br_lvl0;       // [n_br] levels, start in br_lvl
+    const int *br_lvl;                  // level offsets (relative to the tree's first node), nlev + 1 per tree
+    const int *br_node;                 // [ns] node at each heavy-path position
+    const int *br_heavy;                // [ns] child continuing the node's path (-1 at a leaf)
     int n_chain_wg;                     // workgroups of the chain kernel's launch
     int chain_wg;                       // its lanes per workgroup (256, 512 or the precision's maximum)
     int chain_m;                        // stress nodes per lane (CHAIN_M32/CHAIN_M64, or CHAIN_M32W)
@@ -237,6 +244,7 @@ void launch_screen_shared(const Dev &d, bool apply, hipStream_t st);
 // copy the shared screen's steady stress (column 0) to every sample's column
 void launch_psi_bcast(const Dev &d, hipStream_t st);
 void launch_step(const Dev &d, bool fp32, int n_steps, int step0, hipStream_t st);
+void launch_branch(const Dev &d, bool fp32, int n_br, int max_nodes, int n_steps, int step0, hipStream_t st);
 void launch_void_dR(const Dev &d, hipStream_t st);
 void launch_chain(const Dev &d, const Dev *d_dev, bool fp32, int n_steps, int step0, hipStream_t st);
 void launch_set_sigma_T(const Dev &d, bool fp32, hipStream_t st);

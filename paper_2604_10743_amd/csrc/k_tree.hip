@@ -714,6 +714,53 @@ __device__ void add_void(const Dev &d, int inst, int t, int s, int v, int step, 
     factor_instance<R>(d, t, s, vn, vrob, nv);
 }
 
+// The factor of one (tree, sample) after a Robin row was stamped at node v:
+// only v and its ancestors change (a node's pivot depends on its own row and
+// its children's multipliers), walked from v to the root.
+template <typename R>
+__device__ void refactor_path(const Dev &d, int v, int s, const int *vn, const double *vrob, int nv)
+{
+    const int S = d.S;
+    R *dinv = (R *)d.dinv, *lf = (R *)d.lfac;
+    const double dt = d.dt;
+    for (int i = v; i >= 0; i = d.parent[i]) {
+        double gi = 0.0;
+        if (d.parent[i] >= 0) gi = dt * d.xi_k[(size_t)d.seg[i] * S + s] * d.g0[i];
+        double dd = d.V[i] + gi;
+        for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k) {
+            int c = d.child[k];
+            double gc = dt * d.xi_k[(size_t)d.seg[c] * S + s] * d.g0[c];
+            dd += gc * (1.0 - (double)lf[(size_t)c * S + s]);
+        }
+        for (int k = 0; k < nv; ++k)
+            if (vn[k] == i) dd += dt * vrob[k];
+        dinv[(size_t)i * S + s] = (R)(1.0 / dd);
+        lf[(size_t)i * S + s] = (R)(gi / dd);
+    }
+}
+
+template <typename R>
+__device__ void add_void_path(const Dev &d, int inst, int t, int s, int v, int step, int *vn, double *vvol,
+                              double *vlen, double *vrob, int *vseg, int *vphase, int *vearly, int &nv)
+{
+    int k = nv;
+    vn[k] = v;
+    vvol[k] = 0.0;
+    vlen[k] = 0.0;
+    vrob[k] = robin_weight(d, v, s);
+    vseg[k] = host_segment(d, v, s);
+    vphase[k] = 0;
+    vearly[k] = d.vert[v] >= 0 ? d.via_up[d.vert[v]] : 0;
+    d.vstep[inst * MAXV + k] = step;
+    nv = k + 1;
+    unsigned int q = atomicAdd(d.ev_count, 1u);
+    if ((int)q < d.ev_cap) {
+        int *E = d.events + (size_t)q * EV_WORDS;
+        E[0] = s; E[1] = t; E[2] = step; E[3] = v; E[4] = vseg[k];
+    }
+    refactor_path<R>(d, v, s, vn, vrob, nv);
+}
+
 // ------------------------------------------------------------------------
 // Backward-Euler stepping, one (tree, sample) per lane, n_steps steps per
 // launch with the current densities fixed.  Each step solves the BE equation
@@ -873,6 +920,298 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
         d.vvol[q] = vvol[k]; d.vlen[q] = vlen[k]; d.vrob[q] = vrob[k];
     }
     d.n_suppressed[inst] += suppressed;
+}
+
+// ------------------------------------------------------------------------
+// Workgroup stepper for the trees the chain kernel does not take (trees with
+// junctions, and chains too long for it): one workgroup per (tree, sample),
+// the same equation, residual, factors and event logic as k_step, with the
+// two sweeps of the tree elimination run in parallel.
+//
+// The tree is cut into heavy paths (a node continues its path through the
+// child with the largest subtree, so every root-to-leaf path crosses at most
+// log2(n) path changes), grouped by light depth.  Each level lists its nodes
+// path by path, head to bottom (hp_node).  Along that list the elimination
+// b_i = r_i + sum_c l_c b_c is the reverse affine recurrence
+// x_k = c_k + lambda_k x_{k+1}, where c_k adds the light children's b (from
+// deeper levels) and lambda_k = l of the next node (0 at a path's bottom);
+// the back substitution delta_i = b_i / d_i + l_i delta_parent is the
+// forward recurrence y_k = c'_k + mu_k y_{k-1}, mu_k = l_i (0 at a path's
+// head, whose parent's delta -- one level up -- enters c'_k).  Each
+// recurrence is a workgroup scan of affine maps: every thread composes its
+// chunk serially, the threads' maps are scanned in LDS (Hillis-Steele), and
+// every thread applies the incoming value along its chunk.  Any order that
+// eliminates children before parents uses the same factors, so they are
+// those of factor_instance; only the rounding order of the solve differs.
+// After a nucleation only the void's path to the root is refactored.
+// ------------------------------------------------------------------------
+// y -> c + a y over the threads: suffix (rev) or prefix composition; returns
+// the composed map's constant of the neighbouring thread (the value entering
+// this thread's chunk): thread t+1's for a suffix scan, t-1's for a prefix.
+template <int BR_WG, bool REV>
+__device__ inline double br_scan(double a, double c, double (*sa)[BR_WG], double (*sc)[BR_WG])
+{
+    const int t = threadIdx.x;
+    int buf = 0;
+    sa[0][t] = a;
+    sc[0][t] = c;
+    __syncthreads();
+#pragma unroll
+    for (int dd = 1; dd < BR_WG; dd <<= 1) {
+        const int o = REV ? t + dd : t - dd;
+        if (REV ? (o < BR_WG) : (o >= 0)) {
+            const double a2 = sa[buf][o], c2 = sc[buf][o];
+            c = c + a * c2;
+            a = a * a2;
+        }
+        sa[buf ^ 1][t] = a;
+        sc[buf ^ 1][t] = c;
+        buf ^= 1;
+        __syncthreads();
+    }
+    const int o = REV ? t + 1 : t - 1;
+    const double in = (REV ? (o < BR_WG) : (o >= 0)) ? sc[buf][o] : 0.0;
+    __syncthreads();             // the buffers are rewritten by the next call
+    return in;
+}
+
+template <int BR_WG>
+__device__ inline double br_sum(double v, double *red)
+{
+    v = wsum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double a = 0.0;
+#pragma unroll
+    for (int k = 0; k < BR_WG / 64; ++k) a += red[k];
+    __syncthreads();
+    return a;
+}
+template <int BR_WG>
+__device__ inline double br_max(double v, double *red)
+{
+    v = wmax(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double a = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < BR_WG / 64; ++k) a = fmax(a, red[k]);
+    __syncthreads();
+    return a;
+}
+
+template <typename R, int BR_WG>
+__global__ __launch_bounds__(BR_WG) void k_branch(Dev d, int n_steps, int step0)
+{
+    __shared__ double s_a[2][BR_WG], s_c[2][BR_WG];
+    __shared__ double s_red[BR_WG / 64];
+    __shared__ int s_vn[MAXV], s_vseg[MAXV], s_vphase[MAXV], s_vearly[MAXV], s_nv;
+    __shared__ double s_vvol[MAXV], s_vlen[MAXV], s_vrob[MAXV];
+    const int S = d.S;
+    const int g = blockIdx.x / S, s = blockIdx.x - g * S;
+    const int t = d.br_tree[g];
+    const int inst = t * S + s;
+    if (!d.sample_active[s] || !d.inst_active[inst]) return;     // uniform over the workgroup
+    const int tid = threadIdx.x;
+    R *sig = (R *)d.sigma;
+    const R *dtf = (const R *)d.dtf, *dinv = (const R *)d.dinv, *lf = (const R *)d.lfac;
+    const R *sc = (const R *)d.sc;
+    double *W = d.wsp;
+    const int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
+    const int nlev = d.br_nlev[g];
+    const int *lvl = d.br_lvl + d.br_lvl0[g];            // level L: hp positions [i0 + lvl[L], i0 + lvl[L+1])
+    if (tid == 0) {
+        atomicAdd(d.node_steps, (unsigned long long)(i1 - i0) * (unsigned long long)n_steps);
+        const int nv = d.nv[inst];
+        s_nv = nv;
+        for (int k = 0; k < MAXV; ++k) {
+            const int q = inst * MAXV + k;
+            const bool u = k < nv;
+            s_vn[k] = u ? d.vnode[q] : -1;
+            s_vseg[k] = u ? d.vseg[q] : -1;
+            s_vphase[k] = u ? d.vphase[q] : 0;
+            s_vearly[k] = u ? d.vearly[q] : 0;
+            s_vvol[k] = u ? d.vvol[q] : 0.0;
+            s_vlen[k] = u ? d.vlen[q] : 0.0;
+            s_vrob[k] = u ? d.vrob[q] : 0.0;
+        }
+    }
+    __syncthreads();
+    int suppressed = 0;
+    const double Vsum = d.tree_V[t];
+    double q0 = 0.0;
+    for (int i = i0 + tid; i < i1; i += BR_WG) q0 += d.V[i] * ld_sig(d, sig, (size_t)i * S + s);
+    double Q0 = br_sum<BR_WG>(q0, s_red);
+    for (int k = 0; k < s_nv; ++k) Q0 += d.B * s_vvol[k];
+    double corr = 0.0;
+    const double dt = d.dt;
+
+    for (int st = 0; st < n_steps; ++st) {
+        const int nv = s_nv;
+        // residual dt (A sigma + f) in FP64 from exact flux differences
+        for (int i = i0 + tid; i < i1; i += BR_WG) {
+            const size_t x = (size_t)i * S + s;
+            const double si = ld_sig(d, sig, x) + corr;
+            const bool isv = in_list(i, s_vn, nv);
+            double r = isv ? 0.0 : (double)dtf[x];
+            const int p = d.parent[i];
+            if (p >= 0) r += dt * d.xi_k[(size_t)d.seg[i] * S + s] * d.g0[i] * ((ld_sig(d, sig, (size_t)p * S + s) + corr) - si);
+            for (int k = d.child_off[i]; k < d.child_off[i + 1]; ++k) {
+                const int c = d.child[k];
+                r += dt * d.xi_k[(size_t)d.seg[c] * S + s] * d.g0[c] * ((ld_sig(d, sig, (size_t)c * S + s) + corr) - si);
+            }
+            if (isv)
+                for (int k = 0; k < nv; ++k) if (s_vn[k] == i) r -= dt * s_vrob[k] * si;
+            W[x] = r;
+        }
+        __syncthreads();
+        // elimination, deepest level first: b along each path, bottom up
+        for (int L = nlev - 1; L >= 0; --L) {
+            const int lo = i0 + lvl[L], hi = i0 + lvl[L + 1];
+            const int ch = (hi - lo + BR_WG - 1) / BR_WG;
+            const int p0 = lo + tid * ch, p1 = min(p0 + ch, hi);
+            double A = 1.0, C = 0.0;
+            for (int k = p1 - 1; k >= p0; --k) {
+                const int i = d.br_node[k];
+                const size_t x = (size_t)i * S + s;
+                const int hv = d.br_heavy[i];
+                double c = W[x];
+                for (int m = d.child_off[i]; m < d.child_off[i + 1]; ++m) {
+                    const int h = d.child[m];
+                    if (h != hv) c += (double)lf[(size_t)h * S + s] * W[(size_t)h * S + s];
+                }
+                W[x] = c;
+                const double lam = hv >= 0 ? (double)lf[(size_t)hv * S + s] : 0.0;
+                C = c + lam * C;
+                A = lam * A;
+            }
+            double xin = br_scan<BR_WG, true>(A, C, s_a, s_c);
+            for (int k = p1 - 1; k >= p0; --k) {
+                const int i = d.br_node[k];
+                const size_t x = (size_t)i * S + s;
+                const int hv = d.br_heavy[i];
+                const double lam = hv >= 0 ? (double)lf[(size_t)hv * S + s] : 0.0;
+                xin = W[x] + lam * xin;
+                W[x] = xin;
+            }
+            __syncthreads();
+        }
+        // back substitution, root level first: delta along each path, top down
+        for (int L = 0; L < nlev; ++L) {
+            const int lo = i0 + lvl[L], hi = i0 + lvl[L + 1];
+            const int ch = (hi - lo + BR_WG - 1) / BR_WG;
+            const int p0 = lo + tid * ch, p1 = min(p0 + ch, hi);
+            double M = 1.0, D = 0.0;
+            for (int k = p0; k < p1; ++k) {
+                const int i = d.br_node[k];
+                const size_t x = (size_t)i * S + s;
+                const bool head = k == lo || d.br_node[k - 1] != d.parent[i];
+                double c = W[x] * (double)dinv[x];
+                double mu = 0.0;
+                if (head) {
+                    const int p = d.parent[i];
+                    if (p >= 0) c += (double)lf[x] * W[(size_t)p * S + s];
+                } else {
+                    mu = (double)lf[x];
+                }
+                W[x] = c;
+                D = c + mu * D;
+                M = mu * M;
+            }
+            double yin = br_scan<BR_WG, false>(M, D, s_a, s_c);
+            for (int k = p0; k < p1; ++k) {
+                const int i = d.br_node[k];
+                const size_t x = (size_t)i * S + s;
+                const bool head = k == lo || d.br_node[k - 1] != d.parent[i];
+                yin = W[x] + (head ? 0.0 : (double)lf[x] * yin);
+                W[x] = yin;
+            }
+            __syncthreads();
+        }
+        // new stress, stress content, nucleation candidates
+        double qs = 0.0, mx = -INFINITY;
+        for (int i = i0 + tid; i < i1; i += BR_WG) {
+            const size_t x = (size_t)i * S + s;
+            const double v = ld_sig(d, sig, x) + corr + W[x];
+            st_sig(d, sig, x, v);
+            qs += d.V[i] * v;
+            if (v >= (double)sc[x] && !in_list(i, s_vn, nv)) mx = fmax(mx, v);
+        }
+        __syncthreads();            // stores published before the void pass reads them
+        // void growth: dV = (dt/B) (Robin weight * sigma_v + f_v) (eq. 15 accounting)
+        if (tid < nv) {
+            const int k = tid;
+            const size_t x = (size_t)s_vn[k] * S + s;
+            s_vvol[k] += (dt * s_vrob[k] * ld_sig(d, sig, x) + (double)dtf[x]) / d.B;
+            const int e = s_vseg[k];
+            const double Wd = d.w[e], H = d.h[e];
+            const double l = fmin(s_vvol[k] / (Wd * H), d.len[e]);
+            s_vlen[k] = l;
+            if (s_vphase[k] == 0 && l >= Wd) {
+                s_vphase[k] = 1;
+                if (s_vearly[k]) {
+                    d.open[(size_t)s * d.n_res + e] = 1;
+                    *d.open_dirty = 1u;
+                }
+            }
+        }
+        const double Q = br_sum<BR_WG>(qs, s_red);        // its barriers also publish the void records
+        {
+            double vtot = 0.0;
+            for (int k = 0; k < nv; ++k) vtot += s_vvol[k];
+            corr = (Q0 - d.B * vtot - Q) / Vsum;
+        }
+        // nucleation: peak candidate, ties within 1e-12 to the lowest node
+        const double pk = br_max<BR_WG>(mx, s_red);
+        if (pk != -INFINITY) {
+            if (nv < d.max_voids) {
+                const double thr = pk - 1e-12 * (pk < 0 ? -pk : pk);
+                double lowest = INFINITY;
+                for (int i = i0 + tid; i < i1; i += BR_WG) {
+                    const size_t x = (size_t)i * S + s;
+                    const double val = ld_sig(d, sig, x);
+                    if (val >= (double)sc[x] && val >= thr && !in_list(i, s_vn, nv)) lowest = fmin(lowest, (double)i);
+                }
+                lowest = -br_max<BR_WG>(-lowest, s_red);
+                if (tid == 0) {
+                    int vn[MAXV], vseg[MAXV], vphase[MAXV], vearly[MAXV], nv2 = nv;
+                    double vvol[MAXV], vlen[MAXV], vrob[MAXV];
+                    for (int k = 0; k < MAXV; ++k) {
+                        vn[k] = s_vn[k]; vseg[k] = s_vseg[k]; vphase[k] = s_vphase[k]; vearly[k] = s_vearly[k];
+                        vvol[k] = s_vvol[k]; vlen[k] = s_vlen[k]; vrob[k] = s_vrob[k];
+                    }
+                    const int v = (int)lowest;
+                    add_void_path<R>(d, inst, t, s, v, step0 + st, vn, vvol, vlen, vrob, vseg, vphase, vearly, nv2);
+                    for (int k = 0; k < MAXV; ++k) {
+                        s_vn[k] = vn[k]; s_vseg[k] = vseg[k]; s_vphase[k] = vphase[k]; s_vearly[k] = vearly[k];
+                        s_vvol[k] = vvol[k]; s_vlen[k] = vlen[k]; s_vrob[k] = vrob[k];
+                    }
+                    s_nv = nv2;
+                    __threadfence_block();
+                }
+                __syncthreads();
+            } else {
+                ++suppressed;
+            }
+        }
+    }
+    if (corr != 0.0)
+        for (int i = i0 + tid; i < i1; i += BR_WG) {
+            const size_t x = (size_t)i * S + s;
+            st_sig(d, sig, x, ld_sig(d, sig, x) + corr);
+        }
+    if (tid == 0) {
+        const int nv = s_nv;
+        d.nv[inst] = nv;
+        for (int k = 0; k < nv; ++k) {
+            const int q = inst * MAXV + k;
+            d.vnode[q] = s_vn[k]; d.vseg[q] = s_vseg[k]; d.vphase[q] = s_vphase[k]; d.vearly[q] = s_vearly[k];
+            d.vvol[q] = s_vvol[k]; d.vlen[q] = s_vlen[k]; d.vrob[q] = s_vrob[k];
+        }
+        d.n_suppressed[inst] += suppressed;
+    }
 }
 
 // Resistance write-back of one (tree, sample): dR of each segment of the tree
@@ -1244,6 +1583,20 @@ void launch_step(const Dev &d, bool fp32, int n_steps, int step0, hipStream_t st
     int n = d.n_trees * d.S;
     if (fp32) k_step<float><<<nblocks(n), 256, 0, st>>>(d, n_steps, step0);
     else k_step<double><<<nblocks(n), 256, 0, st>>>(d, n_steps, step0);
+}
+// Workgroup size by the largest tree stepped: about four nodes or fewer per
+// thread in each pass (the passes walk a thread's nodes one after another).
+void launch_branch(const Dev &d, bool fp32, int n_br, int max_nodes, int n_steps, int step0, hipStream_t st)
+{
+    if (n_br <= 0) return;
+    const int nb = n_br * d.S;
+    if (max_nodes > 2048) {
+        if (fp32) k_branch<float, 1024><<<nb, 1024, 0, st>>>(d, n_steps, step0);
+        else k_branch<double, 1024><<<nb, 1024, 0, st>>>(d, n_steps, step0);
+    } else {
+        if (fp32) k_branch<float, 256><<<nb, 256, 0, st>>>(d, n_steps, step0);
+        else k_branch<double, 256><<<nb, 256, 0, st>>>(d, n_steps, step0);
+    }
 }
 void launch_void_dR(const Dev &d, hipStream_t st)
 {

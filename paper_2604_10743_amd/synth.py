@@ -198,6 +198,66 @@ def random_branched_trees(seed: int, n_trees: int, n_vertices=(2, 10),
                 seg_j=mag * sign, name=f"branched_{n_trees}_s{seed}")
 
 
+def comb_trees(seed: int, n_trees: int = 200, trunk=(20, 100), p_tooth: float = 0.7, tooth=(1, 4),
+               p_stub: float = 0.3, stub=(1, 2), L_range=(5 * UM, 20 * UM), w_range=(0.2 * UM, 1.0 * UM),
+               H=0.2 * UM, j_range=(1e9, 5e10)) -> Grid:
+    """Branched standalone trees with prescribed currents (trees-only mode):
+    a trunk of U{trunk} segments along x; at each inner trunk vertex, with
+    probability p_tooth, a tooth of U{tooth} segments along +-y; at each
+    tooth vertex, with probability p_stub, a stub of U{stub} segments along
+    x.  Up to a few hundred branches and several thousand FD nodes per tree
+    at 20 intervals per segment (the paper's largest trees have 29-218
+    branches).  Each segment has its own length, width and signed current
+    density."""
+    rng = np.random.default_rng(seed)
+    xy, ra, rb, L, W = [], [], [], [], []
+    base = 0
+    for t in range(n_trees):
+        pts = [(0.0, t * 2000 * UM)]
+
+        def add(frm, dx, dy):
+            lq = float(rng.uniform(*L_range))
+            x0, y0 = pts[frm]
+            pts.append((x0 + dx * lq, y0 + dy * lq))
+            v = len(pts) - 1
+            a, b = (frm, v) if rng.random() < 0.5 else (v, frm)
+            ra.append(base + a); rb.append(base + b)
+            L.append(lq); W.append(float(rng.uniform(*w_range)))
+            return v
+
+        T = int(rng.integers(trunk[0], trunk[1] + 1))
+        cur = 0
+        trunk_v = [0]
+        for _ in range(T):
+            cur = add(cur, 1.0, 0.0)
+            trunk_v.append(cur)
+        for v in trunk_v[1:-1]:
+            if rng.random() >= p_tooth:
+                continue
+            dy = 1.0 if rng.random() < 0.5 else -1.0
+            c = v
+            for _ in range(int(rng.integers(tooth[0], tooth[1] + 1))):
+                c = add(c, 0.0, dy)
+                if rng.random() < p_stub:
+                    s = c
+                    for _ in range(int(rng.integers(stub[0], stub[1] + 1))):
+                        s = add(s, 0.3, 0.0)
+        xy.extend(pts)
+        base += len(pts)
+    nr = len(ra)
+    res_len = np.array(L)
+    res_w = np.array(W)
+    res_h = np.full(nr, H)
+    mag = rng.uniform(j_range[0], j_range[1], nr)
+    sign = np.where(rng.random(nr) < 0.5, -1.0, 1.0)
+    return Grid(xy=np.array(xy), layer=np.ones(base, np.int32),
+                res_a=np.array(ra, np.int32), res_b=np.array(rb, np.int32),
+                res_len=res_len, res_w=res_w, res_h=res_h,
+                res_is_via=np.zeros(nr, np.uint8), res_R0=_wire_R(res_len, res_w, res_h),
+                pad_node=_empty_i32(), vdd=1.0, sink_I=np.zeros(base),
+                seg_j=mag * sign, name=f"combs_{n_trees}_s{seed}")
+
+
 # ----------------------------------------------------------------------------
 # Thermal rasters
 # ----------------------------------------------------------------------------
@@ -534,6 +594,9 @@ def workload(name: str):
     screen_mc       200x200 sparse-via grid (via every 64 nodes), 330 K + hotspots,
                     64 Monte Carlo samples: mortal trees with nucleation times
                     spread over years and failures within the horizon
+    combs           200 comb/stub trees (trunks of 20-100 segments with teeth and
+                    stubs: up to a few hundred branches per tree), prescribed
+                    currents, 378 K, FP32, screen off
     long_lines      24 x 257 two-layer grid whose 24 M1 rows are lines of 212-256
                     segments (4241-5121 stress nodes: the chain kernel's 1024-lane
                     form), short M2 straps, via every 32 nodes, 330 K + hotspots,
@@ -558,6 +621,8 @@ def workload(name: str):
                     seg_range=(48, 95), base_K=330.0)
         return (g, mat, default_run(prec=1, T_ambient=330.0),
                 dict(n_samples=1024, seed=3001, cov_kappa=0.2, cov_scrit=0.2))
+    if name == "combs":
+        return comb_trees(7001), mat, default_run(prec=1, screen=0), None
     if name == "fullchip":
         g = fullchip_grid(5001, sink_scale=FULLCHIP_SINK_SCALE)
         return (g, mat, default_run(prec=1, T_ambient=340.0, ir_every=50, joule=1),
