@@ -459,6 +459,45 @@ def cpu_baseline_stepping(name, n_steps):
     return out
 
 
+def branched_leg(args):
+    """Branched trees: 200 comb/stub trees (about 200 branches and 4000 FD
+    nodes each, trees-only with prescribed currents, 378 K), 200 BE steps of
+    every tree with nucleation and void growth, FP32; the workgroup tree
+    stepper against the per-lane tree kernel (the plain form), both timed
+    with HIP events around each launch inside the library."""
+    import torch
+    import paper_2604_10743_amd as P
+    from paper_2604_10743_amd import synth
+
+    g, mat, run, _ = synth.workload("combs")
+    out = {"metric": "stress-node-steps/s", "unit": "node-steps/s",
+           "workload": "combs: 200 comb/stub trees (trunks of 20-100 segments, teeth and stubs; 200 branches "
+                       "and 4016 FD nodes per tree on average, up to 418 and 8361), prescribed currents, 378 K, "
+                       f"FP{'32' if args.prec else '64'}"}
+    for stepper, key, n in ((0, "workgroup_tree_kernel", 200), (1, "per_lane_tree_kernel", 20)):
+        B = P.Batch(g, mat, dict(run, prec=args.prec, stepper=stepper))
+        B.stress_step(2)
+        torch.cuda.synchronize()
+        i0 = B.info()
+        t0 = time.perf_counter()
+        B.stress_step(n)
+        torch.cuda.synchronize()
+        w = time.perf_counter() - t0
+        i1 = B.info()
+        ns = i1["node_steps"] - i0["node_steps"]
+        ms = i1["step_kernel_ms"] - i0["step_kernel_ms"]
+        bn = BYTES_PER_NODE_STEP[args.prec]
+        out[key] = {"value": ns / w, "steps": n, "kernel_ms": ms, "kernel_node_steps_per_s": ns / (ms * 1e-3),
+                    "roofline": {"bound": "hbm", "achieved": ns * bn / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": ns * bn / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                 "bytes_per_node_step": bn},
+                    "n_events": i1["n_events"]}
+        B.close()
+    out["value"] = out["workgroup_tree_kernel"]["value"]
+    out["speedup_over_per_lane"] = out["workgroup_tree_kernel"]["value"] / out["per_lane_tree_kernel"]["value"]
+    return out
+
+
 def voids_leg(args):
     """pg400 with voids: the critical stress lowered to 200 MPa so that the
     mortal lines nucleate within the horizon, steady-state screen on; void
@@ -607,6 +646,8 @@ def main():
         log("bench: pg400 done")
     out["pg400_voids"] = voids_leg(args)
     log("bench: pg400 with voids done")
+    out["branched"] = branched_leg(args)
+    log("bench: branched trees done")
     if not args.no_mc:
         out["fullchip_mc"] = mc_leg(args, "fullchip", oracle=False, plain=False, n_samples=args.fc_samples)
         log("bench: fullchip mc done")

@@ -30,6 +30,11 @@ def fixed_j_grid(grid, mat, run, factor: float = 1.0):
     return synth.with_prescribed_j(grid, j * factor)
 
 
+def label_cap(run, horizon_steps: int) -> float:
+    """The label of a tree that had not nucleated within the label horizon."""
+    return float(np.log10(horizon_steps * float(run["dt"]) / T_REF))
+
+
 def label_batch(grid_fixed_j, mat, run, mc, horizon_steps: int, chunk: int = 1000):
     """Features and labels of every steady-state-mortal (tree, sample) of a
     trees-only grid: label = log10(min(t_nuc, horizon) / T_REF) with
@@ -64,12 +69,21 @@ def label_batch(grid_fixed_j, mat, run, mc, horizon_steps: int, chunk: int = 100
 
 
 def training_set(seed: int, n_grids: int, mat, run, n_samples: int, horizon_steps: int,
-                 cov=(0.2, 0.2), n: int = 200, log=None):
-    """Concatenated (X, y) over ``n_grids`` random sparse-via grids, each with
-    ``n_samples`` Monte Carlo samples of the diffusivity and critical stress."""
+                 cov=(0.2, 0.2), n: int = 200, log=None, family: str = "sparse_via"):
+    """Concatenated (X, y) over ``n_grids`` random grids of a family (the
+    200x200 sparse-via grids, the long-line grids with ``family="lines"``, or
+    the cold long-line grids with ``family="cold_lines"``),
+    each with ``n_samples`` Monte Carlo samples of the diffusivity and
+    critical stress."""
     import torch
     Xs, ys, infos = [], [], []
-    for k, (g, factor) in enumerate(synth.screen_training_grids(seed, n_grids, n=n)):
+    if family == "lines":
+        grids = synth.line_training_grids(seed, n_grids)
+    elif family == "cold_lines":
+        grids = synth.line_training_grids(seed, n_grids, cold=True)
+    else:
+        grids = synth.screen_training_grids(seed, n_grids, n=n)
+    for k, (g, factor) in enumerate(grids):
         gj = fixed_j_grid(g, mat, run, factor)
         mc = dict(n_samples=n_samples, seed=seed * 1000 + k, cov_kappa=cov[0], cov_scrit=cov[1])
         X, y, info = label_batch(gj, mat, dict(run, screen=1), mc, horizon_steps)
@@ -107,12 +121,17 @@ def train(mlp: MLP, X, y, steps: int, batch: int = 4096, lr: float = 1e-3, seed:
     return loss
 
 
-def calibrate(mlp: MLP, Xv, yv, quantile: float = 0.995) -> float:
+def calibrate(mlp: MLP, Xv, yv, quantile: float = 0.995, y_cap: float | None = None) -> float:
     """Shift the output bias so that the predicted nucleation time is at most
     the label on a ``quantile`` fraction of held-out pairs: the screen then
-    errs towards activating trees early.  Returns the shift (decades)."""
+    errs towards activating trees early.  With ``y_cap`` (the label of the
+    label runs' horizon) the pairs whose tree had not nucleated by then are
+    left out: their label is a lower bound, and a later prediction is no
+    error.  Returns the shift (decades)."""
     pred = mlp.forward(Xv).cpu().numpy().astype(np.float64)
-    err = pred - yv.cpu().numpy().astype(np.float64)
+    lab = yv.cpu().numpy().astype(np.float64)
+    keep = lab < y_cap - 1e-6 if y_cap is not None else np.ones(lab.size, bool)
+    err = pred[keep] - lab[keep]
     shift = float(np.quantile(err, quantile))
     p = mlp.params()
     p[-1] -= shift

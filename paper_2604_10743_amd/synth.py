@@ -591,6 +591,10 @@ def workload(name: str):
     mc_grid         96x96 sparse-via grid (via every 32 nodes, 16 pads), 330 K +
                     hotspots, 1024 Monte Carlo samples, FP32: worst initial drop 7 %,
                     about 40 % of the samples fail within the 10-year horizon
+    screen_cold     64 x 257 long-line grid at 310 K with two +70..100 K hotspots,
+                    256 samples, FP32: every sample fails within years through the hot
+                    lines while most steady-state-mortal lines would nucleate decades
+                    later (the learned screen's workload)
     screen_mc       200x200 sparse-via grid (via every 64 nodes), 330 K + hotspots,
                     64 Monte Carlo samples: mortal trees with nucleation times
                     spread over years and failures within the horizon
@@ -628,10 +632,13 @@ def workload(name: str):
         return (g, mat, default_run(prec=1, T_ambient=340.0, ir_every=50, joule=1),
                 dict(n_samples=256, seed=5001, cov_kappa=0.2, cov_scrit=0.2))
     if name == "long_lines":
-        g = pg_grid(6001, n=24, n_cols=257, seg_range=(212, 256), col_seg_range=(12, 23), via_every=32,
-                    pad_lattice=4, sink_scale=0.16, base_K=330.0)
+        g = line_grid_family(6001)
         return (g, mat, default_run(prec=1, T_ambient=330.0),
                 dict(n_samples=64, seed=6001, cov_kappa=0.2, cov_scrit=0.2))
+    if name == "screen_cold":
+        return (cold_line_grid(6101, sink_scale=0.107), mat,
+                default_run(prec=1, T_ambient=310.0),
+                dict(n_samples=256, seed=6101, cov_kappa=0.2, cov_scrit=0.2))
     if name == "screen_mc":
         return (sparse_via_grid(2101), mat, default_run(prec=1, T_ambient=330.0),
                 dict(n_samples=64, seed=5, cov_kappa=0.2, cov_scrit=0.2))
@@ -686,6 +693,44 @@ def screen_training_grids(seed: int, n_grids: int, n: int = 200, j_scale=(0.8, 1
         lo, hi = (0.014, 0.022) if ve == 48 else (0.008, 0.013)
         g = sparse_via_grid(int(rng.integers(1, 2 ** 31)), n=n, via_every=ve,
                             sink_scale=float(rng.uniform(lo, hi)))
+        out.append((g, float(rng.uniform(*j_scale))))
+    return out
+
+
+def line_grid_family(seed: int, sink_scale: float = 0.16, via_every: int = 32, rows: int = 24,
+                     base_K: float = 330.0, n_spots: int = 6, amp_range=(15.0, 60.0),
+                     sig_range=(30 * UM, 80 * UM)) -> Grid:
+    """The long-line P/G grid family: ``rows`` M1 rows of 212-256 segments
+    (lines of 4241-5121 FD nodes) strapped by M2 columns spanning about half
+    the rows, a via every ``via_every`` nodes, 16 pads, a thermal map of
+    base_K plus n_spots Gaussian hotspots."""
+    return pg_grid(seed, n=rows, n_cols=257, seg_range=(212, 256),
+                   col_seg_range=(rows // 2, rows - 1), via_every=via_every, pad_lattice=4,
+                   sink_scale=sink_scale, base_K=base_K, n_spots=n_spots, amp_range=amp_range,
+                   sig_range=sig_range)
+
+
+def cold_line_grid(seed: int, sink_scale: float = 0.05) -> Grid:
+    """Long-line grid of 64 rows at a cold base temperature (310 K) with two
+    strong hotspots (+70..100 K): lines through a hotspot nucleate and fail
+    within years, while many steady-state-mortal lines in the cold part would
+    need decades (the regime where a nucleation-time screen pays)."""
+    return line_grid_family(seed, sink_scale=sink_scale, rows=64, base_K=310.0, n_spots=2,
+                            amp_range=(70.0, 100.0), sig_range=(60 * UM, 120 * UM))
+
+
+def line_training_grids(seed: int, n_grids: int, j_scale=(0.8, 1.5), cold: bool = False):
+    """Random long-line grids for learned-screen labels (the 24-row family, or
+    with ``cold`` the 64-row cold grids with two hotspots; sink scale drawn so
+    that the initial drop spans about 6-9 %, new line spans, sinks and thermal
+    map per grid), each with a current factor ~ U[j_scale] for the fixed-j
+    label runs.  Returns (grid, factor) pairs."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_grids):
+        sd = int(rng.integers(1, 2 ** 31))
+        g = (cold_line_grid(sd, float(rng.uniform(0.08, 0.12))) if cold
+             else line_grid_family(sd, float(rng.uniform(0.12, 0.18))))
         out.append((g, float(rng.uniform(*j_scale))))
     return out
 
