@@ -105,23 +105,31 @@ def measured_traffic(kernel_src: str, profile_md: str):
 
 def surrogate_leg(args):
     """Learned screen: labels from the library's own transient runs on random
-    sparse-via grids, training with the BF16 MFMA kernels, then the screened
-    and the unscreened Monte Carlo run of the screen_mc workload."""
+    cold long-line grids (trees-only, currents of the t = 0 IR solve held
+    fixed, labels to 100 years), training with the BF16 MFMA kernels, a bias
+    shift calibrated on the held-out pairs whose tree nucleated within the
+    label horizon, then the screened and the unscreened Monte Carlo run to TTF
+    of the screen_cold workload (results compared sample by sample)."""
     import numpy as np
     import torch
     import paper_2604_10743_amd as P
     from paper_2604_10743_amd import surrogate, synth
 
-    g, mat, run, mc = synth.workload("screen_mc")
+    g, mat, run, mc = synth.workload("screen_cold")
     mc = dict(mc, n_samples=args.sur_samples)
-    horizon = 4 * run["n_steps"]                  # labels up to 40 years
+    lab_run = dict(run, dt=run["dt"] * 2.5)      # label steps of 2.5 dt, to 100 years
+    # the FP32 guard band re-runs the same samples in FP64 with and without
+    # the screen (and costs more than the FP32 run on this workload): off in
+    # both runs compared here
+    run = dict(run, guard_band=0.0, guard_ttf=0.0)
+    horizon = 4 * run["n_steps"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    X, y, infos = surrogate.training_set(11, args.sur_grids, mat, run, args.sur_label_samples, horizon,
-                                         log=log)
+    X, y, infos = surrogate.training_set(11, args.sur_grids, mat, lab_run, args.sur_label_samples, horizon,
+                                         log=log, family="cold_lines")
     torch.cuda.synchronize()
     t_label = time.perf_counter() - t0
-    Xv, yv, _ = surrogate.training_set(12, 2, mat, run, args.sur_label_samples, horizon)
+    Xv, yv, _ = surrogate.training_set(12, 4, mat, lab_run, 256, horizon, family="cold_lines")
     model = P.MLP(synth.init_mlp_params(1, out_bias=float(y.mean().item())))
     n = int(X.shape[0])
     batch = min(4096, max(256, n // 16))
@@ -135,22 +143,29 @@ def surrogate_leg(args):
     train_loss = model.grad(X, y)[0]
     val_loss = model.grad(Xv, yv)[0]
     ratio = 10.0 ** (model.forward(Xv).cpu().numpy() - yv.cpu().numpy())
-    # bias shift so that 99.5 % of held-out predictions are not later than the label
-    shift = surrogate.calibrate(model, Xv, yv, 0.995)
+    # bias shift: a fraction q of the held-out trees that nucleated within the
+    # label horizon are predicted no later than they nucleated
+    q = args.sur_quantile
+    shift = surrogate.calibrate(model, Xv, yv, q, y_cap=surrogate.label_cap(lab_run, horizon))
+    margin = 1.0
     log(f"bench: surrogate trained on {n} pairs: loss {train_loss:.4f}, held-out {val_loss:.4f}")
 
-    def mc_run(with_model):
+    def mc_run(with_model, reps=3):
         B = P.Batch(g, mat, run, mc)
-        if with_model:
-            B.surrogate_screen(model, 2.0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = B.run_to_ttf()
-        torch.cuda.synchronize()
-        w = time.perf_counter() - t0
-        inf = B.info()
+        best = None
+        for _ in range(reps):                   # the first run of a batch builds its solver state
+            B.reset()
+            if with_model:
+                B.surrogate_screen(model, margin)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = B.run_to_ttf()
+            torch.cuda.synchronize()
+            w = time.perf_counter() - t0
+            if best is None or w < best[2]:
+                best = (res, B.info(), w)
         B.close()
-        return res, inf, w
+        return best
 
     r0, i0, w0 = mc_run(False)
     r1, i1, w1 = mc_run(True)
@@ -175,12 +190,14 @@ def surrogate_leg(args):
     ttf = np.array([r["ttf_s"] for r in r1 if r["failed"]])
     S = mc["n_samples"]
     return {"metric": "MC samples/s to TTF, learned screen on", "value": S / w1, "unit": "samples/s",
-            "workload": f"screen_mc: 200x200 sparse-via grid (via every 64 nodes), 330 K + 6 hotspots, "
-                        f"{S} samples, 20% CoV on kappa and sigma_crit, FP32, margin 2",
+            "workload": f"screen_cold: 64 x 257 long-line grid at 310 K with two hotspots, {S} samples, "
+                        f"20% CoV on kappa and sigma_crit, FP32 (guard band off), margin {margin:g}, "
+                        f"best of 3 runs each",
             "unscreened_samples_per_s": S / w0, "speedup": w0 / w1,
             "node_steps": i1["node_steps"], "node_steps_unscreened": i0["node_steps"],
             "n_deferred": i1["n_deferred"], "n_activated": i1["n_activated"],
-            "n_late": i1["n_late"], "n_violations": i1["n_violations"], "results_identical": bool(same),
+            "n_late": i1["n_late"], "n_violations": i1["n_violations"], "n_screen_rerun": i1["n_screen_rerun"],
+            "results_identical": bool(same), "calibration_quantile": q,
             "ir_ms": i1["ir_ms"], "ir_ms_unscreened": i0["ir_ms"], "step_kernel_ms": i1["step_kernel_ms"],
             "step_kernel_ms_unscreened": i0["step_kernel_ms"],
             "n_fail": int(ttf.size), "ttf_mean_y": float(ttf.mean() / 3.15576e7) if ttf.size else None,
@@ -598,10 +615,13 @@ def main():
                     help="workload of the headline stepping measurement")
     ap.add_argument("--only-headline", action="store_true", help="run the headline measurement only")
     ap.add_argument("--no-sur", action="store_true", help="skip the learned-screen leg")
+    ap.add_argument("--only-sur", action="store_true", help="run the learned-screen leg only")
     ap.add_argument("--sur-grids", type=int, default=24, help="label grids for the learned screen")
-    ap.add_argument("--sur-label-samples", type=int, default=128)
+    ap.add_argument("--sur-label-samples", type=int, default=1024)
     ap.add_argument("--sur-steps", type=int, default=3000, help="Adam steps of the screen model")
     ap.add_argument("--sur-samples", type=int, default=256, help="MC samples of the screened run")
+    ap.add_argument("--sur-quantile", type=float, default=0.995,
+                    help="held-out quantile of the learned screen's calibration")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only copy this many bytes device-to-device (a plain copy kernel of known "
                          "size, to scale the FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -634,6 +654,10 @@ def main():
                "mc_rho_load": mc_leg(args, "mc_grid", oracle=False, plain=False, var=MC_VAR),
                "mc_joule": mc_leg(args, "mc_grid", oracle=False, plain=False, joule=True)}
         print(json.dumps(out), flush=True)
+        return
+
+    if args.only_sur:
+        print(json.dumps({"surrogate": surrogate_leg(args)}), flush=True)
         return
 
     out = stepping_leg(args, args.workload, headline=True)

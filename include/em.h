@@ -243,7 +243,9 @@ typedef struct {
     int32_t n_nucleated_trees;
     int32_t n_failed_segs; /* segments with dR > 0 or open */
     int32_t redecided;     /* 1: the FP32 run came within the guard band of the threshold and
-                              this result is that of the FP64 re-run (em_run_params.guard_band) */
+                              this result is that of the FP64 re-run (em_run_params.guard_band);
+                              2: a learned-screen violation hit this sample and this result is
+                              that of its re-run without the screen (see em_surrogate_screen) */
 } em_ttf_result;
 
 typedef struct {
@@ -254,7 +256,9 @@ typedef struct {
     int64_t n_events;      /* nucleation events recorded so far (all samples) */
     int32_t cg_iters_last; /* PCG iterations of the last IR solve */
     int32_t n_outer_done;
-    int64_t node_steps;    /* stress-node-steps taken: sum over stepped (tree, sample) of nodes x steps */
+    int64_t node_steps;    /* stress-node-steps taken: sum over stepped (tree, sample) of nodes x steps,
+                              the re-runs of the last em_run_to_ttf (guard band, learned-screen
+                              violations) included */
     int64_t step_launches; /* launches of the stepping kernel */
     double step_kernel_ms; /* summed stream time of those launches (HIP events around each) */
     int64_t cg_iters_total;/* PCG iterations over all IR solves */
@@ -265,7 +269,8 @@ typedef struct {
                               the interval they were activated for */
     int64_t n_violations;  /* learned screen: late activations whose void had also reached the
                               growth phase (a resistance change that earlier IR solves missed);
-                              with none, results equal those of the unscreened run */
+                              the samples they hit are re-run without the screen, so results
+                              equal those of the unscreened run either way */
     double surrogate_ms;   /* wall time of the learned-screen evaluations (features + model) */
     int32_t ir_sys_nodes;  /* nodes of the system the IR PCG iterates (n_nodes, or the terminals
                               of the chain condensation) */
@@ -281,6 +286,8 @@ typedef struct {
                               instances since creation or reset.  Reaching the cap is not an
                               error: the run continues with the voids it has (the paper gives no
                               cap; the cap bounds the per-instance void records) */
+    int32_t n_screen_rerun;/* samples of the last em_run_to_ttf re-run without the learned screen
+                              after a violation */
 } em_info;
 
 /* Allocator hook: device memory for the batch (e.g. a framework's caching
@@ -424,7 +431,7 @@ em_status em_restore(em_batch *b, const void *host_buf, size_t n);
 
 /* ---- learned screen ----
  * A small model, not part of EMSpice 3, that sits in front of the transient
- * stage: from 12 features of a (tree, sample) it predicts the nucleation time
+ * stage: from 16 features of a (tree, sample) it predicts the nucleation time
  * of the steady-state-mortal trees, so trees predicted to nucleate long after
  * the current aging interval need not be stepped yet.  Feature vector
  * (float32, in this order): log10 total wire length/1um; log10 longest
@@ -438,15 +445,26 @@ em_status em_restore(em_batch *b, const void *host_buf, size_t n);
  * the largest ratio); log10 max(r - 1, 1e-6); log10(Lpk^2 / (pi^2 kappa_pk)
  * / 1 s) - 8 with Lpk the difference of root distances from p to the nearest
  * node whose steady stress is at or below sigma_T (floored at 0.1 um);
- * (temperature at p - 300 K)/100.
- * Model: 12 -> 256 -> 256 -> 256 -> 1 perceptron with exact (erf) GELU,
+ * (temperature at p - 300 K)/100; then early-time scales over the edges
+ * (parent(i), i) of length l = segment length / N, diffusivity kappa_e and
+ * steady drive g = |steady stress difference| / l: log10 of the least over
+ * the edges of pi ds^2 / (4 kappa_e g^2) in seconds (the time a blocked end
+ * of a semi-infinite wire with that drive takes to reach the critical stress
+ * by the Korhonen solution sigma(0, t) = 2 g sqrt(kappa t / pi); ds = the
+ * smaller critical stress of the two ends - sigma_T, floored at 1e3 Pa;
+ * clamped to [1, 1e16] s) - 8; log10 kappa_max/1e-15; over the fast edges
+ * (kappa_e >= kappa_max / 4) the stress they could build if blocked on both
+ * sides, sum of g l / 2, over the least node critical stress - sigma_T
+ * (floored at 1e3 Pa, clamped to 10); log10(L_f^2 / (pi^2 kappa_max) / 1 s)
+ * - 8 with L_f their total length (floored at 0.1 um).
+ * Model: 16 -> 256 -> 256 -> 256 -> 1 perceptron with exact (erf) GELU,
  * output y = log10(t_nuc / 1e8 s).  Hidden-layer products run on bfloat16
  * matrix cores with float32 accumulation (operands rounded to nearest even);
  * bias, GELU, output layer, loss and Adam are float32, with a float32 master
  * copy of every parameter.  Parameter vector (float32, em_mlp_num_params()):
- * W1 [256][12], b1 [256], W2 [256][256], b2, W3 [256][256], b3, w4 [256], b4
+ * W1 [256][16], b1 [256], W2 [256][256], b2, W3 [256][256], b3, w4 [256], b4
  * ([out][in] row-major).  X, t, y arguments of the em_mlp_* calls are DEVICE
- * pointers (X [n][12] row-major); calls on one model must not overlap. */
+ * pointers (X [n][16] row-major); calls on one model must not overlap. */
 em_status em_mlp_create(void *hip_stream, em_mlp **out);   /* parameters start at zero */
 em_status em_mlp_destroy(em_mlp *m);
 const char *em_mlp_last_error(const em_mlp *m);
@@ -470,7 +488,7 @@ em_status em_mlp_train_step(em_mlp *m, const float *X, const float *t, int32_t n
  * em_mlp_forward_noalloc computes y [n] = model(X) exactly as em_mlp_forward
  * does (same kernels, same result bit for bit), but keeps the activations in a
  * fixed device array of the library instead of the model's buffers, which
- * em_mlp_forward grows with hipMalloc when n grows.  X [n][12] and y [n] are
+ * em_mlp_forward grows with hipMalloc when n grows.  X [n][16] and y [n] are
  * caller-owned DEVICE pointers; 1 <= n <= em_mlp_noalloc_max_rows() (4096),
  * else EM_ERR_ARG.  Asynchronous on the model's stream (no synchronisation);
  * no device or pinned memory is allocated or freed.  The array (17 MB) exists
@@ -483,7 +501,7 @@ int32_t em_mlp_noalloc_max_rows(void);
 em_status em_mlp_forward_noalloc(em_mlp *m, const float *X, int32_t n, float *y);
 
 /* Features of every (tree, sample) for the current densities, written to X
- * (DEVICE, [n_trees * n_samples][12], row tree * n_samples + sample).
+ * (DEVICE, [n_trees * n_samples][16], row tree * n_samples + sample).
  * Refreshes the screen verdict (em_get_screen) without changing which trees
  * are stepped.  EM_ERR_STATE before any currents exist. */
 em_status em_features(em_batch *b, float *X);
@@ -491,14 +509,25 @@ em_status em_features(em_batch *b, float *X);
  * the model must outlive its use by the batch).  em_run_to_ttf then, at
  * t = 0, defers every steady-state-mortal tree whose predicted nucleation
  * time exceeds m x (end of the first aging interval); before the aging
- * interval ending at t_{k+1} it activates every deferred tree with prediction
- * <= m x t_{k+1} and catches it up from t = 0 by replaying the stored current
- * densities of the earlier intervals.  Before each activation check the
- * deferred trees are re-evaluated with the current densities (a prediction
- * can only move earlier).  The replay reproduces the unscreened run exactly
- * unless an activated tree's void had already reached the growth phase
- * before its activation (counted in em_info.n_violations; nucleation alone
- * before activation is counted in n_late).  Called on a batch that has currents
+ * intervals k = 1, 4, 16, 64, ... (interval k ends at t_{k+1}) it activates
+ * every deferred tree with prediction <= m x t_{4k}, the end of the interval
+ * before the next check, and catches it up from t = 0 by replaying the stored
+ * current densities of the earlier intervals and of interval k on a stream
+ * of its own, beside the main launch of interval k (the replays of a run add
+ * up to a third of its intervals at most).  Every tree is thus active before
+ * the first interval k with prediction <= m x t_{k+1}.  Before each
+ * activation check a deferred tree is re-evaluated with the current
+ * densities once one of its segment currents has moved by more than 1 % of
+ * its largest since its last prediction (a prediction can only move
+ * earlier).  The replay reproduces the unscreened run exactly unless an
+ * activated tree's void had already reached the growth phase before its
+ * activation (a violation, counted in em_info.n_violations; nucleation alone
+ * before activation is counted in n_late and is harmless): em_run_to_ttf
+ * then re-runs the samples a violation hit without the screen, in a batch
+ * over their Monte Carlo sample indices with the same precision and chain
+ * kernel layout, and takes their results, resistance changes and opens from
+ * it (em_ttf_result.redecided = 2, em_info.n_screen_rerun), so its results
+ * equal those of the unscreened run.  Called on a batch that has currents
  * and has not been stepped since creation or reset, it also evaluates the
  * model at once, so that em_stress_step skips the deferred trees;
  * *n_deferred (may be NULL) is then their number, else 0. */

@@ -9,14 +9,17 @@ The learned screen has no counterpart in EMSpice 3; it is this library's own
 addition in front of the transient stage.  What it computes is defined here in
 plain numpy:
 
-* Features (12 per (tree, sample)) from quantities the paper defines: segment
+* Features (16 per (tree, sample)) from quantities the paper defines: segment
   lengths and current densities (Sec. III-C), the Arrhenius diffusivity
   kappa = D0 exp(-Ea/kT) B Omega/(kT) (Sec. III-D), the zero-flux steady
   stress of the immortality screen (Sec. III-B) against the critical stress,
   and the diffusion time L^2/(pi^2 kappa) of the slowest Korhonen mode over
   the span between the stress peak and the neutral point of the steady
-  profile.
-* A multilayer perceptron 12 -> 256 -> 256 -> 256 -> 1 with GELU activations
+  profile; early-time scales from the Korhonen solution of a semi-infinite
+  wire with a blocked end, sigma(0, t) = 2 g sqrt(kappa t / pi) for a drive
+  (steady stress gradient) g, and the fast part of the tree (edges within a
+  factor 4 of the largest diffusivity).
+* A multilayer perceptron 16 -> 256 -> 256 -> 256 -> 1 with GELU activations
   in the exact erf form (Hendrycks & Gimpel, 2016), predicting
   log10(t_nuc / 1e8 s).  Precision contract of the device path, mirrored
   here: the operands of the three hidden-layer products (forward and
@@ -28,9 +31,11 @@ plain numpy:
 * Mean-squared-error loss and Adam with bias-corrected moments (Kingma & Ba,
   ICLR 2015, Algorithm 1).
 * Lazy activation: a steady-state-mortal tree whose predicted nucleation time
-  exceeds margin x (end of the first aging interval) is deferred; before the
-  aging interval ending at t_{k+1} it is activated once t_hat <= margin x
-  t_{k+1} and caught up by replaying the stored per-interval current
+  exceeds margin x (end of the first aging interval) is deferred; it must be
+  active before the aging interval ending at the first t_{k+1} with
+  t_hat <= margin x t_{k+1}.  Activation is checked before the intervals
+  k = 1, 4, 16, 64, ... only, each check activating what is due by t_{4k}, and
+  an activated tree is caught up by replaying the stored per-interval current
   densities from t = 0.
 """
 from __future__ import annotations
@@ -39,7 +44,7 @@ import math
 
 import numpy as np
 
-NF, HID = 12, 256
+NF, HID = 16, 256
 T_REF = 1e8            # s; the network predicts log10(t_nuc / T_REF)
 E_CHG = 1.602176634e-19
 K_B = 1.380649e-23
@@ -188,7 +193,7 @@ FEATURE_NAMES = ["log10 Ltot/um", "log10 Lpath/um", "nseg/8", "njunc/4", "log10 
 
 
 def features(topo, grid, mat, jseg, xi_k, T, sig_ss, sc):
-    """[n_trees][12] features of one sample.
+    """[n_trees][16] features of one sample.
 
     topo: the tree partition; jseg [n_res] current density; xi_k [n_res]
     diffusivity multipliers; T, sig_ss, sc [n_stress]: node temperature, the
@@ -201,6 +206,17 @@ def features(topo, grid, mat, jseg, xi_k, T, sig_ss, sc):
     0.1 um); on a straight line this is the distance to the neutral point of
     the steady profile.  kappa_pk is the mean diffusivity of the edges at p,
     tau_pk = Lpk^2 / (pi^2 kappa_pk).
+
+    Early-time scales over the edges e = (parent(i), i) of length l_e =
+    segment length / N and diffusivity kappa_e: the steady drive g_e =
+    |sig_ss(i) - sig_ss(parent)| / l_e; with ds_e = max(min(sc) of the two
+    ends - sigma_T, 1e3 Pa) the time pi ds_e^2 / (4 kappa_e g_e^2) at which a
+    blocked end of a semi-infinite wire with that drive reaches sc (edges
+    with g_e > 0; the least one, clamped to [1, 1e16] s); kappa_max; the fast
+    edges (kappa_e >= kappa_max / 4): their length L_f (floored at 0.1 um)
+    and the stress they could build if blocked on both sides, sum of
+    g_e l_e / 2, over ds_min = max(min over nodes of sc - sigma_T, 1e3 Pa)
+    (clamped to 10); and L_f^2 / (pi^2 kappa_max).
     """
     N = topo.N
     out = np.zeros((topo.n_trees, NF))
@@ -255,11 +271,34 @@ def features(topo, grid, mat, jseg, xi_k, T, sig_ss, sc):
             ke.append(edge_kappa(pk))
         kpk = float(np.mean(ke))
         tau = lpk ** 2 / (math.pi ** 2 * kpk)
+        # early-time scales
+        ds_min = max(min(sc[i] for i in range(i0, i1)) - mat["sigma_T"], 1e3)
+        edges = [(i, int(topo.parent[i])) for i in range(i0, i1) if topo.parent[i] >= 0]
+        k_e = {i: edge_kappa(i) for i, _ in edges}
+        l_e = {i: grid.res_len[int(topo.seg[i])] / N for i, _ in edges}
+        kmax = max(k_e.values()) if edges else 0.0
+        t_blk = math.inf
+        Lf, Sf = 0.0, 0.0
+        for i, p in edges:
+            dpsi = abs(sig_ss[i] - sig_ss[p])
+            g = dpsi / l_e[i]
+            if math.isfinite(g) and g > 0:
+                ds = max(min(sc[i], sc[p]) - mat["sigma_T"], 1e3)
+                t_blk = min(t_blk, math.pi * ds ** 2 / (4 * k_e[i] * g ** 2))
+            if k_e[i] >= 0.25 * kmax:
+                Lf += l_e[i]
+                if math.isfinite(dpsi):
+                    Sf += 0.5 * dpsi
+        t_blk = min(max(t_blk, 1.0), 1e16)
+        kmax = max(kmax, 1e-30)
+        Lf = max(Lf, 1e-7)
         out[t] = [math.log10(Ltot / 1e-6), math.log10(Lpath / 1e-6), len(segs) / 8.0, njunc / 4.0,
                   math.log10(max(js.max(), 1e3) / 1e9), math.log10(max((lens * js).sum() / Ltot, 1e3) / 1e9),
                   math.log10(kmean / 1e-15), math.log10(kpk / 1e-15), rr,
                   math.log10(max(rr - 1.0, 1e-6)), math.log10(tau) - 8.0,
-                  (float(T[pk]) - 300.0) / 100.0]
+                  (float(T[pk]) - 300.0) / 100.0,
+                  math.log10(t_blk) - 8.0, math.log10(kmax / 1e-15), min(Sf / ds_min, 10.0),
+                  math.log10(Lf ** 2 / (math.pi ** 2 * kmax)) - 8.0]
     return out
 
 
@@ -276,3 +315,19 @@ def activation_interval(that, margin, K, dt):
     smallest k >= 0 with that <= margin t_{k+1}."""
     T1 = margin * K * dt
     return np.maximum(0, np.ceil(np.asarray(that) / T1) - 1).astype(np.int64)
+
+
+def activation_check(a):
+    """Interval before which a deferred tree whose activation interval is
+    a >= 1 is activated when the checks run only before the intervals
+    c = 1, 4, 16, 64, ... and each activates what is due by t_{4c}, the end of
+    the interval before the next check: the largest power of four <= a (the
+    check c with c <= a < 4c)."""
+    a = np.asarray(a, np.int64)
+    out = np.zeros_like(a)
+    for idx, v in np.ndenumerate(a):
+        c = 1
+        while 4 * c <= v:
+            c *= 4
+        out[idx] = c
+    return out

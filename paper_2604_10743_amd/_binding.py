@@ -36,6 +36,7 @@ API = ["em_batch_create", "em_batch_destroy", "em_get_info", "em_last_error", "e
 # Thermal block used when a material dict leaves it out (only read with joule=1):
 # k_cu, k_ILD in W/(m K), t_ILD in m.
 THERMAL_DEFAULTS = {"k_cu": 400.0, "k_ild": 1.4, "t_ild": 0.2e-6}
+N_FEAT = 16        # learned-screen features per (tree, sample)
 
 
 class EmError(RuntimeError):
@@ -96,7 +97,8 @@ class Info(C.Structure):
                 ("n_violations", C.c_int64),
                 ("surrogate_ms", C.c_double), ("ir_sys_nodes", C.c_int32), ("ir_sys_edges", C.c_int32),
                 ("cg_sample_iters", C.c_int64), ("chain_m", C.c_int32), ("chain_wg", C.c_int32),
-                ("n_chain_wg", C.c_int32), ("n_redecided", C.c_int32), ("n_void_capped", C.c_int64)]
+                ("n_chain_wg", C.c_int32), ("n_redecided", C.c_int32), ("n_void_capped", C.c_int64),
+                ("n_screen_rerun", C.c_int32)]
 
 
 class TuneInfo(C.Structure):
@@ -408,8 +410,8 @@ class Batch:
 
     # -- learned screen ------------------------------------------------------
     def features(self):
-        """[n_trees * n_samples][12] float32 device tensor (row tree * S + sample)."""
-        X = self._torch.empty((self.n_trees * self.S, 12), dtype=self._torch.float32, device="cuda")
+        """[n_trees * n_samples][N_FEAT] float32 device tensor (row tree * S + sample)."""
+        X = self._torch.empty((self.n_trees * self.S, N_FEAT), dtype=self._torch.float32, device="cuda")
         self._chk(lib().em_features(self._h, C.c_void_p(X.data_ptr())))
         return X
 
@@ -491,12 +493,12 @@ class MLP:
         return y
 
     def forward_noalloc(self, X, y):
-        """y[:n] = model(X) through the allocation-free entry point: X [n][12]
+        """y[:n] = model(X) through the allocation-free entry point: X [n][N_FEAT]
         and y [>= n] are caller-owned float32 device tensors; the call
         allocates nothing and does not synchronise the model's stream."""
         n = int(X.shape[0])
         assert X.is_cuda and y.is_cuda and X.dtype == y.dtype == self._torch.float32 and y.numel() >= n
-        assert X.is_contiguous() and y.is_contiguous() and tuple(X.shape[1:]) == (12,)
+        assert X.is_contiguous() and y.is_contiguous() and tuple(X.shape[1:]) == (N_FEAT,)
         self._chk(lib().em_mlp_forward_noalloc(self._h, C.c_void_p(X.data_ptr()), C.c_int32(n),
                                                C.c_void_p(y.data_ptr())))
 
@@ -513,7 +515,7 @@ class MLP:
         return loss.value, g
 
     def train_step(self, X, t, lr: float, want_loss: bool = False):
-        """One Adam step on device tensors X [n][12], t [n]."""
+        """One Adam step on device tensors X [n][N_FEAT], t [n]."""
         loss = C.c_float()
         self._chk(lib().em_mlp_train_step(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(t.data_ptr()),
                                           C.c_int32(X.shape[0]), C.c_float(lr),

@@ -57,6 +57,11 @@ struct em_batch {
     // each IR solve; folded in at the next synchronisation
     hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr, ev_d = nullptr;
     bool step_pending = false, ir_pending = false;
+    // catch-up replays of the learned screen run on a stream of their own,
+    // beside the main stepping launch of the same interval
+    hipStream_t rp_stream = nullptr;
+    hipEvent_t ev_j = nullptr, ev_ra = nullptr, ev_rb = nullptr;
+    bool replay_pending = false;
     double step_ms = 0.0, ir_ms = 0.0;
     long long step_launches = 0, cg_iters_total = 0;
     long long cg_sample_iters = 0;      // PCG iterations summed over samples (each sample's own count)
@@ -110,6 +115,8 @@ struct em_batch {
     // samples that came within the band of the failure threshold
     struct GridCopy *gcopy = nullptr;
     int n_redecided = 0;
+    int n_screen_rerun = 0;
+    long long rerun_node_steps = 0;     // node-steps of the re-runs of the last em_run_to_ttf
 };
 
 // Deep host copy of a netlist descriptor (the FP64 re-run builds a batch from it).
@@ -579,6 +586,8 @@ void fold_timers(em_batch *b)
     float ms = 0.f;
     if (b->step_pending && hipEventElapsedTime(&ms, b->ev_a, b->ev_b) == hipSuccess) b->step_ms += ms;
     b->step_pending = false;
+    if (b->replay_pending && hipEventElapsedTime(&ms, b->ev_ra, b->ev_rb) == hipSuccess) b->step_ms += ms;
+    b->replay_pending = false;
     if (b->ir_pending && hipEventElapsedTime(&ms, b->ev_c, b->ev_d) == hipSuccess) b->ir_ms += ms;
     b->ir_pending = false;
 }
@@ -743,7 +752,7 @@ em_status update_forcing(em_batch *b)
 
 // Step the instances that `dd.inst_active` marks (the batch's own set, or the
 // catch-up set of the learned screen with dd a modified copy of the batch's Dev).
-em_status timed_step_dev(em_batch *b, const Dev &dd, int n_steps, int step0)
+em_status timed_step_dev(em_batch *b, const Dev &dd, int n_steps, int step0, bool void_dr = true)
 {
     fold_timers(b);
     b->nominal = false;                   // voids may grow from here on
@@ -755,12 +764,14 @@ em_status timed_step_dev(em_batch *b, const Dev &dd, int n_steps, int step0)
     HIPCHK(b, hipEventRecord(b->ev_b, b->stream));
     b->step_pending = true;
     b->step_launches++;
-    launch_void_dR(b->d, b->stream);
-    LAUNCHCHK(b);
+    if (void_dr) {
+        launch_void_dR(b->d, b->stream);
+        LAUNCHCHK(b);
+    }
     return EM_OK;
 }
 
-em_status timed_step(em_batch *b, int n_steps, int step0)
+em_status timed_step(em_batch *b, int n_steps, int step0, bool void_dr = true)
 {
     em_status rc = ensure_active(b);
     if (rc != EM_OK) return rc;
@@ -769,7 +780,7 @@ em_status timed_step(em_batch *b, int n_steps, int step0)
         if (rc != EM_OK) return rc;
         b->forcing_stale = false;
     }
-    return timed_step_dev(b, b->d, n_steps, step0);
+    return timed_step_dev(b, b->d, n_steps, step0, void_dr);
 }
 
 em_status timed_ir(em_batch *b)
@@ -803,12 +814,19 @@ em_status sur_buffers(em_batch *b)
     d.deferred = (uint8_t *)dalloc(b, IS);
     d.catchup = (uint8_t *)dalloc(b, IS);
     d.def_list = (int *)dalloc(b, 4 * IS);
+    d.def_k = (int *)dalloc(b, 4 * IS);
+    d.sur_viol = (uint8_t *)dalloc(b, (size_t)d.S);
     d.act_list = (int *)dalloc(b, 4 * IS);
     d.sur_cnt = (unsigned int *)dalloc(b, 32);
     b->sur_y = (float *)dalloc(b, 4 * IS);
-    if (!d.tstat || !d.rdist || !d.feat || !d.yhat || !d.deferred || !d.catchup || !d.def_list ||
+    if (!d.tstat || !d.rdist || !d.feat || !d.yhat || !d.deferred || !d.catchup || !d.def_list || !d.def_k ||
+        !d.sur_viol ||
         !d.act_list || !d.sur_cnt || !b->sur_y)
         return fail(b, EM_ERR_OOM, "learned-screen buffers");
+    if (!b->rp_stream) HIPCHK(b, hipStreamCreateWithFlags(&b->rp_stream, hipStreamNonBlocking));
+    if (!b->ev_j) HIPCHK(b, hipEventCreate(&b->ev_j));
+    if (!b->ev_ra) HIPCHK(b, hipEventCreate(&b->ev_ra));
+    if (!b->ev_rb) HIPCHK(b, hipEventCreate(&b->ev_rb));
     launch_tree_static(d, b->stream);
     LAUNCHCHK(b);
     HIPCHK(b, hipMemcpyAsync(b->d_dev, &d, sizeof(Dev), hipMemcpyHostToDevice, b->stream));
@@ -817,27 +835,23 @@ em_status sur_buffers(em_batch *b)
 }
 
 // Features of every (tree, sample) with the current densities: the screen's
-// steady stress is refreshed first (without changing the active set).
-// Every sample's column of the steady stress (after a shared screen only
-// column 0 was written).
-void materialize_psi(em_batch *b)
-{
-    if (!b->psi_shared) return;
-    launch_psi_bcast(b->d, b->stream);
-    b->psi_shared = false;
-}
-
+// steady stress is refreshed first (without changing the active set); after a
+// shared screen the features read its column 0.
 em_status features_impl(em_batch *b, float *X, bool screen_current = false, bool candidates_only = false)
 {
     if (!screen_current) {
         em_status rc = run_screen(b, false);
         if (rc != EM_OK) return rc;
     }
-    materialize_psi(b);
-    launch_features(b->d, X, candidates_only, b->stream);
+    launch_features(b->d, X, candidates_only, b->psi_shared, b->stream);
     LAUNCHCHK(b);
     return EM_OK;
 }
+
+// A deferred instance is re-evaluated once one of its segment currents has
+// moved by more than this fraction of its largest since its last prediction
+// (a 1 % change moves a nucleation time that scales as 1/j^2 by about 2 %).
+constexpr double REEVAL_TOL = 0.01;
 
 // Evaluate the attached model and defer the mortal active instances predicted
 // to nucleate after thr; returns how many were deferred (synchronises).
@@ -870,31 +884,62 @@ em_status sur_evaluate(em_batch *b, double thr, int64_t *n_def, bool screen_curr
         for (size_t i = 0; i < IS; ++i) if (df[i]) lst.push_back((int)i);
         b->n_def_list = (int)lst.size();
         HIPCHK(b, hipMemcpy(d.def_list, lst.data(), 4 * lst.size(), hipMemcpyHostToDevice));
+        HIPCHK(b, hipMemset(d.def_k, 0xff, 4 * lst.size()));      // rows still by instance: evaluate all
     }
     b->sur_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return EM_OK;
 }
 
-// Replay the stored aging intervals 0..k-1 for the instances just activated
-// (catch-up from t = 0), then return them to the active set.
-em_status sur_catch_up(em_batch *b, int k, int n_new)
+// Catch-up of the instances just activated before interval k: their lanes
+// join the lane table, the main set's forcing is brought up to date, then the
+// stored aging intervals 0..k (interval k: nst steps with the present
+// densities) are replayed for them on the replay stream, beside the main
+// launch of interval k (which steps only the already active instances; the
+// two sets share no node, segment or void).  sur_catch_up_end joins the two.
+em_status sur_catch_up_begin(em_batch *b, int k, int n_new, int nst)
 {
     Dev &d = b->d;
     const int K = b->run.ir_every;
     b->act_dirty = true;                  // the activated (catch-up) instances join the lane table
-    em_status rc0 = ensure_active(b);
-    if (rc0 != EM_OK) return rc0;
+    em_status rc = ensure_active(b);
+    if (rc != EM_OK) return rc;
+    if (b->forcing_stale) {
+        rc = update_forcing(b);
+        if (rc != EM_OK) return rc;
+        b->forcing_stale = false;
+    }
+    fold_timers(b);
+    b->nominal = false;
+    HIPCHK(b, hipEventRecord(b->ev_j, b->stream));
+    HIPCHK(b, hipStreamWaitEvent(b->rp_stream, b->ev_j, 0));
     Dev dr = d;
     dr.inst_active = d.catchup;
-    for (int i = 0; i < k; ++i) {
+    HIPCHK(b, hipEventRecord(b->ev_ra, b->rp_stream));
+    for (int i = 0; i <= k; ++i) {
         dr.jseg = b->jhist + (size_t)i * d.S * d.n_res;
-        launch_update_f_list(dr, b->fp32, d.act_list, n_new, b->stream);
+        launch_update_f_list(dr, b->fp32, d.act_list, n_new, b->rp_stream);
         LAUNCHCHK(b);
-        em_status rc = timed_step_dev(b, dr, K, i * K);
-        if (rc != EM_OK) return rc;
+        const int n = i < k ? K : nst;
+        if (dr.n_chain_wg > 0) launch_chain(dr, b->d_dev, b->fp32, n, i * K, b->rp_stream);
+        if (b->n_br > 0) launch_branch(dr, b->fp32, b->n_br, b->br_max_nodes, n, i * K, b->rp_stream);
+        else if (b->n_generic_trees > 0) launch_step(dr, b->fp32, n, i * K, b->rp_stream);
+        LAUNCHCHK(b);
+        b->step_launches++;
     }
-    launch_update_f_list(d, b->fp32, d.act_list, n_new, b->stream);
-    launch_catchup_done(d, k * K, b->stream);
+    HIPCHK(b, hipEventRecord(b->ev_rb, b->rp_stream));
+    return EM_OK;
+}
+
+// After the main launch of interval k: wait for the replays, return the
+// caught-up instances to the active set (counting late activations) and
+// update the resistances from every void.
+em_status sur_catch_up_end(em_batch *b, int k)
+{
+    Dev &d = b->d;
+    HIPCHK(b, hipStreamWaitEvent(b->stream, b->ev_rb, 0));
+    b->replay_pending = true;
+    launch_catchup_done(d, k * b->run.ir_every, b->stream);
+    launch_void_dR(d, b->stream);
     LAUNCHCHK(b);
     return EM_OK;
 }
@@ -1295,7 +1340,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     d.guard_ttf = d.guard_band > 0 ? r->guard_ttf : 0.0;
     d.sid = nullptr;
     if (!b->sid_h.empty()) UP(d.sid, b->sid_h);
-    if (d.guard_band > 0) {
+    if (!b->trees_only) {            // for the guard-band and learned-screen re-runs
         b->gcopy = new (std::nothrow) GridCopy(*g);
         if (!b->gcopy) return fail(b, EM_ERR_OOM, "host copy of the netlist");
     }
@@ -1450,8 +1495,9 @@ em_status em_batch_destroy(em_batch *b)
         else (void)hipFree(p);
     }
     if (b->h_flags) (void)hipHostFree(b->h_flags);
-    for (hipEvent_t e : {b->ev_a, b->ev_b, b->ev_c, b->ev_d})
+    for (hipEvent_t e : {b->ev_a, b->ev_b, b->ev_c, b->ev_d, b->ev_j, b->ev_ra, b->ev_rb})
         if (e) (void)hipEventDestroy(e);
+    if (b->rp_stream) (void)hipStreamDestroy(b->rp_stream);
     if (b->cg_exec) (void)hipGraphExecDestroy(b->cg_exec);
     if (b->cg_graph) (void)hipGraphDestroy(b->cg_graph);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
@@ -1478,7 +1524,7 @@ em_status em_get_info(em_batch *b, em_info *info)
     HIPCHK(b, hipMemcpyAsync(&nsd, b->d.node_steps, 8, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(b, hipStreamSynchronize(b->stream));
     fold_timers(b);
-    info->node_steps = (int64_t)nsd;
+    info->node_steps = (int64_t)nsd + b->rerun_node_steps;
     info->step_launches = b->step_launches;
     info->step_kernel_ms = b->step_ms;
     info->cg_iters_total = b->cg_iters_total;
@@ -1500,6 +1546,7 @@ em_status em_get_info(em_batch *b, em_info *info)
     info->n_violations = sc[3];
     info->surrogate_ms = b->sur_ms;
     info->n_redecided = b->n_redecided;
+    info->n_screen_rerun = b->n_screen_rerun;
     {
         const size_t IS = (size_t)b->n_trees * b->S;
         std::vector<int> sup(IS);
@@ -1588,15 +1635,23 @@ static em_status set_step_size(em_batch *b, double dt)
 // band of the failure threshold are run again from t = 0 in FP64 (a batch over
 // their Monte Carlo sample indices built from the same inputs); their results,
 // resistance changes and opens replace the FP32 run's.
-static em_status redecide_fp64(em_batch *b, const std::vector<int> &pick, em_ttf_result *out)
+//
+// The same re-run in the batch's own precision and chain-kernel layout, without
+// the learned screen (fp64 false), replaces the results of the samples that a
+// learned-screen violation hit; its own guard band applies as in the batch.
+static em_status rerun_samples(em_batch *b, const std::vector<int> &pick, em_ttf_result *out, bool fp64)
 {
     std::vector<int> ids(pick.size());
     for (size_t i = 0; i < pick.size(); ++i) ids[i] = b->sid_h.empty() ? pick[i] : b->sid_h[pick[i]];
     em_run_params r2 = b->run;
-    r2.prec = EM_FP64;
-    r2.guard_band = 0.0;
-    r2.guard_ttf = 0.0;
-    r2.chain_wg = 0; r2.chain_occ = 0; r2.chain_m = 0;
+    if (fp64) {
+        r2.prec = EM_FP64;
+        r2.guard_band = 0.0;
+        r2.guard_ttf = 0.0;
+        r2.chain_wg = 0; r2.chain_occ = 0; r2.chain_m = 0;
+    } else {
+        r2.chain_wg = b->chain_wg; r2.chain_occ = b->chain_occ; r2.chain_m = b->chain_m;
+    }
     em_mc_params mc2{};
     mc2.struct_size = sizeof(em_mc_params);
     mc2.n_samples = (int)pick.size();
@@ -1613,7 +1668,7 @@ static em_status redecide_fp64(em_batch *b, const std::vector<int> &pick, em_ttf
         const size_t nr = b->n_res;
         for (size_t i = 0; i < pick.size() && rc == EM_OK; ++i) {
             out[pick[i]] = res[i];
-            out[pick[i]].redecided = 1;
+            out[pick[i]].redecided = fp64 ? 1 : 2;
             if (hipMemcpyAsync(b->d.dR + pick[i] * nr, sub->d.dR + i * nr, 8 * nr, hipMemcpyDeviceToDevice,
                                b->stream) != hipSuccess ||
                 hipMemcpyAsync(b->d.open + pick[i] * nr, sub->d.open + i * nr, nr, hipMemcpyDeviceToDevice,
@@ -1623,9 +1678,21 @@ static em_status redecide_fp64(em_batch *b, const std::vector<int> &pick, em_ttf
         if (rc == EM_OK && hipStreamSynchronize(b->stream) != hipSuccess) rc = EM_ERR_HIP;
     }
     const std::string msg = sub ? sub->err : std::string("batch creation");
+    const int sub_redecided = sub ? sub->n_redecided : 0;
+    if (rc == EM_OK) {
+        em_info si{};
+        if ((rc = em_get_info(sub, &si)) == EM_OK) b->rerun_node_steps += si.node_steps;
+    }
     em_batch_destroy(sub);
-    if (rc != EM_OK) return fail(b, rc, "FP64 re-run of the guard-band samples failed: " + msg);
-    b->n_redecided = (int)pick.size();
+    if (rc != EM_OK)
+        return fail(b, rc, std::string(fp64 ? "FP64 re-run of the guard-band samples" :
+                                              "re-run of the samples hit by a learned-screen violation") +
+                               " failed: " + msg);
+    if (fp64) b->n_redecided += (int)pick.size();
+    else {
+        b->n_screen_rerun = (int)pick.size();
+        b->n_redecided += sub_redecided;
+    }
     return EM_OK;
 }
 
@@ -1657,6 +1724,7 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
         rc = sur_buffers(b);
         if (rc != EM_OK) return rc;
         HIPCHK(b, hipMemsetAsync(d.deferred, 0, (size_t)b->n_trees * S, st));
+        HIPCHK(b, hipMemsetAsync(d.sur_viol, 0, S, st));
         rc = sur_evaluate(b, b->sur_margin * std::min(K, n_steps) * b->run.dt, nullptr, b->run.screen != 0);
         if (rc != EM_OK) return rc;
     }
@@ -1671,20 +1739,26 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
         if (sur) {
             HIPCHK(b, hipMemcpyAsync(b->jhist + (size_t)k * S * b->n_res, d.jseg, 8 * (size_t)S * b->n_res,
                                      hipMemcpyDeviceToDevice, st));
-            if (k > 0) {
+            if (k > 0 && (k & (k - 1)) == 0 && (k & 0x55555555) != 0) {
+                // activation checks before the intervals k = 1, 4, 16, 64, ...:
                 // predictions of the deferred trees with the current densities
-                // (only ever brought forward), then activation of those due
+                // (only ever brought forward), then activation of those due by
+                // the end of the interval before the next check (t_{4k}).  A
+                // catch-up replays every interval before it one after the
+                // other, at the latency of one stepping launch per interval
+                // whatever the number of trees, so the checks are spaced
+                // geometrically: the replays of a run add up to a third of its
+                // intervals at most
                 const int nl = b->n_def_list;
                 if (nl > 0 && !b->ir_unchanged) {
-                    materialize_psi(b);
-                    launch_reeval_features(d, nl, d.feat, st);
+                    launch_reeval_features(d, nl, d.feat, b->jhist, k, REEVAL_TOL, st);
                     LAUNCHCHK(b);
                     int irc = mlp_forward_async(b->sur, d.feat, nl, b->sur_y, st);
                     if (irc != EM_OK) return fail(b, (em_status)irc, "learned-screen model evaluation failed");
                     launch_yhat_min(d, nl, b->sur_y, st);
                 }
                 HIPCHK(b, hipMemsetAsync(d.sur_cnt + 5, 0, 4, st));
-                launch_activate(d, b->sur_margin * std::min(done + K, n_steps) * b->run.dt, st);
+                launch_activate(d, b->sur_margin * std::min(4 * done, n_steps) * b->run.dt, st);
                 LAUNCHCHK(b);
             }
             HIPCHK(b, hipMemcpyAsync(hcnt, d.sur_cnt, 32, hipMemcpyDeviceToHost, st));
@@ -1694,18 +1768,18 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
         int n_active = 0;
         for (int s = 0; s < S; ++s) n_active += h[s] != 0;
         if (n_active == 0) break;
-        if (sur && hcnt[1] != n_activated) {
-            n_activated = hcnt[1];
-            rc = sur_catch_up(b, k, (int)hcnt[5]);
-            if (rc != EM_OK) return rc;
-            rc = sync_open_dirty(b);
-            if (rc != EM_OK) return rc;
-        }
         int nst = std::min(K, n_steps - done);
         const double dt_k = interval_dt(b, k);
         if ((rc = set_step_size(b, dt_k)) != EM_OK) return rc;
-        rc = timed_step(b, nst, done);
+        const bool catch_up = sur && hcnt[1] != n_activated;
+        if (catch_up) {
+            n_activated = hcnt[1];
+            rc = sur_catch_up_begin(b, k, (int)hcnt[5], nst);
+            if (rc != EM_OK) return rc;
+        }
+        rc = timed_step(b, nst, done, !catch_up);
         if (rc != EM_OK) return rc;
+        if (catch_up && (rc = sur_catch_up_end(b, k)) != EM_OK) return rc;
         done += nst;
         t_now += nst * dt_k;
         ++k;
@@ -1742,14 +1816,26 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
         o.redecided = 0;
     }
     b->n_redecided = 0;
+    b->n_screen_rerun = 0;
+    b->rerun_node_steps = 0;
+    // samples a learned-screen violation hit: re-run without the screen
+    std::vector<uint8_t> viol(S, 0);
+    if (sur) {
+        HIPCHK(b, hipMemcpyAsync(viol.data(), d.sur_viol, S, hipMemcpyDeviceToHost, st));
+        HIPCHK(b, hipStreamSynchronize(st));
+        std::vector<int> pick;
+        for (int s = 0; s < S; ++s)
+            if (viol[s]) pick.push_back(s);
+        if (!pick.empty() && (rc = rerun_samples(b, pick, out, false)) != EM_OK) return rc;
+    }
     if (d.guard_band > 0 && b->gcopy) {
         std::vector<uint8_t> gf(S);
         HIPCHK(b, hipMemcpyAsync(gf.data(), d.guard, S, hipMemcpyDeviceToHost, st));
         HIPCHK(b, hipStreamSynchronize(st));
         std::vector<int> pick;
         for (int s = 0; s < S; ++s)
-            if (gf[s]) pick.push_back(s);
-        if (!pick.empty()) return redecide_fp64(b, pick, out);
+            if (gf[s] && !viol[s]) pick.push_back(s);
+        if (!pick.empty()) return rerun_samples(b, pick, out, true);
     }
     return EM_OK;
 }
@@ -1790,6 +1876,8 @@ em_status em_reset(em_batch *b)
     HIPCHK(b, hipStreamSynchronize(st));
     b->sur_ms = 0.0;
     b->n_redecided = 0;
+    b->n_screen_rerun = 0;
+    b->rerun_node_steps = 0;
     b->live_dirty = true;
     b->any_open = false;
     b->ir_valid = false;

@@ -135,6 +135,8 @@ struct Dev {
     float *yhat;                        // [inst] predicted log10(t_nuc / T_REF)
     uint8_t *deferred, *catchup;        // [inst]
     int *def_list;                      // [inst] instances deferred at t = 0 (in no particular order)
+    int *def_k;                         // [def_list] aging interval of each one's last prediction (-1: t = 0)
+    uint8_t *sur_viol;                  // [S] a learned-screen violation hit the sample
     int *act_list;                      // [inst] instances activated by the last activation check
     unsigned int *sur_cnt;              // [8] deferred, activated, late, violations, def_list length,
                                         //     act_list length
@@ -222,7 +224,7 @@ struct AmgHost {
 AmgHost amg_build(int n_nodes, const uint8_t *is_pad, int n_res, const int *ra, const int *rb,
                   const double *R0);
 
-constexpr int NFEAT = 12;               // learned-screen features per (tree, sample)
+constexpr int NFEAT = 16;               // learned-screen features per (tree, sample)
 constexpr double T_REF = 1e8;           // s; the model predicts log10(t_nuc / T_REF)
 
 // ---- launchers (defined in the kernel translation units) ----
@@ -242,7 +244,6 @@ void launch_screen(const Dev &d, bool apply, hipStream_t st);
 // tree_mortal and seg_mortal zeroed by the caller
 void launch_screen_shared(const Dev &d, bool apply, hipStream_t st);
 // copy the shared screen's steady stress (column 0) to every sample's column
-void launch_psi_bcast(const Dev &d, hipStream_t st);
 void launch_step(const Dev &d, bool fp32, int n_steps, int step0, hipStream_t st);
 void launch_branch(const Dev &d, bool fp32, int n_br, int max_nodes, int n_steps, int step0, hipStream_t st);
 void launch_void_dR(const Dev &d, hipStream_t st);
@@ -306,8 +307,10 @@ void launch_result_counts(const Dev &d, int *cnt, hipStream_t st);
 
 // learned screen
 void launch_tree_static(const Dev &d, hipStream_t st);                 // tstat, rdist
-void launch_features(const Dev &d, float *X, bool candidates_only, hipStream_t st);   // needs psi
-void launch_reeval_features(const Dev &d, int n, float *X, hipStream_t st);   // def_list[0..n)
+void launch_features(const Dev &d, float *X, bool candidates_only, bool psi_col0,
+                     hipStream_t st);   // needs psi (column 0 only with psi_col0)
+void launch_reeval_features(const Dev &d, int n, float *X, const double *jhist, int k_now, double tol,
+                            hipStream_t st);   // def_list[0..n)
 void launch_yhat_min(const Dev &d, int n, const float *y, hipStream_t st);
 void launch_defer(const Dev &d, const float *y, double thr, hipStream_t st);
 void launch_activate(const Dev &d, double thr, hipStream_t st);

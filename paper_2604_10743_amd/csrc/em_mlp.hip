@@ -1,4 +1,4 @@
-// Learned screen: a small MLP (12 -> 256 -> 256 -> 256 -> 1, exact GELU)
+// Learned screen: a small MLP (16 -> 256 -> 256 -> 256 -> 1, exact GELU)
 // predicting log10 of a tree's nucleation time from per-tree features, with
 // hand-written BF16 MFMA GEMMs (FP32 accumulation), backward pass and Adam.
 //
@@ -21,7 +21,7 @@ namespace {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
-constexpr int NF = 12;       // features
+constexpr int NF = 16;       // features
 constexpr int KF = 16;       // padded feature width (MFMA K granularity)
 constexpr int HID = 256;     // hidden width
 constexpr int NPARAM = HID * NF + HID + HID * HID + HID + HID * HID + HID + HID + 1;
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void k_adam(float *p, const float *gr, float *
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// pack the [n][12] feature rows into [n][16] with zero padding
+// pack the [n][NF] feature rows into [n][KF] with zero padding (a copy while NF == KF)
 __global__ __launch_bounds__(256) void k_pad_x(const float *X, float *Xp, int n)
 {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -351,7 +351,7 @@ struct Act {
     float *Xp, *Z1, *H1, *Z2, *H2, *Z3, *H3, *y;
 };
 
-// forward pass into the given activation buffers (X: device [n][12])
+// forward pass into the given activation buffers (X: device [n][NF])
 void forward_into(em_mlp *m, const float *X, int n, const Act &a, hipStream_t st)
 {
     k_pad_x<<<cdiv((long long)n * KF, 256), 256, 0, st>>>(X, a.Xp, n);

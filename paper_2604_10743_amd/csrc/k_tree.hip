@@ -625,7 +625,7 @@ EM_KERNEL void k_screen_ss0(Dev d)
 }
 
 // Every sample's verdict from sample 0's steady stress.  The steady stress
-// itself stays in column 0 until a reader needs every column (k_psi_bcast).
+// itself stays in column 0 (its readers take that column).
 __device__ inline void screen_verdict(const Dev &d, int i, int s)
 {
     const int S = d.S;
@@ -648,14 +648,6 @@ EM_KERNEL void k_screen_bcast_flat(Dev d)
 {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g < (long long)d.ns * d.S) screen_verdict(d, (int)(g / d.S), (int)(g % d.S));
-}
-
-EM_KERNEL void k_psi_bcast(Dev d)
-{
-    const int i = blockIdx.y + blockIdx.z * 65535;
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= d.ns || s >= d.S || s == 0) return;
-    d.psi[(size_t)i * d.S + s] = d.psi[(size_t)i * d.S];
 }
 
 EM_KERNEL void k_screen_activate(Dev d)
@@ -1330,41 +1322,142 @@ __device__ inline double kappa_arrhenius(const Dev &d, double T)
     return d.D0 * exp(-d.Ea_eV * E_CHG / kT) * d.B * d.Omega / kT;
 }
 
-// Features of one instance by a wavefront (the screen's steady stress must
-// be current); lane 0 writes the 12 values.
-__device__ void features_wave(const Dev &d, int t, int s, int lane, float *x)
+// ---- per-instance passes by a workgroup of FB threads (four wavefronts):
+// a tree of a few thousand nodes is read four times as fast as by one wave.
+constexpr int FB = 256, FB_LOG = 8;
+static_assert((1 << FB_LOG) == FB, "FB_LOG");
+
+// Workgroup reductions over FB threads (every thread gets the result; sh is
+// an LDS scratch of FB/64 doubles; the leading barrier guards its reuse).
+__device__ inline double bsum(double v, double *sh)
 {
-    const int S = d.S;
+    v = wsum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+#pragma unroll
+    for (int k = 0; k < FB / 64; ++k) r += sh[k];
+    return r;
+}
+__device__ inline double bmax(double v, double *sh)
+{
+    v = wmax(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = sh[0];
+#pragma unroll
+    for (int k = 1; k < FB / 64; ++k) r = fmax(r, sh[k]);
+    return r;
+}
+__device__ inline double bmin(double v, double *sh)
+{
+    return -bmax(-v, sh);
+}
+
+// psi_i = psi_parent + dir dx (S + M) from the root by a workgroup: chunks of
+// FB nodes in pre-order; within a chunk the parent links are followed by
+// pointer jumping through LDS; a parent in an earlier chunk is read back from
+// psi (written by this workgroup before the chunk's barrier).  Then
+// sigma_ss = sigma_T + psi - <psi>_V.
+__device__ void steady_stress_blk(const Dev &d, int t, int s, double (*vs)[FB], int (*as)[FB], double *sh)
+{
+    const int S = d.S, tid = threadIdx.x;
+    const int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
+    double *psi = d.psi;
+    double num = 0.0, den = 0.0;
+    for (int c = i0; c < i1; c += FB) {
+        const int i = c + tid;
+        const bool ok = i < i1;
+        double v = 0.0;
+        int a = -1;
+        if (ok && i > i0) {
+            const int e = d.seg[i];
+            const double dx = d.len[e] / d.N;
+            const double Sd = E_CHG * d.Z * d.rho * xi_rho(d, e, s) * d.jseg[(size_t)s * d.n_res + e] / d.Omega;
+            v = d.dir[i] * dx * (Sd + d.mdrv[i]);
+            a = d.parent[i];
+        }
+        int buf = 0;
+#pragma unroll
+        for (int r = 0; r < FB_LOG; ++r) {
+            vs[buf][tid] = v;
+            as[buf][tid] = a;
+            __syncthreads();
+            if (a >= c) {
+                v += vs[buf][a - c];
+                a = as[buf][a - c];
+            }
+            buf ^= 1;
+        }
+        if (a >= 0) v += psi[(size_t)a * S + s];
+        if (ok) {
+            psi[(size_t)i * S + s] = v;
+            num += d.V[i] * v;
+            den += d.V[i];
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+    const double mean = bsum(num, sh) / bsum(den, sh);
+    for (int i = i0 + tid; i < i1; i += FB) psi[(size_t)i * S + s] = d.sigT + psi[(size_t)i * S + s] - mean;
+    __threadfence_block();
+    __syncthreads();
+}
+
+// Features of one instance by a workgroup (the screen's steady stress must
+// be current in column pc of psi); thread 0 writes the NFEAT values.
+__device__ void features_blk(const Dev &d, int t, int s, int pc, float *x, double *sh, int *shi)
+{
+    const int S = d.S, tid = threadIdx.x;
     const double *ts = d.tstat + (size_t)t * 4;
+    auto PSI = [&](int i) { return d.psi[(size_t)i * S + pc]; };
     double jmax = 0.0, jl = 0.0;
-    for (int k = d.tseg_off[t] + lane; k < d.tseg_off[t + 1]; k += 64) {
+    for (int k = d.tseg_off[t] + tid; k < d.tseg_off[t + 1]; k += FB) {
         int e = d.tseg[k];
         double j = fabs(d.jseg[(size_t)s * d.n_res + e]);
         jmax = fmax(jmax, j);
         jl += d.len[e] * j;
     }
-    jmax = wmax(jmax);
-    jl = wsum(jl);
+    jmax = bmax(jmax, sh);
+    jl = bsum(jl, sh);
     // edge (parent(i), i): Arrhenius diffusivity at the midpoint temperature
     auto edge_kappa = [&](int i) {
         return d.xi_k[(size_t)d.seg[i] * S + s] * kappa_arrhenius(d, 0.5 * (d.T[i] + d.T[d.parent[i]]));
     };
     const int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
-    double ksum = 0.0, ne = 0.0, r = -INFINITY;
+    // pass 1: mean diffusivity, peak ratio, least critical stress, the
+    // blocked-end time and the largest diffusivity
+    double ksum = 0.0, ne = 0.0, r = -INFINITY, dsmin = INFINITY, tblk = INFINITY, kmax = 0.0;
     int pk = 0x7fffffff;
-    for (int i = i0 + lane; i < i1; i += 64) {
-        if (d.parent[i] >= 0) {
-            ksum += edge_kappa(i);
+    for (int i = i0 + tid; i < i1; i += FB) {
+        const int p = d.parent[i];
+        const double ss = PSI(i);
+        const double sci = node_scrit(d, i, s);
+        dsmin = fmin(dsmin, sci - d.sigT);
+        if (p >= 0) {
+            const double ke = edge_kappa(i);
+            ksum += ke;
             ne += 1.0;
+            kmax = fmax(kmax, ke);
+            const double le = d.len[d.seg[i]] / d.N;
+            const double g = fabs(ss - PSI(p)) / le;
+            if (isfinite(g) && g > 0.0) {
+                const double ds = fmax(fmin(sci, node_scrit(d, p, s)) - d.sigT, 1e3);
+                tblk = fmin(tblk, M_PI * ds * ds / (4.0 * ke * g * g));
+            }
         }
-        double ss = d.psi[(size_t)i * S + s];
         if (isfinite(ss)) {
-            double q = ss / node_scrit(d, i, s);
-            if (q > r) { r = q; pk = i; }          // lanes visit ascending nodes: first max
+            double q = ss / sci;
+            if (q > r) { r = q; pk = i; }          // threads visit ascending nodes: first max
         }
     }
-    ksum = wsum(ksum);
-    ne = wsum(ne);
+    ksum = bsum(ksum, sh);
+    ne = bsum(ne, sh);
+    dsmin = fmax(bmin(dsmin, sh), 1e3);
+    tblk = bmin(tblk, sh);
+    kmax = bmax(kmax, sh);
     // peak: largest ratio, lowest node on ties
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -1372,15 +1465,33 @@ __device__ void features_wave(const Dev &d, int t, int s, int lane, float *x)
         const int po = __shfl_xor(pk, o, 64);
         if (ro > r || (ro == r && po < pk)) { r = ro; pk = po; }
     }
+    __syncthreads();
+    if ((tid & 63) == 0) { sh[tid >> 6] = r; shi[tid >> 6] = pk; }
+    __syncthreads();
+    r = sh[0]; pk = shi[0];
+#pragma unroll
+    for (int k = 1; k < FB / 64; ++k)
+        if (sh[k] > r || (sh[k] == r && shi[k] < pk)) { r = sh[k]; pk = shi[k]; }
     if (pk == 0x7fffffff) { pk = i0; r = -10.0; }
     r = fmin(fmax(r, -10.0), 10.0);
-    // distance from the peak to the nearest node at or below sigma_T
-    double lpk = INFINITY;
+    // pass 2: distance from the peak to the nearest node at or below sigma_T;
+    // the fast edges (kappa >= kappa_max / 4): their length and the stress
+    // they could build if blocked on both sides (sum of g l / 2)
+    double lpk = INFINITY, lf = 0.0, sf = 0.0;
     const double dp = d.rdist[pk];
-    for (int i = i0 + lane; i < i1; i += 64)
-        if (d.psi[(size_t)i * S + s] <= d.sigT) lpk = fmin(lpk, fabs(d.rdist[i] - dp));
-    lpk = wmin(lpk);
-    if (lane != 0) return;
+    for (int i = i0 + tid; i < i1; i += FB) {
+        const double ss = PSI(i);
+        if (ss <= d.sigT) lpk = fmin(lpk, fabs(d.rdist[i] - dp));
+        const int p = d.parent[i];
+        if (p < 0 || !(edge_kappa(i) >= 0.25 * kmax)) continue;
+        const double dpsi = fabs(ss - PSI(p));
+        lf += d.len[d.seg[i]] / d.N;
+        if (isfinite(dpsi)) sf += 0.5 * dpsi;
+    }
+    lpk = bmin(lpk, sh);
+    lf = bsum(lf, sh);
+    sf = bsum(sf, sh);
+    if (tid != 0) return;
     if (!isfinite(lpk)) lpk = ts[1];
     lpk = fmax(lpk, 1e-7);
     double kp = 0.0;
@@ -1402,33 +1513,66 @@ __device__ void features_wave(const Dev &d, int t, int s, int lane, float *x)
     x[9] = (float)log10(fmax(r - 1.0, 1e-6));
     x[10] = (float)(log10(tau) - 8.0);
     x[11] = (float)((d.T[pk] - 300.0) / 100.0);
+    // early-time scales: the time a blocked end of a semi-infinite wire with
+    // an edge's steady drive g and diffusivity would take to reach the
+    // critical stress (sigma(0, t) = 2 g sqrt(kappa t / pi)), least over the
+    // edges; the largest diffusivity; the fast edges' blocked stress over the
+    // least critical stress; their diffusion time L_f^2 / (pi^2 kappa_max)
+    x[12] = (float)(log10(fmin(fmax(tblk, 1.0), 1e16)) - 8.0);
+    x[13] = (float)log10(fmax(kmax, 1e-30) / 1e-15);
+    x[14] = (float)fmin(sf / dsmin, 10.0);
+    lf = fmax(lf, 1e-7);
+    x[15] = (float)(log10(lf * lf / (M_PI * M_PI * fmax(kmax, 1e-30))) - 8.0);
 }
 
 // every instance, or only those a deferral could apply to (mortal, and
-// active or already deferred); one instance per wavefront
-EM_KERNEL void k_features(Dev d, float *X, int candidates_only)
+// active or already deferred); one instance per workgroup.  psi_col0: the
+// steady stress of a shared screen (column 0 holds every sample's).
+__global__ __launch_bounds__(FB) void k_features(Dev d, float *X, int candidates_only, int psi_col0)
 {
-    const int lane = threadIdx.x & 63;
-    const int slot = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (slot >= d.n_trees * d.S) return;
+    __shared__ double sh[FB / 64];
+    __shared__ int shi[FB / 64];
+    const int slot = blockIdx.x;
     int t, s;
     int inst = inst_of_slot(d, slot, t, s);
     if (candidates_only && !(d.tree_mortal[inst] && (d.inst_active[inst] || d.deferred[inst]))) return;
-    features_wave(d, t, s, lane, X + (size_t)inst * NFEAT);
+    features_blk(d, t, s, psi_col0 ? 0 : s, X + (size_t)inst * NFEAT, sh, shi);
 }
 
 // Features of the still-deferred instances of def_list[0..n) with the current
-// densities (their steady stress is refreshed first), row k for def_list[k].
-EM_KERNEL void k_reeval_features(Dev d, int n, float *X)
+// densities (their steady stress is refreshed first, in their own column),
+// row k for def_list[k], one instance per workgroup.  An instance whose
+// segment currents have all stayed within tol x the largest of them since its
+// last evaluation (interval def_k[k], densities in jhist) keeps that row: its
+// prediction would hardly move.
+__global__ __launch_bounds__(FB) void k_reeval_features(Dev d, int n, float *X, const double *jhist, int k_now,
+                                                        double tol)
 {
-    const int lane = threadIdx.x & 63;
-    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (k >= n) return;
+    __shared__ double vs[2][FB];
+    __shared__ int as[2][FB];
+    __shared__ double sh[FB / 64];
+    __shared__ int shi[FB / 64];
+    const int k = blockIdx.x, tid = threadIdx.x;
     int inst = d.def_list[k];
     if (!d.deferred[inst]) return;
     int t = inst / d.S, s = inst - (inst / d.S) * d.S;
-    steady_stress_wave(d, t, s, lane);
-    features_wave(d, t, s, lane, X + (size_t)k * NFEAT);
+    const int kp = d.def_k[k];
+    if (kp >= 0) {
+        const double *jp = jhist + ((size_t)kp * d.S + s) * d.n_res;
+        const double *jn = d.jseg + (size_t)s * d.n_res;
+        double jm = 0.0, dj = 0.0;
+        for (int q = d.tseg_off[t] + tid; q < d.tseg_off[t + 1]; q += FB) {
+            const int e = d.tseg[q];
+            jm = fmax(jm, fabs(jp[e]));
+            dj = fmax(dj, fabs(jn[e] - jp[e]));
+        }
+        dj = bmax(dj, sh);
+        jm = bmax(jm, sh);
+        if (dj <= tol * jm) return;
+    }
+    steady_stress_blk(d, t, s, vs, as, sh);
+    features_blk(d, t, s, s, X + (size_t)k * NFEAT, sh, shi);
+    if (tid == 0) d.def_k[k] = k_now;
 }
 
 // A re-evaluated prediction can only bring a deferred instance's activation forward.
@@ -1480,7 +1624,7 @@ EM_KERNEL void k_activate(Dev d, double thr)
 // interval it was activated for is a late activation; if one of its voids had
 // also reached the growth phase (a resistance change the earlier IR solves
 // did not see), it is a violation: only then can the screened run differ from
-// the unscreened one.
+// the unscreened one, and its sample is flagged for a re-run without the screen.
 EM_KERNEL void k_catchup_done(Dev d, int step_lim)
 {
     int inst = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1491,7 +1635,10 @@ EM_KERNEL void k_catchup_done(Dev d, int step_lim)
         atomicAdd(&d.sur_cnt[2], 1u);
         bool grown = false;
         for (int k = 0; k < nv; ++k) grown |= d.vphase[(size_t)inst * MAXV + k] != 0;
-        if (grown) atomicAdd(&d.sur_cnt[3], 1u);
+        if (grown) {
+            atomicAdd(&d.sur_cnt[3], 1u);
+            d.sur_viol[inst % d.S] = 1;
+        }
     }
     d.catchup[inst] = 0;
     d.inst_active[inst] = 1;
@@ -1572,12 +1719,6 @@ void launch_screen_shared(const Dev &d, bool apply, hipStream_t st)
     }
     if (apply) k_screen_activate<<<nblocks((long long)d.n_trees * d.S), 256, 0, st>>>(d);
 }
-void launch_psi_bcast(const Dev &d, hipStream_t st)
-{
-    if (d.S < 2) return;
-    const int bs = rows_bs(d);
-    k_psi_bcast<<<node_rows_grid(d, bs), bs, 0, st>>>(d);
-}
 void launch_step(const Dev &d, bool fp32, int n_steps, int step0, hipStream_t st)
 {
     int n = d.n_trees * d.S;
@@ -1629,13 +1770,14 @@ void launch_tree_static(const Dev &d, hipStream_t st)
 {
     k_tree_static<<<nblocks(d.n_trees), 256, 0, st>>>(d);
 }
-void launch_features(const Dev &d, float *X, bool candidates_only, hipStream_t st)
+void launch_features(const Dev &d, float *X, bool candidates_only, bool psi_col0, hipStream_t st)
 {
-    k_features<<<nblocks((long long)d.n_trees * d.S, 4), 256, 0, st>>>(d, X, candidates_only ? 1 : 0);
+    k_features<<<d.n_trees * d.S, FB, 0, st>>>(d, X, candidates_only ? 1 : 0, psi_col0 ? 1 : 0);
 }
-void launch_reeval_features(const Dev &d, int n, float *X, hipStream_t st)
+void launch_reeval_features(const Dev &d, int n, float *X, const double *jhist, int k_now, double tol,
+                            hipStream_t st)
 {
-    k_reeval_features<<<nblocks(n, 4), 256, 0, st>>>(d, n, X);
+    k_reeval_features<<<n, FB, 0, st>>>(d, n, X, jhist, k_now, tol);
 }
 void launch_yhat_min(const Dev &d, int n, const float *y, hipStream_t st)
 {

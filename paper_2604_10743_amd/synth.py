@@ -648,11 +648,11 @@ def workload(name: str):
 # ----------------------------------------------------------------------------
 # Learned-screen inputs: initial parameters and training grids
 # ----------------------------------------------------------------------------
-MLP_SHAPES = [(256, 12), (256,), (256, 256), (256,), (256, 256), (256,), (256,), (1,)]
+MLP_SHAPES = [(256, 16), (256,), (256, 256), (256,), (256, 256), (256,), (256,), (1,)]
 
 
 def init_mlp_params(seed: int, out_bias: float = 0.0) -> np.ndarray:
-    """Seeded initial parameters of the 12-256-256-256-1 screen model in its
+    """Seeded initial parameters of the 16-256-256-256-1 screen model in its
     flat layout (W1, b1, W2, b2, W3, b3, w4, b4): weights N(0, 2/fan_in)
     (He scaling for rectifier-like units), biases zero, output bias
     ``out_bias``."""

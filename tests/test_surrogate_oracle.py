@@ -149,6 +149,15 @@ def test_features_straight_line_closed_forms(oracle_mod):
     assert abs(f[9] - math.log10(r - 1)) < 1e-9
     assert abs(f[10] - (math.log10((11.7 * UM) ** 2 / (math.pi ** 2 * k)) - 8)) < 3e-6
     assert abs(f[11] - (T - 300) / 100) < 1e-12
+    # early-time scales: the steady drive is Sd on every edge, all edges are
+    # fast (one temperature); blocked-end time pi ds^2 / (4 kappa Sd^2) with
+    # ds = sigma_crit - sigma_T, the whole line blocked builds Sd Lt / 2
+    ds = mat["sigma_crit"] - mat["sigma_T"]
+    t_blk = math.pi * ds ** 2 / (4 * k * Sd ** 2)
+    assert abs(f[12] - (math.log10(t_blk) - 8)) < 3e-6
+    assert abs(f[13] - f[6]) < 1e-12
+    assert abs(f[14] - Sd * Lt / 2 / ds) < 1e-9 * f[14]
+    assert abs(f[15] - (math.log10(Lt ** 2 / (math.pi ** 2 * k)) - 8)) < 3e-6
 
 
 def test_features_uniform_line_peak_end():
@@ -167,6 +176,40 @@ def test_features_uniform_line_peak_end():
     assert abs(F[0, 8] - 1.25) < 1e-12
     assert abs(F[0, 10] - (math.log10((4 * UM) ** 2 / (math.pi ** 2 * k)) - 8)) < 1e-12
     assert abs(F[0, 11] - 0.5) < 1e-12
+    # edges of 2 um with stress steps 2, 3, 3, 2 x 1e7 Pa: steepest drive
+    # 1.5e13 Pa/m, blocked-end time pi (4e7)^2 / (4 k 1.5e13^2); the whole
+    # line is fast and builds (2 + 3 + 3 + 2) x 1e7 / 2 = 5e7 Pa = 1.25 ds
+    assert abs(F[0, 12] - (math.log10(math.pi * 4e7 ** 2 / (4 * k * 1.5e13 ** 2)) - 8)) < 1e-12
+    assert abs(F[0, 13] - math.log10(k / 1e-15)) < 1e-12
+    assert abs(F[0, 14] - 1.25) < 1e-12
+    assert abs(F[0, 15] - (math.log10((8 * UM) ** 2 / (math.pi ** 2 * k)) - 8)) < 1e-12
+
+
+def test_features_fast_region_of_a_hot_end():
+    # the same profile with node temperatures 350, 350, 400, 400, 400 K: edge
+    # midpoints at 350, 375, 400, 400 K, so only the last two edges are within
+    # a factor 4 of the largest diffusivity (the Arrhenius ratio at 375 K is
+    # about 0.2); they span 4 um and build (3 + 2) x 1e7 / 2 Pa
+    class Topo:
+        pass
+    t = Topo()
+    t.N, t.n_trees, t.n_stress = 4, 1, 5
+    t.tree_off = np.array([0, 5]); t.parent = np.array([-1, 0, 1, 2, 3]); t.seg = np.array([-1, 0, 0, 0, 0])
+    g = Topo()
+    g.res_len = np.array([8 * UM])
+    mat = material()
+    ss = np.array([5.0, 3.0, 0.0, -3.0, -5.0]) * 1e7
+    T = np.array([350.0, 350.0, 400.0, 400.0, 400.0])
+    k375, k400, k350 = SO.kappa0(375.0, mat), SO.kappa0(400.0, mat), SO.kappa0(350.0, mat)
+    assert k375 < 0.25 * k400
+    F = SO.features(t, g, mat, np.array([1e10]), np.ones(1), T, ss, np.full(5, 4e7))
+    assert abs(F[0, 13] - math.log10(k400 / 1e-15)) < 1e-12
+    assert abs(F[0, 14] - 2.5e7 / 4e7) < 1e-12
+    assert abs(F[0, 15] - (math.log10((4 * UM) ** 2 / (math.pi ** 2 * k400)) - 8)) < 1e-12
+    # blocked-end time: least of pi ds^2 / (4 kappa_e g_e^2) over the edges
+    tb = min(math.pi * 4e7 ** 2 / (4 * ke * ge ** 2)
+             for ke, ge in ((k350, 1e13), (k375, 1.5e13), (k400, 1.5e13), (k400, 1e13)))
+    assert abs(F[0, 12] - (math.log10(tb) - 8)) < 1e-12
 
 
 def test_features_branched_tree_hand_measures(oracle_mod):
@@ -193,6 +236,17 @@ def test_activation_interval_hand_values():
     assert list(SO.activation_interval(th, m, K, dt)) == [0, 0, 1, 1, 49]
 
 
+def test_activation_check_schedule():
+    # checks before intervals 1, 4, 16, 64, ...; each covers up to the next
+    a = np.array([1, 2, 3, 4, 7, 15, 16, 63, 64, 200])
+    assert list(SO.activation_check(a)) == [1, 1, 1, 4, 4, 4, 16, 16, 64, 64]
+    # a check never comes after the interval it is for, nor before a quarter of it
+    a = np.arange(1, 300)
+    c = SO.activation_check(a)
+    assert np.all(c <= a) and np.all(4 * c > a) and np.all((c & (c - 1)) == 0)
+    assert np.all(np.isin(c, [1, 4, 16, 64, 256]))
+
+
 def test_grad_magnitude_bounds_gradient():
     # the magnitude sums bound every gradient entry, with equality where all
     # terms share a sign: a single row through a network with non-negative
@@ -200,7 +254,7 @@ def test_grad_magnitude_bounds_gradient():
     from oracle import surrogate_oracle as SO
     rng = np.random.default_rng(5)
     p = synth.init_mlp_params(11)
-    X, t = rng.standard_normal((64, 12)), rng.standard_normal(64)
+    X, t = rng.standard_normal((64, 16)), rng.standard_normal(64)
     _, g = SO.loss_and_grad(p, X, t)
     mg = SO.grad_magnitude(p, X, t)
     assert np.all(mg >= np.abs(g) - 1e-15 * np.abs(g).max())

@@ -22,12 +22,12 @@ def test_mlp_forward_noalloc_matches_forward():
     assert nmax == 4096
     # the first call on a device looks the array up (the runtime materialises
     # the module's device globals then); the calls after it allocate nothing
-    X1 = torch.zeros((1, 12), device="cuda")
+    X1 = torch.zeros((1, 16), device="cuda")
     y1 = torch.zeros(1, device="cuda")
     m.forward_noalloc(X1, y1)
     torch.cuda.synchronize()
     for n in (3000, 257):                      # second call smaller than the first
-        X = torch.as_tensor(rng.standard_normal((n, 12)).astype(np.float32), device="cuda")
+        X = torch.as_tensor(rng.standard_normal((n, 16)).astype(np.float32), device="cuda")
         y = torch.full((n,), float("nan"), device="cuda")
         torch.cuda.synchronize()
         free0 = torch.cuda.mem_get_info()[0]
@@ -41,7 +41,7 @@ def test_mlp_forward_noalloc_matches_forward():
         print(f"noalloc n={n}: max |dy| = {np.max(np.abs(a - b)):.3e}", flush=True)
         assert np.all(np.isfinite(a)) and np.array_equal(a, b)
     # the limit: one row too many is an error, the maximum works
-    Xb = torch.zeros((nmax + 1, 12), device="cuda")
+    Xb = torch.zeros((nmax + 1, 16), device="cuda")
     yb = torch.zeros(nmax + 1, device="cuda")
     with pytest.raises(P.EmError):
         m.forward_noalloc(Xb, yb)
