@@ -387,7 +387,9 @@ typedef struct {
     int32_t wg[8], occ[8];       /* each candidate's lanes per workgroup and register budget */
     double wg_ms[8];             /* stream time of the n_steps steps per candidate */
     double ir_ms[3];             /* cold IR solve: multi-kernel, one workgroup per sample from HBM,
-                                    from LDS (-1: not tried) */
+                                    from LDS (-1: not tried; the one-workgroup forms are not tried
+                                    on an iterated system of more than 65 536 nodes with fewer
+                                    than 32 samples) */
 } em_tune_info;
 em_status em_autotune(em_batch *b, int32_t n_steps, em_tune_info *out);
 /* Per-node temperature, control volume and critical stress for one sample. */

@@ -1914,7 +1914,14 @@ em_status em_autotune(em_batch *b, int32_t n_steps, em_tune_info *out)
         double best = 1e300;
         bool best_wg = b->ir_wg, best_lds = b->ir_lds;
         const bool lds_ok = ir_lds_bytes(b->condensed ? b->rd : b->d, b->n_inc, b->amg) > 0;
+        // the one-workgroup-per-sample forms are timed only where they can win:
+        // one workgroup walking a system of more than ir_wg_max_nodes() (65 536)
+        // nodes for fewer than 32 samples is tens of times slower than the
+        // multi-kernel form
+        const int xn = b->condensed ? b->n_term : b->n_nodes;
+        const bool wg_ok = xn <= ir_wg_max_nodes() || b->S >= 32;
         for (int k = 0; k < 3 && rc == EM_OK; ++k) {
+            if (k >= 1 && !wg_ok) break;
             if (k == 2 && !lds_ok) break;
             b->ir_wg = k >= 1;
             b->ir_lds = k == 2;
