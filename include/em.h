@@ -143,8 +143,9 @@ typedef struct {
                                     the dot products differs. */
     int32_t chain_wg;            /* lanes per workgroup of the resident chain kernel: 0 automatic
                                     (the smallest of 256, 512, 1024 that holds the longest chain
-                                    tree; 1024 with 9-node blocks, see chain_m), or one of those
-                                    (at most 512 in FP64) that holds it.
+                                    tree; 1024 with 9-node blocks, see chain_m), or one of 64, 128,
+                                    256, 512, 1024 (at most 512 in FP64) that holds it (64 and 128:
+                                    one or two wavefronts per workgroup, short trees only).
                                     Results do not depend on it (instances never share a
                                     reduction: the couplings across their boundaries are zero),
                                     except that the FP32 1024-lane form keeps no low part of the
@@ -154,7 +155,7 @@ typedef struct {
                                     registers as it uses (one or two workgroups per compute unit);
                                     4 at most 128 VGPRs (four waves per SIMD: four 256-lane or two
                                     512-lane workgroups share a compute unit, some values spill),
-                                    FP32 with 256 or 512 lanes only.  Pays when a launch holds
+                                    FP32 with 64 to 512 lanes only.  Pays when a launch holds
                                     few instances (Monte Carlo after the screen).  Same results. */
     int32_t joule;               /* 1: one-time Joule-heating thermal pre-pass at batch creation
                                     (Sec. III-A): the currents of a nominal IR solve (or the
@@ -384,8 +385,8 @@ typedef struct {
     int32_t chain_occ;           /* chosen register budget (em_run_params.chain_occ) */
     int32_t ir_launch;           /* chosen IR launch shape (1, 2 or 3; 0: not tuned) */
     int32_t n_wg;                /* chain-kernel candidates tried */
-    int32_t wg[8], occ[8];       /* each candidate's lanes per workgroup and register budget */
-    double wg_ms[8];             /* stream time of the n_steps steps per candidate */
+    int32_t wg[12], occ[12];     /* each candidate's lanes per workgroup and register budget */
+    double wg_ms[12];            /* stream time of the n_steps steps per candidate */
     double ir_ms[3];             /* cold IR solve: multi-kernel, one workgroup per sample from HBM,
                                     from LDS (-1: not tried; the one-workgroup forms are not tried
                                     on an iterated system of more than 65 536 nodes with fewer

@@ -103,8 +103,8 @@ class Info(C.Structure):
 
 class TuneInfo(C.Structure):
     _fields_ = [("chain_wg", C.c_int32), ("chain_occ", C.c_int32), ("ir_launch", C.c_int32),
-                ("n_wg", C.c_int32), ("wg", C.c_int32 * 8), ("occ", C.c_int32 * 8),
-                ("wg_ms", C.c_double * 8), ("ir_ms", C.c_double * 3)]
+                ("n_wg", C.c_int32), ("wg", C.c_int32 * 12), ("occ", C.c_int32 * 12),
+                ("wg_ms", C.c_double * 12), ("ir_ms", C.c_double * 3)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)

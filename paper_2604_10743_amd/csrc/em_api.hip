@@ -1141,21 +1141,24 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
         if (r9 * CHAIN_M32W < r8 * CHAIN_M32) cM = CHAIN_M32W;
         else chain_layout(cM);
     }
-    // workgroup sizes that hold the longest chain tree; the smallest unless
-    // the caller (or the autotuner) names one
+    // workgroup sizes that hold the longest chain tree; by default the
+    // smallest of 256 or more (64 and 128 lanes are candidates of the
+    // autotuner and the caller) unless the caller (or the autotuner) names one
     std::vector<int> wg_cand;
-    for (int w = 256; w <= cWGmax; w *= 2)
+    for (int w = 64; w <= cWGmax; w *= 2)
         if (w >= need && (cM == CHAIN_M32 || cM == CHAIN_M64 || w == CHAIN_WG32)) wg_cand.push_back(w);
-    int cWG = wg_cand.front();
+    int cWG = wg_cand.back();
+    for (int w : wg_cand)
+        if (w >= 256) { cWG = w; break; }
     if (r->chain_wg != 0) {
         if (std::find(wg_cand.begin(), wg_cand.end(), r->chain_wg) == wg_cand.end())
-            return fail(b, EM_ERR_ARG, "chain_wg must be a power of two from 256 to the precision's maximum "
+            return fail(b, EM_ERR_ARG, "chain_wg must be a power of two from 64 to the precision's maximum "
                                        "(1024 FP32, 512 FP64) holding the longest chain tree");
         cWG = r->chain_wg;
     }
     if (r->chain_occ != 0 && r->chain_occ != 1 &&
-        !(r->chain_occ == 4 && b->fp32 && (cWG == 256 || cWG == 512)))
-        return fail(b, EM_ERR_ARG, "chain_occ must be 0, 1, or 4 (FP32 with 256 or 512 lanes)");
+        !(r->chain_occ == 4 && b->fp32 && cWG <= 512))
+        return fail(b, EM_ERR_ARG, "chain_occ must be 0, 1, or 4 (FP32 with 64 to 512 lanes)");
     // placement of each chain instance: first lane (global) and lane count;
     // the per-lane table itself is expanded on the device.  The table is
     // allocated for the largest of the candidate sizes' layouts.
@@ -1949,9 +1952,9 @@ em_status em_autotune(em_batch *b, int32_t n_steps, em_tune_info *out)
         std::vector<std::pair<int, int>> cand;          // (lanes, register budget)
         for (int w : b->wg_cand) {
             cand.push_back({w, 1});
-            if (b->fp32 && (w == 256 || w == 512)) cand.push_back({w, 4});
+            if (b->fp32 && w <= 512) cand.push_back({w, 4});
         }
-        for (size_t k = 0; k < cand.size() && k < 8 && rc == EM_OK; ++k) {
+        for (size_t k = 0; k < cand.size() && k < 12 && rc == EM_OK; ++k) {
             b->chain_wg = cand[k].first;
             b->chain_occ = cand[k].second;
             for (int rep = 0; rep < 2 && rc == EM_OK; ++rep) {

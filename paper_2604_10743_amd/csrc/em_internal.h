@@ -69,9 +69,9 @@ struct Dev {
     const int *br_node;                 // [ns] node at each heavy-path position
     const int *br_heavy;                // [ns] child continuing the node's path (-1 at a leaf)
     int n_chain_wg;                     // workgroups of the chain kernel's launch
-    int chain_wg;                       // its lanes per workgroup (256, 512 or the precision's maximum)
+    int chain_wg;                       // its lanes per workgroup (64 to the precision's maximum)
     int chain_m;                        // stress nodes per lane (CHAIN_M32/CHAIN_M64, or CHAIN_M32W)
-    int chain_occ;                      // 1, or 4: register budget of 128 VGPRs (FP32, 256/512 lanes)
+    int chain_occ;                      // 1, or 4: register budget of 128 VGPRs (FP32, 64-512 lanes)
     // ---- per stress node statics (FP64) ----
     double *T, *V, *g0, *rob0, *gdx0, *mdrv;
     double *tree_V;                     // [n_trees] total control volume

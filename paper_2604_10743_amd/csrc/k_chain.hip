@@ -681,7 +681,6 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
 
 void launch_chain(const Dev &d, const Dev *d_dev, bool fp32, int n_steps, int step0, hipStream_t st)
 {
-    if (d.n_chain_wg <= 0) return;
     ChainHot h;
     h.sigma = d.sigma; h.sig_lo = d.sig_lo; h.Vr = d.Vr; h.dtf = d.dtf; h.sc = d.sc;
     h.lane_inst = d.lane_inst; h.lane_blk = d.lane_blk; h.tree_off = d.tree_off;
@@ -691,23 +690,34 @@ void launch_chain(const Dev &d, const Dev *d_dev, bool fp32, int n_steps, int st
     h.dt = d.dt;
     // the batch's workgroup size (lanes): the smallest that holds its longest
     // chain, or the one the autotuner measured fastest
-    const bool dense = d.chain_occ == 4;    // FP32 256/512 lanes only (checked at creation)
-    if (fp32) {
-        if (d.chain_wg == 256) {
-            if (dense) k_chain<float, CHAIN_M32, 256, 4><<<d.n_chain_wg, 256, 0, st>>>(h);
-            else k_chain<float, CHAIN_M32, 256, 1><<<d.n_chain_wg, 256, 0, st>>>(h);
-        } else if (d.chain_wg == 512) {
-            if (dense) k_chain<float, CHAIN_M32, 512, 4><<<d.n_chain_wg, 512, 0, st>>>(h);
-            else k_chain<float, CHAIN_M32, 512, 1><<<d.n_chain_wg, 512, 0, st>>>(h);
+    const bool dense = d.chain_occ == 4;    // FP32 64-512 lanes only (checked at creation)
+    const int G = d.n_chain_wg;
+    if (G > 0) {
+        if (fp32) {
+            if (d.chain_wg == 64) {
+                if (dense) k_chain<float, CHAIN_M32, 64, 4><<<G, 64, 0, st>>>(h);
+                else k_chain<float, CHAIN_M32, 64, 1><<<G, 64, 0, st>>>(h);
+            } else if (d.chain_wg == 128) {
+                if (dense) k_chain<float, CHAIN_M32, 128, 4><<<G, 128, 0, st>>>(h);
+                else k_chain<float, CHAIN_M32, 128, 1><<<G, 128, 0, st>>>(h);
+            } else if (d.chain_wg == 256) {
+                if (dense) k_chain<float, CHAIN_M32, 256, 4><<<G, 256, 0, st>>>(h);
+                else k_chain<float, CHAIN_M32, 256, 1><<<G, 256, 0, st>>>(h);
+            } else if (d.chain_wg == 512) {
+                if (dense) k_chain<float, CHAIN_M32, 512, 4><<<G, 512, 0, st>>>(h);
+                else k_chain<float, CHAIN_M32, 512, 1><<<G, 512, 0, st>>>(h);
+            } else {
+                if (d.chain_m == CHAIN_M32W)
+                    k_chain<float, CHAIN_M32W, CHAIN_WG32, 1><<<G, CHAIN_WG32, 0, st>>>(h);
+                else
+                    k_chain<float, CHAIN_M32, CHAIN_WG32, 1><<<G, CHAIN_WG32, 0, st>>>(h);
+            }
         } else {
-            if (d.chain_m == CHAIN_M32W)
-                k_chain<float, CHAIN_M32W, CHAIN_WG32, 1><<<d.n_chain_wg, CHAIN_WG32, 0, st>>>(h);
-            else
-                k_chain<float, CHAIN_M32, CHAIN_WG32, 1><<<d.n_chain_wg, CHAIN_WG32, 0, st>>>(h);
+            if (d.chain_wg == 64) k_chain<double, CHAIN_M64, 64, 1><<<G, 64, 0, st>>>(h);
+            else if (d.chain_wg == 128) k_chain<double, CHAIN_M64, 128, 1><<<G, 128, 0, st>>>(h);
+            else if (d.chain_wg == 256) k_chain<double, CHAIN_M64, 256, 1><<<G, 256, 0, st>>>(h);
+            else k_chain<double, CHAIN_M64, CHAIN_WG64, 1><<<G, CHAIN_WG64, 0, st>>>(h);
         }
-    } else {
-        if (d.chain_wg == 256) k_chain<double, CHAIN_M64, 256, 1><<<d.n_chain_wg, 256, 0, st>>>(h);
-        else k_chain<double, CHAIN_M64, CHAIN_WG64, 1><<<d.n_chain_wg, CHAIN_WG64, 0, st>>>(h);
     }
 }
 

@@ -201,7 +201,8 @@ def test_chain_workgroup_sizes_give_identical_results(em, prec):
     g, mat, rn, _ = synth.workload("tiny_trees")
     mc = dict(n_samples=8, seed=5, cov_kappa=0.2, cov_scrit=0.2)
     # (lanes, register budget); the 128-VGPR forms run the same arithmetic
-    sizes = ((256, 1), (512, 1), (256, 4), (512, 4), (1024, 1)) if prec == 1 else ((256, 1), (512, 1))
+    sizes = (((256, 1), (512, 1), (256, 4), (512, 4), (64, 1), (128, 1), (64, 4), (128, 4), (1024, 1))
+             if prec == 1 else ((256, 1), (512, 1), (64, 1), (128, 1)))
     out = []
     for w, occ in sizes:
         B = em.Batch(g, mat, dict(rn, prec=prec, chain_wg=w, chain_occ=occ), mc)
@@ -211,7 +212,7 @@ def test_chain_workgroup_sizes_give_identical_results(em, prec):
         out.append(([B.stress(s) for s in range(8)], ev))
         B.close()
     assert len(out[0][1]) > 0
-    n_exact = 4 if prec == 1 else 2
+    n_exact = len(sizes) - 1 if prec == 1 else len(sizes)
     for st, ev in out[1:n_exact]:
         assert all(np.array_equal(a, b) for a, b in zip(st, out[0][0]))
         assert np.array_equal(ev, out[0][1])
