@@ -87,16 +87,25 @@ def host_cpu():
     return {"model": model, "logical_cores": os.cpu_count()}
 
 
+def kernel_code_sha(kernel_src: str) -> str:
+    """SHA-256 (first 16 hex digits) of a kernel source's device code: the
+    file up to its host-side launcher (`void launch_`), so that a change of
+    the launch dispatch alone does not void the counters."""
+    import hashlib
+    txt = open(os.path.join(ROOT, kernel_src)).read()
+    cut = txt.find("\nvoid launch_")
+    return hashlib.sha256((txt if cut < 0 else txt[:cut + 1]).encode()).hexdigest()[:16]
+
+
 def measured_traffic(kernel_src: str, profile_md: str, kernel: str | None = None):
     """HBM bytes per launch from the committed PMC summary, or None when the
-    kernel source changed since the counters were taken (or they were taken
-    on another instantiation of it)."""
-    import hashlib
+    kernel's device code changed since the counters were taken (or they were
+    taken on another instantiation of it)."""
     try:
         txt = open(os.path.join(ROOT, profile_md)).read()
         block = txt.split("```json", 1)[1].split("```", 1)[0]
         pm = json.loads(block)
-        sha = hashlib.sha256(open(os.path.join(ROOT, kernel_src), "rb").read()).hexdigest()[:16]
+        sha = kernel_code_sha(kernel_src)
         if pm.get("source_sha256_16") != sha:
             return None
         if kernel is not None and pm.get("kernel", kernel) != kernel:
