@@ -114,7 +114,10 @@ typedef struct {
     int32_t n_steps;             /* horizon in steps for em_run_to_ttf */
     int32_t ir_every;            /* steps between IR re-solves */
     double fail_frac;            /* failure when worst IR-drop >= fail_frac * vdd */
-    double cg_rtol;              /* PCG: ||r|| <= cg_rtol ||b|| per sample */
+    double cg_rtol;              /* PCG: ||r|| <= cg_rtol ||b|| per sample; 0 automatic: 1e-11 with
+                                    FP64 stepping, 1e-8 with FP32 (four orders below the FP32
+                                    stepping's own drop error; the guard band's FP64 re-runs
+                                    solve to 1e-11) */
     int32_t cg_max_iter;
     int32_t prec;                /* em_precision of the stress stepping */
     int32_t screen;              /* 1: steady-state immortality screen before stepping */

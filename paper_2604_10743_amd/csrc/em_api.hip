@@ -347,7 +347,8 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
     if (!finite_all(mv, 12) || !(m->B > 0) || !(m->Omega > 0) || !(m->delta > 0) || !(m->D0 > 0) || !(m->h_ta > 0))
         return fail(b, EM_ERR_ARG, "bad material constants");
     if (r->intervals_per_seg < 1 || !(r->dt > 0) || !std::isfinite(r->dt) || r->n_steps < 0 || r->ir_every < 1 ||
-        r->cg_max_iter < 1 || !(r->cg_rtol > 0) || (r->prec != EM_FP64 && r->prec != EM_FP32) ||
+        r->cg_max_iter < 1 || !(r->cg_rtol >= 0) || !std::isfinite(r->cg_rtol) ||
+        (r->prec != EM_FP64 && r->prec != EM_FP32) ||
         r->max_voids_per_tree < 0 || r->max_voids_per_tree > MAXV || !(r->T_ambient > 0) ||
         r->stepper < 0 || r->stepper > 1 || r->ir_precond < 0 || r->ir_precond > 2 ||
         r->ir_launch < 0 || r->ir_launch > 3 || r->joule < 0 || r->joule > 1 ||
@@ -998,6 +999,8 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     if (st != EM_OK) return st;
     b->mat = *m;
     b->run = *r;
+    if (b->run.cg_rtol == 0.0)        // automatic: 1e-11 with FP64 stepping, 1e-8 with FP32
+        b->run.cg_rtol = r->prec == EM_FP32 ? 1e-8 : 1e-11;
     b->S = mc ? mc->n_samples : 1;
     b->seed = mc ? mc->seed : 0;
     b->cov_k = mc ? mc->cov_kappa : 0.0;
@@ -1651,6 +1654,7 @@ static em_status rerun_samples(em_batch *b, const std::vector<int> &pick, em_ttf
         r2.prec = EM_FP64;
         r2.guard_band = 0.0;
         r2.guard_ttf = 0.0;
+        r2.cg_rtol = std::min(r2.cg_rtol, 1e-11);     // the FP64 decision solves as tightly as FP64 runs
         r2.chain_wg = 0; r2.chain_occ = 0; r2.chain_m = 0;
     } else {
         r2.chain_wg = b->chain_wg; r2.chain_occ = b->chain_occ; r2.chain_m = b->chain_m;

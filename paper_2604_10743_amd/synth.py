@@ -85,10 +85,12 @@ def default_run(**over) -> dict:
     drop comes within 0.05 % of the threshold, or whose TTF a drop error of
     that size could move by more than 5e-3 relative (guard band): the FP32
     drop error is below 1e-4 relative, a fifth of the band, so a TTF
-    unflagged by the second rule moves by at most 1e-3."""
+    unflagged by the second rule moves by at most 1e-3.  PCG tolerance
+    automatic (0): a relative residual of 1e-11 with FP64 stepping, 1e-8
+    with FP32."""
     horizon = 10 * 365.25 * 86400.0
     r = dict(intervals_per_seg=20, n_steps=2000, dt=horizon / 2000, ir_every=100,
-             fail_frac=0.10, cg_rtol=1e-11, cg_max_iter=20000, prec=0, screen=1,
+             fail_frac=0.10, cg_rtol=0.0, cg_max_iter=20000, prec=0, screen=1,
              max_voids_per_tree=4, T_ambient=378.0, joule=0, guard_band=5e-4, guard_ttf=5e-3)
     r.update(over)
     return r

@@ -94,6 +94,13 @@ OUTER_CASES = {
 }
 
 
+def pcg_rtol(rn):
+    """The PCG tolerance a run dict asks for (0: the library's automatic
+    choice by stepping precision, 1e-11 FP64 / 1e-8 FP32)."""
+    r = float(rn.get("cg_rtol", 0.0))
+    return r if r > 0 else (1e-11 if int(rn.get("prec", 0)) == 0 else 1e-8)
+
+
 def material(**over):
     m = default_material()
     m.update(over)

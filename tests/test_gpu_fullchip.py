@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import ttf_check
+from cases import pcg_rtol
 from paper_2604_10743_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -89,7 +90,9 @@ def test_fullchip_full_size_properties(em, oracle_mod):
     resid = net[~pad] - g.sink_I[~pad]
     kcl = np.linalg.norm(resid) / np.linalg.norm(b[~pad])
     print(f"  drop {drop:.5f}, KCL residual {kcl:.2e}", flush=True)
-    assert kcl <= 1e-9
+    # the PCG stops at ||r|| <= cg_rtol ||b|| on the condensed system; the
+    # chain interiors follow exactly, so the nodal residual is of that size
+    assert kcl <= 10 * pcg_rtol(rn)
     assert abs(drop - np.max((g.vdd - u) / g.vdd)) <= 1e-12
     assert 0.05 < drop < 0.10
     # one aging interval of every tree (screen off), then the stress content
