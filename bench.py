@@ -268,6 +268,15 @@ def mc_leg(args, name, oracle, plain, var=None, joule=False, n_samples=None):
         torch.cuda.synchronize()
         return B, res, time.perf_counter() - t0
 
+    # the multigrid's coarse-correction scale is a property of the network:
+    # tuned once on a one-sample batch of the same design (outside the timed
+    # region) and passed to the Monte Carlo batch
+    t0 = time.perf_counter()
+    Bt = P.Batch(g, mat, run)
+    tune = Bt.autotune(run["ir_every"])
+    Bt.close()
+    t_tune = time.perf_counter() - t0
+    run = dict(run, amg_alpha=tune["amg_alpha"] if tune["amg_alpha"] > 0 else 0.0)
     B, _, _ = one(run, mc)
     B.close()
     B, res, wall = one(run, mc)
@@ -284,6 +293,7 @@ def mc_leg(args, name, oracle, plain, var=None, joule=False, n_samples=None):
          "ttf_cov": float(ttf.std(ddof=1) / ttf.mean()) if ttf.size > 1 else None,
          "final_drop_mean": float(np.mean([r["final_drop"] for r in res])),
          "node_steps": info["node_steps"], "ir_ms": info["ir_ms"], "step_kernel_ms": info["step_kernel_ms"],
+         "amg_alpha": run["amg_alpha"], "tune_s": t_tune,
          "ir_system_nodes": info["ir_sys_nodes"], "cg_iters_total": info["cg_iters_total"],
          "redecided_in_fp64": info["n_redecided"]}
     # roofline of the whole Monte Carlo job: algorithmic HBM bytes per sample =
@@ -551,6 +561,7 @@ def voids_leg(args):
     mat = dict(mat, sigma_crit=200e6)
     run = dict(run, prec=args.prec, screen=1)
     B = P.Batch(g, mat, run)
+    tune = B.autotune(run["ir_every"])           # outside the timed region
     B.run_to_ttf()
     B.reset()
     torch.cuda.synchronize()
@@ -563,6 +574,7 @@ def voids_leg(args):
     return {"metric": "stress-node-steps/s", "value": i["node_steps"] / wall, "unit": "node-steps/s",
             "workload": "pg400 with sigma_crit 200 MPa, screen on, FP32, one run to failure or the horizon",
             "wall_ms": wall * 1e3, "ir_ms": i["ir_ms"], "step_kernel_ms": i["step_kernel_ms"],
+            "autotune": {k: tune[k] for k in ("chain_wg", "chain_occ", "ir_launch", "amg_alpha")},
             "cg_iters": i["cg_iters_total"], "node_steps": i["node_steps"], "ttf_s": r["ttf_s"],
             "failed": r["failed"], "outer_idx": r["outer_idx"], "init_drop": r["init_drop"],
             "final_drop": r["final_drop"], "n_nucleated_trees": r["n_nucleated_trees"],

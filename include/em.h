@@ -206,6 +206,11 @@ typedef struct {
                                     could move the interpolated TTF by more than guard_ttf
                                     relative: guard_band fail_frac (t_k - t_k-1) >
                                     guard_ttf TTF (drop_k - drop_k-1).  0 = off. */
+    double amg_alpha;            /* coarse-correction scale of the multigrid preconditioner: 0
+                                    automatic (1.4), else in [1, 4].  The best value depends on the
+                                    network (pg400 1.4, the full chip 2.2 in cold-solve iterations);
+                                    em_autotune times 1.4, 1.8 and 2.2 when it is 0.  Same solution
+                                    to cg_rtol. */
 } em_run_params;
 
 /* Monte Carlo (Sec. IV-F): unit-mean lognormal multipliers with coefficient
@@ -390,6 +395,9 @@ typedef struct {
     int32_t n_wg;                /* chain-kernel candidates tried */
     int32_t wg[12], occ[12];     /* each candidate's lanes per workgroup and register budget */
     double wg_ms[12];            /* stream time of the n_steps steps per candidate */
+    double amg_alpha;            /* chosen coarse-correction scale (em_run_params.amg_alpha) */
+    double alpha_ms[3];          /* cold IR solve in the chosen launch shape with 1.4, 1.8, 2.2
+                                    (-1: not tried) */
     double ir_ms[3];             /* cold IR solve: multi-kernel, one workgroup per sample from HBM,
                                     from LDS (-1: not tried; the one-workgroup forms are not tried
                                     on an iterated system of more than 65 536 nodes with fewer

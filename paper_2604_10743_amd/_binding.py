@@ -71,7 +71,7 @@ class RunParams(C.Structure):
                 ("stepper", C.c_int32), ("ir_precond", C.c_int32), ("ir_launch", C.c_int32),
                 ("chain_wg", C.c_int32), ("chain_occ", C.c_int32), ("joule", C.c_int32),
                 ("dt_growth", C.c_double), ("chain_m", C.c_int32), ("guard_band", C.c_double),
-                ("guard_ttf", C.c_double)]
+                ("guard_ttf", C.c_double), ("amg_alpha", C.c_double)]
 
 
 class MCParams(C.Structure):
@@ -104,7 +104,8 @@ class Info(C.Structure):
 class TuneInfo(C.Structure):
     _fields_ = [("chain_wg", C.c_int32), ("chain_occ", C.c_int32), ("ir_launch", C.c_int32),
                 ("n_wg", C.c_int32), ("wg", C.c_int32 * 12), ("occ", C.c_int32 * 12),
-                ("wg_ms", C.c_double * 12), ("ir_ms", C.c_double * 3)]
+                ("wg_ms", C.c_double * 12), ("amg_alpha", C.c_double), ("alpha_ms", C.c_double * 3),
+                ("ir_ms", C.c_double * 3)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -216,7 +217,8 @@ class Batch:
                       joule=int(run.get("joule", 0)), dt_growth=float(run.get("dt_growth", 0.0)),
                       chain_m=int(run.get("chain_m", 0)),
                       guard_band=float(run.get("guard_band", 0.0)),
-                      guard_ttf=float(run.get("guard_ttf", 0.0)))
+                      guard_ttf=float(run.get("guard_ttf", 0.0)),
+                      amg_alpha=float(run.get("amg_alpha", 0.0)))
         mcp = None
         if mc is not None:
             mcp = MCParams(struct_size=C.sizeof(MCParams), n_samples=int(mc["n_samples"]),
@@ -344,7 +346,9 @@ class Batch:
         return {"chain_wg": t.chain_wg, "chain_occ": t.chain_occ, "ir_launch": t.ir_launch,
                 "wg_ms": {int(t.wg[k]): float(t.wg_ms[k]) for k in range(n) if t.occ[k] == 1},
                 "wg_ms_occ4": {int(t.wg[k]): float(t.wg_ms[k]) for k in range(n) if t.occ[k] == 4},
-                "ir_ms": {1: float(t.ir_ms[0]), 3: float(t.ir_ms[1]), 2: float(t.ir_ms[2])}}
+                "ir_ms": {1: float(t.ir_ms[0]), 3: float(t.ir_ms[1]), 2: float(t.ir_ms[2])},
+                "amg_alpha": float(t.amg_alpha),
+                "alpha_ms": {1.4: float(t.alpha_ms[0]), 1.8: float(t.alpha_ms[1]), 2.2: float(t.alpha_ms[2])}}
 
     def set_seg_state(self, sample: int, dR, open_):
         dR = np.ascontiguousarray(dR, np.float64)

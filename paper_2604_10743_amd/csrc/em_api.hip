@@ -353,9 +353,10 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
         r->stepper < 0 || r->stepper > 1 || r->ir_precond < 0 || r->ir_precond > 2 ||
         r->ir_launch < 0 || r->ir_launch > 3 || r->joule < 0 || r->joule > 1 ||
         !(r->dt_growth >= 0) || !std::isfinite(r->dt_growth) || !(r->guard_band >= 0) || !(r->guard_band < 1) ||
-        !(r->guard_ttf >= 0) || !std::isfinite(r->guard_ttf))
+        !(r->guard_ttf >= 0) || !std::isfinite(r->guard_ttf) ||
+        !(r->amg_alpha == 0.0 || (r->amg_alpha >= 1.0 && r->amg_alpha <= 4.0)))
         return fail(b, EM_ERR_ARG, "bad run parameters (max_voids_per_tree <= 4, 0 <= guard_band < 1, "
-                                   "guard_ttf >= 0)");
+                                   "guard_ttf >= 0, amg_alpha 0 or in [1, 4])");
     if (r->joule) {
         const double tv[] = {m->k_cu, m->k_ild, m->t_ild};
         if (!finite_all(tv, 3) || !(m->k_cu > 0) || !(m->k_ild > 0) || !(m->t_ild > 0))
@@ -1444,7 +1445,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
             if (a.dense) AL(a.Ainv, mgreal, (size_t)S * nc * nc);
             b->use_amg = true;
             a.omega = 0.9;          // Jacobi weight and coarse-correction scale chosen by
-            a.alpha = 1.4;          // measurement (PCG iterations on the P/G grids)
+            a.alpha = r->amg_alpha > 0 ? r->amg_alpha : 1.4;   // measurement (PCG iterations)
             // one workgroup per sample pays off when the samples fill the chip
             // or the system is small; a single large system keeps every CU busy
             // only in the one-kernel-per-step form
@@ -1659,6 +1660,7 @@ static em_status rerun_samples(em_batch *b, const std::vector<int> &pick, em_ttf
     } else {
         r2.chain_wg = b->chain_wg; r2.chain_occ = b->chain_occ; r2.chain_m = b->chain_m;
     }
+    if (b->use_amg) r2.amg_alpha = b->amg.alpha;     // the batch's (possibly tuned) preconditioner
     em_mc_params mc2{};
     mc2.struct_size = sizeof(em_mc_params);
     mc2.n_samples = (int)pick.size();
@@ -1899,6 +1901,20 @@ em_status em_reset(em_batch *b)
     return EM_OK;
 }
 
+// The multigrid preconditioner's coarse-correction scale: the host copy, the
+// device copy of the one-workgroup forms, and the captured PCG graph (whose
+// launches carry it) re-captured at the next solve.
+static em_status set_amg_alpha(em_batch *b, double alpha)
+{
+    if (!b->use_amg || b->amg.alpha == alpha) return EM_OK;
+    b->amg.alpha = alpha;
+    HIPCHK(b, hipMemcpyAsync(b->amg_dev, &b->amg, sizeof(Amg), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    if (b->cg_exec) { (void)hipGraphExecDestroy(b->cg_exec); b->cg_exec = nullptr; }
+    if (b->cg_graph) { (void)hipGraphDestroy(b->cg_graph); b->cg_graph = nullptr; }
+    return EM_OK;
+}
+
 em_status em_autotune(em_batch *b, int32_t n_steps, em_tune_info *out)
 {
     if (!b || n_steps < 1) return fail(b, EM_ERR_ARG, "bad step count");
@@ -1948,6 +1964,29 @@ em_status em_autotune(em_batch *b, int32_t n_steps, em_tune_info *out)
         b->ir_wg = best_wg;
         b->ir_lds = best_lds;
         info.ir_launch = best_lds ? 2 : best_wg ? 3 : 1;
+        // coarse-correction scale, in the chosen shape, unless the caller set one
+        info.alpha_ms[0] = info.alpha_ms[1] = info.alpha_ms[2] = -1.0;
+        if (b->run.amg_alpha == 0.0 && rc == EM_OK) {
+            const double cand_a[3] = {1.4, 1.8, 2.2};
+            double best_t = 1e300, best_a = b->amg.alpha;
+            for (int k = 0; k < 3 && rc == EM_OK; ++k) {
+                if ((rc = set_amg_alpha(b, cand_a[k])) != EM_OK) break;
+                for (int rep = 0; rep < 2 && rc == EM_OK; ++rep) {
+                    if ((rc = em_reset(b)) != EM_OK) break;
+                    HIPCHK(b, hipEventRecord(e0, st));
+                    if ((rc = ir_solve_impl(b)) != EM_OK) break;
+                    HIPCHK(b, hipEventRecord(e1, st));
+                    float ms = 0.f;
+                    if ((rc = stream_ms(ms)) != EM_OK) break;
+                    if (rep == 1) {
+                        info.alpha_ms[k] = ms;
+                        if (ms < best_t) { best_t = ms; best_a = cand_a[k]; }
+                    }
+                }
+            }
+            if (rc == EM_OK) rc = set_amg_alpha(b, best_a);
+        }
+        info.amg_alpha = b->amg.alpha;
     }
     // chain-kernel workgroup size: n_steps steps of the screened instances
     if (rc == EM_OK && b->d.n_chain_wg >= 0) {

@@ -292,6 +292,7 @@ def test_autotune_keeps_results_and_resets(em):
     print("autotune", t, flush=True)
     assert set(t["wg_ms"]) == {256, 512} and t["chain_wg"] in t["wg_ms"]      # FP64: up to 512 lanes
     assert t["ir_launch"] in (1, 2, 3) and t["ir_ms"][1] > 0 and t["ir_ms"][3] > 0 and t["ir_ms"][2] > 0
+    assert t["amg_alpha"] in (1.4, 1.8, 2.2) and all(v > 0 for v in t["alpha_ms"].values())
     res = B.run_to_ttf()
     assert sum(r["failed"] for r in ref) > 0
     for a, b in zip(ref, res):
