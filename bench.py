@@ -74,6 +74,21 @@ def _oracle_trees_worker(job):
     return int(topo.tree_off[t1] - topo.tree_off[t0]) * n_steps
 
 
+def _oracle_mc_worker(job):
+    """One host process of the all-core Monte Carlo oracle baseline: the
+    named workload's samples ``ids`` run to TTF by the FP64 oracle."""
+    name, ids, var = job
+    sys.path.insert(0, ROOT)
+    from oracle import oracle as O
+    from paper_2604_10743_amd import synth
+    g, mat, run, mc = synth.workload(name)
+    mc = dict(mc, **(var or {}))
+    topo = O.topology(g, run["intervals_per_seg"])
+    for s in ids:
+        O.run_sample(g, mat, run, mc, s, topo=topo)
+    return len(ids)
+
+
 def host_cpu():
     """Host CPU model and logical core count (for the oracle baselines)."""
     model = None
@@ -326,8 +341,22 @@ def mc_leg(args, name, oracle, plain, var=None, joule=False, n_samples=None):
                                "max_rel_err_ttf": e_ttf, "max_rel_err_final_drop": e_fd,
                                "oracle_failed": int(sum(refs[s]["failed"] for s in refs))}
         o["cpu_baseline"] = {"value": len(refs) / t_or, "unit": "samples/s", "cores": 1, "kind": "oracle",
+                             "cpu": host_cpu(),
                              "sample": f"every 16th of the {S} samples ({len(refs)}), FP64 oracle, "
                                       f"{t_or:.1f} s incl. its IR direct solves"}
+        # the same samples over the host's cores (one spawned process each)
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        ids = list(refs)
+        n_proc = max(1, min(16, os.cpu_count() or 1, len(ids)))
+        jobs = [(name, ids[k::n_proc], var) for k in range(n_proc)]
+        t0 = time.perf_counter()
+        with cf.ProcessPoolExecutor(max_workers=n_proc, mp_context=mp.get_context("spawn")) as ex:
+            n_done = sum(ex.map(_oracle_mc_worker, jobs))
+        ta = time.perf_counter() - t0
+        o["cpu_baseline"]["all_cores"] = {"value": n_done / ta, "unit": "samples/s", "cores": n_proc,
+                                          "sample": f"the same {n_done} samples over {n_proc} spawned processes "
+                                                    f"({ta:.1f} s incl. each process's setup)"}
     if plain:
         Sp = min(64, S)
         runp = dict(run, prec=0, stepper=1, screen=0, ir_precond=0)
@@ -547,19 +576,19 @@ def branched_leg(args):
     return out
 
 
-def voids_leg(args):
-    """pg400 with voids: the critical stress lowered to 200 MPa so that the
-    mortal lines nucleate within the horizon, steady-state screen on; void
-    growth, liner resistance changes and IR re-solves run inside the timed
-    region (one untimed run first)."""
+def voids_leg(args, name="pg400", sigma_crit=200e6, screen=1):
+    """A grid with voids: the critical stress lowered (pg400: 200 MPa, the
+    full chip: 250 MPa) so that the mortal lines nucleate within the horizon;
+    void growth, liner resistance changes and IR re-solves run inside the
+    timed region (one untimed run first)."""
     import numpy as np
     import torch
     import paper_2604_10743_amd as P
     from paper_2604_10743_amd import synth
 
-    g, mat, run, _ = synth.workload("pg400")
-    mat = dict(mat, sigma_crit=200e6)
-    run = dict(run, prec=args.prec, screen=1)
+    g, mat, run, _ = synth.workload(name)
+    mat = dict(mat, sigma_crit=sigma_crit)
+    run = dict(run, prec=args.prec, screen=screen)
     B = P.Batch(g, mat, run)
     tune = B.autotune(run["ir_every"])           # outside the timed region
     B.run_to_ttf()
@@ -572,7 +601,8 @@ def voids_leg(args):
     i = B.info()
     B.close()
     return {"metric": "stress-node-steps/s", "value": i["node_steps"] / wall, "unit": "node-steps/s",
-            "workload": "pg400 with sigma_crit 200 MPa, screen on, FP32, one run to failure or the horizon",
+            "workload": f"{name} with sigma_crit {sigma_crit / 1e6:g} MPa, screen {'on' if screen else 'off'}, "
+                        f"FP32, one run to failure or the horizon",
             "wall_ms": wall * 1e3, "ir_ms": i["ir_ms"], "step_kernel_ms": i["step_kernel_ms"],
             "autotune": {k: tune[k] for k in ("chain_wg", "chain_occ", "ir_launch", "amg_alpha")},
             "cg_iters": i["cg_iters_total"], "node_steps": i["node_steps"], "ttf_s": r["ttf_s"],
@@ -704,6 +734,8 @@ def main():
         log("bench: pg400 done")
     out["pg400_voids"] = voids_leg(args)
     log("bench: pg400 with voids done")
+    out["fullchip_voids"] = voids_leg(args, "fullchip", 250e6, screen=0)
+    log("bench: fullchip with voids done")
     out["branched"] = branched_leg(args)
     log("bench: branched trees done")
     if not args.no_mc:
