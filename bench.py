@@ -273,7 +273,9 @@ def mc_leg(args, name, oracle, plain, var=None, joule=False, n_samples=None):
     if joule:
         run = dict(run, joule=1)
     S = mc["n_samples"]
-    extra = "".join(f", {k[4:]} CoV {v:g}" for k, v in (var or {}).items()) + (", Joule pre-pass" if joule else "")
+    label = {"sd_T_K": "die-temperature sd {:g} K", "sd_ea_eV": "activation-energy sd {:g} eV"}
+    extra = "".join(", " + (label[k].format(v) if k in label else f"{k[4:]} CoV {v:g}")
+                    for k, v in (var or {}).items()) + (", Joule pre-pass" if joule else "")
 
     def one(run_, mc_):
         torch.cuda.synchronize()
@@ -716,7 +718,8 @@ def main():
         out = {"mc": mc_leg(args, "mc_grid", oracle=False, plain=False),
                "mc_mesh": mc_leg(args, "mc_mesh", oracle=False, plain=False),
                "mc_rho_load": mc_leg(args, "mc_grid", oracle=False, plain=False, var=MC_VAR),
-               "mc_joule": mc_leg(args, "mc_grid", oracle=False, plain=False, joule=True)}
+               "mc_joule": mc_leg(args, "mc_grid", oracle=False, plain=False, joule=True),
+               "mc_die_T": mc_leg(args, "mc_grid", oracle=False, plain=False, var={"sd_T_K": 3.0})}
         print(json.dumps(out), flush=True)
         return
 
@@ -746,6 +749,7 @@ def main():
         out["mc_mesh"] = mc_leg(args, "mc_mesh", oracle=False, plain=False)
         out["mc_rho_load"] = mc_leg(args, "mc_grid", oracle=False, plain=False, var=MC_VAR)
         out["mc_joule"] = mc_leg(args, "mc_grid", oracle=False, plain=False, joule=True)
+        out["mc_die_T"] = mc_leg(args, "mc_grid", oracle=False, plain=False, var={"sd_T_K": 3.0})
         log("bench: mc (mc_mesh, variations) done")
         out["thermal_sweep"] = thermal_leg(args)
         log("bench: thermal sweep done")

@@ -226,7 +226,15 @@ typedef struct {
  *            (standard normal from the same counter and Box-Muller branch)
  *            multiplies the segment's diffusivity by exp(-dEa / (k_B T)), T the
  *            map temperature at the segment's midpoint (T_ambient without
- *            thermal data); the factor joins the kappa multiplier.
+ *            thermal data); the factor joins the kappa multiplier;
+ *   param 5  die temperature, per sample (counter index 0): the thermal map
+ *            shifted by dT ~ N(0, sd_T_K) (a perturbation of the map, Sec.
+ *            IV-F); every wire segment's diffusivity takes the Arrhenius
+ *            factor kappa(T + dT) / kappa(T) = exp(Ea/k_B (1/T - 1/(T + dT)))
+ *            T/(T + dT), T as for param 4, folded into the kappa multiplier.
+ *            The thermomigration drive keeps the unshifted map (a uniform
+ *            shift leaves dT/dx unchanged; its 1/T^2 factor moves by under
+ *            2 % for |dT| <= 3 K at 330 K), and sigma_crit does not depend on T.
  * The paper's study perturbs kappa and sigma_crit; resistivity and loading are
  * two of the further sampled inputs it names for the same flow.  With
  * cov_rho = cov_load = 0 every sample starts on the nominal network. */
@@ -237,6 +245,7 @@ typedef struct {
     double cov_kappa, cov_scrit;
     double cov_rho, cov_load;
     double sd_ea_eV;             /* activation-energy spread, eV, 0 <= sd < 1 */
+    double sd_T_K;               /* die-temperature spread, K, 0 <= sd <= 20 */
     const int32_t *sample_ids;   /* [n_samples] host, or NULL: the Monte Carlo sample index
                                     (the Philox counter's sample word) of each batch sample;
                                     NULL = 0 .. n_samples-1.  Entries >= 0, copied at creation.

@@ -338,13 +338,17 @@ def ir_solve(grid, R, open_mask=None):
 K_B_EV = 1.380649e-23 / 1.602176634e-19        # Boltzmann constant, eV/K
 
 
-def sample_xi(grid, mc, sample, T_amb=300.0):
+def sample_xi(grid, mc, sample, T_amb=300.0, Ea_eV=None):
     """Diffusivity and critical-stress multipliers of one sample, per segment.
 
     An activation-energy spread sd_ea_eV > 0 draws dEa ~ N(0, sd) per wire
     segment (param 4); the diffusivity D0 exp(-(Ea + dEa)/(k_B T)) then carries
     the extra factor exp(-dEa/(k_B T)), taken at the segment midpoint's map
-    temperature and folded into the diffusivity multiplier."""
+    temperature and folded into the diffusivity multiplier.  A die-temperature
+    spread sd_T_K > 0 draws one offset dT ~ N(0, sd) per sample (param 5,
+    index 0): the map shifted by dT changes every wire segment's Arrhenius
+    diffusivity D0 exp(-Ea/(k_B T)) B Omega/(k_B T) by the ratio of its values
+    at T + dT and T (the same midpoint temperature), folded in likewise."""
     if mc is None:
         return None, None
     xi_k = lognormal_xi(mc["seed"], sample, grid.n_res, 0, mc["cov_kappa"])
@@ -354,6 +358,16 @@ def sample_xi(grid, mc, sample, T_amb=300.0):
         z = normal_z(mc["seed"], sample, grid.n_res, 4)
         for e in np.nonzero(wire)[0]:
             xi_k[e] *= np.exp(-sd * z[e] / (K_B_EV * thermal.midpoint_map_T(grid, T_amb, int(e))))
+    sdT = float(mc.get("sd_T_K", 0.0))
+    if sdT > 0:
+        wire = (grid.res_is_via == 0) & (grid.layer[grid.res_a] == grid.layer[grid.res_b])
+        if Ea_eV is None:
+            raise ValueError("a die-temperature spread needs the material's activation energy")
+        dT = sdT * float(normal_z(mc["seed"], sample, 1, 5)[0])
+        Ea = float(Ea_eV)
+        for e in np.nonzero(wire)[0]:
+            T = thermal.midpoint_map_T(grid, T_amb, int(e))
+            xi_k[e] *= np.exp(-Ea / (K_B_EV * (T + dT))) / (T + dT) / (np.exp(-Ea / (K_B_EV * T)) / T)
     return xi_k, lognormal_xi(mc["seed"], sample, grid.n_res, 1, mc["cov_scrit"])
 
 
@@ -381,7 +395,7 @@ def run_sample(grid, mat, run, mc=None, sample=0, topo=None, keep_sim=False, max
     init_drop, final_drop, failed_segs, n_nucleated_trees, events, sigma."""
     N = int(run["intervals_per_seg"])
     topo = topo or topology(grid, N)
-    xi_k, xi_s = sample_xi(grid, mc, sample, float(run.get("T_ambient", 300.0)))
+    xi_k, xi_s = sample_xi(grid, mc, sample, float(run.get("T_ambient", 300.0)), mat["Ea_eV"])
     xi_r, R0, sinks = sample_inputs(grid, mc, sample)
     trees_only = grid.seg_j is not None
     gs = grid

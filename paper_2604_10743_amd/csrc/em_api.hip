@@ -22,7 +22,7 @@ struct em_batch {
     em_run_params run;
     int S = 1;
     uint64_t seed = 0;
-    double cov_k = 0, cov_s = 0, cov_r = 0, cov_l = 0, sd_ea = 0;
+    double cov_k = 0, cov_s = 0, cov_r = 0, cov_l = 0, sd_ea = 0, sd_T = 0;
     bool trees_only = false;
     bool fp32 = false;
     hipStream_t stream = nullptr;
@@ -365,7 +365,7 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
     if (mc && (mc->n_samples < 1 || mc->n_samples > 65535 || mc->cov_kappa < 0 || mc->cov_scrit < 0 || !std::isfinite(mc->cov_kappa) ||
                !std::isfinite(mc->cov_scrit) || !(mc->cov_rho >= 0) || !(mc->cov_load >= 0) ||
                !std::isfinite(mc->cov_rho) || !std::isfinite(mc->cov_load) || !(mc->sd_ea_eV >= 0) ||
-               !(mc->sd_ea_eV < 1.0)))
+               !(mc->sd_ea_eV < 1.0) || !(mc->sd_T_K >= 0) || !(mc->sd_T_K <= 20.0)))
         return fail(b, EM_ERR_ARG, "bad Monte Carlo parameters");
     if (mc && mc->sample_ids)
         for (int s = 0; s < mc->n_samples; ++s)
@@ -1010,6 +1010,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     b->cov_r = mc ? mc->cov_rho : 0.0;
     b->cov_l = (mc && !b->trees_only) ? mc->cov_load : 0.0;     // no sinks in trees-only mode
     b->sd_ea = mc ? mc->sd_ea_eV : 0.0;
+    b->sd_T = mc ? mc->sd_T_K : 0.0;
     b->fp32 = r->prec == EM_FP32;
     if (mc && mc->sample_ids) b->sid_h.assign(mc->sample_ids, mc->sample_ids + mc->n_samples);
     b->stream = (hipStream_t)hip_stream;
@@ -1469,7 +1470,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     launch_node_T(d, stq);
     launch_edge_static(d, stq);
     launch_node_V(d, b->fp32, stq);
-    launch_draws(d, b->seed, b->cov_k, b->cov_s, b->cov_r, b->cov_l, b->sd_ea, stq);
+    launch_draws(d, b->seed, b->cov_k, b->cov_s, b->cov_r, b->cov_l, b->sd_ea, b->sd_T, stq);
     b->nominal = !d.xi_r && !d.sink_s;
     launch_node_sc(d, b->fp32, stq);
     launch_set_sigma_T(d, b->fp32, stq);
@@ -1667,6 +1668,7 @@ static em_status rerun_samples(em_batch *b, const std::vector<int> &pick, em_ttf
     mc2.seed = b->seed;
     mc2.cov_kappa = b->cov_k; mc2.cov_scrit = b->cov_s; mc2.cov_rho = b->cov_r; mc2.cov_load = b->cov_l;
     mc2.sd_ea_eV = b->sd_ea;
+    mc2.sd_T_K = b->sd_T;
     mc2.sample_ids = ids.data();
     em_batch *sub = nullptr;
     em_status rc = em_batch_create(&b->gcopy->g, &b->mat, &r2, &mc2, b->has_alloc ? &b->alloc : nullptr,

@@ -235,7 +235,7 @@ void launch_joule_T(const Dev &d, const double *j, double *D, double *r, hipStre
 void launch_edge_static(const Dev &d, hipStream_t st);
 void launch_node_V(const Dev &d, bool fp32, hipStream_t st);   // also per-tree volume
 void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, double cov_r, double cov_l,
-                  double sd_ea, hipStream_t st);
+                  double sd_ea, double sd_T, hipStream_t st);
 void launch_node_sc(const Dev &d, bool fp32, hipStream_t st);
 void launch_update_f(const Dev &d, bool fp32, hipStream_t st);
 void launch_factor(const Dev &d, bool fp32, hipStream_t st);

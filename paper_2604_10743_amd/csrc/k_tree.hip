@@ -294,8 +294,11 @@ __device__ inline double lognormal_xi(uint64_t seed, int sample, int segment, in
 
 // The activation-energy offset dEa ~ N(0, sd_ea) of a wire segment (param 4)
 // scales its diffusivity by exp(-dEa / (k_B T)), T the map temperature at the
-// segment's midpoint; it joins the kappa multiplier.
-EM_KERNEL void k_draws(Dev d, uint64_t seed, double cov_k, double cov_s, double cov_r, double sd_ea, int use_mc)
+// segment's midpoint; the sample's die-temperature offset dT ~ N(0, sd_T)
+// (param 5, one per sample) by the Arrhenius ratio kappa(T + dT) / kappa(T).
+// Both join the kappa multiplier.
+EM_KERNEL void k_draws(Dev d, uint64_t seed, double cov_k, double cov_s, double cov_r, double sd_ea, double sd_T,
+                       int use_mc)
 {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long long)d.n_res * d.S) return;
@@ -304,6 +307,10 @@ EM_KERNEL void k_draws(Dev d, uint64_t seed, double cov_k, double cov_s, double 
     double xk = use_mc ? lognormal_xi(seed, sm, e, 0, cov_k) : 1.0;
     if (sd_ea > 0.0 && d.is_wire[e])
         xk *= exp(-sd_ea * normal_z(seed, sm, e, 4) / ((K_B / E_CHG) * map_T_mid(d, e)));
+    if (sd_T > 0.0 && d.is_wire[e]) {
+        const double T = map_T_mid(d, e), dT = sd_T * normal_z(seed, sm, 0, 5);
+        xk *= exp(d.Ea_eV / (K_B / E_CHG) * (1.0 / T - 1.0 / (T + dT))) * T / (T + dT);
+    }
     d.xi_k[g] = xk;
     d.xi_s[g] = use_mc ? lognormal_xi(seed, sm, e, 1, cov_s) : 1.0;
     if (d.xi_r) d.xi_r[g] = d.is_wire[e] ? lognormal_xi(seed, sm, e, 2, cov_r) : 1.0;
@@ -1664,10 +1671,10 @@ void launch_node_V(const Dev &d, bool fp32, hipStream_t st)
     k_tree_V<<<nblocks(d.n_trees, 4), 256, 0, st>>>(d);
 }
 void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, double cov_r, double cov_l,
-                  double sd_ea, hipStream_t st)
+                  double sd_ea, double sd_T, hipStream_t st)
 {
     int use = (cov_k != 0.0 || cov_s != 0.0) ? 1 : 0;
-    k_draws<<<nblocks((long long)d.n_res * d.S), 256, 0, st>>>(d, seed, cov_k, cov_s, cov_r, sd_ea, use);
+    k_draws<<<nblocks((long long)d.n_res * d.S), 256, 0, st>>>(d, seed, cov_k, cov_s, cov_r, sd_ea, sd_T, use);
     if (d.sink_s) k_draws_load<<<nblocks((long long)d.n_nodes * d.S), 256, 0, st>>>(d, seed, cov_l);
 }
 // grid of one block row per node (rows beyond 65535 folded into z) and the

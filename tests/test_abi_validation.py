@@ -99,6 +99,9 @@ CASES = {
     "bad Monte Carlo (rho)": lambda g, m, r, mc: mc.__setitem__("cov_rho", math.nan),
     "bad Monte Carlo (Ea spread)": lambda g, m, r, mc: mc.__setitem__("sd_ea_eV", -0.01),
     "bad Monte Carlo (Ea spread, huge)": lambda g, m, r, mc: mc.__setitem__("sd_ea_eV", 2.0),
+    "bad Monte Carlo (die temperature spread)": lambda g, m, r, mc: mc.__setitem__("sd_T_K", -1.0),
+    "bad Monte Carlo (die temperature spread, huge)": lambda g, m, r, mc: mc.__setitem__("sd_T_K", 50.0),
+    "bad run parameters (multigrid scale)": lambda g, m, r, mc: r.__setitem__("amg_alpha", 0.5),
 }
 
 

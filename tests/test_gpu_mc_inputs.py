@@ -146,3 +146,33 @@ def test_activation_energy_draws_and_runs_match_oracle(em, oracle_mod):
             assert r["outer_idx"] == ref["outer_idx"], s
         assert np.array_equal(segs[s], ref["failed_segs"]), s
     assert n_fail >= 1
+
+
+def test_die_temperature_offset_draws_and_runs_match_oracle(em, oracle_mod):
+    # one die-temperature offset dT ~ N(0, 3 K) per sample under the hotspot map
+    g, mat, rn, mc = synth.workload("mc_grid")
+    S = 24
+    mc = dict(mc, n_samples=S, sd_T_K=3.0)
+    rn = dict(rn, prec=0)
+    print("mc inputs: die temperature", flush=True)
+    B = em.Batch(g, mat, rn, mc)
+    for s in (0, 5, 23):
+        xk, xs = oracle_mod.sample_xi(g, mc, s, T_amb=rn["T_ambient"], Ea_eV=mat["Ea_eV"])
+        assert np.allclose(B.xi(s, 0), xk, rtol=1e-13, atol=0), s
+        assert np.allclose(B.xi(s, 1), xs, rtol=1e-13, atol=0), s
+    res = B.run_to_ttf()
+    segs = {s: B.failed_segments(s) for s in range(0, S, 3)}
+    B.close()
+    topo = oracle_mod.topology(g, rn["intervals_per_seg"])
+    n_fail = 0
+    for s in range(0, S, 3):
+        ref = oracle_mod.run_sample(g, mat, rn, mc, s, topo=topo)
+        r = res[s]
+        n_fail += ref["failed"]
+        assert r["failed"] == ref["failed"], s
+        assert abs(r["final_drop"] - ref["final_drop"]) <= 1e-6 * ref["final_drop"], s
+        if ref["failed"]:
+            assert abs(r["ttf_s"] - ref["ttf"]) <= 1e-6 * ref["ttf"], s
+            assert r["outer_idx"] == ref["outer_idx"], s
+        assert np.array_equal(segs[s], ref["failed_segs"]), s
+    assert n_fail >= 1

@@ -7,6 +7,7 @@ deliver exactly its own (scaled) sink currents."""
 import math
 
 import numpy as np
+import pytest
 
 from cases import material, run, tree_from_edges
 from paper_2604_10743_amd import synth
@@ -135,3 +136,30 @@ def test_activation_energy_factor_takes_the_midpoint_map_temperature(oracle_mod)
     kB = 1.380649e-23 / 1.602176634e-19
     dEa = -kB * T * np.log(k1[wire] / k0[wire])
     assert np.allclose(dEa, sd * oracle_mod.normal_z(mc["seed"], 2, g.n_res, 4)[wire], rtol=0, atol=1e-15)
+
+
+def test_die_temperature_offset_is_the_arrhenius_ratio(oracle_mod):
+    # one offset dT ~ N(0, sd) per sample (param 5, counter index 0): at a
+    # uniform map temperature every wire segment takes the same factor, the
+    # ratio of the Arrhenius diffusivity kappa = D0 exp(-Ea/k_B T) B Omega /
+    # (k_B T) at T + dT and at T; vias and sigma_crit untouched
+    from oracle import surrogate_oracle as SO
+    g = synth.pg_grid(11, n=24, via_every=8, pad_lattice=2, sink_scale=1.0, seg_range=(10, 23))
+    g = synth.Grid(**{**g.__dict__, "tmap": None, "node_T": None})
+    mat = synth.default_material()
+    wire = (g.res_is_via == 0) & (g.layer[g.res_a] == g.layer[g.res_b])
+    base = dict(seed=21, cov_kappa=0.2, cov_scrit=0.2)
+    for s in (0, 3, 7):
+        k0, s0 = oracle_mod.sample_xi(g, base, s, T_amb=350.0, Ea_eV=mat["Ea_eV"])
+        k1, s1 = oracle_mod.sample_xi(g, dict(base, sd_T_K=3.0), s, T_amb=350.0, Ea_eV=mat["Ea_eV"])
+        assert np.array_equal(s0, s1) and np.array_equal(k0[~wire], k1[~wire])
+        f = k1[wire] / k0[wire]
+        dT = 3.0 * oracle_mod.normal_z(21, s, 1, 5)[0]
+        want = SO.kappa0(350.0 + dT, mat) / SO.kappa0(350.0, mat)
+        assert np.allclose(f, want, rtol=1e-12), (s, dT)
+        assert (want > 1.0) == (dT > 0.0)            # a hotter die diffuses faster
+    # the offsets over many samples: mean 0, spread sd
+    z = np.array([oracle_mod.normal_z(21, s, 1, 5)[0] for s in range(4000)])
+    assert abs(z.mean()) < 4 / math.sqrt(z.size) and abs(z.std() - 1.0) < 0.04
+    with pytest.raises(ValueError):
+        oracle_mod.sample_xi(g, dict(base, sd_T_K=3.0), 0, T_amb=350.0)
