@@ -211,6 +211,23 @@ typedef struct {
                                     network (pg400 1.4, the full chip 2.2 in cold-solve iterations);
                                     em_autotune times 1.4, 1.8 and 2.2 when it is 0.  Same solution
                                     to cg_rtol. */
+    double ss_tol;               /* em_run_to_ttf: steady-state skipping, 0 = off, else in
+                                    (0, 1e-2].  After each aging interval a chain-stepped
+                                    (tree, sample) instance without voids stops being stepped
+                                    when the band its stress can still move in under the
+                                    present currents is at most ss_tol x sigma_crit (nominal)
+                                    wide and keeps every node below its critical stress.  The
+                                    band is exact for backward Euler with constant forcing:
+                                    each step maps the distance to the steady state by a
+                                    nonnegative matrix with unit row sums, and that distance
+                                    follows, up to a constant, from the residual's sums over
+                                    the chain.  So a skipped instance could not have
+                                    nucleated, and its frozen stress stays within
+                                    ss_tol x sigma_crit of the stepped one's at every node (up
+                                    to the stepping's rounding).  An IR re-solve that changes
+                                    its sample's conductances wakes it; every instance is
+                                    awake again when the call returns.  Not with a learned
+                                    screen attached. */
 } em_run_params;
 
 /* Monte Carlo (Sec. IV-F): unit-mean lognormal multipliers with coefficient
@@ -306,6 +323,9 @@ typedef struct {
                               cap; the cap bounds the per-instance void records) */
     int32_t n_screen_rerun;/* samples of the last em_run_to_ttf re-run without the learned screen
                               after a violation */
+    int64_t n_ss_skipped;  /* steady-state skipping: instances skipped in the last em_run_to_ttf
+                              (an instance woken and skipped again counts twice) */
+    int64_t n_ss_woken;    /* of those, woken by an IR re-solve of their sample */
 } em_info;
 
 /* Allocator hook: device memory for the batch (e.g. a framework's caching

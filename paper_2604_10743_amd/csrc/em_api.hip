@@ -117,6 +117,9 @@ struct em_batch {
     int n_redecided = 0;
     int n_screen_rerun = 0;
     long long rerun_node_steps = 0;     // node-steps of the re-runs of the last em_run_to_ttf
+    // steady-state skipping (em_run_params.ss_tol > 0)
+    bool ss_ready = false;
+    long long n_ss_skipped = 0, n_ss_woken = 0;
 };
 
 // Deep host copy of a netlist descriptor (the FP64 re-run builds a batch from it).
@@ -354,9 +357,10 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
         r->ir_launch < 0 || r->ir_launch > 3 || r->joule < 0 || r->joule > 1 ||
         !(r->dt_growth >= 0) || !std::isfinite(r->dt_growth) || !(r->guard_band >= 0) || !(r->guard_band < 1) ||
         !(r->guard_ttf >= 0) || !std::isfinite(r->guard_ttf) ||
-        !(r->amg_alpha == 0.0 || (r->amg_alpha >= 1.0 && r->amg_alpha <= 4.0)))
+        !(r->amg_alpha == 0.0 || (r->amg_alpha >= 1.0 && r->amg_alpha <= 4.0)) ||
+        !(r->ss_tol >= 0) || !(r->ss_tol <= 1e-2))
         return fail(b, EM_ERR_ARG, "bad run parameters (max_voids_per_tree <= 4, 0 <= guard_band < 1, "
-                                   "guard_ttf >= 0, amg_alpha 0 or in [1, 4])");
+                                   "guard_ttf >= 0, amg_alpha 0 or in [1, 4], 0 <= ss_tol <= 1e-2)");
     if (r->joule) {
         const double tv[] = {m->k_cu, m->k_ild, m->t_ild};
         if (!finite_all(tv, 3) || !(m->k_cu > 0) || !(m->k_ild > 0) || !(m->t_ild > 0))
@@ -1555,6 +1559,8 @@ em_status em_get_info(em_batch *b, em_info *info)
     info->surrogate_ms = b->sur_ms;
     info->n_redecided = b->n_redecided;
     info->n_screen_rerun = b->n_screen_rerun;
+    info->n_ss_skipped = b->n_ss_skipped;
+    info->n_ss_woken = b->n_ss_woken;
     {
         const size_t IS = (size_t)b->n_trees * b->S;
         std::vector<int> sup(IS);
@@ -1707,6 +1713,40 @@ static em_status rerun_samples(em_batch *b, const std::vector<int> &pick, em_ttf
     return EM_OK;
 }
 
+// Steady-state skipping: its flags and counters (allocated on first use).
+static em_status ss_begin(em_batch *b)
+{
+    Dev &d = b->d;
+    hipStream_t st = b->stream;
+    const size_t IS = (size_t)d.n_trees * d.S;
+    if (!b->ss_ready) {
+        d.ss_skip = (uint8_t *)dalloc(b, IS);
+        d.ss_cnt = (unsigned int *)dalloc(b, 8);
+        if (!d.ss_skip || !d.ss_cnt) return fail(b, EM_ERR_OOM, "steady-state skipping buffers");
+        b->ss_ready = true;
+    }
+    HIPCHK(b, hipMemsetAsync(d.ss_skip, 0, IS, st));
+    HIPCHK(b, hipMemsetAsync(d.ss_cnt, 0, 8, st));
+    b->n_ss_skipped = b->n_ss_woken = 0;
+    return EM_OK;
+}
+
+// Wakes every skipped instance (the run's end: em_stress_step and a later run
+// step them again).
+static em_status ss_end(em_batch *b)
+{
+    Dev &d = b->d;
+    unsigned int c[2] = {0, 0};
+    HIPCHK(b, hipMemcpyAsync(c, d.ss_cnt, 8, hipMemcpyDeviceToHost, b->stream));
+    launch_ss_wake(d, true, b->stream);
+    LAUNCHCHK(b);
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    b->n_ss_skipped = c[0];
+    b->n_ss_woken = c[1];
+    b->act_dirty = true;
+    return EM_OK;
+}
+
 em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
 {
     if (!b || !out) return fail(b, EM_ERR_ARG, "null output");
@@ -1714,6 +1754,9 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
     const bool graded = b->run.dt_growth > 0 && b->run.dt_growth != 1.0;
     if (graded && b->sur)
         return fail(b, EM_ERR_STATE, "a graded time grid cannot be combined with the learned screen");
+    const bool ssk = b->run.ss_tol > 0;
+    if (ssk && b->sur)
+        return fail(b, EM_ERR_STATE, "steady-state skipping cannot be combined with the learned screen");
     Dev &d = b->d;
     hipStream_t st = b->stream;
     const int S = b->S;
@@ -1740,10 +1783,15 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
         if (rc != EM_OK) return rc;
     }
     const size_t cnt_off = (std::max<size_t>(S, 8) + 15) & ~(size_t)15;
-    uint8_t *h = pinned(b, cnt_off + 32);
+    uint8_t *h = pinned(b, cnt_off + 48);
     if (!h) return fail(b, EM_ERR_OOM, "pinned host buffer");
     unsigned int *hcnt = (unsigned int *)(h + cnt_off);
-    unsigned int n_activated = 0;
+    unsigned int *hss = hcnt + 8;
+    unsigned int n_activated = 0, ss_seen = 0;
+    if (ssk) {
+        if ((rc = ss_begin(b)) != EM_OK) return rc;
+        hss[0] = hss[1] = 0;
+    }
     int done = 0, k = 0;
     double t_now = 0.0;                   // time at the end of the last interval
     while (done < n_steps) {
@@ -1775,7 +1823,12 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
             HIPCHK(b, hipMemcpyAsync(hcnt, d.sur_cnt, 32, hipMemcpyDeviceToHost, st));
         }
         HIPCHK(b, hipMemcpyAsync(h, d.sample_active, S, hipMemcpyDeviceToHost, st));
+        if (ssk) HIPCHK(b, hipMemcpyAsync(hss, d.ss_cnt, 8, hipMemcpyDeviceToHost, st));
         HIPCHK(b, hipStreamSynchronize(st));
+        if (ssk && hss[0] + hss[1] != ss_seen) {       // skips or wakes: rebuild the lane table
+            ss_seen = hss[0] + hss[1];
+            b->act_dirty = true;
+        }
         int n_active = 0;
         for (int s = 0; s < S; ++s) n_active += h[s] != 0;
         if (n_active == 0) break;
@@ -1791,6 +1844,7 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
         rc = timed_step(b, nst, done, !catch_up);
         if (rc != EM_OK) return rc;
         if (catch_up && (rc = sur_catch_up_end(b, k)) != EM_OK) return rc;
+        if (ssk) launch_ss_check(d, b->fp32, b->run.ss_tol * d.scrit, st);
         done += nst;
         t_now += nst * dt_k;
         ++k;
@@ -1799,10 +1853,12 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
         fold_timers(b);
         rc = timed_ir(b);
         if (rc != EM_OK) return rc;
+        if (ssk) launch_ss_wake(d, false, st);      // samples whose currents changed
         launch_ttf_update(d, fail_frac, k, graded ? t_now : done * b->run.dt, st);
         LAUNCHCHK(b);
     }
     b->n_outer_done = k;
+    if (ssk && (rc = ss_end(b)) != EM_OK) return rc;
     if ((rc = set_step_size(b, b->run.dt)) != EM_OK) return rc;   // em_stress_step steps with dt
     // per-sample results
     std::vector<double> ttf(S), fd(S), idr(S);
@@ -1889,6 +1945,8 @@ em_status em_reset(em_batch *b)
     b->n_redecided = 0;
     b->n_screen_rerun = 0;
     b->rerun_node_steps = 0;
+    b->n_ss_skipped = b->n_ss_woken = 0;
+    if (b->ss_ready) HIPCHK(b, hipMemsetAsync(d.ss_skip, 0, IS, st));
     b->live_dirty = true;
     b->any_open = false;
     b->ir_valid = false;

@@ -140,6 +140,9 @@ struct Dev {
     int *act_list;                      // [inst] instances activated by the last activation check
     unsigned int *sur_cnt;              // [8] deferred, activated, late, violations, def_list length,
                                         //     act_list length
+    // ---- steady-state skipping (allocated when em_run_params.ss_tol > 0) ----
+    uint8_t *ss_skip;                   // [inst] skipped at its steady state
+    unsigned int *ss_cnt;               // [2] skips, wakes (cumulative)
 };
 
 // Aggregation multigrid preconditioner of the IR solve.  Level 0 is the nodal
@@ -234,6 +237,8 @@ void launch_node_T(const Dev &d, hipStream_t st);
 void launch_joule_T(const Dev &d, const double *j, double *D, double *r, hipStream_t st);
 void launch_edge_static(const Dev &d, hipStream_t st);
 void launch_node_V(const Dev &d, bool fp32, hipStream_t st);   // also per-tree volume
+void launch_ss_check(const Dev &d, bool fp32, double tol_abs, hipStream_t st);  // skip converged chain instances
+void launch_ss_wake(const Dev &d, bool all, hipStream_t st);  // wake those of re-solved samples (all: every one)
 void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, double cov_r, double cov_l,
                   double sd_ea, double sd_T, hipStream_t st);
 void launch_node_sc(const Dev &d, bool fp32, hipStream_t st);

@@ -1651,7 +1651,265 @@ EM_KERNEL void k_catchup_done(Dev d, int step_lim)
     d.inst_active[inst] = 1;
 }
 
+// ------------------------------------------------------------------------
+// Steady-state skipping.  Between two IR solves an instance without voids
+// steps C s' = f - A s by backward Euler: C = diag(V) the node volumes, A the
+// Laplacian of the edge conductances g (positive).  A step of any size maps
+// the distance e = s - s_inf to the steady state by (C + dt A)^-1 C, a
+// nonnegative matrix (C + dt A is an M-matrix) with unit row sums (A 1 = 0),
+// so every later e lies componentwise within [min e_n, max e_n].  On a tree e
+// is known up to a constant from the residual: across the edge above a
+// subtree, g (e_child - e_parent) is the sum of A s - f over the subtree.  On
+// a chain (node i's parent i - 1) with r = dt (f - A s), the edge (i - 1, i)
+// carries dt g (e_i - e_i-1) = sum of r over the nodes before i, and the
+// potential P_i = sum over edges up to i of that sum / (dt g) equals e + const.
+// Every later state then satisfies
+//   s_n,i - (P_i - min P) <= s_m,i <= s_n,i + (max P - P_i),
+// a band the steady state itself reaches (exact arithmetic; the stepping adds
+// its rounding).  The forcing's total (zero but for rounding) is taken out in
+// proportion to V first, as the stepping's content projection does; dt*f and
+// dt*g are those the chain kernel steps with (the state's precision), the
+// sums are FP64.  Skipped: an active chain instance without voids whose
+// band is within tol_abs and keeps every node below its critical stress.
+//
+// Two launch forms.  With 64 samples or more, one lane per instance and the
+// wavefront over 64 consecutive samples of one tree: every node's state,
+// forcing and diffusivity multiplier is one coalesced load, and each lane
+// walks its chain in order, so the prefix sums are running sums.  With fewer
+// samples, the chain kernel's lane table (each lane its block of chain_m
+// consecutive nodes, instances never straddling a workgroup): the lane's
+// loads issued together, then segmented scans over the instance's lanes in
+// LDS.
+// ------------------------------------------------------------------------
+template <typename R>
+EM_KERNEL void k_ss_check_s(Dev d, double tol_abs)
+{
+    constexpr int B = 8;                         // nodes whose loads are issued together
+    const int lane = threadIdx.x & 63;
+    const int S = d.S, SW = (S + 63) / 64;
+    const long long w = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (w >= (long long)d.n_trees * SW) return;
+    const int t = (int)(w / SW), s0 = (int)(w - (long long)t * SW) * 64;
+    if (!d.tree_chain[t]) return;
+    const int s = min(s0 + lane, S - 1);          // lanes past S repeat the last sample, unused
+    const size_t inst = (size_t)t * S + s;
+    const bool act = s0 + lane < S && d.inst_active[inst] && d.sample_active[s] && d.nv[inst] == 0;
+    if (!__any(act)) return;
+    const R *sig = (const R *)d.sigma, *fv = (const R *)d.dtf, *sc = (const R *)d.sc, *Vr = (const R *)d.Vr;
+    const float *slo = d.sig_lo;
+    auto sv = [&](int i) -> double {
+        const size_t x = (size_t)i * S + s;
+        double v = (double)sig[x];
+        if (slo) v += (double)slo[x];
+        return v;
+    };
+    auto dtg = [&](int i) -> double {        // edge (i - 1, i)
+        return (double)(R)(d.dt * d.xi_k[(size_t)d.seg[i] * S + s] * d.g0[i]);
+    };
+    const int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
+    double fs = 0.0, vs = 0.0;
+    for (int c = i0; c < i1; c += B) {
+        double a[B], v[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            a[k] = c + k < i1 ? (double)fv[(size_t)(c + k) * S + s] : 0.0;
+            v[k] = c + k < i1 ? (double)Vr[c + k] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            fs += a[k];
+            vs += v[k];
+        }
+    }
+    const double fm = fs / vs;
+    double pre = 0.0, lp = 0.0, pmax = -INFINITY, pmin = INFINITY, mmax = -INFINITY;
+    double sp = 0.0, gl = 0.0, si = sv(i0);
+    for (int c = i0; c < i1; c += B) {
+        // nodes c .. c+B-1: their right neighbours' states and edges, drive,
+        // volume and critical stress
+        double sn[B], gr[B], f[B], v[B], q[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int i = c + k;
+            const bool in = i < i1, nx = i + 1 < i1;
+            sn[k] = nx ? sv(i + 1) : 0.0;
+            gr[k] = nx ? dtg(i + 1) : 0.0;
+            f[k] = in ? (double)fv[(size_t)i * S + s] : 0.0;
+            v[k] = in ? (double)Vr[i] : 0.0;
+            q[k] = in ? (double)sc[(size_t)i * S + s] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int i = c + k;
+            if (i >= i1) break;
+            double r = f[k] - v[k] * fm + gr[k] * (sn[k] - si);
+            if (i > i0) {
+                r += gl * (sp - si);
+                lp += pre / gl;
+            }
+            pre += r;
+            pmax = fmax(pmax, lp);
+            pmin = fmin(pmin, lp);
+            mmax = fmax(mmax, si - q[k] - lp);
+            sp = si;
+            si = sn[k];
+            gl = gr[k];
+        }
+    }
+    if (act && pmax - pmin <= tol_abs && mmax + pmax < 0.0) {
+        d.inst_active[inst] = 0;
+        d.ss_skip[inst] = 1;
+        atomicAdd(&d.ss_cnt[0], 1u);
+    }
+}
+
+constexpr int SS_WG_MAX = 1024, SS_M_MAX = CHAIN_M32W > CHAIN_M64 ? CHAIN_M32W : CHAIN_M64;
+
+template <typename R>
+__global__ __launch_bounds__(SS_WG_MAX) void k_ss_check(Dev d, double tol_abs)
+{
+    __shared__ double sa[SS_WG_MAX], sb[SS_WG_MAX];
+    const int WG = blockDim.x, lane = threadIdx.x, S = d.S, M = d.chain_m;
+    const size_t gl = (size_t)blockIdx.x * WG + lane;
+    const int inst = d.lane_inst[gl];
+    int s = 0, i0 = 0, i1 = 0, start = 0, cnt = 0, lo = lane, hi = lane;
+    bool act = false;
+    if (inst >= 0) {
+        const int t = inst / S;
+        s = inst - t * S;
+        i0 = d.tree_off[t];
+        i1 = d.tree_off[t + 1];
+        const int kb = d.lane_blk[gl];
+        start = i0 + kb * M;
+        cnt = min(M, i1 - start);
+        lo = lane - kb;
+        hi = lo + (i1 - i0 + M - 1) / M - 1;
+        act = d.inst_active[inst] && d.sample_active[s] && d.nv[inst] == 0;
+    }
+    if (!act) cnt = 0;
+    // segmented inclusive scans of two values over the lanes [lo, lane]
+    // (sums, or maxima), and the segment's results at its last lane
+    auto scan2 = [&](double &x, double &y, bool mx) {
+        sa[lane] = x;
+        sb[lane] = y;
+        __syncthreads();
+        for (int dd = 1; dd < WG; dd <<= 1) {
+            const bool in = lane - dd >= lo;
+            const double u = in ? sa[lane - dd] : 0.0, w = in ? sb[lane - dd] : 0.0;
+            __syncthreads();
+            if (in) {
+                x = mx ? fmax(x, u) : x + u;
+                y = mx ? fmax(y, w) : y + w;
+            }
+            sa[lane] = x;
+            sb[lane] = y;
+            __syncthreads();
+        }
+    };
+    auto totals = [&](double &x, double &y) {
+        x = sa[hi];
+        y = sb[hi];
+        __syncthreads();
+    };
+    const R *sig = (const R *)d.sigma, *fv = (const R *)d.dtf, *sc = (const R *)d.sc, *Vr = (const R *)d.Vr;
+    const float *slo = d.sig_lo;
+    auto sv = [&](int i) -> double {
+        const size_t x = (size_t)i * S + s;
+        double v = (double)sig[x];
+        if (slo) v += (double)slo[x];
+        return v;
+    };
+    auto dtg = [&](int i) -> double {        // edge (i - 1, i)
+        return (double)(R)(d.dt * d.xi_k[(size_t)d.seg[i] * S + s] * d.g0[i]);
+    };
+    // the lane's nodes and their neighbours: xs[j + 1] = state of node
+    // start + j, xs[0] and xs[cnt + 1] the neighbours (0 past the chain's
+    // ends, where ge = 0); ge[j] = dt g of the edge (start + j - 1, start + j)
+    double xs[SS_M_MAX + 2], ge[SS_M_MAX + 1], fr[SS_M_MAX], vv[SS_M_MAX], cr[SS_M_MAX];
+#pragma unroll
+    for (int j = 0; j <= SS_M_MAX; ++j) {
+        const int i = start - 1 + j;
+        xs[j] = (j <= cnt + 1 && i >= i0 && i < i1 && cnt > 0) ? sv(i) : 0.0;
+        ge[j] = (j <= cnt && start + j > i0 && start + j < i1 && cnt > 0) ? dtg(start + j) : 0.0;
+    }
+    xs[SS_M_MAX + 1] = (cnt == SS_M_MAX && start + cnt < i1) ? sv(start + cnt) : 0.0;
+#pragma unroll
+    for (int j = 0; j < SS_M_MAX; ++j) {
+        const size_t x = (size_t)(start + j) * S + s;
+        fr[j] = j < cnt ? (double)fv[x] : 0.0;
+        vv[j] = j < cnt ? (double)Vr[start + j] : 0.0;
+        cr[j] = j < cnt ? (double)sc[x] : 0.0;
+    }
+    double fs = 0.0, vs = 0.0, rs = 0.0;
+#pragma unroll
+    for (int j = 0; j < SS_M_MAX; ++j)
+        if (j < cnt) {
+            fs += fr[j];
+            vs += vv[j];
+            fr[j] += ge[j] * (xs[j] - xs[j + 1]) + ge[j + 1] * (xs[j + 2] - xs[j + 1]);   // dt f - dt A s
+            rs += fr[j];
+        }
+    double ft = fs, vt = vs;
+    scan2(ft, vt, false);
+    totals(ft, vt);
+    const double fm = act ? ft / vt : 0.0;
+    const double rl = rs - fm * vs;
+    double rinc = rl, dummy = 0.0;
+    scan2(rinc, dummy, false);
+    double pre = rinc - rl;                    // sum of r' over the instance's nodes before this lane's
+    double lp = 0.0, lmax = -INFINITY, lmin = INFINITY, lm = -INFINITY;
+#pragma unroll
+    for (int j = 0; j < SS_M_MAX; ++j)
+        if (j < cnt) {
+            if (start + j > i0) lp += pre / ge[j];
+            pre += fr[j] - vv[j] * fm;
+            lmax = fmax(lmax, lp);
+            lmin = fmin(lmin, lp);
+            lm = fmax(lm, xs[j + 1] - cr[j] - lp);
+        }
+    double pinc = lp;
+    scan2(pinc, dummy, false);
+    const double cp = pinc - lp;               // the potential where this lane's nodes start
+    double pmax = cp + lmax, mmax = lm - cp;   // largest P; largest s - sigma_crit - P
+    scan2(pmax, mmax, true);
+    totals(pmax, mmax);
+    double npmin = -(cp + lmin), unused = -INFINITY;
+    scan2(npmin, unused, true);
+    totals(npmin, unused);
+    if (act && lane == lo && pmax + npmin <= tol_abs && mmax + pmax < 0.0) {
+        d.inst_active[inst] = 0;
+        d.ss_skip[inst] = 1;
+        atomicAdd(&d.ss_cnt[0], 1u);
+    }
+}
+
+EM_KERNEL void k_ss_wake(Dev d, int all)
+{
+    const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+    if (inst >= d.n_trees * d.S) return;
+    if (!d.ss_skip[inst] || !(all || d.g_chg_s[inst % d.S])) return;
+    d.ss_skip[inst] = 0;
+    d.inst_active[inst] = 1;
+    atomicAdd(&d.ss_cnt[1], 1u);
+}
+
 // ---------------------------- launchers ---------------------------------
+void launch_ss_check(const Dev &d, bool fp32, double tol_abs, hipStream_t st)
+{
+    if (d.n_chain_wg <= 0 || d.chain_wg <= 0 || d.chain_wg > SS_WG_MAX) return;
+    if (d.S >= 64) {
+        const int nb = (int)(((long long)d.n_trees * ((d.S + 63) / 64) + 3) / 4);
+        if (fp32) k_ss_check_s<float><<<nb, 256, 0, st>>>(d, tol_abs);
+        else k_ss_check_s<double><<<nb, 256, 0, st>>>(d, tol_abs);
+        return;
+    }
+    if (fp32) k_ss_check<float><<<d.n_chain_wg, d.chain_wg, 0, st>>>(d, tol_abs);
+    else k_ss_check<double><<<d.n_chain_wg, d.chain_wg, 0, st>>>(d, tol_abs);
+}
+void launch_ss_wake(const Dev &d, bool all, hipStream_t st)
+{
+    k_ss_wake<<<nblocks((long long)d.n_trees * d.S), 256, 0, st>>>(d, all ? 1 : 0);
+}
 void launch_node_T(const Dev &d, hipStream_t st)
 {
     k_node_T<<<nblocks(d.ns), 256, 0, st>>>(d);

@@ -1,0 +1,96 @@
+"""Steady-state skipping (em_run_params.ss_tol) against the run without it
+and against the FP64 oracle.  Between IR solves backward Euler maps the
+distance to the steady state by a nonnegative matrix with unit row sums, so
+an instance whose remaining band (from the residual's prefix sums) is within
+ss_tol x sigma_crit and below every node's critical stress cannot nucleate,
+and its frozen stress stays within the band: results equal those of the
+full run, stress within the tolerance, with fewer node-steps."""
+import numpy as np
+import pytest
+
+import ttf_check
+
+from paper_2604_10743_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def em():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2604_10743_amd as P
+    return P
+
+
+def _run(em, g, mat, rn, mc, picks):
+    B = em.Batch(g, mat, rn, mc)
+    res = B.run_to_ttf()
+    info = B.info()
+    st = {s: B.stress(s) for s in picks}
+    segs = {s: B.failed_segments(s) for s in picks}
+    ev = B.events()
+    B.close()
+    return res, info, st, segs, ev
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_skipping_matches_full_run_and_oracle(em, oracle_mod, prec):
+    """The 96x96 sparse-via grid with the immortality screen off (every tree
+    stepped), FP32 and FP64 batches: node-steps drop, every result and event
+    is that of the full run, and the stress stays within ss_tol x sigma_crit
+    at every node; three samples against the oracle."""
+    g, mat, rn, mc = synth.workload("mc_grid")
+    S = 64 if prec == 1 else 32
+    mc = dict(mc, n_samples=S)
+    rn = dict(rn, prec=prec, screen=0)
+    picks = list(range(S))
+    print(f"mc_grid {S} samples prec {prec} screen off: full run", flush=True)
+    r0, i0, st0, _, ev0 = _run(em, g, mat, rn, mc, picks)
+    print("with steady-state skipping", flush=True)
+    rs = dict(rn, ss_tol=TOL)
+    r1, i1, st1, segs1, ev1 = _run(em, g, mat, rs, mc, picks)
+    print(f"skipped {i1['n_ss_skipped']} woken {i1['n_ss_woken']}; node-steps "
+          f"{i1['node_steps']} vs {i0['node_steps']}", flush=True)
+    assert i1["n_ss_skipped"] > 0
+    assert i1["n_ss_woken"] > 0
+    assert i1["node_steps"] < 0.9 * i0["node_steps"]
+    n_fail = 0
+    for s in range(S):
+        a, b = r0[s], r1[s]
+        assert a["failed"] == b["failed"], s
+        assert a["outer_idx"] == b["outer_idx"], s
+        assert a["n_nucleated_trees"] == b["n_nucleated_trees"], s
+        assert abs(a["ttf_s"] - b["ttf_s"]) <= 1e-6 * abs(a["ttf_s"]) or (np.isnan(a["ttf_s"]) and np.isnan(b["ttf_s"])), s
+        assert abs(a["final_drop"] - b["final_drop"]) <= 1e-6 * abs(a["final_drop"]), s
+        n_fail += a["failed"]
+    assert sorted(map(tuple, ev0[:, :4].tolist())) == sorted(map(tuple, ev1[:, :4].tolist()))
+    scrit = mat["sigma_crit"]
+    worst = max(float(np.max(np.abs(st0[s] - st1[s]))) for s in picks)
+    print(f"largest stress difference {worst:.4g} Pa (bound {TOL * scrit:.4g})", flush=True)
+    assert worst <= 1.01 * TOL * scrit
+    assert n_fail > 0
+    # the skipped run against the oracle (screen off), at the bar of the full run
+    topo = oracle_mod.topology(g, rn["intervals_per_seg"])
+    failed = [s for s in range(S) if r1[s]["failed"]]
+    alive = [s for s in range(S) if not r1[s]["failed"]]
+    for s in failed[:2] + alive[:1]:
+        print(f"oracle sample {s}", flush=True)
+        ref = oracle_mod.run_sample(g, mat, rs, mc, s, topo=topo)
+        ttf_check.check(r1[s], ref, segs1[s], prec, rs, s)
+
+
+def test_skipping_is_refused_with_the_learned_screen(em):
+    g, mat, rn, mc = synth.workload("mc_grid")
+    mc = dict(mc, n_samples=4)
+    B = em.Batch(g, mat, dict(rn, ss_tol=TOL), mc)
+    mlp = em.MLP()
+    try:
+        B.surrogate_screen(mlp, 2.0)
+        with pytest.raises(em.EmError):
+            B.run_to_ttf()
+    finally:
+        mlp.close()
+        B.close()
