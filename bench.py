@@ -613,6 +613,50 @@ def voids_leg(args, name="pg400", sigma_crit=200e6, screen=1):
             "n_failed_segs": r["n_failed_segs"]}
 
 
+def skip_leg(args, name, n_samples=None, tol=1e-6, reps=3):
+    """Steady-state skipping (ss_tol) against the full run: the immortality
+    screen off (every tree stepped), the same batch run to the horizon with
+    and without skipping (best of reps each, after an untimed run), results
+    compared sample by sample and the largest stress difference reported."""
+    import numpy as np
+    import torch
+    import paper_2604_10743_amd as P
+    from paper_2604_10743_amd import synth
+
+    g, mat, run, mc = synth.workload(name)
+    mc = dict(mc, n_samples=n_samples) if (mc is not None and n_samples) else None
+    legs = {}
+    for label, ss in (("full", 0.0), ("skip", tol)):
+        B = P.Batch(g, mat, dict(run, prec=args.prec, screen=0, ss_tol=ss), mc)
+        B.autotune(run["ir_every"])
+        B.run_to_ttf()
+        best, res = 1e30, None
+        for _ in range(reps):
+            B.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = B.run_to_ttf()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        i = B.info()
+        st = [B.stress(s) for s in range(min(len(res), 8))]
+        B.close()
+        legs[label] = (best, res, i, st)
+    (tf, rf, i_f, sf), (ts, rs, i_s, ss_) = legs["full"], legs["skip"]
+    same = all(a["failed"] == b["failed"] and a["outer_idx"] == b["outer_idx"] and
+               a["n_nucleated_trees"] == b["n_nucleated_trees"] and
+               abs(a["final_drop"] - b["final_drop"]) <= 1e-6 * abs(a["final_drop"]) for a, b in zip(rf, rs))
+    dmax = max(float(np.max(np.abs(a - b))) for a, b in zip(sf, ss_))
+    return {"workload": f"{name}{f' x {len(rf)} Monte Carlo samples' if mc else ''}, screen off, "
+                        f"FP32, run to the horizon, ss_tol {tol:g}",
+            "full_ms": tf * 1e3, "skip_ms": ts * 1e3, "speedup": tf / ts,
+            "node_steps_full": i_f["node_steps"], "node_steps_skip": i_s["node_steps"],
+            "full_node_steps_per_s_at_skip_time": i_f["node_steps"] / ts,
+            "n_skipped": i_s["n_ss_skipped"], "n_woken": i_s["n_ss_woken"],
+            "results_identical": bool(same), "max_stress_diff_Pa": dmax,
+            "stress_bound_Pa": tol * mat["sigma_crit"]}
+
+
 def thermal_leg(args):
     """Equal-average thermal maps (the paper's thermal-profile observation):
     the mc_grid network under a uniform map, four hotspots over the wires of
@@ -682,6 +726,7 @@ def main():
     ap.add_argument("--only-headline", action="store_true", help="run the headline measurement only")
     ap.add_argument("--no-sur", action="store_true", help="skip the learned-screen leg")
     ap.add_argument("--only-sur", action="store_true", help="run the learned-screen leg only")
+    ap.add_argument("--only-skip", action="store_true", help="run the steady-state skipping legs only")
     ap.add_argument("--sur-grids", type=int, default=24, help="label grids for the learned screen")
     ap.add_argument("--sur-label-samples", type=int, default=1024)
     ap.add_argument("--sur-steps", type=int, default=3000, help="Adam steps of the screen model")
@@ -727,6 +772,11 @@ def main():
         print(json.dumps({"surrogate": surrogate_leg(args)}), flush=True)
         return
 
+    if args.only_skip:
+        print(json.dumps({"fullchip_skip": skip_leg(args, "fullchip"),
+                          "mc_skip": skip_leg(args, "mc_grid", n_samples=256)}), flush=True)
+        return
+
     out = stepping_leg(args, args.workload, headline=True)
     log(f"bench: headline ({args.workload}) done")
     if args.only_headline:
@@ -741,6 +791,8 @@ def main():
     log("bench: fullchip with voids done")
     out["branched"] = branched_leg(args)
     log("bench: branched trees done")
+    out["fullchip_skip"] = skip_leg(args, "fullchip")
+    log("bench: fullchip steady-state skipping done")
     if not args.no_mc:
         out["fullchip_mc"] = mc_leg(args, "fullchip", oracle=False, plain=False, n_samples=args.fc_samples)
         log("bench: fullchip mc done")
@@ -751,6 +803,8 @@ def main():
         out["mc_joule"] = mc_leg(args, "mc_grid", oracle=False, plain=False, joule=True)
         out["mc_die_T"] = mc_leg(args, "mc_grid", oracle=False, plain=False, var={"sd_T_K": 3.0})
         log("bench: mc (mc_mesh, variations) done")
+        out["mc_skip"] = skip_leg(args, "mc_grid", n_samples=256)
+        log("bench: mc_grid steady-state skipping done")
         out["thermal_sweep"] = thermal_leg(args)
         log("bench: thermal sweep done")
     if not args.no_sur:
