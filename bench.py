@@ -657,6 +657,50 @@ def skip_leg(args, name, n_samples=None, tol=1e-6, reps=3):
             "stress_bound_Pa": tol * mat["sigma_crit"]}
 
 
+def krylov_leg(args, name, n_samples=None, q=4, reps=3):
+    """Reduced (extended rational Krylov) stepping of the long chains against
+    exact elimination: the immortality screen off, the same batch run to the
+    horizon with krylov_q = q and without (best of reps each, after an
+    untimed run), results and stress compared."""
+    import numpy as np
+    import torch
+    import paper_2604_10743_amd as P
+    from paper_2604_10743_amd import synth
+
+    g, mat, run, mc = synth.workload(name)
+    mc = dict(mc, n_samples=n_samples) if (mc is not None and n_samples) else None
+    legs = {}
+    for label, kq in (("exact", 0), ("krylov", q)):
+        B = P.Batch(g, mat, dict(run, prec=args.prec, screen=0, krylov_q=kq), mc)
+        B.autotune(run["ir_every"])
+        B.run_to_ttf()
+        best, res = 1e30, None
+        for _ in range(reps):
+            B.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = B.run_to_ttf()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        i = B.info()
+        st = [B.stress(s) for s in range(min(len(res), 8))]
+        B.close()
+        legs[label] = (best, res, i, st)
+    (te, re_, ie, se), (tk, rk, ik, sk) = legs["exact"], legs["krylov"]
+    same = all(a["failed"] == b["failed"] and a["outer_idx"] == b["outer_idx"] for a, b in zip(re_, rk))
+    drop_err = max(abs(a["final_drop"] - b["final_drop"]) / a["final_drop"] for a, b in zip(re_, rk))
+    srel = max(float(np.max(np.abs(a - b)) / np.max(np.abs(a))) for a, b in zip(se, sk))
+    return {"workload": f"{name}{f' x {len(re_)} Monte Carlo samples' if mc else ''}, screen off, "
+                        f"FP32, run to the horizon, krylov_q {q}",
+            "exact_ms": te * 1e3, "krylov_ms": tk * 1e3, "speedup": te / tk,
+            "exact_step_ms": ie["step_kernel_ms"], "krylov_step_ms": ik["step_kernel_ms"],
+            "node_steps_exact": ie["node_steps"], "node_steps_exact_in_krylov_run": ik["node_steps"],
+            "krylov_node_steps": ik["krylov_node_steps"], "bases_built": ik["n_krylov_bases"],
+            "reduced_intervals": ik["n_krylov_intervals"], "fallbacks": ik["n_krylov_fallbacks"],
+            "decisions_identical": bool(same), "max_final_drop_rel_err": drop_err,
+            "max_stress_rel_err": srel}
+
+
 def thermal_leg(args):
     """Equal-average thermal maps (the paper's thermal-profile observation):
     the mc_grid network under a uniform map, four hotspots over the wires of
@@ -727,6 +771,7 @@ def main():
     ap.add_argument("--no-sur", action="store_true", help="skip the learned-screen leg")
     ap.add_argument("--only-sur", action="store_true", help="run the learned-screen leg only")
     ap.add_argument("--only-skip", action="store_true", help="run the steady-state skipping legs only")
+    ap.add_argument("--only-krylov", action="store_true", help="run the reduced (Krylov) stepping legs only")
     ap.add_argument("--sur-grids", type=int, default=24, help="label grids for the learned screen")
     ap.add_argument("--sur-label-samples", type=int, default=1024)
     ap.add_argument("--sur-steps", type=int, default=3000, help="Adam steps of the screen model")
@@ -777,6 +822,11 @@ def main():
                           "mc_skip": skip_leg(args, "mc_grid", n_samples=256)}), flush=True)
         return
 
+    if args.only_krylov:
+        print(json.dumps({"fullchip_krylov": krylov_leg(args, "fullchip"),
+                          "pg400_krylov": krylov_leg(args, "pg400")}), flush=True)
+        return
+
     out = stepping_leg(args, args.workload, headline=True)
     log(f"bench: headline ({args.workload}) done")
     if args.only_headline:
@@ -793,6 +843,9 @@ def main():
     log("bench: branched trees done")
     out["fullchip_skip"] = skip_leg(args, "fullchip")
     log("bench: fullchip steady-state skipping done")
+    out["fullchip_krylov"] = krylov_leg(args, "fullchip")
+    out["pg400_krylov"] = krylov_leg(args, "pg400")
+    log("bench: reduced (Krylov) stepping legs done")
     if not args.no_mc:
         out["fullchip_mc"] = mc_leg(args, "fullchip", oracle=False, plain=False, n_samples=args.fc_samples)
         log("bench: fullchip mc done")

@@ -228,6 +228,25 @@ typedef struct {
                                     its sample's conductances wakes it; every instance is
                                     awake again when the call returns.  Not with a learned
                                     screen attached. */
+    int32_t krylov_q;            /* extended rational Krylov reduced stepping (Sec. IV-E, Alg. 1):
+                                    0 = off, else the reduction order q in [1, 8] (at most 2q
+                                    basis columns).  Chain-stepped (tree, sample) instances of at
+                                    least max(3q, 30) nodes (eq. 27) without voids build a basis
+                                    of the block rational Krylov space over [K^-1 C s, K^-1 f],
+                                    K = s0 C - A, s0 = 1/t_s (eq. 26), and step the reduced
+                                    model by backward Euler, lifting the state at each call's
+                                    end; an interval whose lifted states could reach a critical
+                                    stress (bound: the reduced states' distance from the end
+                                    state) is stepped exactly instead and the basis dropped.  A
+                                    basis is kept while the drive is unchanged (an IR re-solve
+                                    that changes the sample's conductances, em_set_stress,
+                                    em_set_seg_state, em_inject_void, em_restore and em_reset
+                                    drop it).  An approximation of the stepping (the paper
+                                    reports under 0.05 % TTF / final-drop error); not with
+                                    ss_tol or a learned screen. */
+    double krylov_eta;           /* shift-time scale eta of eq. 26, t_s = eta L^2 / (pi^2 kappa)
+                                    with L the chain's length and kappa its volume-weighted
+                                    diffusivity; 0 means 1, else in (0, 100] */
 } em_run_params;
 
 /* Monte Carlo (Sec. IV-F): unit-mean lognormal multipliers with coefficient
@@ -326,6 +345,10 @@ typedef struct {
     int64_t n_ss_skipped;  /* steady-state skipping: instances skipped in the last em_run_to_ttf
                               (an instance woken and skipped again counts twice) */
     int64_t n_ss_woken;    /* of those, woken by an IR re-solve of their sample */
+    int64_t n_krylov_bases;      /* reduced stepping: bases built since creation or reset */
+    int64_t n_krylov_intervals;  /* instance-intervals taken in reduced form */
+    int64_t n_krylov_fallbacks;  /* instance-intervals handed back to exact stepping */
+    int64_t krylov_node_steps;   /* stress-node-steps advanced in reduced form (not in node_steps) */
 } em_info;
 
 /* Allocator hook: device memory for the batch (e.g. a framework's caching

@@ -32,7 +32,7 @@ import scipy.sparse as sp
 import scipy.sparse.csgraph as csg
 import scipy.sparse.linalg as spla
 
-from . import thermal
+from . import krylov, thermal
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
@@ -415,13 +415,25 @@ def run_sample(grid, mat, run, mc=None, sample=0, topo=None, keep_sim=False, max
     sim = SampleSim(grid, mat, run, topo, xi_k, xi_s, T_stress=T_stress, xi_r=xi_r)
     n_steps, K = int(run["n_steps"]), int(run["ir_every"])
     res = dict(sample=sample)
+    # reduced (extended rational Krylov) stepping of long chains (Sec. IV-E)
+    kq = int(run.get("krylov_q", 0))
+    keta = float(run.get("krylov_eta", 0.0)) or 1.0
+    bases = {}
+    active = np.ones(topo.n_trees, np.uint8)
+
+    def step_interval(nst, step0, dt):
+        if kq > 0:
+            krylov.interval(sim, topo, grid, bases, active, nst, step0, dt, kq, keta)
+        else:
+            sim.steps(nst, step0)
     if trees_only:
         sim.set_j(grid.seg_j)
         if run.get("screen", 0):
             tm, sm, _ = sim.screen()
             sim.set_active(tm)
+            active[:] = tm
             res["tree_mortal"], res["seg_mortal"] = tm, sm
-        sim.steps(n_steps, 0)
+        step_interval(n_steps, 0, float(run["dt"]))
         res.update(ttf=float("nan"), failed=0, outer_idx=0, init_drop=float("nan"),
                    final_drop=float("nan"))
     else:
@@ -431,8 +443,10 @@ def run_sample(grid, mat, run, mc=None, sample=0, topo=None, keep_sim=False, max
         if run.get("screen", 0):
             tm, sm, _ = sim.screen()
             sim.set_active(tm)
+            active[:] = tm
             res["tree_mortal"], res["seg_mortal"] = tm, sm
         fail = float(run["fail_frac"])
+        seg_prev = None
         # time grid: interval k (ir_every steps) steps with dt * dt_growth^k
         growth = float(run.get("dt_growth", 0.0)) or 1.0
         t_now = 0.0
@@ -451,10 +465,13 @@ def run_sample(grid, mat, run, mc=None, sample=0, topo=None, keep_sim=False, max
                 k += 1
                 nst = min(K, n_steps - done)
                 sim.set_dt(dt_k)
-                sim.steps(nst, done)
+                step_interval(nst, done, dt_k)
                 done += nst
                 t_now += nst * dt_k
                 dR, op = sim.seg_state()
+                if seg_prev is not None and (np.any(dR != seg_prev[0]) or np.any(op != seg_prev[1])):
+                    bases.clear()                       # new conductances: a new drive
+                seg_prev = (dR.copy(), op.copy())
                 u, I, j, dk = ir_solve(gs, R0 + dR, op)
                 drops.append(dk)
                 t = t_now

@@ -71,7 +71,8 @@ class RunParams(C.Structure):
                 ("stepper", C.c_int32), ("ir_precond", C.c_int32), ("ir_launch", C.c_int32),
                 ("chain_wg", C.c_int32), ("chain_occ", C.c_int32), ("joule", C.c_int32),
                 ("dt_growth", C.c_double), ("chain_m", C.c_int32), ("guard_band", C.c_double),
-                ("guard_ttf", C.c_double), ("amg_alpha", C.c_double), ("ss_tol", C.c_double)]
+                ("guard_ttf", C.c_double), ("amg_alpha", C.c_double), ("ss_tol", C.c_double),
+                ("krylov_q", C.c_int32), ("krylov_eta", C.c_double)]
 
 
 class MCParams(C.Structure):
@@ -99,7 +100,9 @@ class Info(C.Structure):
                 ("surrogate_ms", C.c_double), ("ir_sys_nodes", C.c_int32), ("ir_sys_edges", C.c_int32),
                 ("cg_sample_iters", C.c_int64), ("chain_m", C.c_int32), ("chain_wg", C.c_int32),
                 ("n_chain_wg", C.c_int32), ("n_redecided", C.c_int32), ("n_void_capped", C.c_int64),
-                ("n_screen_rerun", C.c_int32), ("n_ss_skipped", C.c_int64), ("n_ss_woken", C.c_int64)]
+                ("n_screen_rerun", C.c_int32), ("n_ss_skipped", C.c_int64), ("n_ss_woken", C.c_int64),
+                ("n_krylov_bases", C.c_int64), ("n_krylov_intervals", C.c_int64),
+                ("n_krylov_fallbacks", C.c_int64), ("krylov_node_steps", C.c_int64)]
 
 
 class TuneInfo(C.Structure):
@@ -220,7 +223,8 @@ class Batch:
                       guard_band=float(run.get("guard_band", 0.0)),
                       guard_ttf=float(run.get("guard_ttf", 0.0)),
                       amg_alpha=float(run.get("amg_alpha", 0.0)),
-                      ss_tol=float(run.get("ss_tol", 0.0)))
+                      ss_tol=float(run.get("ss_tol", 0.0)),
+                      krylov_q=int(run.get("krylov_q", 0)), krylov_eta=float(run.get("krylov_eta", 0.0)))
         mcp = None
         if mc is not None:
             mcp = MCParams(struct_size=C.sizeof(MCParams), n_samples=int(mc["n_samples"]),

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libem.so")
-SOURCES = ["em_api.hip", "k_tree.hip", "k_ir.hip", "k_chain.hip", "em_mlp.hip", "ir_amg.hip", "ir_wg.hip", "ir_chain.hip"]
+SOURCES = ["em_api.hip", "k_tree.hip", "k_ir.hip", "k_chain.hip", "em_mlp.hip", "ir_amg.hip", "ir_wg.hip", "ir_chain.hip",
+           "k_krylov.hip"]
 ARCH = os.environ.get("EM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -358,9 +358,13 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
         !(r->dt_growth >= 0) || !std::isfinite(r->dt_growth) || !(r->guard_band >= 0) || !(r->guard_band < 1) ||
         !(r->guard_ttf >= 0) || !std::isfinite(r->guard_ttf) ||
         !(r->amg_alpha == 0.0 || (r->amg_alpha >= 1.0 && r->amg_alpha <= 4.0)) ||
-        !(r->ss_tol >= 0) || !(r->ss_tol <= 1e-2))
+        !(r->ss_tol >= 0) || !(r->ss_tol <= 1e-2) || r->krylov_q < 0 || r->krylov_q > KRY_RM_MAX / 2 ||
+        !(r->krylov_eta >= 0) || !(r->krylov_eta <= 100.0))
         return fail(b, EM_ERR_ARG, "bad run parameters (max_voids_per_tree <= 4, 0 <= guard_band < 1, "
-                                   "guard_ttf >= 0, amg_alpha 0 or in [1, 4], 0 <= ss_tol <= 1e-2)");
+                                   "guard_ttf >= 0, amg_alpha 0 or in [1, 4], 0 <= ss_tol <= 1e-2, "
+                                   "0 <= krylov_q <= 8, 0 <= krylov_eta <= 100)");
+    if (r->krylov_q > 0 && r->ss_tol > 0)
+        return fail(b, EM_ERR_ARG, "reduced (Krylov) stepping and steady-state skipping are exclusive");
     if (r->joule) {
         const double tv[] = {m->k_cu, m->k_ild, m->t_ild};
         if (!finite_all(tv, 3) || !(m->k_cu > 0) || !(m->k_ild > 0) || !(m->t_ild > 0))
@@ -763,9 +767,12 @@ em_status timed_step_dev(em_batch *b, const Dev &dd, int n_steps, int step0, boo
     fold_timers(b);
     b->nominal = false;                   // voids may grow from here on
     HIPCHK(b, hipEventRecord(b->ev_a, b->stream));
+    // long chains in reduced form first: an interval they take sits out the exact launch
+    if (dd.kq > 0) launch_kry_step(dd, b->fp32, n_steps, b->stream);
     if (dd.n_chain_wg > 0) launch_chain(dd, b->d_dev, b->fp32, n_steps, step0, b->stream);
     if (b->n_br > 0) launch_branch(dd, b->fp32, b->n_br, b->br_max_nodes, n_steps, step0, b->stream);
     else if (b->n_generic_trees > 0) launch_step(dd, b->fp32, n_steps, step0, b->stream);
+    if (dd.kq > 0) launch_kry_restore(dd, b->stream);
     LAUNCHCHK(b);
     HIPCHK(b, hipEventRecord(b->ev_b, b->stream));
     b->step_pending = true;
@@ -794,6 +801,7 @@ em_status timed_ir(em_batch *b)
     HIPCHK(b, hipEventRecord(b->ev_c, b->stream));
     em_status st = ir_solve_impl(b);
     if (st != EM_OK) return st;
+    if (b->d.kq > 0 && !b->ir_unchanged) launch_kry_invalidate(b->d, false, b->stream);   // new drive
     HIPCHK(b, hipEventRecord(b->ev_d, b->stream));
     b->ir_pending = true;
     b->cg_iters_total += b->cg_iters_last;
@@ -1225,6 +1233,31 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     UP(d.vinc_off, P.inc_off); UP(d.vinc, P.inc);
     UP(d.tseg_off, tseg_off); UP(d.tseg, tseg);
     UP(d.via_up, via_up); UP(d.tree_perm, tree_perm); UP(d.tree_chain, tree_chain);
+    if (r->krylov_q > 0) {
+        // reduced stepping: the chain instances of at least max(3q, 30) nodes (eq. 27)
+        const int q = r->krylov_q;
+        std::vector<int> kl;
+        for (int t = 0; t < nt; ++t)
+            if (tree_chain[t] && P.tree_off[t + 1] - P.tree_off[t] >= std::max(3 * q, 30))
+                for (int s = 0; s < S; ++s) kl.push_back(t * S + s);
+        d.kq = q;
+        d.krm = 2 * q;
+        d.keta = r->krylov_eta > 0 ? r->krylov_eta : 1.0;
+        d.n_kry_list = (int)kl.size();
+        const size_t ISk = (size_t)nt * S;
+        if (!kl.empty()) {
+            UP(d.kry_list, kl);
+            AL(d.kv, double, (size_t)d.krm * ns * S);
+            AL(d.kred, double, ISk * KRY_KS(d.krm));
+            AL(d.kscr, double, (size_t)ns * S);
+        }
+        AL(d.kr, int, ISk);
+        AL(d.kdone, uint8_t, ISk);
+        AL(d.kcnt, unsigned long long, 4);
+        HIPCHK(b, hipMemsetAsync(d.kr, 0, 4 * ISk, b->stream));
+        HIPCHK(b, hipMemsetAsync(d.kdone, 0, ISk, b->stream));
+        HIPCHK(b, hipMemsetAsync(d.kcnt, 0, 32, b->stream));
+    }
     if (lanes_cap / 256 > (1LL << 30)) return fail(b, EM_ERR_ARG, "batch too large");
     d.n_chain_wg = (int)(n_lanes / cWG);
     b->n_generic_trees = 0;
@@ -1562,6 +1595,17 @@ em_status em_get_info(em_batch *b, em_info *info)
     info->n_ss_skipped = b->n_ss_skipped;
     info->n_ss_woken = b->n_ss_woken;
     {
+        unsigned long long kc[4] = {0, 0, 0, 0};
+        if (b->d.kq > 0) {
+            HIPCHK(b, hipMemcpyAsync(kc, b->d.kcnt, 32, hipMemcpyDeviceToHost, b->stream));
+            HIPCHK(b, hipStreamSynchronize(b->stream));
+        }
+        info->n_krylov_bases = (int64_t)kc[0];
+        info->n_krylov_intervals = (int64_t)kc[1];
+        info->n_krylov_fallbacks = (int64_t)kc[2];
+        info->krylov_node_steps = (int64_t)kc[3];
+    }
+    {
         const size_t IS = (size_t)b->n_trees * b->S;
         std::vector<int> sup(IS);
         HIPCHK(b, hipMemcpyAsync(sup.data(), b->d.n_suppressed, 4 * IS, hipMemcpyDeviceToHost, b->stream));
@@ -1757,6 +1801,8 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
     const bool ssk = b->run.ss_tol > 0;
     if (ssk && b->sur)
         return fail(b, EM_ERR_STATE, "steady-state skipping cannot be combined with the learned screen");
+    if (b->d.kq > 0 && b->sur)
+        return fail(b, EM_ERR_STATE, "reduced (Krylov) stepping cannot be combined with the learned screen");
     Dev &d = b->d;
     hipStream_t st = b->stream;
     const int S = b->S;
@@ -1947,6 +1993,11 @@ em_status em_reset(em_batch *b)
     b->rerun_node_steps = 0;
     b->n_ss_skipped = b->n_ss_woken = 0;
     if (b->ss_ready) HIPCHK(b, hipMemsetAsync(d.ss_skip, 0, IS, st));
+    if (d.kq > 0) {
+        HIPCHK(b, hipMemsetAsync(d.kr, 0, 4 * IS, st));
+        HIPCHK(b, hipMemsetAsync(d.kdone, 0, IS, st));
+        HIPCHK(b, hipMemsetAsync(d.kcnt, 0, 32, st));
+    }
     b->live_dirty = true;
     b->any_open = false;
     b->ir_valid = false;
@@ -2125,8 +2176,15 @@ static em_status column_io(em_batch *b, int sample, double *host, bool to_state,
 }
 
 em_status em_get_stress(em_batch *b, int32_t sample, double *sigma) { return column_io(b, sample, sigma, false, -1); }
+// A state replaced from outside the stepping leaves the reduced bases' span.
+static void kry_drop_all(em_batch *b)
+{
+    if (b && b->d.kq > 0) launch_kry_invalidate(b->d, true, b->stream);
+}
+
 em_status em_set_stress(em_batch *b, int32_t sample, const double *sigma)
 {
+    kry_drop_all(b);
     return column_io(b, sample, const_cast<double *>(sigma), true, -1);
 }
 
@@ -2171,6 +2229,7 @@ em_status em_get_seg_state(em_batch *b, int32_t sample, double *dR, uint8_t *ope
 
 em_status em_set_seg_state(em_batch *b, int32_t sample, const double *dR, const uint8_t *open)
 {
+    kry_drop_all(b);
     if (!b || sample < 0 || sample >= b->S || !dR || !open) return fail(b, EM_ERR_ARG, "bad sample or null state");
     if (b->trees_only) return fail(b, EM_ERR_STATE, "trees-only batch has no IR network");
     bool any = false;
@@ -2268,6 +2327,7 @@ em_status em_get_screen(em_batch *b, int32_t sample, uint8_t *tree_mortal, uint8
 
 em_status em_inject_void(em_batch *b, int32_t sample, int32_t tree, int32_t node)
 {
+    kry_drop_all(b);
     if (!b || sample < 0 || sample >= b->S || tree < 0 || tree >= b->n_trees ||
         node < b->tree_off[tree] || node >= b->tree_off[tree + 1])
         return fail(b, EM_ERR_ARG, "bad void location");
@@ -2381,6 +2441,7 @@ em_status em_snapshot(em_batch *b, void *host_buf, size_t cap, size_t *used)
 
 em_status em_restore(em_batch *b, const void *host_buf, size_t n)
 {
+    kry_drop_all(b);
     if (!b || !host_buf) return fail(b, EM_ERR_ARG, "null argument");
     uint32_t hdr[12];
     if (n < sizeof hdr) return fail(b, EM_ERR_ARG, "snapshot too short");

@@ -143,7 +143,22 @@ struct Dev {
     // ---- steady-state skipping (allocated when em_run_params.ss_tol > 0) ----
     uint8_t *ss_skip;                   // [inst] skipped at its steady state
     unsigned int *ss_cnt;               // [2] skips, wakes (cumulative)
+    // ---- reduced (extended rational Krylov) stepping of long chains (kq > 0) ----
+    int kq, krm;                        // reduction order q (blocks), columns at most 2q
+    double keta;                        // shift-time scale eta (eq. 26)
+    const int *kry_list;                // chain instances of at least max(3q, 30) nodes
+    int n_kry_list;
+    double *kv;                         // [krm][ns][S] basis columns
+    double *kred;                       // [inst][KRY_KS(krm)] A_h, C_h, f_h, z
+    double *kscr;                       // [ns][S] inverse pivots of K = s0 C - A
+    int *kr;                            // [inst] basis columns (0: none)
+    uint8_t *kdone;                     // [inst] interval taken in reduced form
+    unsigned long long *kcnt;           // [4] bases built, reduced intervals, fallbacks,
+                                        //     node-steps advanced in reduced form
 };
+
+constexpr int KRY_RM_MAX = 16;           // 2 q for q <= 8
+__host__ __device__ constexpr int KRY_KS(int rm) { return 2 * rm * rm + 2 * rm; }
 
 // Aggregation multigrid preconditioner of the IR solve.  Level 0 is the nodal
 // system on the free nodes; level l >= 1 has one node per aggregate of level
@@ -239,6 +254,9 @@ void launch_edge_static(const Dev &d, hipStream_t st);
 void launch_node_V(const Dev &d, bool fp32, hipStream_t st);   // also per-tree volume
 void launch_ss_check(const Dev &d, bool fp32, double tol_abs, hipStream_t st);  // skip converged chain instances
 void launch_ss_wake(const Dev &d, bool all, hipStream_t st);  // wake those of re-solved samples (all: every one)
+void launch_kry_step(const Dev &d, bool fp32, int n_steps, hipStream_t st);   // reduced intervals
+void launch_kry_restore(const Dev &d, hipStream_t st);                        // after the exact launch
+void launch_kry_invalidate(const Dev &d, bool all, hipStream_t st);           // after an IR solve
 void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, double cov_r, double cov_l,
                   double sd_ea, double sd_T, hipStream_t st);
 void launch_node_sc(const Dev &d, bool fp32, hipStream_t st);

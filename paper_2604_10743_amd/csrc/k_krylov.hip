@@ -1,0 +1,374 @@
+// Extended rational Krylov reduced stepping of long chains (Sec. IV-E,
+// Alg. 1, eqs. 21-27), for (tree, sample) instances without voids.
+//
+// Between two IR solves a chain's stress obeys C s' = A s + f (C = diag(V),
+// A = -L the negated Laplacian of the edge conductances g = xi_k g0, f the
+// constant drive).  With the shift s0 = 1/t_s, t_s = eta L^2 / (pi^2 kappa)
+// (eq. 26: L the chain's length, kappa its volume-weighted diffusivity) and
+// K = s0 C - A, the basis V spans the block rational Krylov space of R C over
+// the starting block [K^-1 C s, K^-1 f] (eq. 23): block Gram-Schmidt, two
+// passes, a column kept when its norm after orthogonalisation exceeds 1e-10
+// of its norm before, at most q blocks.  The reduced model
+// A_h = V^T A V, C_h = V^T C V, f_h = V^T f (eq. 25) is stepped by backward
+// Euler, z <- (C_h - dt A_h)^-1 (C_h z + dt f_h), and lifted as s = V z.
+//
+// The basis is built from the state and drive of the instance's first
+// reduced interval and kept while both stay in its span: the state does (it
+// is V z), the drive until an IR re-solve changes the sample's conductances.
+// An interval is taken in reduced form only when the lifted states provably
+// stay below every critical stress: |V_i . (z_k - z_end)| <= |z_k - z_end|_2
+// (the rows of an orthonormal V have norm at most 1), so
+// max_i (s_end,i - sigma_crit,i) + max_k |z_k - z_end|_2 < 0 suffices;
+// otherwise the interval is stepped by the exact chain kernel and the basis
+// dropped (the exact state leaves the span).
+//
+// Layout: V columns [(c ns + i) S + s] (samples fastest, as the state); per
+// instance KS doubles: A_h, C_h (RM x RM), f_h, z (RM); pivots of K's
+// tridiagonal factorisation [i S + s].  Everything in FP64; the state is
+// written back in the batch's precision (FP32: high and low parts).
+#include "em_internal.h"
+
+namespace em {
+
+constexpr int KB = 256;                 // threads per instance workgroup
+constexpr double KRY_EPS = 1e-10;
+#define EM_KERNEL_KB __global__ __launch_bounds__(256)
+
+__device__ inline double kb_sum(double v, double *sh)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+#pragma unroll
+    for (int k = 0; k < KB / 64; ++k) r += sh[k];
+    return r;
+}
+
+__device__ inline double kb_max(double v, double *sh)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = sh[0];
+#pragma unroll
+    for (int k = 1; k < KB / 64; ++k) r = fmax(r, sh[k]);
+    return r;
+}
+
+// a chain instance the reduced path may take: active, without voids, of at
+// least max(3q, 30) nodes (eq. 27)
+__device__ inline bool kry_eligible(const Dev &d, int inst, int &s, int &i0, int &i1)
+{
+    const int t = inst / d.S;
+    s = inst - t * d.S;
+    if (!d.tree_chain[t] || !d.inst_active[inst] || !d.sample_active[s] || d.nv[inst] > 0) return false;
+    i0 = d.tree_off[t];
+    i1 = d.tree_off[t + 1];
+    return i1 - i0 >= max(3 * d.kq, 30);
+}
+
+template <typename R>
+__device__ inline double kry_state(const Dev &d, int i, int s)
+{
+    const size_t x = (size_t)i * d.S + s;
+    double v = (double)((const R *)d.sigma)[x];
+    if (d.sig_lo) v += (double)d.sig_lo[x];
+    return v;
+}
+
+template <typename R>
+EM_KERNEL_KB void k_kry_basis(Dev d)
+{
+    __shared__ double sh[KB / 64];
+    const int inst = d.kry_list[blockIdx.x];
+    int s, i0, i1;
+    if (!kry_eligible(d, inst, s, i0, i1) || d.kr[inst] > 0) return;
+    const int tid = threadIdx.x, S = d.S, RM = d.krm;
+    auto col = [&](int c, int i) -> double & { return d.kv[((size_t)c * d.ns + i) * S + s]; };
+    auto ge = [&](int i) -> double { return d.xi_k[(size_t)d.seg[i] * S + s] * d.g0[i]; };   // edge (i-1, i)
+    double *ip = d.kscr;                // inverse pivots [i S + s]
+    // shift (eq. 26)
+    double a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int i = i0 + tid; i < i1; i += KB) {
+        a2 += d.V[i];
+        if (i > i0) {
+            const double dx = d.len[d.seg[i]] / d.N;
+            a1 += ge(i) * dx * dx;
+            a3 += dx;
+        }
+    }
+    const double kap = kb_sum(a1, sh) / kb_sum(a2, sh);
+    const double L = kb_sum(a3, sh);
+    const double s0 = M_PI * M_PI * kap / (d.keta * L * L);
+    // K = s0 C + L is tridiagonal along the chain: pivots in order (one thread)
+    if (tid == 0) {
+        double p = 0.0, gl = 0.0;
+        for (int i = i0; i < i1; ++i) {
+            const double gr = i + 1 < i1 ? ge(i + 1) : 0.0;
+            const double D = s0 * d.V[i] + gl + gr;
+            p = i > i0 ? D - gl * gl * p : D;          // p: the previous inverse pivot
+            p = 1.0 / p;
+            ip[(size_t)i * S + s] = p;
+            gl = gr;
+        }
+    }
+    __syncthreads();
+    // column c <- K^-1 column c (forward and back substitution, one thread)
+    auto solve = [&](int c) {
+        if (tid == 0) {
+            double y = 0.0;
+            for (int i = i0; i < i1; ++i) {
+                const double b = col(c, i);
+                y = i > i0 ? b + ge(i) * ip[(size_t)(i - 1) * S + s] * y : b;
+                col(c, i) = y;
+            }
+            double x = 0.0;
+            for (int i = i1 - 1; i >= i0; --i) {
+                const double yi = col(c, i);
+                x = (i + 1 < i1 ? yi + ge(i + 1) * x : yi) * ip[(size_t)i * S + s];
+                col(c, i) = x;
+            }
+        }
+        __syncthreads();
+    };
+    auto dot = [&](int b, int c) -> double {
+        double a = 0.0;
+        for (int i = i0 + tid; i < i1; i += KB) a += col(b, i) * col(c, i);
+        return kb_sum(a, sh);
+    };
+    // orthonormalise column c against columns 0 .. c-1; true when kept
+    auto accept = [&](int c) -> bool {
+        const double n0 = sqrt(dot(c, c));
+        if (!(n0 > 0.0)) return false;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int b = 0; b < c; ++b) {
+                const double h = dot(b, c);
+                for (int i = i0 + tid; i < i1; i += KB) col(c, i) -= h * col(b, i);
+                __syncthreads();
+            }
+        const double nw = sqrt(dot(c, c));
+        if (!(nw > KRY_EPS * n0)) return false;
+        const double inv = 1.0 / nw;
+        for (int i = i0 + tid; i < i1; i += KB) col(c, i) *= inv;
+        __syncthreads();
+        return true;
+    };
+    const R *fv = (const R *)d.dtf;
+    int r = 0;
+    // starting block (eq. 23): K^-1 C s, K^-1 f
+    for (int i = i0 + tid; i < i1; i += KB) col(r, i) = d.V[i] * kry_state<R>(d, i, s);
+    __syncthreads();
+    solve(r);
+    if (accept(r)) ++r;
+    for (int i = i0 + tid; i < i1; i += KB) col(r, i) = (double)fv[(size_t)i * S + s] / d.dt;
+    __syncthreads();
+    solve(r);
+    if (accept(r)) ++r;
+    int b0 = 0, b1 = r;
+    for (int j = 1; j < d.kq && b1 > b0; ++j) {
+        const int nb = r;
+        for (int c = b0; c < b1 && r < RM; ++c) {
+            for (int i = i0 + tid; i < i1; i += KB) col(r, i) = d.V[i] * col(c, i);
+            __syncthreads();
+            solve(r);
+            if (accept(r)) ++r;
+        }
+        b0 = nb;
+        b1 = r;
+    }
+    // reduced matrices (eq. 25) and the reduced state V^T s
+    double *kh = d.kred + (size_t)inst * KRY_KS(RM);
+    double *Ah = kh, *Ch = kh + RM * RM, *fh = kh + 2 * RM * RM, *z = fh + RM;
+    for (int b = 0; b < r; ++b)
+        for (int c = b; c < r; ++c) {
+            double aa = 0.0, cc = 0.0;
+            for (int i = i0 + tid; i < i1; i += KB) {
+                cc += d.V[i] * col(b, i) * col(c, i);
+                if (i > i0) aa -= ge(i) * (col(b, i) - col(b, i - 1)) * (col(c, i) - col(c, i - 1));
+            }
+            aa = kb_sum(aa, sh);
+            cc = kb_sum(cc, sh);
+            if (tid == 0) {
+                Ah[b * RM + c] = Ah[c * RM + b] = aa;
+                Ch[b * RM + c] = Ch[c * RM + b] = cc;
+            }
+        }
+    for (int b = 0; b < r; ++b) {
+        double ff = 0.0, zz = 0.0;
+        for (int i = i0 + tid; i < i1; i += KB) {
+            ff += (double)fv[(size_t)i * S + s] / d.dt * col(b, i);
+            zz += kry_state<R>(d, i, s) * col(b, i);
+        }
+        ff = kb_sum(ff, sh);
+        zz = kb_sum(zz, sh);
+        if (tid == 0) {
+            fh[b] = ff;
+            z[b] = zz;
+        }
+    }
+    if (tid == 0) {
+        d.kr[inst] = r;
+        atomicAdd(&d.kcnt[0], 1ull);
+    }
+}
+
+// n_steps of reduced backward Euler for every instance with a basis; the
+// lifted end state replaces the state when the interval provably stays below
+// every critical stress (the instance then sits out the exact launch).
+template <typename R>
+EM_KERNEL_KB void k_kry_step(Dev d, int n_steps)
+{
+    __shared__ double sh[KB / 64];
+    __shared__ double M[KRY_RM_MAX * KRY_RM_MAX], F[KRY_RM_MAX * KRY_RM_MAX];
+    __shared__ double g[KRY_RM_MAX], z0[KRY_RM_MAX], ze[KRY_RM_MAX], s_dist;
+    const int inst = d.kry_list[blockIdx.x];
+    int s, i0, i1;
+    if (!kry_eligible(d, inst, s, i0, i1)) return;
+    const int r = d.kr[inst];
+    if (r <= 0) return;
+    const int tid = threadIdx.x, S = d.S, RM = d.krm;
+    double *kh = d.kred + (size_t)inst * KRY_KS(RM);
+    const double *Ah = kh, *Ch = kh + RM * RM, *fh = kh + 2 * RM * RM;
+    double *z = kh + 2 * RM * RM + RM;
+    if (tid == 0) {
+        const double dt = d.dt;
+        for (int a = 0; a < r; ++a)
+            for (int b = 0; b < r; ++b) M[a * r + b] = Ch[a * RM + b] - dt * Ah[a * RM + b];
+        // M = LU in place (M is symmetric positive definite: no pivoting)
+        for (int k = 0; k < r; ++k)
+            for (int a = k + 1; a < r; ++a) {
+                const double l = M[a * r + k] / M[k * r + k];
+                M[a * r + k] = l;
+                for (int b = k + 1; b < r; ++b) M[a * r + b] -= l * M[k * r + b];
+            }
+        auto lu_solve = [&](double *x) {
+            for (int a = 1; a < r; ++a)
+                for (int b = 0; b < a; ++b) x[a] -= M[a * r + b] * x[b];
+            for (int a = r - 1; a >= 0; --a) {
+                for (int b = a + 1; b < r; ++b) x[a] -= M[a * r + b] * x[b];
+                x[a] /= M[a * r + a];
+            }
+        };
+        double x[KRY_RM_MAX];
+        for (int c = 0; c < r; ++c) {           // F = M^-1 C_h, column by column
+            for (int a = 0; a < r; ++a) x[a] = Ch[a * RM + c];
+            lu_solve(x);
+            for (int a = 0; a < r; ++a) F[a * r + c] = x[a];
+        }
+        for (int a = 0; a < r; ++a) x[a] = dt * fh[a];
+        lu_solve(x);
+        for (int a = 0; a < r; ++a) {
+            g[a] = x[a];
+            z0[a] = z[a];
+        }
+        double zc[KRY_RM_MAX], zn[KRY_RM_MAX];
+        for (int a = 0; a < r; ++a) zc[a] = z0[a];
+        for (int k = 0; k < n_steps; ++k) {
+            for (int a = 0; a < r; ++a) {
+                double v = g[a];
+                for (int b = 0; b < r; ++b) v += F[a * r + b] * zc[b];
+                zn[a] = v;
+            }
+            for (int a = 0; a < r; ++a) zc[a] = zn[a];
+        }
+        for (int a = 0; a < r; ++a) ze[a] = zc[a];
+        // the largest distance of a reduced state of the interval from its end
+        double dist = 0.0;
+        for (int a = 0; a < r; ++a) zc[a] = z0[a];
+        for (int k = 0; k <= n_steps; ++k) {
+            double q = 0.0;
+            for (int a = 0; a < r; ++a) q += (zc[a] - ze[a]) * (zc[a] - ze[a]);
+            dist = fmax(dist, sqrt(q));
+            if (k == n_steps) break;
+            for (int a = 0; a < r; ++a) {
+                double v = g[a];
+                for (int b = 0; b < r; ++b) v += F[a * r + b] * zc[b];
+                zn[a] = v;
+            }
+            for (int a = 0; a < r; ++a) zc[a] = zn[a];
+        }
+        s_dist = dist;
+    }
+    __syncthreads();
+    const R *sc = (const R *)d.sc;
+    auto lift = [&](int i) -> double {
+        double v = 0.0;
+        for (int c = 0; c < r; ++c) v += d.kv[((size_t)c * d.ns + i) * S + s] * ze[c];
+        return v;
+    };
+    double mg = -INFINITY;
+    for (int i = i0 + tid; i < i1; i += KB) mg = fmax(mg, lift(i) - (double)sc[(size_t)i * S + s]);
+    mg = kb_max(mg, sh);
+    const bool ok = mg + s_dist < 0.0;
+    if (ok) {
+        R *sig = (R *)d.sigma;
+        for (int i = i0 + tid; i < i1; i += KB) {
+            const size_t x = (size_t)i * S + s;
+            const double v = lift(i);
+            sig[x] = (R)v;
+            if (d.sig_lo) d.sig_lo[x] = (float)(v - (double)(R)v);
+        }
+    }
+    if (tid == 0) {
+        if (ok) {
+            for (int a = 0; a < r; ++a) z[a] = ze[a];
+            d.kdone[inst] = 1;
+            d.inst_active[inst] = 0;
+            atomicAdd(&d.kcnt[1], 1ull);
+            atomicAdd(&d.kcnt[3], (unsigned long long)(i1 - i0) * (unsigned long long)n_steps);
+        } else {
+            d.kr[inst] = 0;
+            atomicAdd(&d.kcnt[2], 1ull);
+        }
+    }
+}
+
+// the instances taken in reduced form rejoin the active set
+EM_KERNEL_KB void k_kry_restore(Dev d)
+{
+    const int inst = blockIdx.x * KB + threadIdx.x;
+    if (inst >= d.n_trees * d.S || !d.kdone[inst]) return;
+    d.kdone[inst] = 0;
+    d.inst_active[inst] = 1;
+}
+
+// bases of the samples whose conductances changed at the last IR solve (all:
+// every basis) are dropped: the drive left their span
+EM_KERNEL_KB void k_kry_invalidate(Dev d, int all)
+{
+    const int inst = blockIdx.x * KB + threadIdx.x;
+    if (inst >= d.n_trees * d.S) return;
+    if (all || d.g_chg_s[inst % d.S]) d.kr[inst] = 0;
+}
+
+void launch_kry_step(const Dev &d, bool fp32, int n_steps, hipStream_t st)
+{
+    const int n = d.n_kry_list;
+    if (n <= 0 || d.kq <= 0) return;
+    if (fp32) {
+        k_kry_basis<float><<<n, KB, 0, st>>>(d);
+        k_kry_step<float><<<n, KB, 0, st>>>(d, n_steps);
+    } else {
+        k_kry_basis<double><<<n, KB, 0, st>>>(d);
+        k_kry_step<double><<<n, KB, 0, st>>>(d, n_steps);
+    }
+}
+
+void launch_kry_restore(const Dev &d, hipStream_t st)
+{
+    const int n = d.n_trees * d.S;
+    if (n > 0 && d.kq > 0) k_kry_restore<<<(n + KB - 1) / KB, KB, 0, st>>>(d);
+}
+
+void launch_kry_invalidate(const Dev &d, bool all, hipStream_t st)
+{
+    const int n = d.n_trees * d.S;
+    if (n > 0 && d.kq > 0) k_kry_invalidate<<<(n + KB - 1) / KB, KB, 0, st>>>(d, all ? 1 : 0);
+}
+
+}  // namespace em

@@ -1,0 +1,87 @@
+"""Reduced (extended rational Krylov) stepping of long chains (Sec. IV-E,
+Alg. 1, eqs. 21-27; em_run_params.krylov_q) against the FP64 oracle running
+the same reduced path, and against the library's exact stepping.  The
+96x96 sparse-via grid with the immortality screen off: its 169 chains of
+41-1901 nodes all take the reduced path until they could nucleate, then
+fall back to exact stepping."""
+import numpy as np
+import pytest
+
+import ttf_check
+
+from paper_2604_10743_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def em():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2604_10743_amd as P
+    return P
+
+
+def _run(em, g, mat, rn, mc, picks):
+    B = em.Batch(g, mat, rn, mc)
+    res = B.run_to_ttf()
+    info = B.info()
+    st = {s: B.stress(s) for s in picks}
+    segs = {s: B.failed_segments(s) for s in picks}
+    B.close()
+    return res, info, st, segs
+
+
+def test_krylov_fp64_matches_oracle_reduced_path(em, oracle_mod):
+    g, mat, rn, mc = synth.workload("mc_grid")
+    S = 2
+    mc = dict(mc, n_samples=S)
+    rk = dict(rn, prec=0, screen=0, krylov_q=4)
+    print("mc_grid FP64 screen off, krylov q=4", flush=True)
+    res, info, st, segs = _run(em, g, mat, rk, mc, range(S))
+    print({k: info[k] for k in ("n_krylov_bases", "n_krylov_intervals", "n_krylov_fallbacks",
+                                "krylov_node_steps", "node_steps")}, flush=True)
+    assert info["n_krylov_intervals"] > 1000
+    topo = oracle_mod.topology(g, rn["intervals_per_seg"])
+    for s in range(S):
+        print(f"oracle sample {s}", flush=True)
+        ref = oracle_mod.run_sample(g, mat, rk, mc, s, topo=topo)
+        ttf_check.check(res[s], ref, segs[s], 0, rk, s)
+        scale = float(np.abs(ref["sigma"]).max())
+        d = float(np.abs(st[s] - ref["sigma"]).max())
+        print(f"sample {s}: largest stress difference {d:.3e} Pa of {scale:.3e}", flush=True)
+        assert d <= 1e-8 * scale
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_krylov_against_exact_stepping(em, prec):
+    """Same batch with and without the reduced path: failure decisions,
+    re-solve indices and nucleated trees identical, TTF and final drop within
+    the paper's reported error (0.05 %), the stress within 1e-5 of its scale
+    in FP64 (q = 4 on these lines: about 1e-6) and 1e-4 in FP32 (the FP32
+    state's own distance from FP64 stepping);
+    the exact node-steps drop by the reduced ones."""
+    g, mat, rn, mc = synth.workload("mc_grid")
+    S = 64
+    mc = dict(mc, n_samples=S)
+    r0 = dict(rn, prec=prec, screen=0)
+    picks = list(range(0, S, 8))
+    a, ia, sa, _ = _run(em, g, mat, r0, mc, picks)
+    b, ib, sb, _ = _run(em, g, mat, dict(r0, krylov_q=4), mc, picks)
+    print(f"prec {prec}: node-steps {ia['node_steps']} exact vs {ib['node_steps']} + "
+          f"{ib['krylov_node_steps']} reduced; {ib['n_krylov_fallbacks']} fallbacks", flush=True)
+    assert ib["node_steps"] + ib["krylov_node_steps"] == ia["node_steps"]
+    assert ib["node_steps"] < 0.5 * ia["node_steps"]
+    n_fail = 0
+    for s in range(S):
+        assert a[s]["failed"] == b[s]["failed"], s
+        assert a[s]["outer_idx"] == b[s]["outer_idx"], s
+        assert a[s]["n_nucleated_trees"] == b[s]["n_nucleated_trees"], s
+        assert abs(a[s]["final_drop"] - b[s]["final_drop"]) <= 5e-4 * a[s]["final_drop"], s
+        if a[s]["failed"]:
+            assert abs(a[s]["ttf_s"] - b[s]["ttf_s"]) <= 5e-4 * a[s]["ttf_s"], s
+        n_fail += a[s]["failed"]
+    for s in picks:
+        scale = float(np.abs(sa[s]).max())
+        assert float(np.abs(sa[s] - sb[s]).max()) <= (1e-5 if prec == 0 else 1e-4) * scale, s
+    assert n_fail > 0
