@@ -85,3 +85,53 @@ def test_krylov_against_exact_stepping(em, prec):
         scale = float(np.abs(sa[s]).max())
         assert float(np.abs(sa[s] - sb[s]).max()) <= (1e-5 if prec == 0 else 1e-4) * scale, s
     assert n_fail > 0
+
+
+def test_krylov_follows_state_changes_and_the_graded_grid(em):
+    """The stepping API: bases are dropped when the state is replaced
+    (em_set_stress, em_restore) and rebuilt from the new state, so the
+    reduced batch keeps to the exact one (a stale basis would be off by the
+    halving); and a graded time grid (a new step size every interval) runs to
+    the same decisions."""
+    g, mat, rn, mc = synth.workload("mc_grid")
+    mc = dict(mc, n_samples=2)
+    r0 = dict(rn, prec=0, screen=0)
+    Be = em.Batch(g, mat, r0, mc)
+    Bk = em.Batch(g, mat, dict(r0, krylov_q=4), mc)
+
+    def same(tag, tol=1e-4):                    # mid-transient, q = 4: about 1e-5
+        for s in range(2):
+            a, b = Be.stress(s), Bk.stress(s)
+            d = float(np.abs(a - b).max())
+            assert d <= tol * float(np.abs(a).max()), (tag, s, d)
+
+    try:
+        for B in (Be, Bk):
+            B.ir_solve()
+            B.stress_step(100)
+        same("first interval")
+        assert Bk.info()["n_krylov_intervals"] > 0
+        snap_e, snap_k = Be.snapshot(), Bk.snapshot()
+        half = 0.5 * Be.stress(0)
+        for B in (Be, Bk):
+            B.set_stress(half, 0)
+            B.stress_step(100)
+        same("after set_stress")
+        for B in (Be, Bk):
+            B.stress_step(100)
+        same("second interval")
+        Be.restore(snap_e)
+        Bk.restore(snap_k)
+        for B in (Be, Bk):
+            B.stress_step(200)
+        same("after restore")
+    finally:
+        Be.close()
+        Bk.close()
+    rg = dict(r0, dt_growth=1.08, n_steps=1000)
+    a, _, _, _ = _run(em, g, mat, rg, mc, [])
+    b, ib, _, _ = _run(em, g, mat, dict(rg, krylov_q=4), mc, [])
+    assert ib["n_krylov_intervals"] > 0
+    for s in range(2):
+        assert a[s]["failed"] == b[s]["failed"] and a[s]["outer_idx"] == b[s]["outer_idx"], s
+        assert abs(a[s]["final_drop"] - b[s]["final_drop"]) <= 5e-4 * a[s]["final_drop"], s

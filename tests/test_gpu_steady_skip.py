@@ -94,3 +94,20 @@ def test_skipping_is_refused_with_the_learned_screen(em):
     finally:
         mlp.close()
         B.close()
+
+
+def test_skipping_on_a_graded_time_grid(em):
+    """The band holds for any sequence of step sizes: with a new step size
+    every interval the skipped run keeps the full run's results."""
+    g, mat, rn, mc = synth.workload("mc_grid")
+    mc = dict(mc, n_samples=16)
+    rn = dict(rn, prec=0, screen=0, dt_growth=1.08, n_steps=1000)
+    picks = list(range(16))
+    r0, i0, st0, _, _ = _run(em, g, mat, rn, mc, picks)
+    r1, i1, st1, _, _ = _run(em, g, mat, dict(rn, ss_tol=TOL), mc, picks)
+    assert i1["n_ss_skipped"] > 0
+    for s in range(16):
+        assert r0[s]["failed"] == r1[s]["failed"] and r0[s]["outer_idx"] == r1[s]["outer_idx"], s
+        assert abs(r0[s]["final_drop"] - r1[s]["final_drop"]) <= 1e-6 * r0[s]["final_drop"], s
+    worst = max(float(np.max(np.abs(st0[s] - st1[s]))) for s in picks)
+    assert worst <= 1.01 * TOL * mat["sigma_crit"]
