@@ -1233,6 +1233,25 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     UP(d.vinc_off, P.inc_off); UP(d.vinc, P.inc);
     UP(d.tseg_off, tseg_off); UP(d.tseg, tseg);
     UP(d.via_up, via_up); UP(d.tree_perm, tree_perm); UP(d.tree_chain, tree_chain);
+    if (r->ss_tol > 0 && S >= 64) {
+        // steady-state skipping with many samples: chunks of the chain trees
+        std::vector<int> coff(nt + 1, 0), ctree, cstart;
+        for (int t = 0; t < nt; ++t) {
+            coff[t] = (int)ctree.size();
+            if (!tree_chain[t]) continue;
+            for (int i = P.tree_off[t]; i < P.tree_off[t + 1]; i += SS_CL) {
+                ctree.push_back(t);
+                cstart.push_back(i);
+            }
+        }
+        coff[nt] = (int)ctree.size();
+        d.ss_nc = (int)ctree.size();
+        UP(d.ss_coff, coff);
+        if (d.ss_nc > 0) {
+            UP(d.ss_ctree, ctree);
+            UP(d.ss_cstart, cstart);
+        }
+    }
     if (r->krylov_q > 0) {
         // reduced stepping: the chain instances of at least max(3q, 30) nodes (eq. 27)
         const int q = r->krylov_q;
@@ -1767,6 +1786,10 @@ static em_status ss_begin(em_batch *b)
         d.ss_skip = (uint8_t *)dalloc(b, IS);
         d.ss_cnt = (unsigned int *)dalloc(b, 8);
         if (!d.ss_skip || !d.ss_cnt) return fail(b, EM_ERR_OOM, "steady-state skipping buffers");
+        if (d.ss_nc > 0) {
+            d.ss_scr = (double *)dalloc(b, 8 * ((size_t)d.ss_nc * 11 * d.S + IS));
+            if (!d.ss_scr) return fail(b, EM_ERR_OOM, "steady-state skipping buffers");
+        }
         b->ss_ready = true;
     }
     HIPCHK(b, hipMemsetAsync(d.ss_skip, 0, IS, st));

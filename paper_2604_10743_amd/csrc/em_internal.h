@@ -143,6 +143,9 @@ struct Dev {
     // ---- steady-state skipping (allocated when em_run_params.ss_tol > 0) ----
     uint8_t *ss_skip;                   // [inst] skipped at its steady state
     unsigned int *ss_cnt;               // [2] skips, wakes (cumulative)
+    int ss_nc;                          // chunks of SS_CL nodes over the chain trees (64+ samples)
+    const int *ss_coff, *ss_ctree, *ss_cstart;   // [n_trees+1] first chunk; [nc] tree, first node
+    double *ss_scr;                     // [nc][11][S] chunk sums, carries, extremes; [IS] fm
     // ---- reduced (extended rational Krylov) stepping of long chains (kq > 0) ----
     int kq, krm;                        // reduction order q (blocks), columns at most 2q
     double keta;                        // shift-time scale eta (eq. 26)
@@ -157,6 +160,7 @@ struct Dev {
                                         //     node-steps advanced in reduced form
 };
 
+constexpr int SS_CL = 64;                // nodes per chunk of the many-sample skipping check
 constexpr int KRY_RM_MAX = 16;           // 2 q for q <= 8
 __host__ __device__ constexpr int KRY_KS(int rm) { return 2 * rm * rm + 2 * rm; }
 

@@ -1672,77 +1672,169 @@ EM_KERNEL void k_catchup_done(Dev d, int step_lim)
 // sums are FP64.  Skipped: an active chain instance without voids whose
 // band is within tol_abs and keeps every node below its critical stress.
 //
-// Two launch forms.  With 64 samples or more, one lane per instance and the
-// wavefront over 64 consecutive samples of one tree: every node's state,
-// forcing and diffusivity multiplier is one coalesced load, and each lane
-// walks its chain in order, so the prefix sums are running sums.  With fewer
-// samples, the chain kernel's lane table (each lane its block of chain_m
+// Two launch forms.  With 64 samples or more, the chunked passes below.  With
+// fewer samples, the chain kernel's lane table (each lane its block of chain_m
 // consecutive nodes, instances never straddling a workgroup): the lane's
 // loads issued together, then segmented scans over the instance's lanes in
 // LDS.
 // ------------------------------------------------------------------------
+// Many-sample form: one lane per sample, the wavefront over 64 consecutive
+// samples of one chain (every load coalesced), the chain cut into chunks of
+// SS_CL nodes walked in parallel.  Per chunk (pass a): sums of dt f, V and
+// the raw residual r, and of 1/(dt g), (the chunk's raw residual before the
+// node)/(dt g) and (its volume before the node)/(dt g) over the chunk's
+// edges.  Per instance (pass b): the forcing mean fm, then the chunks'
+// carries in order -- r' before the chunk, and P where it starts, since the
+// chunk adds carry G + H - fm K to P.  Per chunk (pass c): P at its nodes,
+// its extremes and the margin.  Per instance (pass d): the decision.
+// Scratch per (chunk, sample): 6 + 2 + 3 doubles; fm per instance.
 template <typename R>
-EM_KERNEL void k_ss_check_s(Dev d, double tol_abs)
-{
-    constexpr int B = 8;                         // nodes whose loads are issued together
-    const int lane = threadIdx.x & 63;
-    const int S = d.S, SW = (S + 63) / 64;
-    const long long w = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (w >= (long long)d.n_trees * SW) return;
-    const int t = (int)(w / SW), s0 = (int)(w - (long long)t * SW) * 64;
-    if (!d.tree_chain[t]) return;
-    const int s = min(s0 + lane, S - 1);          // lanes past S repeat the last sample, unused
-    const size_t inst = (size_t)t * S + s;
-    const bool act = s0 + lane < S && d.inst_active[inst] && d.sample_active[s] && d.nv[inst] == 0;
-    if (!__any(act)) return;
-    const R *sig = (const R *)d.sigma, *fv = (const R *)d.dtf, *sc = (const R *)d.sc, *Vr = (const R *)d.Vr;
-    const float *slo = d.sig_lo;
-    auto sv = [&](int i) -> double {
+struct SsView {
+    const Dev &d;
+    int S, s;
+    __device__ double sv(int i) const
+    {
         const size_t x = (size_t)i * S + s;
-        double v = (double)sig[x];
-        if (slo) v += (double)slo[x];
+        double v = (double)((const R *)d.sigma)[x];
+        if (d.sig_lo) v += (double)d.sig_lo[x];
         return v;
-    };
-    auto dtg = [&](int i) -> double {        // edge (i - 1, i)
+    }
+    __device__ double dtg(int i) const        // edge (i - 1, i)
+    {
         return (double)(R)(d.dt * d.xi_k[(size_t)d.seg[i] * S + s] * d.g0[i]);
-    };
+    }
+    __device__ double fv(int i) const { return (double)((const R *)d.dtf)[(size_t)i * S + s]; }
+    __device__ double vr(int i) const { return (double)((const R *)d.Vr)[i]; }
+    __device__ double sc(int i) const { return (double)((const R *)d.sc)[(size_t)i * S + s]; }
+};
+
+__device__ inline bool ss_lane(const Dev &d, long long w, bool by_chunk, int &t, int &s, int &cg, size_t &inst)
+{
+    const int S = d.S, SW = (S + 63) / 64, lane = threadIdx.x & 63;
+    const long long u = w / SW;
+    const int s0 = (int)(w - u * SW) * 64;
+    cg = by_chunk ? (int)u : -1;
+    t = by_chunk ? d.ss_ctree[cg] : (int)u;
+    s = min(s0 + lane, S - 1);                 // lanes past S repeat the last sample, unused
+    inst = (size_t)t * S + s;
+    return s0 + lane < S && d.tree_chain[t] && d.inst_active[inst] && d.sample_active[s] && d.nv[inst] == 0;
+}
+
+template <typename R>
+EM_KERNEL void k_ssc_a(Dev d)
+{
+    const long long w = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (w >= (long long)d.ss_nc * ((d.S + 63) / 64)) return;
+    int t, s, cg;
+    size_t inst;
+    const bool act = ss_lane(d, w, true, t, s, cg, inst);
+    if (!__any(act)) return;
+    const SsView<R> v{d, d.S, s};
     const int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
-    double fs = 0.0, vs = 0.0;
-    for (int c = i0; c < i1; c += B) {
-        double a[B], v[B];
+    const int c0 = d.ss_cstart[cg], c1 = min(c0 + SS_CL, i1);
+    double F = 0.0, Vs = 0.0, lr = 0.0, lv = 0.0, G = 0.0, H = 0.0, K = 0.0;
+    double sp = c0 > i0 ? v.sv(c0 - 1) : 0.0, si = v.sv(c0), gl = c0 > i0 ? v.dtg(c0) : 0.0;
+    for (int c = c0; c < c1; c += 8) {
+        double sn[8], gr[8], f[8], vv[8];
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-            a[k] = c + k < i1 ? (double)fv[(size_t)(c + k) * S + s] : 0.0;
-            v[k] = c + k < i1 ? (double)Vr[c + k] : 0.0;
+        for (int k = 0; k < 8; ++k) {
+            const int i = c + k;
+            const bool in = i < c1, nx = i + 1 < i1;
+            sn[k] = in && nx ? v.sv(i + 1) : 0.0;
+            gr[k] = in && nx ? v.dtg(i + 1) : 0.0;
+            f[k] = in ? v.fv(i) : 0.0;
+            vv[k] = in ? v.vr(i) : 0.0;
         }
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-            fs += a[k];
-            vs += v[k];
+        for (int k = 0; k < 8; ++k) {
+            const int i = c + k;
+            if (i >= c1) break;
+            double r = f[k] + gr[k] * (sn[k] - si);
+            if (i > i0) {
+                r += gl * (sp - si);
+                const double ig = 1.0 / gl;
+                G += ig;
+                H += lr * ig;
+                K += lv * ig;
+            }
+            F += f[k];
+            Vs += vv[k];
+            lr += r;
+            lv += vv[k];
+            sp = si;
+            si = sn[k];
+            gl = gr[k];
         }
     }
-    const double fm = fs / vs;
-    double pre = 0.0, lp = 0.0, pmax = -INFINITY, pmin = INFINITY, mmax = -INFINITY;
-    double sp = 0.0, gl = 0.0, si = sv(i0);
-    for (int c = i0; c < i1; c += B) {
-        // nodes c .. c+B-1: their right neighbours' states and edges, drive,
-        // volume and critical stress
-        double sn[B], gr[B], f[B], v[B], q[B];
+    if (!act) return;
+    const size_t S = d.S;
+    double *o = d.ss_scr + (size_t)cg * 6 * S + s;
+    o[0] = F; o[S] = Vs; o[2 * S] = lr; o[3 * S] = G; o[4 * S] = H; o[5 * S] = K;
+}
+
+EM_KERNEL void k_ssc_b(Dev d)
+{
+    const long long w = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (w >= (long long)d.n_trees * ((d.S + 63) / 64)) return;
+    int t, s, cg;
+    size_t inst;
+    if (!ss_lane(d, w, false, t, s, cg, inst)) return;
+    const size_t S = d.S, NC = d.ss_nc;
+    const int k0 = d.ss_coff[t], k1 = d.ss_coff[t + 1];
+    const double *a = d.ss_scr;
+    double *b = d.ss_scr + NC * 6 * S;
+    double F = 0.0, V = 0.0;
+    for (int c = k0; c < k1; ++c) {
+        F += a[(size_t)c * 6 * S + s];
+        V += a[((size_t)c * 6 + 1) * S + s];
+    }
+    const double fm = F / V;
+    double cr = 0.0, cp = 0.0;
+    for (int c = k0; c < k1; ++c) {
+        const double *q = a + (size_t)c * 6 * S + s;
+        b[(size_t)c * 2 * S + s] = cr;
+        b[((size_t)c * 2 + 1) * S + s] = cp;
+        cp += cr * q[3 * S] + q[4 * S] - fm * q[5 * S];
+        cr += q[2 * S] - fm * q[S];
+    }
+    d.ss_scr[NC * 11 * S + inst] = fm;
+}
+
+template <typename R>
+EM_KERNEL void k_ssc_c(Dev d)
+{
+    const long long w = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (w >= (long long)d.ss_nc * ((d.S + 63) / 64)) return;
+    int t, s, cg;
+    size_t inst;
+    const bool act = ss_lane(d, w, true, t, s, cg, inst);
+    if (!__any(act)) return;
+    const SsView<R> v{d, d.S, s};
+    const size_t S = d.S, NC = d.ss_nc;
+    const int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
+    const int c0 = d.ss_cstart[cg], c1 = min(c0 + SS_CL, i1);
+    const double fm = act ? d.ss_scr[NC * 11 * S + inst] : 0.0;
+    const double *b = d.ss_scr + NC * 6 * S;
+    double pre = act ? b[(size_t)cg * 2 * S + s] : 0.0, lp = act ? b[((size_t)cg * 2 + 1) * S + s] : 0.0;
+    double pmax = -INFINITY, pmin = INFINITY, mmax = -INFINITY;
+    double sp = c0 > i0 ? v.sv(c0 - 1) : 0.0, si = v.sv(c0), gl = c0 > i0 ? v.dtg(c0) : 0.0;
+    for (int c = c0; c < c1; c += 8) {
+        double sn[8], gr[8], f[8], vv[8], q[8];
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
+        for (int k = 0; k < 8; ++k) {
             const int i = c + k;
-            const bool in = i < i1, nx = i + 1 < i1;
-            sn[k] = nx ? sv(i + 1) : 0.0;
-            gr[k] = nx ? dtg(i + 1) : 0.0;
-            f[k] = in ? (double)fv[(size_t)i * S + s] : 0.0;
-            v[k] = in ? (double)Vr[i] : 0.0;
-            q[k] = in ? (double)sc[(size_t)i * S + s] : 0.0;
+            const bool in = i < c1, nx = i + 1 < i1;
+            sn[k] = in && nx ? v.sv(i + 1) : 0.0;
+            gr[k] = in && nx ? v.dtg(i + 1) : 0.0;
+            f[k] = in ? v.fv(i) : 0.0;
+            vv[k] = in ? v.vr(i) : 0.0;
+            q[k] = in ? v.sc(i) : 0.0;
         }
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
+        for (int k = 0; k < 8; ++k) {
             const int i = c + k;
-            if (i >= i1) break;
-            double r = f[k] - v[k] * fm + gr[k] * (sn[k] - si);
+            if (i >= c1) break;
+            double r = f[k] - vv[k] * fm + gr[k] * (sn[k] - si);
             if (i > i0) {
                 r += gl * (sp - si);
                 lp += pre / gl;
@@ -1756,7 +1848,28 @@ EM_KERNEL void k_ss_check_s(Dev d, double tol_abs)
             gl = gr[k];
         }
     }
-    if (act && pmax - pmin <= tol_abs && mmax + pmax < 0.0) {
+    if (!act) return;
+    double *o = d.ss_scr + NC * 8 * S + (size_t)cg * 3 * S + s;
+    o[0] = pmax; o[S] = pmin; o[2 * S] = mmax;
+}
+
+EM_KERNEL void k_ssc_d(Dev d, double tol_abs)
+{
+    const long long w = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (w >= (long long)d.n_trees * ((d.S + 63) / 64)) return;
+    int t, s, cg;
+    size_t inst;
+    if (!ss_lane(d, w, false, t, s, cg, inst)) return;
+    const size_t S = d.S, NC = d.ss_nc;
+    const double *c3 = d.ss_scr + NC * 8 * S;
+    double pmax = -INFINITY, pmin = INFINITY, mmax = -INFINITY;
+    for (int c = d.ss_coff[t]; c < d.ss_coff[t + 1]; ++c) {
+        const double *o = c3 + (size_t)c * 3 * S + s;
+        pmax = fmax(pmax, o[0]);
+        pmin = fmin(pmin, o[S]);
+        mmax = fmax(mmax, o[2 * S]);
+    }
+    if (pmax - pmin <= tol_abs && mmax + pmax < 0.0) {
         d.inst_active[inst] = 0;
         d.ss_skip[inst] = 1;
         atomicAdd(&d.ss_cnt[0], 1u);
@@ -1897,10 +2010,15 @@ EM_KERNEL void k_ss_wake(Dev d, int all)
 void launch_ss_check(const Dev &d, bool fp32, double tol_abs, hipStream_t st)
 {
     if (d.n_chain_wg <= 0 || d.chain_wg <= 0 || d.chain_wg > SS_WG_MAX) return;
-    if (d.S >= 64) {
-        const int nb = (int)(((long long)d.n_trees * ((d.S + 63) / 64) + 3) / 4);
-        if (fp32) k_ss_check_s<float><<<nb, 256, 0, st>>>(d, tol_abs);
-        else k_ss_check_s<double><<<nb, 256, 0, st>>>(d, tol_abs);
+    if (d.S >= 64 && d.ss_nc > 0 && d.ss_scr) {
+        const long long SW = (d.S + 63) / 64;
+        const int nbc = (int)((d.ss_nc * SW + 3) / 4), nbt = (int)(((long long)d.n_trees * SW + 3) / 4);
+        if (fp32) k_ssc_a<float><<<nbc, 256, 0, st>>>(d);
+        else k_ssc_a<double><<<nbc, 256, 0, st>>>(d);
+        k_ssc_b<<<nbt, 256, 0, st>>>(d);
+        if (fp32) k_ssc_c<float><<<nbc, 256, 0, st>>>(d);
+        else k_ssc_c<double><<<nbc, 256, 0, st>>>(d);
+        k_ssc_d<<<nbt, 256, 0, st>>>(d, tol_abs);
         return;
     }
     if (fp32) k_ss_check<float><<<d.n_chain_wg, d.chain_wg, 0, st>>>(d, tol_abs);
