@@ -1268,7 +1268,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
             UP(d.kry_list, kl);
             AL(d.kv, double, (size_t)d.krm * ns * S);
             AL(d.kred, double, ISk * KRY_KS(d.krm));
-            AL(d.kscr, double, (size_t)ns * S);
+            AL(d.kscr, double, 3 * (size_t)ns * S);
         }
         AL(d.kr, int, ISk);
         AL(d.kdone, uint8_t, ISk);

@@ -152,8 +152,8 @@ struct Dev {
     const int *kry_list;                // chain instances of at least max(3q, 30) nodes
     int n_kry_list;
     double *kv;                         // [krm][ns][S] basis columns
-    double *kred;                       // [inst][KRY_KS(krm)] A_h, C_h, f_h, z
-    double *kscr;                       // [ns][S] inverse pivots of K = s0 C - A
+    double *kred;                       // [inst][KRY_KS(krm)] A_h, C_h, f_h, z, F, g, dt of F
+    double *kscr;                       // [3][ns][S] inverse pivots and multipliers of K = s0 C - A
     int *kr;                            // [inst] basis columns (0: none)
     uint8_t *kdone;                     // [inst] interval taken in reduced form
     unsigned long long *kcnt;           // [4] bases built, reduced intervals, fallbacks,
@@ -162,7 +162,7 @@ struct Dev {
 
 constexpr int SS_CL = 64;                // nodes per chunk of the many-sample skipping check
 constexpr int KRY_RM_MAX = 16;           // 2 q for q <= 8
-__host__ __device__ constexpr int KRY_KS(int rm) { return 2 * rm * rm + 2 * rm; }
+__host__ __device__ constexpr int KRY_KS(int rm) { return 3 * rm * rm + 3 * rm + 1; }
 
 // Aggregation multigrid preconditioner of the IR solve.  Level 0 is the nodal
 // system on the free nodes; level l >= 1 has one node per aggregate of level

@@ -23,7 +23,8 @@
 // dropped (the exact state leaves the span).
 //
 // Layout: V columns [(c ns + i) S + s] (samples fastest, as the state); per
-// instance KS doubles: A_h, C_h (RM x RM), f_h, z (RM); pivots of K's
+// instance KS doubles: A_h, C_h (RM x RM), f_h, z (RM), the step operator F
+// (RM x RM), g (RM) and the step size they were formed for; pivots of K's
 // tridiagonal factorisation [i S + s].  Everything in FP64; the state is
 // written back in the batch's precision (FP32: high and low parts).
 #include "em_internal.h"
@@ -91,7 +92,9 @@ EM_KERNEL_KB void k_kry_basis(Dev d)
     const int tid = threadIdx.x, S = d.S, RM = d.krm;
     auto col = [&](int c, int i) -> double & { return d.kv[((size_t)c * d.ns + i) * S + s]; };
     auto ge = [&](int i) -> double { return d.xi_k[(size_t)d.seg[i] * S + s] * d.g0[i]; };   // edge (i-1, i)
-    double *ip = d.kscr;                // inverse pivots [i S + s]
+    // per node: inverse pivot, forward multiplier m_i = g_i / p_(i-1) and
+    // backward multiplier u_i = g_(i+1) / p_i of K's tridiagonal factorisation
+    double *ip = d.kscr, *mf = ip + (size_t)d.ns * S, *ub = mf + (size_t)d.ns * S;   // [i S + s]
     // shift (eq. 26)
     double a1 = 0.0, a2 = 0.0, a3 = 0.0;
     for (int i = i0 + tid; i < i1; i += KB) {
@@ -105,33 +108,62 @@ EM_KERNEL_KB void k_kry_basis(Dev d)
     const double kap = kb_sum(a1, sh) / kb_sum(a2, sh);
     const double L = kb_sum(a3, sh);
     const double s0 = M_PI * M_PI * kap / (d.keta * L * L);
-    // K = s0 C + L is tridiagonal along the chain: pivots in order (one thread)
+    // K = s0 C + L is tridiagonal along the chain: the edge conductances in
+    // parallel, then the pivots in order (one thread)
+    for (int i = i0 + tid; i < i1; i += KB) mf[(size_t)i * S + s] = i > i0 ? ge(i) : 0.0;
+    __syncthreads();
     if (tid == 0) {
-        double p = 0.0, gl = 0.0;
+        double p = 0.0;
         for (int i = i0; i < i1; ++i) {
-            const double gr = i + 1 < i1 ? ge(i + 1) : 0.0;
+            const double gl = mf[(size_t)i * S + s], gr = i + 1 < i1 ? mf[(size_t)(i + 1) * S + s] : 0.0;
             const double D = s0 * d.V[i] + gl + gr;
-            p = i > i0 ? D - gl * gl * p : D;          // p: the previous inverse pivot
-            p = 1.0 / p;
-            ip[(size_t)i * S + s] = p;
-            gl = gr;
+            const double np = 1.0 / (i > i0 ? D - gl * gl * p : D);    // p: the previous inverse pivot
+            ip[(size_t)i * S + s] = np;
+            ub[(size_t)i * S + s] = gr * np;
+            if (i > i0) mf[(size_t)i * S + s] = gl * p;
+            p = np;
         }
     }
     __syncthreads();
-    // column c <- K^-1 column c (forward and back substitution, one thread)
+    // column c <- K^-1 column c: y_i = b_i + m_i y_(i-1), then
+    // x_i = p_i^-1 y_i + u_i x_(i+1) (one thread, loads issued eight nodes at a time)
     auto solve = [&](int c) {
         if (tid == 0) {
             double y = 0.0;
-            for (int i = i0; i < i1; ++i) {
-                const double b = col(c, i);
-                y = i > i0 ? b + ge(i) * ip[(size_t)(i - 1) * S + s] * y : b;
-                col(c, i) = y;
+            for (int i = i0; i < i1; i += 8) {
+                double b[8], m[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    b[k] = i + k < i1 ? col(c, i + k) : 0.0;
+                    m[k] = i + k < i1 ? mf[(size_t)(i + k) * S + s] : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    y = b[k] + m[k] * y;              // m = 0 at the chain's first node
+                    b[k] = y;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (i + k < i1) col(c, i + k) = b[k];
             }
             double x = 0.0;
-            for (int i = i1 - 1; i >= i0; --i) {
-                const double yi = col(c, i);
-                x = (i + 1 < i1 ? yi + ge(i + 1) * x : yi) * ip[(size_t)i * S + s];
-                col(c, i) = x;
+            for (int i = i1 - 1; i >= i0; i -= 8) {
+                double yv[8], pv[8], uv[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const bool in = i - k >= i0;
+                    yv[k] = in ? col(c, i - k) : 0.0;
+                    pv[k] = in ? ip[(size_t)(i - k) * S + s] : 0.0;
+                    uv[k] = in ? ub[(size_t)(i - k) * S + s] : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    x = pv[k] * yv[k] + uv[k] * x;     // u = 0 at the chain's last node
+                    yv[k] = x;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (i - k >= i0) col(c, i - k) = yv[k];
             }
         }
         __syncthreads();
@@ -212,6 +244,7 @@ EM_KERNEL_KB void k_kry_basis(Dev d)
         }
     }
     if (tid == 0) {
+        kh[3 * RM * RM + 3 * RM] = 0.0;        // step operator not formed yet
         d.kr[inst] = r;
         atomicAdd(&d.kcnt[0], 1ull);
     }
@@ -219,104 +252,110 @@ EM_KERNEL_KB void k_kry_basis(Dev d)
 
 // n_steps of reduced backward Euler for every instance with a basis; the
 // lifted end state replaces the state when the interval provably stays below
-// every critical stress (the instance then sits out the exact launch).
+// every critical stress (the instance then sits out the exact launch).  One
+// wavefront per instance: the step operator F = (C_h - dt A_h)^-1 C_h and
+// g = dt (C_h - dt A_h)^-1 f_h are formed once per basis and step size (one
+// lane, LU without pivoting: C_h - dt A_h is symmetric positive definite) and
+// kept with the basis; lane a holds row a of F in registers, so a step is r
+// shuffles and multiply-adds per lane.
+constexpr int KW = 64;
+
 template <typename R>
-EM_KERNEL_KB void k_kry_step(Dev d, int n_steps)
+__global__ __launch_bounds__(KW) void k_kry_step(Dev d, int n_steps)
 {
-    __shared__ double sh[KB / 64];
-    __shared__ double M[KRY_RM_MAX * KRY_RM_MAX], F[KRY_RM_MAX * KRY_RM_MAX];
-    __shared__ double g[KRY_RM_MAX], z0[KRY_RM_MAX], ze[KRY_RM_MAX], s_dist;
+    __shared__ double M[KRY_RM_MAX * KRY_RM_MAX], ze_s[KRY_RM_MAX];
     const int inst = d.kry_list[blockIdx.x];
     int s, i0, i1;
     if (!kry_eligible(d, inst, s, i0, i1)) return;
     const int r = d.kr[inst];
     if (r <= 0) return;
-    const int tid = threadIdx.x, S = d.S, RM = d.krm;
+    const int lane = threadIdx.x, S = d.S, RM = d.krm;
     double *kh = d.kred + (size_t)inst * KRY_KS(RM);
     const double *Ah = kh, *Ch = kh + RM * RM, *fh = kh + 2 * RM * RM;
-    double *z = kh + 2 * RM * RM + RM;
-    if (tid == 0) {
-        const double dt = d.dt;
-        for (int a = 0; a < r; ++a)
-            for (int b = 0; b < r; ++b) M[a * r + b] = Ch[a * RM + b] - dt * Ah[a * RM + b];
-        // M = LU in place (M is symmetric positive definite: no pivoting)
-        for (int k = 0; k < r; ++k)
-            for (int a = k + 1; a < r; ++a) {
-                const double l = M[a * r + k] / M[k * r + k];
-                M[a * r + k] = l;
-                for (int b = k + 1; b < r; ++b) M[a * r + b] -= l * M[k * r + b];
-            }
-        auto lu_solve = [&](double *x) {
+    double *z = kh + 2 * RM * RM + RM, *F = z + RM, *g = F + RM * RM, *dtF = g + RM;
+    const double dt = d.dt;
+    if (*dtF != dt) {                          // a new basis or a new step size
+        if (lane == 0) {
+            for (int a = 0; a < r; ++a)
+                for (int b = 0; b < r; ++b) M[a * r + b] = Ch[a * RM + b] - dt * Ah[a * RM + b];
+            for (int k = 0; k < r; ++k)
+                for (int a = k + 1; a < r; ++a) {
+                    const double l = M[a * r + k] / M[k * r + k];
+                    M[a * r + k] = l;
+                    for (int b = k + 1; b < r; ++b) M[a * r + b] -= l * M[k * r + b];
+                }
+        }
+        __syncthreads();
+        // column c of F (c < r) and, on lane r, g: one triangular pair each
+        if (lane <= r) {
+            double x[KRY_RM_MAX];
+            for (int a = 0; a < r; ++a) x[a] = lane < r ? Ch[a * RM + lane] : dt * fh[a];
             for (int a = 1; a < r; ++a)
                 for (int b = 0; b < a; ++b) x[a] -= M[a * r + b] * x[b];
             for (int a = r - 1; a >= 0; --a) {
                 for (int b = a + 1; b < r; ++b) x[a] -= M[a * r + b] * x[b];
                 x[a] /= M[a * r + a];
             }
-        };
-        double x[KRY_RM_MAX];
-        for (int c = 0; c < r; ++c) {           // F = M^-1 C_h, column by column
-            for (int a = 0; a < r; ++a) x[a] = Ch[a * RM + c];
-            lu_solve(x);
-            for (int a = 0; a < r; ++a) F[a * r + c] = x[a];
-        }
-        for (int a = 0; a < r; ++a) x[a] = dt * fh[a];
-        lu_solve(x);
-        for (int a = 0; a < r; ++a) {
-            g[a] = x[a];
-            z0[a] = z[a];
-        }
-        double zc[KRY_RM_MAX], zn[KRY_RM_MAX];
-        for (int a = 0; a < r; ++a) zc[a] = z0[a];
-        for (int k = 0; k < n_steps; ++k) {
             for (int a = 0; a < r; ++a) {
-                double v = g[a];
-                for (int b = 0; b < r; ++b) v += F[a * r + b] * zc[b];
-                zn[a] = v;
+                if (lane < r) F[a * RM + lane] = x[a];
+                else g[a] = x[a];
             }
-            for (int a = 0; a < r; ++a) zc[a] = zn[a];
         }
-        for (int a = 0; a < r; ++a) ze[a] = zc[a];
-        // the largest distance of a reduced state of the interval from its end
-        double dist = 0.0;
-        for (int a = 0; a < r; ++a) zc[a] = z0[a];
-        for (int k = 0; k <= n_steps; ++k) {
-            double q = 0.0;
-            for (int a = 0; a < r; ++a) q += (zc[a] - ze[a]) * (zc[a] - ze[a]);
-            dist = fmax(dist, sqrt(q));
-            if (k == n_steps) break;
-            for (int a = 0; a < r; ++a) {
-                double v = g[a];
-                for (int b = 0; b < r; ++b) v += F[a * r + b] * zc[b];
-                zn[a] = v;
-            }
-            for (int a = 0; a < r; ++a) zc[a] = zn[a];
-        }
-        s_dist = dist;
+        __syncthreads();
+        if (lane == 0) *dtF = dt;
+        __threadfence_block();
+        __syncthreads();
     }
+    // row `lane` of F in registers
+    double fr[KRY_RM_MAX];
+#pragma unroll
+    for (int b = 0; b < KRY_RM_MAX; ++b) fr[b] = (lane < r && b < r) ? F[lane * RM + b] : 0.0;
+    const double gl = lane < r ? g[lane] : 0.0, z0 = lane < r ? z[lane] : 0.0;
+    auto step = [&](double zc) -> double {
+        double v = gl;
+#pragma unroll
+        for (int b = 0; b < KRY_RM_MAX; ++b)
+            if (b < r) v += fr[b] * __shfl(zc, b, 64);
+        return v;
+    };
+    double zc = z0;
+    for (int k = 0; k < n_steps; ++k) zc = step(zc);
+    const double ze = zc;
+    // the largest distance of a reduced state of the interval from its end
+    double dist = 0.0;
+    zc = z0;
+    for (int k = 0; k <= n_steps; ++k) {
+        double q = lane < r ? (zc - ze) * (zc - ze) : 0.0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
+        dist = fmax(dist, sqrt(q));
+        if (k < n_steps) zc = step(zc);
+    }
+    if (lane < r) ze_s[lane] = ze;
     __syncthreads();
     const R *sc = (const R *)d.sc;
     auto lift = [&](int i) -> double {
         double v = 0.0;
-        for (int c = 0; c < r; ++c) v += d.kv[((size_t)c * d.ns + i) * S + s] * ze[c];
+        for (int c = 0; c < r; ++c) v += d.kv[((size_t)c * d.ns + i) * S + s] * ze_s[c];
         return v;
     };
     double mg = -INFINITY;
-    for (int i = i0 + tid; i < i1; i += KB) mg = fmax(mg, lift(i) - (double)sc[(size_t)i * S + s]);
-    mg = kb_max(mg, sh);
-    const bool ok = mg + s_dist < 0.0;
+    for (int i = i0 + lane; i < i1; i += KW) mg = fmax(mg, lift(i) - (double)sc[(size_t)i * S + s]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mg = fmax(mg, __shfl_xor(mg, o, 64));
+    const bool ok = mg + dist < 0.0;
     if (ok) {
         R *sig = (R *)d.sigma;
-        for (int i = i0 + tid; i < i1; i += KB) {
+        for (int i = i0 + lane; i < i1; i += KW) {
             const size_t x = (size_t)i * S + s;
             const double v = lift(i);
             sig[x] = (R)v;
             if (d.sig_lo) d.sig_lo[x] = (float)(v - (double)(R)v);
         }
+        if (lane < r) z[lane] = ze;
     }
-    if (tid == 0) {
+    if (lane == 0) {
         if (ok) {
-            for (int a = 0; a < r; ++a) z[a] = ze[a];
             d.kdone[inst] = 1;
             d.inst_active[inst] = 0;
             atomicAdd(&d.kcnt[1], 1ull);
@@ -352,10 +391,10 @@ void launch_kry_step(const Dev &d, bool fp32, int n_steps, hipStream_t st)
     if (n <= 0 || d.kq <= 0) return;
     if (fp32) {
         k_kry_basis<float><<<n, KB, 0, st>>>(d);
-        k_kry_step<float><<<n, KB, 0, st>>>(d, n_steps);
+        k_kry_step<float><<<n, KW, 0, st>>>(d, n_steps);
     } else {
         k_kry_basis<double><<<n, KB, 0, st>>>(d);
-        k_kry_step<double><<<n, KB, 0, st>>>(d, n_steps);
+        k_kry_step<double><<<n, KW, 0, st>>>(d, n_steps);
     }
 }
 
