@@ -104,6 +104,11 @@ CASES = {
     "bad run parameters (multigrid scale)": lambda g, m, r, mc: r.__setitem__("amg_alpha", 0.5),
     "bad run parameters (steady-state tolerance)": lambda g, m, r, mc: r.__setitem__("ss_tol", -1e-6),
     "bad run parameters (steady-state tolerance, huge)": lambda g, m, r, mc: r.__setitem__("ss_tol", 0.05),
+    "bad run parameters (Krylov order)": lambda g, m, r, mc: r.__setitem__("krylov_q", 9),
+    "bad run parameters (Krylov order, negative)": lambda g, m, r, mc: r.__setitem__("krylov_q", -1),
+    "bad run parameters (Krylov shift scale)": lambda g, m, r, mc: r.__setitem__("krylov_eta", -0.5),
+    "reduced (Krylov) stepping and steady-state skipping are exclusive":
+        lambda g, m, r, mc: r.update(krylov_q=4, ss_tol=1e-6),
 }
 
 
