@@ -657,7 +657,7 @@ def skip_leg(args, name, n_samples=None, tol=1e-6, reps=3):
             "stress_bound_Pa": tol * mat["sigma_crit"]}
 
 
-def krylov_leg(args, name, n_samples=None, q=4, reps=3):
+def krylov_leg(args, name, n_samples=None, q=6, reps=3):
     """Reduced (extended rational Krylov) stepping of the long chains against
     exact elimination: the immortality screen off, the same batch run to the
     horizon with krylov_q = q and without (best of reps each, after an

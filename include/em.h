@@ -236,8 +236,9 @@ typedef struct {
                                     K = s0 C - A, s0 = 1/t_s (eq. 26), and step the reduced
                                     model by backward Euler, lifting the state at each call's
                                     end; an interval whose lifted states could reach a critical
-                                    stress (bound: the reduced states' distance from the end
-                                    state) is stepped exactly instead and the basis dropped.  A
+                                    stress (bound: each node's row norm of the basis times the
+                                    reduced states' distance from the end state) is stepped
+                                    exactly instead and the basis dropped.  A
                                     basis is kept while the drive is unchanged (an IR re-solve
                                     that changes the sample's conductances, em_set_stress,
                                     em_set_seg_state, em_inject_void, em_restore and em_reset

@@ -168,8 +168,8 @@ def interval(sim, topo, grid, bases, active, n_steps, step0, dt, q, eta):
     """One aging interval of one sample with the reduced path: every active
     chain of at least max(3q, 30) nodes without voids builds (or keeps) its
     basis and steps the reduced model; the interval is kept in reduced form
-    when max_i(s_end,i - sigma_crit,i) + max_k |z_k - z_end|_2 < 0 (the lifted
-    states cannot reach a critical stress), else the chain is stepped exactly
+    when max_i(s_end,i - sigma_crit,i + |V_i|_2 max_k |z_k - z_end|_2) < 0
+    (the lifted states cannot reach a critical stress), else the chain is stepped exactly
     and its basis dropped.  The other trees are stepped exactly.  bases maps
     tree -> ChainBasis and persists across intervals."""
     arr = sim.node_arrays()
@@ -205,7 +205,8 @@ def interval(sim, topo, grid, bases, active, n_steps, step0, dt, q, eta):
         ze = zs[-1]
         dist = max(float(np.linalg.norm(zk - ze)) for zk in zs)
         s_end = b.V @ ze
-        if np.max(s_end - arr["sc"][i0:i1]) + dist < 0.0:
+        rown = np.sqrt(np.sum(b.V * b.V, axis=1))      # node i moves by at most |V_i| dist
+        if np.max(s_end - arr["sc"][i0:i1] + rown * dist) < 0.0:
             sig[i0:i1] = s_end
             b.z = ze
             exact[t] = 0

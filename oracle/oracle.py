@@ -446,7 +446,7 @@ def run_sample(grid, mat, run, mc=None, sample=0, topo=None, keep_sim=False, max
             active[:] = tm
             res["tree_mortal"], res["seg_mortal"] = tm, sm
         fail = float(run["fail_frac"])
-        seg_prev = None
+        seg_prev = sim.seg_state()                   # the conductances of the last IR solve
         # time grid: interval k (ir_every steps) steps with dt * dt_growth^k
         growth = float(run.get("dt_growth", 0.0)) or 1.0
         t_now = 0.0
@@ -469,7 +469,7 @@ def run_sample(grid, mat, run, mc=None, sample=0, topo=None, keep_sim=False, max
                 done += nst
                 t_now += nst * dt_k
                 dR, op = sim.seg_state()
-                if seg_prev is not None and (np.any(dR != seg_prev[0]) or np.any(op != seg_prev[1])):
+                if np.any(dR != seg_prev[0]) or np.any(op != seg_prev[1]):
                     bases.clear()                       # new conductances: a new drive
                 seg_prev = (dR.copy(), op.copy())
                 u, I, j, dk = ir_solve(gs, R0 + dR, op)

@@ -16,9 +16,9 @@
 // reduced interval and kept while both stay in its span: the state does (it
 // is V z), the drive until an IR re-solve changes the sample's conductances.
 // An interval is taken in reduced form only when the lifted states provably
-// stay below every critical stress: |V_i . (z_k - z_end)| <= |z_k - z_end|_2
-// (the rows of an orthonormal V have norm at most 1), so
-// max_i (s_end,i - sigma_crit,i) + max_k |z_k - z_end|_2 < 0 suffices;
+// stay below every critical stress: |V_i . (z_k - z_end)| <= |V_i|_2
+// |z_k - z_end|_2 (V_i the node's row of V), so
+// max_i (s_end,i - sigma_crit,i + |V_i|_2 max_k |z_k - z_end|_2) < 0 suffices;
 // otherwise the interval is stepped by the exact chain kernel and the basis
 // dropped (the exact state leaves the span).
 //
@@ -339,11 +339,20 @@ __global__ __launch_bounds__(KW) void k_kry_step(Dev d, int n_steps)
         for (int c = 0; c < r; ++c) v += d.kv[((size_t)c * d.ns + i) * S + s] * ze_s[c];
         return v;
     };
+    // node i moves by |V_i . (z_k - z_end)| <= |V_i|_2 |z_k - z_end|_2 during the interval
     double mg = -INFINITY;
-    for (int i = i0 + lane; i < i1; i += KW) mg = fmax(mg, lift(i) - (double)sc[(size_t)i * S + s]);
+    for (int i = i0 + lane; i < i1; i += KW) {
+        double v = 0.0, w = 0.0;
+        for (int c = 0; c < r; ++c) {
+            const double e = d.kv[((size_t)c * d.ns + i) * S + s];
+            v += e * ze_s[c];
+            w += e * e;
+        }
+        mg = fmax(mg, v - (double)sc[(size_t)i * S + s] + sqrt(w) * dist);
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) mg = fmax(mg, __shfl_xor(mg, o, 64));
-    const bool ok = mg + dist < 0.0;
+    const bool ok = mg < 0.0;
     if (ok) {
         R *sig = (R *)d.sigma;
         for (int i = i0 + lane; i < i1; i += KW) {

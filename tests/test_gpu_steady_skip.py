@@ -111,3 +111,21 @@ def test_skipping_on_a_graded_time_grid(em):
         assert abs(r0[s]["final_drop"] - r1[s]["final_drop"]) <= 1e-6 * r0[s]["final_drop"], s
     worst = max(float(np.max(np.abs(st0[s] - st1[s]))) for s in picks)
     assert worst <= 1.01 * TOL * mat["sigma_crit"]
+
+
+def test_skipping_in_the_1024_lane_chain_form(em):
+    """Lines of 4241-5121 nodes (FP32 1024-lane chain form, lane-table check
+    with 1024-thread workgroups), screen off: the full run's results."""
+    g, mat, rn, mc = synth.workload("long_lines")
+    mc = dict(mc, n_samples=8)
+    rn = dict(rn, screen=0)
+    picks = list(range(8))
+    r0, i0, st0, _, _ = _run(em, g, mat, rn, mc, picks)
+    r1, i1, st1, _, _ = _run(em, g, mat, dict(rn, ss_tol=1e-4), mc, picks)
+    assert i1["chain_wg"] == 1024
+    print(f"skipped {i1['n_ss_skipped']}, node-steps {i1['node_steps']} vs {i0['node_steps']}", flush=True)
+    for s in picks:
+        assert r0[s]["failed"] == r1[s]["failed"] and r0[s]["outer_idx"] == r1[s]["outer_idx"], s
+        assert abs(r0[s]["final_drop"] - r1[s]["final_drop"]) <= 1e-6 * r0[s]["final_drop"], s
+    worst = max(float(np.max(np.abs(st0[s] - st1[s]))) for s in picks)
+    assert worst <= 1.01 * 1e-4 * mat["sigma_crit"] + 1e-6 * max(float(np.abs(st0[s]).max()) for s in picks)
