@@ -701,6 +701,50 @@ def krylov_leg(args, name, n_samples=None, q=6, reps=3):
             "max_stress_rel_err": srel}
 
 
+def adaptive_leg(args, name, sigma_crit=None, screen=0, levels=3, reps=3):
+    """The adaptive time grid (dt_adapt: up to dt 2^levels between
+    nucleations, back to dt after one) against the uniform grid on the same
+    one-sample batch: run time to failure or the horizon (best of reps, after
+    an untimed run), re-solves, and the TTF / final drop difference (the
+    adaptive grid's discretisation error against the uniform one)."""
+    import numpy as np
+    import torch
+    import paper_2604_10743_amd as P
+    from paper_2604_10743_amd import synth
+
+    g, mat, run, _ = synth.workload(name)
+    if sigma_crit:
+        mat = dict(mat, sigma_crit=sigma_crit)
+    legs = {}
+    for label, lv in (("uniform", 0), ("adaptive", levels)):
+        B = P.Batch(g, mat, dict(run, prec=args.prec, screen=screen, dt_adapt=lv))
+        B.autotune(run["ir_every"])
+        B.run_to_ttf()
+        best, res = 1e30, None
+        for _ in range(reps):
+            B.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = B.run_to_ttf()[0]
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        i = B.info()
+        B.close()
+        legs[label] = (best, res, i)
+    (tu, ru, iu), (ta, ra, ia) = legs["uniform"], legs["adaptive"]
+    o = {"workload": f"{name}{f' with sigma_crit {sigma_crit / 1e6:g} MPa' if sigma_crit else ''}, "
+                     f"screen {'on' if screen else 'off'}, FP32, one run to failure or the horizon, "
+                     f"dt_adapt {levels}",
+         "uniform_ms": tu * 1e3, "adaptive_ms": ta * 1e3, "speedup": tu / ta,
+         "resolves_uniform": ru["outer_idx"], "resolves_adaptive": ra["outer_idx"],
+         "node_steps_uniform": iu["node_steps"], "node_steps_adaptive": ia["node_steps"],
+         "failed": [ru["failed"], ra["failed"]], "ttf_s": [ru["ttf_s"], ra["ttf_s"]],
+         "final_drop": [ru["final_drop"], ra["final_drop"]]}
+    if ru["failed"] and ra["failed"]:
+        o["ttf_rel_diff"] = abs(ra["ttf_s"] - ru["ttf_s"]) / ru["ttf_s"]
+    return o
+
+
 def thermal_leg(args):
     """Equal-average thermal maps (the paper's thermal-profile observation):
     the mc_grid network under a uniform map, four hotspots over the wires of
@@ -772,6 +816,7 @@ def main():
     ap.add_argument("--only-sur", action="store_true", help="run the learned-screen leg only")
     ap.add_argument("--only-skip", action="store_true", help="run the steady-state skipping legs only")
     ap.add_argument("--only-krylov", action="store_true", help="run the reduced (Krylov) stepping legs only")
+    ap.add_argument("--only-adaptive", action="store_true", help="run the adaptive time grid legs only")
     ap.add_argument("--sur-grids", type=int, default=24, help="label grids for the learned screen")
     ap.add_argument("--sur-label-samples", type=int, default=1024)
     ap.add_argument("--sur-steps", type=int, default=3000, help="Adam steps of the screen model")
@@ -822,6 +867,12 @@ def main():
                           "mc_skip": skip_leg(args, "mc_grid", n_samples=256)}), flush=True)
         return
 
+    if args.only_adaptive:
+        print(json.dumps({"fullchip_adaptive": adaptive_leg(args, "fullchip"),
+                          "pg400_voids_adaptive": adaptive_leg(args, "pg400", sigma_crit=200e6, screen=1)}),
+              flush=True)
+        return
+
     if args.only_krylov:
         print(json.dumps({"fullchip_krylov": krylov_leg(args, "fullchip"),
                           "pg400_krylov": krylov_leg(args, "pg400")}), flush=True)
@@ -846,6 +897,9 @@ def main():
     out["fullchip_krylov"] = krylov_leg(args, "fullchip")
     out["pg400_krylov"] = krylov_leg(args, "pg400")
     log("bench: reduced (Krylov) stepping legs done")
+    out["fullchip_adaptive"] = adaptive_leg(args, "fullchip")
+    out["pg400_voids_adaptive"] = adaptive_leg(args, "pg400", sigma_crit=200e6, screen=1)
+    log("bench: adaptive time grid legs done")
     if not args.no_mc:
         out["fullchip_mc"] = mc_leg(args, "fullchip", oracle=False, plain=False, n_samples=args.fc_samples)
         log("bench: fullchip mc done")

@@ -248,6 +248,15 @@ typedef struct {
     double krylov_eta;           /* shift-time scale eta of eq. 26, t_s = eta L^2 / (pi^2 kappa)
                                     with L the chain's length and kappa its volume-weighted
                                     diffusivity; 0 means 1, else in (0, 100] */
+    int32_t dt_adapt;            /* em_run_to_ttf: adaptive time grid, 0 = off, else in [1, 12]:
+                                    aging interval k takes ir_every steps of dt 2^m_k, m_0 = 0,
+                                    m_(k+1) = 0 after an interval in which a void nucleated
+                                    (any sample of the batch) and min(m_k + 1, dt_adapt)
+                                    otherwise; the run ends at the horizon n_steps dt, its last
+                                    interval's steps shortened to end there.  Coarse steps where
+                                    nothing nucleates, fine ones while voids form and grow.  The
+                                    batch's samples share the grid.  Not with dt_growth or a
+                                    learned screen. */
 } em_run_params;
 
 /* Monte Carlo (Sec. IV-F): unit-mean lognormal multipliers with coefficient

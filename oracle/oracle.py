@@ -23,6 +23,7 @@ Parity unpinned: nothing here reproduces a number of the paper's own designs
 from __future__ import annotations
 
 import ctypes as C
+import math
 import dataclasses
 import os
 import subprocess
@@ -458,16 +459,34 @@ def run_sample(grid, mat, run, mc=None, sample=0, topo=None, keep_sim=False, max
             res.update(ttf=0.0, failed=1)
         else:
             k = 0
-            while done < n_steps:
+            # adaptive grid (dt_adapt > 0): K steps of dt 2^m per interval, m
+            # back to 0 after an interval in which a void nucleated and one
+            # level up (to dt_adapt) after one without; the last interval's
+            # steps shortened to end at the horizon n_steps dt
+            amax = int(run.get("dt_adapt", 0))
+            horizon = n_steps * float(run["dt"])
+            m = 0
+            times = []
+            while (t_now < horizon * (1.0 - 1e-12)) if amax > 0 else (done < n_steps):
                 if max_outer is not None and k >= max_outer:
                     break
                 dt_k = float(run["dt"]) * growth ** k
-                k += 1
                 nst = min(K, n_steps - done)
+                if amax > 0:
+                    dt_k = math.ldexp(float(run["dt"]), m)
+                    rem = horizon - t_now
+                    nst = max(1, int(min(K, math.ceil(rem / dt_k - 1e-9))))
+                    if nst * dt_k > rem:
+                        dt_k = rem / nst
+                k += 1
+                n_ev = lib().ora_n_events(sim._h)
                 sim.set_dt(dt_k)
                 step_interval(nst, done, dt_k)
+                if amax > 0:
+                    m = 0 if lib().ora_n_events(sim._h) > n_ev else min(m + 1, amax)
                 done += nst
                 t_now += nst * dt_k
+                times.append(t_now)
                 dR, op = sim.seg_state()
                 if np.any(dR != seg_prev[0]) or np.any(op != seg_prev[1]):
                     bases.clear()                       # new conductances: a new drive
@@ -484,6 +503,7 @@ def run_sample(grid, mat, run, mc=None, sample=0, topo=None, keep_sim=False, max
                 sim.set_j(j)
                 t_prev, d_prev = t, dk
         res["drops"] = np.array(drops)
+        res["times"] = np.array(times) if d0 < fail else np.zeros(0)
         res["u"] = u
     dR, op = sim.seg_state()
     res["dR"], res["open"] = dR, op

@@ -72,7 +72,7 @@ class RunParams(C.Structure):
                 ("chain_wg", C.c_int32), ("chain_occ", C.c_int32), ("joule", C.c_int32),
                 ("dt_growth", C.c_double), ("chain_m", C.c_int32), ("guard_band", C.c_double),
                 ("guard_ttf", C.c_double), ("amg_alpha", C.c_double), ("ss_tol", C.c_double),
-                ("krylov_q", C.c_int32), ("krylov_eta", C.c_double)]
+                ("krylov_q", C.c_int32), ("krylov_eta", C.c_double), ("dt_adapt", C.c_int32)]
 
 
 class MCParams(C.Structure):
@@ -224,7 +224,8 @@ class Batch:
                       guard_ttf=float(run.get("guard_ttf", 0.0)),
                       amg_alpha=float(run.get("amg_alpha", 0.0)),
                       ss_tol=float(run.get("ss_tol", 0.0)),
-                      krylov_q=int(run.get("krylov_q", 0)), krylov_eta=float(run.get("krylov_eta", 0.0)))
+                      krylov_q=int(run.get("krylov_q", 0)), krylov_eta=float(run.get("krylov_eta", 0.0)),
+                      dt_adapt=int(run.get("dt_adapt", 0)))
         mcp = None
         if mc is not None:
             mcp = MCParams(struct_size=C.sizeof(MCParams), n_samples=int(mc["n_samples"]),

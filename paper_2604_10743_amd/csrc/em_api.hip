@@ -365,6 +365,10 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
                                    "0 <= krylov_q <= 8, 0 <= krylov_eta <= 100)");
     if (r->krylov_q > 0 && r->ss_tol > 0)
         return fail(b, EM_ERR_ARG, "reduced (Krylov) stepping and steady-state skipping are exclusive");
+    if (r->dt_adapt < 0 || r->dt_adapt > 12)
+        return fail(b, EM_ERR_ARG, "bad run parameters (0 <= dt_adapt <= 12)");
+    if (r->dt_adapt > 0 && r->dt_growth > 0 && r->dt_growth != 1.0)
+        return fail(b, EM_ERR_ARG, "the adaptive and the graded time grids are exclusive");
     if (r->joule) {
         const double tv[] = {m->k_cu, m->k_ild, m->t_ild};
         if (!finite_all(tv, 3) || !(m->k_cu > 0) || !(m->k_ild > 0) || !(m->t_ild > 0))
@@ -1819,8 +1823,9 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
     if (!b || !out) return fail(b, EM_ERR_ARG, "null output");
     if (b->trees_only) return fail(b, EM_ERR_STATE, "trees-only batch has no IR coupling");
     const bool graded = b->run.dt_growth > 0 && b->run.dt_growth != 1.0;
-    if (graded && b->sur)
-        return fail(b, EM_ERR_STATE, "a graded time grid cannot be combined with the learned screen");
+    const int amax = b->run.dt_adapt;          // adaptive grid: interval step dt 2^m, m <= amax
+    if ((graded || amax > 0) && b->sur)
+        return fail(b, EM_ERR_STATE, "a graded or adaptive time grid cannot be combined with the learned screen");
     const bool ssk = b->run.ss_tol > 0;
     if (ssk && b->sur)
         return fail(b, EM_ERR_STATE, "steady-state skipping cannot be combined with the learned screen");
@@ -1852,18 +1857,21 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
         if (rc != EM_OK) return rc;
     }
     const size_t cnt_off = (std::max<size_t>(S, 8) + 15) & ~(size_t)15;
-    uint8_t *h = pinned(b, cnt_off + 48);
+    uint8_t *h = pinned(b, cnt_off + 64);
     if (!h) return fail(b, EM_ERR_OOM, "pinned host buffer");
     unsigned int *hcnt = (unsigned int *)(h + cnt_off);
     unsigned int *hss = hcnt + 8;
-    unsigned int n_activated = 0, ss_seen = 0;
+    unsigned int *hev = hss + 2;               // event count at the top of each interval
+    unsigned int n_activated = 0, ss_seen = 0, ev_prev = 0;
+    int m_adapt = 0;
+    const double horizon = (double)n_steps * b->run.dt;
     if (ssk) {
         if ((rc = ss_begin(b)) != EM_OK) return rc;
         hss[0] = hss[1] = 0;
     }
     int done = 0, k = 0;
     double t_now = 0.0;                   // time at the end of the last interval
-    while (done < n_steps) {
+    while (amax > 0 ? t_now < horizon * (1.0 - 1e-12) : done < n_steps) {
         if (sur) {
             HIPCHK(b, hipMemcpyAsync(b->jhist + (size_t)k * S * b->n_res, d.jseg, 8 * (size_t)S * b->n_res,
                                      hipMemcpyDeviceToDevice, st));
@@ -1893,7 +1901,14 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
         }
         HIPCHK(b, hipMemcpyAsync(h, d.sample_active, S, hipMemcpyDeviceToHost, st));
         if (ssk) HIPCHK(b, hipMemcpyAsync(hss, d.ss_cnt, 8, hipMemcpyDeviceToHost, st));
+        if (amax > 0) HIPCHK(b, hipMemcpyAsync(hev, d.ev_count, 4, hipMemcpyDeviceToHost, st));
         HIPCHK(b, hipStreamSynchronize(st));
+        if (amax > 0) {
+            // adaptive grid: the step doubles after an interval without a new
+            // nucleation (up to dt 2^amax) and returns to dt after one that had one
+            if (k > 0) m_adapt = *hev != ev_prev ? 0 : std::min(m_adapt + 1, amax);
+            ev_prev = *hev;
+        }
         if (ssk && hss[0] + hss[1] != ss_seen) {       // skips or wakes: rebuild the lane table
             ss_seen = hss[0] + hss[1];
             b->act_dirty = true;
@@ -1902,7 +1917,15 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
         for (int s = 0; s < S; ++s) n_active += h[s] != 0;
         if (n_active == 0) break;
         int nst = std::min(K, n_steps - done);
-        const double dt_k = interval_dt(b, k);
+        double dt_k = interval_dt(b, k);
+        if (amax > 0) {
+            // K steps of dt 2^m, the last interval shortened to end at the horizon
+            dt_k = std::ldexp(b->run.dt, m_adapt);
+            const double rem = horizon - t_now;
+            nst = (int)std::min<double>(K, std::ceil(rem / dt_k - 1e-9));
+            if (nst < 1) nst = 1;
+            if (nst * dt_k > rem) dt_k = rem / nst;
+        }
         if ((rc = set_step_size(b, dt_k)) != EM_OK) return rc;
         const bool catch_up = sur && hcnt[1] != n_activated;
         if (catch_up) {
@@ -1923,7 +1946,7 @@ em_status em_run_to_ttf(em_batch *b, em_ttf_result *out)
         rc = timed_ir(b);
         if (rc != EM_OK) return rc;
         if (ssk) launch_ss_wake(d, false, st);      // samples whose currents changed
-        launch_ttf_update(d, fail_frac, k, graded ? t_now : done * b->run.dt, st);
+        launch_ttf_update(d, fail_frac, k, (graded || amax > 0) ? t_now : done * b->run.dt, st);
         LAUNCHCHK(b);
     }
     b->n_outer_done = k;

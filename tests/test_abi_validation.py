@@ -109,6 +109,9 @@ CASES = {
     "bad run parameters (Krylov shift scale)": lambda g, m, r, mc: r.__setitem__("krylov_eta", -0.5),
     "reduced (Krylov) stepping and steady-state skipping are exclusive":
         lambda g, m, r, mc: r.update(krylov_q=4, ss_tol=1e-6),
+    "bad run parameters (adaptive grid levels)": lambda g, m, r, mc: r.__setitem__("dt_adapt", 13),
+    "the adaptive and the graded time grids are exclusive":
+        lambda g, m, r, mc: r.update(dt_adapt=2, dt_growth=1.1),
 }
 
 

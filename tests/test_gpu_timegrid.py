@@ -68,3 +68,27 @@ def test_uniform_step_restored_after_graded_run(em):
     B.close()
     with pytest.raises(em.EmError):
         em.Batch(g, mat, dict(rn, dt_growth=-1.0), mc)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_adaptive_grid_matches_oracle(em, oracle_mod, prec):
+    """The adaptive grid (dt_adapt = 3: steps up to 8 dt between nucleations,
+    back to dt after one) on one-sample batches, each a Monte Carlo sample of
+    mc_grid picked by its index, against the oracle on the same rule: the
+    failure decision, re-solve index, TTF, final drop and failed segments, at
+    the precision's bar; fewer re-solves than the uniform grid's 20."""
+    g, mat, rn, mc = synth.workload("mc_grid")
+    rn = dict(rn, prec=prec, dt_adapt=3)
+    topo = oracle_mod.topology(g, rn["intervals_per_seg"])
+    n_fail = 0
+    for s in (0, 1, 2, 5):
+        print(f"adaptive grid prec {prec} sample {s}", flush=True)
+        B = em.Batch(g, mat, rn, dict(mc, n_samples=1, sample_ids=[s]))
+        r = B.run_to_ttf()[0]
+        segs = B.failed_segments(0)
+        B.close()
+        ref = oracle_mod.run_sample(g, mat, rn, mc, s, topo=topo)
+        ttf_check.check(r, ref, segs, prec, rn, s)
+        assert ref["outer_idx"] < 20 or ref["failed"]
+        n_fail += ref["failed"]
+    assert n_fail >= 1

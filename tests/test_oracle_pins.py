@@ -647,3 +647,64 @@ def test_outer_loop_against_hand_drops(oracle_mod, case):
         assert abs(ttf_uni - e["ttf"]) > 1e-2 * e["ttf"]
     if k + 1 < len(drops):
         assert abs(drops[k + 1] - e["final_drop"]) > 1e-3 * e["final_drop"]
+
+
+# Adaptive grid (em_run_params.dt_adapt; reading R34): the clock written out
+# by hand -- K steps of dt 2^m, m back to 0 after an interval in which a void
+# nucleated and one level up (to dt_adapt) otherwise, the last interval
+# shortened to end at the horizon -- against the oracle's loop, with the same
+# hand drops as above.
+def _outer_adaptive_by_hand(oracle_mod, g, mat, rn, I):
+    N, K, n_steps, amax = rn["intervals_per_seg"], rn["ir_every"], rn["n_steps"], rn["dt_adapt"]
+    W, H, L = g.res_w[0], g.res_h[0], g.res_len[0]
+    topo = oracle_mod.topology(g, N)
+    sim = oracle_mod.SampleSim(g, mat, rn, topo)
+    sim.set_j(np.full(g.n_res, I / (W * H)))
+    drops, times, levels = [I * g.res_R0.sum() / g.vdd], [0.0], []
+    T = n_steps * rn["dt"]
+    t, done, m = 0.0, 0, 0
+    while t < T * (1 - 1e-12):
+        dt = rn["dt"] * 2.0 ** m
+        n = max(1, min(K, math.ceil((T - t) / dt - 1e-9)))
+        if n * dt > T - t:
+            dt = (T - t) / n
+        levels.append(m)
+        n_ev = len(sim.events())
+        sim.set_dt(dt)
+        sim.steps(n, done)
+        m = 0 if len(sim.events()) > n_ev else min(m + 1, amax)
+        done += n
+        t += n * dt
+        iv, dv = sim.voids()
+        dR = np.zeros(g.n_res)
+        for (tree, node, seg, phase, step, early), (vol, _) in zip(iv, dv):
+            l_v = min(vol / (W * H), L)
+            dR[seg] += max(0.0, l_v - W) * _eq17_per_metre(mat, W, H)
+        drops.append(I * (g.res_R0 + dR).sum() / g.vdd)
+        times.append(t)
+    return np.array(drops), np.array(times), levels
+
+
+@pytest.mark.parametrize("fail_frac", [0.10, 0.5])
+def test_outer_loop_adaptive_grid_against_hand_drops(oracle_mod, fail_frac):
+    I = 4e-3
+    g = line_pad_load(I=I, vdd=1.2)
+    mat = material(sigma_crit=200e6)
+    rn = run(intervals_per_seg=10, screen=1, dt=1e3, ir_every=10, n_steps=400, fail_frac=fail_frac, dt_adapt=3)
+    r = oracle_mod.run_sample(g, mat, rn)
+    drops, times, levels = _outer_adaptive_by_hand(oracle_mod, g, mat, rn, I)
+    e = _expect(drops, times, fail_frac)
+    assert r["failed"] == e["failed"] and r["outer_idx"] == e["outer_idx"]
+    k = e["outer_idx"]
+    assert np.allclose(r["drops"], drops[:k + 1], rtol=1e-10, atol=0)
+    assert np.allclose(r["times"], times[1:k + 1], rtol=1e-12, atol=0)
+    # the grid refines at the nucleation and coarsens before and after it
+    assert 0 in levels[1:] and max(levels) == 3
+    if e["failed"]:
+        assert abs(r["ttf"] - e["ttf"]) <= 1e-9 * e["ttf"]
+        assert times[k - 1] < r["ttf"] <= times[k]
+    else:
+        # censored: the clock ends exactly at the horizon, in fewer re-solves
+        # than the uniform grid's 40
+        assert math.isnan(r["ttf"]) and abs(times[-1] - 400 * 1e3) <= 1e-9 * 400e3
+        assert k == len(times) - 1 < 40
