@@ -92,3 +92,30 @@ def test_adaptive_grid_matches_oracle(em, oracle_mod, prec):
         assert ref["outer_idx"] < 20 or ref["failed"]
         n_fail += ref["failed"]
     assert n_fail >= 1
+
+
+def test_adaptive_grid_with_skipping_and_reduced_stepping(em):
+    """The adaptive grid combined with steady-state skipping (exact within its
+    band: the same results) and with reduced stepping (the same decisions,
+    drops within the paper's 0.05 %), screen off, on a 16-sample batch."""
+    g, mat, rn, mc = synth.workload("mc_grid")
+    mc = dict(mc, n_samples=16)
+    ra = dict(rn, prec=0, screen=0, dt_adapt=3)
+
+    def go(over):
+        B = em.Batch(g, mat, dict(ra, **over), mc)
+        res = B.run_to_ttf()
+        info = B.info()
+        B.close()
+        return res, info
+
+    a, ia = go({})
+    b, ib = go({"ss_tol": 1e-6})
+    c, ic = go({"krylov_q": 6})
+    assert ib["n_ss_skipped"] > 0 and ic["n_krylov_intervals"] > 0
+    for s in range(16):
+        for x, tol in ((b, 1e-6), (c, 5e-4)):
+            assert a[s]["failed"] == x[s]["failed"] and a[s]["outer_idx"] == x[s]["outer_idx"], s
+            assert abs(a[s]["final_drop"] - x[s]["final_drop"]) <= tol * a[s]["final_drop"], s
+            if a[s]["failed"]:
+                assert abs(a[s]["ttf_s"] - x[s]["ttf_s"]) <= tol * a[s]["ttf_s"], s
