@@ -273,7 +273,8 @@ def mc_leg(args, name, oracle, plain, var=None, joule=False, n_samples=None):
     if joule:
         run = dict(run, joule=1)
     S = mc["n_samples"]
-    label = {"sd_T_K": "die-temperature sd {:g} K", "sd_ea_eV": "activation-energy sd {:g} eV"}
+    label = {"sd_T_K": "die-temperature sd {:g} K", "sd_ea_eV": "activation-energy sd {:g} eV",
+             "cov_map": "thermal-map amplitude CoV {:g}"}
     extra = "".join(", " + (label[k].format(v) if k in label else f"{k[4:]} CoV {v:g}")
                     for k, v in (var or {}).items()) + (", Joule pre-pass" if joule else "")
 
@@ -854,7 +855,8 @@ def main():
                "mc_mesh": mc_leg(args, "mc_mesh", oracle=False, plain=False),
                "mc_rho_load": mc_leg(args, "mc_grid", oracle=False, plain=False, var=MC_VAR),
                "mc_joule": mc_leg(args, "mc_grid", oracle=False, plain=False, joule=True),
-               "mc_die_T": mc_leg(args, "mc_grid", oracle=False, plain=False, var={"sd_T_K": 3.0})}
+               "mc_die_T": mc_leg(args, "mc_grid", oracle=False, plain=False, var={"sd_T_K": 3.0}),
+               "mc_map": mc_leg(args, "mc_grid", oracle=False, plain=False, var={"cov_map": 0.2})}
         print(json.dumps(out), flush=True)
         return
 
@@ -909,6 +911,7 @@ def main():
         out["mc_rho_load"] = mc_leg(args, "mc_grid", oracle=False, plain=False, var=MC_VAR)
         out["mc_joule"] = mc_leg(args, "mc_grid", oracle=False, plain=False, joule=True)
         out["mc_die_T"] = mc_leg(args, "mc_grid", oracle=False, plain=False, var={"sd_T_K": 3.0})
+        out["mc_map"] = mc_leg(args, "mc_grid", oracle=False, plain=False, var={"cov_map": 0.2})
         log("bench: mc (mc_mesh, variations) done")
         out["mc_skip"] = skip_leg(args, "mc_grid", n_samples=256)
         log("bench: mc_grid steady-state skipping done")

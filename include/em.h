@@ -281,6 +281,15 @@ typedef struct {
  *            The thermomigration drive keeps the unshifted map (a uniform
  *            shift leaves dT/dx unchanged; its 1/T^2 factor moves by under
  *            2 % for |dT| <= 3 K at 330 K), and sigma_crit does not depend on T.
+ *   param 6  thermal-map amplitude, per sample (counter index 0): the map's rise
+ *            above T_ambient scaled by a unit-mean lognormal a (CoV cov_map),
+ *            T_a = T_ambient + a (T - T_ambient).  Each wire segment's
+ *            diffusivity takes kappa(T_a) / kappa(T) at its midpoint map
+ *            temperature (folded into the kappa multiplier, as param 5), and
+ *            every edge's thermomigration drive (Q / (Omega T)) dT/dx becomes
+ *            that of the scaled field, a T_e / T_a,e times the nominal one
+ *            (T_e the edge's midpoint temperature).  Not with the Joule
+ *            pre-pass (whose temperatures are not the map's).
  * The paper's study perturbs kappa and sigma_crit; resistivity and loading are
  * two of the further sampled inputs it names for the same flow.  With
  * cov_rho = cov_load = 0 every sample starts on the nominal network. */
@@ -296,6 +305,7 @@ typedef struct {
                                     (the Philox counter's sample word) of each batch sample;
                                     NULL = 0 .. n_samples-1.  Entries >= 0, copied at creation.
                                     Lets a batch re-run any subset of a study's samples. */
+    double cov_map;              /* thermal-map amplitude CoV (param 6), 0 <= cov <= 1 */
 } em_mc_params;
 
 typedef struct {

@@ -73,7 +73,22 @@ typedef struct {
      * input); NULL means 1.  They scale the electron-wind drive and the
      * copper term of eq. 17 (the IR resistances are scaled by the caller). */
     const double *xi_r;
+    /* thermal-map amplitude of the sample (Sec. IV-F map perturbation): the
+     * rise above T_amb scaled by map_a; 0 means 1 (unscaled).  Scales each
+     * edge's thermomigration drive as the scaled field would; the diffusivity
+     * factor is in xi_k. */
+    double map_a;
 } ora_problem;
+
+/* thermomigration drive of an edge at midpoint temperature Te under the
+ * sample's map amplitude: (Q/(Omega T)) dT/dx of the scaled field over the
+ * nominal one */
+static double tm_factor(const ora_problem *P, double Te)
+{
+    if (!(P->map_a > 0)) return 1.0;
+    const double a = P->map_a;
+    return a * Te / (P->T_amb + a * (Te - P->T_amb));
+}
 
 static double seg_rho(const ora_problem *P, int e)
 {
@@ -420,6 +435,7 @@ void ora_set_j(ora_state *S, const double *jseg)
         double Te = 0.5 * (S->T[i] + S->T[p]);
         double Sd = ORA_E * P->Z * seg_rho(P, e) * jseg[e] / P->Omega;
         double Md = S->dir[i] * (P->Q_eV * ORA_E / (P->Omega * Te)) * (S->T[i] - S->T[p]) / dx;
+        Md *= tm_factor(P, Te);
         double phi = S->dir[i] * S->g[i] * dx * (Sd + Md);
         S->phi[i] = phi;
         S->f[i] += phi;
@@ -446,6 +462,7 @@ void ora_screen(ora_state *S, unsigned char *tree_mortal, unsigned char *seg_mor
             double Te = 0.5 * (S->T[i] + S->T[p]);
             double Sd = ORA_E * P->Z * seg_rho(P, e) * S->jseg[e] / P->Omega;
             double Md = S->dir[i] * (P->Q_eV * ORA_E / (P->Omega * Te)) * (S->T[i] - S->T[p]) / dx;
+            Md *= tm_factor(P, Te);
             psi[i] = psi[p] + S->dir[i] * dx * (Sd + Md);
         }
         double num = 0, den = 0;

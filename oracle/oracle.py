@@ -88,6 +88,7 @@ class _Problem(C.Structure):
         ("sigT", C.c_double), ("delta", C.c_double), ("rho_ta", C.c_double), ("h_ta", C.c_double),
         ("N", C.c_int), ("dt", C.c_double), ("max_voids", C.c_int),
         ("xi_k", C.c_void_p), ("xi_s", C.c_void_p), ("T_stress", C.c_void_p), ("xi_r", C.c_void_p),
+        ("map_a", C.c_double),
     ]
 
 
@@ -115,7 +116,7 @@ class _Keep:
         return a
 
 
-def make_problem(grid, mat, run, xi_k=None, xi_s=None, T_stress=None, xi_r=None):
+def make_problem(grid, mat, run, xi_k=None, xi_s=None, T_stress=None, xi_r=None, map_a=None):
     keep = _Keep()
     P = _Problem()
     P.n_nodes = grid.n_nodes
@@ -139,6 +140,7 @@ def make_problem(grid, mat, run, xi_k=None, xi_s=None, T_stress=None, xi_r=None)
     P.xi_k = _pi(keep(xi_k, np.float64)); P.xi_s = _pi(keep(xi_s, np.float64))
     P.T_stress = _pi(keep(T_stress, np.float64))
     P.xi_r = _pi(keep(xi_r, np.float64))
+    P.map_a = float(map_a) if map_a else 0.0
     return P, keep
 
 
@@ -200,10 +202,10 @@ class SampleSim:
     """One sample's stress/void state (wraps the C oracle)."""
 
     def __init__(self, grid, mat, run, topo: Topology, xi_k=None, xi_s=None, cap_events=1 << 16,
-                 T_stress=None, xi_r=None):
+                 T_stress=None, xi_r=None, map_a=None):
         L = lib()
         self.grid, self.mat, self.run, self.topo = grid, mat, run, topo
-        self.P, self.keep = make_problem(grid, mat, run, xi_k, xi_s, T_stress, xi_r)
+        self.P, self.keep = make_problem(grid, mat, run, xi_k, xi_s, T_stress, xi_r, map_a)
         t = topo
         self._t = [np.ascontiguousarray(a, np.int32) for a in
                    (t.tree_off, t.parent, t.seg, t.dir, t.vert, t.kpos, t.seg_tree)]
@@ -369,7 +371,30 @@ def sample_xi(grid, mc, sample, T_amb=300.0, Ea_eV=None):
         for e in np.nonzero(wire)[0]:
             T = thermal.midpoint_map_T(grid, T_amb, int(e))
             xi_k[e] *= np.exp(-Ea / (K_B_EV * (T + dT))) / (T + dT) / (np.exp(-Ea / (K_B_EV * T)) / T)
+    a = sample_map_amplitude(mc, sample)
+    if a is not None:
+        wire = (grid.res_is_via == 0) & (grid.layer[grid.res_a] == grid.layer[grid.res_b])
+        if Ea_eV is None:
+            raise ValueError("a thermal-map amplitude spread needs the material's activation energy")
+        Ea = float(Ea_eV)
+        for e in np.nonzero(wire)[0]:
+            T = thermal.midpoint_map_T(grid, T_amb, int(e))
+            Ta = T_amb + a * (T - T_amb)
+            xi_k[e] *= np.exp(-Ea / (K_B_EV * Ta)) / Ta / (np.exp(-Ea / (K_B_EV * T)) / T)
     return xi_k, lognormal_xi(mc["seed"], sample, grid.n_res, 1, mc["cov_scrit"])
+
+
+def sample_map_amplitude(mc, sample):
+    """The sample's thermal-map amplitude a (param 6, counter index 0): a
+    unit-mean lognormal with CoV cov_map scaling the map's rise above the
+    ambient, T_a = T_amb + a (T - T_amb).  Each wire segment's diffusivity
+    takes the Arrhenius ratio at its midpoint map temperature (sample_xi);
+    each edge's thermomigration drive (Q/(Omega T)) dT/dx that of the scaled
+    field (the C oracle, from a).  None without the spread."""
+    cov = float(mc.get("cov_map", 0.0)) if mc else 0.0
+    if cov <= 0:
+        return None
+    return float(lognormal_xi(mc["seed"], sample, 1, 6, cov)[0])
 
 
 def sample_inputs(grid, mc, sample):
@@ -413,7 +438,8 @@ def run_sample(grid, mat, run, mc=None, sample=0, topo=None, keep_sim=False, max
         else:
             j_nom = ir_solve(grid, grid.res_R0.astype(np.float64))[2]
         T_stress = thermal.node_temperatures(grid, mat, float(run.get("T_ambient", 300.0)), topo, j_nom)
-    sim = SampleSim(grid, mat, run, topo, xi_k, xi_s, T_stress=T_stress, xi_r=xi_r)
+    sim = SampleSim(grid, mat, run, topo, xi_k, xi_s, T_stress=T_stress, xi_r=xi_r,
+                    map_a=sample_map_amplitude(mc, sample))
     n_steps, K = int(run["n_steps"]), int(run["ir_every"])
     res = dict(sample=sample)
     # reduced (extended rational Krylov) stepping of long chains (Sec. IV-E)

@@ -79,7 +79,7 @@ class MCParams(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("n_samples", C.c_int32), ("seed", C.c_uint64),
                 ("cov_kappa", C.c_double), ("cov_scrit", C.c_double), ("cov_rho", C.c_double),
                 ("cov_load", C.c_double), ("sd_ea_eV", C.c_double), ("sd_T_K", C.c_double),
-                ("sample_ids", C.c_void_p)]
+                ("sample_ids", C.c_void_p), ("cov_map", C.c_double)]
 
 
 class TTFResult(C.Structure):
@@ -233,7 +233,8 @@ class Batch:
                            cov_scrit=float(mc["cov_scrit"]), cov_rho=float(mc.get("cov_rho", 0.0)),
                            cov_load=float(mc.get("cov_load", 0.0)), sd_ea_eV=float(mc.get("sd_ea_eV", 0.0)),
                            sd_T_K=float(mc.get("sd_T_K", 0.0)),
-                           sample_ids=_pint(keep(mc.get("sample_ids"), np.int32)))
+                           sample_ids=_pint(keep(mc.get("sample_ids"), np.int32)),
+                           cov_map=float(mc.get("cov_map", 0.0)))
         self._alloc = None
         if torch_alloc:
             dev = torch.cuda.current_device()

@@ -22,7 +22,7 @@ struct em_batch {
     em_run_params run;
     int S = 1;
     uint64_t seed = 0;
-    double cov_k = 0, cov_s = 0, cov_r = 0, cov_l = 0, sd_ea = 0, sd_T = 0;
+    double cov_k = 0, cov_s = 0, cov_r = 0, cov_l = 0, sd_ea = 0, sd_T = 0, cov_map = 0;
     bool trees_only = false;
     bool fp32 = false;
     hipStream_t stream = nullptr;
@@ -377,8 +377,11 @@ em_status validate(em_batch *b, const em_grid_desc *g, const em_material *m, con
     if (mc && (mc->n_samples < 1 || mc->n_samples > 65535 || mc->cov_kappa < 0 || mc->cov_scrit < 0 || !std::isfinite(mc->cov_kappa) ||
                !std::isfinite(mc->cov_scrit) || !(mc->cov_rho >= 0) || !(mc->cov_load >= 0) ||
                !std::isfinite(mc->cov_rho) || !std::isfinite(mc->cov_load) || !(mc->sd_ea_eV >= 0) ||
-               !(mc->sd_ea_eV < 1.0) || !(mc->sd_T_K >= 0) || !(mc->sd_T_K <= 20.0)))
+               !(mc->sd_ea_eV < 1.0) || !(mc->sd_T_K >= 0) || !(mc->sd_T_K <= 20.0) ||
+               !(mc->cov_map >= 0) || !(mc->cov_map <= 1.0)))
         return fail(b, EM_ERR_ARG, "bad Monte Carlo parameters");
+    if (mc && mc->cov_map > 0 && r->joule)
+        return fail(b, EM_ERR_ARG, "a thermal-map amplitude spread cannot be combined with the Joule pre-pass");
     if (mc && mc->sample_ids)
         for (int s = 0; s < mc->n_samples; ++s)
             if (mc->sample_ids[s] < 0) return fail(b, EM_ERR_ARG, "Monte Carlo sample indices must be >= 0");
@@ -612,7 +615,7 @@ void fold_timers(em_batch *b)
 em_status run_screen(em_batch *b, bool apply)
 {
     Dev &d = b->d;
-    if ((b->nominal || b->trees_only) && !d.xi_r) {
+    if ((b->nominal || b->trees_only) && !d.xi_r && !d.map_a) {
         HIPCHK(b, hipMemsetAsync(d.tree_mortal, 0, (size_t)d.n_trees * d.S, b->stream));
         HIPCHK(b, hipMemsetAsync(d.seg_mortal, 0, (size_t)d.n_res * d.S, b->stream));
         launch_screen_shared(d, apply, b->stream);
@@ -1027,6 +1030,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     b->cov_l = (mc && !b->trees_only) ? mc->cov_load : 0.0;     // no sinks in trees-only mode
     b->sd_ea = mc ? mc->sd_ea_eV : 0.0;
     b->sd_T = mc ? mc->sd_T_K : 0.0;
+    b->cov_map = mc ? mc->cov_map : 0.0;
     b->fp32 = r->prec == EM_FP32;
     if (mc && mc->sample_ids) b->sid_h.assign(mc->sample_ids, mc->sample_ids + mc->n_samples);
     b->stream = (hipStream_t)hip_stream;
@@ -1380,6 +1384,8 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     AL(d.xi_k, double, RS); AL(d.xi_s, double, RS);
     d.xi_r = nullptr;
     if (b->cov_r > 0) AL(d.xi_r, double, RS);
+    d.map_a = nullptr;
+    if (b->cov_map > 0) AL(d.map_a, double, S);
     d.sink_s = nullptr;
     if (b->cov_l > 0) AL(d.sink_s, double, (size_t)S * nn);
     AL(d.jseg, double, RS);
@@ -1530,7 +1536,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     launch_node_T(d, stq);
     launch_edge_static(d, stq);
     launch_node_V(d, b->fp32, stq);
-    launch_draws(d, b->seed, b->cov_k, b->cov_s, b->cov_r, b->cov_l, b->sd_ea, b->sd_T, stq);
+    launch_draws(d, b->seed, b->cov_k, b->cov_s, b->cov_r, b->cov_l, b->sd_ea, b->sd_T, b->cov_map, stq);
     b->nominal = !d.xi_r && !d.sink_s;
     launch_node_sc(d, b->fp32, stq);
     launch_set_sigma_T(d, b->fp32, stq);
@@ -1742,6 +1748,7 @@ static em_status rerun_samples(em_batch *b, const std::vector<int> &pick, em_ttf
     mc2.cov_kappa = b->cov_k; mc2.cov_scrit = b->cov_s; mc2.cov_rho = b->cov_r; mc2.cov_load = b->cov_l;
     mc2.sd_ea_eV = b->sd_ea;
     mc2.sd_T_K = b->sd_T;
+    mc2.cov_map = b->cov_map;
     mc2.sample_ids = ids.data();
     em_batch *sub = nullptr;
     em_status rc = em_batch_create(&b->gcopy->g, &b->mat, &r2, &mc2, b->has_alloc ? &b->alloc : nullptr,

@@ -84,6 +84,7 @@ struct Dev {
     const int *sid;                     // [S] Monte Carlo sample index of each batch sample, or null
                                         // (identity)
     double *xi_k, *xi_s;
+    double *map_a;                      // [S] thermal-map amplitude of each sample (null: 1)
     double *xi_r;                       // resistivity multipliers (1 for vias), or null
     // ---- per (sample, segment) ----
     double *jseg;                       // [S][res]
@@ -262,7 +263,7 @@ void launch_kry_step(const Dev &d, bool fp32, int n_steps, hipStream_t st);   //
 void launch_kry_restore(const Dev &d, hipStream_t st);                        // after the exact launch
 void launch_kry_invalidate(const Dev &d, bool all, hipStream_t st);           // after an IR solve
 void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, double cov_r, double cov_l,
-                  double sd_ea, double sd_T, hipStream_t st);
+                  double sd_ea, double sd_T, double cov_map, hipStream_t st);
 void launch_node_sc(const Dev &d, bool fp32, hipStream_t st);
 void launch_update_f(const Dev &d, bool fp32, hipStream_t st);
 void launch_factor(const Dev &d, bool fp32, hipStream_t st);

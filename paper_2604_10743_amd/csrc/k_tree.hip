@@ -295,10 +295,12 @@ __device__ inline double lognormal_xi(uint64_t seed, int sample, int segment, in
 // The activation-energy offset dEa ~ N(0, sd_ea) of a wire segment (param 4)
 // scales its diffusivity by exp(-dEa / (k_B T)), T the map temperature at the
 // segment's midpoint; the sample's die-temperature offset dT ~ N(0, sd_T)
-// (param 5, one per sample) by the Arrhenius ratio kappa(T + dT) / kappa(T).
-// Both join the kappa multiplier.
+// (param 5, one per sample) by the Arrhenius ratio kappa(T + dT) / kappa(T);
+// the sample's map amplitude a (param 6, unit-mean lognormal) by
+// kappa(T_a) / kappa(T), T_a = T_amb + a (T - T_amb).  All join the kappa
+// multiplier; a itself scales the thermomigration drive (tm_scale).
 EM_KERNEL void k_draws(Dev d, uint64_t seed, double cov_k, double cov_s, double cov_r, double sd_ea, double sd_T,
-                       int use_mc)
+                       double cov_map, int use_mc)
 {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long long)d.n_res * d.S) return;
@@ -310,6 +312,14 @@ EM_KERNEL void k_draws(Dev d, uint64_t seed, double cov_k, double cov_s, double 
     if (sd_T > 0.0 && d.is_wire[e]) {
         const double T = map_T_mid(d, e), dT = sd_T * normal_z(seed, sm, 0, 5);
         xk *= exp(d.Ea_eV / (K_B / E_CHG) * (1.0 / T - 1.0 / (T + dT))) * T / (T + dT);
+    }
+    if (cov_map > 0.0) {
+        const double a = lognormal_xi(seed, sm, 0, 6, cov_map);
+        if (e == 0) d.map_a[s] = a;
+        if (d.is_wire[e]) {
+            const double T = map_T_mid(d, e), Ta = d.T_amb + a * (T - d.T_amb);
+            xk *= exp(d.Ea_eV / (K_B / E_CHG) * (1.0 / T - 1.0 / Ta)) * T / Ta;
+        }
     }
     d.xi_k[g] = xk;
     d.xi_s[g] = use_mc ? lognormal_xi(seed, sm, e, 1, cov_s) : 1.0;
@@ -362,6 +372,17 @@ EM_KERNEL void k_node_sc_rows(Dev d)
     ((R *)d.sc)[(size_t)i * d.S + s] = (R)node_scrit(d, i, s);
 }
 
+// The thermomigration drive of the edge (parent(i), i) in sample s relative
+// to the nominal map's: with the map's rise scaled by the sample's amplitude
+// a, (Q / (Omega T)) dT/dx becomes a T_e / (T_amb + a (T_e - T_amb)) times
+// itself, T_e the edge's midpoint temperature.
+__device__ inline double tm_scale(const Dev &d, int i, int s)
+{
+    if (!d.map_a) return 1.0;
+    const double a = d.map_a[s], Te = 0.5 * (d.T[i] + d.T[d.parent[i]]);
+    return a * Te / (d.T_amb + a * (Te - d.T_amb));
+}
+
 // ------------------------------------------------------------------------
 // Forcing f of the descriptor system (eq. 18): the edge (p, i) carries
 // phi = dir * g dx (S + M) from p into i, with S = eZ rho j/Omega along
@@ -372,7 +393,7 @@ __device__ inline double edge_phi(const Dev &d, int i, int s)
     int e = d.seg[i];
     double j = d.S == 1 ? d.jseg[e] : d.jT[(size_t)e * d.S + s];
     double Sd = E_CHG * d.Z * d.rho * xi_rho(d, e, s) * j / d.Omega;
-    return d.dir[i] * d.xi_k[(size_t)e * d.S + s] * d.gdx0[i] * (Sd + d.mdrv[i]);
+    return d.dir[i] * d.xi_k[(size_t)e * d.S + s] * d.gdx0[i] * (Sd + tm_scale(d, i, s) * d.mdrv[i]);
 }
 
 __device__ inline double node_dtf(const Dev &d, int i, int s)
@@ -564,7 +585,7 @@ __device__ void steady_stress_wave(const Dev &d, int t, int s, int lane)
             const int e = d.seg[i];
             const double dx = d.len[e] / d.N;
             const double Sd = E_CHG * d.Z * d.rho * xi_rho(d, e, s) * d.jseg[(size_t)s * d.n_res + e] / d.Omega;
-            v = d.dir[i] * dx * (Sd + d.mdrv[i]);
+            v = d.dir[i] * dx * (Sd + tm_scale(d, i, s) * d.mdrv[i]);
             a = d.parent[i];
         }
 #pragma unroll
@@ -1383,7 +1404,7 @@ __device__ void steady_stress_blk(const Dev &d, int t, int s, double (*vs)[FB], 
             const int e = d.seg[i];
             const double dx = d.len[e] / d.N;
             const double Sd = E_CHG * d.Z * d.rho * xi_rho(d, e, s) * d.jseg[(size_t)s * d.n_res + e] / d.Omega;
-            v = d.dir[i] * dx * (Sd + d.mdrv[i]);
+            v = d.dir[i] * dx * (Sd + tm_scale(d, i, s) * d.mdrv[i]);
             a = d.parent[i];
         }
         int buf = 0;
@@ -2047,10 +2068,11 @@ void launch_node_V(const Dev &d, bool fp32, hipStream_t st)
     k_tree_V<<<nblocks(d.n_trees, 4), 256, 0, st>>>(d);
 }
 void launch_draws(const Dev &d, uint64_t seed, double cov_k, double cov_s, double cov_r, double cov_l,
-                  double sd_ea, double sd_T, hipStream_t st)
+                  double sd_ea, double sd_T, double cov_map, hipStream_t st)
 {
     int use = (cov_k != 0.0 || cov_s != 0.0) ? 1 : 0;
-    k_draws<<<nblocks((long long)d.n_res * d.S), 256, 0, st>>>(d, seed, cov_k, cov_s, cov_r, sd_ea, sd_T, use);
+    k_draws<<<nblocks((long long)d.n_res * d.S), 256, 0, st>>>(d, seed, cov_k, cov_s, cov_r, sd_ea, sd_T, cov_map,
+                                                               use);
     if (d.sink_s) k_draws_load<<<nblocks((long long)d.n_nodes * d.S), 256, 0, st>>>(d, seed, cov_l);
 }
 // grid of one block row per node (rows beyond 65535 folded into z) and the

@@ -101,6 +101,8 @@ CASES = {
     "bad Monte Carlo (Ea spread, huge)": lambda g, m, r, mc: mc.__setitem__("sd_ea_eV", 2.0),
     "bad Monte Carlo (die temperature spread)": lambda g, m, r, mc: mc.__setitem__("sd_T_K", -1.0),
     "bad Monte Carlo (die temperature spread, huge)": lambda g, m, r, mc: mc.__setitem__("sd_T_K", 50.0),
+    "bad Monte Carlo (map amplitude spread)": lambda g, m, r, mc: mc.__setitem__("cov_map", -0.1),
+    "bad Monte Carlo (map amplitude spread, huge)": lambda g, m, r, mc: mc.__setitem__("cov_map", 1.5),
     "bad run parameters (multigrid scale)": lambda g, m, r, mc: r.__setitem__("amg_alpha", 0.5),
     "bad run parameters (steady-state tolerance)": lambda g, m, r, mc: r.__setitem__("ss_tol", -1e-6),
     "bad run parameters (steady-state tolerance, huge)": lambda g, m, r, mc: r.__setitem__("ss_tol", 0.05),

@@ -176,3 +176,38 @@ def test_die_temperature_offset_draws_and_runs_match_oracle(em, oracle_mod):
             assert r["outer_idx"] == ref["outer_idx"], s
         assert np.array_equal(segs[s], ref["failed_segs"]), s
     assert n_fail >= 1
+
+
+@pytest.mark.parametrize("screen", [1, 0])
+def test_map_amplitude_draws_and_runs_match_oracle(em, oracle_mod, screen):
+    # one thermal-map amplitude a (unit-mean lognormal, CoV 0.3) per sample:
+    # the diffusivity factors at the segments' midpoints and the scaled
+    # thermomigration drive of every edge, with the screen on (a per-sample
+    # steady stress) and off
+    g, mat, rn, mc = synth.workload("mc_grid")
+    S = 24
+    mc = dict(mc, n_samples=S, cov_map=0.3)
+    rn = dict(rn, prec=0, screen=screen)
+    print(f"mc inputs: map amplitude, screen {screen}", flush=True)
+    B = em.Batch(g, mat, rn, mc)
+    for s in (0, 5, 23):
+        xk, xs = oracle_mod.sample_xi(g, mc, s, T_amb=rn["T_ambient"], Ea_eV=mat["Ea_eV"])
+        assert np.allclose(B.xi(s, 0), xk, rtol=1e-13, atol=0), s
+    res = B.run_to_ttf()
+    picks = range(0, S, 6) if screen else (0, 12)
+    segs = {s: B.failed_segments(s) for s in picks}
+    B.close()
+    topo = oracle_mod.topology(g, rn["intervals_per_seg"])
+    n_fail = 0
+    for s in picks:
+        ref = oracle_mod.run_sample(g, mat, rn, mc, s, topo=topo)
+        r = res[s]
+        n_fail += ref["failed"]
+        assert r["failed"] == ref["failed"], s
+        assert abs(r["final_drop"] - ref["final_drop"]) <= 1e-6 * ref["final_drop"], s
+        if ref["failed"]:
+            assert abs(r["ttf_s"] - ref["ttf"]) <= 1e-6 * ref["ttf"], s
+            assert r["outer_idx"] == ref["outer_idx"], s
+        assert np.array_equal(segs[s], ref["failed_segs"]), s
+    if screen:
+        assert n_fail >= 1

@@ -163,3 +163,35 @@ def test_die_temperature_offset_is_the_arrhenius_ratio(oracle_mod):
     assert abs(z.mean()) < 4 / math.sqrt(z.size) and abs(z.std() - 1.0) < 0.04
     with pytest.raises(ValueError):
         oracle_mod.sample_xi(g, dict(base, sd_T_K=3.0), 0, T_amb=350.0)
+
+
+def test_map_amplitude_drives_thermomigration_as_the_scaled_map(oracle_mod):
+    """Param 6: the sample's amplitude a scales the map's rise above the
+    ambient.  With no current, the zero-flux steady stress (the screen's,
+    kappa-independent) is the path integral of the thermomigration drive
+    alone; under map_a = a it must equal that of the same grid whose raster
+    was scaled by hand, T_amb + a (T - T_amb) (node temperatures interpolate
+    the raster linearly).  The amplitudes are unit-mean lognormal."""
+    g, mat, rn, mc = synth.workload("mc_grid")
+    T_amb = float(rn["T_ambient"])
+    topo = oracle_mod.topology(g, rn["intervals_per_seg"])
+    zero = np.zeros(g.n_res)
+    for a in (0.7, 1.3):
+        sim_a = oracle_mod.SampleSim(g, mat, rn, topo, map_a=a)
+        sim_a.set_j(zero)
+        _, _, ss_a = sim_a.screen()
+        g2 = synth.Grid(**{**g.__dict__, "tmap": T_amb + a * (g.tmap - T_amb)})
+        sim_b = oracle_mod.SampleSim(g2, mat, rn, topo)
+        sim_b.set_j(zero)
+        _, _, ss_b = sim_b.screen()
+        scale = np.abs(ss_b - mat["sigma_T"]).max()
+        assert scale > 1e5                                  # the map drives a real stress
+        assert np.allclose(ss_a, ss_b, rtol=0, atol=1e-9 * scale), a
+    # and not the unscaled map's
+    sim_0 = oracle_mod.SampleSim(g, mat, rn, topo)
+    sim_0.set_j(zero)
+    _, _, ss_0 = sim_0.screen()
+    assert np.abs(ss_0 - ss_a).max() > 0.1 * scale
+    amps = np.array([oracle_mod.sample_map_amplitude(dict(mc, cov_map=0.2), s) for s in range(4000)])
+    assert abs(amps.mean() - 1.0) < 0.02 and abs(amps.std() - 0.2) < 0.02 and amps.min() > 0
+    assert oracle_mod.sample_map_amplitude(dict(mc, cov_map=0.0), 0) is None
