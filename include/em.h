@@ -159,7 +159,9 @@ typedef struct {
                                     4 at most 128 VGPRs (four waves per SIMD: four 256-lane or two
                                     512-lane workgroups share a compute unit, some values spill),
                                     FP32 with 64 to 512 lanes only.  Pays when a launch holds
-                                    few instances (Monte Carlo after the screen).  Same results. */
+                                    few instances (Monte Carlo after the screen); 3 at most 168
+                                    VGPRs (three waves per SIMD, fewer spills), FP32 with 256 or
+                                    512 lanes.  Same results. */
     int32_t joule;               /* 1: one-time Joule-heating thermal pre-pass at batch creation
                                     (Sec. III-A): the currents of a nominal IR solve (or the
                                     prescribed seg_j) heat every wire segment; each segment's

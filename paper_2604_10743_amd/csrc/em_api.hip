@@ -98,7 +98,7 @@ struct em_batch {
     std::vector<int> tree_perm_h;
     int chain_wg = 0;
     int chain_m = 8;                    // stress nodes per lane of the chain kernel
-    int chain_occ = 1;                  // chain kernel register budget: 1 default, 4 (128 VGPRs)
+    int chain_occ = 1;                  // chain kernel register budget: 1 default, 3 (168 VGPRs), 4 (128)
     bool psi_shared = false;            // steady stress of the last screen only in column 0 (shared screen)
     std::vector<int> wg_cand;           // chain workgroup sizes that hold the longest chain tree
     long long lanes_cap = 0;            // lanes allocated for the chain kernel's table
@@ -1182,8 +1182,10 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
         cWG = r->chain_wg;
     }
     if (r->chain_occ != 0 && r->chain_occ != 1 &&
-        !(r->chain_occ == 4 && b->fp32 && cWG <= 512))
-        return fail(b, EM_ERR_ARG, "chain_occ must be 0, 1, or 4 (FP32 with 64 to 512 lanes)");
+        !(r->chain_occ == 4 && b->fp32 && cWG <= 512) &&
+        !(r->chain_occ == 3 && b->fp32 && (cWG == 256 || cWG == 512)))
+        return fail(b, EM_ERR_ARG, "chain_occ must be 0, 1, 3 (FP32 with 256 or 512 lanes) or 4 (FP32 with "
+                                   "64 to 512 lanes)");
     // placement of each chain instance: first lane (global) and lane count;
     // the per-lane table itself is expanded on the device.  The table is
     // allocated for the largest of the candidate sizes' layouts.
@@ -1342,7 +1344,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     b->chain_wg = cWG;
     b->chain_m = cM;
     d.chain_m = cM;
-    b->chain_occ = r->chain_occ == 4 ? 4 : 1;
+    b->chain_occ = (r->chain_occ == 4 || r->chain_occ == 3) ? r->chain_occ : 1;
     b->wg_cand = wg_cand;
     b->lanes_cap = lanes_cap;
     b->tree_perm_h = tree_perm;
@@ -2160,6 +2162,7 @@ em_status em_autotune(em_batch *b, int32_t n_steps, em_tune_info *out)
         for (int w : b->wg_cand) {
             cand.push_back({w, 1});
             if (b->fp32 && w <= 512) cand.push_back({w, 4});
+            if (b->fp32 && (w == 256 || w == 512)) cand.push_back({w, 3});
         }
         for (size_t k = 0; k < cand.size() && k < 12 && rc == EM_OK; ++k) {
             b->chain_wg = cand[k].first;

@@ -691,6 +691,7 @@ void launch_chain(const Dev &d, const Dev *d_dev, bool fp32, int n_steps, int st
     // the batch's workgroup size (lanes): the smallest that holds its longest
     // chain, or the one the autotuner measured fastest
     const bool dense = d.chain_occ == 4;    // FP32 64-512 lanes only (checked at creation)
+    const bool mid = d.chain_occ == 3;      // FP32 256 and 512 lanes only
     const int G = d.n_chain_wg;
     if (G > 0) {
         if (fp32) {
@@ -702,9 +703,11 @@ void launch_chain(const Dev &d, const Dev *d_dev, bool fp32, int n_steps, int st
                 else k_chain<float, CHAIN_M32, 128, 1><<<G, 128, 0, st>>>(h);
             } else if (d.chain_wg == 256) {
                 if (dense) k_chain<float, CHAIN_M32, 256, 4><<<G, 256, 0, st>>>(h);
+                else if (mid) k_chain<float, CHAIN_M32, 256, 3><<<G, 256, 0, st>>>(h);
                 else k_chain<float, CHAIN_M32, 256, 1><<<G, 256, 0, st>>>(h);
             } else if (d.chain_wg == 512) {
                 if (dense) k_chain<float, CHAIN_M32, 512, 4><<<G, 512, 0, st>>>(h);
+                else if (mid) k_chain<float, CHAIN_M32, 512, 3><<<G, 512, 0, st>>>(h);
                 else k_chain<float, CHAIN_M32, 512, 1><<<G, 512, 0, st>>>(h);
             } else {
                 if (d.chain_m == CHAIN_M32W)

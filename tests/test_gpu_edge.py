@@ -200,8 +200,9 @@ def test_chain_workgroup_sizes_give_identical_results(em, prec):
     # of the state, with the same nucleation sites.
     g, mat, rn, _ = synth.workload("tiny_trees")
     mc = dict(n_samples=8, seed=5, cov_kappa=0.2, cov_scrit=0.2)
-    # (lanes, register budget); the 128-VGPR forms run the same arithmetic
-    sizes = (((256, 1), (512, 1), (256, 4), (512, 4), (64, 1), (128, 1), (64, 4), (128, 4), (1024, 1))
+    # (lanes, register budget); the 128- and 168-VGPR forms run the same arithmetic
+    sizes = (((256, 1), (512, 1), (256, 4), (512, 4), (256, 3), (512, 3), (64, 1), (128, 1), (64, 4), (128, 4),
+              (1024, 1))
              if prec == 1 else ((256, 1), (512, 1), (64, 1), (128, 1)))
     out = []
     for w, occ in sizes:
@@ -225,7 +226,8 @@ def test_chain_workgroup_sizes_give_identical_results(em, prec):
     with pytest.raises(em.EmError):
         em.Batch(g, mat, dict(rn, prec=0, chain_wg=1024), mc)     # above the FP64 maximum
     for bad in (dict(prec=0, chain_wg=256, chain_occ=4), dict(prec=1, chain_wg=1024, chain_occ=4),
-                dict(prec=1, chain_wg=256, chain_occ=2)):
+                dict(prec=1, chain_wg=256, chain_occ=2), dict(prec=1, chain_wg=128, chain_occ=3),
+                dict(prec=0, chain_wg=256, chain_occ=3)):
         with pytest.raises(em.EmError):
             em.Batch(g, mat, dict(rn, **bad), mc)
 
