@@ -1279,13 +1279,19 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
             AL(d.kv, double, (size_t)d.krm * ns * S);
             AL(d.kred, double, ISk * KRY_KS(d.krm));
             AL(d.kscr, double, 3 * (size_t)ns * S);
+            AL(d.kbl, int, kl.size());
+            AL(d.kfl, int, kl.size());
+            AL(d.kze, double, ISk * d.krm);
+            AL(d.kdist, double, ISk);
         }
+        AL(d.kbn, unsigned int, 2);
+        HIPCHK(b, hipMemsetAsync(d.kbn, 0, 2 * sizeof(unsigned int), b->stream));
         AL(d.kr, int, ISk);
         AL(d.kdone, uint8_t, ISk);
-        AL(d.kcnt, unsigned long long, 4);
+        AL(d.kcnt, unsigned long long, 4 * KRY_CNT_SLOTS);
         HIPCHK(b, hipMemsetAsync(d.kr, 0, 4 * ISk, b->stream));
         HIPCHK(b, hipMemsetAsync(d.kdone, 0, ISk, b->stream));
-        HIPCHK(b, hipMemsetAsync(d.kcnt, 0, 32, b->stream));
+        HIPCHK(b, hipMemsetAsync(d.kcnt, 0, 4 * KRY_CNT_SLOTS * sizeof(unsigned long long), b->stream));
     }
     if (lanes_cap / 256 > (1LL << 30)) return fail(b, EM_ERR_ARG, "batch too large");
     d.n_chain_wg = (int)(n_lanes / cWG);
@@ -1628,8 +1634,12 @@ em_status em_get_info(em_batch *b, em_info *info)
     {
         unsigned long long kc[4] = {0, 0, 0, 0};
         if (b->d.kq > 0) {
-            HIPCHK(b, hipMemcpyAsync(kc, b->d.kcnt, 32, hipMemcpyDeviceToHost, b->stream));
+            std::vector<unsigned long long> slots(4 * KRY_CNT_SLOTS);
+            HIPCHK(b, hipMemcpyAsync(slots.data(), b->d.kcnt, slots.size() * sizeof(unsigned long long),
+                                     hipMemcpyDeviceToHost, b->stream));
             HIPCHK(b, hipStreamSynchronize(b->stream));
+            for (int k = 0; k < 4; ++k)
+                for (int j = 0; j < KRY_CNT_SLOTS; ++j) kc[k] += slots[(size_t)k * KRY_CNT_SLOTS + j];
         }
         info->n_krylov_bases = (int64_t)kc[0];
         info->n_krylov_intervals = (int64_t)kc[1];
@@ -2051,7 +2061,8 @@ em_status em_reset(em_batch *b)
     if (d.kq > 0) {
         HIPCHK(b, hipMemsetAsync(d.kr, 0, 4 * IS, st));
         HIPCHK(b, hipMemsetAsync(d.kdone, 0, IS, st));
-        HIPCHK(b, hipMemsetAsync(d.kcnt, 0, 32, st));
+        HIPCHK(b, hipMemsetAsync(d.kcnt, 0, 4 * KRY_CNT_SLOTS * sizeof(unsigned long long), st));
+        HIPCHK(b, hipMemsetAsync(d.kbn, 0, 2 * sizeof(unsigned int), st));
     }
     b->live_dirty = true;
     b->any_open = false;

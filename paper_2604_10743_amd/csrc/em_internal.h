@@ -157,12 +157,19 @@ struct Dev {
     double *kscr;                       // [3][ns][S] inverse pivots and multipliers of K = s0 C - A
     int *kr;                            // [inst] basis columns (0: none)
     uint8_t *kdone;                     // [inst] interval taken in reduced form
-    unsigned long long *kcnt;           // [4] bases built, reduced intervals, fallbacks,
-                                        //     node-steps advanced in reduced form
+    unsigned long long *kcnt;           // [4][KRY_CNT_SLOTS] bases built, reduced intervals, fallbacks,
+                                        //     node-steps advanced in reduced form; each count spread over
+                                        //     slots picked by workgroup (summed on readout), so that tens of
+                                        //     thousands of workgroups do not queue on one address
+    int *kbl, *kfl;                     // [n_kry_list] instances needing a basis / a step operator
+    unsigned int *kbn;                  // [2] their lengths (cleared by the bound-and-lift launch)
+    double *kze;                        // [inst][krm] reduced end state of the interval
+    double *kdist;                      // [inst] largest distance of the interval's reduced states from it
 };
 
 constexpr int SS_CL = 64;                // nodes per chunk of the many-sample skipping check
 constexpr int KRY_RM_MAX = 16;           // 2 q for q <= 8
+constexpr int KRY_CNT_SLOTS = 256;       // slots per reduced-stepping counter (a power of two)
 __host__ __device__ constexpr int KRY_KS(int rm) { return 3 * rm * rm + 3 * rm + 1; }
 
 // Aggregation multigrid preconditioner of the IR solve.  Level 0 is the nodal
