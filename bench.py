@@ -113,20 +113,21 @@ def kernel_code_sha(kernel_src: str) -> str:
 
 
 def measured_traffic(kernel_src: str, profile_md: str, kernel: str | None = None):
-    """HBM bytes per launch from the committed PMC summary, or None when the
-    kernel's device code changed since the counters were taken (or they were
-    taken on another instantiation of it)."""
+    """HBM bytes per launch from the committed PMC summary (one JSON block per
+    instantiation measured), or None when the kernel's device code changed
+    since the counters were taken (or none was taken on this instantiation)."""
     try:
         txt = open(os.path.join(ROOT, profile_md)).read()
-        block = txt.split("```json", 1)[1].split("```", 1)[0]
-        pm = json.loads(block)
         sha = kernel_code_sha(kernel_src)
-        if pm.get("source_sha256_16") != sha:
-            return None
-        if kernel is not None and pm.get("kernel", kernel) != kernel:
-            return None
-        return pm["traffic_bytes_per_launch"]
-    except (OSError, IndexError, ValueError, KeyError):
+        for part in txt.split("```json")[1:]:
+            pm = json.loads(part.split("```", 1)[0])
+            if pm.get("source_sha256_16") != sha:
+                continue
+            if kernel is not None and pm.get("kernel", kernel) != kernel:
+                continue
+            return pm["traffic_bytes_per_launch"]
+        return None
+    except (OSError, ValueError, KeyError):
         return None
 
 
