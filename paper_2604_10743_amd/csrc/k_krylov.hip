@@ -49,6 +49,29 @@ __device__ inline double kry_bcast(double v, int b)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// A strided node loop (first, first + step, ... below end) in batches of KU
+// nodes: the batch's values are all computed (their loads issued together)
+// before any is stored, so a long chain costs one memory round trip per batch
+// rather than per node.  load(i) must not read what op(j, .) writes for
+// another node j of the batch.
+template <int KU, typename L, typename O>
+__device__ inline void kw_batched(int first, int end, int step, L load, O op)
+{
+    for (int i = first; i < end; i += KU * step) {
+        double v[KU];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int ii = i + u * step;
+            v[u] = ii < end ? load(ii) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int ii = i + u * step;
+            if (ii < end) op(ii, v[u]);
+        }
+    }
+}
+
 // sum over the wavefront, every lane gets it
 __device__ inline double kw_sum(double v)
 {
@@ -190,6 +213,7 @@ __global__ __launch_bounds__(KBW) void k_kry_basis(Dev d)
         double *ip = d.kscr, *mf = ip + (size_t)d.ns * S, *ub = mf + (size_t)d.ns * S;   // [i S + s]
         // shift (eq. 26)
         double a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 4
         for (int i = i0 + lane; i < i1; i += KBW) {
             a2 += d.V[i];
             if (i > i0) {
@@ -207,6 +231,7 @@ __global__ __launch_bounds__(KBW) void k_kry_basis(Dev d)
         // pivots p_i = 1 / (D_i - g_i^2 p_(i-1)), D_i = s0 V_i + g_i + g_(i+1)
         {
             double a = 1.0, b = 0.0, c = 0.0, e = 1.0;
+#pragma unroll 4
             for (int i = lo; i < hi; ++i) {
                 const double gl = i > i0 ? ge(i) : 0.0, gr = i + 1 < i1 ? ge(i + 1) : 0.0;
                 const double D = s0 * d.V[i] + gl + gr, h = gl * gl;
@@ -218,15 +243,28 @@ __global__ __launch_bounds__(KBW) void k_kry_basis(Dev d)
                 e = ne;
             }
             double p = kw_projective_entry(a, b, c, e);
-            for (int i = lo; i < hi; ++i) {
-                const double gl = i > i0 ? ge(i) : 0.0, gr = i + 1 < i1 ? ge(i + 1) : 0.0;
-                const double D = s0 * d.V[i] + gl + gr;
-                const double np = 1.0 / (i > i0 ? D - gl * gl * p : D);
-                const size_t x = (size_t)i * S + s;
-                ip[x] = np;
-                ub[x] = gr * np;
-                mf[x] = i > i0 ? gl * p : 0.0;
-                p = np;
+            for (int i = lo; i < hi; i += 4) {
+                double glv[4], grv[4], Vv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int ii = i + u;
+                    glv[u] = ii < hi && ii > i0 ? ge(ii) : 0.0;
+                    grv[u] = ii < hi && ii + 1 < i1 ? ge(ii + 1) : 0.0;
+                    Vv[u] = ii < hi ? d.V[ii] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int ii = i + u;
+                    if (ii >= hi) break;
+                    const double gl = glv[u], gr = grv[u];
+                    const double D = s0 * Vv[u] + gl + gr;
+                    const double np = 1.0 / (ii > i0 ? D - gl * gl * p : D);
+                    const size_t x = (size_t)ii * S + s;
+                    ip[x] = np;
+                    ub[x] = gr * np;
+                    mf[x] = ii > i0 ? gl * p : 0.0;
+                    p = np;
+                }
             }
         }
         __syncthreads();                       // lanes read other lanes' nodes from here on
@@ -236,29 +274,51 @@ __global__ __launch_bounds__(KBW) void k_kry_basis(Dev d)
         auto solve = [&](int c) {
             __syncthreads();
             double m = 1.0, b = 0.0;
+#pragma unroll 4
             for (int i = lo; i < hi; ++i) {
                 const double mi = mf[(size_t)i * S + s];
                 b = mi * b + col(c, i);
                 m = mi * m;
             }
             double y = kw_affine_entry(m, b);
-            for (int i = lo; i < hi; ++i) {
-                y = col(c, i) + mf[(size_t)i * S + s] * y;   // m = 0 at the chain's first node
-                col(c, i) = y;
+            for (int i = lo; i < hi; i += 4) {
+                double bv[4], mv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    bv[u] = i + u < hi ? col(c, i + u) : 0.0;
+                    mv[u] = i + u < hi ? mf[(size_t)(i + u) * S + s] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    y = bv[u] + mv[u] * y;                // m = 0 at the chain's first node
+                    if (i + u < hi) col(c, i + u) = y;
+                }
             }
             __syncthreads();
             m = 1.0;
             b = 0.0;
+#pragma unroll 4
             for (int i = rhi - 1; i >= rlo; --i) {
                 const size_t x = (size_t)i * S + s;
                 b = ub[x] * b + ip[x] * col(c, i);
                 m = ub[x] * m;
             }
             double xv = kw_affine_entry(m, b);
-            for (int i = rhi - 1; i >= rlo; --i) {
-                const size_t x = (size_t)i * S + s;
-                xv = ip[x] * col(c, i) + ub[x] * xv;         // u = 0 at the chain's last node
-                col(c, i) = xv;
+            for (int i = rhi - 1; i >= rlo; i -= 4) {
+                double yv[4], pv[4], uv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool in = i - u >= rlo;
+                    const size_t x = (size_t)(i - u) * S + s;
+                    yv[u] = in ? col(c, i - u) : 0.0;
+                    pv[u] = in ? ip[x] : 0.0;
+                    uv[u] = in ? ub[x] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    xv = pv[u] * yv[u] + uv[u] * xv;       // u = 0 at the chain's last node
+                    if (i - u >= rlo) col(c, i - u) = xv;
+                }
             }
             __syncthreads();
         };
@@ -266,6 +326,7 @@ __global__ __launch_bounds__(KBW) void k_kry_basis(Dev d)
         // Gram-Schmidt, two passes); true when kept
         auto accept = [&](int c) -> bool {
             double n0 = 0.0;
+#pragma unroll 4
             for (int i = i0 + lane; i < i1; i += KBW) n0 += col(c, i) * col(c, i);
             n0 = sqrt(kw_sum(n0));
             if (!(n0 > 0.0)) return false;
@@ -280,36 +341,41 @@ __global__ __launch_bounds__(KBW) void k_kry_basis(Dev d)
                         if (q < c) h[q] += col(q, i) * w;
                 }
                 kw_sum_n(h, c);
-                for (int i = i0 + lane; i < i1; i += KBW) {
+                kw_batched<2>(i0 + lane, i1, KBW, [&](int i) {
                     double w = col(c, i);
 #pragma unroll
                     for (int q = 0; q < KRY_RM_MAX; ++q)
                         if (q < c) w -= h[q] * col(q, i);
-                    col(c, i) = w;
-                }
+                    return w;
+                }, [&](int i, double w) { col(c, i) = w; });
             }
             double nw = 0.0;
+#pragma unroll 4
             for (int i = i0 + lane; i < i1; i += KBW) nw += col(c, i) * col(c, i);
             nw = sqrt(kw_sum(nw));
             if (!(nw > KRY_EPS * n0)) return false;
             const double inv = 1.0 / nw;
-            for (int i = i0 + lane; i < i1; i += KBW) col(c, i) *= inv;
+            kw_batched<4>(i0 + lane, i1, KBW, [&](int i) { return col(c, i) * inv; },
+                          [&](int i, double w) { col(c, i) = w; });
             return true;
         };
         const R *fv = (const R *)d.dtf;
         int r = 0;
         // starting block (eq. 23): K^-1 C s, K^-1 f
-        for (int i = i0 + lane; i < i1; i += KBW) col(r, i) = d.V[i] * kry_state<R>(d, i, s);
+        kw_batched<4>(i0 + lane, i1, KBW, [&](int i) { return d.V[i] * kry_state<R>(d, i, s); },
+                      [&](int i, double w) { col(r, i) = w; });
         solve(r);
         if (accept(r)) ++r;
-        for (int i = i0 + lane; i < i1; i += KBW) col(r, i) = (double)fv[(size_t)i * S + s] / d.dt;
+        kw_batched<4>(i0 + lane, i1, KBW, [&](int i) { return (double)fv[(size_t)i * S + s] / d.dt; },
+                      [&](int i, double w) { col(r, i) = w; });
         solve(r);
         if (accept(r)) ++r;
         int b0 = 0, b1 = r;
         for (int j = 1; j < d.kq && b1 > b0; ++j) {
             const int nbk = r;
             for (int c = b0; c < b1 && r < RM; ++c) {
-                for (int i = i0 + lane; i < i1; i += KBW) col(r, i) = d.V[i] * col(c, i);
+                kw_batched<4>(i0 + lane, i1, KBW, [&](int i) { return d.V[i] * col(c, i); },
+                              [&](int i, double w) { col(r, i) = w; });
                 solve(r);
                 if (accept(r)) ++r;
             }
@@ -347,6 +413,7 @@ __global__ __launch_bounds__(KBW) void k_kry_basis(Dev d)
             double ff[KRY_RM_MAX], zz[KRY_RM_MAX];
 #pragma unroll
             for (int q = 0; q < KRY_RM_MAX; ++q) ff[q] = zz[q] = 0.0;
+#pragma unroll 2
             for (int i = i0 + lane; i < i1; i += KBW) {
                 const double fi = (double)fv[(size_t)i * S + s] / d.dt, si = kry_state<R>(d, i, s);
 #pragma unroll
