@@ -25,15 +25,24 @@
 // Layout: V columns [(c ns + i) S + s] (samples fastest, as the state); per
 // instance KS doubles: A_h, C_h (RM x RM), f_h, z (RM), the step operator F
 // (RM x RM), g (RM) and the step size they were formed for; pivots of K's
-// tridiagonal factorisation [i S + s].  Everything in FP64; the state is
-// written back in the batch's precision (FP32: high and low parts).
+// tridiagonal factorisation [i S + s]; per instance the interval's reduced
+// end state (RM) and the largest distance of its states from it.  Everything
+// in FP64; the state is written back in the batch's precision (FP32: high and
+// low parts).
+//
+// Per aging interval: k_kry_need lists the instances that need a basis or a
+// step operator; k_kry_basis and k_kry_form work through those lists only;
+// k_kry_rec runs the reduced recurrence (one instance per lane); k_kry_step
+// checks the bound and lifts (one wavefront per instance).  Every count the
+// kernels keep is spread over slots (see KRY_CNT_SLOTS): tens of thousands of
+// workgroups adding to one device-scope counter queue on its address.
 #include "em_internal.h"
 
 #include <type_traits>
 
 namespace em {
 
-constexpr int KB = 256;                 // threads per instance workgroup
+constexpr int KB = 256;                 // threads per workgroup of the per-instance flag kernels
 constexpr double KRY_EPS = 1e-10;
 #define EM_KERNEL_KB __global__ __launch_bounds__(256)
 
