@@ -1407,7 +1407,7 @@ em_status em_batch_create(const em_grid_desc *g, const em_material *m, const em_
     AL(d.sample_active, uint8_t, S); AL(d.open_dirty, uint32_t, 1);
     d.ev_cap = 1 << 20;
     AL(d.events, int, (size_t)d.ev_cap * EV_WORDS); AL(d.ev_count, unsigned int, 1);
-    AL(d.node_steps, unsigned long long, 1);
+    AL(d.node_steps, unsigned long long, NS_SLOTS);
     HIPCHK(b, hipEventCreate(&b->ev_a)); HIPCHK(b, hipEventCreate(&b->ev_b));
     HIPCHK(b, hipEventCreate(&b->ev_c)); HIPCHK(b, hipEventCreate(&b->ev_d));
     AL(d.G, double, RS); AL(d.u, double, VS);
@@ -1602,9 +1602,10 @@ em_status em_get_info(em_batch *b, em_info *info)
     info->n_events = cnt;
     info->cg_iters_last = b->cg_iters_last;
     info->n_outer_done = b->n_outer_done;
-    unsigned long long nsd = 0;
-    HIPCHK(b, hipMemcpyAsync(&nsd, b->d.node_steps, 8, hipMemcpyDeviceToHost, b->stream));
+    unsigned long long nsd = 0, nss[NS_SLOTS];
+    HIPCHK(b, hipMemcpyAsync(nss, b->d.node_steps, sizeof nss, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(b, hipStreamSynchronize(b->stream));
+    for (int k = 0; k < NS_SLOTS; ++k) nsd += nss[k];
     fold_timers(b);
     info->node_steps = (int64_t)nsd + b->rerun_node_steps;
     info->step_launches = b->step_launches;
@@ -2035,7 +2036,7 @@ em_status em_reset(em_batch *b)
     HIPCHK(b, hipMemsetAsync(d.dR, 0, 8 * RS, st));
     HIPCHK(b, hipMemsetAsync(d.open, 0, RS, st));
     HIPCHK(b, hipMemsetAsync(d.ev_count, 0, 4, st));
-    HIPCHK(b, hipMemsetAsync(d.node_steps, 0, 8, st));
+    HIPCHK(b, hipMemsetAsync(d.node_steps, 0, 8 * NS_SLOTS, st));
     HIPCHK(b, hipMemsetAsync(d.open_dirty, 0, 4, st));
     if (b->sur_ready) {
         HIPCHK(b, hipMemsetAsync(d.deferred, 0, IS, st));
@@ -2476,7 +2477,7 @@ em_status snap_walk(em_batch *b, SnapIO &io, bool restore)
         {d.nv, 4 * IS}, {d.vnode, 4 * IV}, {d.vseg, 4 * IV}, {d.vphase, 4 * IV}, {d.vstep, 4 * IV},
         {d.vearly, 4 * IV}, {d.vvol, 8 * IV}, {d.vlen, 8 * IV}, {d.vrob, 8 * IV}, {d.n_suppressed, 4 * IS},
         {d.ttf, 8 * S}, {d.final_drop, 8 * S}, {d.init_drop, 8 * S}, {d.t_prev, 8 * S}, {d.d_prev, 8 * S},
-        {d.failed, 4 * S}, {d.outer_idx, 4 * S}, {d.node_steps, 8}, {d.ev_count, 4}};
+        {d.failed, 4 * S}, {d.outer_idx, 4 * S}, {d.node_steps, 8 * NS_SLOTS}, {d.ev_count, 4}};
     for (const Item &it : items) {
         em_status rc = snap_dev(b, io, it.p, it.n, restore);
         if (rc != EM_OK) return rc;

@@ -102,7 +102,8 @@ struct Dev {
     // ---- per sample ----
     uint8_t *sample_active;             // not yet retired
     uint32_t *open_dirty;               // [1] set when a segment opened
-    unsigned long long *node_steps;     // [1] stepped (node, sample) x steps
+    unsigned long long *node_steps;     // [NS_SLOTS] stepped (node, sample) x steps, spread over slots
+                                        //     picked by workgroup (summed on readout)
     // ---- events ----
     int *events;                        // [ev_cap][EV_WORDS]
     unsigned int *ev_count;
@@ -169,6 +170,8 @@ struct Dev {
 
 constexpr int SS_CL = 64;                // nodes per chunk of the many-sample skipping check
 constexpr int KRY_RM_MAX = 16;           // 2 q for q <= 8
+constexpr int NS_SLOTS = 64;             // slots of the node-step count (a power of two): one address
+                                        // taking an atomic from every wavefront of a launch queues them
 constexpr int KRY_CNT_SLOTS = 256;       // slots per reduced-stepping counter (a power of two)
 __host__ __device__ constexpr int KRY_KS(int rm) { return 3 * rm * rm + 3 * rm + 1; }
 

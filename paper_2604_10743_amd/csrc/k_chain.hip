@@ -154,7 +154,7 @@ __global__ __launch_bounds__(WG, OCC) void k_chain(ChainHot h)
     const bool last = act && (kb * M + cnt == nT);
     if (!act) cnt = 0;
     if (act && lane == lo)
-        atomicAdd(d->node_steps, (unsigned long long)nT * (unsigned long long)h.n_steps);
+        atomicAdd(&d->node_steps[blockIdx.x & (NS_SLOTS - 1)], (unsigned long long)nT * (unsigned long long)h.n_steps);
 
     R *sig = (R *)h.sigma;
     float *sig_lo = h.sig_lo;

@@ -815,7 +815,7 @@ EM_KERNEL void k_step(Dev d, int n_steps, int step0)
     const R *dtf = (const R *)d.dtf, *dinv = (const R *)d.dinv, *lf = (const R *)d.lfac;
     const R *sc = (const R *)d.sc;
     const int i0 = d.tree_off[t], i1 = d.tree_off[t + 1];
-    atomicAdd(d.node_steps, (unsigned long long)(i1 - i0) * (unsigned long long)n_steps);
+    atomicAdd(&d.node_steps[blockIdx.x & (NS_SLOTS - 1)], (unsigned long long)(i1 - i0) * (unsigned long long)n_steps);
 
     int nv = d.nv[inst];
     int vn[MAXV], vseg[MAXV], vphase[MAXV], vearly[MAXV];
@@ -1043,7 +1043,7 @@ __global__ __launch_bounds__(BR_WG) void k_branch(Dev d, int n_steps, int step0)
     const int nlev = d.br_nlev[g];
     const int *lvl = d.br_lvl + d.br_lvl0[g];            // level L: hp positions [i0 + lvl[L], i0 + lvl[L+1])
     if (tid == 0) {
-        atomicAdd(d.node_steps, (unsigned long long)(i1 - i0) * (unsigned long long)n_steps);
+        atomicAdd(&d.node_steps[blockIdx.x & (NS_SLOTS - 1)], (unsigned long long)(i1 - i0) * (unsigned long long)n_steps);
         const int nv = d.nv[inst];
         s_nv = nv;
         for (int k = 0; k < MAXV; ++k) {
